@@ -1,0 +1,136 @@
+"""Level-set functions of the interfaces (paper Sec. 5.1: Gamma = {H = 0},
+H < 0 inside, outward normal n = grad H / |grad H|).
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+Every family is written with +, -, *, / and sqrt only, in a fixed
+left-to-right order, so that the sign of H at a node and every bisection
+decision is an IEEE-exact function of the inputs.  The polar star
+r(theta) = c0 + sum_k (A_k cos k theta + B_k sin k theta) therefore obtains
+cos k theta and sin k theta from powers of the unit vector (dx + i dy)/rho
+(de Moivre) instead of atan2/sin; a pin in tests checks that this equals the
+trigonometric definition.
+
+Parameter vectors (shared interface with the HIP library, documented in the
+design notes):
+  ellipse2d   [cx, cy, c, s, a, b]          X = c dx + s dy, Y = c dy - s dx,
+                                            H = (X/a)^2 + (Y/b)^2 - 1
+  star2d      [cx, cy, c0, A1..A8, B1..B8]  H = rho - r(theta)  (H(centre) = -c0)
+  sphere3d    [cx, cy, cz, r]               H = |d|^2 - r^2
+  ellipsoid3d [cx, cy, cz, a0, a1, a2, R00..R22]  X = R^T d (R row-major),
+                                            H = sum (X_j/a_j)^2 - 1
+  torus3d     [cx, cy, cz, R, r]            H = (sqrt(dx^2+dy^2) - R)^2 + dz^2 - r^2
+"""
+import numpy as np
+
+KINDS = ("ellipse2d", "star2d", "sphere3d", "ellipsoid3d", "torus3d")
+DIM_OF = {"ellipse2d": 2, "star2d": 2, "sphere3d": 3, "ellipsoid3d": 3, "torus3d": 3}
+NMODES = 8
+
+
+def _ellipse(p, X, grad):
+    x, y = X
+    cx, cy, c, s, a, b = p[:6]
+    dx = x - cx
+    dy = y - cy
+    XX = c * dx + s * dy
+    YY = c * dy - s * dx
+    Xa = XX / a
+    Yb = YY / b
+    H = Xa * Xa + Yb * Yb - 1.0
+    if not grad:
+        return H
+    GX = 2.0 * Xa / a
+    GY = 2.0 * Yb / b
+    return (GX * c - GY * s, GX * s + GY * c)
+
+
+def _star(p, X, grad):
+    x, y = X
+    cx, cy, c0 = p[0], p[1], p[2]
+    A = p[3:3 + NMODES]
+    B = p[3 + NMODES:3 + 2 * NMODES]
+    dx = x - cx
+    dy = y - cy
+    rho = np.sqrt(dx * dx + dy * dy)
+    zero = rho == 0.0
+    safe = np.where(zero, 1.0, rho)
+    ux = dx / safe
+    uy = dy / safe
+    cr = np.ones_like(ux)
+    ci = np.zeros_like(ux)
+    r = np.zeros_like(ux) + c0
+    rp = np.zeros_like(ux)
+    for k in range(1, NMODES + 1):
+        cr, ci = cr * ux - ci * uy, cr * uy + ci * ux
+        r = r + (A[k - 1] * cr + B[k - 1] * ci)
+        rp = rp + float(k) * (B[k - 1] * cr - A[k - 1] * ci)
+    if not grad:
+        return np.where(zero, -c0, rho - r)
+    return (ux + rp * uy / safe, uy - rp * ux / safe)
+
+
+def _sphere(p, X, grad):
+    x, y, z = X
+    d0 = x - p[0]
+    d1 = y - p[1]
+    d2 = z - p[2]
+    if not grad:
+        return d0 * d0 + d1 * d1 + d2 * d2 - p[3] * p[3]
+    return (2.0 * d0, 2.0 * d1, 2.0 * d2)
+
+
+def _ellipsoid(p, X, grad):
+    x, y, z = X
+    d = (x - p[0], y - p[1], z - p[2])
+    ax = p[3:6]
+    R = p[6:15]
+    Xa = []
+    for j in range(3):
+        Xj = R[0 * 3 + j] * d[0] + R[1 * 3 + j] * d[1] + R[2 * 3 + j] * d[2]
+        Xa.append(Xj / ax[j])
+    if not grad:
+        return Xa[0] * Xa[0] + Xa[1] * Xa[1] + Xa[2] * Xa[2] - 1.0
+    G = [2.0 * Xa[j] / ax[j] for j in range(3)]
+    return tuple(R[i * 3 + 0] * G[0] + R[i * 3 + 1] * G[1] + R[i * 3 + 2] * G[2]
+                 for i in range(3))
+
+
+def _torus(p, X, grad):
+    x, y, z = X
+    d0 = x - p[0]
+    d1 = y - p[1]
+    d2 = z - p[2]
+    RR, rr = p[3], p[4]
+    rho = np.sqrt(d0 * d0 + d1 * d1)
+    q = rho - RR
+    if not grad:
+        return q * q + d2 * d2 - rr * rr
+    safe = np.where(rho == 0.0, 1.0, rho)
+    return (2.0 * q * d0 / safe, 2.0 * q * d1 / safe, 2.0 * d2)
+
+
+_FUN = {"ellipse2d": _ellipse, "star2d": _star, "sphere3d": _sphere,
+        "ellipsoid3d": _ellipsoid, "torus3d": _torus}
+
+
+def H(iface, X):
+    """Level-set value at points X = (x, y[, z]) (arrays of equal shape)."""
+    kind, p = iface
+    return _FUN[kind](np.asarray(p, dtype=np.float64), X, False)
+
+
+def gradH(iface, X):
+    """Gradient of H at points X, as a tuple of d arrays."""
+    kind, p = iface
+    return _FUN[kind](np.asarray(p, dtype=np.float64), X, True)
+
+
+def normal(iface, X):
+    """Unit outward normal n = grad H / |grad H| (Sec. 5.1)."""
+    g = gradH(iface, X)
+    s = g[0] * g[0] + g[1] * g[1]
+    if len(g) == 3:
+        s = s + g[2] * g[2]
+    nrm = np.sqrt(s)
+    return tuple(gi / nrm for gi in g)

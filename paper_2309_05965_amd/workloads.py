@@ -1,0 +1,261 @@
+"""Seeded synthetic workloads: problem descriptors and manufactured solutions.
+
+This module holds input generators only, none of the method's arithmetic.  It
+serves both the HIP library (tests, bench) and the CPU oracle: each side
+computes its own surface points, then asks this module for the data at those
+points.
+
+A problem is a dict
+    dim, order (2|4), N, lo, hi, beta_in, beta_out, kappa (reduced reaction
+    coefficient kappa_i / beta_i), cos_alpha, ifaces = [(kind, params), ...]
+with the level-set parameter layouts of the library header.  A manufactured
+solution gives, per region s (0 = exterior, k = interior of interface k), a
+smooth function u_s with its gradient and Laplacian; from it
+    fhat_s = Lap u_s - kappa u_s,   g1 = u_k - u_0,
+    g2 = beta_in d_n u_k - beta_out d_n u_0,  ftilde = fhat_k - fhat_0,
+    gB = u_0 on the box boundary.
+"""
+import math
+
+import numpy as np
+
+SEED_BATCH = 2309059654
+
+
+# ----------------------------------------------------------------------------
+# level-set parameter vectors
+# ----------------------------------------------------------------------------
+def ellipse2d(cx, cy, a, b, theta=0.0):
+    c = 1.0 if theta == 0.0 else math.cos(theta)
+    s = 0.0 if theta == 0.0 else math.sin(theta)
+    return ("ellipse2d", [cx, cy, c, s, a, b])
+
+
+def star2d(cx, cy, c0, A=None, B=None):
+    A = (list(A) if A is not None else []) + [0.0] * 8
+    B = (list(B) if B is not None else []) + [0.0] * 8
+    return ("star2d", [cx, cy, c0] + A[:8] + B[:8])
+
+
+def sphere3d(cx, cy, cz, r):
+    return ("sphere3d", [cx, cy, cz, r])
+
+
+def ellipsoid3d(c, axes, R):
+    R = np.asarray(R, dtype=np.float64).reshape(3, 3)
+    return ("ellipsoid3d", list(c) + list(axes) + R.ravel().tolist())
+
+
+def torus3d(cx, cy, cz, R, r):
+    return ("torus3d", [cx, cy, cz, R, r])
+
+
+# ----------------------------------------------------------------------------
+# manufactured functions: each returns (value, grad tuple, laplacian)
+# ----------------------------------------------------------------------------
+def f_exp_cos(X):                       # exp(x) cos(y)
+    x, y = X[0], X[1]
+    e = np.exp(x)
+    return e * np.cos(y), (e * np.cos(y), -e * np.sin(y)), 0.0 * x
+
+
+def f_sin_sin(X):                       # sin(x) sin(y)
+    x, y = X[0], X[1]
+    v = np.sin(x) * np.sin(y)
+    return v, (np.cos(x) * np.sin(y), np.sin(x) * np.cos(y)), -2.0 * v
+
+
+def f_cos2x_expy(X):                    # cos(2x) exp(y)
+    x, y = X[0], X[1]
+    v = np.cos(2 * x) * np.exp(y)
+    return v, (-2 * np.sin(2 * x) * np.exp(y), v), -3.0 * v
+
+
+def f_x2_my3(X):                        # x^2 - y^3
+    x, y = X[0], X[1]
+    return x * x - y ** 3, (2 * x, -3 * y * y), 2.0 - 6.0 * y
+
+
+def f_sin3(X):                          # sin x sin y sin z
+    x, y, z = X
+    sx, sy, sz = np.sin(x), np.sin(y), np.sin(z)
+    cx, cy, cz = np.cos(x), np.cos(y), np.cos(z)
+    v = sx * sy * sz
+    return v, (cx * sy * sz, sx * cy * sz, sx * sy * cz), -3.0 * v
+
+
+def f_exp3(X):                          # exp(x + y + z) / 10
+    x, y, z = X
+    v = np.exp(x + y + z) / 10.0
+    return v, (v, v, v), 3.0 * v
+
+
+def f_zero(X):
+    z = 0.0 * X[0]
+    return z, tuple(z for _ in X), z
+
+
+def polynomial(coef):
+    """Polynomial sum c * x^a y^b (z^c) from {(a, b[, c]): c}."""
+    items = list(coef.items())
+
+    def f(X):
+        d = len(X)
+        v = 0.0 * X[0]
+        g = [0.0 * X[0] for _ in range(d)]
+        lap = 0.0 * X[0]
+        for e, c in items:
+            def mon(ee):
+                if any(t < 0 for t in ee):
+                    return 0.0 * X[0]
+                out = 1.0 + 0.0 * X[0]
+                for a in range(d):
+                    out = out * X[a] ** ee[a]
+                return out
+            v = v + c * mon(e)
+            for a in range(d):
+                ea = list(e); ea[a] -= 1
+                g[a] = g[a] + c * e[a] * mon(ea)
+                eaa = list(e); eaa[a] -= 2
+                lap = lap + c * e[a] * (e[a] - 1) * mon(eaa)
+        return v, tuple(g), lap
+    return f
+
+
+# ----------------------------------------------------------------------------
+# problems
+# ----------------------------------------------------------------------------
+def problem(dim, order, N, lo, hi, beta_in, beta_out, kappa, ifaces, cos_alpha=0.5):
+    return {"dim": dim, "order": order, "N": int(N), "lo": float(lo), "hi": float(hi),
+            "beta_in": float(beta_in), "beta_out": float(beta_out), "kappa": float(kappa),
+            "cos_alpha": float(cos_alpha), "ifaces": list(ifaces)}
+
+
+def config1(N=64):
+    """2D Poisson, 2nd order, ellipse x^2 + y^2/0.36 = 1 in [-1.5, 1.5]^2,
+    beta 2/1, u_in = exp(x) cos y, u_out = sin x sin y."""
+    prob = problem(2, 2, N, -1.5, 1.5, 2.0, 1.0, 0.0, [ellipse2d(0.0, 0.0, 1.0, 0.6)])
+    return prob, {0: f_sin_sin, 1: f_exp_cos}
+
+
+def config2(N=512):
+    """2D 4th order, star r = 0.5 + 0.15 sin 5t in [-1, 1]^2, beta 1000/1,
+    reduced kappa 1, u_in = cos 2x exp y, u_out = x^2 - y^3."""
+    B = [0.0] * 8
+    B[4] = 0.15
+    prob = problem(2, 4, N, -1.0, 1.0, 1000.0, 1.0, 1.0, [star2d(0.0, 0.0, 0.5, None, B)])
+    return prob, {0: f_x2_my3, 1: f_cos2x_expy}
+
+
+def config3(N=128):
+    """3D 4th order, torus (R 0.6, r 0.25) plus a concentric sphere of radius
+    0.35 - 2h (gap 2h to the torus), box [-1, 1]^3, beta 1/100, kappa 0,
+    u_in = sin x sin y sin z in both interiors, u_out = exp(x+y+z)/10."""
+    h = 2.0 / N
+    prob = problem(3, 4, N, -1.0, 1.0, 1.0, 100.0, 0.0,
+                   [torus3d(0.0, 0.0, 0.0, 0.6, 0.25), sphere3d(0.0, 0.0, 0.0, 0.35 - 2.0 * h)])
+    return prob, {0: f_exp3, 1: f_sin3, 2: f_sin3}
+
+
+def config4_batch(n=512, seed=SEED_BATCH):
+    """Random stars r(t) = 0.4 + sum_{k=2..8} a_k cos(k t + p_k),
+    a_k ~ U(0, 0.04), p_k ~ U(0, 2 pi), log10 beta_in ~ U(-2, 2), beta_out = 1,
+    N ~ U{64, 128, 256, 512}, reduced kappa 1, config-2 solution."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for _ in range(n):
+        N = int(rng.choice([64, 128, 256, 512]))
+        a = rng.uniform(0.0, 0.04, size=7)
+        ph = rng.uniform(0.0, 2.0 * math.pi, size=7)
+        beta_in = 10.0 ** rng.uniform(-2.0, 2.0)
+        A = [0.0] * 8
+        B = [0.0] * 8
+        for j, k in enumerate(range(2, 9)):
+            A[k - 1] = a[j] * math.cos(ph[j])
+            B[k - 1] = -a[j] * math.sin(ph[j])
+        prob = problem(2, 4, N, -1.0, 1.0, beta_in, 1.0, 1.0, [star2d(0.0, 0.0, 0.4, A, B)])
+        out.append((prob, {0: f_x2_my3, 1: f_cos2x_expy}))
+    return out
+
+
+# ----------------------------------------------------------------------------
+# data at query points
+# ----------------------------------------------------------------------------
+def _cols(P):
+    P = np.asarray(P, dtype=np.float64)
+    return tuple(P[..., a] for a in range(P.shape[-1]))
+
+
+def grid_coords(prob):
+    d, N = prob["dim"], prob["N"]
+    h = (prob["hi"] - prob["lo"]) / N
+    x1 = prob["lo"] + np.arange(N + 1, dtype=np.float64) * h
+    out = []
+    for a in range(d):
+        shape = [1] * d
+        shape[d - 1 - a] = N + 1
+        out.append(np.broadcast_to(x1.reshape(shape), (N + 1,) * d))
+    return tuple(out)
+
+
+def fhat_fn(prob, fun):
+    def f(X):
+        v, _, lap = fun(X)
+        return lap - prob["kappa"] * v
+    return f
+
+
+def make_data(prob, sol, surf_pos, surf_nrm, surf_iface, pde_pts, cen_iface):
+    """Data of the interface problem at the solver's own query points.
+    surf_pos, surf_nrm: (Ns, d) surface points; surf_iface: (Ns,) 1-based;
+    pde_pts: (Nb, nP, d) PDE collocation points of the centres, whose
+    interfaces are cen_iface (Nb,).  g1, g2 are returned on all surface
+    points."""
+    dof_pos, dof_nrm, dof_iface = surf_pos, surf_nrm, surf_iface
+    K = len(prob["ifaces"])
+    X = _cols(dof_pos)
+    k = np.asarray(dof_iface)
+    n = np.asarray(dof_nrm, dtype=np.float64)
+    v0, g0, _ = sol[0](X)
+    g1 = np.zeros(k.size)
+    g2 = np.zeros(k.size)
+    for kk in range(1, K + 1):
+        m = k == kk
+        vk, gk, _ = sol[kk](X)
+        dn_k = sum(np.asarray(gk[a]) * n[:, a] for a in range(n.shape[1]))
+        dn_0 = sum(np.asarray(g0[a]) * n[:, a] for a in range(n.shape[1]))
+        g1 = np.where(m, vk - v0, g1)
+        g2 = np.where(m, prob["beta_in"] * dn_k - prob["beta_out"] * dn_0, g2)
+    Xp = _cols(pde_pts)
+    f0 = fhat_fn(prob, sol[0])(Xp)
+    ft = np.zeros(np.asarray(pde_pts).shape[:-1])
+    for kk in range(1, K + 1):
+        fk = fhat_fn(prob, sol[kk])(Xp)
+        ft = np.where(np.asarray(cen_iface)[:, None] == kk, fk - f0, ft)
+    G = grid_coords(prob)
+    fhat = np.stack([np.broadcast_to(fhat_fn(prob, sol[s])(G), G[0].shape) for s in range(K + 1)])
+    gB = np.array(np.broadcast_to(sol[0](G)[0], G[0].shape))
+    return {"g1": g1, "g2": g2, "ftilde": ft, "fhat": fhat, "gB": gB}
+
+
+def exact_solution(prob, sol, reg):
+    """u_{reg(node)} at every node."""
+    G = grid_coords(prob)
+    u = np.zeros(G[0].shape)
+    for s in sol:
+        u = np.where(reg == s, np.broadcast_to(sol[s](G)[0], G[0].shape), u)
+    return u
+
+
+def exact_density(prob, sol, dof_pos, dof_nrm, dof_iface):
+    """psi = [d_n u] = d_n u_k - d_n u_0 at the DOFs."""
+    X = _cols(dof_pos)
+    n = np.asarray(dof_nrm, dtype=np.float64)
+    _, g0, _ = sol[0](X)
+    k = np.asarray(dof_iface)
+    out = np.zeros(k.size)
+    for kk in set(k.tolist()):
+        _, gk, _ = sol[kk](X)
+        dn = sum((np.asarray(gk[a]) - np.asarray(g0[a])) * n[:, a] for a in range(n.shape[1]))
+        out = np.where(k == kk, dn, out)
+    return out

@@ -1,0 +1,179 @@
+"""Pins of the oracle's geometry (Sec. 5.1-5.3 of the paper): level sets,
+intersections and normals against closed forms, surface-point counts
+against the paper's printed N_b, lattices, stencil and closest-centre
+invariants, irregular nodes against their definition."""
+import math
+import os
+
+import numpy as np
+import pytest
+
+from oracle import geometry as G
+from oracle import levelset
+from paper_2309_05965_amd import workloads as W
+
+GOLD = os.path.join(os.path.dirname(__file__), "golden")
+
+
+def test_star_matches_trigonometric_definition():
+    rng = np.random.default_rng(1)
+    A = rng.uniform(-0.05, 0.05, 8)
+    B = rng.uniform(-0.05, 0.05, 8)
+    iface = W.star2d(0.1, -0.2, 0.5, A, B)
+    x = rng.uniform(-1, 1, 200)
+    y = rng.uniform(-1, 1, 200)
+    t = np.arctan2(y + 0.2, x - 0.1)
+    r = 0.5 + sum(A[k - 1] * np.cos(k * t) + B[k - 1] * np.sin(k * t) for k in range(1, 9))
+    rho = np.hypot(x - 0.1, y + 0.2)
+    assert np.allclose(levelset.H(iface, (x, y)), rho - r, atol=1e-14)
+    # gradient by central differences
+    e = 1e-6
+    gx, gy = levelset.gradH(iface, (x, y))
+    fx = (levelset.H(iface, (x + e, y)) - levelset.H(iface, (x - e, y))) / (2 * e)
+    fy = (levelset.H(iface, (x, y + e)) - levelset.H(iface, (x, y - e))) / (2 * e)
+    assert np.allclose(gx, fx, atol=1e-7) and np.allclose(gy, fy, atol=1e-7)
+
+
+@pytest.mark.parametrize("iface", [
+    W.ellipsoid3d([0.1, 0.0, -0.1], [0.5, 0.4, 0.3], np.eye(3)),
+    W.torus3d(0.0, 0.1, 0.0, 0.6, 0.2),
+    W.sphere3d(0.0, 0.0, 0.1, 0.45),
+    W.ellipse2d(0.1, 0.2, 0.7, 0.4, theta=-math.pi / 6),
+])
+def test_gradient_by_differences(iface):
+    rng = np.random.default_rng(2)
+    d = levelset.DIM_OF[iface[0]]
+    X = tuple(rng.uniform(-0.8, 0.8, 100) for _ in range(d))
+    g = levelset.gradH(iface, X)
+    e = 1e-6
+    for a in range(d):
+        Xp = list(X); Xp[a] = X[a] + e
+        Xm = list(X); Xm[a] = X[a] - e
+        fd = (levelset.H(iface, tuple(Xp)) - levelset.H(iface, tuple(Xm))) / (2 * e)
+        assert np.allclose(g[a], fd, atol=1e-6)
+
+
+def test_intersections_of_a_circle_are_exact():
+    """Roots and normals of a circle against x = +-sqrt(r^2 - y^2)."""
+    r0 = 0.61
+    prob = W.problem(2, 4, 64, -1.0, 1.0, 1.0, 1.0, 0.0, [W.ellipse2d(0.0, 0.0, r0, r0)])
+    reg = G.node_regions(prob)
+    sp = G.surface_points(prob, reg)
+    assert sp["pos"].shape[0] > 100
+    P, n = sp["pos"], sp["nrm"]
+    for a in range(2):
+        o = 1 - a
+        sel = sp["fam"] == a
+        exact = np.sqrt(r0 * r0 - P[sel, o] ** 2)
+        assert np.allclose(np.abs(P[sel, a]), exact, atol=1e-15)
+    assert np.allclose(n, P / r0, atol=1e-14)
+    # primary points carry their own family's largest normal component
+    prim = sp["prim"]
+    assert np.all(np.abs(n[prim, :]).argmax(axis=1) == sp["fam"][prim])
+    assert np.all(np.abs(n[np.arange(n.shape[0]), sp["fam"]]) > 0.5)
+
+
+def test_canonical_order():
+    prob, _ = W.config2(128)
+    sp = G.surface_points(prob, G.node_regions(prob))
+    key = (sp["fam"] * 10 ** 6 + sp["lid"]) * 1000 + sp["seg"]
+    assert np.all(np.diff(key) > 0)
+
+
+def _paper_nb():
+    rows = []
+    for line in open(os.path.join(GOLD, "paper_nb.txt")):
+        if line.startswith("#") or not line.strip():
+            continue
+        c, N, nb = line.split()
+        rows.append((c, int(N), int(nb)))
+    return rows
+
+
+@pytest.mark.parametrize("case,N,nb", [r for r in _paper_nb() if r[0] == "E1" or r[1] == 64])
+def test_primary_count_matches_paper(case, N, nb):
+    """The primary points (argmax family) reproduce the N_b printed in the
+    paper's Tables 2d-poi-o4 and 3d-neu-poi within 2%."""
+    if case == "E1":
+        prob = W.problem(2, 4, N, -1.2, 1.2, 1.0, 1.0, 0.0,
+                         [W.ellipse2d(0.0, 0.0, 1.0, 0.5, theta=-math.pi / 6)])
+    else:
+        prob = W.problem(3, 4, N, -1.5, 1.5, 1.0, 1.0, 0.0, [W.torus3d(0.0, 0.0, 0.0, 1.0, 0.4)])
+    sp = G.surface_points(prob, G.node_regions(prob))
+    ours = int(np.count_nonzero(sp["prim"]))
+    assert abs(ours - nb) <= 0.02 * nb, (ours, nb)
+
+
+@pytest.mark.parametrize("D,m", [(1, 0), (1, 3), (1, 4), (2, 0), (2, 2), (2, 3), (2, 4), (3, 2)])
+def test_lattice_is_unisolvent(D, m):
+    pts = np.array(G.lattice(D, m), dtype=float).reshape(-1, D)
+    assert len(pts) == math.comb(m + D, D)
+    exps = [e for e in np.ndindex(*(m + 1,) * D) if sum(e) <= m]
+    V = np.array([[np.prod([p[a] ** e[a] for a in range(D)]) for e in exps] for p in pts])
+    assert abs(np.linalg.det(V)) > 1e-8
+
+
+def test_lattice_matches_hand_listing():
+    """Degree-2 PDE lattice in 2D and its 3D extension."""
+    assert G.lattice(2, 2) == [(-1, 0), (0, 0), (1, 0), (0, 1), (1, 1), (0, -1)]
+    assert G.lattice(3, 2)[6:] == [(0, 0, 1), (1, 0, 1), (0, 1, 1), (0, 0, -1)]
+
+
+@pytest.mark.parametrize("cfg,N", [("config1", 64), ("config2", 128)])
+def test_stencil_invariants(cfg, N):
+    prob, _ = getattr(W, cfg)(N)
+    geo = G.build(prob)
+    surf, st, dofs = geo["surf"], geo["st"], geo["dofs"]
+    h = geo["h"]
+    for c, s in enumerate(dofs["sidx"]):
+        # the centre is its own Dirichlet and Neumann point
+        assert s in st["D"][c] and s in st["N"][c]
+        for j in list(st["D"][c]) + list(st["N"][c]):
+            assert surf["iface"][j] == surf["iface"][s]
+            assert surf["fam"][j] == surf["fam"][s]
+            assert abs(surf["pos"][j, surf["fam"][s]] - surf["pos"][s, surf["fam"][s]]) <= 6 * 2 * h
+        # distinct points
+        assert len(set(st["D"][c])) == len(st["D"][c])
+        assert len(set(st["N"][c])) == len(st["N"][c])
+    # extension weights reproduce constants and linear functions of the
+    # interpolation coordinate: rows sum to one
+    need = np.zeros(surf["pos"].shape[0], bool)
+    need[st["N"].ravel()] = True
+    assert np.allclose(geo["ext_w"][need].sum(axis=1), 1.0, atol=1e-13)
+    assert np.all(geo["ext_idx"][need][:, 0] >= 0)
+
+
+@pytest.mark.parametrize("cfg,N", [("config1", 64), ("config2", 128)])
+def test_closest_centres_match_brute_force(cfg, N):
+    prob, _ = getattr(W, cfg)(N)
+    geo = G.build(prob)
+    own = G.closest_centres_brute(prob, geo["dofs"], geo["ck"], geo["cnode"])
+    assert np.array_equal(own, geo["cowner"])
+
+
+def test_irregular_nodes_by_definition():
+    prob, _ = W.config2(64)
+    reg = G.node_regions(prob)
+    irr = set(G.irregular_nodes(prob, reg).tolist())
+    N = prob["N"]
+    flat = reg.ravel()
+    want = set()
+    for j in range(1, N):
+        for i in range(1, N):
+            p = i + (N + 1) * j
+            for dj in (-1, 0, 1):
+                for di in (-1, 0, 1):
+                    if flat[(i + di) + (N + 1) * (j + dj)] != flat[p]:
+                        want.add(p)
+    assert irr == want
+
+
+def test_overlap_and_margin_are_rejected():
+    prob = W.problem(2, 4, 32, -1.0, 1.0, 1.0, 1.0, 0.0,
+                     [W.ellipse2d(0.0, 0.0, 0.5, 0.5), W.ellipse2d(0.2, 0.0, 0.5, 0.5)])
+    with pytest.raises(G.GeometryError) as e:
+        G.build(prob)
+    assert e.value.status == "invalid"
+    prob = W.problem(2, 4, 32, -1.0, 1.0, 1.0, 1.0, 0.0, [W.ellipse2d(0.0, 0.0, 0.95, 0.5)])
+    with pytest.raises(G.GeometryError):
+        G.build(prob)
