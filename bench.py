@@ -1,0 +1,152 @@
+"""Benchmark: KFBI solves/s at 1e-8 relative GMRES residual on one MI355X.
+
+Workload (N=1): the 2D fourth-order interface problem with the star
+r(t) = 0.5 + 0.15 sin 5t on a 512 x 512 grid over [-1, 1]^2, beta 1000/1,
+reduced kappa 1, manufactured u_in = cos 2x e^y, u_out = x^2 - y^3 (seeded
+synthetic data).  One step is one whole solve of the hot path from data
+resident in HBM: geometry set-up and collocation factorisation on the
+device (S0, S1), the BIE right-hand side, GMRES over the simple-interface-
+problem operator (S2-S6) to |r| <= 1e-8 |b|, the final grid solve (S7) and
+the true-residual check, all in FP64 with the FFT (DST-I) box solver and a
+zero initial density.
+
+Prints one JSON line (rank 0, N=1 only).  The roofline object reports the
+dominant kernel, the box-solve pass (k_dst), timed with HIP events on the
+plan's stream during the timed region; the cpu_baseline object times the
+FP64 NumPy oracle on this host on a bounded sample of the same workload.
+"""
+import os
+
+for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
+    os.environ[_v] = "1"
+
+import argparse  # noqa: E402
+import json  # noqa: E402
+import sys  # noqa: E402
+import time  # noqa: E402
+
+import numpy as np  # noqa: E402
+
+METRIC = "KFBI solves/s at 1e-8 rel residual: plain FP64 vs FP32-MG+learned warm start"
+HBM_PEAK_GBS = 8000.0
+
+
+def parse():
+    ap = argparse.ArgumentParser()
+    ap.add_argument("--gpus", type=int, default=1)
+    ap.add_argument("--steps", type=int, default=20)
+    ap.add_argument("--warmup", type=int, default=3)
+    ap.add_argument("--N", type=int, default=512)
+    ap.add_argument("--tol", type=float, default=1e-8)
+    ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    return ap.parse_args()
+
+
+def cpu_baseline(N, tol, budget):
+    """The oracle as it stands, single-threaded BLAS, repeated whole solves
+    of the same workload until the time budget is used."""
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from oracle import kfbi as okfbi
+    from paper_2309_05965_amd import workloads as W
+    prob, sol = W.config2(N)
+    n = 0
+    t0 = time.perf_counter()
+    while True:
+        pl = okfbi.Plan(prob)
+        s = pl.geo["surf"]
+        data = W.make_data(prob, sol, s["pos"], s["nrm"], s["iface"], pl.geo["st"]["pde_pts"],
+                           pl.geo["dofs"]["iface"])
+        pl.solve(data, tol=tol)
+        n += 1
+        el = time.perf_counter() - t0
+        if el > budget or n >= 50:
+            break
+    return {"value": n / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
+            "sample": "%d whole solves of the same 512^2 workload (geometry, collocation, data, "
+                      "GMRES to 1e-8, final solve) in %.1f s, NumPy/SciPy FP64, 1 thread" % (n, el)}
+
+
+def main():
+    args = parse()
+    if args.gpus != 1:
+        print("bench.py runs on one GPU only: the method has no multi-GPU path in this build "
+              "(--gpus %d requested)" % args.gpus, file=sys.stderr)
+        sys.exit(2)
+    import torch
+    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+    from paper_2309_05965_amd import kfbi
+    from paper_2309_05965_amd import workloads as W
+
+    torch.cuda.set_device(0)
+    prob, sol = W.config2(args.N)
+    plan = kfbi.Plan(prob)
+    data = kfbi.device_data(plan, prob, sol)          # inputs resident in HBM
+    u = torch.zeros(plan.n_nodes, dtype=torch.float64, device="cuda")
+
+    def step():
+        plan.setup(prob)                              # S0 + S1 on the device
+        return plan.solve(data, tol=args.tol, u_out=u)
+
+    for _ in range(args.warmup):
+        step()
+    torch.cuda.synchronize()
+    plan.profile(True)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = []
+    for _ in range(args.steps):
+        _, _, info = step()
+        infos.append(info)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    solves, launches, ms = plan.timing()
+    plan.profile(False)
+
+    N = args.N
+    d = prob["dim"]
+    bytes_per_launch = 2 * 8 * (N - 1) ** d           # one read and one write of every interior value
+    avg_launch_s = ms / 1e3 / launches
+    achieved = bytes_per_launch / avg_launch_s / 1e9
+    out = {
+        "metric": METRIC,
+        "value": args.steps / el,
+        "unit": "solves/s",
+        "n_gpus": 1,
+        "steps": args.steps,
+        "warmup": args.warmup,
+        "ms_per_step": 1e3 * el / args.steps,
+        "higher_is_better": True,
+        "scaling": "weak",
+        "vs_baseline": None,
+        "dtype": "f64",
+        "data": "synthetic",
+        "config": {
+            "workload": "2D 4th-order KFBI, star r=0.5+0.15 sin 5t, %dx%d grid on [-1,1]^2, beta_in/out "
+                        "1000/1, reduced kappa 1, GMRES tol %g, plain FP64, FFT box solver, zero start"
+                        % (N, N, args.tol),
+            "n_dof": int(plan.n_dof),
+            "n_surf": int(plan.n_surf),
+            "gmres_iters": int(infos[-1]["iters"]),
+            "true_rel_res": float(infos[-1]["true_rel_res"]),
+            "box_solves_per_step": solves / args.steps,
+        },
+        "roofline": {
+            "kernel": "k_dst (box-solve pass)",
+            "bound": "hbm",
+            "achieved": achieved,
+            "peak": HBM_PEAK_GBS,
+            "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS,
+            "traffic": None,
+            "avg_launch_us": avg_launch_s * 1e6,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+        },
+    }
+    if not args.no_cpu_baseline:
+        out["cpu_baseline"] = cpu_baseline(N, args.tol, args.cpu_seconds)
+    print(json.dumps(out), flush=True)
+
+
+if __name__ == "__main__":
+    main()

@@ -1,0 +1,244 @@
+/*
+ * kfbi.h -- C ABI of the MI355X (gfx950) correction-function KFBI library.
+ *
+ * The library solves the elliptic interface problem of Zhou & Ying,
+ * "A correction function-based kernel-free boundary integral method for
+ * elliptic PDEs with implicitly defined interfaces" (arXiv 2309.05965),
+ * Sec. 2.2 (eqs. IFP, IFP-bc), divided by the coefficients as in Sec. 3.2
+ * (eq. bie-ifp-2):
+ *
+ *     Lap u - kappa u = fhat_s   in region s,
+ *     [u] = g1,  [beta d_n u] = g2   on every interface (interior - exterior),
+ *     u = gB   on the boundary of the box [lo, hi]^d,
+ *
+ * with beta = beta_in inside every interface and beta_out outside.  The
+ * unknown density psi = [d_n u] lives on the primary surface points and
+ * solves the second-kind BIE  psi/2 + mu K' psi = rhs  (Sec. 3.2) by GMRES
+ * (Alg. 1), whose matrix-vector product is one "simple interface problem"
+ * solve on the Cartesian grid (Sec. 4, eq. equi-ifp; Sec. 5): collocation
+ * for the local correction functions (Secs. 5.3, 5.4), the corrected
+ * compact finite-difference right-hand side (Sec. 5.2, eqs. corrected-FDS,
+ * crc-formula), a box solve, and corrected interpolation of the normal
+ * derivative at the surface points (Sec. 5.5).
+ *
+ * Conventions
+ *  - All array arguments are DEVICE pointers owned by the caller, FP64
+ *    unless stated, and all work is ordered on the stream given to
+ *    kfbi_plan_create.  Functions return after enqueueing work, except
+ *    where a count or a convergence test needs the device (plan set-up,
+ *    kfbi_solve), which synchronise the plan's stream.
+ *  - Grid arrays have (N+1)^d entries in node order i0 + (N+1) i1
+ *    (+ (N+1)^2 i2) (x fastest); node x_i = lo + i h, h = (hi - lo)/N.
+ *  - Surface arrays are indexed by the surface-point table of the plan
+ *    (n_surf entries, canonical order: family r, line, segment, interface).
+ *    Density arrays (psi) are indexed by the primary points (n_dof entries,
+ *    the primary subsequence of the surface table).
+ *  - Errors: every call returns a kfbi_status; kfbi_last_error() gives a
+ *    thread-local message.  No exception crosses the ABI.  A plan whose
+ *    set-up failed must still be destroyed.
+ */
+#ifndef KFBI_H
+#define KFBI_H
+
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+typedef enum {
+  KFBI_OK = 0,
+  KFBI_E_INVALID = 1,        /* bad argument or geometry (overlap, too close to the box) */
+  KFBI_E_UNRESOLVED = 2,     /* no valid collocation / interpolation stencil */
+  KFBI_E_SINGULAR = 3,       /* a collocation matrix is singular (cond > 1e10) */
+  KFBI_E_NOT_CONVERGED = 4,  /* GMRES reached max_iter */
+  KFBI_E_NONFINITE = 5,      /* NaN or Inf in the data */
+  KFBI_E_DEVICE = 6,         /* HIP runtime error */
+  KFBI_E_OOM = 7             /* device allocation failed */
+} kfbi_status;
+
+/* Level-set families (Sec. 5.1: Gamma = {H = 0}, H < 0 inside, outward
+ * normal grad H / |grad H|).  Parameter layouts:
+ *   ELLIPSE2D   p = [cx, cy, c, s, a, b]: X = c dx + s dy, Y = c dy - s dx,
+ *               H = (X/a)^2 + (Y/b)^2 - 1
+ *   STAR2D      p = [cx, cy, c0, A1..A8, B1..B8]:
+ *               H = rho - (c0 + sum_k A_k cos k theta + B_k sin k theta)
+ *   SPHERE3D    p = [cx, cy, cz, r]:  H = |x - c|^2 - r^2
+ *   ELLIPSOID3D p = [cx, cy, cz, a0, a1, a2, R00..R22]: X = R^T (x - c)
+ *               (R row-major), H = sum_j (X_j / a_j)^2 - 1
+ *   TORUS3D     p = [cx, cy, cz, R, r]: H = (sqrt(dx^2+dy^2) - R)^2 + dz^2 - r^2 */
+enum {
+  KFBI_LS_ELLIPSE2D = 1,
+  KFBI_LS_STAR2D = 2,
+  KFBI_LS_SPHERE3D = 3,
+  KFBI_LS_ELLIPSOID3D = 4,
+  KFBI_LS_TORUS3D = 5
+};
+
+#define KFBI_MAX_IFACE 4
+#define KFBI_LS_NPARAM 32
+
+typedef struct {
+  int32_t kind;              /* KFBI_LS_* */
+  int32_t reserved;
+  double p[KFBI_LS_NPARAM];
+} kfbi_levelset;
+
+/* Problem descriptor (Sec. 2.2).  dim 2|3; order 2 (5/7-point scheme,
+ * quadratic correction) or 4 (eqs. 9p-cds / 27p-cds, quartic correction);
+ * N a power of two, 8 <= N <= 1024; interiors of the interfaces must be
+ * disjoint and stay 3 nodes away from the box boundary; kappa is the
+ * reduced reaction coefficient kappa_i / beta_i (equal on both sides);
+ * cos_alpha in (0, 1/sqrt(dim)) defines the overlapping surface sets
+ * Gamma_r = {|n_r| > cos alpha} (Sec. 5.1). */
+typedef struct {
+  int32_t dim, order, N, n_iface;
+  double lo, hi;
+  double beta_in, beta_out, kappa, cos_alpha;
+  kfbi_levelset iface[KFBI_MAX_IFACE];
+} kfbi_problem;
+
+typedef struct kfbi_plan kfbi_plan;
+
+typedef struct {
+  int64_t n_nodes;      /* (N+1)^d */
+  int64_t n_surf;       /* surface points (overlapping set Gamma^h) */
+  int64_t n_dof;        /* primary points = centres = unknowns */
+  int64_t n_irregular;  /* irregular grid nodes (Sec. 5.2) */
+  int64_t n_corr;       /* (interface, node) correction entries */
+  int32_t n_pde;        /* PDE collocation points per centre */
+  int32_t n_dir;        /* Dirichlet collocation points per centre */
+  int32_t n_neu;        /* Neumann collocation points per centre */
+  int32_t n_coef;       /* polynomial coefficients per centre */
+  double h;
+  double cond_max;      /* largest 1-norm condition number of the collocation matrices */
+} kfbi_sizes;
+
+/* Data of one interface problem (device pointers):
+ *   g1, g2  [n_surf]             jumps [u] and [beta d_n u] at the surface points
+ *   ftilde  [n_dof][n_pde]       fhat_in - fhat_out at the PDE collocation points
+ *   fhat    [n_iface+1][n_nodes] fhat_s at every node for every region s
+ *                                (s = 0 exterior, s = k inside interface k)
+ *   gB      [n_nodes]            box data; only box-boundary nodes are read */
+typedef struct {
+  const double* g1;
+  const double* g2;
+  const double* ftilde;
+  const double* fhat;
+  const double* gB;
+} kfbi_data;
+
+typedef struct {
+  double tol;           /* GMRES stop: |r_k| <= tol |b| (default 1e-10) */
+  int32_t max_iter;     /* unrestarted GMRES length (<= 512) */
+  int32_t use_x0;       /* 1: psi_inout holds the initial guess; 0: zero start */
+} kfbi_opts;
+
+typedef struct {
+  int32_t iters;
+  int32_t status;       /* kfbi_status of the solve */
+  double est_rel_res;   /* GMRES residual estimate / |b| */
+  double true_rel_res;  /* |b - A psi| / |b| recomputed with a fresh matvec */
+} kfbi_info;
+
+/* Step S0 + S1: build the plan of one problem (geometry on the device:
+ * regions, surface points, stencils, irregular nodes, correction entries and
+ * their closest centres; then factor every collocation matrix).  `stream`
+ * is a hipStream_t (NULL = default stream).  On failure *out is still set
+ * (destroy it) unless the status is KFBI_E_OOM or KFBI_E_INVALID from the
+ * descriptor check. */
+kfbi_status kfbi_plan_create(const kfbi_problem* prob, void* stream, kfbi_plan** out);
+
+/* Re-run S0 + S1 for another problem with the same dim, order and N,
+ * reusing the plan's buffers (they grow when the new geometry needs more). */
+kfbi_status kfbi_plan_setup(kfbi_plan* plan, const kfbi_problem* prob);
+
+kfbi_status kfbi_plan_sizes(const kfbi_plan* plan, kfbi_sizes* out);
+
+/* Copy a plan table to caller memory (device pointer, `bytes` available).
+ * Layouts (int32 unless stated):
+ *   REGION     int8 [n_nodes]             region id per node
+ *   SURF_POS   double [n_surf][dim]       surface points
+ *   SURF_NRM   double [n_surf][dim]       unit normals
+ *   SURF_META  int32 [n_surf][5]          family, line id, segment, interface, primary
+ *   DOF_SURF   [n_dof]                    surface index of every primary point
+ *   STENCIL_D  [n_dof][n_dir]             Dirichlet points (surface indices)
+ *   STENCIL_N  [n_dof][n_neu]             Neumann points (surface indices)
+ *   EXT_IDX    [n_surf][p]                density extension: primary indices
+ *   EXT_W      double [n_surf][p]         density extension weights
+ *   PDE_PTS    double [n_dof][n_pde][dim] PDE collocation points
+ *   IRREGULAR  [n_irregular]              irregular node indices
+ *   CORR       [n_corr][3]                interface, node, owner centre
+ *   COND       double [n_dof]             collocation 1-norm condition numbers */
+enum {
+  KFBI_EXPORT_REGION = 0,
+  KFBI_EXPORT_SURF_POS = 1,
+  KFBI_EXPORT_SURF_NRM = 2,
+  KFBI_EXPORT_SURF_META = 3,
+  KFBI_EXPORT_DOF_SURF = 4,
+  KFBI_EXPORT_STENCIL_D = 5,
+  KFBI_EXPORT_STENCIL_N = 6,
+  KFBI_EXPORT_EXT_IDX = 7,
+  KFBI_EXPORT_EXT_W = 8,
+  KFBI_EXPORT_PDE_PTS = 9,
+  KFBI_EXPORT_IRREGULAR = 10,
+  KFBI_EXPORT_CORR = 11,
+  KFBI_EXPORT_COND = 12
+};
+kfbi_status kfbi_plan_export(const kfbi_plan* plan, int which, void* dst, int64_t bytes);
+
+/* Box solve alone (step S3; Alg. 1 Step 3.3): A_h v = F on the interior
+ * nodes with v = 0 on the box boundary, A_h the plan's scheme, exactly by
+ * the type-I sine transform.  F, v: [n_nodes] (interior of F read; all of v
+ * written).  F and v may not alias. */
+kfbi_status kfbi_box_solve(kfbi_plan* plan, const double* F, double* v);
+
+/* One simple interface problem (eq. con-ifp with box data; Secs. 4, 5):
+ * w with [w] = a, [d_n w] = b, Lap w - kappa w = fhat_s, w = gB on the box.
+ * a, b: [n_surf] (NULL = 0); ftilde [n_dof][n_pde], fhat, gB as in
+ * kfbi_data (NULL = 0).  Outputs: v [n_nodes] (may be NULL), d_n w_in and
+ * d_n w_out at the primary points [n_dof] (may be NULL). */
+kfbi_status kfbi_simple_solve(kfbi_plan* plan, const double* a, const double* b,
+                              const double* ftilde, const double* fhat, const double* gB,
+                              double* v, double* dn_in, double* dn_out);
+
+/* The BIE operator (hot path, steps S2-S5): Apsi = J[w(0, E psi, 0, 0, 0)] /
+ * (beta_in + beta_out), J = beta_in d_n w_in - beta_out d_n w_out, E the
+ * density extension to the surface table.  Equals psi/2 + mu K' psi of
+ * Sec. 3.2 with mu = (beta_out - beta_in)/(beta_out + beta_in).
+ * psi, Apsi: [n_dof], distinct buffers. */
+kfbi_status kfbi_matvec(kfbi_plan* plan, const double* psi, double* Apsi);
+
+/* BIE right-hand side (Alg. 1 Step 1):
+ * b = (g2 - J[w(g1, 0, ftilde, fhat, gB)]) / (beta_in + beta_out), b [n_dof]. */
+kfbi_status kfbi_rhs(kfbi_plan* plan, const kfbi_data* data, double* b);
+
+/* Full solve (Alg. 1): b, GMRES on kfbi_matvec to opts->tol, then
+ * u = w(g1, E psi, ftilde, fhat, gB).  psi_inout [n_dof] (initial guess if
+ * opts->use_x0, density on return); u_out [n_nodes] (may be NULL).
+ * Synchronises the plan's stream once per GMRES iteration.  Returns
+ * KFBI_E_NOT_CONVERGED (with psi and u of the last iterate) if max_iter is
+ * reached. */
+kfbi_status kfbi_solve(kfbi_plan* plan, const kfbi_data* data, const kfbi_opts* opts,
+                       double* psi_inout, double* u_out, kfbi_info* info);
+
+/* Event timing of the box-solve kernels (tracing aid).  With enable = 1
+ * every subsequent box solve of the plan is bracketed by two HIP events on
+ * the plan's stream; kfbi_plan_timing synchronises the stream and returns
+ * the number of box solves and kernel launches recorded since enabling and
+ * their total elapsed milliseconds (launches are back to back, so
+ * ms / launches is the average launch duration).  enable = 0 stops and
+ * clears the record. */
+kfbi_status kfbi_plan_profile(kfbi_plan* plan, int enable);
+kfbi_status kfbi_plan_timing(kfbi_plan* plan, int64_t* solves, int64_t* launches, double* ms);
+
+kfbi_status kfbi_plan_destroy(kfbi_plan* plan);
+
+/* Thread-local message of the last failing call (never NULL). */
+const char* kfbi_last_error(void);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* KFBI_H */

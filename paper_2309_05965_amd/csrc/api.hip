@@ -1,0 +1,608 @@
+// Host side of the C ABI: plan life cycle, table export and the solve
+// orchestration (Alg. 1 of the paper: right-hand side, GMRES over the
+// simple-interface-problem operator, final solve).
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <new>
+
+#include "kfbi_internal.h"
+
+void kfbi_pde_lattice(int d, int p, int (*off)[3], int* n);
+void kfbi_dn_lattice(int D, int m, int (*off)[2], int* n);
+
+namespace {
+
+thread_local char g_err[512] = "no error";
+
+template <class T>
+kfbi_status dalloc(T** p, int64_t n) {
+  *p = nullptr;
+  if (n <= 0) n = 1;
+  if (hipMalloc((void**)p, (size_t)n * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    kfbi_set_error("device allocation of %lld bytes failed", (long long)(n * sizeof(T)));
+    return KFBI_E_OOM;
+  }
+  return KFBI_OK;
+}
+
+template <class T>
+void dfree(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+kfbi_status check_problem(const kfbi_problem* pr) {
+  if (!pr) {
+    kfbi_set_error("problem descriptor is NULL");
+    return KFBI_E_INVALID;
+  }
+  if (pr->dim != 2 && pr->dim != 3) {
+    kfbi_set_error("dim must be 2 or 3 (got %d)", pr->dim);
+    return KFBI_E_INVALID;
+  }
+  if (pr->order != 2 && pr->order != 4) {
+    kfbi_set_error("order must be 2 or 4 (got %d)", pr->order);
+    return KFBI_E_INVALID;
+  }
+  if (pr->N < 8 || pr->N > 1024 || (pr->N & (pr->N - 1))) {
+    kfbi_set_error("N must be a power of two in [8, 1024] (got %d)", pr->N);
+    return KFBI_E_INVALID;
+  }
+  if (pr->n_iface < 1 || pr->n_iface > KFBI_MAX_IFACE) {
+    kfbi_set_error("n_iface must be in [1, %d] (got %d)", KFBI_MAX_IFACE, pr->n_iface);
+    return KFBI_E_INVALID;
+  }
+  if (!(pr->hi > pr->lo) || !(pr->beta_in > 0.0) || !(pr->beta_out > 0.0) || !(pr->kappa >= 0.0)) {
+    kfbi_set_error("need hi > lo, beta_in > 0, beta_out > 0, kappa >= 0");
+    return KFBI_E_INVALID;
+  }
+  if (!(pr->cos_alpha > 0.0) || !(pr->cos_alpha * pr->cos_alpha * pr->dim < 1.0)) {
+    kfbi_set_error("cos_alpha must lie in (0, 1/sqrt(dim))");
+    return KFBI_E_INVALID;
+  }
+  for (int k = 0; k < pr->n_iface; ++k) {
+    int kind = pr->iface[k].kind;
+    bool two = kind == KFBI_LS_ELLIPSE2D || kind == KFBI_LS_STAR2D;
+    bool three = kind == KFBI_LS_SPHERE3D || kind == KFBI_LS_ELLIPSOID3D || kind == KFBI_LS_TORUS3D;
+    if ((pr->dim == 2 && !two) || (pr->dim == 3 && !three)) {
+      kfbi_set_error("level set %d: kind %d does not fit dim %d", k, kind, pr->dim);
+      return KFBI_E_INVALID;
+    }
+  }
+  return KFBI_OK;
+}
+
+void free_plan(kfbi_plan* pl) {
+  dfree(pl->region);
+  dfree(pl->need);
+  dfree(pl->Cg);
+  dfree(pl->Fm);
+  dfree(pl->Fs);
+  dfree(pl->T1);
+  dfree(pl->T2);
+  dfree(pl->vbuf);
+  dfree(pl->vsbuf);
+  dfree(pl->c_r);
+  dfree(pl->c_lid);
+  dfree(pl->c_seg);
+  dfree(pl->c_k);
+  dfree(pl->c_ina);
+  dfree(pl->c_pos);
+  dfree(pl->c_nrm);
+  dfree(pl->c_acc);
+  dfree(pl->s_pos);
+  dfree(pl->s_nrm);
+  dfree(pl->s_meta);
+  dfree(pl->s2d);
+  dfree(pl->d2s);
+  dfree(pl->s_need);
+  dfree(pl->line_start);
+  dfree(pl->line_end);
+  dfree(pl->stD);
+  dfree(pl->stN);
+  dfree(pl->ext_idx);
+  dfree(pl->ext_w);
+  dfree(pl->MinvT);
+  dfree(pl->cond);
+  dfree(pl->psiS);
+  dfree(pl->aS);
+  dfree(pl->U);
+  dfree(pl->dn_in);
+  dfree(pl->dn_out);
+  dfree(pl->irr);
+  dfree(pl->ce_k);
+  dfree(pl->ce_node);
+  dfree(pl->ce_owner);
+  dfree(pl->cell_count);
+  dfree(pl->cell_start);
+  dfree(pl->cell_items);
+  dfree(pl->blk);
+  dfree(pl->blk_total);
+  dfree(pl->d_flags);
+  dfree(pl->tw);
+  dfree(pl->eig1);
+  dfree(pl->V);
+  dfree(pl->Hm);
+  dfree(pl->gv);
+  dfree(pl->cs);
+  dfree(pl->sn);
+  dfree(pl->work);
+  dfree(pl->work2);
+  dfree(pl->bvec);
+  dfree(pl->scal);
+  if (pl->prof_ev) {
+    for (hipEvent_t e : *pl->prof_ev) (void)hipEventDestroy(e);
+    delete pl->prof_ev;
+    pl->prof_ev = nullptr;
+  }
+  if (pl->h_pinned) (void)hipHostFree(pl->h_pinned);
+  if (pl->h_dpinned) (void)hipHostFree(pl->h_dpinned);
+  pl->h_pinned = nullptr;
+  pl->h_dpinned = nullptr;
+}
+
+GridDesc make_grid(const kfbi_problem& pr) {
+  GridDesc g;
+  g.d = pr.dim;
+  g.order = pr.order;
+  g.p = pr.order == 4 ? 4 : 2;
+  g.N = pr.N;
+  g.n1 = pr.N + 1;
+  g.K = pr.n_iface;
+  g.lo = pr.lo;
+  g.hi = pr.hi;
+  g.h = (pr.hi - pr.lo) / pr.N;
+  g.kappa = pr.kappa;
+  g.cos_alpha = pr.cos_alpha;
+  g.beta_in = pr.beta_in;
+  g.beta_out = pr.beta_out;
+  g.n_nodes = 1;
+  for (int a = 0; a < g.d; ++a) g.n_nodes *= g.n1;
+  return g;
+}
+
+// grid-sized and fixed buffers of a plan
+kfbi_status alloc_fixed(kfbi_plan* pl) {
+  const GridDesc& g = pl->g;
+  int64_t n = g.n_nodes;
+  KCHK(dalloc(&pl->region, n));
+  KCHK(dalloc(&pl->need, (int64_t)g.K * n));
+  KCHK(dalloc(&pl->Cg, (int64_t)g.K * n));
+  KCHK(dalloc(&pl->Fm, n));
+  KCHK(dalloc(&pl->Fs, n));
+  KCHK(dalloc(&pl->T1, n));
+  KCHK(dalloc(&pl->T2, n));
+  KCHK(dalloc(&pl->vbuf, n));
+  KCHK(dalloc(&pl->vsbuf, n));
+  KCHK(dalloc(&pl->line_start, pl->n_lines));
+  KCHK(dalloc(&pl->line_end, pl->n_lines));
+  int64_t nkeys = (int64_t)g.K * pl->ncell;
+  KCHK(dalloc(&pl->cell_count, nkeys + 1));
+  KCHK(dalloc(&pl->cell_start, nkeys + 1));
+  KCHK(dalloc(&pl->blk_total, 4));
+  KCHK(dalloc(&pl->d_flags, 4));
+  KCHK(dalloc(&pl->tw, 2 * g.N));
+  KCHK(dalloc(&pl->eig1, g.N + 1));
+  KCHK(dalloc(&pl->scal, 16 + KFBI_GMRES_MAX + 8));
+  KCHK(dalloc(&pl->Hm, (int64_t)(KFBI_GMRES_MAX + 1) * (KFBI_GMRES_MAX + 1)));
+  KCHK(dalloc(&pl->gv, KFBI_GMRES_MAX + 1));
+  KCHK(dalloc(&pl->cs, KFBI_GMRES_MAX));
+  KCHK(dalloc(&pl->sn, KFBI_GMRES_MAX));
+  if (hipHostMalloc((void**)&pl->h_pinned, 64 * sizeof(int), 0) != hipSuccess) {
+    kfbi_set_error("pinned host allocation failed");
+    return KFBI_E_OOM;
+  }
+  if (hipHostMalloc((void**)&pl->h_dpinned, 64 * sizeof(double), 0) != hipSuccess) {
+    kfbi_set_error("pinned host allocation failed");
+    return KFBI_E_OOM;
+  }
+  return KFBI_OK;
+}
+
+kfbi_status run_setup(kfbi_plan* pl) {
+  pl->ready = false;
+  KCHK(geo_setup(pl));
+  KCHK(colloc_factor(pl));
+  // the matvec right-hand side is zero away from the irregular nodes and the
+  // matvec grid solution is zero on the box boundary
+  HIPCHK(hipMemsetAsync(pl->Fm, 0, sizeof(double) * pl->g.n_nodes, pl->stream));
+  HIPCHK(hipMemsetAsync(pl->vbuf, 0, sizeof(double) * pl->g.n_nodes, pl->stream));
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  pl->ready = true;
+  return KFBI_OK;
+}
+
+kfbi_status need_ready(const kfbi_plan* pl) {
+  if (!pl) {
+    kfbi_set_error("plan is NULL");
+    return KFBI_E_INVALID;
+  }
+  if (!pl->ready) {
+    kfbi_set_error("plan set-up did not complete");
+    return KFBI_E_INVALID;
+  }
+  return KFBI_OK;
+}
+
+kfbi_status ensure_gmres(kfbi_plan* pl, int m) {
+  if (m <= pl->gm_cap && pl->n_dof <= pl->gm_n && pl->V) return KFBI_OK;
+  dfree(pl->V);
+  int mm = m > pl->gm_cap ? m : pl->gm_cap;
+  KCHK(dalloc(&pl->V, (int64_t)(mm + 1) * pl->cap_dof));
+  pl->gm_cap = mm;
+  pl->gm_n = pl->cap_dof;
+  return KFBI_OK;
+}
+
+void simple_solve_impl(kfbi_plan* pl, const double* a, const double* b, const double* ftilde,
+                       const double* fhat, const double* gB, double* v, double* dn_in, double* dn_out) {
+  op_coefficients(pl, a, b, ftilde);
+  op_correction_values(pl);
+  op_rhs_base(pl, fhat, gB, pl->Fs);
+  op_rhs_correct(pl, pl->Fs, false);
+  dst_solve(pl, pl->Fs, v);
+  op_boundary(pl, gB, v);
+  op_normal_derivatives(pl, v, dn_in, dn_out, nullptr);
+}
+
+void matvec_impl(kfbi_plan* pl, const double* psi, double* Apsi) {
+  op_extend(pl, psi, pl->psiS);
+  op_coefficients(pl, nullptr, pl->psiS, nullptr);
+  op_correction_values(pl);
+  op_rhs_correct(pl, pl->Fm, true);
+  dst_solve(pl, pl->Fm, pl->vbuf);
+  op_normal_derivatives(pl, pl->vbuf, nullptr, nullptr, Apsi);
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- errors
+void kfbi_set_error(const char* fmt, ...) {
+  va_list ap;
+  va_start(ap, fmt);
+  vsnprintf(g_err, sizeof(g_err), fmt, ap);
+  va_end(ap);
+}
+
+kfbi_status kfbi_hip_status(hipError_t e, const char* what) {
+  kfbi_set_error("HIP error %d (%s) in %s", (int)e, hipGetErrorString(e), what);
+  return e == hipErrorOutOfMemory ? KFBI_E_OOM : KFBI_E_DEVICE;
+}
+
+kfbi_status kfbi_flags_status(int f) {
+  if (f & (FLAG_OVERLAP | FLAG_MARGIN)) {
+    kfbi_set_error("invalid geometry:%s%s", f & FLAG_OVERLAP ? " interface interiors overlap" : "",
+                   f & FLAG_MARGIN ? " interface too close to the box boundary" : "");
+    return KFBI_E_INVALID;
+  }
+  if (f & (FLAG_UNRESOLVED_STENCIL | FLAG_UNRESOLVED_EXT | FLAG_UNRESOLVED_OWNER)) {
+    kfbi_set_error("geometry not resolved by the grid:%s%s%s",
+                   f & FLAG_UNRESOLVED_STENCIL ? " no collocation stencil" : "",
+                   f & FLAG_UNRESOLVED_EXT ? " no density interpolation stencil" : "",
+                   f & FLAG_UNRESOLVED_OWNER ? " no closest centre" : "");
+    return KFBI_E_UNRESOLVED;
+  }
+  if (f & FLAG_SINGULAR) {
+    kfbi_set_error("singular collocation matrix");
+    return KFBI_E_SINGULAR;
+  }
+  if (f & FLAG_NONFINITE) {
+    kfbi_set_error("non-finite data");
+    return KFBI_E_NONFINITE;
+  }
+  kfbi_set_error("device flags 0x%x", f);
+  return KFBI_E_DEVICE;
+}
+
+extern "C" const char* kfbi_last_error(void) { return g_err; }
+
+// ---------------------------------------------------------------- plan
+extern "C" kfbi_status kfbi_plan_create(const kfbi_problem* prob, void* stream, kfbi_plan** out) {
+  if (!out) {
+    kfbi_set_error("out is NULL");
+    return KFBI_E_INVALID;
+  }
+  *out = nullptr;
+  KCHK(check_problem(prob));
+  kfbi_plan* pl = new (std::nothrow) kfbi_plan();
+  if (!pl) {
+    kfbi_set_error("host allocation failed");
+    return KFBI_E_OOM;
+  }
+  memset((void*)pl, 0, sizeof(*pl));
+  pl->prob = *prob;
+  pl->g = make_grid(*prob);
+  pl->stream = (hipStream_t)stream;
+  const GridDesc& g = pl->g;
+  int p = g.p, d = g.d;
+  pl->nC = kfbi_ncoef(d, p);
+  {
+    int offP[KFBI_MAXP][3], offD[KFBI_MAXD][2], offN[KFBI_MAXN][2];
+    kfbi_pde_lattice(d, p, offP, &pl->nP);
+    kfbi_dn_lattice(d - 1, p, offD, &pl->nD);
+    kfbi_dn_lattice(d - 1, p - 1, offN, &pl->nN);
+  }
+  int64_t L = d == 2 ? g.n1 : (int64_t)g.n1 * g.n1;
+  pl->n_seg = (int64_t)d * g.N * L;
+  pl->n_lines = (int64_t)d * L;
+  pl->ncell_axis = g.N / 2 + 1;
+  pl->ncell = 1;
+  for (int a = 0; a < d; ++a) pl->ncell *= pl->ncell_axis;
+  kfbi_status st = alloc_fixed(pl);
+  if (st == KFBI_OK) st = dst_init(pl);
+  *out = pl;
+  if (st != KFBI_OK) return st;
+  return run_setup(pl);
+}
+
+extern "C" kfbi_status kfbi_plan_setup(kfbi_plan* pl, const kfbi_problem* prob) {
+  if (!pl) {
+    kfbi_set_error("plan is NULL");
+    return KFBI_E_INVALID;
+  }
+  KCHK(check_problem(prob));
+  if (prob->dim != pl->prob.dim || prob->order != pl->prob.order || prob->N != pl->prob.N ||
+      prob->n_iface != pl->prob.n_iface || prob->lo != pl->prob.lo || prob->hi != pl->prob.hi) {
+    kfbi_set_error("kfbi_plan_setup needs the same dim, order, N, n_iface and box");
+    return KFBI_E_INVALID;
+  }
+  pl->prob = *prob;
+  pl->g = make_grid(*prob);
+  return run_setup(pl);
+}
+
+extern "C" kfbi_status kfbi_plan_sizes(const kfbi_plan* pl, kfbi_sizes* out) {
+  if (!pl || !out) {
+    kfbi_set_error("NULL argument");
+    return KFBI_E_INVALID;
+  }
+  out->n_nodes = pl->g.n_nodes;
+  out->n_surf = pl->n_surf;
+  out->n_dof = pl->n_dof;
+  out->n_irregular = pl->n_irr;
+  out->n_corr = pl->n_corr;
+  out->n_pde = pl->nP;
+  out->n_dir = pl->nD;
+  out->n_neu = pl->nN;
+  out->n_coef = pl->nC;
+  out->h = pl->g.h;
+  out->cond_max = pl->cond_max;
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_plan_destroy(kfbi_plan* pl) {
+  if (!pl) return KFBI_OK;
+  if (pl->stream) (void)hipStreamSynchronize(pl->stream);
+  else (void)hipDeviceSynchronize();
+  free_plan(pl);
+  delete pl;
+  return KFBI_OK;
+}
+
+namespace {
+__global__ void k_pde_points(int64_t n_dof, int d, int nP, double h, const int* d2s, const double* spos,
+                             const int* offs, double* out) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_dof * nP) return;
+  int64_t c = t / nP;
+  int j = (int)(t % nP);
+  const double* P = spos + (int64_t)d2s[c] * d;
+  for (int a = 0; a < d; ++a) out[t * d + a] = P[a] + (double)offs[j * 3 + a] * h;
+}
+
+__global__ void k_corr_table(int64_t n, const int* k, const int* node, const int* own, int* out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n) return;
+  out[e * 3] = k[e];
+  out[e * 3 + 1] = node[e];
+  out[e * 3 + 2] = own[e];
+}
+}  // namespace
+
+extern "C" kfbi_status kfbi_plan_export(const kfbi_plan* pl_c, int which, void* dst, int64_t bytes) {
+  KCHK(need_ready(pl_c));
+  kfbi_plan* pl = const_cast<kfbi_plan*>(pl_c);
+  const int d = pl->g.d;
+  const void* src = nullptr;
+  int64_t need = 0;
+  switch (which) {
+    case KFBI_EXPORT_REGION: src = pl->region; need = pl->g.n_nodes; break;
+    case KFBI_EXPORT_SURF_POS: src = pl->s_pos; need = pl->n_surf * d * 8; break;
+    case KFBI_EXPORT_SURF_NRM: src = pl->s_nrm; need = pl->n_surf * d * 8; break;
+    case KFBI_EXPORT_SURF_META: src = pl->s_meta; need = pl->n_surf * 5 * 4; break;
+    case KFBI_EXPORT_DOF_SURF: src = pl->d2s; need = pl->n_dof * 4; break;
+    case KFBI_EXPORT_STENCIL_D: src = pl->stD; need = pl->n_dof * pl->nD * 4; break;
+    case KFBI_EXPORT_STENCIL_N: src = pl->stN; need = pl->n_dof * pl->nN * 4; break;
+    case KFBI_EXPORT_EXT_IDX: src = pl->ext_idx; need = pl->n_surf * pl->g.p * 4; break;
+    case KFBI_EXPORT_EXT_W: src = pl->ext_w; need = pl->n_surf * pl->g.p * 8; break;
+    case KFBI_EXPORT_IRREGULAR: src = pl->irr; need = pl->n_irr * 4; break;
+    case KFBI_EXPORT_COND: src = pl->cond; need = pl->n_dof * 8; break;
+    case KFBI_EXPORT_PDE_PTS: need = pl->n_dof * pl->nP * d * 8; break;
+    case KFBI_EXPORT_CORR: need = pl->n_corr * 3 * 4; break;
+    default:
+      kfbi_set_error("unknown export table %d", which);
+      return KFBI_E_INVALID;
+  }
+  if (!dst || bytes < need) {
+    kfbi_set_error("export table %d needs %lld bytes (got %lld)", which, (long long)need, (long long)bytes);
+    return KFBI_E_INVALID;
+  }
+  if (need == 0) return KFBI_OK;
+  if (src) {
+    HIPCHK(hipMemcpyAsync(dst, src, (size_t)need, hipMemcpyDeviceToDevice, pl->stream));
+    return KFBI_OK;
+  }
+  if (which == KFBI_EXPORT_CORR) {
+    hipLaunchKernelGGL(k_corr_table, dim3((unsigned)((pl->n_corr + 255) / 256)), dim3(256), 0, pl->stream,
+                       pl->n_corr, pl->ce_k, pl->ce_node, pl->ce_owner, (int*)dst);
+    HIPCHK(hipGetLastError());
+    return KFBI_OK;
+  }
+  int offP[KFBI_MAXP][3], nP;
+  kfbi_pde_lattice(d, pl->g.p, offP, &nP);
+  int* doff;
+  KCHK(dalloc(&doff, 3 * KFBI_MAXP));
+  HIPCHK(hipMemcpy(doff, offP, sizeof(offP), hipMemcpyHostToDevice));
+  int64_t n = pl->n_dof * nP;
+  hipLaunchKernelGGL(k_pde_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pl->stream, pl->n_dof, d, nP,
+                     pl->g.h, pl->d2s, pl->s_pos, doff, (double*)dst);
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  dfree(doff);
+  return KFBI_OK;
+}
+
+// ---------------------------------------------------------------- operators
+extern "C" kfbi_status kfbi_box_solve(kfbi_plan* pl, const double* F, double* v) {
+  KCHK(need_ready(pl));
+  if (!F || !v || F == v) {
+    kfbi_set_error("box solve needs distinct F and v");
+    return KFBI_E_INVALID;
+  }
+  dst_solve(pl, F, v);
+  op_boundary(pl, nullptr, v);
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_simple_solve(kfbi_plan* pl, const double* a, const double* b, const double* ftilde,
+                                         const double* fhat, const double* gB, double* v, double* dn_in,
+                                         double* dn_out) {
+  KCHK(need_ready(pl));
+  simple_solve_impl(pl, a, b, ftilde, fhat, gB, v ? v : pl->vsbuf, dn_in ? dn_in : pl->dn_in,
+                    dn_out ? dn_out : pl->dn_out);
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_matvec(kfbi_plan* pl, const double* psi, double* Apsi) {
+  KCHK(need_ready(pl));
+  if (!psi || !Apsi || psi == Apsi) {
+    kfbi_set_error("matvec needs distinct psi and Apsi");
+    return KFBI_E_INVALID;
+  }
+  matvec_impl(pl, psi, Apsi);
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_rhs(kfbi_plan* pl, const kfbi_data* data, double* b) {
+  KCHK(need_ready(pl));
+  if (!data || !b) {
+    kfbi_set_error("NULL argument");
+    return KFBI_E_INVALID;
+  }
+  simple_solve_impl(pl, data->g1, nullptr, data->ftilde, data->fhat, data->gB, pl->vsbuf, pl->dn_in, pl->dn_out);
+  op_bie_rhs(pl, data->g2, pl->dn_in, pl->dn_out, b);
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_solve(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* opts, double* psi,
+                                  double* u_out, kfbi_info* info) {
+  KCHK(need_ready(pl));
+  if (!data || !opts || !psi || !data->g2) {
+    kfbi_set_error("NULL argument");
+    return KFBI_E_INVALID;
+  }
+  int m = opts->max_iter;
+  if (m < 1 || m > KFBI_GMRES_MAX) {
+    kfbi_set_error("max_iter must be in [1, %d]", KFBI_GMRES_MAX);
+    return KFBI_E_INVALID;
+  }
+  double tol = opts->tol > 0.0 ? opts->tol : 1e-10;
+  KCHK(ensure_gmres(pl, m));
+  hipStream_t st = pl->stream;
+  // Step 1: right-hand side
+  KCHK(kfbi_rhs(pl, data, pl->bvec));
+  // Step 2: initial residual
+  if (opts->use_x0) matvec_impl(pl, psi, pl->work);
+  gm_residual_start(pl, pl->bvec, pl->work, opts->use_x0);
+  HIPCHK(hipMemcpyAsync(pl->h_dpinned, pl->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  double beta = pl->h_dpinned[0], nb = pl->h_dpinned[1];
+  double est = nb > 0.0 ? beta / nb : 0.0;
+  int k = 0;
+  bool conv = !(beta > tol * nb);
+  // Steps 3-4: Arnoldi with the simple-interface-problem operator
+  for (int j = 0; j < m && !conv; ++j) {
+    matvec_impl(pl, pl->V + (int64_t)j * pl->n_dof, pl->V + (int64_t)(j + 1) * pl->n_dof);
+    gm_arnoldi(pl, j);
+    HIPCHK(hipMemcpyAsync(pl->h_dpinned, pl->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    k = j + 1;
+    est = nb > 0.0 ? pl->h_dpinned[0] / nb : 0.0;
+    if (pl->h_dpinned[0] <= tol * nb) conv = true;
+    if (pl->h_dpinned[2] != 0.0) break;     // lucky breakdown: exact solution in the space
+  }
+  gm_update(pl, k, psi, opts->use_x0);
+  // final solve u = w(g1, E psi, ftilde, fhat, gB)
+  op_extend(pl, psi, pl->aS);
+  simple_solve_impl(pl, data->g1, pl->aS, data->ftilde, data->fhat, data->gB, u_out ? u_out : pl->vsbuf,
+                    pl->dn_in, pl->dn_out);
+  // true residual with a fresh matvec
+  matvec_impl(pl, psi, pl->work2);
+  gm_true_residual(pl, pl->bvec, pl->work2, pl->scal + 4);
+  HIPCHK(hipMemcpyAsync(pl->h_dpinned + 4, pl->scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  double tr = pl->h_dpinned[5] > 0.0 ? sqrt(pl->h_dpinned[4] / pl->h_dpinned[5]) : 0.0;
+  kfbi_status s = conv ? KFBI_OK : KFBI_E_NOT_CONVERGED;
+  if (!isfinite(tr) || !isfinite(est)) s = KFBI_E_NONFINITE;
+  if (info) {
+    info->iters = k;
+    info->status = s;
+    info->est_rel_res = est;
+    info->true_rel_res = tr;
+  }
+  if (s == KFBI_E_NOT_CONVERGED) kfbi_set_error("GMRES did not reach tol %g in %d iterations", tol, m);
+  if (s == KFBI_E_NONFINITE) kfbi_set_error("non-finite residual");
+  return s;
+}
+
+// ---------------------------------------------------------------- tracing
+extern "C" kfbi_status kfbi_plan_profile(kfbi_plan* pl, int enable) {
+  if (!pl) {
+    kfbi_set_error("plan is NULL");
+    return KFBI_E_INVALID;
+  }
+  if (pl->prof_ev) {
+    HIPCHK(pl->stream ? hipStreamSynchronize(pl->stream) : hipDeviceSynchronize());
+    for (hipEvent_t e : *pl->prof_ev) (void)hipEventDestroy(e);
+    pl->prof_ev->clear();
+  } else {
+    pl->prof_ev = new (std::nothrow) std::vector<hipEvent_t>();
+    if (!pl->prof_ev) {
+      kfbi_set_error("host allocation failed");
+      return KFBI_E_OOM;
+    }
+  }
+  pl->prof_launches = 0;
+  pl->prof_on = enable ? 1 : 0;
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_plan_timing(kfbi_plan* pl, int64_t* solves, int64_t* launches, double* ms) {
+  if (!pl || !solves || !launches || !ms) {
+    kfbi_set_error("NULL argument");
+    return KFBI_E_INVALID;
+  }
+  *solves = 0;
+  *launches = 0;
+  *ms = 0.0;
+  if (!pl->prof_ev) return KFBI_OK;
+  HIPCHK(pl->stream ? hipStreamSynchronize(pl->stream) : hipDeviceSynchronize());
+  double tot = 0.0;
+  for (size_t i = 0; i + 1 < pl->prof_ev->size(); i += 2) {
+    float t = 0.f;
+    HIPCHK(hipEventElapsedTime(&t, (*pl->prof_ev)[i], (*pl->prof_ev)[i + 1]));
+    tot += t;
+  }
+  *solves = (int64_t)(pl->prof_ev->size() / 2);
+  *launches = pl->prof_launches;
+  *ms = tot;
+  return KFBI_OK;
+}

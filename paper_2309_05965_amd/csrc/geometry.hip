@@ -1,0 +1,1267 @@
+// Step S0 -- geometry of the simple interface problem on the device.
+//
+// Paper: Sec. 5.1 (level set, grid-line intersections by bisection, normals,
+// overlapping surface sets Gamma_r = {|n_r| > cos alpha}, reference plane of
+// the largest normal component), Sec. 5.2 (regular / irregular nodes),
+// Sec. 5.3 (closest-primary-point partition of unity), Sec. 5.4 (collocation
+// lattices), Sec. 5.5 (interpolation blocks).  Where the paper leaves a
+// choice open, the rules below are the library's readings; every discrete
+// decision is a function of IEEE-exact operations only (+ - * / sqrt floor,
+// compiled without contraction), so it is reproducible on any IEEE machine.
+//
+// Surface points are kept in canonical order (family r, line id, segment,
+// interface) by order-preserving stream compaction; no sort is needed.
+#include <math.h>
+#include <stdio.h>
+
+#include <algorithm>
+#include <array>
+#include <cstdlib>
+#include <vector>
+
+#include "kfbi_internal.h"
+
+#pragma clang fp contract(off)
+
+namespace {
+
+constexpr int CMP_IT = 16;
+constexpr int CMP_CH = KFBI_BLOCK * CMP_IT;
+constexpr int BISECT_STEPS = 52;
+constexpr int MARGIN = 3;
+constexpr double TIE_BAND = 1e-12;
+
+struct LSet {
+  int K;
+  int kind[KFBI_MAX_IFACE];
+  double p[KFBI_MAX_IFACE][KFBI_LS_NPARAM];
+};
+
+// Collocation lattices and window shifts (host-built, mirrors of the lattice
+// rules documented in collocation.hip).
+struct Lattices {
+  int nD, nN, nSD, nSN;
+  int offD[KFBI_MAXD][2];
+  int offN[KFBI_MAXN][2];
+  int shD[81][2];
+  int shN[81][2];
+};
+
+// ---------------------------------------------------------------- level sets
+__device__ double ls_value(const LSet& L, int k, double x, double y, double z) {
+  const double* p = L.p[k];
+  switch (L.kind[k]) {
+    case KFBI_LS_ELLIPSE2D: {
+      double dx = x - p[0], dy = y - p[1];
+      double XX = p[2] * dx + p[3] * dy;
+      double YY = p[2] * dy - p[3] * dx;
+      double Xa = XX / p[4], Yb = YY / p[5];
+      return Xa * Xa + Yb * Yb - 1.0;
+    }
+    case KFBI_LS_STAR2D: {
+      double dx = x - p[0], dy = y - p[1];
+      double rho = sqrt(dx * dx + dy * dy);
+      if (rho == 0.0) return -p[2];
+      double ux = dx / rho, uy = dy / rho;
+      double cr = 1.0, ci = 0.0, r = 0.0 + p[2];
+      for (int k = 1; k <= 8; ++k) {
+        double ncr = cr * ux - ci * uy;
+        double nci = cr * uy + ci * ux;
+        cr = ncr;
+        ci = nci;
+        r = r + (p[2 + k] * cr + p[10 + k] * ci);
+      }
+      return rho - r;
+    }
+    case KFBI_LS_SPHERE3D: {
+      double d0 = x - p[0], d1 = y - p[1], d2 = z - p[2];
+      return d0 * d0 + d1 * d1 + d2 * d2 - p[3] * p[3];
+    }
+    case KFBI_LS_ELLIPSOID3D: {
+      double d0 = x - p[0], d1 = y - p[1], d2 = z - p[2];
+      const double* R = p + 6;
+      double s = 0.0;
+      double Xa0, Xa1, Xa2;
+      {
+        double X0 = R[0] * d0 + R[3] * d1 + R[6] * d2;
+        double X1 = R[1] * d0 + R[4] * d1 + R[7] * d2;
+        double X2 = R[2] * d0 + R[5] * d1 + R[8] * d2;
+        Xa0 = X0 / p[3];
+        Xa1 = X1 / p[4];
+        Xa2 = X2 / p[5];
+      }
+      s = Xa0 * Xa0 + Xa1 * Xa1 + Xa2 * Xa2 - 1.0;
+      return s;
+    }
+    case KFBI_LS_TORUS3D: {
+      double d0 = x - p[0], d1 = y - p[1], d2 = z - p[2];
+      double rho = sqrt(d0 * d0 + d1 * d1);
+      double q = rho - p[3];
+      return q * q + d2 * d2 - p[4] * p[4];
+    }
+  }
+  return 1.0;
+}
+
+__device__ void ls_grad(const LSet& L, int k, double x, double y, double z, double g[3]) {
+  const double* p = L.p[k];
+  g[0] = g[1] = g[2] = 0.0;
+  switch (L.kind[k]) {
+    case KFBI_LS_ELLIPSE2D: {
+      double dx = x - p[0], dy = y - p[1];
+      double XX = p[2] * dx + p[3] * dy;
+      double YY = p[2] * dy - p[3] * dx;
+      double Xa = XX / p[4], Yb = YY / p[5];
+      double GX = 2.0 * Xa / p[4], GY = 2.0 * Yb / p[5];
+      g[0] = GX * p[2] - GY * p[3];
+      g[1] = GX * p[3] + GY * p[2];
+      return;
+    }
+    case KFBI_LS_STAR2D: {
+      double dx = x - p[0], dy = y - p[1];
+      double rho = sqrt(dx * dx + dy * dy);
+      double safe = rho == 0.0 ? 1.0 : rho;
+      double ux = dx / safe, uy = dy / safe;
+      double cr = 1.0, ci = 0.0, rp = 0.0;
+      for (int k = 1; k <= 8; ++k) {
+        double ncr = cr * ux - ci * uy;
+        double nci = cr * uy + ci * ux;
+        cr = ncr;
+        ci = nci;
+        rp = rp + (double)k * (p[10 + k] * cr - p[2 + k] * ci);
+      }
+      g[0] = ux + rp * uy / safe;
+      g[1] = uy - rp * ux / safe;
+      return;
+    }
+    case KFBI_LS_SPHERE3D:
+      g[0] = 2.0 * (x - p[0]);
+      g[1] = 2.0 * (y - p[1]);
+      g[2] = 2.0 * (z - p[2]);
+      return;
+    case KFBI_LS_ELLIPSOID3D: {
+      double d0 = x - p[0], d1 = y - p[1], d2 = z - p[2];
+      const double* R = p + 6;
+      double X0 = R[0] * d0 + R[3] * d1 + R[6] * d2;
+      double X1 = R[1] * d0 + R[4] * d1 + R[7] * d2;
+      double X2 = R[2] * d0 + R[5] * d1 + R[8] * d2;
+      double G0 = 2.0 * (X0 / p[3]) / p[3];
+      double G1 = 2.0 * (X1 / p[4]) / p[4];
+      double G2 = 2.0 * (X2 / p[5]) / p[5];
+      for (int i = 0; i < 3; ++i) g[i] = R[i * 3 + 0] * G0 + R[i * 3 + 1] * G1 + R[i * 3 + 2] * G2;
+      return;
+    }
+    case KFBI_LS_TORUS3D: {
+      double d0 = x - p[0], d1 = y - p[1], d2 = z - p[2];
+      double rho = sqrt(d0 * d0 + d1 * d1);
+      double q = rho - p[3];
+      double safe = rho == 0.0 ? 1.0 : rho;
+      g[0] = 2.0 * q * d0 / safe;
+      g[1] = 2.0 * q * d1 / safe;
+      g[2] = 2.0 * d2;
+      return;
+    }
+  }
+}
+
+__device__ __forceinline__ double node_x(const GridDesc& g, int i) { return g.lo + (double)i * g.h; }
+
+__device__ __forceinline__ void unravel(const GridDesc& g, int64_t idx, int c[3]) {
+  c[0] = (int)(idx % g.n1);
+  int64_t r = idx / g.n1;
+  c[1] = (int)(r % g.n1);
+  c[2] = (int)(r / g.n1);
+  if (g.d == 2) c[2] = 0;
+}
+
+__device__ __forceinline__ int64_t ravel(const GridDesc& g, const int c[3]) {
+  return (int64_t)c[0] + (int64_t)g.n1 * ((int64_t)c[1] + (g.d == 3 ? (int64_t)g.n1 * c[2] : 0));
+}
+
+__device__ __forceinline__ void trans_axes(int d, int r, int T[2]) {
+  int j = 0;
+  for (int a = 0; a < d; ++a)
+    if (a != r) T[j++] = a;
+}
+
+// line id of the family-r line through the integer coordinates c[b], b != r
+__device__ __forceinline__ int64_t line_id(const GridDesc& g, int r, const int c[3]) {
+  int T[2];
+  trans_axes(g.d, r, T);
+  int64_t lid = c[T[0]];
+  if (g.d == 3) lid += (int64_t)g.n1 * c[T[1]];
+  return lid;
+}
+
+// ---------------------------------------------------------------- compaction
+__device__ __forceinline__ int wave_sum(int v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_down(v, off, 64);
+  return v;
+}
+
+template <class Pred>
+__global__ void __launch_bounds__(KFBI_BLOCK) k_count(int64_t n, Pred pred, int* blk) {
+  int64_t base = (int64_t)blockIdx.x * CMP_CH;
+  int c = 0;
+  for (int j = 0; j < CMP_IT; ++j) {
+    int64_t i = base + (int64_t)j * KFBI_BLOCK + threadIdx.x;
+    if (i < n && pred(i)) ++c;
+  }
+  __shared__ int red[KFBI_BLOCK / 64];
+  c = wave_sum(c);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int w = 0; w < KFBI_BLOCK / 64; ++w) s += red[w];
+    blk[blockIdx.x] = s;
+  }
+}
+
+// exclusive scan of blk[0..nb) in place (one block of 1024 threads); total -> *tot
+__global__ void __launch_bounds__(1024) k_scan(int* blk, int64_t nb, int* tot) {
+  __shared__ long long sh[1024];
+  int64_t per = (nb + 1023) / 1024;
+  int64_t b0 = (int64_t)threadIdx.x * per;
+  int64_t b1 = b0 + per < nb ? b0 + per : nb;
+  long long s = 0;
+  for (int64_t i = b0; i < b1; ++i) s += blk[i];
+  sh[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = 1; off < 1024; off <<= 1) {
+    long long v = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
+    __syncthreads();
+    sh[threadIdx.x] += v;
+    __syncthreads();
+  }
+  long long run = sh[threadIdx.x] - s;
+  for (int64_t i = b0; i < b1; ++i) {
+    int t = blk[i];
+    blk[i] = (int)run;
+    run += t;
+  }
+  if (threadIdx.x == 1023) *tot = (int)sh[1023];
+}
+
+template <class Pred, class Emit>
+__global__ void __launch_bounds__(KFBI_BLOCK) k_emit(int64_t n, Pred pred, Emit emit, const int* blk) {
+  __shared__ int wtot[KFBI_BLOCK / 64];
+  int64_t base = (int64_t)blockIdx.x * CMP_CH;
+  int run = blk[blockIdx.x];
+  int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = 0; j < CMP_IT; ++j) {
+    int64_t i = base + (int64_t)j * KFBI_BLOCK + threadIdx.x;
+    bool f = i < n && pred(i);
+    unsigned long long m = __ballot(f);
+    int r = __popcll(m & ((1ull << lane) - 1ull));
+    if (lane == 0) wtot[wave] = __popcll(m);
+    __syncthreads();
+    int pre = 0, tot = 0;
+    for (int w = 0; w < KFBI_BLOCK / 64; ++w) {
+      if (w < wave) pre += wtot[w];
+      tot += wtot[w];
+    }
+    if (f) emit(i, run + pre + r);
+    run += tot;
+    __syncthreads();
+  }
+}
+
+// ---------------------------------------------------------------- predicates / emitters
+struct RegionArgs {
+  GridDesc g;
+  LSet L;
+  int8_t* region;
+  int* flags;
+};
+
+__global__ void k_regions(RegionArgs a) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.g.n_nodes) return;
+  int c[3];
+  unravel(a.g, i, c);
+  double x = node_x(a.g, c[0]), y = node_x(a.g, c[1]), z = a.g.d == 3 ? node_x(a.g, c[2]) : 0.0;
+  int reg = 0, fl = 0;
+  for (int k = 0; k < a.L.K; ++k) {
+    if (ls_value(a.L, k, x, y, z) < 0.0) {
+      if (reg != 0) fl |= FLAG_OVERLAP;
+      reg = k + 1;
+    }
+  }
+  if (reg != 0) {
+    for (int ax = 0; ax < a.g.d; ++ax)
+      if (c[ax] < MARGIN || c[ax] > a.g.N - MARGIN) fl |= FLAG_MARGIN;
+  }
+  a.region[i] = (int8_t)reg;
+  if (fl) atomicOr(a.flags, fl);
+}
+
+struct SegInfo {
+  int r, s;
+  int64_t lid, a, b;
+};
+
+__device__ __forceinline__ SegInfo seg_info(const GridDesc& g, int64_t seg) {
+  SegInfo o;
+  int64_t L = g.d == 2 ? g.n1 : (int64_t)g.n1 * g.n1;
+  o.s = (int)(seg % g.N);
+  int64_t rest = seg / g.N;
+  o.lid = rest % L;
+  o.r = (int)(rest / L);
+  int T[2];
+  trans_axes(g.d, o.r, T);
+  int c[3] = {0, 0, 0};
+  c[T[0]] = (int)(o.lid % g.n1);
+  if (g.d == 3) c[T[1]] = (int)(o.lid / g.n1);
+  c[o.r] = o.s;
+  o.a = ravel(g, c);
+  c[o.r] = o.s + 1;
+  o.b = ravel(g, c);
+  return o;
+}
+
+struct CandPred {
+  GridDesc g;
+  const int8_t* region;
+  __device__ bool operator()(int64_t item) const {
+    int64_t seg = item / g.K;
+    int k = (int)(item % g.K) + 1;
+    SegInfo si = seg_info(g, seg);
+    return (region[si.a] == k) != (region[si.b] == k);
+  }
+};
+
+struct CandEmit {
+  GridDesc g;
+  const int8_t* region;
+  int *r, *lid, *segs, *k, *ina;
+  __device__ void operator()(int64_t item, int pos) const {
+    int64_t seg = item / g.K;
+    int kk = (int)(item % g.K) + 1;
+    SegInfo si = seg_info(g, seg);
+    r[pos] = si.r;
+    lid[pos] = (int)si.lid;
+    segs[pos] = si.s;
+    k[pos] = kk;
+    ina[pos] = region[si.a] == kk;
+  }
+};
+
+struct BisectArgs {
+  GridDesc g;
+  LSet L;
+  int64_t n;
+  const int *r, *lid, *seg, *k, *ina;
+  double *pos, *nrm;
+  int* acc;
+};
+
+__global__ void k_bisect(BisectArgs a) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const GridDesc& g = a.g;
+  int r = a.r[i], k = a.k[i] - 1;
+  int T[2];
+  trans_axes(g.d, r, T);
+  double X[3] = {0.0, 0.0, 0.0};
+  int lid = a.lid[i];
+  X[T[0]] = node_x(g, lid % g.n1);
+  if (g.d == 3) X[T[1]] = node_x(g, lid / g.n1);
+  double xr0 = g.lo + (double)a.seg[i] * g.h;
+  bool ina = a.ina[i] != 0;
+  double tlo = 0.0, thi = 1.0;
+  for (int it = 0; it < BISECT_STEPS; ++it) {
+    double mid = 0.5 * (tlo + thi);
+    X[r] = xr0 + mid * g.h;
+    bool inside = ls_value(a.L, k, X[0], X[1], X[2]) < 0.0;
+    if (inside == ina)
+      tlo = mid;
+    else
+      thi = mid;
+  }
+  double tr = 0.5 * (tlo + thi);
+  X[r] = xr0 + tr * g.h;
+  double G[3];
+  ls_grad(a.L, k, X[0], X[1], X[2], G);
+  double s = G[0] * G[0] + G[1] * G[1];
+  if (g.d == 3) s = s + G[2] * G[2];
+  double nr = sqrt(s);
+  double n[3] = {G[0] / nr, G[1] / nr, g.d == 3 ? G[2] / nr : 0.0};
+  for (int ax = 0; ax < g.d; ++ax) {
+    a.pos[i * g.d + ax] = X[ax];
+    a.nrm[i * g.d + ax] = n[ax];
+  }
+  a.acc[i] = fabs(n[r]) > g.cos_alpha;
+}
+
+struct AccPred {
+  const int* acc;
+  __device__ bool operator()(int64_t i) const { return acc[i] != 0; }
+};
+
+struct SurfEmit {
+  int d;
+  const double *cpos, *cnrm;
+  const int *r, *lid, *seg, *k;
+  double *pos, *nrm;
+  int* meta;
+  __device__ void operator()(int64_t i, int o) const {
+    double best = -1.0;
+    int arg = 0;
+    for (int ax = 0; ax < d; ++ax) {
+      pos[(int64_t)o * d + ax] = cpos[i * d + ax];
+      nrm[(int64_t)o * d + ax] = cnrm[i * d + ax];
+      double v = fabs(cnrm[i * d + ax]);
+      if (ax == 0 || v > best) {
+        best = v;
+        arg = ax;
+      }
+    }
+    meta[(int64_t)o * 5 + 0] = r[i];
+    meta[(int64_t)o * 5 + 1] = lid[i];
+    meta[(int64_t)o * 5 + 2] = seg[i];
+    meta[(int64_t)o * 5 + 3] = k[i];
+    meta[(int64_t)o * 5 + 4] = arg == r[i];
+  }
+};
+
+__global__ void k_lines(int64_t n, int64_t L, const int* meta, int* ls, int* le) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  int64_t key = (int64_t)meta[i * 5] * L + meta[i * 5 + 1];
+  int64_t kp = i > 0 ? (int64_t)meta[(i - 1) * 5] * L + meta[(i - 1) * 5 + 1] : -1;
+  int64_t kn = i + 1 < n ? (int64_t)meta[(i + 1) * 5] * L + meta[(i + 1) * 5 + 1] : -1;
+  if (kp != key) ls[key] = (int)i;
+  if (kn != key) le[key] = (int)(i + 1);
+}
+
+struct PrimPred {
+  const int* meta;
+  __device__ bool operator()(int64_t i) const { return meta[i * 5 + 4] != 0; }
+};
+
+struct PrimEmit {
+  int *d2s, *s2d;
+  __device__ void operator()(int64_t i, int o) const {
+    d2s[o] = (int)i;
+    s2d[i] = o;
+  }
+};
+
+// ---------------------------------------------------------------- stencils
+struct SurfView {
+  GridDesc g;
+  const double *pos, *nrm;
+  const int* meta;
+  const int *ls, *le;
+  int64_t L;
+  __device__ int fam(int i) const { return meta[(int64_t)i * 5]; }
+  __device__ int iface(int i) const { return meta[(int64_t)i * 5 + 3]; }
+  __device__ bool prim(int i) const { return meta[(int64_t)i * 5 + 4] != 0; }
+  __device__ double x(int i, int ax) const { return pos[(int64_t)i * g.d + ax]; }
+  // nearest point of the interface of `ref` on line (r, lid) to xref along
+  // e_r; primaries only if only_prim; -1 if none (distance in *bd)
+  __device__ int nearest(int r, int64_t lid, int kref, double xref, bool only_prim, double* bd) const {
+    int64_t key = (int64_t)r * L + lid;
+    int bj = -1;
+    double best = 0.0;
+    for (int j = ls[key]; j < le[key]; ++j) {
+      if (iface(j) != kref) continue;
+      if (only_prim && !prim(j)) continue;
+      double dd = fabs(x(j, r) - xref);
+      if (bj < 0 || dd < best) {
+        bj = j;
+        best = dd;
+      }
+    }
+    *bd = best;
+    return bj;
+  }
+};
+
+// one shifted window; false if any point is invalid (or, with need_prim,
+// not primary)
+__device__ bool pick_window(const SurfView& S, int i, int r, const int a0[2], const int (*offs)[2],
+                            int no, const int s[2], bool need_prim, int* out) {
+  const GridDesc& g = S.g;
+  int T[2];
+  trans_axes(g.d, r, T);
+  int ki = S.iface(i);
+  double xr = S.x(i, r);
+  for (int m = 0; m < no; ++m) {
+    int c[3] = {0, 0, 0};
+    int l1 = 0;
+    for (int j = 0; j < g.d - 1; ++j) {
+      int v = a0[j] + offs[m][j] + s[j];
+      if (v < 0 || v > g.N) return false;
+      c[T[j]] = v;
+      int o = offs[m][j] + s[j];
+      l1 += o < 0 ? -o : o;
+    }
+    double bd;
+    int bj = S.nearest(r, line_id(g, r, c), ki, xr, false, &bd);
+    if (bj < 0 || !(bd <= 2.0 * g.h * ((double)l1 + 1.0))) return false;
+    if (need_prim && !S.prim(bj)) return false;
+    out[m] = bj;
+  }
+  return true;
+}
+
+struct StencilArgs {
+  SurfView S;
+  Lattices lat;
+  int64_t n_dof;
+  const int* d2s;
+  int *stD, *stN;
+  uint8_t* s_need;
+  int* flags;
+};
+
+__global__ void k_stencils(StencilArgs a) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n_dof) return;
+  const SurfView& S = a.S;
+  const GridDesc& g = S.g;
+  int i = a.d2s[c];
+  int r = S.fam(i);
+  int T[2];
+  trans_axes(g.d, r, T);
+  int a0[2] = {0, 0};
+  for (int j = 0; j < g.d - 1; ++j) a0[j] = (int)floor((S.x(i, T[j]) - g.lo) / g.h + 0.5);
+  int outD[KFBI_MAXD], outN[KFBI_MAXN];
+  bool okD = false, okN = false;
+  for (int si = 0; si < a.lat.nSD && !okD; ++si)
+    okD = pick_window(S, i, r, a0, a.lat.offD, a.lat.nD, a.lat.shD[si], false, outD);
+  for (int pass = 0; pass < 2 && !okN; ++pass)
+    for (int si = 0; si < a.lat.nSN && !okN; ++si)
+      okN = pick_window(S, i, r, a0, a.lat.offN, a.lat.nN, a.lat.shN[si], pass == 0, outN);
+  if (!okD || !okN) {
+    atomicOr(a.flags, FLAG_UNRESOLVED_STENCIL);
+    for (int m = 0; m < a.lat.nD; ++m) a.stD[c * a.lat.nD + m] = i;
+    for (int m = 0; m < a.lat.nN; ++m) a.stN[c * a.lat.nN + m] = i;
+    return;
+  }
+  for (int m = 0; m < a.lat.nD; ++m) a.stD[c * a.lat.nD + m] = outD[m];
+  for (int m = 0; m < a.lat.nN; ++m) {
+    a.stN[c * a.lat.nN + m] = outN[m];
+    a.s_need[outN[m]] = 1;
+  }
+}
+
+// ---------------------------------------------------------------- density extension
+__device__ void lagrange(double u, const double* nodes, int n, double* w) {
+  for (int j = 0; j < n; ++j) {
+    double wj = 1.0;
+    for (int m = 0; m < n; ++m)
+      if (m != j) wj = wj * (u - nodes[m]) / (nodes[j] - nodes[m]);
+    w[j] = wj;
+  }
+}
+
+struct ExtArgs {
+  SurfView S;
+  int64_t n_surf;
+  const int* s2d;
+  const uint8_t* s_need;
+  int* idx;
+  double* w;
+  int* flags;
+};
+
+// point of family F on the line through `coords` moved by o along `axis`,
+// primary, of the interface of q, nearest to q along e_F; gate relative to oref
+__device__ int ext_point(const SurfView& S, int q, int F, const int coords[3], int axis, int o,
+                         int oref) {
+  const GridDesc& g = S.g;
+  int c[3] = {coords[0], coords[1], coords[2]};
+  c[axis] = c[axis] + o;
+  if (c[axis] < 0 || c[axis] > g.N) return -1;
+  double bd;
+  int bj = S.nearest(F, line_id(g, F, c), S.iface(q), S.x(q, F), true, &bd);
+  int dof = o - oref;
+  dof = dof < 0 ? -dof : dof;
+  if (bj < 0 || !(bd <= 2.0 * g.h * ((double)dof + 1.0))) return -1;
+  return bj;
+}
+
+__global__ void k_extension(ExtArgs a) {
+  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= a.n_surf) return;
+  const SurfView& S = a.S;
+  const GridDesc& g = S.g;
+  const int p = g.p;
+  int* oi = a.idx + q * p;
+  double* ow = a.w + q * p;
+  for (int j = 0; j < p; ++j) {
+    oi[j] = -1;
+    ow[j] = 0.0;
+  }
+  if (S.prim((int)q)) {
+    oi[0] = a.s2d[q];
+    ow[0] = 1.0;
+    return;
+  }
+  if (!a.s_need[q]) return;
+  int r = S.fam((int)q);
+  int rp = 0;
+  double best = fabs(S.nrm[q * g.d]);
+  for (int ax = 1; ax < g.d; ++ax) {
+    double v = fabs(S.nrm[q * g.d + ax]);
+    if (v > best) {
+      best = v;
+      rp = ax;
+    }
+  }
+  int grid[3] = {0, 0, 0};
+  for (int b = 0; b < g.d; ++b)
+    if (b != r) grid[b] = (int)floor((S.x((int)q, b) - g.lo) / g.h + 0.5);
+  double t = (S.x((int)q, r) - g.lo) / g.h;
+  int ft = (int)floor(t);
+  int base = ft - (p / 2 - 1);
+  const int shifts[5] = {0, 1, -1, 2, -2};
+  const int own[8] = {-1, 1, -2, 2, -3, 3, -4, 4};
+  bool have = false;
+  double bestL = 0.0;
+  int bsel[4];
+  double bw[4];
+  // (i) lines of the argmax family along e_r
+  for (int si = 0; si < 5; ++si) {
+    int c[3] = {grid[0], grid[1], grid[2]};
+    c[r] = 0;
+    int sel[4];
+    double nodes[4];
+    bool ok = true;
+    for (int j = 0; j < p && ok; ++j) {
+      int o = base + shifts[si] + j;
+      sel[j] = ext_point(S, (int)q, rp, c, r, o, ft);
+      nodes[j] = (double)o;
+      ok = sel[j] >= 0;
+    }
+    if (!ok) continue;
+    double w[4];
+    lagrange(t, nodes, p, w);
+    double L = 0.0;
+    for (int j = 0; j < p; ++j) L = L + fabs(w[j]);
+    if (!have || L < bestL) {
+      have = true;
+      bestL = L;
+      for (int j = 0; j < p; ++j) {
+        bsel[j] = sel[j];
+        bw[j] = w[j];
+      }
+    }
+  }
+  // (ii) own-family lines moved along each transverse axis
+  int T[2];
+  trans_axes(g.d, r, T);
+  for (int tb = 0; tb < g.d - 1; ++tb) {
+    int b = T[tb];
+    int sel[4], cnt = 0;
+    double nodes[4];
+    for (int m = 0; m < 8 && cnt < p; ++m) {
+      int j = ext_point(S, (int)q, r, grid, b, own[m], 0);
+      if (j >= 0) {
+        sel[cnt] = j;
+        nodes[cnt] = (double)own[m];
+        ++cnt;
+      }
+    }
+    if (cnt < p) continue;
+    double w[4];
+    lagrange(0.0, nodes, p, w);
+    double L = 0.0;
+    for (int j = 0; j < p; ++j) L = L + fabs(w[j]);
+    if (!have || L < bestL) {
+      have = true;
+      bestL = L;
+      for (int j = 0; j < p; ++j) {
+        bsel[j] = sel[j];
+        bw[j] = w[j];
+      }
+    }
+  }
+  if (!have) {
+    atomicOr(a.flags, FLAG_UNRESOLVED_EXT);
+    return;
+  }
+  for (int j = 0; j < p; ++j) {
+    oi[j] = a.s2d[bsel[j]];
+    ow[j] = bw[j];
+  }
+}
+
+// ---------------------------------------------------------------- irregular nodes
+__device__ __forceinline__ bool in_stencil(int order, int o0, int o1, int o2) {
+  if (o0 == 0 && o1 == 0 && o2 == 0) return false;
+  if (order == 2) return (o0 != 0) + (o1 != 0) + (o2 != 0) == 1;
+  return true;
+}
+
+struct IrrPred {
+  GridDesc g;
+  const int8_t* region;
+  __device__ bool operator()(int64_t i) const {
+    int c[3];
+    unravel(g, i, c);
+    for (int ax = 0; ax < g.d; ++ax)
+      if (c[ax] < 1 || c[ax] > g.N - 1) return false;
+    int rp = region[i];
+    int zr = g.d == 3 ? 1 : 0;
+    for (int o2 = -zr; o2 <= zr; ++o2)
+      for (int o1 = -1; o1 <= 1; ++o1)
+        for (int o0 = -1; o0 <= 1; ++o0) {
+          if (!in_stencil(g.order, o0, o1, o2)) continue;
+          int q[3] = {c[0] + o0, c[1] + o1, c[2] + o2};
+          if (region[ravel(g, q)] != rp) return true;
+        }
+    return false;
+  }
+};
+
+struct IdxEmit {
+  int* out;
+  __device__ void operator()(int64_t i, int o) const { out[o] = (int)i; }
+};
+
+__global__ void k_need_irr(GridDesc g, int64_t n_irr, const int* irr, const int8_t* region,
+                           uint8_t* need) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_irr) return;
+  int64_t P = irr[t];
+  int c[3];
+  unravel(g, P, c);
+  int rp = region[P];
+  int zr = g.d == 3 ? 1 : 0;
+  for (int o2 = -zr; o2 <= zr; ++o2)
+    for (int o1 = -1; o1 <= 1; ++o1)
+      for (int o0 = -1; o0 <= 1; ++o0) {
+        if (!in_stencil(g.order, o0, o1, o2)) continue;
+        int q[3] = {c[0] + o0, c[1] + o1, c[2] + o2};
+        int64_t Q = ravel(g, q);
+        int rq = region[Q];
+        if (rq == rp) continue;
+        if (rp != 0) need[(int64_t)(rp - 1) * g.n_nodes + Q] = 1;
+        if (rq != 0) need[(int64_t)(rq - 1) * g.n_nodes + Q] = 1;
+      }
+}
+
+__device__ __forceinline__ int block_start(const GridDesc& g, double x) {
+  int q = g.p;
+  int st = (int)floor((x - g.lo) / g.h + 0.5) - q / 2;
+  if (st < 0) st = 0;
+  if (st > g.N - q) st = g.N - q;
+  return st;
+}
+
+__global__ void k_need_blocks(GridDesc g, int64_t n_dof, const int* d2s, const double* spos,
+                              const int* meta, const int8_t* region, uint8_t* need) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= n_dof) return;
+  int s = d2s[c];
+  int k = meta[(int64_t)s * 5 + 3];
+  int st[3] = {0, 0, 0};
+  for (int ax = 0; ax < g.d; ++ax) st[ax] = block_start(g, spos[(int64_t)s * g.d + ax]);
+  int q1 = g.p + 1;
+  int nz = g.d == 3 ? q1 : 1;
+  for (int b2 = 0; b2 < nz; ++b2)
+    for (int b1 = 0; b1 < q1; ++b1)
+      for (int b0 = 0; b0 < q1; ++b0) {
+        int cc[3] = {st[0] + b0, st[1] + b1, st[2] + b2};
+        int64_t Q = ravel(g, cc);
+        int rq = region[Q];
+        if (rq == k) continue;
+        need[(int64_t)(k - 1) * g.n_nodes + Q] = 1;
+        if (rq != 0) need[(int64_t)(rq - 1) * g.n_nodes + Q] = 1;
+      }
+}
+
+struct NeedPred {
+  const uint8_t* need;
+  __device__ bool operator()(int64_t i) const { return need[i] != 0; }
+};
+
+struct CorrEmit {
+  int64_t n_nodes;
+  int *k, *node;
+  __device__ void operator()(int64_t i, int o) const {
+    k[o] = (int)(i / n_nodes) + 1;
+    node[o] = (int)(i % n_nodes);
+  }
+};
+
+// ---------------------------------------------------------------- closest centres
+struct BinArgs {
+  GridDesc g;
+  int64_t n_dof, nca, ncell;
+  const int* d2s;
+  const double* spos;
+  const int* meta;
+  int* cnt;
+  int* items;
+};
+
+__device__ __forceinline__ int64_t bin_of(const GridDesc& g, int64_t nca, const double* x, int k,
+                                          int64_t ncell, int cc[3]) {
+  double cs = 2.0 * g.h;
+  for (int ax = 0; ax < 3; ++ax) cc[ax] = 0;
+  for (int ax = 0; ax < g.d; ++ax) {
+    int v = (int)floor((x[ax] - g.lo) / cs);
+    if (v < 0) v = 0;
+    if (v > nca - 1) v = (int)nca - 1;
+    cc[ax] = v;
+  }
+  int64_t cell = cc[0] + nca * (cc[1] + (g.d == 3 ? nca * cc[2] : 0));
+  return (int64_t)(k - 1) * ncell + cell;
+}
+
+__global__ void k_bin_count(BinArgs a) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n_dof) return;
+  int s = a.d2s[c];
+  int cc[3];
+  int64_t key = bin_of(a.g, a.nca, a.spos + (int64_t)s * a.g.d, a.meta[(int64_t)s * 5 + 3], a.ncell, cc);
+  atomicAdd(a.cnt + key, 1);
+}
+
+__global__ void k_bin_fill(BinArgs a, const int* start, int* cursor) {
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n_dof) return;
+  int s = a.d2s[c];
+  int cc[3];
+  int64_t key = bin_of(a.g, a.nca, a.spos + (int64_t)s * a.g.d, a.meta[(int64_t)s * 5 + 3], a.ncell, cc);
+  int pos = start[key] + atomicAdd(cursor + key, 1);
+  a.items[pos] = (int)c;
+}
+
+struct OwnerArgs {
+  GridDesc g;
+  int64_t n_corr, nca, ncell;
+  const int *ck, *cnode;
+  const int* d2s;
+  const double* spos;
+  const int *start, *cnt, *items;
+  int* owner;
+  int* flags;
+};
+
+__global__ void k_owner(OwnerArgs a) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.n_corr) return;
+  const GridDesc& g = a.g;
+  int k = a.ck[e];
+  int c[3];
+  unravel(g, a.cnode[e], c);
+  double X[3] = {node_x(g, c[0]), node_x(g, c[1]), g.d == 3 ? node_x(g, c[2]) : 0.0};
+  int cq[3];
+  bin_of(g, a.nca, X, k, a.ncell, cq);
+  int64_t koff = (int64_t)(k - 1) * a.ncell;
+  double cs = 2.0 * g.h;
+  double d2min = 0.0;
+  bool found = false;
+  int mfinal = -1;
+  int nz = g.d == 3 ? 1 : 0;
+  for (int m = 0; m <= a.nca; ++m) {
+    for (int z = -m * nz; z <= m * nz; ++z)
+      for (int y = -m; y <= m; ++y)
+        for (int x = -m; x <= m; ++x) {
+          int ax = x < 0 ? -x : x, ay = y < 0 ? -y : y, az = z < 0 ? -z : z;
+          int cheb = ax > ay ? ax : ay;
+          cheb = cheb > az ? cheb : az;
+          if (cheb != m) continue;
+          int cc[3] = {cq[0] + x, cq[1] + y, cq[2] + z};
+          bool ok = true;
+          for (int t = 0; t < g.d; ++t) ok = ok && cc[t] >= 0 && cc[t] < a.nca;
+          if (!ok) continue;
+          int64_t key = koff + cc[0] + a.nca * (cc[1] + (g.d == 3 ? a.nca * cc[2] : 0));
+          for (int j = a.start[key]; j < a.start[key] + a.cnt[key]; ++j) {
+            int ctr = a.items[j];
+            const double* P = a.spos + (int64_t)a.d2s[ctr] * g.d;
+            double dx = X[0] - P[0], dy = X[1] - P[1];
+            double d2 = dx * dx + dy * dy;
+            if (g.d == 3) {
+              double dz = X[2] - P[2];
+              d2 = d2 + dz * dz;
+            }
+            if (!found || d2 < d2min) {
+              found = true;
+              d2min = d2;
+            }
+          }
+        }
+    double lim = (double)m * cs;
+    if (found && d2min * (1.0 + TIE_BAND) < lim * lim) {
+      mfinal = m;
+      break;
+    }
+  }
+  if (mfinal < 0) {
+    if (!found) {
+      atomicOr(a.flags, FLAG_UNRESOLVED_OWNER);
+      a.owner[e] = 0;
+      return;
+    }
+    mfinal = (int)a.nca;
+  }
+  double thr = d2min * (1.0 + TIE_BAND);
+  int best = -1;
+  for (int m = 0; m <= mfinal; ++m)
+    for (int z = -m * nz; z <= m * nz; ++z)
+      for (int y = -m; y <= m; ++y)
+        for (int x = -m; x <= m; ++x) {
+          int ax = x < 0 ? -x : x, ay = y < 0 ? -y : y, az = z < 0 ? -z : z;
+          int cheb = ax > ay ? ax : ay;
+          cheb = cheb > az ? cheb : az;
+          if (cheb != m) continue;
+          int cc[3] = {cq[0] + x, cq[1] + y, cq[2] + z};
+          bool ok = true;
+          for (int t = 0; t < g.d; ++t) ok = ok && cc[t] >= 0 && cc[t] < a.nca;
+          if (!ok) continue;
+          int64_t key = koff + cc[0] + a.nca * (cc[1] + (g.d == 3 ? a.nca * cc[2] : 0));
+          for (int j = a.start[key]; j < a.start[key] + a.cnt[key]; ++j) {
+            int ctr = a.items[j];
+            const double* P = a.spos + (int64_t)a.d2s[ctr] * g.d;
+            double dx = X[0] - P[0], dy = X[1] - P[1];
+            double d2 = dx * dx + dy * dy;
+            if (g.d == 3) {
+              double dz = X[2] - P[2];
+              d2 = d2 + dz * dz;
+            }
+            if (d2 <= thr && (best < 0 || ctr < best)) best = ctr;
+          }
+        }
+  a.owner[e] = best;
+}
+
+// ---------------------------------------------------------------- host helpers
+inline unsigned nblk(int64_t n, int b = KFBI_BLOCK) { return (unsigned)((n + b - 1) / b); }
+
+template <class T>
+kfbi_status grow(T** p, int64_t* cap, int64_t n) {
+  if (n <= *cap && *p) return KFBI_OK;
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  int64_t c = n + n / 4 + 64;
+  if (hipMalloc((void**)p, (size_t)c * sizeof(T)) != hipSuccess) {
+    *cap = 0;
+    kfbi_set_error("device allocation of %lld bytes failed", (long long)(c * sizeof(T)));
+    return KFBI_E_OOM;
+  }
+  *cap = c;
+  return KFBI_OK;
+}
+
+// (re)allocate exactly n elements (contents discarded)
+template <class T>
+kfbi_status realloc_n(T** p, int64_t n) {
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  if (n < 1) n = 1;
+  if (hipMalloc((void**)p, (size_t)n * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    kfbi_set_error("device allocation of %lld bytes failed", (long long)(n * sizeof(T)));
+    return KFBI_E_OOM;
+  }
+  return KFBI_OK;
+}
+
+inline int64_t headroom(int64_t n) { return n + n / 4 + 64; }
+
+kfbi_status ensure_blk(kfbi_plan* pl, int64_t nb) { return grow(&pl->blk, &pl->cap_blk, nb + 1); }
+
+template <class Pred>
+kfbi_status compact_count(kfbi_plan* pl, int64_t n, Pred pred, int64_t* count) {
+  int64_t nb = (n + CMP_CH - 1) / CMP_CH;
+  if (nb == 0) {
+    *count = 0;
+    return KFBI_OK;
+  }
+  KCHK(ensure_blk(pl, nb));
+  hipLaunchKernelGGL(k_count<Pred>, dim3((unsigned)nb), dim3(KFBI_BLOCK), 0, pl->stream, n, pred, pl->blk);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, pl->stream, pl->blk, nb, pl->blk_total);
+  HIPCHK(hipMemcpyAsync(pl->h_pinned, pl->blk_total, sizeof(int), hipMemcpyDeviceToHost, pl->stream));
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  *count = pl->h_pinned[0];
+  return KFBI_OK;
+}
+
+template <class Pred, class Emit>
+void compact_emit(kfbi_plan* pl, int64_t n, Pred pred, Emit emit) {
+  int64_t nb = (n + CMP_CH - 1) / CMP_CH;
+  if (nb == 0) return;
+  hipLaunchKernelGGL((k_emit<Pred, Emit>), dim3((unsigned)nb), dim3(KFBI_BLOCK), 0, pl->stream, n, pred,
+                     emit, pl->blk);
+}
+
+// lattice of degree m in D dims (D <= 2), stacking offsets 0, +1, -1, ...
+void lattice(int D, int m, std::vector<std::array<int, 3>>& out) {
+  out.clear();
+  if (m < 0) return;
+  auto window = [](int L, std::vector<int>& w) {
+    w.clear();
+    int a = -((L - 1) / 2);
+    for (int i = 0; i < L; ++i) w.push_back(a + i);
+  };
+  auto stack = [](int j) { return j == 0 ? 0 : (j % 2 == 1 ? (j + 1) / 2 : -(j / 2)); };
+  std::vector<int> w;
+  if (D == 1) {
+    window(m + 1, w);
+    for (int o : w) out.push_back({o, 0, 0});
+    return;
+  }
+  for (int j = 0; j <= m; ++j) {
+    window(m - j + 1, w);
+    for (int o : w) out.push_back({o, stack(j), 0});
+  }
+}
+
+void shift_list(int d, const std::vector<std::array<int, 3>>& offs, int (*sh)[2], int* n) {
+  std::vector<std::array<int, 2>> cand;
+  if (d == 2) {
+    int c[9] = {0, 1, -1, 2, -2, 3, -3, 4, -4};
+    for (int v : c) cand.push_back({v, 0});
+  } else {
+    for (int a = -4; a <= 4; ++a)
+      for (int b = -4; b <= 4; ++b) cand.push_back({a, b});
+    std::stable_sort(cand.begin(), cand.end(), [](const std::array<int, 2>& s, const std::array<int, 2>& t) {
+      int ks0 = std::abs(s[0]) + std::abs(s[1]), kt0 = std::abs(t[0]) + std::abs(t[1]);
+      if (ks0 != kt0) return ks0 < kt0;
+      if (std::abs(s[1]) != std::abs(t[1])) return std::abs(s[1]) < std::abs(t[1]);
+      if (s[0] != t[0]) return s[0] > t[0];
+      return s[1] > t[1];
+    });
+  }
+  *n = 0;
+  for (auto& s : cand) {
+    bool member = false;
+    for (auto& o : offs)
+      if (o[0] == -s[0] && (d == 2 || o[1] == -s[1])) member = true;
+    if (member) {
+      sh[*n][0] = s[0];
+      sh[*n][1] = s[1];
+      ++*n;
+    }
+  }
+}
+
+}  // namespace
+
+// ---------------------------------------------------------------- S0 driver
+kfbi_status geo_setup(kfbi_plan* pl) {
+  GridDesc g = pl->g;
+  hipStream_t st = pl->stream;
+  LSet L;
+  L.K = g.K;
+  for (int k = 0; k < g.K; ++k) {
+    L.kind[k] = pl->prob.iface[k].kind;
+    for (int j = 0; j < KFBI_LS_NPARAM; ++j) L.p[k][j] = pl->prob.iface[k].p[j];
+  }
+  HIPCHK(hipMemsetAsync(pl->d_flags, 0, sizeof(int), st));
+  // regions
+  hipLaunchKernelGGL(k_regions, dim3(nblk(g.n_nodes)), dim3(KFBI_BLOCK), 0, st,
+                     RegionArgs{g, L, pl->region, pl->d_flags});
+  HIPCHK(hipMemcpyAsync(pl->h_pinned + 1, pl->d_flags, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  if (pl->h_pinned[1]) return kfbi_flags_status(pl->h_pinned[1]);
+
+  // candidates: (segment, interface) items with a sign change
+  int64_t n_items = pl->n_seg * g.K;
+  CandPred cp{g, pl->region};
+  int64_t nc;
+  KCHK(compact_count(pl, n_items, cp, &nc));
+  if (nc == 0) {
+    kfbi_set_error("no grid segment crosses an interface");
+    return KFBI_E_INVALID;
+  }
+  if (nc > pl->cap_cand) {
+    int64_t cap = headroom(nc);
+    pl->cap_cand = 0;
+    KCHK(realloc_n(&pl->c_r, cap));
+    KCHK(realloc_n(&pl->c_lid, cap));
+    KCHK(realloc_n(&pl->c_seg, cap));
+    KCHK(realloc_n(&pl->c_k, cap));
+    KCHK(realloc_n(&pl->c_ina, cap));
+    KCHK(realloc_n(&pl->c_acc, cap));
+    KCHK(realloc_n(&pl->c_pos, cap * g.d));
+    KCHK(realloc_n(&pl->c_nrm, cap * g.d));
+    pl->cap_cand = cap;
+  }
+  pl->n_cand = nc;
+  compact_emit(pl, n_items, cp, CandEmit{g, pl->region, pl->c_r, pl->c_lid, pl->c_seg, pl->c_k, pl->c_ina});
+  hipLaunchKernelGGL(k_bisect, dim3(nblk(nc)), dim3(KFBI_BLOCK), 0, st,
+                     BisectArgs{g, L, nc, pl->c_r, pl->c_lid, pl->c_seg, pl->c_k, pl->c_ina, pl->c_pos,
+                                pl->c_nrm, pl->c_acc});
+
+  // surface table
+  AccPred ap{pl->c_acc};
+  int64_t ns;
+  KCHK(compact_count(pl, nc, ap, &ns));
+  if (ns > pl->cap_surf) {
+    int64_t cap = headroom(ns);
+    pl->cap_surf = 0;
+    KCHK(realloc_n(&pl->s_pos, cap * g.d));
+    KCHK(realloc_n(&pl->s_nrm, cap * g.d));
+    KCHK(realloc_n(&pl->s_meta, cap * 5));
+    KCHK(realloc_n(&pl->s2d, cap));
+    KCHK(realloc_n(&pl->s_need, cap));
+    KCHK(realloc_n(&pl->ext_idx, cap * g.p));
+    KCHK(realloc_n(&pl->ext_w, cap * g.p));
+    KCHK(realloc_n(&pl->psiS, cap));
+    KCHK(realloc_n(&pl->aS, cap));
+    pl->cap_surf = cap;
+  }
+  pl->n_surf = ns;
+  compact_emit(pl, nc, ap, SurfEmit{g.d, pl->c_pos, pl->c_nrm, pl->c_r, pl->c_lid, pl->c_seg, pl->c_k,
+                                    pl->s_pos, pl->s_nrm, pl->s_meta});
+  int64_t L1 = g.d == 2 ? g.n1 : (int64_t)g.n1 * g.n1;
+  HIPCHK(hipMemsetAsync(pl->line_start, 0, sizeof(int) * pl->n_lines, st));
+  HIPCHK(hipMemsetAsync(pl->line_end, 0, sizeof(int) * pl->n_lines, st));
+  hipLaunchKernelGGL(k_lines, dim3(nblk(ns)), dim3(KFBI_BLOCK), 0, st, ns, L1, pl->s_meta, pl->line_start,
+                     pl->line_end);
+
+  // primary points
+  PrimPred pp{pl->s_meta};
+  int64_t nd;
+  KCHK(compact_count(pl, ns, pp, &nd));
+  if (nd == 0) {
+    kfbi_set_error("no primary surface points");
+    return KFBI_E_INVALID;
+  }
+  if (nd > pl->cap_dof) {
+    int64_t cap = headroom(nd);
+    pl->cap_dof = 0;
+    KCHK(realloc_n(&pl->d2s, cap));
+    KCHK(realloc_n(&pl->stD, cap * pl->nD));
+    KCHK(realloc_n(&pl->stN, cap * pl->nN));
+    KCHK(realloc_n(&pl->MinvT, cap * pl->nC * pl->nC));
+    KCHK(realloc_n(&pl->cond, cap));
+    KCHK(realloc_n(&pl->U, cap * pl->nC));
+    KCHK(realloc_n(&pl->dn_in, cap));
+    KCHK(realloc_n(&pl->dn_out, cap));
+    KCHK(realloc_n(&pl->bvec, cap));
+    KCHK(realloc_n(&pl->work, cap));
+    KCHK(realloc_n(&pl->work2, cap));
+    KCHK(realloc_n(&pl->cell_items, cap));
+    pl->cap_dof = cap;
+  }
+  pl->n_dof = nd;
+  HIPCHK(hipMemsetAsync(pl->s2d, 0xff, sizeof(int) * ns, st));
+  compact_emit(pl, ns, pp, PrimEmit{pl->d2s, pl->s2d});
+
+  // collocation stencils
+  Lattices lat;
+  std::vector<std::array<int, 3>> offs;
+  lattice(g.d - 1, g.p, offs);
+  lat.nD = (int)offs.size();
+  for (int m = 0; m < lat.nD; ++m) {
+    lat.offD[m][0] = offs[m][0];
+    lat.offD[m][1] = offs[m][1];
+  }
+  shift_list(g.d, offs, lat.shD, &lat.nSD);
+  lattice(g.d - 1, g.p - 1, offs);
+  lat.nN = (int)offs.size();
+  for (int m = 0; m < lat.nN; ++m) {
+    lat.offN[m][0] = offs[m][0];
+    lat.offN[m][1] = offs[m][1];
+  }
+  shift_list(g.d, offs, lat.shN, &lat.nSN);
+  SurfView S{g, pl->s_pos, pl->s_nrm, pl->s_meta, pl->line_start, pl->line_end, L1};
+  HIPCHK(hipMemsetAsync(pl->s_need, 0, ns, st));
+  hipLaunchKernelGGL(k_stencils, dim3(nblk(nd)), dim3(KFBI_BLOCK), 0, st,
+                     StencilArgs{S, lat, nd, pl->d2s, pl->stD, pl->stN, pl->s_need, pl->d_flags});
+  hipLaunchKernelGGL(k_extension, dim3(nblk(ns)), dim3(KFBI_BLOCK), 0, st,
+                     ExtArgs{S, ns, pl->s2d, pl->s_need, pl->ext_idx, pl->ext_w, pl->d_flags});
+
+  // irregular nodes
+  IrrPred ip{g, pl->region};
+  int64_t ni;
+  KCHK(compact_count(pl, g.n_nodes, ip, &ni));
+  if (ni > pl->cap_irr) {
+    int64_t cap = headroom(ni);
+    pl->cap_irr = 0;
+    KCHK(realloc_n(&pl->irr, cap));
+    pl->cap_irr = cap;
+  }
+  pl->n_irr = ni;
+  compact_emit(pl, g.n_nodes, ip, IdxEmit{pl->irr});
+
+  // correction entries
+  HIPCHK(hipMemsetAsync(pl->need, 0, (size_t)g.K * g.n_nodes, st));
+  if (ni > 0)
+    hipLaunchKernelGGL(k_need_irr, dim3(nblk(ni)), dim3(KFBI_BLOCK), 0, st, g, ni, pl->irr, pl->region,
+                       pl->need);
+  hipLaunchKernelGGL(k_need_blocks, dim3(nblk(nd)), dim3(KFBI_BLOCK), 0, st, g, nd, pl->d2s, pl->s_pos,
+                     pl->s_meta, pl->region, pl->need);
+  NeedPred np{pl->need};
+  int64_t ne;
+  KCHK(compact_count(pl, (int64_t)g.K * g.n_nodes, np, &ne));
+  if (ne > pl->cap_corr) {
+    int64_t cap = headroom(ne);
+    pl->cap_corr = 0;
+    KCHK(realloc_n(&pl->ce_k, cap));
+    KCHK(realloc_n(&pl->ce_node, cap));
+    KCHK(realloc_n(&pl->ce_owner, cap));
+    pl->cap_corr = cap;
+  }
+  pl->n_corr = ne;
+  compact_emit(pl, (int64_t)g.K * g.n_nodes, np, CorrEmit{g.n_nodes, pl->ce_k, pl->ce_node});
+
+  // closest centres: bin the centres of every interface on a 2h lattice
+  int64_t nkeys = (int64_t)g.K * pl->ncell;
+  HIPCHK(hipMemsetAsync(pl->cell_count, 0, sizeof(int) * (nkeys + 1), st));
+  BinArgs ba{g, nd, pl->ncell_axis, pl->ncell, pl->d2s, pl->s_pos, pl->s_meta, pl->cell_count, nullptr};
+  hipLaunchKernelGGL(k_bin_count, dim3(nblk(nd)), dim3(KFBI_BLOCK), 0, st, ba);
+  HIPCHK(hipMemcpyAsync(pl->cell_start, pl->cell_count, sizeof(int) * nkeys, hipMemcpyDeviceToDevice, st));
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, pl->cell_start, nkeys, pl->blk_total);
+  KCHK(ensure_blk(pl, nkeys));
+  int* cursor = pl->blk;   // scan scratch reused as per-cell cursor
+  HIPCHK(hipMemsetAsync(cursor, 0, sizeof(int) * nkeys, st));
+  ba.items = pl->cell_items;
+  hipLaunchKernelGGL(k_bin_fill, dim3(nblk(nd)), dim3(KFBI_BLOCK), 0, st, ba, pl->cell_start, cursor);
+  if (ne > 0)
+    hipLaunchKernelGGL(k_owner, dim3(nblk(ne)), dim3(KFBI_BLOCK), 0, st,
+                       OwnerArgs{g, ne, pl->ncell_axis, pl->ncell, pl->ce_k, pl->ce_node, pl->d2s, pl->s_pos,
+                                 pl->cell_start, pl->cell_count, pl->cell_items, pl->ce_owner, pl->d_flags});
+  HIPCHK(hipMemcpyAsync(pl->h_pinned + 1, pl->d_flags, sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipStreamSynchronize(st));
+  HIPCHK(hipGetLastError());
+  if (pl->h_pinned[1]) return kfbi_flags_status(pl->h_pinned[1]);
+  return KFBI_OK;
+}
+
+// PDE collocation lattice (degree p-2 in d dims) for other translation units
+void kfbi_pde_lattice(int d, int p, int (*off)[3], int* n) {
+  std::vector<std::array<int, 3>> pts;
+  int m = p - 2;
+  *n = 0;
+  if (m < 0) return;
+  if (d == 2) {
+    lattice(2, m, pts);
+    for (auto& o : pts) {
+      off[*n][0] = o[0];
+      off[*n][1] = o[1];
+      off[*n][2] = 0;
+      ++*n;
+    }
+    return;
+  }
+  auto stack = [](int j) { return j == 0 ? 0 : (j % 2 == 1 ? (j + 1) / 2 : -(j / 2)); };
+  for (int j = 0; j <= m; ++j) {
+    lattice(2, m - j, pts);
+    for (auto& o : pts) {
+      off[*n][0] = o[0];
+      off[*n][1] = o[1];
+      off[*n][2] = stack(j);
+      ++*n;
+    }
+  }
+}
+
+void kfbi_dn_lattice(int D, int m, int (*off)[2], int* n) {
+  std::vector<std::array<int, 3>> pts;
+  lattice(D, m, pts);
+  *n = (int)pts.size();
+  for (int i = 0; i < *n; ++i) {
+    off[i][0] = pts[i][0];
+    off[i][1] = pts[i][1];
+  }
+}

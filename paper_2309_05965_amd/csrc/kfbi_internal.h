@@ -1,0 +1,142 @@
+// Internal definitions of the KFBI library: the plan, device buffers and the
+// host launchers of every kernel translation unit.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include <string>
+#include <vector>
+
+#include "../../include/kfbi.h"
+
+#define KFBI_BLOCK 256
+#define KFBI_MAXC 35       // max polynomial coefficients (3D, degree 4)
+#define KFBI_MAXP 10       // max PDE collocation points
+#define KFBI_MAXD 15       // max Dirichlet points
+#define KFBI_MAXN 10       // max Neumann points
+#define KFBI_GMRES_MAX 512
+
+// device-side status bits (OR-ed into plan->d_flags)
+enum {
+  FLAG_OVERLAP = 1,
+  FLAG_MARGIN = 2,
+  FLAG_UNRESOLVED_STENCIL = 4,
+  FLAG_UNRESOLVED_EXT = 8,
+  FLAG_UNRESOLVED_OWNER = 16,
+  FLAG_SINGULAR = 32,
+  FLAG_NONFINITE = 64
+};
+
+struct GridDesc {           // plain-value grid/problem description for kernels
+  int d, order, p, N, n1, K;
+  double lo, hi, h, kappa, cos_alpha, beta_in, beta_out;
+  int64_t n_nodes;
+};
+
+struct kfbi_plan {
+  kfbi_problem prob;
+  GridDesc g;
+  hipStream_t stream;
+  int nP, nD, nN, nC;            // collocation sizes
+  int64_t n_seg;                 // grid segments = d N (N+1)^(d-1)
+  int64_t n_lines;               // d (N+1)^(d-1)
+  int64_t n_cand, n_surf, n_dof, n_irr, n_corr;
+  int64_t ncell_axis, ncell;     // closest-centre bins (per interface)
+  double cond_max;
+  bool ready;
+
+  // capacities (elements) of the count-dependent buffers
+  int64_t cap_cand, cap_surf, cap_dof, cap_irr, cap_corr;
+
+  // grid-sized
+  int8_t* region;
+  uint8_t* need;                 // [K][n_nodes] correction-entry flags
+  double* Cg;                    // [K][n_nodes] correction values
+  double *Fm, *Fs, *T1, *T2, *vbuf, *vsbuf;
+  // candidates
+  int *c_r, *c_lid, *c_seg, *c_k, *c_ina;
+  double *c_pos, *c_nrm;
+  int* c_acc;
+  // surface table
+  double *s_pos, *s_nrm;
+  int *s_meta;                   // [n_surf][5]: fam, lid, seg, iface, prim
+  int *s2d, *d2s;
+  uint8_t* s_need;
+  int *line_start, *line_end;
+  // centres
+  int *stD, *stN;
+  int* ext_idx;
+  double* ext_w;
+  double* MinvT;                 // [n_dof][nC][nC], element (alpha, j) at j*nC + alpha
+  double* cond;
+  double *psiS, *aS, *U, *dn_in, *dn_out;
+  // irregular nodes and correction entries
+  int* irr;
+  int *ce_k, *ce_node, *ce_owner;
+  // closest-centre bins
+  int *cell_count, *cell_start, *cell_items;
+  // scan scratch
+  int *blk, *blk_total;
+  int64_t cap_blk;
+  int* d_flags;
+  int* h_pinned;                 // pinned host scratch for counts
+  double* h_dpinned;
+  // box solver tables
+  double *tw, *eig1;
+  // GMRES
+  double *V, *Hm, *gv, *cs, *sn, *work, *work2, *bvec, *scal;
+  int gm_cap;
+  int64_t gm_n;
+  // box-solve event timing
+  int prof_on;
+  std::vector<hipEvent_t>* prof_ev;
+  int64_t prof_launches;
+};
+
+// ---------------------------------------------------------------- errors
+void kfbi_set_error(const char* fmt, ...);
+kfbi_status kfbi_hip_status(hipError_t e, const char* what);
+kfbi_status kfbi_flags_status(int flags);
+
+#define HIPCHK(call)                                              \
+  do {                                                            \
+    hipError_t e_ = (call);                                       \
+    if (e_ != hipSuccess) return kfbi_hip_status(e_, #call);      \
+  } while (0)
+
+#define KCHK(call)                                                \
+  do {                                                            \
+    kfbi_status s_ = (call);                                      \
+    if (s_ != KFBI_OK) return s_;                                 \
+  } while (0)
+
+// ---------------------------------------------------------------- launchers
+// geometry.hip (step S0)
+kfbi_status geo_setup(kfbi_plan* pl);
+// collocation.hip (step S1)
+kfbi_status colloc_factor(kfbi_plan* pl);
+// operator.hip (steps S2, S4, S5 and right-hand sides)
+void op_extend(kfbi_plan* pl, const double* psi, double* psiS);
+void op_coefficients(kfbi_plan* pl, const double* a, const double* b, const double* ftilde);
+void op_correction_values(kfbi_plan* pl);
+void op_rhs_base(kfbi_plan* pl, const double* fhat, const double* gB, double* F);
+void op_rhs_correct(kfbi_plan* pl, double* F, bool overwrite);
+void op_boundary(kfbi_plan* pl, const double* gB, double* v);
+void op_normal_derivatives(kfbi_plan* pl, const double* v, double* dn_in, double* dn_out,
+                           double* Apsi);
+void op_bie_rhs(kfbi_plan* pl, const double* g2, const double* dn_in, const double* dn_out,
+                double* b);
+// dst.hip (step S3)
+kfbi_status dst_init(kfbi_plan* pl);
+void dst_solve(kfbi_plan* pl, const double* F, double* v);
+// gmres.hip (step S6)
+void gm_residual_start(kfbi_plan* pl, const double* b, const double* Ax0, int use_x0);
+void gm_arnoldi(kfbi_plan* pl, int j);
+void gm_update(kfbi_plan* pl, int k, double* x, int use_x0);
+void gm_true_residual(kfbi_plan* pl, const double* b, const double* Ax, double* out2);
+
+// ---------------------------------------------------------------- device helpers
+__host__ __device__ inline int kfbi_ncoef(int d, int p) {
+  return d == 2 ? (p + 1) * (p + 2) / 2 : (p + 1) * (p + 2) * (p + 3) / 6;
+}

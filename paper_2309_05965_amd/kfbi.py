@@ -1,0 +1,265 @@
+"""ctypes binding of libkfbi.so (C ABI in include/kfbi.h).
+
+Argument marshalling only: every step of the method runs in the library's
+HIP kernels.  Device memory and streams come from PyTorch: arrays are
+torch tensors on a HIP device, passed by data_ptr(), and the plan's work is
+ordered on the torch stream current at plan creation.  The binding raises
+if the library is not built; there is no fallback path.
+"""
+import ctypes
+import os
+
+import torch
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(_HERE, "libkfbi.so")
+
+KINDS = {"ellipse2d": 1, "star2d": 2, "sphere3d": 3, "ellipsoid3d": 4, "torus3d": 5}
+STATUS = {0: "OK", 1: "INVALID", 2: "UNRESOLVED", 3: "SINGULAR", 4: "NOT_CONVERGED",
+          5: "NONFINITE", 6: "DEVICE", 7: "OOM"}
+EXPORT = {"region": 0, "surf_pos": 1, "surf_nrm": 2, "surf_meta": 3, "dof_surf": 4,
+          "stencil_d": 5, "stencil_n": 6, "ext_idx": 7, "ext_w": 8, "pde_pts": 9,
+          "irregular": 10, "corr": 11, "cond": 12}
+
+c_double_p = ctypes.c_void_p
+
+
+class LevelSet(ctypes.Structure):
+    _fields_ = [("kind", ctypes.c_int32), ("reserved", ctypes.c_int32), ("p", ctypes.c_double * 32)]
+
+
+class Problem(ctypes.Structure):
+    _fields_ = [("dim", ctypes.c_int32), ("order", ctypes.c_int32), ("N", ctypes.c_int32),
+                ("n_iface", ctypes.c_int32), ("lo", ctypes.c_double), ("hi", ctypes.c_double),
+                ("beta_in", ctypes.c_double), ("beta_out", ctypes.c_double),
+                ("kappa", ctypes.c_double), ("cos_alpha", ctypes.c_double),
+                ("iface", LevelSet * 4)]
+
+
+class Sizes(ctypes.Structure):
+    _fields_ = [("n_nodes", ctypes.c_int64), ("n_surf", ctypes.c_int64), ("n_dof", ctypes.c_int64),
+                ("n_irregular", ctypes.c_int64), ("n_corr", ctypes.c_int64),
+                ("n_pde", ctypes.c_int32), ("n_dir", ctypes.c_int32), ("n_neu", ctypes.c_int32),
+                ("n_coef", ctypes.c_int32), ("h", ctypes.c_double), ("cond_max", ctypes.c_double)]
+
+
+class Data(ctypes.Structure):
+    _fields_ = [("g1", c_double_p), ("g2", c_double_p), ("ftilde", c_double_p),
+                ("fhat", c_double_p), ("gB", c_double_p)]
+
+
+class Opts(ctypes.Structure):
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("use_x0", ctypes.c_int32)]
+
+
+class Info(ctypes.Structure):
+    _fields_ = [("iters", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("est_rel_res", ctypes.c_double), ("true_rel_res", ctypes.c_double)]
+
+
+ABI = {
+    "kfbi_plan_create": ([ctypes.POINTER(Problem), ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "kfbi_plan_setup": ([ctypes.c_void_p, ctypes.POINTER(Problem)], ctypes.c_int),
+    "kfbi_plan_sizes": ([ctypes.c_void_p, ctypes.POINTER(Sizes)], ctypes.c_int),
+    "kfbi_plan_export": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int64], ctypes.c_int),
+    "kfbi_box_solve": ([ctypes.c_void_p, c_double_p, c_double_p], ctypes.c_int),
+    "kfbi_simple_solve": ([ctypes.c_void_p] + [c_double_p] * 8, ctypes.c_int),
+    "kfbi_matvec": ([ctypes.c_void_p, c_double_p, c_double_p], ctypes.c_int),
+    "kfbi_rhs": ([ctypes.c_void_p, ctypes.POINTER(Data), c_double_p], ctypes.c_int),
+    "kfbi_solve": ([ctypes.c_void_p, ctypes.POINTER(Data), ctypes.POINTER(Opts), c_double_p, c_double_p,
+                    ctypes.POINTER(Info)], ctypes.c_int),
+    "kfbi_plan_profile": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
+    "kfbi_plan_timing": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
+                          ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
+    "kfbi_plan_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "kfbi_last_error": ([], ctypes.c_char_p),
+}
+
+_lib = None
+
+
+def load():
+    """Open libkfbi.so (raises if it has not been built)."""
+    global _lib
+    if _lib is None:
+        if not os.path.exists(LIB_PATH):
+            raise RuntimeError("libkfbi.so is not built (python -m paper_2309_05965_amd.build)")
+        lib = ctypes.CDLL(LIB_PATH)
+        for name, (args, res) in ABI.items():
+            f = getattr(lib, name)
+            f.argtypes = args
+            f.restype = res
+        _lib = lib
+    return _lib
+
+
+class KfbiError(RuntimeError):
+    def __init__(self, status, msg):
+        super().__init__("%s: %s" % (STATUS.get(status, status), msg))
+        self.status = status
+        self.name = STATUS.get(status, str(status))
+
+
+def _check(st):
+    if st != 0:
+        raise KfbiError(st, load().kfbi_last_error().decode())
+
+
+def problem_struct(prob):
+    s = Problem()
+    s.dim, s.order, s.N = prob["dim"], prob["order"], prob["N"]
+    s.n_iface = len(prob["ifaces"])
+    s.lo, s.hi = prob["lo"], prob["hi"]
+    s.beta_in, s.beta_out, s.kappa = prob["beta_in"], prob["beta_out"], prob["kappa"]
+    s.cos_alpha = prob.get("cos_alpha", 0.5)
+    for k, (kind, params) in enumerate(prob["ifaces"]):
+        s.iface[k].kind = KINDS[kind]
+        for j, v in enumerate(params):
+            s.iface[k].p[j] = float(v)
+    return s
+
+
+def _ptr(t):
+    if t is None:
+        return None
+    if not (t.is_cuda and t.dtype == torch.float64 and t.is_contiguous()):
+        raise ValueError("expected a contiguous float64 tensor on the GPU")
+    return ctypes.c_void_p(t.data_ptr())
+
+
+class Plan:
+    """Geometry (step S0) and collocation factorisation (step S1) of one
+    problem, plus the operators of the hot path."""
+
+    def __init__(self, prob, device="cuda"):
+        lib = load()
+        self.device = torch.device(device)
+        self.stream = torch.cuda.current_stream(self.device)
+        self.prob = prob
+        self._p = problem_struct(prob)
+        h = ctypes.c_void_p()
+        st = lib.kfbi_plan_create(ctypes.byref(self._p), ctypes.c_void_p(self.stream.cuda_stream),
+                                  ctypes.byref(h))
+        self._h = h
+        if st != 0:
+            msg = lib.kfbi_last_error().decode()
+            self.close()
+            raise KfbiError(st, msg)
+        self._sizes()
+
+    def _sizes(self):
+        s = Sizes()
+        _check(load().kfbi_plan_sizes(self._h, ctypes.byref(s)))
+        self.sizes = s
+        self.n_nodes, self.n_surf, self.n_dof = s.n_nodes, s.n_surf, s.n_dof
+
+    def setup(self, prob):
+        """Re-run S0 + S1 for another problem on the same grid."""
+        self.prob = prob
+        self._p = problem_struct(prob)
+        _check(load().kfbi_plan_setup(self._h, ctypes.byref(self._p)))
+        self._sizes()
+
+    def close(self):
+        if getattr(self, "_h", None) is not None and self._h.value:
+            load().kfbi_plan_destroy(self._h)
+        self._h = ctypes.c_void_p()
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    # ------------------------------------------------------------------ tracing
+    def profile(self, enable=True):
+        """Start (or stop) HIP-event timing of the box-solve kernels."""
+        _check(load().kfbi_plan_profile(self._h, 1 if enable else 0))
+
+    def timing(self):
+        """(box solves, kernel launches, total ms) recorded since profile()."""
+        a, b, c = ctypes.c_int64(), ctypes.c_int64(), ctypes.c_double()
+        _check(load().kfbi_plan_timing(self._h, ctypes.byref(a), ctypes.byref(b), ctypes.byref(c)))
+        return a.value, b.value, c.value
+
+    # ------------------------------------------------------------------ tables
+    def export(self, name):
+        s = self.sizes
+        d = self.prob["dim"]
+        p = 4 if self.prob["order"] == 4 else 2
+        shapes = {
+            "region": ((s.n_nodes,), torch.int8), "surf_pos": ((s.n_surf, d), torch.float64),
+            "surf_nrm": ((s.n_surf, d), torch.float64), "surf_meta": ((s.n_surf, 5), torch.int32),
+            "dof_surf": ((s.n_dof,), torch.int32), "stencil_d": ((s.n_dof, s.n_dir), torch.int32),
+            "stencil_n": ((s.n_dof, s.n_neu), torch.int32), "ext_idx": ((s.n_surf, p), torch.int32),
+            "ext_w": ((s.n_surf, p), torch.float64), "pde_pts": ((s.n_dof, s.n_pde, d), torch.float64),
+            "irregular": ((s.n_irregular,), torch.int32), "corr": ((s.n_corr, 3), torch.int32),
+            "cond": ((s.n_dof,), torch.float64),
+        }
+        shape, dt = shapes[name]
+        out = torch.empty(shape, dtype=dt, device=self.device)
+        nbytes = out.numel() * out.element_size()
+        _check(load().kfbi_plan_export(self._h, EXPORT[name], ctypes.c_void_p(out.data_ptr() if nbytes else 0),
+                                       nbytes))
+        return out
+
+    def _zeros(self, n):
+        return torch.zeros(n, dtype=torch.float64, device=self.device)
+
+    # ------------------------------------------------------------------ operators
+    def box_solve(self, F):
+        v = self._zeros(self.n_nodes)
+        _check(load().kfbi_box_solve(self._h, _ptr(F), _ptr(v)))
+        return v
+
+    def simple_solve(self, a=None, b=None, ftilde=None, fhat=None, gB=None):
+        v = self._zeros(self.n_nodes)
+        dn_in = self._zeros(self.n_dof)
+        dn_out = self._zeros(self.n_dof)
+        _check(load().kfbi_simple_solve(self._h, _ptr(a), _ptr(b), _ptr(ftilde), _ptr(fhat), _ptr(gB),
+                                        _ptr(v), _ptr(dn_in), _ptr(dn_out)))
+        return v, dn_in, dn_out
+
+    def matvec(self, psi, out=None):
+        out = self._zeros(self.n_dof) if out is None else out
+        _check(load().kfbi_matvec(self._h, _ptr(psi), _ptr(out)))
+        return out
+
+    @staticmethod
+    def data_struct(data):
+        return Data(_ptr(data["g1"]), _ptr(data["g2"]), _ptr(data["ftilde"]), _ptr(data["fhat"]),
+                    _ptr(data["gB"]))
+
+    def rhs(self, data):
+        b = self._zeros(self.n_dof)
+        ds = self.data_struct(data)
+        _check(load().kfbi_rhs(self._h, ctypes.byref(ds), _ptr(b)))
+        return b
+
+    def solve(self, data, tol=1e-10, max_iter=200, psi0=None, u_out=None, raise_on_fail=True):
+        """Full KFBI solve; returns (psi, u, info dict)."""
+        psi = self._zeros(self.n_dof) if psi0 is None else psi0.clone()
+        u = self._zeros(self.n_nodes) if u_out is None else u_out
+        ds = self.data_struct(data)
+        o = Opts(tol, max_iter, 0 if psi0 is None else 1)
+        info = Info()
+        st = load().kfbi_solve(self._h, ctypes.byref(ds), ctypes.byref(o), _ptr(psi), _ptr(u), ctypes.byref(info))
+        if st != 0 and raise_on_fail:
+            _check(st)
+        return psi, u, {"iters": info.iters, "status": info.status, "est_rel_res": info.est_rel_res,
+                        "true_rel_res": info.true_rel_res}
+
+
+def device_data(plan, prob, sol):
+    """Manufactured data of `sol` at the plan's own query points, as device
+    tensors (input generation; uses the workloads module)."""
+    from . import workloads as W
+    pos = plan.export("surf_pos").cpu().numpy()
+    nrm = plan.export("surf_nrm").cpu().numpy()
+    meta = plan.export("surf_meta").cpu().numpy()
+    pde = plan.export("pde_pts").cpu().numpy()
+    dsurf = plan.export("dof_surf").cpu().numpy()
+    data = W.make_data(prob, sol, pos, nrm, meta[:, 3], pde, meta[dsurf, 3])
+    dev = plan.device
+    return {k: torch.from_numpy(v.reshape(-1).copy() if k != "ftilde" else v.copy()).to(dev).contiguous()
+            for k, v in data.items()}

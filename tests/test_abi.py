@@ -1,0 +1,67 @@
+"""The C-ABI library loads, exports every entry point that include/kfbi.h
+declares, its structs have the layout the binding assumes, and descriptor
+errors are reported before any device work.  No GPU needed."""
+import ctypes
+import os
+import re
+import subprocess
+
+import pytest
+
+ROOT = os.path.dirname(os.path.dirname(os.path.abspath(__file__)))
+HEADER = os.path.join(ROOT, "include", "kfbi.h")
+
+
+def _lib():
+    from paper_2309_05965_amd import kfbi
+    if not os.path.exists(kfbi.LIB_PATH):
+        pytest.skip("libkfbi.so not built")
+    return kfbi, kfbi.load()
+
+
+def declared_functions():
+    src = open(HEADER).read()
+    return sorted(set(re.findall(r"^(?:kfbi_status|const char\*)\s+(kfbi_\w+)\s*\(", src, re.M)))
+
+
+def test_every_declared_symbol_is_exported():
+    kfbi, lib = _lib()
+    names = declared_functions()
+    assert len(names) >= 11
+    for n in names:
+        assert hasattr(lib, n), n
+        assert n in kfbi.ABI, n
+
+
+def test_struct_layout_matches_header(tmp_path):
+    kfbi, _ = _lib()
+    prog = tmp_path / "sz.c"
+    prog.write_text('#include <stdio.h>\n#include <stddef.h>\n#include "kfbi.h"\n'
+                    'int main(void){printf("%zu %zu %zu %zu %zu %zu %zu\\n", sizeof(kfbi_problem),'
+                    ' sizeof(kfbi_sizes), sizeof(kfbi_data), sizeof(kfbi_opts), sizeof(kfbi_info),'
+                    ' offsetof(kfbi_problem, iface), sizeof(kfbi_levelset)); return 0;}\n')
+    exe = tmp_path / "sz"
+    subprocess.run(["gcc", "-I", os.path.join(ROOT, "include"), str(prog), "-o", str(exe)], check=True)
+    got = [int(x) for x in subprocess.run([str(exe)], capture_output=True, text=True, check=True).stdout.split()]
+    want = [ctypes.sizeof(kfbi.Problem), ctypes.sizeof(kfbi.Sizes), ctypes.sizeof(kfbi.Data),
+            ctypes.sizeof(kfbi.Opts), ctypes.sizeof(kfbi.Info), kfbi.Problem.iface.offset,
+            ctypes.sizeof(kfbi.LevelSet)]
+    assert got == want
+
+
+@pytest.mark.parametrize("change,frag", [
+    ({"N": 100}, "power of two"), ({"order": 3}, "order"), ({"dim": 4}, "dim"),
+    ({"beta_in": -1.0}, "beta"), ({"cos_alpha": 0.9}, "cos_alpha"),
+    ({"ifaces": [("torus3d", [0, 0, 0, 0.5, 0.2])]}, "kind"),
+])
+def test_descriptor_errors_need_no_device(change, frag):
+    kfbi, lib = _lib()
+    from paper_2309_05965_amd import workloads as W
+    prob, _ = W.config1(64)
+    prob = dict(prob, **change)
+    ps = kfbi.problem_struct(prob)
+    h = ctypes.c_void_p()
+    st = lib.kfbi_plan_create(ctypes.byref(ps), None, ctypes.byref(h))
+    assert st == 1
+    assert h.value is None
+    assert frag in lib.kfbi_last_error().decode()

@@ -1,0 +1,218 @@
+"""Parity of the HIP library with the FP64 oracle (runs on an MI355X).
+
+Discrete geometry decisions (regions, surface points, stencils, density
+extension, irregular nodes, correction entries and owners) must match
+exactly; floating-point results within the stated tolerances:
+  box solve, simple solve, matvec: max |gpu - oracle| <= 1e-11 max |oracle|
+  full solve (GMRES tol 1e-13): psi and u within 1e-10 relative (the
+  spec FP64 parity bar).
+"""
+import sys
+
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import fd, kfbi as okfbi  # noqa: E402
+from paper_2309_05965_amd import workloads as W  # noqa: E402
+
+CASES = {
+    "c1_64": lambda: W.config1(64),
+    "c2_128": lambda: W.config2(128),
+    "c2_512": lambda: W.config2(512),
+    "sphere_32": lambda: (W.problem(3, 4, 32, -1.0, 1.0, 1.0, 5.0, 0.5,
+                                    [W.sphere3d(0.03, -0.02, 0.01, 0.52)]),
+                          {0: W.f_exp3, 1: W.f_sin3}),
+    "ellipse_o4_64": lambda: (W.problem(2, 4, 64, -1.0, 1.0, 3.0, 1.0, 0.0,
+                                        [W.ellipse2d(0.05, -0.02, 0.7, 0.45, theta=0.3)]),
+                              {0: W.f_x2_my3, 1: W.f_cos2x_expy}),
+}
+
+_cache = {}
+
+
+def case(name):
+    if name not in _cache:
+        prob, sol = CASES[name]()
+        print("case", name, flush=True)
+        sys.stdout.flush()
+        from paper_2309_05965_amd import kfbi
+        gp = kfbi.Plan(prob)
+        op = okfbi.Plan(prob)
+        _cache[name] = (prob, sol, gp, op)
+    return _cache[name]
+
+
+def oracle_data(op, prob, sol):
+    s = op.geo["surf"]
+    return W.make_data(prob, sol, s["pos"], s["nrm"], s["iface"], op.geo["st"]["pde_pts"],
+                       op.geo["dofs"]["iface"])
+
+
+def dev(x):
+    return torch.from_numpy(np.ascontiguousarray(x, dtype=np.float64).reshape(-1)).cuda()
+
+
+def host(t):
+    return t.cpu().numpy()
+
+
+def rel(a, b):
+    return np.max(np.abs(a - b)) / max(1e-300, np.max(np.abs(b)))
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_geometry_matches_exactly(name):
+    prob, sol, gp, op = case(name)
+    geo = op.geo
+    assert np.array_equal(host(gp.export("region")), geo["reg"].ravel())
+    s = geo["surf"]
+    assert gp.n_surf == s["pos"].shape[0]
+    assert np.array_equal(host(gp.export("surf_pos")), s["pos"])          # bitwise
+    assert np.array_equal(host(gp.export("surf_nrm")), s["nrm"])
+    meta = host(gp.export("surf_meta"))
+    assert np.array_equal(meta[:, 0], s["fam"]) and np.array_equal(meta[:, 1], s["lid"])
+    assert np.array_equal(meta[:, 2], s["seg"]) and np.array_equal(meta[:, 3], s["iface"])
+    assert np.array_equal(meta[:, 4].astype(bool), s["prim"])
+    assert np.array_equal(host(gp.export("dof_surf")), geo["dofs"]["sidx"])
+    assert np.array_equal(host(gp.export("stencil_d")), geo["st"]["D"])
+    assert np.array_equal(host(gp.export("stencil_n")), geo["st"]["N"])
+    assert np.array_equal(host(gp.export("ext_idx")), geo["ext_idx"])
+    assert np.array_equal(host(gp.export("ext_w")), geo["ext_w"])
+    assert np.array_equal(host(gp.export("pde_pts")), geo["st"]["pde_pts"])
+    assert np.array_equal(host(gp.export("irregular")), geo["irr"])
+    corr = host(gp.export("corr"))
+    assert np.array_equal(corr[:, 0], geo["ck"]) and np.array_equal(corr[:, 1], geo["cnode"])
+    assert np.array_equal(corr[:, 2], geo["cowner"])
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_collocation_conditioning(name):
+    prob, sol, gp, op = case(name)
+    c = host(gp.export("cond"))
+    assert np.max(np.abs(c - op.cond) / op.cond) < 1e-6
+    assert gp.sizes.cond_max == pytest.approx(op.cond.max(), rel=1e-6)
+
+
+@pytest.mark.parametrize("name", ["c1_64", "c2_512", "sphere_32"])
+def test_box_solve(name):
+    prob, sol, gp, op = case(name)
+    d, N = prob["dim"], prob["N"]
+    F = np.random.default_rng(0).standard_normal((N + 1,) * d)
+    v = host(gp.box_solve(dev(F))).reshape(F.shape)
+    ref = fd.dst_solve(F[(slice(1, N),) * d], d, prob["order"], N, op.h, prob["kappa"])
+    assert rel(v[(slice(1, N),) * d], ref) < 1e-11
+    inner = np.zeros_like(v)
+    inner[(slice(1, N),) * d] = v[(slice(1, N),) * d]
+    assert np.array_equal(v, inner)            # zero box boundary
+
+
+@pytest.mark.parametrize("N", [32, 1024])
+def test_box_solve_extreme_sizes(N):
+    """Smallest grid with a resolvable interface and the largest grid (2048-point FFTs)."""
+    from paper_2309_05965_amd import kfbi
+    prob = W.problem(2, 4, N, -1.0, 1.0, 1.0, 1.0, 1.0, [W.ellipse2d(0.0, 0.0, 0.45, 0.45)])
+    gp = kfbi.Plan(prob)
+    F = np.random.default_rng(N).standard_normal((N + 1, N + 1))
+    v = host(gp.box_solve(dev(F))).reshape(F.shape)
+    h = 2.0 / N
+    ref = fd.dst_solve(F[1:N, 1:N], 2, 4, N, h, 1.0)
+    assert rel(v[1:N, 1:N], ref) < 1e-11
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_simple_solve(name):
+    prob, sol, gp, op = case(name)
+    rng = np.random.default_rng(1)
+    ns, nb = op.geo["surf"]["pos"].shape[0], op.Nb
+    a = rng.standard_normal(ns)
+    b = rng.standard_normal(ns)
+    ft = rng.standard_normal((nb, len(op.geo["st"]["offP"])))
+    d, N = prob["dim"], prob["N"]
+    fhat = rng.standard_normal((op.K + 1,) + (N + 1,) * d)
+    gB = rng.standard_normal((N + 1,) * d)
+    v_o, din_o, dout_o, _ = op.simple_solve(a=a, b=b, ftilde=ft, fhat=fhat, gB=gB)
+    v, din, dout = gp.simple_solve(dev(a), dev(b), dev(ft), dev(fhat), dev(gB))
+    assert rel(host(v), v_o.ravel()) < 1e-11
+    assert rel(host(din), din_o) < 1e-11
+    assert rel(host(dout), dout_o) < 1e-11
+
+
+@pytest.mark.parametrize("name", list(CASES))
+def test_matvec(name):
+    prob, sol, gp, op = case(name)
+    psi = np.random.default_rng(2).standard_normal(op.Nb)
+    ref = op.matvec(psi)
+    out1 = gp.matvec(dev(psi))
+    out2 = gp.matvec(dev(psi))
+    assert rel(host(out1), ref) < 1e-11
+    assert torch.equal(out1, out2)             # bitwise deterministic
+
+
+@pytest.mark.parametrize("name", ["c1_64", "c2_128", "c2_512", "sphere_32", "ellipse_o4_64"])
+def test_full_solve(name):
+    from paper_2309_05965_amd import kfbi
+    prob, sol, gp, op = case(name)
+    data_o = oracle_data(op, prob, sol)
+    ref = op.solve(data_o, tol=1e-13, maxit=300)
+    data = kfbi.device_data(gp, prob, sol)
+    psi, u, info = gp.solve(data, tol=1e-13, max_iter=300)
+    assert info["status"] == 0
+    assert rel(host(psi), ref["psi"]) < 1e-10
+    assert rel(host(u), ref["u"].ravel()) < 1e-10
+    assert abs(info["iters"] - ref["iters"]) <= 2
+    assert info["true_rel_res"] < 1e-11
+
+
+def test_metric_tolerance_solve():
+    """The benchmark's stopping tolerance 1e-8: the true FP64 residual
+    recomputed at exit meets it, and the solution error against the exact
+    solution is the discretisation error (4th order at 512^2)."""
+    from paper_2309_05965_amd import kfbi
+    prob, sol, gp, op = case("c2_512")
+    data = kfbi.device_data(gp, prob, sol)
+    psi, u, info = gp.solve(data, tol=1e-8)
+    assert info["true_rel_res"] < 2e-8
+    ue = W.exact_solution(prob, sol, op.geo["reg"]).ravel()
+    assert np.max(np.abs(host(u) - ue)) < 1e-7
+
+
+def test_replan_same_grid():
+    """kfbi_plan_setup reuses buffers for a new geometry on the same grid."""
+    from paper_2309_05965_amd import kfbi
+    prob, sol = W.config2(128)
+    gp = kfbi.Plan(prob)
+    prob2 = dict(prob, ifaces=[W.star2d(0.02, 0.0, 0.45, None, [0, 0, 0.05, 0, 0, 0, 0, 0])])
+    gp.setup(prob2)
+    op = okfbi.Plan(prob2)
+    psi = np.random.default_rng(3).standard_normal(op.Nb)
+    assert gp.n_dof == op.Nb
+    assert rel(host(gp.matvec(dev(psi))), op.matvec(psi)) < 1e-11
+    gp.setup(prob)
+    op1 = okfbi.Plan(prob)
+    psi = np.random.default_rng(4).standard_normal(op1.Nb)
+    assert rel(host(gp.matvec(dev(psi))), op1.matvec(psi)) < 1e-11
+
+
+@pytest.mark.parametrize("N", [8, 16])
+def test_coarse_grid_status_matches_oracle(N):
+    """A circle of radius 0.3 is not resolved at N = 8, 16: both sides say so."""
+    from oracle import geometry as G
+    from paper_2309_05965_amd import kfbi
+    prob = W.problem(2, 4, N, -1.0, 1.0, 1.0, 1.0, 1.0, [W.ellipse2d(0.0, 0.0, 0.3, 0.3)])
+    with pytest.raises(G.GeometryError) as eo:
+        okfbi.Plan(prob)
+    with pytest.raises(kfbi.KfbiError) as eg:
+        kfbi.Plan(prob)
+    assert eg.value.name.lower() == eo.value.status
+
+
+def test_unresolved_geometry_reports_status():
+    from paper_2309_05965_amd import kfbi
+    prob = W.problem(2, 4, 16, -1.0, 1.0, 1.0, 1.0, 0.0, [W.star2d(0.0, 0.0, 0.5, None, [0, 0, 0, 0, 0, 0, 0.3, 0])])
+    with pytest.raises(kfbi.KfbiError) as e:
+        kfbi.Plan(prob)
+    assert e.value.name in ("UNRESOLVED", "SINGULAR", "INVALID")
