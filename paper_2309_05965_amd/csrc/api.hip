@@ -134,11 +134,38 @@ void free_plan(kfbi_plan* pl) {
   dfree(pl->work2);
   dfree(pl->bvec);
   dfree(pl->scal);
+  dfree(pl->FI);
+  dfree(pl->FW);
+  dfree(pl->Cv);
+  dfree(pl->GI);
+  dfree(pl->GW);
+  dfree(pl->IW);
+  dfree(pl->IB);
+  dfree(pl->IE1);
+  dfree(pl->IE2);
+  dfree(pl->PA);
+  dfree(pl->PE1);
+  dfree(pl->PE2);
+  dfree(pl->EI);
+  dfree(pl->row_start);
+  dfree(pl->row_end);
   if (pl->prof_ev) {
     for (hipEvent_t e : *pl->prof_ev) (void)hipEventDestroy(e);
     delete pl->prof_ev;
     pl->prof_ev = nullptr;
   }
+  if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  pl->graph_exec = nullptr;
+  pl->graph = nullptr;
+  if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
+  if (pl->ev_in) (void)hipEventDestroy(pl->ev_in);
+  if (pl->ev_out) (void)hipEventDestroy(pl->ev_out);
+  pl->gstream = nullptr;
+  pl->ev_in = pl->ev_out = nullptr;
+  dfree(pl->ctl);
+  if (pl->h_ctl) (void)hipHostFree(pl->h_ctl);
+  pl->h_ctl = nullptr;
   if (pl->h_pinned) (void)hipHostFree(pl->h_pinned);
   if (pl->h_dpinned) (void)hipHostFree(pl->h_dpinned);
   pl->h_pinned = nullptr;
@@ -178,6 +205,10 @@ kfbi_status alloc_fixed(kfbi_plan* pl) {
   KCHK(dalloc(&pl->T2, n));
   KCHK(dalloc(&pl->vbuf, n));
   KCHK(dalloc(&pl->vsbuf, n));
+  KCHK(dalloc(&pl->EI, (int64_t)g.K * n));
+  int64_t nrows = g.d == 3 ? (int64_t)g.n1 * g.n1 : g.n1;
+  KCHK(dalloc(&pl->row_start, nrows));
+  KCHK(dalloc(&pl->row_end, nrows));
   KCHK(dalloc(&pl->line_start, pl->n_lines));
   KCHK(dalloc(&pl->line_end, pl->n_lines));
   int64_t nkeys = (int64_t)g.K * pl->ncell;
@@ -185,7 +216,7 @@ kfbi_status alloc_fixed(kfbi_plan* pl) {
   KCHK(dalloc(&pl->cell_start, nkeys + 1));
   KCHK(dalloc(&pl->blk_total, 4));
   KCHK(dalloc(&pl->d_flags, 4));
-  KCHK(dalloc(&pl->tw, 2 * g.N));
+  KCHK(dalloc(&pl->tw, 4 * g.N));
   KCHK(dalloc(&pl->eig1, g.N + 1));
   KCHK(dalloc(&pl->scal, 16 + KFBI_GMRES_MAX + 8));
   KCHK(dalloc(&pl->Hm, (int64_t)(KFBI_GMRES_MAX + 1) * (KFBI_GMRES_MAX + 1)));
@@ -200,6 +231,14 @@ kfbi_status alloc_fixed(kfbi_plan* pl) {
     kfbi_set_error("pinned host allocation failed");
     return KFBI_E_OOM;
   }
+  if (hipHostMalloc((void**)&pl->h_ctl, 16 * sizeof(int), 0) != hipSuccess) {
+    kfbi_set_error("pinned host allocation failed");
+    return KFBI_E_OOM;
+  }
+  KCHK(dalloc(&pl->ctl, 8));
+  HIPCHK(hipStreamCreateWithFlags(&pl->gstream, hipStreamNonBlocking));
+  HIPCHK(hipEventCreateWithFlags(&pl->ev_in, hipEventDisableTiming));
+  HIPCHK(hipEventCreateWithFlags(&pl->ev_out, hipEventDisableTiming));
   return KFBI_OK;
 }
 
@@ -207,6 +246,7 @@ kfbi_status run_setup(kfbi_plan* pl) {
   pl->ready = false;
   KCHK(geo_setup(pl));
   KCHK(colloc_factor(pl));
+  KCHK(op_fold(pl));
   // the matvec right-hand side is zero away from the irregular nodes and the
   // matvec grid solution is zero on the box boundary
   HIPCHK(hipMemsetAsync(pl->Fm, 0, sizeof(double) * pl->g.n_nodes, pl->stream));
@@ -249,13 +289,37 @@ void simple_solve_impl(kfbi_plan* pl, const double* a, const double* b, const do
   op_normal_derivatives(pl, v, dn_in, dn_out, nullptr);
 }
 
-void matvec_impl(kfbi_plan* pl, const double* psi, double* Apsi) {
-  op_extend(pl, psi, pl->psiS);
-  op_coefficients(pl, nullptr, pl->psiS, nullptr);
-  op_correction_values(pl);
-  op_rhs_correct(pl, pl->Fm, true);
-  dst_solve(pl, pl->Fm, pl->vbuf);
-  op_normal_derivatives(pl, pl->vbuf, nullptr, nullptr, Apsi);
+void matvec_impl(kfbi_plan* pl, const double* psi, double* Apsi) { op_matvec(pl, psi, Apsi); }
+
+// Graph of one GMRES iteration (matvec of V[j] into V[j+1], Arnoldi step),
+// captured on the private stream; every kernel reads j and the stop flag
+// from the device control word.  Rebuilt when buffers or sizes change.
+kfbi_status ensure_graph(kfbi_plan* pl) {
+  uint64_t bi, bo, ka;
+  memcpy(&bi, &pl->g.beta_in, 8);
+  memcpy(&bo, &pl->g.beta_out, 8);
+  memcpy(&ka, &pl->g.kappa, 8);
+  uint64_t key[20] = {bi, bo, ka, 0,(uint64_t)pl->n_dof, (uint64_t)pl->n_surf, (uint64_t)pl->n_corr, (uint64_t)pl->n_irr,
+                      (uint64_t)(uintptr_t)pl->V, (uint64_t)(uintptr_t)pl->psiS, (uint64_t)(uintptr_t)pl->Cg,
+                      (uint64_t)(uintptr_t)pl->FI, (uint64_t)(uintptr_t)pl->IW, (uint64_t)(uintptr_t)pl->stN,
+                      (uint64_t)(uintptr_t)pl->ext_idx, (uint64_t)(uintptr_t)pl->irr,
+                      (uint64_t)(uintptr_t)pl->ce_node, (uint64_t)pl->gm_cap, (uint64_t)(uintptr_t)pl->d2s,
+                      (uint64_t)(uintptr_t)pl->PA ^ (uint64_t)(uintptr_t)pl->GI};
+  if (pl->graph_exec && memcmp(key, pl->graph_key, sizeof(key)) == 0) return KFBI_OK;
+  if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  pl->graph_exec = nullptr;
+  pl->graph = nullptr;
+  HIPCHK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
+  pl->ctl_active = pl->ctl;
+  op_matvec(pl, nullptr, nullptr);
+  gm_arnoldi(pl);
+  pl->ctl_active = nullptr;
+  hipError_t e = hipStreamEndCapture(pl->stream, &pl->graph);
+  if (e != hipSuccess) return kfbi_hip_status(e, "hipStreamEndCapture");
+  HIPCHK(hipGraphInstantiate(&pl->graph_exec, pl->graph, nullptr, nullptr, 0));
+  memcpy(pl->graph_key, key, sizeof(key));
+  return KFBI_OK;
 }
 
 }  // namespace
@@ -501,43 +565,47 @@ extern "C" kfbi_status kfbi_rhs(kfbi_plan* pl, const kfbi_data* data, double* b)
   return KFBI_OK;
 }
 
-extern "C" kfbi_status kfbi_solve(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* opts, double* psi,
-                                  double* u_out, kfbi_info* info) {
-  KCHK(need_ready(pl));
-  if (!data || !opts || !psi || !data->g2) {
-    kfbi_set_error("NULL argument");
-    return KFBI_E_INVALID;
-  }
-  int m = opts->max_iter;
-  if (m < 1 || m > KFBI_GMRES_MAX) {
-    kfbi_set_error("max_iter must be in [1, %d]", KFBI_GMRES_MAX);
-    return KFBI_E_INVALID;
-  }
-  double tol = opts->tol > 0.0 ? opts->tol : 1e-10;
-  KCHK(ensure_gmres(pl, m));
+namespace {
+kfbi_status solve_body(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* opts, double* psi, double* u_out,
+                       kfbi_info* info, int m, double tol) {
   hipStream_t st = pl->stream;
   // Step 1: right-hand side
-  KCHK(kfbi_rhs(pl, data, pl->bvec));
-  // Step 2: initial residual
+  simple_solve_impl(pl, data->g1, nullptr, data->ftilde, data->fhat, data->gB, pl->vsbuf, pl->dn_in, pl->dn_out);
+  op_bie_rhs(pl, data->g2, pl->dn_in, pl->dn_out, pl->bvec);
+  // Step 2: initial residual and control word
   if (opts->use_x0) matvec_impl(pl, psi, pl->work);
-  gm_residual_start(pl, pl->bvec, pl->work, opts->use_x0);
-  HIPCHK(hipMemcpyAsync(pl->h_dpinned, pl->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  gm_residual_start(pl, pl->bvec, pl->work, opts->use_x0, tol, m);
+  KCHK(ensure_graph(pl));
+  HIPCHK(hipMemcpyAsync(pl->h_ctl, pl->ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+  HIPCHK(hipMemcpyAsync(pl->h_dpinned, pl->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
-  double beta = pl->h_dpinned[0], nb = pl->h_dpinned[1];
-  double est = nb > 0.0 ? beta / nb : 0.0;
-  int k = 0;
-  bool conv = !(beta > tol * nb);
-  // Steps 3-4: Arnoldi with the simple-interface-problem operator
-  for (int j = 0; j < m && !conv; ++j) {
-    matvec_impl(pl, pl->V + (int64_t)j * pl->n_dof, pl->V + (int64_t)(j + 1) * pl->n_dof);
-    gm_arnoldi(pl, j);
-    HIPCHK(hipMemcpyAsync(pl->h_dpinned, pl->scal, 3 * sizeof(double), hipMemcpyDeviceToHost, st));
+  double nb = pl->h_dpinned[1];
+  double res_prev = pl->h_dpinned[0];
+  int k_prev = 0;
+  // Steps 3-4: launch captured iterations in batches; the batch length is
+  // predicted from the observed convergence rate
+  int launched = 0, batch = 4;
+  while (!pl->h_ctl[1] && launched < m) {
+    int B = batch < m - launched ? batch : m - launched;
+    for (int b = 0; b < B; ++b) HIPCHK(hipGraphLaunch(pl->graph_exec, st));
+    launched += B;
+    HIPCHK(hipMemcpyAsync(pl->h_ctl, pl->ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pl->h_dpinned, pl->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    k = j + 1;
-    est = nb > 0.0 ? pl->h_dpinned[0] / nb : 0.0;
-    if (pl->h_dpinned[0] <= tol * nb) conv = true;
-    if (pl->h_dpinned[2] != 0.0) break;     // lucky breakdown: exact solution in the space
+    int k = pl->h_ctl[2];
+    double res = pl->h_dpinned[0];
+    batch = 4;
+    if (k > k_prev && res > 0.0 && res < res_prev && res_prev > 0.0) {
+      double rate = pow(res / res_prev, 1.0 / (double)(k - k_prev));
+      double need = log(tol * nb / res) / log(rate);
+      batch = need < 1.0 ? 1 : (need > 16.0 ? 16 : (int)ceil(need));
+    }
+    res_prev = res;
+    k_prev = k;
   }
+  const int k = pl->h_ctl[2];
+  const double est = nb > 0.0 ? pl->h_dpinned[0] / nb : 0.0;
+  const bool conv = pl->h_ctl[1] && (nb == 0.0 || pl->h_dpinned[0] <= tol * nb || pl->h_dpinned[2] != 0.0);
   gm_update(pl, k, psi, opts->use_x0);
   // final solve u = w(g1, E psi, ftilde, fhat, gB)
   op_extend(pl, psi, pl->aS);
@@ -560,6 +628,36 @@ extern "C" kfbi_status kfbi_solve(kfbi_plan* pl, const kfbi_data* data, const kf
   }
   if (s == KFBI_E_NOT_CONVERGED) kfbi_set_error("GMRES did not reach tol %g in %d iterations", tol, m);
   if (s == KFBI_E_NONFINITE) kfbi_set_error("non-finite residual");
+  return s;
+}
+}  // namespace
+
+extern "C" kfbi_status kfbi_solve(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* opts, double* psi,
+                                  double* u_out, kfbi_info* info) {
+  KCHK(need_ready(pl));
+  if (!data || !opts || !psi || !data->g2) {
+    kfbi_set_error("NULL argument");
+    return KFBI_E_INVALID;
+  }
+  int m = opts->max_iter;
+  if (m < 1 || m > KFBI_GMRES_MAX) {
+    kfbi_set_error("max_iter must be in [1, %d]", KFBI_GMRES_MAX);
+    return KFBI_E_INVALID;
+  }
+  double tol = opts->tol > 0.0 ? opts->tol : 1e-10;
+  KCHK(ensure_gmres(pl, m));
+  // the solve runs on the plan's private stream (graph launches need a
+  // capturable stream), ordered after and before the caller's stream
+  hipStream_t user = pl->stream;
+  HIPCHK(hipEventRecord(pl->ev_in, user));
+  HIPCHK(hipStreamWaitEvent(pl->gstream, pl->ev_in, 0));
+  pl->stream = pl->gstream;
+  kfbi_status s = solve_body(pl, data, opts, psi, u_out, info, m, tol);
+  pl->stream = user;
+  hipError_t e1 = hipEventRecord(pl->ev_out, pl->gstream);
+  hipError_t e2 = hipStreamWaitEvent(user, pl->ev_out, 0);
+  if (s == KFBI_OK && e1 != hipSuccess) return kfbi_hip_status(e1, "hipEventRecord");
+  if (s == KFBI_OK && e2 != hipSuccess) return kfbi_hip_status(e2, "hipStreamWaitEvent");
   return s;
 }
 

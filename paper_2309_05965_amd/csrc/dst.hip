@@ -14,7 +14,8 @@
 // Design for gfx950: one HBM read and one HBM write per axis pass.  A work
 // group loads a tile of TL lines (coalesced along x), forms the odd
 // extension of two real lines as the real and imaginary parts of one complex
-// sequence of length M = 2N, runs radix-2 FFTs in LDS, and unpacks both
+// sequence of length M = 2N, runs self-sorting Stockham FFTs (radix 4) in
+// LDS ping-pong buffers, and unpacks both
 // sine transforms from the result (Re Z_k = 2 S_B(k), Im Z_k = -2 S_A(k)).
 // The last axis is fused: forward DST, spectral divide and inverse DST in
 // LDS, so 2D takes 3 passes and 3D 5 passes of 16 B per node.
@@ -26,9 +27,19 @@
 
 namespace {
 
-constexpr int LDS_COMPLEX = 4096;   // complex slots for the FFT working set (64 KiB)
+constexpr int LDS_COMPLEX = 4096;   // complex slots of the two ping-pong buffers (64 KiB)
 
 struct DstArgs {
+  const int* ctl;      // nothing to do once ctl[1] is set (device GMRES loop)
+  // source of the first pass of the matvec: the corrected right-hand side,
+  // zero except at the irregular nodes, built here from the density
+  int src_corr;
+  const double* psi;   // density (or V[ctl[0]] in the device GMRES loop)
+  const double* Vb;
+  int64_t n_dof;
+  const int *row_start, *row_end, *irr, *PE1, *PE2;
+  const double *PA, *Cv;
+  int maxpairs, nF;
   GridDesc g;
   int ax;          // transform axis
   int mode;        // 0: DST; 1: DST, divide by lambda and scale, DST
@@ -37,41 +48,71 @@ struct DstArgs {
   int tiles_u;     // tiles along the tile axis
   const double* in;
   double* out;
-  const double2* tw;   // exp(-2 pi i m / M), m < M/2
+  const double2* tw;   // exp(-2 pi i m / M), m < M
   const double* eig1;  // s_k, k = 0..N
   double scale;        // (2/N)^d
 };
-
-__device__ __forceinline__ unsigned bitrev(unsigned x, int bits) { return __brev(x) >> (32 - bits); }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// In-place radix-2 DIT FFTs of nf sequences of length M held in bit-reversed
-// order in buf[f * M + i].
-__device__ void fft_lds(double2* buf, const double2* tw, int nf, int M, int logM) {
-  const int half_total = nf * (M / 2);
-  for (int s = 1; s <= logM; ++s) {
-    const int half = 1 << (s - 1);
-    const int tstride = M / (2 * half);
-    for (int b = threadIdx.x; b < half_total; b += blockDim.x) {
-      int f = b / (M / 2);
-      int i = b % (M / 2);
-      int grp = i / half, pos = i % half;
-      int i0 = f * M + grp * 2 * half + pos;
-      int i1 = i0 + half;
-      double2 w = tw[pos * tstride];
-      double2 t = cmul(w, buf[i1]);
-      double2 u = buf[i0];
-      buf[i0] = make_double2(u.x + t.x, u.y + t.y);
-      buf[i1] = make_double2(u.x - t.x, u.y - t.y);
+// nf forward DFTs of length M = 2^logM (natural order in, natural order out)
+// by self-sorting Stockham stages, radix 4 then one radix 2 if logM is odd:
+// stage with span Ns reads x[j + r M/R], twiddles by exp(-2 pi i r k/(R Ns)),
+// k = j mod Ns, and writes y[(j - k) R + k + r Ns].  Returns the buffer that
+// holds the result (a or b).
+__device__ double2* fft_stockham(double2* a, double2* b, const double2* __restrict__ tw, int nf, int M,
+                                 int logM) {
+  int Ns = 1, lNs = 0;
+  while (Ns < M) {
+    if (4 * Ns <= M) {
+      const int lQ = logM - 2, Q = 1 << lQ;
+      const int tsh = logM - 2 - lNs;             // twiddle step M / (4 Ns)
+      for (int t = threadIdx.x; t < (nf << lQ); t += blockDim.x) {
+        const int f = t >> lQ, j = t & (Q - 1), k = j & (Ns - 1);
+        const double2* x = a + (f << logM);
+        double2* y = b + (f << logM);
+        double2 v0 = x[j], v1 = x[j + Q], v2 = x[j + 2 * Q], v3 = x[j + 3 * Q];
+        const int st = k << tsh;
+        v1 = cmul(v1, tw[st]);
+        v2 = cmul(v2, tw[2 * st]);
+        v3 = cmul(v3, tw[3 * st]);
+        double2 t0 = make_double2(v0.x + v2.x, v0.y + v2.y), t1 = make_double2(v0.x - v2.x, v0.y - v2.y);
+        double2 t2 = make_double2(v1.x + v3.x, v1.y + v3.y), t3 = make_double2(v1.x - v3.x, v1.y - v3.y);
+        const int d = ((j - k) << 2) + k;
+        y[d] = make_double2(t0.x + t2.x, t0.y + t2.y);
+        y[d + Ns] = make_double2(t1.x + t3.y, t1.y - t3.x);
+        y[d + 2 * Ns] = make_double2(t0.x - t2.x, t0.y - t2.y);
+        y[d + 3 * Ns] = make_double2(t1.x - t3.y, t1.y + t3.x);
+      }
+      Ns <<= 2;
+      lNs += 2;
+    } else {
+      const int lQ = logM - 1, Q = 1 << lQ;
+      const int tsh = logM - 1 - lNs;
+      for (int t = threadIdx.x; t < (nf << lQ); t += blockDim.x) {
+        const int f = t >> lQ, j = t & (Q - 1), k = j & (Ns - 1);
+        const double2* x = a + (f << logM);
+        double2* y = b + (f << logM);
+        double2 v0 = x[j], v1 = cmul(x[j + Q], tw[k << tsh]);
+        const int d = ((j - k) << 1) + k;
+        y[d] = make_double2(v0.x + v1.x, v0.y + v1.y);
+        y[d + Ns] = make_double2(v0.x - v1.x, v0.y - v1.y);
+      }
+      Ns <<= 1;
+      lNs += 1;
     }
     __syncthreads();
+    double2* t = a;
+    a = b;
+    b = t;
   }
+  return a;
 }
 
-// coordinate of line l of the tile and element j (1..N-1) along the axis
+// address of element j (1..N-1 along the axis) of the line at tile
+// coordinate u and remaining coordinate w
 __device__ __forceinline__ int64_t elem_addr(const DstArgs& a, int u, int w, int j) {
   const GridDesc& g = a.g;
   int c[3] = {0, 0, 0};
@@ -85,21 +126,74 @@ __device__ __forceinline__ int64_t elem_addr(const DstArgs& a, int u, int w, int
   return (int64_t)c[0] + (int64_t)g.n1 * ((int64_t)c[1] + (int64_t)g.n1 * c[2]);
 }
 
+__device__ __forceinline__ double eigenvalue(const DstArgs& a, int k, int u, int w) {
+  const GridDesc& g = a.g;
+  double sv[3] = {0.0, 0.0, 0.0};
+  int ua = a.ax == 0 ? 1 : 0;
+  sv[a.ax] = a.eig1[k];
+  sv[ua] = a.eig1[u];
+  if (g.d == 3) sv[3 - a.ax - ua] = a.eig1[w];
+  double h2 = g.h * g.h;
+  double lap = 0.0, pr = 0.0;
+  for (int t = 0; t < g.d; ++t) {
+    lap += sv[t];
+    for (int t2 = t + 1; t2 < g.d; ++t2) pr += sv[t] * sv[t2];
+  }
+  if (g.order == 2) return lap - g.kappa;
+  double lam = lap + h2 / 6.0 * pr;
+  if (g.d == 3) lam += h2 * h2 / 48.0 * sv[0] * sv[1] * sv[2];
+  return lam - g.kappa * (1.0 + h2 / 12.0 * lap);
+}
+
 __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
+  if (a.ctl && a.ctl[1]) return;
   extern __shared__ double2 lds[];
-  double2* buf = lds;                               // [nf][M]
-  double2* tw = lds + (a.TL / 2) * a.M;             // [M/2]
   const GridDesc& g = a.g;
   const int N = g.N, M = a.M, TL = a.TL, nf = TL / 2;
+  double2* A = lds;                                 // [nf][M]
+  double2* B = lds + nf * M;                        // [nf][M]
   const int tile = blockIdx.x % a.tiles_u;
   const int w = blockIdx.x / a.tiles_u + 1;         // remaining interior coordinate (3D)
   const int u0 = 1 + tile * TL;                     // first tile coordinate
-  for (int m = threadIdx.x; m < M / 2; m += blockDim.x) tw[m] = a.tw[m];
-  // zero the working set (positions 0 and N of every sequence stay zero)
-  for (int i = threadIdx.x; i < nf * M; i += blockDim.x) buf[i] = make_double2(0.0, 0.0);
-  __syncthreads();
   const int nl = N - 1;
   const int total = TL * nl;
+  if (a.src_corr) {
+    // F = -sum over cut neighbours Q of A_PQ (C^(reg P) - C^(reg Q))(x_Q) at
+    // the irregular nodes of the tile's rows (correction values of the
+    // current density, computed just before), zero elsewhere
+    for (int i = threadIdx.x; i < nf * M; i += blockDim.x) A[i] = make_double2(0.0, 0.0);
+    __syncthreads();
+    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    for (int l = wave; l < TL; l += nw) {
+      const int u = u0 + l;
+      if (u > nl) continue;
+      const int64_t row = (int64_t)u + (int64_t)g.n1 * (g.d == 3 ? w : 0);
+      for (int t = a.row_start[row] + lane; t < a.row_end[row]; t += 64) {
+        double F = 0.0;
+        for (int m = 0; m < a.maxpairs; ++m) {
+          const double cf = a.PA[(int64_t)t * a.maxpairs + m];
+          if (cf == 0.0) break;
+          const int e1 = a.PE1[(int64_t)t * a.maxpairs + m], e2 = a.PE2[(int64_t)t * a.maxpairs + m];
+          const double c1 = e1 >= 0 ? a.Cv[e1] : 0.0, c2 = e2 >= 0 ? a.Cv[e2] : 0.0;
+          F -= cf * (c1 - c2);
+        }
+        const int j = a.irr[t] % g.n1;
+        double2* z = A + (l >> 1) * M;
+        if (l & 1) {
+          z[j].y = F;
+          z[M - j].y = -F;
+        } else {
+          z[j].x = F;
+          z[M - j].x = -F;
+        }
+      }
+    }
+    __syncthreads();
+  } else {
+  for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+    A[f * M] = make_double2(0.0, 0.0);
+    A[f * M + N] = make_double2(0.0, 0.0);
+  }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     int l, j;
     if (a.ax == 0) {
@@ -110,94 +204,40 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
       j = idx / TL + 1;
     }
     int u = u0 + l;
-    double x = u <= N - 1 ? a.in[elem_addr(a, u, w, j)] : 0.0;
-    int f = l >> 1;
-    unsigned p1 = bitrev((unsigned)j, a.logM), p2 = bitrev((unsigned)(M - j), a.logM);
+    double x = u <= nl ? a.in[elem_addr(a, u, w, j)] : 0.0;
+    double2* z = A + (l >> 1) * M;
     if (l & 1) {
-      buf[f * M + p1].y = x;
-      buf[f * M + p2].y = -x;
+      z[j].y = x;
+      z[M - j].y = -x;
     } else {
-      buf[f * M + p1].x = x;
-      buf[f * M + p2].x = -x;
+      z[j].x = x;
+      z[M - j].x = -x;
     }
   }
   __syncthreads();
-  fft_lds(buf, tw, nf, M, a.logM);
+  }
+  double2* R = fft_stockham(A, B, a.tw, nf, M, a.logM);
   if (a.mode == 1) {
-    // unpack, divide by lambda and scale; the scaled coefficients are
-    // stashed in the unused upper half of each sequence, then re-placed as
-    // new odd sequences in bit-reversed order for the inverse transform
+    // S_A(k) = -Im Z_k / 2 (even line), S_B(k) = Re Z_k / 2 (odd line); divide
+    // by lambda, scale, and form the odd sequences of the inverse transform
+    double2* S = R == A ? B : A;
+    for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+      S[f * M] = make_double2(0.0, 0.0);
+      S[f * M + N] = make_double2(0.0, 0.0);
+    }
     for (int idx = threadIdx.x; idx < nf * nl; idx += blockDim.x) {
       int f = idx / nl, k = idx % nl + 1;
-      double2 Z = buf[f * M + k];
-      // S_A = -Im/2 (even line), S_B = Re/2 (odd line)
-      double SA = -0.5 * Z.y, SB = 0.5 * Z.x;
+      double2 Z = R[f * M + k];
       int uA = u0 + 2 * f, uB = uA + 1;
-      // mode indices of the already transformed axes are the line coordinates
-      double s_ax = a.eig1[k];
-      double lamA, lamB;
-      {
-        double sA[3], sB[3];
-        int ua = a.ax == 0 ? 1 : 0;
-        for (int t = 0; t < 3; ++t) sA[t] = sB[t] = 0.0;
-        sA[a.ax] = s_ax;
-        sB[a.ax] = s_ax;
-        sA[ua] = a.eig1[uA <= N - 1 ? uA : 1];
-        sB[ua] = a.eig1[uB <= N - 1 ? uB : 1];
-        if (g.d == 3) {
-          int wa = 3 - a.ax - ua;
-          sA[wa] = a.eig1[w];
-          sB[wa] = a.eig1[w];
-        }
-        double h2 = g.h * g.h;
-        double lapA = 0.0, lapB = 0.0, prA = 0.0, prB = 0.0;
-        for (int t = 0; t < g.d; ++t) {
-          lapA += sA[t];
-          lapB += sB[t];
-          for (int t2 = t + 1; t2 < g.d; ++t2) {
-            prA += sA[t] * sA[t2];
-            prB += sB[t] * sB[t2];
-          }
-        }
-        if (g.order == 2) {
-          lamA = lapA - g.kappa;
-          lamB = lapB - g.kappa;
-        } else {
-          lamA = lapA + h2 / 6.0 * prA;
-          lamB = lapB + h2 / 6.0 * prB;
-          if (g.d == 3) {
-            lamA += h2 * h2 / 48.0 * sA[0] * sA[1] * sA[2];
-            lamB += h2 * h2 / 48.0 * sB[0] * sB[1] * sB[2];
-          }
-          lamA -= g.kappa * (1.0 + h2 / 12.0 * lapA);
-          lamB -= g.kappa * (1.0 + h2 / 12.0 * lapB);
-        }
-      }
-      // stash the scaled coefficients in the (unused) slot M - k
-      buf[f * M + (M - k)] = make_double2(a.scale * SA / lamA, a.scale * SB / lamB);
+      double lamA = eigenvalue(a, k, uA <= nl ? uA : 1, w);
+      double lamB = eigenvalue(a, k, uB <= nl ? uB : 1, w);
+      double2 c = make_double2(a.scale * (-0.5 * Z.y) / lamA, a.scale * (0.5 * Z.x) / lamB);
+      S[f * M + k] = c;
+      S[f * M + M - k] = make_double2(-c.x, -c.y);
     }
     __syncthreads();
-    // move stashed values into registers per thread, zero, and re-place
-    for (int f0 = 0; f0 < nf; ++f0) {
-      // each pass handles one sequence to keep the register footprint small
-      double2 keep[8];
-      int cnt = 0;
-      for (int k = threadIdx.x + 1; k <= nl && cnt < 8; k += blockDim.x) keep[cnt++] = buf[f0 * M + (M - k)];
-      __syncthreads();
-      for (int i = threadIdx.x; i < M; i += blockDim.x) buf[f0 * M + i] = make_double2(0.0, 0.0);
-      __syncthreads();
-      cnt = 0;
-      for (int k = threadIdx.x + 1; k <= nl && cnt < 8; k += blockDim.x) {
-        double2 v = keep[cnt++];
-        unsigned p1 = bitrev((unsigned)k, a.logM), p2 = bitrev((unsigned)(M - k), a.logM);
-        buf[f0 * M + p1] = make_double2(v.x, v.y);
-        buf[f0 * M + p2] = make_double2(-v.x, -v.y);
-      }
-      __syncthreads();
-    }
-    fft_lds(buf, tw, nf, M, a.logM);
+    R = fft_stockham(S, R, a.tw, nf, M, a.logM);
   }
-  // unpack and store
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     int l, k;
     if (a.ax == 0) {
@@ -208,24 +248,38 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
       k = idx / TL + 1;
     }
     int u = u0 + l;
-    if (u > N - 1) continue;
-    double2 Z = buf[(l >> 1) * M + k];
-    double v = (l & 1) ? 0.5 * Z.x : -0.5 * Z.y;
-    a.out[elem_addr(a, u, w, k)] = v;
+    if (u > nl) continue;
+    double2 Z = R[(l >> 1) * M + k];
+    a.out[elem_addr(a, u, w, k)] = (l & 1) ? 0.5 * Z.x : -0.5 * Z.y;
   }
 }
 
-// lines per tile: (TL/2) sequences of M complex values plus M/2 twiddles
-// within LDS_COMPLEX complex slots (64 KiB)
+// lines per tile: two ping-pong buffers of (TL/2) sequences of M complex
+// values within LDS_COMPLEX slots (64 KiB)
 int tile_lines(int M) {
-  int nf = (LDS_COMPLEX - M / 2) / M;
+  int nf = LDS_COMPLEX / (2 * M);
   if (nf > 16) nf = 16;
   if (nf < 1) nf = 1;
   return 2 * nf;
 }
 
-void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out) {
+void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out, const double* psi = nullptr,
+                 bool src_corr = false) {
   DstArgs a;
+  a.ctl = pl->ctl_active;
+  a.src_corr = src_corr ? 1 : 0;
+  a.psi = psi;
+  a.Vb = pl->V;
+  a.n_dof = pl->n_dof;
+  a.row_start = pl->row_start;
+  a.row_end = pl->row_end;
+  a.irr = pl->irr;
+  a.PE1 = pl->PE1;
+  a.PE2 = pl->PE2;
+  a.PA = pl->PA;
+  a.Cv = pl->Cv;
+  a.maxpairs = pl->maxpairs;
+  a.nF = pl->nF;
   a.g = pl->g;
   a.ax = ax;
   a.mode = mode;
@@ -248,7 +302,7 @@ void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out)
   a.scale = 1.0;
   for (int t = 0; t < pl->g.d; ++t) a.scale *= 2.0 / pl->g.N;
   unsigned blocks = (unsigned)a.tiles_u * (pl->g.d == 3 ? nl : 1);
-  size_t lds = sizeof(double2) * ((size_t)(a.TL / 2) * a.M + a.M / 2);
+  size_t lds = sizeof(double2) * 2 * (size_t)(a.TL / 2) * a.M;
   hipLaunchKernelGGL(k_dst, dim3(blocks), dim3(KFBI_BLOCK), lds, pl->stream, a);
 }
 
@@ -256,8 +310,8 @@ void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out)
 
 kfbi_status dst_init(kfbi_plan* pl) {
   int N = pl->g.N, M = 2 * N;
-  std::vector<double> tw((size_t)M), eig((size_t)N + 1);
-  for (int m = 0; m < M / 2; ++m) {
+  std::vector<double> tw((size_t)2 * M), eig((size_t)N + 1);
+  for (int m = 0; m < M; ++m) {
     double ang = -2.0 * M_PI * (double)m / (double)M;
     tw[2 * m] = cos(ang);
     tw[2 * m + 1] = sin(ang);
@@ -266,9 +320,9 @@ kfbi_status dst_init(kfbi_plan* pl) {
     double sn = sin((double)k * M_PI / (2.0 * N));
     eig[k] = -4.0 / (pl->g.h * pl->g.h) * sn * sn;
   }
-  HIPCHK(hipMemcpy(pl->tw, tw.data(), sizeof(double) * M, hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpy(pl->tw, tw.data(), sizeof(double) * 2 * M, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(pl->eig1, eig.data(), sizeof(double) * (N + 1), hipMemcpyHostToDevice));
-  int lds = (int)(sizeof(double2) * ((size_t)(tile_lines(M) / 2) * M + M / 2));
+  int lds = (int)(sizeof(double2) * 2 * (size_t)(tile_lines(M) / 2) * M);
   if (lds > 65536) {
     kfbi_set_error("box solver LDS footprint too large (N = %d)", N);
     return KFBI_E_INVALID;
@@ -278,7 +332,7 @@ kfbi_status dst_init(kfbi_plan* pl) {
 
 void dst_solve(kfbi_plan* pl, const double* F, double* v) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (pl->prof_on && pl->prof_ev) {
+  if (pl->prof_on && pl->prof_ev && !pl->ctl_active) {
     if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
       (void)hipEventRecord(e0, pl->stream);
     } else {
@@ -301,5 +355,21 @@ void dst_solve(kfbi_plan* pl, const double* F, double* v) {
     pl->prof_ev->push_back(e0);
     pl->prof_ev->push_back(e1);
     pl->prof_launches += pl->g.d == 2 ? 3 : 5;
+  }
+}
+
+// box solve of the matvec: the right-hand side is formed from the density
+// inside the first pass (no right-hand-side array)
+void dst_solve_corrections(kfbi_plan* pl, const double* psi, double* v) {
+  if (pl->g.d == 2) {
+    launch_pass(pl, 0, 0, nullptr, pl->T1, psi, true);
+    launch_pass(pl, 1, 1, pl->T1, pl->T2);
+    launch_pass(pl, 0, 0, pl->T2, v);
+  } else {
+    launch_pass(pl, 0, 0, nullptr, pl->T1, psi, true);
+    launch_pass(pl, 1, 0, pl->T1, pl->T2);
+    launch_pass(pl, 2, 1, pl->T2, pl->T1);
+    launch_pass(pl, 1, 0, pl->T1, pl->T2);
+    launch_pass(pl, 0, 0, pl->T2, v);
   }
 }

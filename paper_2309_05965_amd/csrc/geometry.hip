@@ -218,29 +218,86 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_count(int64_t n, Pred pred, int*
   }
 }
 
-// exclusive scan of blk[0..nb) in place (one block of 1024 threads); total -> *tot
+// exclusive scan of blk[0..nb) in place (one block of 1024 threads, each
+// owning a contiguous chunk; wave-level shuffle scans, two barriers);
+// total -> *tot
 __global__ void __launch_bounds__(1024) k_scan(int* blk, int64_t nb, int* tot) {
-  __shared__ long long sh[1024];
+  __shared__ long long wpre[16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   int64_t per = (nb + 1023) / 1024;
   int64_t b0 = (int64_t)threadIdx.x * per;
   int64_t b1 = b0 + per < nb ? b0 + per : nb;
   long long s = 0;
   for (int64_t i = b0; i < b1; ++i) s += blk[i];
-  sh[threadIdx.x] = s;
-  __syncthreads();
-  for (int off = 1; off < 1024; off <<= 1) {
-    long long v = threadIdx.x >= (unsigned)off ? sh[threadIdx.x - off] : 0;
-    __syncthreads();
-    sh[threadIdx.x] += v;
-    __syncthreads();
+  long long v = s;
+  for (int off = 1; off < 64; off <<= 1) {
+    long long n = __shfl_up(v, off, 64);
+    if (lane >= off) v += n;
   }
-  long long run = sh[threadIdx.x] - s;
+  if (lane == 63) wpre[wave] = v;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    long long run = 0;
+    for (int w = 0; w < 16; ++w) {
+      long long t = wpre[w];
+      wpre[w] = run;
+      run += t;
+    }
+    *tot = (int)run;
+  }
+  __syncthreads();
+  long long run = wpre[wave] + v - s;
   for (int64_t i = b0; i < b1; ++i) {
     int t = blk[i];
     blk[i] = (int)run;
     run += t;
   }
-  if (threadIdx.x == 1023) *tot = (int)sh[1023];
+}
+
+// device-wide exclusive scan out[i] = sum_{j<i} in[j]: block sums, scan of
+// the block sums, then a block-local scan per chunk (coalesced, in order)
+__global__ void __launch_bounds__(KFBI_BLOCK) k_scan_sums(int64_t n, const int* in, int* blk) {
+  int64_t base = (int64_t)blockIdx.x * CMP_CH;
+  int c = 0;
+  for (int j = 0; j < CMP_IT; ++j) {
+    int64_t i = base + (int64_t)j * KFBI_BLOCK + threadIdx.x;
+    if (i < n) c += in[i];
+  }
+  __shared__ int red[KFBI_BLOCK / 64];
+  c = wave_sum(c);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int w = 0; w < KFBI_BLOCK / 64; ++w) s += red[w];
+    blk[blockIdx.x] = s;
+  }
+}
+
+__global__ void __launch_bounds__(KFBI_BLOCK) k_scan_apply(int64_t n, const int* in, int* out, const int* blk) {
+  __shared__ int wtot[KFBI_BLOCK / 64];
+  int64_t base = (int64_t)blockIdx.x * CMP_CH;
+  int run = blk[blockIdx.x];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int j = 0; j < CMP_IT; ++j) {
+    int64_t i = base + (int64_t)j * KFBI_BLOCK + threadIdx.x;
+    int x = i < n ? in[i] : 0;
+    int v = x;
+    for (int off = 1; off < 64; off <<= 1) {
+      int y = __shfl_up(v, off, 64);
+      if (lane >= off) v += y;
+    }
+    if (lane == 63) wtot[wave] = v;
+    __syncthreads();
+    int pre = 0, tot = 0;
+    for (int w = 0; w < KFBI_BLOCK / 64; ++w) {
+      if (w < wave) pre += wtot[w];
+      tot += wtot[w];
+    }
+    if (i < n) out[i] = run + pre + v - x;
+    run += tot;
+    __syncthreads();
+  }
 }
 
 template <class Pred, class Emit>
@@ -1210,8 +1267,14 @@ kfbi_status geo_setup(kfbi_plan* pl) {
   HIPCHK(hipMemsetAsync(pl->cell_count, 0, sizeof(int) * (nkeys + 1), st));
   BinArgs ba{g, nd, pl->ncell_axis, pl->ncell, pl->d2s, pl->s_pos, pl->s_meta, pl->cell_count, nullptr};
   hipLaunchKernelGGL(k_bin_count, dim3(nblk(nd)), dim3(KFBI_BLOCK), 0, st, ba);
-  HIPCHK(hipMemcpyAsync(pl->cell_start, pl->cell_count, sizeof(int) * nkeys, hipMemcpyDeviceToDevice, st));
-  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, pl->cell_start, nkeys, pl->blk_total);
+  {
+    int64_t nbs = (nkeys + CMP_CH - 1) / CMP_CH;
+    KCHK(ensure_blk(pl, nbs));
+    hipLaunchKernelGGL(k_scan_sums, dim3((unsigned)nbs), dim3(KFBI_BLOCK), 0, st, nkeys, pl->cell_count, pl->blk);
+    hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, st, pl->blk, nbs, pl->blk_total);
+    hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nbs), dim3(KFBI_BLOCK), 0, st, nkeys, pl->cell_count,
+                       pl->cell_start, pl->blk);
+  }
   KCHK(ensure_blk(pl, nkeys));
   int* cursor = pl->blk;   // scan scratch reused as per-cell cursor
   HIPCHK(hipMemsetAsync(cursor, 0, sizeof(int) * nkeys, st));

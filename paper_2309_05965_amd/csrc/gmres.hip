@@ -1,10 +1,12 @@
 // Step S6 -- GMRES driver kernels (Alg. 1 Steps 2 and 4).
 //
-// Unrestarted GMRES with modified Gram-Schmidt and Givens rotations; the
-// stopping test |g_{k}| <= tol |b| is taken on the host from one scalar
-// read back per iteration.  The Krylov basis V[j][n] and the Hessenberg
-// columns live in device memory; every reduction is a fixed-order tree in
-// one work group, so results are bitwise reproducible run to run.
+// Unrestarted GMRES (CGS2 Arnoldi, Givens rotations).  The iteration index,
+// the stopping test |g_k| <= tol |b| and the iteration count live in a
+// device control word, so the host can launch a captured iteration
+// (matvec + Arnoldi step) repeatedly and read the state back only now and
+// then.  The Krylov basis V[j][n] and the Hessenberg columns live in device
+// memory; every reduction has a fixed order, so results are bitwise
+// reproducible run to run.
 #include <math.h>
 
 #include "kfbi_internal.h"
@@ -26,9 +28,11 @@ __device__ double block_sum(double v, double* sh) {
   return t;
 }
 
-// r0 = b - A x0 (or b); beta = |r0|; V0 = r0 / beta; g0 = beta; scal[1] = |b|
+// r0 = b - A x0 (or b); beta = |r0|; V0 = r0 / beta; g0 = beta; scal[1] = |b|.
+// Initialises the control word ctl = [j = 0, done, k = 0, max_iter] and the
+// stopping threshold scal[3] = tol.
 __global__ void __launch_bounds__(GB) k_start(int64_t n, const double* b, const double* Ax0, double* V,
-                                             double* gv, double* scal) {
+                                             double* gv, double* scal, int* ctl, double tol, int maxit) {
   __shared__ double sh[GB];
   double sb = 0.0, sr = 0.0;
   for (int64_t i = threadIdx.x; i < n; i += GB) {
@@ -46,34 +50,76 @@ __global__ void __launch_bounds__(GB) k_start(int64_t n, const double* b, const 
     scal[0] = beta;
     scal[1] = nb;
     scal[2] = 0.0;
+    scal[3] = tol;
+    ctl[0] = 0;
+    ctl[1] = (nb == 0.0 || beta <= tol * nb) ? 1 : 0;
+    ctl[2] = 0;
+    ctl[3] = maxit;
   }
 }
 
-// Arnoldi step j: w = V[j+1] (holds A V[j]) orthogonalised against V[0..j]
-// by MGS, normalised, then the Givens rotations are applied to column j.
-__global__ void __launch_bounds__(GB) k_arnoldi(int64_t n, int j, int ldh, double* V, double* Hm, double* cs,
+// Arnoldi step j: w = V[j+1] (holds A V[j]) is orthogonalised against
+// V[0..j] by classical Gram-Schmidt applied twice (CGS2: the j+1 dot
+// products of a pass are computed concurrently, one wavefront per basis
+// vector, with fixed-order wave reductions), then normalised; the Givens
+// rotations are applied to column j.
+__device__ __forceinline__ double wave_reduce(double v) {
+  for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
+  return v;
+}
+
+__global__ void __launch_bounds__(GB) k_arnoldi(int64_t n, int* ctl, int ldh, double* V, double* Hm, double* cs,
                                                double* sn, double* gv, double* scal) {
-  __shared__ double sh[GB];
+  __shared__ double hp[KFBI_GMRES_MAX + 1];
+  __shared__ double hs[KFBI_GMRES_MAX + 1];
+  __shared__ double red[GB / 64];
+  if (ctl[1]) return;
+  const int j = ctl[0];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double* w = V + (int64_t)(j + 1) * n;
   double* hcol = Hm + (int64_t)j * ldh;
-  for (int i = 0; i <= j; ++i) {
-    const double* vi = V + (int64_t)i * n;
-    double s = 0.0;
-    for (int64_t t = threadIdx.x; t < n; t += GB) s += w[t] * vi[t];
-    double hij = block_sum(s, sh);
-    for (int64_t t = threadIdx.x; t < n; t += GB) w[t] = w[t] - hij * vi[t];
-    if (threadIdx.x == 0) hcol[i] = hij;
+  for (int pass = 0; pass < 2; ++pass) {
+    // one wavefront per basis vector: h_i = <w, V_i>; four independent
+    // partial sums per lane keep several loads in flight
+    for (int i = wave; i <= j; i += GB / 64) {
+      const double* vi = V + (int64_t)i * n;
+      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
+      int64_t t = lane;
+      for (; t + 192 < n; t += 256) {
+        s0 += w[t] * vi[t];
+        s1 += w[t + 64] * vi[t + 64];
+        s2 += w[t + 128] * vi[t + 128];
+        s3 += w[t + 192] * vi[t + 192];
+      }
+      for (; t < n; t += 64) s0 += w[t] * vi[t];
+      double sacc = wave_reduce((s0 + s1) + (s2 + s3));
+      if (lane == 0) hp[i] = sacc;
+    }
+    __syncthreads();
+    for (int i = threadIdx.x; i <= j; i += GB) hs[i] = pass == 0 ? hp[i] : hs[i] + hp[i];
+    for (int64_t t = threadIdx.x; t < n; t += GB) {
+      double v = w[t];
+#pragma unroll 8
+      for (int i = 0; i <= j; ++i) v -= hp[i] * V[(int64_t)i * n + t];
+      w[t] = v;
+    }
     __syncthreads();
   }
-  double s = 0.0;
-  for (int64_t t = threadIdx.x; t < n; t += GB) s += w[t] * w[t];
-  double hn = sqrt(block_sum(s, sh));
+  double sq = 0.0;
+  for (int64_t t = threadIdx.x; t < n; t += GB) sq += w[t] * w[t];
+  sq = wave_reduce(sq);
+  if (lane == 0) red[wave] = sq;
+  __syncthreads();
+  double tot = 0.0;
+  for (int wv = 0; wv < GB / 64; ++wv) tot += red[wv];
+  double hn = sqrt(tot);
   bool breakdown = !(hn > 0.0);
   if (!breakdown) {
     double inv = 1.0 / hn;
     for (int64_t t = threadIdx.x; t < n; t += GB) w[t] = w[t] * inv;
   }
   if (threadIdx.x == 0) {
+    for (int i = 0; i <= j; ++i) hcol[i] = hs[i];
     hcol[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
       double t = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
@@ -87,8 +133,12 @@ __global__ void __launch_bounds__(GB) k_arnoldi(int64_t n, int j, int ldh, doubl
     hcol[j + 1] = 0.0;
     gv[j + 1] = -sn[j] * gv[j];
     gv[j] = cs[j] * gv[j];
-    scal[0] = fabs(gv[j + 1]);
+    double res = fabs(gv[j + 1]);
+    scal[0] = res;
     scal[2] = breakdown ? 1.0 : 0.0;
+    ctl[2] = j + 1;
+    ctl[0] = j + 1;
+    ctl[1] = (res <= scal[3] * scal[1] || breakdown || j + 1 >= ctl[3]) ? 1 : 0;
   }
 }
 
@@ -128,13 +178,13 @@ __global__ void __launch_bounds__(GB) k_resid(int64_t n, const double* b, const 
 
 }  // namespace
 
-void gm_residual_start(kfbi_plan* pl, const double* b, const double* Ax0, int use_x0) {
+void gm_residual_start(kfbi_plan* pl, const double* b, const double* Ax0, int use_x0, double tol, int maxit) {
   hipLaunchKernelGGL(k_start, dim3(1), dim3(GB), 0, pl->stream, pl->n_dof, b, use_x0 ? Ax0 : nullptr, pl->V,
-                     pl->gv, pl->scal);
+                     pl->gv, pl->scal, pl->ctl, tol, maxit);
 }
 
-void gm_arnoldi(kfbi_plan* pl, int j) {
-  hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(GB), 0, pl->stream, pl->n_dof, j, pl->gm_cap + 1, pl->V, pl->Hm,
+void gm_arnoldi(kfbi_plan* pl) {
+  hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(GB), 0, pl->stream, pl->n_dof, pl->ctl, pl->gm_cap + 1, pl->V, pl->Hm,
                      pl->cs, pl->sn, pl->gv, pl->scal);
 }
 

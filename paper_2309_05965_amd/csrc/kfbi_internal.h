@@ -88,6 +88,30 @@ struct kfbi_plan {
   double *V, *Hm, *gv, *cs, *sn, *work, *work2, *bvec, *scal;
   int gm_cap;
   int64_t gm_n;
+  // folded operators of the matvec (set-up products of the inverses with the
+  // density extension): C at entry e = sum_t FW[e][t] psi[FI[e][t]],
+  // d_n C at centre c = sum_t GW[c][t] psi[GI[c][t]]  (nF = nN p terms)
+  int nF, maxpairs;
+  int *FI, *GI;
+  double *FW, *GW, *IW;          // IW: [n_dof][(q+1)^d] normal-derivative weights
+  double* Cv;                    // [n_corr] correction values of the current matvec
+  int* IB;                       // [n_dof] first node of the interpolation block
+  int *IE1, *IE2;                // [n_dof][(q+1)^d] entries of C^(k), C^(reg q) at block nodes
+  double* PA;                    // [n_irr][maxpairs] stencil coefficients of the cut neighbours
+  int *PE1, *PE2;                // [n_irr][maxpairs] entries of C^(reg P), C^(reg Q)
+  int *EI;                       // [K][n_nodes] entry index of (interface, node), -1 if none
+  int *row_start, *row_end;      // irregular nodes of every x-line
+  int64_t cap_fold_corr, cap_fold_dof, cap_fold_irr;
+  // GMRES iteration on the device: control word [j, done, k, max_iter] and a
+  // captured graph of one iteration (matvec + Arnoldi step)
+  int* ctl;
+  const int* ctl_active;         // non-null while the iteration is captured
+  hipStream_t gstream;           // private stream of kfbi_solve (graph launches)
+  hipEvent_t ev_in, ev_out;
+  hipGraph_t graph;
+  hipGraphExec_t graph_exec;
+  uint64_t graph_key[20];
+  int* h_ctl;
   // box-solve event timing
   int prof_on;
   std::vector<hipEvent_t>* prof_ev;
@@ -125,14 +149,17 @@ void op_rhs_correct(kfbi_plan* pl, double* F, bool overwrite);
 void op_boundary(kfbi_plan* pl, const double* gB, double* v);
 void op_normal_derivatives(kfbi_plan* pl, const double* v, double* dn_in, double* dn_out,
                            double* Apsi);
+kfbi_status op_fold(kfbi_plan* pl);
+void op_matvec(kfbi_plan* pl, const double* psi, double* Apsi);
 void op_bie_rhs(kfbi_plan* pl, const double* g2, const double* dn_in, const double* dn_out,
                 double* b);
 // dst.hip (step S3)
 kfbi_status dst_init(kfbi_plan* pl);
 void dst_solve(kfbi_plan* pl, const double* F, double* v);
+void dst_solve_corrections(kfbi_plan* pl, const double* psi, double* v);
 // gmres.hip (step S6)
-void gm_residual_start(kfbi_plan* pl, const double* b, const double* Ax0, int use_x0);
-void gm_arnoldi(kfbi_plan* pl, int j);
+void gm_residual_start(kfbi_plan* pl, const double* b, const double* Ax0, int use_x0, double tol, int maxit);
+void gm_arnoldi(kfbi_plan* pl);
 void gm_update(kfbi_plan* pl, int k, double* x, int use_x0);
 void gm_true_residual(kfbi_plan* pl, const double* b, const double* Ax, double* out2);
 

@@ -120,8 +120,14 @@ __device__ __forceinline__ double mono_eval(const Mono& M, const double* U, cons
 }
 
 // ---------------------------------------------------------------- kernels
+// ctl != null: GMRES iteration on the device; the input is the basis vector
+// V[j] with j = ctl[0], and nothing is done once ctl[1] (converged) is set
 __global__ void k_extend(int64_t ns, int p, const int* idx, const double* w, const double* psi,
-                         double* out) {
+                         double* out, const int* ctl, const double* Vb, int64_t nv) {
+  if (ctl) {
+    if (ctl[1]) return;
+    psi = Vb + (int64_t)ctl[0] * nv;
+  }
   int64_t s = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (s >= ns) return;
   double v = 0.0;
@@ -223,6 +229,7 @@ __global__ void k_rhs_base(RhsArgs a) {
 }
 
 struct RhsCorrArgs {
+  const int* ctl;
   GridDesc g;
   Stencil S;
   int64_t n_irr;
@@ -234,6 +241,7 @@ struct RhsCorrArgs {
 };
 
 __global__ void k_rhs_correct(RhsCorrArgs a) {
+  if (a.ctl && a.ctl[1]) return;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.n_irr) return;
   const GridDesc& g = a.g;
@@ -267,85 +275,6 @@ __global__ void k_boundary(GridDesc g, const double* gB, double* v) {
   if (bd) v[i] = gB ? gB[i] : 0.0;
 }
 
-struct NdArgs {
-  GridDesc g;
-  int nC;
-  int lin[3];
-  int64_t n_dof;
-  const int *d2s, *meta;
-  const double *spos, *snrm, *U, *v, *Cg;
-  const int8_t* region;
-  double *dn_in, *dn_out, *Apsi;
-};
-
-// corrected tensor-product Lagrange interpolation of degree q = p on the
-// (q+1)^d block centred at floor(t + 1/2), clamped into the grid (Sec. 5.5)
-__global__ void k_normal_derivative(NdArgs a) {
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.n_dof) return;
-  const GridDesc& g = a.g;
-  const int q = g.p;
-  int s = a.d2s[c];
-  int k = a.meta[(int64_t)s * 5 + 3];
-  const double* P = a.spos + (int64_t)s * g.d;
-  const double* nv = a.snrm + (int64_t)s * g.d;
-  int st[3] = {0, 0, 0};
-  double val[3][5], der[3][5];
-  for (int ax = 0; ax < 3; ++ax)
-    for (int j = 0; j < 5; ++j) val[ax][j] = (ax < g.d ? 0.0 : (j == 0 ? 1.0 : 0.0)), der[ax][j] = 0.0;
-  for (int ax = 0; ax < g.d; ++ax) {
-    double t = (P[ax] - g.lo) / g.h;
-    int b0 = (int)floor(t + 0.5) - q / 2;
-    if (b0 < 0) b0 = 0;
-    if (b0 > g.N - q) b0 = g.N - q;
-    st[ax] = b0;
-    double u = t - (double)b0;
-    for (int j = 0; j <= q; ++j) {
-      double v = 1.0;
-      for (int m = 0; m <= q; ++m)
-        if (m != j) v = v * (u - (double)m) / (double)(j - m);
-      val[ax][j] = v;
-      double dv = 0.0;
-      for (int l = 0; l <= q; ++l) {
-        if (l == j) continue;
-        double w = 1.0 / (double)(j - l);
-        for (int m = 0; m <= q; ++m)
-          if (m != j && m != l) w = w * (u - (double)m) / (double)(j - m);
-        dv += w;
-      }
-      der[ax][j] = dv;
-    }
-  }
-  double grad[3] = {0.0, 0.0, 0.0};
-  int nz = g.d == 3 ? q + 1 : 1;
-  for (int b2 = 0; b2 < nz; ++b2)
-    for (int b1 = 0; b1 <= q; ++b1)
-      for (int b0 = 0; b0 <= q; ++b0) {
-        int64_t Q = ravel(g, st[0] + b0, st[1] + b1, st[2] + b2);
-        int rq = a.region[Q];
-        double vt = a.v[Q];
-        if (rq != k) vt += Cval(a.Cg, g.n_nodes, k, Q) - Cval(a.Cg, g.n_nodes, rq, Q);
-        int bb[3] = {b0, b1, b2};
-        for (int ax = 0; ax < g.d; ++ax) {
-          double w = der[ax][bb[ax]] / g.h;
-          for (int b = 0; b < g.d; ++b)
-            if (b != ax) w = w * val[b][bb[b]];
-          grad[ax] += w * vt;
-        }
-      }
-  double dn = 0.0, dnC = 0.0;
-  const double* Uc = a.U + c * (int64_t)a.nC;
-  for (int ax = 0; ax < g.d; ++ax) {
-    dn += nv[ax] * grad[ax];
-    dnC += nv[ax] * Uc[a.lin[ax]];
-  }
-  dnC = dnC / g.h;
-  double dout = dn - dnC;
-  if (a.dn_in) a.dn_in[c] = dn;
-  if (a.dn_out) a.dn_out[c] = dout;
-  if (a.Apsi) a.Apsi[c] = (g.beta_in * dn - g.beta_out * dout) / (g.beta_in + g.beta_out);
-}
-
 __global__ void k_bie_rhs(GridDesc g, int64_t n_dof, const int* d2s, const double* g2, const double* dn_in,
                           const double* dn_out, double* b) {
   int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -354,12 +283,279 @@ __global__ void k_bie_rhs(GridDesc g, int64_t n_dof, const int* d2s, const doubl
   b[c] = (g2[d2s[c]] - J) / (g.beta_in + g.beta_out);
 }
 
+
+// ---------------------------------------------------------------- folded operators
+// At set-up the inverses and the density extension are folded into the
+// linear maps the matvec needs (U = Minv Q with Q = [0; 0; h psiS(N pts)]):
+//   C at entry e        = sum_t FW[e][t] psi[FI[e][t]]
+//                         (FW = h phi(xi_e)^T Minv[:, N col j] * extension weight)
+//   d_n C_c(p_c)        = sum_t GW[c][t] psi[GI[c][t]]
+//                         (GW = sum_a n_a Minv[e_a, N col j] * extension weight)
+//   d_n v_in(p_c)       = sum_b IW[c][b] vtilde(block node b)
+// plus the cut-neighbour lists of the irregular nodes and the entries of the
+// interpolation blocks, so a matvec is a short chain of gathers.
+struct FoldArgs {
+  GridDesc g;
+  Mono M;
+  int nP, nD, nN, nC, nF, maxpairs;
+  int64_t n_dof, n_corr, n_irr;
+  const int *d2s, *ck, *cnode, *cown, *stN, *ext_idx, *irr, *EI, *meta;
+  const int8_t* region;
+  const double *spos, *snrm, *MinvT, *ext_w;
+  int *FI, *GI, *IB, *IE1, *IE2, *PE1, *PE2;
+  double *FW, *GW, *IW, *PA;
+  Stencil S;
+};
+
+__global__ void k_entry_map(int64_t n_corr, int64_t n_nodes, const int* ck, const int* cnode, int* EI) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n_corr) return;
+  EI[(int64_t)(ck[e] - 1) * n_nodes + cnode[e]] = (int)e;
+}
+
+__global__ void k_fold_corr(FoldArgs a) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= a.n_corr) return;
+  const GridDesc& g = a.g;
+  int c[3];
+  unravel(g, a.cnode[e], c);
+  int own = a.cown[e];
+  const double* P = a.spos + (int64_t)a.d2s[own] * g.d;
+  double xi[3] = {0.0, 0.0, 0.0};
+  for (int ax = 0; ax < g.d; ++ax) xi[ax] = ((g.lo + (double)c[ax] * g.h) - P[ax]) / g.h;
+  const double* Mi = a.MinvT + (int64_t)own * a.nC * a.nC;
+  for (int j = 0; j < a.nN; ++j) {
+    const double* col = Mi + (int64_t)(a.nP + a.nD + j) * a.nC;
+    double sacc = 0.0;
+    for (int al = 0; al < a.nC; ++al) {
+      double t = col[al];
+      for (int ax = 0; ax < g.d; ++ax) {
+        const int ex = a.M.E[al][ax];
+        for (int q = 0; q < ex; ++q) t *= xi[ax];
+      }
+      sacc += t;
+    }
+    const double rn = g.h * sacc;
+    const int sN = a.stN[(int64_t)own * a.nN + j];
+    for (int m = 0; m < g.p; ++m) {
+      const int idx = a.ext_idx[(int64_t)sN * g.p + m];
+      const int64_t o = e * a.nF + (int64_t)j * g.p + m;
+      a.FI[o] = idx >= 0 ? idx : 0;
+      a.FW[o] = idx >= 0 ? rn * a.ext_w[(int64_t)sN * g.p + m] : 0.0;
+    }
+  }
+}
+
+__global__ void k_fold_dof(FoldArgs a) {
+  const GridDesc& g = a.g;
+  const int q = g.p, q1 = q + 1;
+  const int nbk = g.d == 3 ? q1 * q1 * q1 : q1 * q1;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t c = t / nbk;
+  int b = (int)(t % nbk);
+  if (c >= a.n_dof) return;
+  int s = a.d2s[c];
+  const int k = a.meta[(int64_t)s * 5 + 3];
+  const double* P = a.spos + (int64_t)s * g.d;
+  const double* nv = a.snrm + (int64_t)s * g.d;
+  int bb[3] = {b % q1, (b / q1) % q1, b / (q1 * q1)};
+  int st[3] = {0, 0, 0};
+  double val[3], der[3];
+  for (int ax = 0; ax < g.d; ++ax) {
+    double tt = (P[ax] - g.lo) / g.h;
+    int b0 = (int)floor(tt + 0.5) - q / 2;
+    if (b0 < 0) b0 = 0;
+    if (b0 > g.N - q) b0 = g.N - q;
+    st[ax] = b0;
+    double u = tt - (double)b0;
+    int j = bb[ax];
+    double v = 1.0;
+    for (int m = 0; m <= q; ++m)
+      if (m != j) v = v * (u - (double)m) / (double)(j - m);
+    double dv = 0.0;
+    for (int l = 0; l <= q; ++l) {
+      if (l == j) continue;
+      double w = 1.0 / (double)(j - l);
+      for (int m = 0; m <= q; ++m)
+        if (m != j && m != l) w = w * (u - (double)m) / (double)(j - m);
+      dv += w;
+    }
+    val[ax] = v;
+    der[ax] = dv;
+  }
+  double w = 0.0;
+  for (int ax = 0; ax < g.d; ++ax) {
+    double t2 = der[ax] / g.h;
+    for (int o = 0; o < g.d; ++o)
+      if (o != ax) t2 = t2 * val[o];
+    w += nv[ax] * t2;
+  }
+  a.IW[c * nbk + b] = w;
+  // entries of C^(k) and C^(reg q) at the block node (-1 where not needed)
+  const int64_t Q = ravel(g, st[0] + bb[0], st[1] + bb[1], st[2] + bb[2]);
+  const int rq = a.region[Q];
+  int e1 = -1, e2 = -1;
+  if (rq != k) {
+    e1 = a.EI[(int64_t)(k - 1) * g.n_nodes + Q];
+    if (rq != 0) e2 = a.EI[(int64_t)(rq - 1) * g.n_nodes + Q];
+  }
+  a.IE1[c * nbk + b] = e1;
+  a.IE2[c * nbk + b] = e2;
+  if (b == 0) {
+    a.IB[c] = (int)ravel(g, st[0], st[1], st[2]);
+    const double* Mi = a.MinvT + c * (int64_t)a.nC * a.nC;
+    for (int j = 0; j < a.nN; ++j) {
+      const double* col = Mi + (int64_t)(a.nP + a.nD + j) * a.nC;
+      double gsum = 0.0;
+      for (int ax = 0; ax < g.d; ++ax) gsum += nv[ax] * col[1 + ax];   // graded order: 1, x, y(, z)
+      const int sN = a.stN[c * a.nN + j];
+      for (int m = 0; m < g.p; ++m) {
+        const int idx = a.ext_idx[(int64_t)sN * g.p + m];
+        const int64_t o = c * a.nF + (int64_t)j * g.p + m;
+        a.GI[o] = idx >= 0 ? idx : 0;
+        a.GW[o] = idx >= 0 ? gsum * a.ext_w[(int64_t)sN * g.p + m] : 0.0;
+      }
+    }
+  }
+}
+
+// cut neighbours of every irregular node: stencil coefficient and the
+// entries of C^(reg P) and C^(reg Q) at the neighbour (Sec. 5.2 remark)
+__global__ void k_fold_pairs(FoldArgs a) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= a.n_irr) return;
+  const GridDesc& g = a.g;
+  int64_t P = a.irr[t];
+  int c[3];
+  unravel(g, P, c);
+  int rp = a.region[P];
+  int zr = g.d == 3 ? 1 : 0;
+  int m = 0;
+  for (int o2 = -zr; o2 <= zr; ++o2)
+    for (int o1 = -1; o1 <= 1; ++o1)
+      for (int o0 = -1; o0 <= 1; ++o0) {
+        int idx = (o0 + 1) + 3 * (o1 + 1) + 9 * (o2 + 1);
+        double w = a.S.A[idx];
+        if (w == 0.0 || (o0 == 0 && o1 == 0 && o2 == 0)) continue;
+        int64_t Q = ravel(g, c[0] + o0, c[1] + o1, c[2] + o2);
+        int rq = a.region[Q];
+        if (rq == rp) continue;
+        a.PA[t * a.maxpairs + m] = w;
+        a.PE1[t * a.maxpairs + m] = rp ? a.EI[(int64_t)(rp - 1) * g.n_nodes + Q] : -1;
+        a.PE2[t * a.maxpairs + m] = rq ? a.EI[(int64_t)(rq - 1) * g.n_nodes + Q] : -1;
+        ++m;
+      }
+  for (; m < a.maxpairs; ++m) {
+    a.PA[t * a.maxpairs + m] = 0.0;
+    a.PE1[t * a.maxpairs + m] = -1;
+    a.PE2[t * a.maxpairs + m] = -1;
+  }
+}
+
+__global__ void k_irr_rows(int64_t n_irr, int n1, const int* irr, int* rs, int* re) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_irr) return;
+  int row = irr[t] / n1;
+  int prev = t > 0 ? irr[t - 1] / n1 : -1;
+  int next = t + 1 < n_irr ? irr[t + 1] / n1 : -1;
+  if (prev != row) rs[row] = (int)t;
+  if (next != row) re[row] = (int)(t + 1);
+}
+
+// correction values of all entries: C(e) = sum_t FW[e][t] psi[FI[e][t]],
+// G lanes per entry
+template <int G>
+__global__ void __launch_bounds__(KFBI_BLOCK) k_centry(int64_t n_corr, int nF, const int* FI, const double* FW,
+                                                      const double* psi, double* Cv, const int* ctl,
+                                                      const double* Vb, int64_t n_dof) {
+  if (ctl) {
+    if (ctl[1]) return;
+    psi = Vb + (int64_t)ctl[0] * n_dof;
+  }
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t e = t / G;
+  int lane = (int)(t % G);
+  if (e >= n_corr) return;
+  double s = 0.0;
+  for (int q = lane; q < nF; q += G) s += FW[e * nF + q] * psi[FI[e * nF + q]];
+  for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
+  if (lane == 0) Cv[e] = s;
+}
+
+struct InterpArgs {
+  const int* ctl;        // GMRES iteration on the device: psi = V[j], output V[j + 1], j = ctl[0]
+  double* Vb;
+  GridDesc g;
+  int nbk, nC, nF;
+  int64_t n_dof;
+  const int *d2s, *meta, *IB;
+  const double *IW, *U, *snrm, *v, *Cg;
+  // folded matvec path (U == null)
+  const int *IE1, *IE2, *GI;
+  const double *Cv, *GW, *psi;
+  const int8_t* region;
+  double *dn_in, *dn_out, *Apsi;
+};
+
+// one group of G lanes per centre: sum_b IW[c][b] vtilde(b), then the combine
+template <int G>
+__global__ void __launch_bounds__(KFBI_BLOCK) k_interp(InterpArgs a) {
+  if (a.ctl) {
+    if (a.ctl[1]) return;
+    a.psi = a.Vb + (int64_t)a.ctl[0] * a.n_dof;
+    a.Apsi = a.Vb + (int64_t)(a.ctl[0] + 1) * a.n_dof;
+  }
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t c = t / G;
+  int lane = (int)(t % G);
+  if (c >= a.n_dof) return;           // whole groups leave together
+  const GridDesc& g = a.g;
+  const int q1 = g.p + 1;
+  const int s = a.d2s[c];
+  const int k = a.meta[(int64_t)s * 5 + 3];
+  const int64_t base = a.IB[c];
+  const double* w = a.IW + c * a.nbk;
+  double acc = 0.0;
+  for (int b = lane; b < a.nbk; b += G) {
+    int b0 = b % q1, b1 = (b / q1) % q1, b2 = b / (q1 * q1);
+    int64_t Q = base + b0 + (int64_t)g.n1 * (b1 + (int64_t)g.n1 * b2);
+    double vt = a.v[Q];
+    if (a.U) {
+      int rq = a.region[Q];
+      if (rq != k) vt += Cval(a.Cg, g.n_nodes, k, Q) - Cval(a.Cg, g.n_nodes, rq, Q);
+    } else {
+      const int e1 = a.IE1[c * a.nbk + b], e2 = a.IE2[c * a.nbk + b];
+      if (e1 >= 0) vt += a.Cv[e1];
+      if (e2 >= 0) vt -= a.Cv[e2];
+    }
+    acc += w[b] * vt;
+  }
+  double dnC = 0.0;
+  if (!a.U)
+    for (int q = lane; q < a.nF; q += G) dnC += a.GW[c * a.nF + q] * a.psi[a.GI[c * a.nF + q]];
+  for (int off = G / 2; off > 0; off >>= 1) {
+    acc += __shfl_xor(acc, off, G);
+    dnC += __shfl_xor(dnC, off, G);
+  }
+  if (lane != 0) return;
+  if (a.U) {
+    const double* nv = a.snrm + (int64_t)s * g.d;
+    const double* Uc = a.U + c * (int64_t)a.nC;
+    for (int ax = 0; ax < g.d; ++ax) dnC += nv[ax] * Uc[1 + ax];
+    dnC = dnC / g.h;
+  }
+  double dout = acc - dnC;
+  if (a.dn_in) a.dn_in[c] = acc;
+  if (a.dn_out) a.dn_out[c] = dout;
+  if (a.Apsi) a.Apsi[c] = (g.beta_in * acc - g.beta_out * dout) / (g.beta_in + g.beta_out);
+}
+
 }  // namespace
 
 // ---------------------------------------------------------------- launchers
 void op_extend(kfbi_plan* pl, const double* psi, double* psiS) {
   hipLaunchKernelGGL(k_extend, dim3(nb(pl->n_surf)), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_surf, pl->g.p,
-                     pl->ext_idx, pl->ext_w, psi, psiS);
+                     pl->ext_idx, pl->ext_w, psi, psiS, pl->ctl_active, pl->V, pl->n_dof);
 }
 
 void op_coefficients(kfbi_plan* pl, const double* a, const double* b, const double* ftilde) {
@@ -381,7 +577,8 @@ void op_rhs_base(kfbi_plan* pl, const double* fhat, const double* gB, double* F)
 
 void op_rhs_correct(kfbi_plan* pl, double* F, bool overwrite) {
   if (pl->n_irr == 0) return;
-  RhsCorrArgs A{pl->g, make_stencil(pl->g), pl->n_irr, pl->irr, pl->region, pl->Cg, F, overwrite ? 1 : 0};
+  RhsCorrArgs A{pl->ctl_active, pl->g, make_stencil(pl->g), pl->n_irr, pl->irr, pl->region, pl->Cg, F,
+                overwrite ? 1 : 0};
   hipLaunchKernelGGL(k_rhs_correct, dim3(nb(pl->n_irr)), dim3(KFBI_BLOCK), 0, pl->stream, A);
 }
 
@@ -389,24 +586,161 @@ void op_boundary(kfbi_plan* pl, const double* gB, double* v) {
   hipLaunchKernelGGL(k_boundary, dim3(nb(pl->g.n_nodes)), dim3(KFBI_BLOCK), 0, pl->stream, pl->g, gB, v);
 }
 
-void op_normal_derivatives(kfbi_plan* pl, const double* v, double* dn_in, double* dn_out, double* Apsi) {
-  NdArgs A;
+namespace {
+void launch_interp(kfbi_plan* pl, const double* v, const double* U, const double* psi, double* dn_in,
+                   double* dn_out, double* Apsi) {
+  const int q1 = pl->g.p + 1;
+  InterpArgs A;
+  A.ctl = pl->ctl_active;
+  A.Vb = pl->V;
   A.g = pl->g;
+  A.nbk = pl->g.d == 3 ? q1 * q1 * q1 : q1 * q1;
   A.nC = pl->nC;
-  for (int ax = 0; ax < 3; ++ax) A.lin[ax] = ax + 1;   // graded order: 1, x, y(, z)
+  A.nF = pl->nF;
   A.n_dof = pl->n_dof;
   A.d2s = pl->d2s;
   A.meta = pl->s_meta;
-  A.spos = pl->s_pos;
+  A.IB = pl->IB;
+  A.IW = pl->IW;
+  A.U = U;
   A.snrm = pl->s_nrm;
-  A.U = pl->U;
   A.v = v;
   A.Cg = pl->Cg;
+  A.IE1 = pl->IE1;
+  A.IE2 = pl->IE2;
+  A.GI = pl->GI;
+  A.Cv = pl->Cv;
+  A.GW = pl->GW;
+  A.psi = psi;
   A.region = pl->region;
   A.dn_in = dn_in;
   A.dn_out = dn_out;
   A.Apsi = Apsi;
-  hipLaunchKernelGGL(k_normal_derivative, dim3(nb(pl->n_dof)), dim3(KFBI_BLOCK), 0, pl->stream, A);
+  if (pl->g.d == 3)
+    hipLaunchKernelGGL(k_interp<64>, dim3(nb(pl->n_dof * 64)), dim3(KFBI_BLOCK), 0, pl->stream, A);
+  else if (q1 == 5)
+    hipLaunchKernelGGL(k_interp<32>, dim3(nb(pl->n_dof * 32)), dim3(KFBI_BLOCK), 0, pl->stream, A);
+  else
+    hipLaunchKernelGGL(k_interp<16>, dim3(nb(pl->n_dof * 16)), dim3(KFBI_BLOCK), 0, pl->stream, A);
+}
+}  // namespace
+
+void op_normal_derivatives(kfbi_plan* pl, const double* v, double* dn_in, double* dn_out, double* Apsi) {
+  launch_interp(pl, v, pl->U, nullptr, dn_in, dn_out, Apsi);
+}
+
+template <class T>
+static kfbi_status regrow(T** p, int64_t n) {
+  if (*p) (void)hipFree(*p);
+  *p = nullptr;
+  if (n < 1) n = 1;
+  if (hipMalloc((void**)p, (size_t)n * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    kfbi_set_error("device allocation of %lld bytes failed", (long long)(n * sizeof(T)));
+    return KFBI_E_OOM;
+  }
+  return KFBI_OK;
+}
+
+kfbi_status op_fold(kfbi_plan* pl) {
+  const GridDesc& g = pl->g;
+  const int q1 = g.p + 1;
+  const int nbk = g.d == 3 ? q1 * q1 * q1 : q1 * q1;
+  pl->nF = pl->nN * g.p;
+  pl->maxpairs = g.order == 2 ? 2 * g.d : (g.d == 3 ? 26 : 8);
+  if (pl->n_corr > pl->cap_fold_corr) {
+    int64_t cap = pl->n_corr + pl->n_corr / 4 + 64;
+    pl->cap_fold_corr = 0;
+    KCHK(regrow(&pl->FI, cap * pl->nF));
+    KCHK(regrow(&pl->FW, cap * pl->nF));
+    KCHK(regrow(&pl->Cv, cap));
+    pl->cap_fold_corr = cap;
+  }
+  if (pl->n_dof > pl->cap_fold_dof) {
+    int64_t cap = pl->n_dof + pl->n_dof / 4 + 64;
+    pl->cap_fold_dof = 0;
+    KCHK(regrow(&pl->GI, cap * pl->nF));
+    KCHK(regrow(&pl->GW, cap * pl->nF));
+    KCHK(regrow(&pl->IW, cap * nbk));
+    KCHK(regrow(&pl->IE1, cap * nbk));
+    KCHK(regrow(&pl->IE2, cap * nbk));
+    KCHK(regrow(&pl->IB, cap));
+    pl->cap_fold_dof = cap;
+  }
+  if (pl->n_irr > pl->cap_fold_irr) {
+    int64_t cap = pl->n_irr + pl->n_irr / 4 + 64;
+    pl->cap_fold_irr = 0;
+    KCHK(regrow(&pl->PA, cap * pl->maxpairs));
+    KCHK(regrow(&pl->PE1, cap * pl->maxpairs));
+    KCHK(regrow(&pl->PE2, cap * pl->maxpairs));
+    pl->cap_fold_irr = cap;
+  }
+  int64_t nrows = g.d == 3 ? (int64_t)g.n1 * g.n1 : g.n1;
+  HIPCHK(hipMemsetAsync(pl->EI, 0xff, sizeof(int) * (size_t)g.K * g.n_nodes, pl->stream));
+  HIPCHK(hipMemsetAsync(pl->row_start, 0, sizeof(int) * nrows, pl->stream));
+  HIPCHK(hipMemsetAsync(pl->row_end, 0, sizeof(int) * nrows, pl->stream));
+  if (pl->n_corr > 0)
+    hipLaunchKernelGGL(k_entry_map, dim3(nb(pl->n_corr)), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_corr, g.n_nodes,
+                       pl->ce_k, pl->ce_node, pl->EI);
+  FoldArgs A;
+  A.g = g;
+  A.M = make_mono(pl);
+  A.nP = pl->nP;
+  A.nD = pl->nD;
+  A.nN = pl->nN;
+  A.nC = pl->nC;
+  A.nF = pl->nF;
+  A.maxpairs = pl->maxpairs;
+  A.n_dof = pl->n_dof;
+  A.n_corr = pl->n_corr;
+  A.n_irr = pl->n_irr;
+  A.d2s = pl->d2s;
+  A.ck = pl->ce_k;
+  A.cnode = pl->ce_node;
+  A.cown = pl->ce_owner;
+  A.stN = pl->stN;
+  A.ext_idx = pl->ext_idx;
+  A.irr = pl->irr;
+  A.EI = pl->EI;
+  A.meta = pl->s_meta;
+  A.region = pl->region;
+  A.spos = pl->s_pos;
+  A.snrm = pl->s_nrm;
+  A.MinvT = pl->MinvT;
+  A.ext_w = pl->ext_w;
+  A.FI = pl->FI;
+  A.GI = pl->GI;
+  A.IB = pl->IB;
+  A.IE1 = pl->IE1;
+  A.IE2 = pl->IE2;
+  A.PE1 = pl->PE1;
+  A.PE2 = pl->PE2;
+  A.FW = pl->FW;
+  A.GW = pl->GW;
+  A.IW = pl->IW;
+  A.PA = pl->PA;
+  A.S = make_stencil(g);
+  if (pl->n_corr > 0)
+    hipLaunchKernelGGL(k_fold_corr, dim3(nb(pl->n_corr)), dim3(KFBI_BLOCK), 0, pl->stream, A);
+  hipLaunchKernelGGL(k_fold_dof, dim3(nb(pl->n_dof * nbk)), dim3(KFBI_BLOCK), 0, pl->stream, A);
+  if (pl->n_irr > 0) {
+    hipLaunchKernelGGL(k_fold_pairs, dim3(nb(pl->n_irr)), dim3(KFBI_BLOCK), 0, pl->stream, A);
+    hipLaunchKernelGGL(k_irr_rows, dim3(nb(pl->n_irr)), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_irr, g.n1, pl->irr,
+                       pl->row_start, pl->row_end);
+  }
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+// the BIE operator (S2-S5) with the folded maps: the corrected right-hand
+// side is formed inside the first box-solve pass, the correction values
+// inside the interpolation
+void op_matvec(kfbi_plan* pl, const double* psi, double* Apsi) {
+  if (pl->n_corr > 0)
+    hipLaunchKernelGGL(k_centry<16>, dim3(nb(pl->n_corr * 16)), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_corr,
+                       pl->nF, pl->FI, pl->FW, psi, pl->Cv, pl->ctl_active, pl->V, pl->n_dof);
+  dst_solve_corrections(pl, psi, pl->vbuf);
+  launch_interp(pl, pl->vbuf, nullptr, psi, nullptr, nullptr, Apsi);
 }
 
 void op_bie_rhs(kfbi_plan* pl, const double* g2, const double* dn_in, const double* dn_out, double* b) {
