@@ -17,6 +17,8 @@ namespace {
 
 thread_local char g_err[512] = "no error";
 
+void destroy_graphs(kfbi_plan* pl);
+
 template <class T>
 kfbi_status dalloc(T** p, int64_t n) {
   *p = nullptr;
@@ -147,6 +149,7 @@ void free_plan(kfbi_plan* pl) {
   dfree(pl->PE1);
   dfree(pl->PE2);
   dfree(pl->EI);
+  dfree(pl->flags8);
   dfree(pl->row_start);
   dfree(pl->row_end);
   if (pl->prof_ev) {
@@ -154,10 +157,7 @@ void free_plan(kfbi_plan* pl) {
     delete pl->prof_ev;
     pl->prof_ev = nullptr;
   }
-  if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
-  if (pl->graph) (void)hipGraphDestroy(pl->graph);
-  pl->graph_exec = nullptr;
-  pl->graph = nullptr;
+  destroy_graphs(pl);
   if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
   if (pl->ev_in) (void)hipEventDestroy(pl->ev_in);
   if (pl->ev_out) (void)hipEventDestroy(pl->ev_out);
@@ -205,6 +205,7 @@ kfbi_status alloc_fixed(kfbi_plan* pl) {
   KCHK(dalloc(&pl->T2, n));
   KCHK(dalloc(&pl->vbuf, n));
   KCHK(dalloc(&pl->vsbuf, n));
+  KCHK(dalloc(&pl->flags8, pl->n_seg * g.K > n ? pl->n_seg * g.K : n));
   KCHK(dalloc(&pl->EI, (int64_t)g.K * n));
   int64_t nrows = g.d == 3 ? (int64_t)g.n1 * g.n1 : g.n1;
   KCHK(dalloc(&pl->row_start, nrows));
@@ -291,7 +292,17 @@ void simple_solve_impl(kfbi_plan* pl, const double* a, const double* b, const do
 
 void matvec_impl(kfbi_plan* pl, const double* psi, double* Apsi) { op_matvec(pl, psi, Apsi); }
 
-// Graph of one GMRES iteration (matvec of V[j] into V[j+1], Arnoldi step),
+void destroy_graphs(kfbi_plan* pl) {
+  if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
+  if (pl->graph) (void)hipGraphDestroy(pl->graph);
+  if (pl->graph4_exec) (void)hipGraphExecDestroy(pl->graph4_exec);
+  if (pl->graph4) (void)hipGraphDestroy(pl->graph4);
+  pl->graph_exec = pl->graph4_exec = nullptr;
+  pl->graph = pl->graph4 = nullptr;
+}
+
+// Graphs of one and of four GMRES iterations (matvec of V[j] into V[j+1],
+// Arnoldi step),
 // captured on the private stream; every kernel reads j and the stop flag
 // from the device control word.  Rebuilt when buffers or sizes change.
 kfbi_status ensure_graph(kfbi_plan* pl) {
@@ -305,19 +316,34 @@ kfbi_status ensure_graph(kfbi_plan* pl) {
                       (uint64_t)(uintptr_t)pl->ext_idx, (uint64_t)(uintptr_t)pl->irr,
                       (uint64_t)(uintptr_t)pl->ce_node, (uint64_t)pl->gm_cap, (uint64_t)(uintptr_t)pl->d2s,
                       (uint64_t)(uintptr_t)pl->PA ^ (uint64_t)(uintptr_t)pl->GI};
-  if (pl->graph_exec && memcmp(key, pl->graph_key, sizeof(key)) == 0) return KFBI_OK;
-  if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
-  if (pl->graph) (void)hipGraphDestroy(pl->graph);
-  pl->graph_exec = nullptr;
-  pl->graph = nullptr;
-  HIPCHK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
-  pl->ctl_active = pl->ctl;
-  op_matvec(pl, nullptr, nullptr);
-  gm_arnoldi(pl);
-  pl->ctl_active = nullptr;
-  hipError_t e = hipStreamEndCapture(pl->stream, &pl->graph);
-  if (e != hipSuccess) return kfbi_hip_status(e, "hipStreamEndCapture");
-  HIPCHK(hipGraphInstantiate(&pl->graph_exec, pl->graph, nullptr, nullptr, 0));
+  if (pl->graph_exec && pl->graph4_exec && memcmp(key, pl->graph_key, sizeof(key)) == 0) return KFBI_OK;
+  destroy_graphs(pl);
+  for (int v = 0; v < 2; ++v) {
+    const int iters = v == 0 ? 1 : 4;
+    HIPCHK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
+    pl->ctl_active = pl->ctl;
+    for (int it = 0; it < iters; ++it) {
+      op_matvec(pl, nullptr, nullptr);
+      gm_arnoldi(pl);
+    }
+    pl->ctl_active = nullptr;
+    hipGraph_t gr = nullptr;
+    hipError_t e = hipStreamEndCapture(pl->stream, &gr);
+    if (e != hipSuccess) return kfbi_hip_status(e, "hipStreamEndCapture");
+    hipGraphExec_t ex = nullptr;
+    e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+    if (e != hipSuccess) {
+      (void)hipGraphDestroy(gr);
+      return kfbi_hip_status(e, "hipGraphInstantiate");
+    }
+    if (v == 0) {
+      pl->graph = gr;
+      pl->graph_exec = ex;
+    } else {
+      pl->graph4 = gr;
+      pl->graph4_exec = ex;
+    }
+  }
   memcpy(pl->graph_key, key, sizeof(key));
   return KFBI_OK;
 }
@@ -587,7 +613,8 @@ kfbi_status solve_body(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* op
   int launched = 0, batch = 4;
   while (!pl->h_ctl[1] && launched < m) {
     int B = batch < m - launched ? batch : m - launched;
-    for (int b = 0; b < B; ++b) HIPCHK(hipGraphLaunch(pl->graph_exec, st));
+    for (int b = 0; b + 4 <= B; b += 4) HIPCHK(hipGraphLaunch(pl->graph4_exec, st));
+    for (int b = 0; b < B % 4; ++b) HIPCHK(hipGraphLaunch(pl->graph_exec, st));
     launched += B;
     HIPCHK(hipMemcpyAsync(pl->h_ctl, pl->ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(pl->h_dpinned, pl->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));

@@ -45,6 +45,7 @@ struct DstArgs {
   int mode;        // 0: DST; 1: DST, divide by lambda and scale, DST
   int TL;          // lines per tile (even)
   int M, logM;     // FFT length 2N
+  int ps;          // LDS pad shift (see padi)
   int tiles_u;     // tiles along the tile axis
   const double* in;
   double* out;
@@ -52,6 +53,12 @@ struct DstArgs {
   const double* eig1;  // s_k, k = 0..N
   double scale;        // (2/N)^d
 };
+
+// LDS layout of a sequence: element i at i + (i >> ps), one pad slot per
+// 2^ps 16-byte elements (ps = 3 when the padded tile fits, else ps = 31, no
+// padding), so the strided writes of the early Stockham stages spread over
+// the banks
+__device__ __forceinline__ int padi(int i, int ps) { return i + (i >> ps); }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
@@ -63,7 +70,8 @@ __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
 // k = j mod Ns, and writes y[(j - k) R + k + r Ns].  Returns the buffer that
 // holds the result (a or b).
 __device__ double2* fft_stockham(double2* a, double2* b, const double2* __restrict__ tw, int nf, int M,
-                                 int logM) {
+                                 int logM, int ps) {
+  const int Mp = M + (M >> ps);    // padded sequence stride
   int Ns = 1, lNs = 0;
   while (Ns < M) {
     if (4 * Ns <= M) {
@@ -71,9 +79,9 @@ __device__ double2* fft_stockham(double2* a, double2* b, const double2* __restri
       const int tsh = logM - 2 - lNs;             // twiddle step M / (4 Ns)
       for (int t = threadIdx.x; t < (nf << lQ); t += blockDim.x) {
         const int f = t >> lQ, j = t & (Q - 1), k = j & (Ns - 1);
-        const double2* x = a + (f << logM);
-        double2* y = b + (f << logM);
-        double2 v0 = x[j], v1 = x[j + Q], v2 = x[j + 2 * Q], v3 = x[j + 3 * Q];
+        const double2* x = a + f * Mp;
+        double2* y = b + f * Mp;
+        double2 v0 = x[padi(j, ps)], v1 = x[padi(j + Q, ps)], v2 = x[padi(j + 2 * Q, ps)], v3 = x[padi(j + 3 * Q, ps)];
         const int st = k << tsh;
         v1 = cmul(v1, tw[st]);
         v2 = cmul(v2, tw[2 * st]);
@@ -81,10 +89,10 @@ __device__ double2* fft_stockham(double2* a, double2* b, const double2* __restri
         double2 t0 = make_double2(v0.x + v2.x, v0.y + v2.y), t1 = make_double2(v0.x - v2.x, v0.y - v2.y);
         double2 t2 = make_double2(v1.x + v3.x, v1.y + v3.y), t3 = make_double2(v1.x - v3.x, v1.y - v3.y);
         const int d = ((j - k) << 2) + k;
-        y[d] = make_double2(t0.x + t2.x, t0.y + t2.y);
-        y[d + Ns] = make_double2(t1.x + t3.y, t1.y - t3.x);
-        y[d + 2 * Ns] = make_double2(t0.x - t2.x, t0.y - t2.y);
-        y[d + 3 * Ns] = make_double2(t1.x - t3.y, t1.y + t3.x);
+        y[padi(d, ps)] = make_double2(t0.x + t2.x, t0.y + t2.y);
+        y[padi(d + Ns, ps)] = make_double2(t1.x + t3.y, t1.y - t3.x);
+        y[padi(d + 2 * Ns, ps)] = make_double2(t0.x - t2.x, t0.y - t2.y);
+        y[padi(d + 3 * Ns, ps)] = make_double2(t1.x - t3.y, t1.y + t3.x);
       }
       Ns <<= 2;
       lNs += 2;
@@ -93,12 +101,12 @@ __device__ double2* fft_stockham(double2* a, double2* b, const double2* __restri
       const int tsh = logM - 1 - lNs;
       for (int t = threadIdx.x; t < (nf << lQ); t += blockDim.x) {
         const int f = t >> lQ, j = t & (Q - 1), k = j & (Ns - 1);
-        const double2* x = a + (f << logM);
-        double2* y = b + (f << logM);
-        double2 v0 = x[j], v1 = cmul(x[j + Q], tw[k << tsh]);
+        const double2* x = a + f * Mp;
+        double2* y = b + f * Mp;
+        double2 v0 = x[padi(j, ps)], v1 = cmul(x[padi(j + Q, ps)], tw[k << tsh]);
         const int d = ((j - k) << 1) + k;
-        y[d] = make_double2(v0.x + v1.x, v0.y + v1.y);
-        y[d + Ns] = make_double2(v0.x - v1.x, v0.y - v1.y);
+        y[padi(d, ps)] = make_double2(v0.x + v1.x, v0.y + v1.y);
+        y[padi(d + Ns, ps)] = make_double2(v0.x - v1.x, v0.y - v1.y);
       }
       Ns <<= 1;
       lNs += 1;
@@ -150,8 +158,17 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
   extern __shared__ double2 lds[];
   const GridDesc& g = a.g;
   const int N = g.N, M = a.M, TL = a.TL, nf = TL / 2;
-  double2* A = lds;                                 // [nf][M]
-  double2* B = lds + nf * M;                        // [nf][M]
+  const int ps = a.ps;
+  const int Mp = M + (M >> ps);                     // padded sequence stride
+  double2* A = lds;                                 // [nf][Mp]
+  double2* B = lds + nf * Mp;                       // [nf][Mp]
+  // twiddle table in LDS when it fits next to the two buffers
+  const double2* tw = a.tw;
+  if (2 * nf * Mp + M <= LDS_COMPLEX) {
+    double2* tl = lds + 2 * nf * Mp;
+    for (int m = threadIdx.x; m < M; m += blockDim.x) tl[m] = a.tw[m];
+    tw = tl;
+  }
   const int tile = blockIdx.x % a.tiles_u;
   const int w = blockIdx.x / a.tiles_u + 1;         // remaining interior coordinate (3D)
   const int u0 = 1 + tile * TL;                     // first tile coordinate
@@ -161,7 +178,7 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
     // F = -sum over cut neighbours Q of A_PQ (C^(reg P) - C^(reg Q))(x_Q) at
     // the irregular nodes of the tile's rows (correction values of the
     // current density, computed just before), zero elsewhere
-    for (int i = threadIdx.x; i < nf * M; i += blockDim.x) A[i] = make_double2(0.0, 0.0);
+    for (int i = threadIdx.x; i < nf * Mp; i += blockDim.x) A[i] = make_double2(0.0, 0.0);
     __syncthreads();
     const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
     for (int l = wave; l < TL; l += nw) {
@@ -178,65 +195,81 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
           F -= cf * (c1 - c2);
         }
         const int j = a.irr[t] % g.n1;
-        double2* z = A + (l >> 1) * M;
+        double2* z = A + (l >> 1) * Mp;
         if (l & 1) {
-          z[j].y = F;
-          z[M - j].y = -F;
+          z[padi(j, ps)].y = F;
+          z[padi(M - j, ps)].y = -F;
         } else {
-          z[j].x = F;
-          z[M - j].x = -F;
+          z[padi(j, ps)].x = F;
+          z[padi(M - j, ps)].x = -F;
         }
       }
     }
     __syncthreads();
   } else {
   for (int f = threadIdx.x; f < nf; f += blockDim.x) {
-    A[f * M] = make_double2(0.0, 0.0);
-    A[f * M + N] = make_double2(0.0, 0.0);
+    A[f * Mp] = make_double2(0.0, 0.0);
+    A[f * Mp + padi(N, ps)] = make_double2(0.0, 0.0);
   }
-  for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
-    int l, j;
-    if (a.ax == 0) {
-      j = idx % nl + 1;
-      l = idx / nl;
-    } else {
-      l = idx % TL;
-      j = idx / TL + 1;
+  // all loads of a chunk are issued before the LDS stores
+  constexpr int CH = 8;
+  for (int base = threadIdx.x; base < total; base += CH * (int)blockDim.x) {
+    double xv[CH];
+    int lv[CH], jv[CH];
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int idx = base + q * (int)blockDim.x;
+      int l = 0, j = 1;
+      if (a.ax == 0) {
+        j = idx % nl + 1;
+        l = idx / nl;
+      } else {
+        l = idx % TL;
+        j = idx / TL + 1;
+      }
+      const int u = u0 + l;
+      lv[q] = idx < total ? l : -1;
+      jv[q] = j;
+      xv[q] = (idx < total && u <= nl) ? a.in[elem_addr(a, u, w, j)] : 0.0;
     }
-    int u = u0 + l;
-    double x = u <= nl ? a.in[elem_addr(a, u, w, j)] : 0.0;
-    double2* z = A + (l >> 1) * M;
-    if (l & 1) {
-      z[j].y = x;
-      z[M - j].y = -x;
-    } else {
-      z[j].x = x;
-      z[M - j].x = -x;
+#pragma unroll
+    for (int q = 0; q < CH; ++q) {
+      const int l = lv[q], j = jv[q];
+      if (l < 0) continue;
+      double2* z = A + (l >> 1) * Mp;
+      if (l & 1) {
+        z[padi(j, ps)].y = xv[q];
+        z[padi(M - j, ps)].y = -xv[q];
+      } else {
+        z[padi(j, ps)].x = xv[q];
+        z[padi(M - j, ps)].x = -xv[q];
+      }
     }
   }
   __syncthreads();
   }
-  double2* R = fft_stockham(A, B, a.tw, nf, M, a.logM);
+  __syncthreads();
+  double2* R = fft_stockham(A, B, tw, nf, M, a.logM, ps);
   if (a.mode == 1) {
     // S_A(k) = -Im Z_k / 2 (even line), S_B(k) = Re Z_k / 2 (odd line); divide
     // by lambda, scale, and form the odd sequences of the inverse transform
     double2* S = R == A ? B : A;
     for (int f = threadIdx.x; f < nf; f += blockDim.x) {
-      S[f * M] = make_double2(0.0, 0.0);
-      S[f * M + N] = make_double2(0.0, 0.0);
+      S[f * Mp] = make_double2(0.0, 0.0);
+      S[f * Mp + padi(N, ps)] = make_double2(0.0, 0.0);
     }
     for (int idx = threadIdx.x; idx < nf * nl; idx += blockDim.x) {
       int f = idx / nl, k = idx % nl + 1;
-      double2 Z = R[f * M + k];
+      double2 Z = R[f * Mp + padi(k, ps)];
       int uA = u0 + 2 * f, uB = uA + 1;
       double lamA = eigenvalue(a, k, uA <= nl ? uA : 1, w);
       double lamB = eigenvalue(a, k, uB <= nl ? uB : 1, w);
       double2 c = make_double2(a.scale * (-0.5 * Z.y) / lamA, a.scale * (0.5 * Z.x) / lamB);
-      S[f * M + k] = c;
-      S[f * M + M - k] = make_double2(-c.x, -c.y);
+      S[f * Mp + padi(k, ps)] = c;
+      S[f * Mp + padi(M - k, ps)] = make_double2(-c.x, -c.y);
     }
     __syncthreads();
-    R = fft_stockham(S, R, a.tw, nf, M, a.logM);
+    R = fft_stockham(S, R, tw, nf, M, a.logM, ps);
   }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     int l, k;
@@ -249,15 +282,20 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
     }
     int u = u0 + l;
     if (u > nl) continue;
-    double2 Z = R[(l >> 1) * M + k];
+    double2 Z = R[(l >> 1) * Mp + padi(k, ps)];
     a.out[elem_addr(a, u, w, k)] = (l & 1) ? 0.5 * Z.x : -0.5 * Z.y;
   }
 }
 
 // lines per tile: two ping-pong buffers of (TL/2) sequences of M complex
-// values within LDS_COMPLEX slots (64 KiB)
+// values (plus the twiddle table when it fits) within LDS_COMPLEX slots
+// LDS pad shift for FFT length M: padded when one padded pair of buffers fits
+int pad_shift(int M) { return 2 * (M + M / 8) <= LDS_COMPLEX ? 3 : 31; }
+
 int tile_lines(int M) {
-  int nf = LDS_COMPLEX / (2 * M);
+  const int Mp = M + (pad_shift(M) == 3 ? M / 8 : 0);
+  int nf = (LDS_COMPLEX - M) / (2 * Mp);
+  if (nf < 1) nf = LDS_COMPLEX / (2 * Mp);
   if (nf > 16) nf = 16;
   if (nf < 1) nf = 1;
   return 2 * nf;
@@ -302,7 +340,10 @@ void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out,
   a.scale = 1.0;
   for (int t = 0; t < pl->g.d; ++t) a.scale *= 2.0 / pl->g.N;
   unsigned blocks = (unsigned)a.tiles_u * (pl->g.d == 3 ? nl : 1);
-  size_t lds = sizeof(double2) * 2 * (size_t)(a.TL / 2) * a.M;
+  size_t nfs = (size_t)(a.TL / 2);
+  a.ps = pad_shift(a.M);
+  size_t Mp = (size_t)a.M + (a.ps == 3 ? a.M / 8 : 0);
+  size_t lds = sizeof(double2) * (2 * nfs * Mp + a.M <= (size_t)LDS_COMPLEX ? 2 * nfs * Mp + a.M : 2 * nfs * Mp);
   hipLaunchKernelGGL(k_dst, dim3(blocks), dim3(KFBI_BLOCK), lds, pl->stream, a);
 }
 
@@ -322,7 +363,7 @@ kfbi_status dst_init(kfbi_plan* pl) {
   }
   HIPCHK(hipMemcpy(pl->tw, tw.data(), sizeof(double) * 2 * M, hipMemcpyHostToDevice));
   HIPCHK(hipMemcpy(pl->eig1, eig.data(), sizeof(double) * (N + 1), hipMemcpyHostToDevice));
-  int lds = (int)(sizeof(double2) * 2 * (size_t)(tile_lines(M) / 2) * M);
+  int lds = (int)(sizeof(double2) * 2 * (size_t)(tile_lines(M) / 2) * (M + (pad_shift(M) == 3 ? M / 8 : 0)));
   if (lds > 65536) {
     kfbi_set_error("box solver LDS footprint too large (N = %d)", N);
     return KFBI_E_INVALID;

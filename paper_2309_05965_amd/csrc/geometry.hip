@@ -166,12 +166,13 @@ __device__ void ls_grad(const LSet& L, int k, double x, double y, double z, doub
 
 __device__ __forceinline__ double node_x(const GridDesc& g, int i) { return g.lo + (double)i * g.h; }
 
+// node indices fit 32 bits ((N+1)^3 < 2^31 for N <= 1024)
 __device__ __forceinline__ void unravel(const GridDesc& g, int64_t idx, int c[3]) {
-  c[0] = (int)(idx % g.n1);
-  int64_t r = idx / g.n1;
-  c[1] = (int)(r % g.n1);
-  c[2] = (int)(r / g.n1);
-  if (g.d == 2) c[2] = 0;
+  const unsigned u = (unsigned)idx, n1 = (unsigned)g.n1;
+  const unsigned r = u / n1;
+  c[0] = (int)(u - r * n1);
+  c[1] = (int)(r % n1);
+  c[2] = g.d == 2 ? 0 : (int)(r / n1);
 }
 
 __device__ __forceinline__ int64_t ravel(const GridDesc& g, const int c[3]) {
@@ -206,6 +207,31 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_count(int64_t n, Pred pred, int*
   for (int j = 0; j < CMP_IT; ++j) {
     int64_t i = base + (int64_t)j * KFBI_BLOCK + threadIdx.x;
     if (i < n && pred(i)) ++c;
+  }
+  __shared__ int red[KFBI_BLOCK / 64];
+  c = wave_sum(c);
+  if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = c;
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    int s = 0;
+    for (int w = 0; w < KFBI_BLOCK / 64; ++w) s += red[w];
+    blk[blockIdx.x] = s;
+  }
+}
+
+// as k_count, also storing the predicate per item (later compaction passes
+// read the flag instead of re-evaluating the predicate)
+template <class Pred>
+__global__ void __launch_bounds__(KFBI_BLOCK) k_count_flags(int64_t n, Pred pred, int* blk, uint8_t* flags) {
+  int64_t base = (int64_t)blockIdx.x * CMP_CH;
+  int c = 0;
+  for (int j = 0; j < CMP_IT; ++j) {
+    int64_t i = base + (int64_t)j * KFBI_BLOCK + threadIdx.x;
+    if (i < n) {
+      bool f = pred(i);
+      flags[i] = f ? 1 : 0;
+      c += f ? 1 : 0;
+    }
   }
   __shared__ int red[KFBI_BLOCK / 64];
   c = wave_sum(c);
@@ -360,16 +386,20 @@ struct SegInfo {
 
 __device__ __forceinline__ SegInfo seg_info(const GridDesc& g, int64_t seg) {
   SegInfo o;
-  int64_t L = g.d == 2 ? g.n1 : (int64_t)g.n1 * g.n1;
-  o.s = (int)(seg % g.N);
-  int64_t rest = seg / g.N;
-  o.lid = rest % L;
-  o.r = (int)(rest / L);
+  const unsigned L = g.d == 2 ? (unsigned)g.n1 : (unsigned)g.n1 * (unsigned)g.n1;
+  const int logN = __ffs(g.N) - 1;                 // N is a power of two
+  o.s = (int)(seg & (g.N - 1));
+  const unsigned rest = (unsigned)(seg >> logN);   // < d (N+1)^(d-1)
+  const unsigned r = rest / L;
+  o.r = (int)r;
+  const unsigned lid = rest - r * L;
+  o.lid = lid;
   int T[2];
   trans_axes(g.d, o.r, T);
   int c[3] = {0, 0, 0};
-  c[T[0]] = (int)(o.lid % g.n1);
-  if (g.d == 3) c[T[1]] = (int)(o.lid / g.n1);
+  const unsigned l1 = lid / (unsigned)g.n1;
+  c[T[0]] = (int)(lid - l1 * (unsigned)g.n1);
+  if (g.d == 3) c[T[1]] = (int)l1;
   c[o.r] = o.s;
   o.a = ravel(g, c);
   c[o.r] = o.s + 1;
@@ -377,12 +407,22 @@ __device__ __forceinline__ SegInfo seg_info(const GridDesc& g, int64_t seg) {
   return o;
 }
 
+__device__ __forceinline__ int64_t item_seg(const GridDesc& g, int64_t item, int* k) {
+  if (g.K == 1) {
+    *k = 1;
+    return item;
+  }
+  int64_t seg = item / g.K;
+  *k = (int)(item - seg * g.K) + 1;
+  return seg;
+}
+
 struct CandPred {
   GridDesc g;
   const int8_t* region;
   __device__ bool operator()(int64_t item) const {
-    int64_t seg = item / g.K;
-    int k = (int)(item % g.K) + 1;
+    int k;
+    int64_t seg = item_seg(g, item, &k);
     SegInfo si = seg_info(g, seg);
     return (region[si.a] == k) != (region[si.b] == k);
   }
@@ -393,8 +433,8 @@ struct CandEmit {
   const int8_t* region;
   int *r, *lid, *segs, *k, *ina;
   __device__ void operator()(int64_t item, int pos) const {
-    int64_t seg = item / g.K;
-    int kk = (int)(item % g.K) + 1;
+    int kk;
+    int64_t seg = item_seg(g, item, &kk);
     SegInfo si = seg_info(g, seg);
     r[pos] = si.r;
     lid[pos] = (int)si.lid;
@@ -413,9 +453,15 @@ struct BisectArgs {
   int* acc;
 };
 
-__global__ void k_bisect(BisectArgs a) {
-  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (i >= a.n) return;
+// Bisection of BISECT_STEPS halvings, three halvings per round: the 7
+// midpoints of the next three levels are evaluated by 8 lanes at once and
+// the sequential decisions are replayed; every midpoint is 0.5*(lo+hi) of
+// the same endpoints as in plain bisection, so the root is identical.
+__global__ void __launch_bounds__(KFBI_BLOCK) k_bisect(BisectArgs a) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t i = t >> 3;
+  int lane = (int)(t & 7);
+  if (i >= a.n) return;               // groups of 8 leave together
   const GridDesc& g = a.g;
   int r = a.r[i], k = a.k[i] - 1;
   int T[2];
@@ -427,15 +473,34 @@ __global__ void k_bisect(BisectArgs a) {
   double xr0 = g.lo + (double)a.seg[i] * g.h;
   bool ina = a.ina[i] != 0;
   double tlo = 0.0, thi = 1.0;
-  for (int it = 0; it < BISECT_STEPS; ++it) {
-    double mid = 0.5 * (tlo + thi);
-    X[r] = xr0 + mid * g.h;
-    bool inside = ls_value(a.L, k, X[0], X[1], X[2]) < 0.0;
-    if (inside == ina)
-      tlo = mid;
-    else
-      thi = mid;
+  int left = BISECT_STEPS;
+  while (left > 0) {
+    const int depth = left >= 3 ? 3 : left;
+    double p0 = 0.5 * (tlo + thi);
+    double pL = 0.5 * (tlo + p0), pR = 0.5 * (p0 + thi);
+    double pts[7] = {p0, pL, pR, 0.5 * (tlo + pL), 0.5 * (pL + p0), 0.5 * (p0 + pR), 0.5 * (pR + thi)};
+    bool mine = false;
+    if (lane < 7 && (depth == 3 || lane < (depth == 2 ? 3 : 1))) {
+      double pt = pts[lane];
+      X[r] = xr0 + pt * g.h;
+      mine = ls_value(a.L, k, X[0], X[1], X[2]) < 0.0;
+    }
+    unsigned long long bal = __ballot(mine);
+    const unsigned bits = (unsigned)(bal >> ((threadIdx.x & 63) & ~7)) & 0xffu;
+    int node = 0;   // heap index of the midpoint used at this level
+    for (int lev = 0; lev < depth; ++lev) {
+      double mid = pts[node];
+      bool inside = (bits >> node) & 1u;
+      bool right = inside == ina;     // same side as the start: root is to the right
+      if (right)
+        tlo = mid;
+      else
+        thi = mid;
+      node = 2 * node + (right ? 2 : 1);
+    }
+    left -= depth;
   }
+  if (lane != 0) return;
   double tr = 0.5 * (tlo + thi);
   X[r] = xr0 + tr * g.h;
   double G[3];
@@ -536,32 +601,28 @@ struct SurfView {
   }
 };
 
-// one shifted window; false if any point is invalid (or, with need_prim,
-// not primary)
-__device__ bool pick_window(const SurfView& S, int i, int r, const int a0[2], const int (*offs)[2],
-                            int no, const int s[2], bool need_prim, int* out) {
+// the point of one window offset (o + s): the surface point of the centre's
+// interface on the family-r line a0 + o + s nearest to the centre along e_r,
+// or -1 if there is none, it fails the gate, or (need_prim) it is not primary
+__device__ int pick_one(const SurfView& S, int i, int r, const int a0[2], const int o[2], const int s[2],
+                        bool need_prim) {
   const GridDesc& g = S.g;
   int T[2];
   trans_axes(g.d, r, T);
-  int ki = S.iface(i);
-  double xr = S.x(i, r);
-  for (int m = 0; m < no; ++m) {
-    int c[3] = {0, 0, 0};
-    int l1 = 0;
-    for (int j = 0; j < g.d - 1; ++j) {
-      int v = a0[j] + offs[m][j] + s[j];
-      if (v < 0 || v > g.N) return false;
-      c[T[j]] = v;
-      int o = offs[m][j] + s[j];
-      l1 += o < 0 ? -o : o;
-    }
-    double bd;
-    int bj = S.nearest(r, line_id(g, r, c), ki, xr, false, &bd);
-    if (bj < 0 || !(bd <= 2.0 * g.h * ((double)l1 + 1.0))) return false;
-    if (need_prim && !S.prim(bj)) return false;
-    out[m] = bj;
+  int c[3] = {0, 0, 0};
+  int l1 = 0;
+  for (int j = 0; j < g.d - 1; ++j) {
+    int v = a0[j] + o[j] + s[j];
+    if (v < 0 || v > g.N) return -1;
+    c[T[j]] = v;
+    int oo = o[j] + s[j];
+    l1 += oo < 0 ? -oo : oo;
   }
-  return true;
+  double bd;
+  int bj = S.nearest(r, line_id(g, r, c), S.iface(i), S.x(i, r), false, &bd);
+  if (bj < 0 || !(bd <= 2.0 * g.h * ((double)l1 + 1.0))) return -1;
+  if (need_prim && !S.prim(bj)) return -1;
+  return bj;
 }
 
 struct StencilArgs {
@@ -574,8 +635,21 @@ struct StencilArgs {
   int* flags;
 };
 
-__global__ void k_stencils(StencilArgs a) {
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int STG = 16;   // lanes per centre (>= the largest lattice, 15)
+
+__device__ __forceinline__ bool group_all(bool v) {
+  int x = v ? 1 : 0;
+  for (int off = STG / 2; off > 0; off >>= 1) x &= __shfl_xor(x, off, STG);
+  return x != 0;
+}
+
+// Collocation stencils, one group of STG lanes per centre: every window
+// shift is tested with one lane per lattice offset, the first shift whose
+// points are all valid wins (same order as a sequential search).
+__global__ void __launch_bounds__(KFBI_BLOCK) k_stencils(StencilArgs a) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t c = t / STG;
+  int lane = (int)(t % STG);
   if (c >= a.n_dof) return;
   const SurfView& S = a.S;
   const GridDesc& g = S.g;
@@ -585,23 +659,33 @@ __global__ void k_stencils(StencilArgs a) {
   trans_axes(g.d, r, T);
   int a0[2] = {0, 0};
   for (int j = 0; j < g.d - 1; ++j) a0[j] = (int)floor((S.x(i, T[j]) - g.lo) / g.h + 0.5);
-  int outD[KFBI_MAXD], outN[KFBI_MAXN];
+  int pD = -1, pN = -1;
   bool okD = false, okN = false;
-  for (int si = 0; si < a.lat.nSD && !okD; ++si)
-    okD = pick_window(S, i, r, a0, a.lat.offD, a.lat.nD, a.lat.shD[si], false, outD);
+  for (int si = 0; si < a.lat.nSD && !okD; ++si) {
+    int my = lane < a.lat.nD ? pick_one(S, i, r, a0, a.lat.offD[lane], a.lat.shD[si], false) : 0;
+    if (group_all(my >= 0)) {
+      okD = true;
+      pD = my;
+    }
+  }
   for (int pass = 0; pass < 2 && !okN; ++pass)
-    for (int si = 0; si < a.lat.nSN && !okN; ++si)
-      okN = pick_window(S, i, r, a0, a.lat.offN, a.lat.nN, a.lat.shN[si], pass == 0, outN);
+    for (int si = 0; si < a.lat.nSN && !okN; ++si) {
+      int my = lane < a.lat.nN ? pick_one(S, i, r, a0, a.lat.offN[lane], a.lat.shN[si], pass == 0) : 0;
+      if (group_all(my >= 0)) {
+        okN = true;
+        pN = my;
+      }
+    }
   if (!okD || !okN) {
-    atomicOr(a.flags, FLAG_UNRESOLVED_STENCIL);
-    for (int m = 0; m < a.lat.nD; ++m) a.stD[c * a.lat.nD + m] = i;
-    for (int m = 0; m < a.lat.nN; ++m) a.stN[c * a.lat.nN + m] = i;
+    if (lane == 0) atomicOr(a.flags, FLAG_UNRESOLVED_STENCIL);
+    if (lane < a.lat.nD) a.stD[c * a.lat.nD + lane] = i;
+    if (lane < a.lat.nN) a.stN[c * a.lat.nN + lane] = i;
     return;
   }
-  for (int m = 0; m < a.lat.nD; ++m) a.stD[c * a.lat.nD + m] = outD[m];
-  for (int m = 0; m < a.lat.nN; ++m) {
-    a.stN[c * a.lat.nN + m] = outN[m];
-    a.s_need[outN[m]] = 1;
+  if (lane < a.lat.nD) a.stD[c * a.lat.nD + lane] = pD;
+  if (lane < a.lat.nN) {
+    a.stN[c * a.lat.nN + lane] = pN;
+    a.s_need[pN] = 1;
   }
 }
 
@@ -641,24 +725,37 @@ __device__ int ext_point(const SurfView& S, int q, int F, const int coords[3], i
   return bj;
 }
 
-__global__ void k_extension(ExtArgs a) {
-  int64_t q = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int EXG = 8;    // lanes per surface point
+
+// Density extension, one group of EXG lanes per surface point: lanes 0..4
+// build the candidates (i) of the five shifts, lanes 0..7 test the eight
+// own-family offsets of (ii); lane 0 then compares the candidates in the
+// fixed order (i) shifts 0, 1, -1, 2, -2, then (ii) per transverse axis,
+// and keeps the first with the smallest sum |w|.
+__global__ void __launch_bounds__(KFBI_BLOCK) k_extension(ExtArgs a) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t q = t / EXG;
+  int lane = (int)(t % EXG);
   if (q >= a.n_surf) return;
   const SurfView& S = a.S;
   const GridDesc& g = S.g;
   const int p = g.p;
   int* oi = a.idx + q * p;
   double* ow = a.w + q * p;
-  for (int j = 0; j < p; ++j) {
-    oi[j] = -1;
-    ow[j] = 0.0;
-  }
   if (S.prim((int)q)) {
-    oi[0] = a.s2d[q];
-    ow[0] = 1.0;
+    if (lane < p) {
+      oi[lane] = lane == 0 ? a.s2d[q] : -1;
+      ow[lane] = lane == 0 ? 1.0 : 0.0;
+    }
     return;
   }
-  if (!a.s_need[q]) return;
+  if (!a.s_need[q]) {
+    if (lane < p) {
+      oi[lane] = -1;
+      ow[lane] = 0.0;
+    }
+    return;
+  }
   int r = S.fam((int)q);
   int rp = 0;
   double best = fabs(S.nrm[q * g.d]);
@@ -672,39 +769,51 @@ __global__ void k_extension(ExtArgs a) {
   int grid[3] = {0, 0, 0};
   for (int b = 0; b < g.d; ++b)
     if (b != r) grid[b] = (int)floor((S.x((int)q, b) - g.lo) / g.h + 0.5);
-  double t = (S.x((int)q, r) - g.lo) / g.h;
-  int ft = (int)floor(t);
+  double tq = (S.x((int)q, r) - g.lo) / g.h;
+  int ft = (int)floor(tq);
   int base = ft - (p / 2 - 1);
   const int shifts[5] = {0, 1, -1, 2, -2};
   const int own[8] = {-1, 1, -2, 2, -3, 3, -4, 4};
-  bool have = false;
-  double bestL = 0.0;
-  int bsel[4];
-  double bw[4];
-  // (i) lines of the argmax family along e_r
-  for (int si = 0; si < 5; ++si) {
+  // (i) this lane's shift candidate
+  bool cval = false;
+  double cL = 0.0;
+  int csel[4] = {0, 0, 0, 0};
+  double cw[4] = {0.0, 0.0, 0.0, 0.0};
+  if (lane < 5) {
     int c[3] = {grid[0], grid[1], grid[2]};
     c[r] = 0;
-    int sel[4];
     double nodes[4];
-    bool ok = true;
-    for (int j = 0; j < p && ok; ++j) {
-      int o = base + shifts[si] + j;
-      sel[j] = ext_point(S, (int)q, rp, c, r, o, ft);
+    cval = true;
+    for (int j = 0; j < p && cval; ++j) {
+      int o = base + shifts[lane] + j;
+      csel[j] = ext_point(S, (int)q, rp, c, r, o, ft);
       nodes[j] = (double)o;
-      ok = sel[j] >= 0;
+      cval = csel[j] >= 0;
     }
-    if (!ok) continue;
-    double w[4];
-    lagrange(t, nodes, p, w);
-    double L = 0.0;
-    for (int j = 0; j < p; ++j) L = L + fabs(w[j]);
-    if (!have || L < bestL) {
+    if (cval) {
+      lagrange(tq, nodes, p, cw);
+      for (int j = 0; j < p; ++j) cL = cL + fabs(cw[j]);
+    }
+  }
+  bool have = false;
+  double bestL = 0.0;
+  int bsel[4] = {0, 0, 0, 0};
+  double bw[4] = {0.0, 0.0, 0.0, 0.0};
+  for (int si = 0; si < 5; ++si) {
+    bool v = __shfl(cval ? 1 : 0, si, EXG) != 0;
+    double L = __shfl(cL, si, EXG);
+    int sl[4];
+    double wl[4];
+    for (int j = 0; j < 4; ++j) {
+      sl[j] = __shfl(csel[j], si, EXG);
+      wl[j] = __shfl(cw[j], si, EXG);
+    }
+    if (v && (!have || L < bestL)) {
       have = true;
       bestL = L;
-      for (int j = 0; j < p; ++j) {
-        bsel[j] = sel[j];
-        bw[j] = w[j];
+      for (int j = 0; j < 4; ++j) {
+        bsel[j] = sl[j];
+        bw[j] = wl[j];
       }
     }
   }
@@ -713,12 +822,13 @@ __global__ void k_extension(ExtArgs a) {
   trans_axes(g.d, r, T);
   for (int tb = 0; tb < g.d - 1; ++tb) {
     int b = T[tb];
+    int mine = ext_point(S, (int)q, r, grid, b, own[lane], 0);
     int sel[4], cnt = 0;
     double nodes[4];
-    for (int m = 0; m < 8 && cnt < p; ++m) {
-      int j = ext_point(S, (int)q, r, grid, b, own[m], 0);
-      if (j >= 0) {
-        sel[cnt] = j;
+    for (int m = 0; m < 8; ++m) {
+      int jm = __shfl(mine, m, EXG);
+      if (jm >= 0 && cnt < p) {
+        sel[cnt] = jm;
         nodes[cnt] = (double)own[m];
         ++cnt;
       }
@@ -737,8 +847,13 @@ __global__ void k_extension(ExtArgs a) {
       }
     }
   }
+  if (lane != 0) return;
   if (!have) {
     atomicOr(a.flags, FLAG_UNRESOLVED_EXT);
+    for (int j = 0; j < p; ++j) {
+      oi[j] = -1;
+      ow[j] = 0.0;
+    }
     return;
   }
   for (int j = 0; j < p; ++j) {
@@ -901,8 +1016,35 @@ struct OwnerArgs {
   int* flags;
 };
 
-__global__ void k_owner(OwnerArgs a) {
-  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+constexpr int OWG = 16;   // lanes per correction entry
+
+// cell of the (2m+1)^d box around cq with linear index idx, if it lies on
+// ring m (Chebyshev distance m) and inside the grid of bins
+__device__ __forceinline__ bool ring_cell(const GridDesc& g, int64_t nca, const int cq[3], int m, int idx,
+                                          int64_t koff, int64_t* key) {
+  const int w = 2 * m + 1;
+  int o[3] = {idx % w - m, (idx / w) % w - m, g.d == 3 ? idx / (w * w) - m : 0};
+  int cheb = 0;
+  for (int t = 0; t < 3; ++t) {
+    int v = o[t] < 0 ? -o[t] : o[t];
+    cheb = v > cheb ? v : cheb;
+  }
+  if (cheb != m) return false;
+  int cc[3] = {cq[0] + o[0], cq[1] + o[1], cq[2] + o[2]};
+  for (int t = 0; t < g.d; ++t)
+    if (cc[t] < 0 || cc[t] >= nca) return false;
+  *key = koff + cc[0] + nca * (cc[1] + (g.d == 3 ? nca * cc[2] : 0));
+  return true;
+}
+
+// Closest centre of every correction entry, one group of OWG lanes per
+// entry: rings of bins are scanned in parallel (lanes over the cells of a
+// ring); the same stop rule and tie rule as a sequential scan, so the owner
+// is identical.
+__global__ void __launch_bounds__(KFBI_BLOCK) k_owner(OwnerArgs a) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t e = t / OWG;
+  int lane = (int)(t % OWG);
   if (e >= a.n_corr) return;
   const GridDesc& g = a.g;
   int k = a.ck[e];
@@ -913,80 +1055,71 @@ __global__ void k_owner(OwnerArgs a) {
   bin_of(g, a.nca, X, k, a.ncell, cq);
   int64_t koff = (int64_t)(k - 1) * a.ncell;
   double cs = 2.0 * g.h;
-  double d2min = 0.0;
-  bool found = false;
+  double d2min = INFINITY;
   int mfinal = -1;
-  int nz = g.d == 3 ? 1 : 0;
   for (int m = 0; m <= a.nca; ++m) {
-    for (int z = -m * nz; z <= m * nz; ++z)
-      for (int y = -m; y <= m; ++y)
-        for (int x = -m; x <= m; ++x) {
-          int ax = x < 0 ? -x : x, ay = y < 0 ? -y : y, az = z < 0 ? -z : z;
-          int cheb = ax > ay ? ax : ay;
-          cheb = cheb > az ? cheb : az;
-          if (cheb != m) continue;
-          int cc[3] = {cq[0] + x, cq[1] + y, cq[2] + z};
-          bool ok = true;
-          for (int t = 0; t < g.d; ++t) ok = ok && cc[t] >= 0 && cc[t] < a.nca;
-          if (!ok) continue;
-          int64_t key = koff + cc[0] + a.nca * (cc[1] + (g.d == 3 ? a.nca * cc[2] : 0));
-          for (int j = a.start[key]; j < a.start[key] + a.cnt[key]; ++j) {
-            int ctr = a.items[j];
-            const double* P = a.spos + (int64_t)a.d2s[ctr] * g.d;
-            double dx = X[0] - P[0], dy = X[1] - P[1];
-            double d2 = dx * dx + dy * dy;
-            if (g.d == 3) {
-              double dz = X[2] - P[2];
-              d2 = d2 + dz * dz;
-            }
-            if (!found || d2 < d2min) {
-              found = true;
-              d2min = d2;
-            }
-          }
+    const int w = 2 * m + 1;
+    const int ncells = g.d == 3 ? w * w * w : w * w;
+    double loc = INFINITY;
+    for (int idx = lane; idx < ncells; idx += OWG) {
+      int64_t key;
+      if (!ring_cell(g, a.nca, cq, m, idx, koff, &key)) continue;
+      for (int j = a.start[key]; j < a.start[key] + a.cnt[key]; ++j) {
+        const double* P = a.spos + (int64_t)a.d2s[a.items[j]] * g.d;
+        double dx = X[0] - P[0], dy = X[1] - P[1];
+        double d2 = dx * dx + dy * dy;
+        if (g.d == 3) {
+          double dz = X[2] - P[2];
+          d2 = d2 + dz * dz;
         }
+        loc = d2 < loc ? d2 : loc;
+      }
+    }
+    for (int off = OWG / 2; off > 0; off >>= 1) {
+      double o = __shfl_xor(loc, off, OWG);
+      loc = o < loc ? o : loc;
+    }
+    d2min = loc < d2min ? loc : d2min;
     double lim = (double)m * cs;
-    if (found && d2min * (1.0 + TIE_BAND) < lim * lim) {
+    if (d2min < INFINITY && d2min * (1.0 + TIE_BAND) < lim * lim) {
       mfinal = m;
       break;
     }
   }
-  if (mfinal < 0) {
-    if (!found) {
+  if (!(d2min < INFINITY)) {
+    if (lane == 0) {
       atomicOr(a.flags, FLAG_UNRESOLVED_OWNER);
       a.owner[e] = 0;
-      return;
     }
-    mfinal = (int)a.nca;
+    return;
   }
-  double thr = d2min * (1.0 + TIE_BAND);
-  int best = -1;
-  for (int m = 0; m <= mfinal; ++m)
-    for (int z = -m * nz; z <= m * nz; ++z)
-      for (int y = -m; y <= m; ++y)
-        for (int x = -m; x <= m; ++x) {
-          int ax = x < 0 ? -x : x, ay = y < 0 ? -y : y, az = z < 0 ? -z : z;
-          int cheb = ax > ay ? ax : ay;
-          cheb = cheb > az ? cheb : az;
-          if (cheb != m) continue;
-          int cc[3] = {cq[0] + x, cq[1] + y, cq[2] + z};
-          bool ok = true;
-          for (int t = 0; t < g.d; ++t) ok = ok && cc[t] >= 0 && cc[t] < a.nca;
-          if (!ok) continue;
-          int64_t key = koff + cc[0] + a.nca * (cc[1] + (g.d == 3 ? a.nca * cc[2] : 0));
-          for (int j = a.start[key]; j < a.start[key] + a.cnt[key]; ++j) {
-            int ctr = a.items[j];
-            const double* P = a.spos + (int64_t)a.d2s[ctr] * g.d;
-            double dx = X[0] - P[0], dy = X[1] - P[1];
-            double d2 = dx * dx + dy * dy;
-            if (g.d == 3) {
-              double dz = X[2] - P[2];
-              d2 = d2 + dz * dz;
-            }
-            if (d2 <= thr && (best < 0 || ctr < best)) best = ctr;
-          }
+  if (mfinal < 0) mfinal = (int)a.nca;
+  const double thr = d2min * (1.0 + TIE_BAND);
+  int best = 0x7fffffff;
+  for (int m = 0; m <= mfinal; ++m) {
+    const int w = 2 * m + 1;
+    const int ncells = g.d == 3 ? w * w * w : w * w;
+    for (int idx = lane; idx < ncells; idx += OWG) {
+      int64_t key;
+      if (!ring_cell(g, a.nca, cq, m, idx, koff, &key)) continue;
+      for (int j = a.start[key]; j < a.start[key] + a.cnt[key]; ++j) {
+        const int ctr = a.items[j];
+        const double* P = a.spos + (int64_t)a.d2s[ctr] * g.d;
+        double dx = X[0] - P[0], dy = X[1] - P[1];
+        double d2 = dx * dx + dy * dy;
+        if (g.d == 3) {
+          double dz = X[2] - P[2];
+          d2 = d2 + dz * dz;
         }
-  a.owner[e] = best;
+        if (d2 <= thr && ctr < best) best = ctr;
+      }
+    }
+  }
+  for (int off = OWG / 2; off > 0; off >>= 1) {
+    int o = __shfl_xor(best, off, OWG);
+    best = o < best ? o : best;
+  }
+  if (lane == 0) a.owner[e] = best;
 }
 
 // ---------------------------------------------------------------- host helpers
@@ -1034,6 +1167,23 @@ kfbi_status compact_count(kfbi_plan* pl, int64_t n, Pred pred, int64_t* count) {
   }
   KCHK(ensure_blk(pl, nb));
   hipLaunchKernelGGL(k_count<Pred>, dim3((unsigned)nb), dim3(KFBI_BLOCK), 0, pl->stream, n, pred, pl->blk);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, pl->stream, pl->blk, nb, pl->blk_total);
+  HIPCHK(hipMemcpyAsync(pl->h_pinned, pl->blk_total, sizeof(int), hipMemcpyDeviceToHost, pl->stream));
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  *count = pl->h_pinned[0];
+  return KFBI_OK;
+}
+
+template <class Pred>
+kfbi_status compact_count_flags(kfbi_plan* pl, int64_t n, Pred pred, int64_t* count) {
+  int64_t nb = (n + CMP_CH - 1) / CMP_CH;
+  if (nb == 0) {
+    *count = 0;
+    return KFBI_OK;
+  }
+  KCHK(ensure_blk(pl, nb));
+  hipLaunchKernelGGL(k_count_flags<Pred>, dim3((unsigned)nb), dim3(KFBI_BLOCK), 0, pl->stream, n, pred, pl->blk,
+                     pl->flags8);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, pl->stream, pl->blk, nb, pl->blk_total);
   HIPCHK(hipMemcpyAsync(pl->h_pinned, pl->blk_total, sizeof(int), hipMemcpyDeviceToHost, pl->stream));
   HIPCHK(hipStreamSynchronize(pl->stream));
@@ -1124,7 +1274,7 @@ kfbi_status geo_setup(kfbi_plan* pl) {
   int64_t n_items = pl->n_seg * g.K;
   CandPred cp{g, pl->region};
   int64_t nc;
-  KCHK(compact_count(pl, n_items, cp, &nc));
+  KCHK(compact_count_flags(pl, n_items, cp, &nc));
   if (nc == 0) {
     kfbi_set_error("no grid segment crosses an interface");
     return KFBI_E_INVALID;
@@ -1143,8 +1293,9 @@ kfbi_status geo_setup(kfbi_plan* pl) {
     pl->cap_cand = cap;
   }
   pl->n_cand = nc;
-  compact_emit(pl, n_items, cp, CandEmit{g, pl->region, pl->c_r, pl->c_lid, pl->c_seg, pl->c_k, pl->c_ina});
-  hipLaunchKernelGGL(k_bisect, dim3(nblk(nc)), dim3(KFBI_BLOCK), 0, st,
+  compact_emit(pl, n_items, NeedPred{pl->flags8},
+               CandEmit{g, pl->region, pl->c_r, pl->c_lid, pl->c_seg, pl->c_k, pl->c_ina});
+  hipLaunchKernelGGL(k_bisect, dim3(nblk(nc * 8)), dim3(KFBI_BLOCK), 0, st,
                      BisectArgs{g, L, nc, pl->c_r, pl->c_lid, pl->c_seg, pl->c_k, pl->c_ina, pl->c_pos,
                                 pl->c_nrm, pl->c_acc});
 
@@ -1223,15 +1374,15 @@ kfbi_status geo_setup(kfbi_plan* pl) {
   shift_list(g.d, offs, lat.shN, &lat.nSN);
   SurfView S{g, pl->s_pos, pl->s_nrm, pl->s_meta, pl->line_start, pl->line_end, L1};
   HIPCHK(hipMemsetAsync(pl->s_need, 0, ns, st));
-  hipLaunchKernelGGL(k_stencils, dim3(nblk(nd)), dim3(KFBI_BLOCK), 0, st,
+  hipLaunchKernelGGL(k_stencils, dim3(nblk(nd * STG)), dim3(KFBI_BLOCK), 0, st,
                      StencilArgs{S, lat, nd, pl->d2s, pl->stD, pl->stN, pl->s_need, pl->d_flags});
-  hipLaunchKernelGGL(k_extension, dim3(nblk(ns)), dim3(KFBI_BLOCK), 0, st,
+  hipLaunchKernelGGL(k_extension, dim3(nblk(ns * EXG)), dim3(KFBI_BLOCK), 0, st,
                      ExtArgs{S, ns, pl->s2d, pl->s_need, pl->ext_idx, pl->ext_w, pl->d_flags});
 
   // irregular nodes
   IrrPred ip{g, pl->region};
   int64_t ni;
-  KCHK(compact_count(pl, g.n_nodes, ip, &ni));
+  KCHK(compact_count_flags(pl, g.n_nodes, ip, &ni));
   if (ni > pl->cap_irr) {
     int64_t cap = headroom(ni);
     pl->cap_irr = 0;
@@ -1239,7 +1390,7 @@ kfbi_status geo_setup(kfbi_plan* pl) {
     pl->cap_irr = cap;
   }
   pl->n_irr = ni;
-  compact_emit(pl, g.n_nodes, ip, IdxEmit{pl->irr});
+  compact_emit(pl, g.n_nodes, NeedPred{pl->flags8}, IdxEmit{pl->irr});
 
   // correction entries
   HIPCHK(hipMemsetAsync(pl->need, 0, (size_t)g.K * g.n_nodes, st));
@@ -1281,7 +1432,7 @@ kfbi_status geo_setup(kfbi_plan* pl) {
   ba.items = pl->cell_items;
   hipLaunchKernelGGL(k_bin_fill, dim3(nblk(nd)), dim3(KFBI_BLOCK), 0, st, ba, pl->cell_start, cursor);
   if (ne > 0)
-    hipLaunchKernelGGL(k_owner, dim3(nblk(ne)), dim3(KFBI_BLOCK), 0, st,
+    hipLaunchKernelGGL(k_owner, dim3(nblk(ne * OWG)), dim3(KFBI_BLOCK), 0, st,
                        OwnerArgs{g, ne, pl->ncell_axis, pl->ncell, pl->ce_k, pl->ce_node, pl->d2s, pl->s_pos,
                                  pl->cell_start, pl->cell_count, pl->cell_items, pl->ce_owner, pl->d_flags});
   HIPCHK(hipMemcpyAsync(pl->h_pinned + 1, pl->d_flags, sizeof(int), hipMemcpyDeviceToHost, st));

@@ -118,33 +118,66 @@ __global__ void __launch_bounds__(GB) k_arnoldi(int64_t n, int* ctl, int ldh, do
     double inv = 1.0 / hn;
     for (int64_t t = threadIdx.x; t < n; t += GB) w[t] = w[t] * inv;
   }
+  // Givens rotations of column j, in LDS (the previous rotations are read in
+  // parallel first; the recurrence itself is sequential)
+  __shared__ double lcs[KFBI_GMRES_MAX], lsn[KFBI_GMRES_MAX];
+  for (int i = threadIdx.x; i < j; i += GB) {
+    lcs[i] = cs[i];
+    lsn[i] = sn[i];
+  }
+  if (threadIdx.x == 0) hs[j + 1] = hn;
+  __syncthreads();
   if (threadIdx.x == 0) {
-    for (int i = 0; i <= j; ++i) hcol[i] = hs[i];
-    hcol[j + 1] = hn;
     for (int i = 0; i < j; ++i) {
-      double t = cs[i] * hcol[i] + sn[i] * hcol[i + 1];
-      hcol[i + 1] = -sn[i] * hcol[i] + cs[i] * hcol[i + 1];
-      hcol[i] = t;
+      double t = lcs[i] * hs[i] + lsn[i] * hs[i + 1];
+      hs[i + 1] = -lsn[i] * hs[i] + lcs[i] * hs[i + 1];
+      hs[i] = t;
     }
-    double den = hypot(hcol[j], hcol[j + 1]);
-    cs[j] = hcol[j] / den;
-    sn[j] = hcol[j + 1] / den;
-    hcol[j] = den;
-    hcol[j + 1] = 0.0;
-    gv[j + 1] = -sn[j] * gv[j];
-    gv[j] = cs[j] * gv[j];
-    double res = fabs(gv[j + 1]);
+    double den = hypot(hs[j], hs[j + 1]);
+    double cj = hs[j] / den, sj = hs[j + 1] / den;
+    cs[j] = cj;
+    sn[j] = sj;
+    hs[j] = den;
+    hs[j + 1] = 0.0;
+    double gj = gv[j];
+    gv[j + 1] = -sj * gj;
+    gv[j] = cj * gj;
+    double res = fabs(-sj * gj);
     scal[0] = res;
     scal[2] = breakdown ? 1.0 : 0.0;
     ctl[2] = j + 1;
     ctl[0] = j + 1;
     ctl[1] = (res <= scal[3] * scal[1] || breakdown || j + 1 >= ctl[3]) ? 1 : 0;
   }
+  __syncthreads();
+  for (int i = threadIdx.x; i <= j + 1; i += GB) hcol[i] = hs[i];
 }
 
-// y = H^{-1} g (upper triangular, k x k), then x = x0 + V^T y
-__global__ void k_trisolve(int k, int ldh, const double* Hm, const double* gv, double* y) {
-  if (threadIdx.x != 0 || blockIdx.x != 0) return;
+// y = H^{-1} g (upper triangular, k x k), then x = x0 + V^T y.  The
+// triangle is staged in LDS (k <= 64) so the sequential back substitution
+// reads no global memory.
+__global__ void __launch_bounds__(256) k_trisolve(int k, int ldh, const double* Hm, const double* gv, double* y) {
+  __shared__ double H[64][65];
+  __shared__ double gl[64];
+  if (k <= 64) {
+    for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
+      int m = t / k, i = t % k;      // column m, row i
+      H[i][m] = Hm[(int64_t)m * ldh + i];
+    }
+    for (int t = threadIdx.x; t < k; t += blockDim.x) gl[t] = gv[t];
+    __syncthreads();
+    __shared__ double yl[64];
+    if (threadIdx.x == 0) {
+      for (int i = k - 1; i >= 0; --i) {
+        double s = gl[i];
+        for (int m = i + 1; m < k; ++m) s -= H[i][m] * yl[m];
+        yl[i] = s / H[i][i];
+      }
+      for (int i = 0; i < k; ++i) y[i] = yl[i];
+    }
+    return;
+  }
+  if (threadIdx.x != 0) return;
   for (int i = k - 1; i >= 0; --i) {
     double s = gv[i];
     for (int m = i + 1; m < k; ++m) s -= Hm[(int64_t)m * ldh + i] * y[m];
@@ -189,7 +222,7 @@ void gm_arnoldi(kfbi_plan* pl) {
 }
 
 void gm_update(kfbi_plan* pl, int k, double* x, int use_x0) {
-  if (k > 0) hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(64), 0, pl->stream, k, pl->gm_cap + 1, pl->Hm, pl->gv,
+  if (k > 0) hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(256), 0, pl->stream, k, pl->gm_cap + 1, pl->Hm, pl->gv,
                                 pl->scal + 8);
   unsigned nbk = (unsigned)((pl->n_dof + KFBI_BLOCK - 1) / KFBI_BLOCK);
   hipLaunchKernelGGL(k_combine, dim3(nbk), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_dof, k, pl->V, pl->scal + 8, x,

@@ -77,6 +77,7 @@ struct kfbi_plan {
   // closest-centre bins
   int *cell_count, *cell_start, *cell_items;
   // scan scratch
+  uint8_t* flags8;               // predicate per item, max(d N (N+1)^(d-1) K, n_nodes)
   int *blk, *blk_total;
   int64_t cap_blk;
   int* d_flags;
@@ -108,8 +109,8 @@ struct kfbi_plan {
   const int* ctl_active;         // non-null while the iteration is captured
   hipStream_t gstream;           // private stream of kfbi_solve (graph launches)
   hipEvent_t ev_in, ev_out;
-  hipGraph_t graph;
-  hipGraphExec_t graph_exec;
+  hipGraph_t graph, graph4;
+  hipGraphExec_t graph_exec, graph4_exec;     // one and four iterations
   uint64_t graph_key[20];
   int* h_ctl;
   // box-solve event timing

@@ -104,6 +104,38 @@ __device__ __forceinline__ double Cval(const double* Cg, int64_t n, int k, int64
   return k == 0 ? 0.0 : Cg[(int64_t)(k - 1) * n + q];
 }
 
+// monomials xi^alpha of total degree <= P in graded order (fully unrolled,
+// so every index is a compile-time constant)
+template <int D, int P>
+__device__ __forceinline__ void monomials(const double xi[3], double* phi) {
+  double px[P + 1], py[P + 1], pz[P + 1];
+  px[0] = py[0] = pz[0] = 1.0;
+#pragma unroll
+  for (int e = 1; e <= P; ++e) {
+    px[e] = px[e - 1] * xi[0];
+    py[e] = py[e - 1] * xi[1];
+    pz[e] = D == 3 ? pz[e - 1] * xi[2] : 0.0;
+  }
+  int n = 0;
+#pragma unroll
+  for (int m = 0; m <= P; ++m) {
+    if (D == 2) {
+#pragma unroll
+      for (int j = 0; j <= m; ++j) phi[n++] = px[m - j] * py[j];
+    } else {
+#pragma unroll
+      for (int x = m; x >= 0; --x)
+#pragma unroll
+        for (int y = m - x; y >= 0; --y) phi[n++] = px[x] * py[y] * pz[m - x - y];
+    }
+  }
+}
+
+template <int D, int P>
+constexpr int ncoef_t() {
+  return D == 2 ? (P + 1) * (P + 2) / 2 : (P + 1) * (P + 2) * (P + 3) / 6;
+}
+
 __device__ __forceinline__ double mono_eval(const Mono& M, const double* U, const double xi[3]) {
   double pw[3][5];
   for (int a = 0; a < 3; ++a) {
@@ -313,35 +345,35 @@ __global__ void k_entry_map(int64_t n_corr, int64_t n_nodes, const int* ck, cons
   EI[(int64_t)(ck[e] - 1) * n_nodes + cnode[e]] = (int)e;
 }
 
+template <int D, int P>
 __global__ void k_fold_corr(FoldArgs a) {
+  constexpr int NC = ncoef_t<D, P>();
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= a.n_corr) return;
   const GridDesc& g = a.g;
   int c[3];
   unravel(g, a.cnode[e], c);
   int own = a.cown[e];
-  const double* P = a.spos + (int64_t)a.d2s[own] * g.d;
+  const double* P0 = a.spos + (int64_t)a.d2s[own] * D;
   double xi[3] = {0.0, 0.0, 0.0};
-  for (int ax = 0; ax < g.d; ++ax) xi[ax] = ((g.lo + (double)c[ax] * g.h) - P[ax]) / g.h;
-  const double* Mi = a.MinvT + (int64_t)own * a.nC * a.nC;
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) xi[ax] = ((g.lo + (double)c[ax] * g.h) - P0[ax]) / g.h;
+  double phi[NC];
+  monomials<D, P>(xi, phi);
+  const double* Mi = a.MinvT + (int64_t)own * NC * NC;
   for (int j = 0; j < a.nN; ++j) {
-    const double* col = Mi + (int64_t)(a.nP + a.nD + j) * a.nC;
+    const double* col = Mi + (int64_t)(a.nP + a.nD + j) * NC;
     double sacc = 0.0;
-    for (int al = 0; al < a.nC; ++al) {
-      double t = col[al];
-      for (int ax = 0; ax < g.d; ++ax) {
-        const int ex = a.M.E[al][ax];
-        for (int q = 0; q < ex; ++q) t *= xi[ax];
-      }
-      sacc += t;
-    }
+#pragma unroll
+    for (int al = 0; al < NC; ++al) sacc += col[al] * phi[al];
     const double rn = g.h * sacc;
     const int sN = a.stN[(int64_t)own * a.nN + j];
-    for (int m = 0; m < g.p; ++m) {
-      const int idx = a.ext_idx[(int64_t)sN * g.p + m];
-      const int64_t o = e * a.nF + (int64_t)j * g.p + m;
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      const int idx = a.ext_idx[(int64_t)sN * P + m];
+      const int64_t o = e * a.nF + (int64_t)j * P + m;
       a.FI[o] = idx >= 0 ? idx : 0;
-      a.FW[o] = idx >= 0 ? rn * a.ext_w[(int64_t)sN * g.p + m] : 0.0;
+      a.FW[o] = idx >= 0 ? rn * a.ext_w[(int64_t)sN * P + m] : 0.0;
     }
   }
 }
@@ -720,8 +752,13 @@ kfbi_status op_fold(kfbi_plan* pl) {
   A.IW = pl->IW;
   A.PA = pl->PA;
   A.S = make_stencil(g);
-  if (pl->n_corr > 0)
-    hipLaunchKernelGGL(k_fold_corr, dim3(nb(pl->n_corr)), dim3(KFBI_BLOCK), 0, pl->stream, A);
+  if (pl->n_corr > 0) {
+    dim3 gr(nb(pl->n_corr)), bl(KFBI_BLOCK);
+    if (g.d == 2 && g.p == 2) hipLaunchKernelGGL((k_fold_corr<2, 2>), gr, bl, 0, pl->stream, A);
+    if (g.d == 2 && g.p == 4) hipLaunchKernelGGL((k_fold_corr<2, 4>), gr, bl, 0, pl->stream, A);
+    if (g.d == 3 && g.p == 2) hipLaunchKernelGGL((k_fold_corr<3, 2>), gr, bl, 0, pl->stream, A);
+    if (g.d == 3 && g.p == 4) hipLaunchKernelGGL((k_fold_corr<3, 4>), gr, bl, 0, pl->stream, A);
+  }
   hipLaunchKernelGGL(k_fold_dof, dim3(nb(pl->n_dof * nbk)), dim3(KFBI_BLOCK), 0, pl->stream, A);
   if (pl->n_irr > 0) {
     hipLaunchKernelGGL(k_fold_pairs, dim3(nb(pl->n_irr)), dim3(KFBI_BLOCK), 0, pl->stream, A);
