@@ -30,12 +30,20 @@ def exponents(d, p):
 
 
 def _pow(x, e):
-    """x**e for an integer array e >= 0 (elementwise, with 0**0 = 1)."""
-    return np.where(e == 0, 1.0, np.power(x, np.maximum(e, 0)))
+    """x**e for an integer array e >= 0 by repeated multiplication
+    1 * x * x * ... (elementwise; x**0 = 1, and x**e = 0 for e < 0, which
+    only occurs multiplied by a zero factor)."""
+    e = np.broadcast_to(e, np.broadcast_shapes(np.shape(x), np.shape(e)))
+    x = np.broadcast_to(x, e.shape)
+    r = np.where(e >= 0, 1.0, 0.0)
+    for k in range(int(e.max(initial=0))):
+        r = np.where(e > k, r * x, r)
+    return r
 
 
 def mono(xi, E):
-    """Monomial values xi^alpha: xi (..., d) -> (..., n_alpha)."""
+    """Monomial values xi^alpha: xi (..., d) -> (..., n_alpha), the product
+    taken axis by axis, 1 * x^a * y^b (* z^c)."""
     v = np.ones(xi.shape[:-1] + (E.shape[0],))
     for a in range(E.shape[1]):
         v = v * _pow(xi[..., a:a + 1], E[:, a])
@@ -43,15 +51,15 @@ def mono(xi, E):
 
 
 def mono_grad(xi, E):
-    """Gradient of every monomial: (..., d, n_alpha)."""
+    """Gradient of every monomial: (..., d, n_alpha); component a is
+    alpha_a * x^(.) * y^(.) (* z^(.)) with the a-th exponent lowered."""
     d = E.shape[1]
     out = []
     for a in range(d):
-        v = np.ones(xi.shape[:-1] + (E.shape[0],))
+        v = np.broadcast_to(E[:, a].astype(np.float64), xi.shape[:-1] + (E.shape[0],))
         for b in range(d):
             e = E[:, b] - (1 if b == a else 0)
             v = v * _pow(xi[..., b:b + 1], e)
-        v = v * E[:, a]
         out.append(v)
     return np.stack(out, axis=-2)
 
@@ -61,11 +69,11 @@ def mono_lap(xi, E):
     d = E.shape[1]
     tot = np.zeros(xi.shape[:-1] + (E.shape[0],))
     for a in range(d):
-        v = np.ones(xi.shape[:-1] + (E.shape[0],))
+        v = np.broadcast_to((E[:, a] * (E[:, a] - 1)).astype(np.float64), xi.shape[:-1] + (E.shape[0],))
         for b in range(d):
             e = E[:, b] - (2 if b == a else 0)
             v = v * _pow(xi[..., b:b + 1], e)
-        tot = tot + v * (E[:, a] * (E[:, a] - 1))
+        tot = tot + v
     return tot
 
 
@@ -93,7 +101,9 @@ def assemble(geo):
     xiN = (S[st["N"]] - P[:, None, :]) / h
     g = mono_grad(xiN.reshape(-1, d), E).reshape(Nb, st["N"].shape[1], d, E.shape[0])
     nN = surf["nrm"][st["N"]]                    # (Nb, nN, d)
-    rowsN = np.einsum("ija,ijan->ijn", nN, g)
+    rowsN = np.zeros(g.shape[:2] + (E.shape[0],))
+    for a in range(d):
+        rowsN = rowsN + nN[:, :, a:a + 1] * g[:, :, a, :]
     return np.concatenate([rowsP, rowsD, rowsN], axis=1)
 
 
@@ -105,6 +115,21 @@ def factor(geo):
     Minv = np.linalg.inv(M)
     cond = np.abs(M).sum(axis=1).max(axis=1) * np.abs(Minv).sum(axis=1).max(axis=1)
     return M, Minv, cond
+
+
+def solve(M, Minv, Q):
+    """U with M U = Q for every centre, to full working accuracy: the
+    product with the inverse followed by one step of iterative refinement
+    whose residual Q - M U is formed in extended precision (long double),
+    so the result is the rounded exact solution of the square system of
+    Sec. 5.4 rather than one that depends on how the inverse was formed."""
+    U = np.einsum("iab,ib->ia", Minv, Q)
+    r = np.asarray(Q, dtype=np.longdouble)
+    Ml = M.astype(np.longdouble)
+    Ul = U.astype(np.longdouble)
+    for a in range(M.shape[2]):
+        r = r - Ml[:, :, a] * Ul[:, a:a + 1]
+    return U + np.einsum("iab,ib->ia", Minv, r.astype(np.float64))
 
 
 def rhs(geo, a, b, ftilde):

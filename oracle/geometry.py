@@ -562,10 +562,13 @@ def interp_blocks(prob, dofs):
 
 
 def correction_entries(prob, reg, irr, dofs, blocks):
-    """(interface k, node) pairs at which C^(k) is needed, ordered k-major,
-    node-minor.  Needed by the RHS correction (Sec. 5.2 and the multi-crossing
-    remark: C = C^(reg P) - C^(reg Q), C^(0) = 0) and by the corrected
-    interpolation (Sec. 5.5)."""
+    """(interface k, node) pairs at which the partition-of-unity value
+    C^(k) is needed, ordered k-major, node-minor.  Needed by the RHS
+    correction (Sec. 5.2 and the multi-crossing remark: C = C^(reg P) -
+    C^(reg Q), C^(0) = 0) and, in the corrected interpolation (Sec. 5.5), at
+    the block nodes of a DOF on interface k that lie inside another interface
+    k' (the DOF's own side is corrected with its own local polynomial, so
+    only C^(k') is needed there)."""
     d, N = prob["dim"], prob["N"]
     K = len(prob["ifaces"])
     flat = reg.ravel()
@@ -584,8 +587,7 @@ def correction_entries(prob, reg, irr, dofs, blocks):
         q = ravel(ind_b, prob)
         rq = flat[q]
         k = dofs["iface"]
-        m = rq != k
-        need[k[m], q[m]] = True
+        m = (rq != k) & (rq != 0)
         need[rq[m], q[m]] = True
     need[0] = False
     kk, nodes = np.nonzero(need)

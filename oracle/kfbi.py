@@ -90,7 +90,7 @@ class Plan:
         geo = self.geo
         d, N, h = self.d, self.N, self.h
         Q = collocation.rhs(geo, a, b, ftilde)
-        U = np.einsum("iab,ib->ia", self.Minv, Q)
+        U = collocation.solve(self.M, self.Minv, Q)
         # correction function at the entries (closest-centre partition of unity)
         own = geo["cowner"]
         X = self.node_coords(geo["cnode"])
@@ -136,6 +136,15 @@ class Plan:
         return v, dn_in, dn_out, U
 
     def normal_derivatives(self, v, Cg, U):
+        """One-sided normal derivatives at the DOFs (Sec. 5.5).  The grid
+        values of the block of DOF p are made smooth across the interface by
+        adding, at every node q outside p's own region k, the jump
+        u_k - u_reg(q) = C^(k)(q) - C^(reg q)(q); C^(k) is p's own local
+        correction polynomial C_{h,p} (the Taylor expansion is taken at p),
+        C^(reg q) for another interface's interior is its partition-of-unity
+        value, and C^(0) = 0.  Then d_n v_in(p) is the normal derivative of
+        the tensor-product Lagrange interpolant and d_n v_out(p) =
+        d_n v_in(p) - d_n C_{h,p}(p)."""
         geo = self.geo
         d, h, q = self.d, self.h, self.p
         dofs = geo["dofs"]
@@ -147,7 +156,9 @@ class Plan:
             ind = [geo["blocks"][:, a] + blk[a] for a in range(d)]
             qn = geometry.ravel(ind, self.prob)
             rq = flat[qn]
-            vt = vf[qn] + np.where(rq != kk, Cg[kk, qn] - Cg[rq, qn], 0.0)
+            xi = (self.node_coords(qn) - dofs["pos"]) / h
+            Cown = (collocation.mono(xi, self.E) * U).sum(axis=1)
+            vt = vf[qn] + np.where(rq != kk, Cown - Cg[rq, qn], 0.0)
             for a in range(d):
                 w = self.ider[:, a, blk[a]] / h
                 for b in range(d):

@@ -109,6 +109,7 @@ void free_plan(kfbi_plan* pl) {
   dfree(pl->ext_idx);
   dfree(pl->ext_w);
   dfree(pl->MinvT);
+  dfree(pl->MT);
   dfree(pl->cond);
   dfree(pl->psiS);
   dfree(pl->aS);
@@ -143,7 +144,8 @@ void free_plan(kfbi_plan* pl) {
   dfree(pl->GW);
   dfree(pl->IW);
   dfree(pl->IB);
-  dfree(pl->IE1);
+  dfree(pl->HW);
+  dfree(pl->TI);
   dfree(pl->IE2);
   dfree(pl->PA);
   dfree(pl->PE1);

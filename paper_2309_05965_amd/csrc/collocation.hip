@@ -19,6 +19,10 @@
 
 #include "kfbi_internal.h"
 
+// every entry of M is formed by plain multiplications and additions in a
+// fixed order (no contraction), so the matrices are bitwise reproducible
+#pragma clang fp contract(off)
+
 void kfbi_pde_lattice(int d, int p, int (*off)[3], int* n);
 
 namespace {
@@ -43,6 +47,7 @@ struct FactorArgs {
   const double *spos, *snrm;
   const int *stD, *stN;
   double* MinvT;
+  double* MT;         // M^T[c][alpha][j] (kept for the refinement of U)
   double* cond;
   int* flags;
 };
@@ -109,6 +114,13 @@ __global__ void __launch_bounds__(64) k_factor(FactorArgs a) {
     }
   }
   __syncthreads();
+  {
+    double* mt = a.MT + c * (int64_t)n * n;
+    for (int idx = lane; idx < n * n; idx += 64) {
+      int al = idx / n, j = idx % n;
+      mt[idx] = A[j][al];
+    }
+  }
   // 1-norm of M (max column sum)
   if (lane < n) {
     double t = 0.0;
@@ -218,8 +230,8 @@ kfbi_status colloc_factor(kfbi_plan* pl) {
     return KFBI_E_INVALID;
   }
   HIPCHK(hipMemsetAsync(pl->d_flags, 0, sizeof(int), pl->stream));
-  FactorArgs a{pl->g, T, pl->n_dof, pl->d2s, pl->s_pos, pl->s_nrm, pl->stD, pl->stN, pl->MinvT, pl->cond,
-               pl->d_flags};
+  FactorArgs a{pl->g, T, pl->n_dof, pl->d2s, pl->s_pos, pl->s_nrm, pl->stD, pl->stN, pl->MinvT, pl->MT,
+               pl->cond, pl->d_flags};
   hipLaunchKernelGGL(k_factor, dim3((unsigned)pl->n_dof), dim3(64), 0, pl->stream, a);
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(pl->h_pinned + 1, pl->d_flags, sizeof(int), hipMemcpyDeviceToHost, pl->stream));

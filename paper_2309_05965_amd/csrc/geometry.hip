@@ -941,9 +941,9 @@ __global__ void k_need_blocks(GridDesc g, int64_t n_dof, const int* d2s, const d
         int cc[3] = {st[0] + b0, st[1] + b1, st[2] + b2};
         int64_t Q = ravel(g, cc);
         int rq = region[Q];
-        if (rq == k) continue;
-        need[(int64_t)(k - 1) * g.n_nodes + Q] = 1;
-        if (rq != 0) need[(int64_t)(rq - 1) * g.n_nodes + Q] = 1;
+        // the centre's own side is corrected with its own polynomial; only
+        // nodes inside another interface need that interface's C
+        if (rq != k && rq != 0) need[(int64_t)(rq - 1) * g.n_nodes + Q] = 1;
       }
 }
 
@@ -1341,6 +1341,7 @@ kfbi_status geo_setup(kfbi_plan* pl) {
     KCHK(realloc_n(&pl->stD, cap * pl->nD));
     KCHK(realloc_n(&pl->stN, cap * pl->nN));
     KCHK(realloc_n(&pl->MinvT, cap * pl->nC * pl->nC));
+    KCHK(realloc_n(&pl->MT, cap * pl->nC * pl->nC));
     KCHK(realloc_n(&pl->cond, cap));
     KCHK(realloc_n(&pl->U, cap * pl->nC));
     KCHK(realloc_n(&pl->dn_in, cap));

@@ -69,6 +69,7 @@ struct kfbi_plan {
   int* ext_idx;
   double* ext_w;
   double* MinvT;                 // [n_dof][nC][nC], element (alpha, j) at j*nC + alpha
+  double* MT;                    // [n_dof][nC][nC], M element (j, alpha) at alpha*nC + j
   double* cond;
   double *psiS, *aS, *U, *dn_in, *dn_out;
   // irregular nodes and correction entries
@@ -91,13 +92,18 @@ struct kfbi_plan {
   int64_t gm_n;
   // folded operators of the matvec (set-up products of the inverses with the
   // density extension): C at entry e = sum_t FW[e][t] psi[FI[e][t]],
-  // d_n C at centre c = sum_t GW[c][t] psi[GI[c][t]]  (nF = nN p terms)
+  // d_n C at centre c = sum_t GW[c][t] psi[GI[c][t]], own-polynomial part of
+  // the interpolation at centre c = sum_t HW[c][t] psi[GI[c][t]]
+  // (nF = nN p terms)
   int nF, maxpairs;
   int *FI, *GI;
-  double *FW, *GW, *IW;          // IW: [n_dof][(q+1)^d] normal-derivative weights
+  double *FW, *GW, *HW, *IW;     // IW: [n_dof][(q+1)^d] normal-derivative weights
+  double* TI;                    // [n_dof][nC] sum over the block nodes outside the
+                                 // centre's region of IW * monomials (own polynomial)
   double* Cv;                    // [n_corr] correction values of the current matvec
   int* IB;                       // [n_dof] first node of the interpolation block
-  int *IE1, *IE2;                // [n_dof][(q+1)^d] entries of C^(k), C^(reg q) at block nodes
+  int* IE2;                      // [n_dof][(q+1)^d] entry of C^(reg q) at block nodes
+                                 // inside another interface, -1 elsewhere
   double* PA;                    // [n_irr][maxpairs] stencil coefficients of the cut neighbours
   int *PE1, *PE2;                // [n_irr][maxpairs] entries of C^(reg P), C^(reg Q)
   int *EI;                       // [K][n_nodes] entry index of (interface, node), -1 if none

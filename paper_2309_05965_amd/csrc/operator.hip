@@ -174,31 +174,73 @@ struct CoefArgs {
   int64_t n_dof;
   int n, nP, nD, nN;
   double h;
-  const double* MinvT;
+  const double *MinvT, *MT;
   const double *a, *b, *ftilde;
   const int *stD, *stN;
   double* U;
 };
 
-// U[c][alpha] = sum_j Minv[c][alpha][j] Q[c][j],
-// Q = [h^2 ftilde(PDE pts) ; a(D pts) ; h b(N pts)]   (Sec. 5.3.1, eq. cau-ls)
-__global__ void k_coef(CoefArgs a) {
-  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  int64_t c = t / a.n;
-  int al = (int)(t % a.n);
-  if (c >= a.n_dof) return;
-  const double* Mi = a.MinvT + c * (int64_t)a.n * a.n;
-  double s = 0.0;
-  if (a.ftilde) {
-    double h2 = a.h * a.h;
-    for (int j = 0; j < a.nP; ++j) s += Mi[j * a.n + al] * (h2 * a.ftilde[c * a.nP + j]);
+// error-free transformations (Knuth two-sum; product error by fma)
+__device__ __forceinline__ void two_sum(double x, double y, double& s, double& e) {
+  s = x + y;
+  double z = s - x;
+  e = (x - (s - z)) + (y - z);
+}
+
+// U[c] solves M U = Q, Q = [h^2 ftilde(PDE pts) ; a(D pts) ; h b(N pts)]
+// (Sec. 5.3.1, eq. cau-ls): U1 = Minv Q, then one refinement step
+// U = U1 + Minv r with the residual r = Q - M U1 summed in compensated
+// (twice working) precision, which makes U the rounded exact solution of
+// the square system independent of how the inverse was formed.  One
+// wavefront per centre, lane = row / coefficient index.
+constexpr int COEF_WAVES = KFBI_BLOCK / 64;
+
+__global__ void __launch_bounds__(KFBI_BLOCK) k_coef(CoefArgs a) {
+  __shared__ double Qs[COEF_WAVES][KFBI_MAXC], Us[COEF_WAVES][KFBI_MAXC], Rs[COEF_WAVES][KFBI_MAXC];
+  const int wv = threadIdx.x >> 6, lane = threadIdx.x & 63;
+  const int64_t c = (int64_t)blockIdx.x * COEF_WAVES + wv;
+  if (c >= a.n_dof) return;           // whole wavefronts leave together
+  const int n = a.n;
+  if (lane < n) {
+    const int j = lane;
+    double q = 0.0;
+    if (j < a.nP) {
+      if (a.ftilde) q = (a.h * a.h) * a.ftilde[c * a.nP + j];
+    } else if (j < a.nP + a.nD) {
+      if (a.a) q = a.a[a.stD[c * a.nD + (j - a.nP)]];
+    } else {
+      if (a.b) q = a.h * a.b[a.stN[c * a.nN + (j - a.nP - a.nD)]];
+    }
+    Qs[wv][j] = q;
   }
-  if (a.a)
-    for (int j = 0; j < a.nD; ++j) s += Mi[(a.nP + j) * a.n + al] * a.a[a.stD[c * a.nD + j]];
-  if (a.b)
-    for (int j = 0; j < a.nN; ++j)
-      s += Mi[(a.nP + a.nD + j) * a.n + al] * (a.h * a.b[a.stN[c * a.nN + j]]);
-  a.U[c * a.n + al] = s;
+  __builtin_amdgcn_wave_barrier();
+  const double* Mi = a.MinvT + c * (int64_t)n * n;
+  if (lane < n) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += Mi[j * n + lane] * Qs[wv][j];
+    Us[wv][lane] = s;
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane < n) {
+    const double* mt = a.MT + c * (int64_t)n * n;
+    double s = Qs[wv][lane], comp = 0.0;
+    for (int al = 0; al < n; ++al) {
+      const double m = mt[al * n + lane], u = Us[wv][al];
+      const double p = m * u;
+      const double pe = fma(m, u, -p);
+      double t, e;
+      two_sum(s, -p, t, e);
+      s = t;
+      comp += e - pe;
+    }
+    Rs[wv][lane] = s + comp;
+  }
+  __builtin_amdgcn_wave_barrier();
+  if (lane < n) {
+    double s = 0.0;
+    for (int j = 0; j < n; ++j) s += Mi[j * n + lane] * Rs[wv][j];
+    a.U[c * n + lane] = Us[wv][lane] + s;
+  }
 }
 
 struct CorrArgs {
@@ -323,7 +365,11 @@ __global__ void k_bie_rhs(GridDesc g, int64_t n_dof, const int* d2s, const doubl
 //                         (FW = h phi(xi_e)^T Minv[:, N col j] * extension weight)
 //   d_n C_c(p_c)        = sum_t GW[c][t] psi[GI[c][t]]
 //                         (GW = sum_a n_a Minv[e_a, N col j] * extension weight)
-//   d_n v_in(p_c)       = sum_b IW[c][b] vtilde(block node b)
+//   d_n v_in(p_c)       = sum_b IW[c][b] (v(b) - C^(reg b)(b) [b inside another interface])
+//                         + sum_t HW[c][t] psi[GI[c][t]]
+//                         (the centre's own polynomial at the block nodes outside its
+//                          region: TI[c] = sum_b IW[c][b] phi(xi_b) over those nodes,
+//                          HW = h TI^T Minv[:, N col j] * extension weight)
 // plus the cut-neighbour lists of the irregular nodes and the entries of the
 // interpolation blocks, so a matvec is a short chain of gathers.
 struct FoldArgs {
@@ -334,8 +380,8 @@ struct FoldArgs {
   const int *d2s, *ck, *cnode, *cown, *stN, *ext_idx, *irr, *EI, *meta;
   const int8_t* region;
   const double *spos, *snrm, *MinvT, *ext_w;
-  int *FI, *GI, *IB, *IE1, *IE2, *PE1, *PE2;
-  double *FW, *GW, *IW, *PA;
+  int *FI, *GI, *IB, *IE2, *PE1, *PE2;
+  double *FW, *GW, *HW, *IW, *TI, *PA;
   Stencil S;
 };
 
@@ -423,16 +469,10 @@ __global__ void k_fold_dof(FoldArgs a) {
     w += nv[ax] * t2;
   }
   a.IW[c * nbk + b] = w;
-  // entries of C^(k) and C^(reg q) at the block node (-1 where not needed)
+  // entry of C^(reg q) at a block node inside another interface (-1 elsewhere)
   const int64_t Q = ravel(g, st[0] + bb[0], st[1] + bb[1], st[2] + bb[2]);
   const int rq = a.region[Q];
-  int e1 = -1, e2 = -1;
-  if (rq != k) {
-    e1 = a.EI[(int64_t)(k - 1) * g.n_nodes + Q];
-    if (rq != 0) e2 = a.EI[(int64_t)(rq - 1) * g.n_nodes + Q];
-  }
-  a.IE1[c * nbk + b] = e1;
-  a.IE2[c * nbk + b] = e2;
+  a.IE2[c * nbk + b] = (rq != k && rq != 0) ? a.EI[(int64_t)(rq - 1) * g.n_nodes + Q] : -1;
   if (b == 0) {
     a.IB[c] = (int)ravel(g, st[0], st[1], st[2]);
     const double* Mi = a.MinvT + c * (int64_t)a.nC * a.nC;
@@ -447,6 +487,57 @@ __global__ void k_fold_dof(FoldArgs a) {
         a.GI[o] = idx >= 0 ? idx : 0;
         a.GW[o] = idx >= 0 ? gsum * a.ext_w[(int64_t)sN * g.p + m] : 0.0;
       }
+    }
+  }
+}
+
+// the centre's own polynomial in its interpolation: TI[c] = sum over the
+// block nodes outside the centre's region of IW * monomials(xi_b), and its
+// fold HW with the Neumann columns of the inverse and the extension
+template <int D, int P>
+__global__ void k_fold_own(FoldArgs a) {
+  constexpr int NC = ncoef_t<D, P>();
+  constexpr int Q1 = P + 1;
+  constexpr int NBK = D == 3 ? Q1 * Q1 * Q1 : Q1 * Q1;
+  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= a.n_dof) return;
+  const GridDesc& g = a.g;
+  const int s = a.d2s[c];
+  const int k = a.meta[(int64_t)s * 5 + 3];
+  const double* P0 = a.spos + (int64_t)s * D;
+  const int64_t base = a.IB[c];
+  int st[3] = {0, 0, 0};
+  unravel(g, base, st);
+  double T[NC];
+#pragma unroll
+  for (int al = 0; al < NC; ++al) T[al] = 0.0;
+  for (int b = 0; b < NBK; ++b) {
+    const int bb[3] = {b % Q1, (b / Q1) % Q1, b / (Q1 * Q1)};
+    const int64_t Q = ravel(g, st[0] + bb[0], st[1] + bb[1], st[2] + bb[2]);
+    if (a.region[Q] == k) continue;
+    double xi[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) xi[ax] = ((g.lo + (double)(st[ax] + bb[ax]) * g.h) - P0[ax]) / g.h;
+    double phi[NC];
+    monomials<D, P>(xi, phi);
+    const double w = a.IW[c * NBK + b];
+#pragma unroll
+    for (int al = 0; al < NC; ++al) T[al] += w * phi[al];
+  }
+#pragma unroll
+  for (int al = 0; al < NC; ++al) a.TI[c * NC + al] = T[al];
+  const double* Mi = a.MinvT + c * (int64_t)NC * NC;
+  for (int j = 0; j < a.nN; ++j) {
+    const double* col = Mi + (int64_t)(a.nP + a.nD + j) * NC;
+    double sacc = 0.0;
+#pragma unroll
+    for (int al = 0; al < NC; ++al) sacc += T[al] * col[al];
+    const double rn = g.h * sacc;
+    const int sN = a.stN[c * a.nN + j];
+#pragma unroll
+    for (int m = 0; m < P; ++m) {
+      const int idx = a.ext_idx[(int64_t)sN * P + m];
+      a.HW[c * a.nF + (int64_t)j * P + m] = idx >= 0 ? rn * a.ext_w[(int64_t)sN * P + m] : 0.0;
     }
   }
 }
@@ -523,8 +614,8 @@ struct InterpArgs {
   const int *d2s, *meta, *IB;
   const double *IW, *U, *snrm, *v, *Cg;
   // folded matvec path (U == null)
-  const int *IE1, *IE2, *GI;
-  const double *Cv, *GW, *psi;
+  const int *IE2, *GI;
+  const double *Cv, *GW, *HW, *TI, *psi;
   const int8_t* region;
   double *dn_in, *dn_out, *Apsi;
 };
@@ -554,17 +645,24 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_interp(InterpArgs a) {
     double vt = a.v[Q];
     if (a.U) {
       int rq = a.region[Q];
-      if (rq != k) vt += Cval(a.Cg, g.n_nodes, k, Q) - Cval(a.Cg, g.n_nodes, rq, Q);
+      if (rq != k && rq != 0) vt -= Cval(a.Cg, g.n_nodes, rq, Q);
     } else {
-      const int e1 = a.IE1[c * a.nbk + b], e2 = a.IE2[c * a.nbk + b];
-      if (e1 >= 0) vt += a.Cv[e1];
+      const int e2 = a.IE2[c * a.nbk + b];
       if (e2 >= 0) vt -= a.Cv[e2];
     }
     acc += w[b] * vt;
   }
+  // the centre's own polynomial at the block nodes outside its region
   double dnC = 0.0;
-  if (!a.U)
-    for (int q = lane; q < a.nF; q += G) dnC += a.GW[c * a.nF + q] * a.psi[a.GI[c * a.nF + q]];
+  if (!a.U) {
+    for (int q = lane; q < a.nF; q += G) {
+      const double ps = a.psi[a.GI[c * a.nF + q]];
+      dnC += a.GW[c * a.nF + q] * ps;
+      acc += a.HW[c * a.nF + q] * ps;
+    }
+  } else {
+    for (int al = lane; al < a.nC; al += G) acc += a.TI[c * a.nC + al] * a.U[c * (int64_t)a.nC + al];
+  }
   for (int off = G / 2; off > 0; off >>= 1) {
     acc += __shfl_xor(acc, off, G);
     dnC += __shfl_xor(dnC, off, G);
@@ -591,8 +689,10 @@ void op_extend(kfbi_plan* pl, const double* psi, double* psiS) {
 }
 
 void op_coefficients(kfbi_plan* pl, const double* a, const double* b, const double* ftilde) {
-  CoefArgs A{pl->n_dof, pl->nC, pl->nP, pl->nD, pl->nN, pl->g.h, pl->MinvT, a, b, ftilde, pl->stD, pl->stN, pl->U};
-  hipLaunchKernelGGL(k_coef, dim3(nb(pl->n_dof * pl->nC)), dim3(KFBI_BLOCK), 0, pl->stream, A);
+  CoefArgs A{pl->n_dof, pl->nC, pl->nP, pl->nD, pl->nN, pl->g.h, pl->MinvT, pl->MT, a, b, ftilde, pl->stD,
+             pl->stN, pl->U};
+  unsigned blocks = (unsigned)((pl->n_dof + COEF_WAVES - 1) / COEF_WAVES);
+  hipLaunchKernelGGL(k_coef, dim3(blocks), dim3(KFBI_BLOCK), 0, pl->stream, A);
 }
 
 void op_correction_values(kfbi_plan* pl) {
@@ -638,11 +738,12 @@ void launch_interp(kfbi_plan* pl, const double* v, const double* U, const double
   A.snrm = pl->s_nrm;
   A.v = v;
   A.Cg = pl->Cg;
-  A.IE1 = pl->IE1;
   A.IE2 = pl->IE2;
   A.GI = pl->GI;
   A.Cv = pl->Cv;
   A.GW = pl->GW;
+  A.HW = pl->HW;
+  A.TI = pl->TI;
   A.psi = psi;
   A.region = pl->region;
   A.dn_in = dn_in;
@@ -693,8 +794,9 @@ kfbi_status op_fold(kfbi_plan* pl) {
     pl->cap_fold_dof = 0;
     KCHK(regrow(&pl->GI, cap * pl->nF));
     KCHK(regrow(&pl->GW, cap * pl->nF));
+    KCHK(regrow(&pl->HW, cap * pl->nF));
+    KCHK(regrow(&pl->TI, cap * pl->nC));
     KCHK(regrow(&pl->IW, cap * nbk));
-    KCHK(regrow(&pl->IE1, cap * nbk));
     KCHK(regrow(&pl->IE2, cap * nbk));
     KCHK(regrow(&pl->IB, cap));
     pl->cap_fold_dof = cap;
@@ -743,13 +845,14 @@ kfbi_status op_fold(kfbi_plan* pl) {
   A.FI = pl->FI;
   A.GI = pl->GI;
   A.IB = pl->IB;
-  A.IE1 = pl->IE1;
   A.IE2 = pl->IE2;
   A.PE1 = pl->PE1;
   A.PE2 = pl->PE2;
   A.FW = pl->FW;
   A.GW = pl->GW;
+  A.HW = pl->HW;
   A.IW = pl->IW;
+  A.TI = pl->TI;
   A.PA = pl->PA;
   A.S = make_stencil(g);
   if (pl->n_corr > 0) {
@@ -760,6 +863,13 @@ kfbi_status op_fold(kfbi_plan* pl) {
     if (g.d == 3 && g.p == 4) hipLaunchKernelGGL((k_fold_corr<3, 4>), gr, bl, 0, pl->stream, A);
   }
   hipLaunchKernelGGL(k_fold_dof, dim3(nb(pl->n_dof * nbk)), dim3(KFBI_BLOCK), 0, pl->stream, A);
+  {
+    dim3 gr(nb(pl->n_dof)), bl(KFBI_BLOCK);
+    if (g.d == 2 && g.p == 2) hipLaunchKernelGGL((k_fold_own<2, 2>), gr, bl, 0, pl->stream, A);
+    if (g.d == 2 && g.p == 4) hipLaunchKernelGGL((k_fold_own<2, 4>), gr, bl, 0, pl->stream, A);
+    if (g.d == 3 && g.p == 2) hipLaunchKernelGGL((k_fold_own<3, 2>), gr, bl, 0, pl->stream, A);
+    if (g.d == 3 && g.p == 4) hipLaunchKernelGGL((k_fold_own<3, 4>), gr, bl, 0, pl->stream, A);
+  }
   if (pl->n_irr > 0) {
     hipLaunchKernelGGL(k_fold_pairs, dim3(nb(pl->n_irr)), dim3(KFBI_BLOCK), 0, pl->stream, A);
     hipLaunchKernelGGL(k_irr_rows, dim3(nb(pl->n_irr)), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_irr, g.n1, pl->irr,
