@@ -187,10 +187,32 @@ enum {
 };
 kfbi_status kfbi_plan_export(const kfbi_plan* plan, int which, void* dst, int64_t bytes);
 
+/* Box solver of the plan (Alg. 1 Step 3.3; the paper uses the FFT):
+ *   KFBI_BOX_FFT   exact solve by the type-I sine transform (default);
+ *   KFBI_BOX_MG64  multigrid: FP64 V(2,2) cycles (damped Jacobi, full
+ *                  weighting, linear interpolation, rediscretised coarse
+ *                  operators) inside FP64 defect correction;
+ *   KFBI_BOX_MG32  the same V-cycles in FP32 inside the FP64 defect
+ *                  correction (residual r = F - A_h v always in FP64).
+ * The multigrid loop stops when |F - A_h v|_2 <= eps_in |F|_2 or after
+ * max_cycles corrections (1..64).  Every later box solve, simple solve,
+ * matvec and solve of the plan uses this solver; a re-setup keeps it.
+ * Allocates the level arrays (about (2^d/(2^d-1)) 3 n_nodes values) on
+ * the first multigrid request.  Returns KFBI_E_INVALID for an unknown
+ * solver, eps_in <= 0 or max_cycles out of range. */
+enum { KFBI_BOX_FFT = 0, KFBI_BOX_MG64 = 1, KFBI_BOX_MG32 = 2 };
+kfbi_status kfbi_plan_set_box_solver(kfbi_plan* plan, int solver, double eps_in, int max_cycles);
+
+/* Corrections used by, and relative residual |F - A_h v| / |F| reached in,
+ * the last multigrid box solve of the plan (synchronises the plan's
+ * stream).  For the FFT solver both are 0. */
+kfbi_status kfbi_plan_box_stats(kfbi_plan* plan, int32_t* cycles, double* rel_res);
+
 /* Box solve alone (step S3; Alg. 1 Step 3.3): A_h v = F on the interior
- * nodes with v = 0 on the box boundary, A_h the plan's scheme, exactly by
- * the type-I sine transform.  F, v: [n_nodes] (interior of F read; all of v
- * written).  F and v may not alias. */
+ * nodes with v = 0 on the box boundary, A_h the plan's scheme, by the
+ * plan's box solver (exact with the FFT; to eps_in with multigrid).
+ * F, v: [n_nodes] (interior of F read; all of v written).  F and v may not
+ * alias. */
 kfbi_status kfbi_box_solve(kfbi_plan* plan, const double* F, double* v);
 
 /* One simple interface problem (eq. con-ifp with box data; Secs. 4, 5):

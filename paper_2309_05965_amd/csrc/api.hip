@@ -110,6 +110,13 @@ void free_plan(kfbi_plan* pl) {
   dfree(pl->ext_w);
   dfree(pl->MinvT);
   dfree(pl->MT);
+  if (pl->mg_u) (void)hipFree(pl->mg_u);
+  if (pl->mg_t) (void)hipFree(pl->mg_t);
+  if (pl->mg_f) (void)hipFree(pl->mg_f);
+  dfree(pl->mg_part);
+  dfree(pl->mg_ctl);
+  dfree(pl->mg_scal);
+  dfree(pl->Fmg);
   dfree(pl->cond);
   dfree(pl->psiS);
   dfree(pl->aS);
@@ -254,6 +261,7 @@ kfbi_status run_setup(kfbi_plan* pl) {
   // matvec grid solution is zero on the box boundary
   HIPCHK(hipMemsetAsync(pl->Fm, 0, sizeof(double) * pl->g.n_nodes, pl->stream));
   HIPCHK(hipMemsetAsync(pl->vbuf, 0, sizeof(double) * pl->g.n_nodes, pl->stream));
+  if (pl->Fmg) HIPCHK(hipMemsetAsync(pl->Fmg, 0, sizeof(double) * pl->g.n_nodes, pl->stream));
   HIPCHK(hipStreamSynchronize(pl->stream));
   pl->ready = true;
   return KFBI_OK;
@@ -281,13 +289,20 @@ kfbi_status ensure_gmres(kfbi_plan* pl, int m) {
   return KFBI_OK;
 }
 
+void box_solve_any(kfbi_plan* pl, const double* F, double* v) {
+  if (pl->box_solver == KFBI_BOX_FFT)
+    dst_solve(pl, F, v);
+  else
+    mg_solve(pl, F, v);
+}
+
 void simple_solve_impl(kfbi_plan* pl, const double* a, const double* b, const double* ftilde,
                        const double* fhat, const double* gB, double* v, double* dn_in, double* dn_out) {
   op_coefficients(pl, a, b, ftilde);
   op_correction_values(pl);
   op_rhs_base(pl, fhat, gB, pl->Fs);
   op_rhs_correct(pl, pl->Fs, false);
-  dst_solve(pl, pl->Fs, v);
+  box_solve_any(pl, pl->Fs, v);
   op_boundary(pl, gB, v);
   op_normal_derivatives(pl, v, dn_in, dn_out, nullptr);
 }
@@ -312,12 +327,12 @@ kfbi_status ensure_graph(kfbi_plan* pl) {
   memcpy(&bi, &pl->g.beta_in, 8);
   memcpy(&bo, &pl->g.beta_out, 8);
   memcpy(&ka, &pl->g.kappa, 8);
-  uint64_t key[20] = {bi, bo, ka, 0,(uint64_t)pl->n_dof, (uint64_t)pl->n_surf, (uint64_t)pl->n_corr, (uint64_t)pl->n_irr,
+  uint64_t key[20] = {bi, bo, ka, (uint64_t)pl->box_solver * 1000003u + (uint64_t)pl->mg_maxit,(uint64_t)pl->n_dof, (uint64_t)pl->n_surf, (uint64_t)pl->n_corr, (uint64_t)pl->n_irr,
                       (uint64_t)(uintptr_t)pl->V, (uint64_t)(uintptr_t)pl->psiS, (uint64_t)(uintptr_t)pl->Cg,
                       (uint64_t)(uintptr_t)pl->FI, (uint64_t)(uintptr_t)pl->IW, (uint64_t)(uintptr_t)pl->stN,
                       (uint64_t)(uintptr_t)pl->ext_idx, (uint64_t)(uintptr_t)pl->irr,
                       (uint64_t)(uintptr_t)pl->ce_node, (uint64_t)pl->gm_cap, (uint64_t)(uintptr_t)pl->d2s,
-                      (uint64_t)(uintptr_t)pl->PA ^ (uint64_t)(uintptr_t)pl->GI};
+                      (uint64_t)(uintptr_t)pl->PA ^ (uint64_t)(uintptr_t)pl->GI ^ (uint64_t)(uintptr_t)pl->mg_u};
   if (pl->graph_exec && pl->graph4_exec && memcmp(key, pl->graph_key, sizeof(key)) == 0) return KFBI_OK;
   destroy_graphs(pl);
   for (int v = 0; v < 2; ++v) {
@@ -554,9 +569,41 @@ extern "C" kfbi_status kfbi_box_solve(kfbi_plan* pl, const double* F, double* v)
     kfbi_set_error("box solve needs distinct F and v");
     return KFBI_E_INVALID;
   }
-  dst_solve(pl, F, v);
+  box_solve_any(pl, F, v);
   op_boundary(pl, nullptr, v);
   HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_plan_set_box_solver(kfbi_plan* pl, int solver, double eps_in, int max_cycles) {
+  KCHK(need_ready(pl));
+  if (solver != KFBI_BOX_FFT && solver != KFBI_BOX_MG64 && solver != KFBI_BOX_MG32) {
+    kfbi_set_error("unknown box solver %d", solver);
+    return KFBI_E_INVALID;
+  }
+  if (!(eps_in > 0.0) || max_cycles < 1 || max_cycles > 64) {
+    kfbi_set_error("box solver needs eps_in > 0 and 1 <= max_cycles <= 64");
+    return KFBI_E_INVALID;
+  }
+  destroy_graphs(pl);
+  return mg_configure(pl, solver, eps_in, max_cycles);
+}
+
+extern "C" kfbi_status kfbi_plan_box_stats(kfbi_plan* pl, int32_t* cycles, double* rel_res) {
+  KCHK(need_ready(pl));
+  int c = 0;
+  double r = 0.0;
+  if (pl->box_solver != KFBI_BOX_FFT) {
+    int h[2];
+    double sc[2];
+    HIPCHK(hipStreamSynchronize(pl->stream));
+    HIPCHK(hipMemcpy(h, pl->mg_ctl, sizeof(h), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpy(sc, pl->mg_scal, sizeof(sc), hipMemcpyDeviceToHost));
+    c = h[1];
+    r = sc[1];
+  }
+  if (cycles) *cycles = c;
+  if (rel_res) *rel_res = r;
   return KFBI_OK;
 }
 

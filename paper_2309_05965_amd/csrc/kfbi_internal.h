@@ -16,6 +16,7 @@
 #define KFBI_MAXD 15       // max Dirichlet points
 #define KFBI_MAXN 10       // max Neumann points
 #define KFBI_GMRES_MAX 512
+#define KFBI_MG_MAXL 12    // multigrid levels (N <= 2048)
 
 // device-side status bits (OR-ed into plan->d_flags)
 enum {
@@ -109,6 +110,21 @@ struct kfbi_plan {
   int *EI;                       // [K][n_nodes] entry index of (interface, node), -1 if none
   int *row_start, *row_end;      // irregular nodes of every x-line
   int64_t cap_fold_corr, cap_fold_dof, cap_fold_irr;
+  // box solver: FFT, or multigrid V-cycles (FP64 or FP32) inside FP64
+  // defect correction to |F - A v| <= mg_eps |F|, at most mg_maxit cycles
+  int box_solver;
+  double mg_eps;
+  int mg_maxit;
+  int mg_L, mg_lc;               // levels; first level run in LDS
+  int64_t mg_off[KFBI_MG_MAXL];  // element offset of each level
+  double mg_c[KFBI_MG_MAXL][27]; // A_l on the 3^d cube
+  double mg_w[KFBI_MG_MAXL];     // Jacobi weights
+  void *mg_u, *mg_t, *mg_f;      // level arrays (float or double), boundaries zero
+  int64_t mg_bytes;
+  double* mg_part;               // partial sums of the outer residual
+  int* mg_ctl;                   // [done, corrections]
+  double* mg_scal;               // [|F|, last relative residual]
+  double* Fmg;                   // matvec right-hand side (full grid), zero off the irregular nodes
   // GMRES iteration on the device: control word [j, done, k, max_iter] and a
   // captured graph of one iteration (matvec + Arnoldi step)
   int* ctl;
@@ -163,6 +179,9 @@ void op_bie_rhs(kfbi_plan* pl, const double* g2, const double* dn_in, const doub
 // dst.hip (step S3)
 kfbi_status dst_init(kfbi_plan* pl);
 void dst_solve(kfbi_plan* pl, const double* F, double* v);
+kfbi_status mg_configure(kfbi_plan* pl, int solver, double eps, int maxit);
+void mg_solve(kfbi_plan* pl, const double* F, double* v);
+void mg_matvec_rhs(kfbi_plan* pl);
 void dst_solve_corrections(kfbi_plan* pl, const double* psi, double* v);
 // gmres.hip (step S6)
 void gm_residual_start(kfbi_plan* pl, const double* b, const double* Ax0, int use_x0, double tol, int maxit);

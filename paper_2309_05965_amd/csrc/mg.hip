@@ -1,0 +1,633 @@
+// Step S3 / S8 -- multigrid box solver: V-cycles in FP32 (or FP64) inside an
+// FP64 defect-correction loop.
+//
+// The box solve of Alg. 1 Step 3.3 is A_h v = F on the interior nodes with
+// v = 0 on the box boundary.  The paper uses the FFT; this module is the
+// multigrid alternative for the same system:
+//   levels       N_l = N / 2^l down to 2, the compact operator rediscretised
+//                with h_l = 2^l h (same reduced kappa);
+//   smoother     damped Jacobi u <- u + (omega_l / a_l)(f - A_l u), a_l the
+//                central coefficient, omega_l = 2 / (rho_lo + rho_hi) over the
+//                high-frequency range of the symbol lambda(theta) / a_l;
+//   transfers    full weighting (1/4, 1/2, 1/4)^d and (bi/tri)linear
+//                interpolation;
+//   coarsest     one interior node, solved exactly;
+//   cycle        V(2, 2) from a zero initial guess.
+// Defect correction: r = F - A_h v in FP64, then one V-cycle on (T) r in the
+// inner precision T, v <- v + e, until |r|_2 <= eps |F|_2 or max_cycles
+// corrections.  All grids carry their boundary (zero) so every stencil
+// access is in bounds without branches.  Coarse levels with N_l <= 32 (2D)
+// or 8 (3D) run inside one workgroup in LDS.  Every kernel reads a device
+// control word and returns at once when the loop has converged, so the
+// whole schedule can be captured in a graph; it also honours the GMRES
+// control word when it runs inside a captured GMRES iteration.
+#include <math.h>
+
+#include <vector>
+
+#include "kfbi_internal.h"
+
+namespace {
+
+constexpr int MG_BLOCK = 256;
+constexpr int MG_PART = 1024;            // partial sums of the outer residual
+constexpr int LDS_BLOCK = 1024;          // threads of the in-LDS coarse cycle
+
+template <typename T>
+struct Lev {
+  int N, n1, d;
+  int64_t off;       // element offset of this level in the level arrays
+  T c[27];           // A_l on the 3^d cube, index (o0+1) + 3 (o1+1) + 9 (o2+1)
+  T coef;            // omega_l / a_l
+  T inva;            // 1 / a_l
+};
+
+template <typename T>
+struct Hier {
+  int L, lc, d;      // levels; first level handled in LDS
+  Lev<T> lv[KFBI_MG_MAXL];
+};
+
+struct Ctl {
+  const int* gctl;   // GMRES control word (captured iteration) or null
+  int* mctl;         // [done, corrections done]
+};
+
+__device__ __forceinline__ bool skip(const Ctl& c) { return (c.gctl && c.gctl[1]) || c.mctl[0]; }
+
+__device__ __forceinline__ int64_t node_of(int d, int n1, int64_t t, int N) {
+  const int m = N - 1;
+  int i = (int)(t % m) + 1;
+  int64_t r = t / m;
+  if (d == 2) return i + (int64_t)n1 * (r + 1);
+  int j = (int)(r % m) + 1;
+  int k = (int)(r / m) + 1;
+  return i + (int64_t)n1 * (j + (int64_t)n1 * k);
+}
+
+template <typename T, typename S>
+__device__ __forceinline__ S apply_A(const S* c, int d, int n1, const T* u, int64_t idx) {
+  S s = 0;
+  const int zr = d == 3 ? 1 : 0;
+  for (int o2 = -zr; o2 <= zr; ++o2)
+    for (int o1 = -1; o1 <= 1; ++o1)
+      for (int o0 = -1; o0 <= 1; ++o0) {
+        const S cf = c[(o0 + 1) + 3 * (o1 + 1) + 9 * (o2 + 1)];
+        if (cf != (S)0) s += cf * (S)u[idx + o0 + (int64_t)n1 * (o1 + (int64_t)n1 * o2)];
+      }
+  return s;
+}
+
+// per-node operations shared by the global-memory and the in-LDS cycle
+template <typename T>
+__device__ __forceinline__ void op_smooth(const Lev<T>& L, const T* uin, const T* f, T* uout, int64_t idx) {
+  if (uin)
+    uout[idx] = uin[idx] + L.coef * (f[idx] - apply_A<T, T>(L.c, L.d, L.n1, uin, idx));
+  else
+    uout[idx] = L.coef * f[idx];
+}
+
+template <typename T>
+__device__ __forceinline__ void op_resid(const Lev<T>& L, const T* u, const T* f, T* r, int64_t idx) {
+  r[idx] = f[idx] - apply_A<T, T>(L.c, L.d, L.n1, u, idx);
+}
+
+// coarse value at coarse interior node I from the fine residual r
+template <typename T>
+__device__ __forceinline__ T op_restrict(int d, int n1f, const T* r, int I0, int I1, int I2) {
+  const T w1[3] = {(T)0.25, (T)0.5, (T)0.25};
+  const int zr = d == 3 ? 1 : 0;
+  T s = 0;
+  for (int o2 = -zr; o2 <= zr; ++o2)
+    for (int o1 = -1; o1 <= 1; ++o1)
+      for (int o0 = -1; o0 <= 1; ++o0) {
+        T w = w1[o0 + 1] * w1[o1 + 1];
+        if (d == 3) w *= w1[o2 + 1];
+        const int64_t fi = (2 * I0 + o0) + (int64_t)n1f * ((2 * I1 + o1) + (int64_t)n1f * (d == 3 ? 2 * I2 + o2 : 0));
+        s += w * r[fi];
+      }
+  return s;
+}
+
+// (bi/tri)linear interpolation of the coarse grid at fine node (i0,i1,i2)
+template <typename T>
+__device__ __forceinline__ T op_prolong(int d, int n1c, const T* e, int i0, int i1, int i2) {
+  const int p0 = i0 & 1, p1 = i1 & 1, p2 = d == 3 ? (i2 & 1) : 0;
+  const int I0 = i0 >> 1, I1 = i1 >> 1, I2 = d == 3 ? (i2 >> 1) : 0;
+  T s = 0;
+  int cnt = 0;
+  for (int c2 = 0; c2 <= p2; ++c2)
+    for (int c1 = 0; c1 <= p1; ++c1)
+      for (int c0 = 0; c0 <= p0; ++c0) {
+        s += e[(I0 + c0) + (int64_t)n1c * ((I1 + c1) + (int64_t)n1c * (I2 + c2))];
+        ++cnt;
+      }
+  return s / (T)cnt;
+}
+
+__device__ __forceinline__ void coords(int d, int n1, int64_t idx, int& i0, int& i1, int& i2) {
+  i0 = (int)(idx % n1);
+  int64_t r = idx / n1;
+  if (d == 2) {
+    i1 = (int)r;
+    i2 = 0;
+  } else {
+    i1 = (int)(r % n1);
+    i2 = (int)(r / n1);
+  }
+}
+
+// ---------------------------------------------------------------- global kernels
+template <typename T>
+__global__ void __launch_bounds__(MG_BLOCK) k_smooth(Ctl ctl, Lev<T> L, const T* uin, const T* f, T* uout) {
+  if (skip(ctl)) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t m = L.d == 3 ? (int64_t)(L.N - 1) * (L.N - 1) * (L.N - 1) : (int64_t)(L.N - 1) * (L.N - 1);
+  if (t >= m) return;
+  op_smooth(L, uin ? uin + L.off : nullptr, f + L.off, uout + L.off, node_of(L.d, L.n1, t, L.N));
+}
+
+template <typename T>
+__global__ void __launch_bounds__(MG_BLOCK) k_resid(Ctl ctl, Lev<T> L, const T* u, const T* f, T* r) {
+  if (skip(ctl)) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t m = L.d == 3 ? (int64_t)(L.N - 1) * (L.N - 1) * (L.N - 1) : (int64_t)(L.N - 1) * (L.N - 1);
+  if (t >= m) return;
+  op_resid(L, u + L.off, f + L.off, r + L.off, node_of(L.d, L.n1, t, L.N));
+}
+
+// coarse right-hand side f_c = R r_f (coarse level C, fine level Fl)
+template <typename T>
+__global__ void __launch_bounds__(MG_BLOCK) k_restrict(Ctl ctl, Lev<T> Fl, Lev<T> C, const T* r, T* f) {
+  if (skip(ctl)) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t m = C.d == 3 ? (int64_t)(C.N - 1) * (C.N - 1) * (C.N - 1) : (int64_t)(C.N - 1) * (C.N - 1);
+  if (t >= m) return;
+  const int64_t idx = node_of(C.d, C.n1, t, C.N);
+  int I0, I1, I2;
+  coords(C.d, C.n1, idx, I0, I1, I2);
+  f[C.off + idx] = op_restrict<T>(C.d, Fl.n1, r + Fl.off, I0, I1, I2);
+}
+
+// u_f += P e_c at the fine interior
+template <typename T>
+__global__ void __launch_bounds__(MG_BLOCK) k_prolong(Ctl ctl, Lev<T> Fl, Lev<T> C, const T* e, T* u) {
+  if (skip(ctl)) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t m = Fl.d == 3 ? (int64_t)(Fl.N - 1) * (Fl.N - 1) * (Fl.N - 1) : (int64_t)(Fl.N - 1) * (Fl.N - 1);
+  if (t >= m) return;
+  const int64_t idx = node_of(Fl.d, Fl.n1, t, Fl.N);
+  int i0, i1, i2;
+  coords(Fl.d, Fl.n1, idx, i0, i1, i2);
+  u[Fl.off + idx] += op_prolong<T>(Fl.d, C.n1, e + C.off, i0, i1, i2);
+}
+
+// levels lc .. L-1 of one V(2,2) cycle in LDS, one workgroup: f_lc in, u_lc out
+template <typename T>
+__global__ void __launch_bounds__(LDS_BLOCK) k_coarse_cycle(Ctl ctl, Hier<T> H, const T* fg, T* ug) {
+  if (skip(ctl)) return;
+  extern __shared__ unsigned char smem[];
+  T* base = reinterpret_cast<T*>(smem);
+  // per level three arrays u, t, f of (N_l+1)^d, packed level after level
+  int64_t loff[KFBI_MG_MAXL];
+  int64_t tot = 0;
+  for (int l = H.lc; l < H.L; ++l) {
+    const int64_t n = H.d == 3 ? (int64_t)H.lv[l].n1 * H.lv[l].n1 * H.lv[l].n1 : (int64_t)H.lv[l].n1 * H.lv[l].n1;
+    loff[l] = tot;
+    tot += 3 * n;
+  }
+  for (int64_t i = threadIdx.x; i < tot; i += blockDim.x) base[i] = (T)0;
+  __syncthreads();
+  {
+    const Lev<T>& L = H.lv[H.lc];
+    const int64_t n = H.d == 3 ? (int64_t)L.n1 * L.n1 * L.n1 : (int64_t)L.n1 * L.n1;
+    T* f = base + loff[H.lc] + 2 * n;
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) f[i] = fg[L.off + i];
+  }
+  __syncthreads();
+  auto arr = [&](int l, int which) -> T* {
+    const Lev<T>& L = H.lv[l];
+    const int64_t n = H.d == 3 ? (int64_t)L.n1 * L.n1 * L.n1 : (int64_t)L.n1 * L.n1;
+    return base + loff[l] + which * n;
+  };
+  auto interior = [&](int l) -> int64_t {
+    const int m = H.lv[l].N - 1;
+    return H.d == 3 ? (int64_t)m * m * m : (int64_t)m * m;
+  };
+  // descend
+  for (int l = H.lc; l < H.L; ++l) {
+    const Lev<T>& L = H.lv[l];
+    T *u = arr(l, 0), *tb = arr(l, 1), *f = arr(l, 2);
+    const int64_t m = interior(l);
+    if (L.N == 2) {
+      for (int64_t t = threadIdx.x; t < m; t += blockDim.x) {
+        const int64_t idx = node_of(H.d, L.n1, t, L.N);
+        u[idx] = f[idx] * L.inva;
+      }
+      __syncthreads();
+      break;
+    }
+    for (int64_t t = threadIdx.x; t < m; t += blockDim.x) op_smooth<T>(L, nullptr, f, tb, node_of(H.d, L.n1, t, L.N));
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < m; t += blockDim.x) op_smooth<T>(L, tb, f, u, node_of(H.d, L.n1, t, L.N));
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < m; t += blockDim.x) op_resid<T>(L, u, f, tb, node_of(H.d, L.n1, t, L.N));
+    __syncthreads();
+    const Lev<T>& C = H.lv[l + 1];
+    T* fc = arr(l + 1, 2);
+    const int64_t mc = interior(l + 1);
+    for (int64_t t = threadIdx.x; t < mc; t += blockDim.x) {
+      const int64_t idx = node_of(H.d, C.n1, t, C.N);
+      int I0, I1, I2;
+      coords(H.d, C.n1, idx, I0, I1, I2);
+      fc[idx] = op_restrict<T>(H.d, L.n1, tb, I0, I1, I2);
+    }
+    __syncthreads();
+  }
+  // ascend
+  for (int l = H.L - 2; l >= H.lc; --l) {
+    const Lev<T>& L = H.lv[l];
+    const Lev<T>& C = H.lv[l + 1];
+    T *u = arr(l, 0), *tb = arr(l, 1), *f = arr(l, 2);
+    const T* ec = arr(l + 1, 0);
+    const int64_t m = interior(l);
+    for (int64_t t = threadIdx.x; t < m; t += blockDim.x) {
+      const int64_t idx = node_of(H.d, L.n1, t, L.N);
+      int i0, i1, i2;
+      coords(H.d, L.n1, idx, i0, i1, i2);
+      u[idx] += op_prolong<T>(H.d, C.n1, ec, i0, i1, i2);
+    }
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < m; t += blockDim.x) op_smooth<T>(L, u, f, tb, node_of(H.d, L.n1, t, L.N));
+    __syncthreads();
+    for (int64_t t = threadIdx.x; t < m; t += blockDim.x) op_smooth<T>(L, tb, f, u, node_of(H.d, L.n1, t, L.N));
+    __syncthreads();
+  }
+  {
+    const Lev<T>& L = H.lv[H.lc];
+    const int64_t n = H.d == 3 ? (int64_t)L.n1 * L.n1 * L.n1 : (int64_t)L.n1 * L.n1;
+    const T* u = arr(H.lc, 0);
+    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) ug[L.off + i] = u[i];
+  }
+}
+
+// ---------------------------------------------------------------- FP64 outer loop
+struct OuterArgs {
+  Ctl ctl;
+  int d, N, n1;
+  double c[27];
+  const double* F;
+  double* v;
+  int first;          // v = 0 (written here): r = F, and |F| is accumulated too
+  double* part;       // [2][MG_PART]
+};
+
+// r = F - A_h v (FP64) -> f_0 = (T) r; per-block sums of r^2 (and F^2)
+template <typename T>
+__global__ void __launch_bounds__(MG_BLOCK) k_outer_resid(OuterArgs a, T* f0) {
+  __shared__ double sr[MG_BLOCK], sf[MG_BLOCK];
+  double acc_r = 0.0, acc_f = 0.0;
+  if (!skip(a.ctl)) {
+    const int64_t m = a.d == 3 ? (int64_t)(a.N - 1) * (a.N - 1) * (a.N - 1) : (int64_t)(a.N - 1) * (a.N - 1);
+    for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+      const int64_t idx = node_of(a.d, a.n1, t, a.N);
+      const double Fv = a.F[idx];
+      double r;
+      if (a.first) {
+        r = Fv;
+        a.v[idx] = 0.0;
+      } else {
+        r = Fv - apply_A<double, double>(a.c, a.d, a.n1, a.v, idx);
+      }
+      f0[idx] = (T)r;
+      acc_r += r * r;
+      acc_f += Fv * Fv;
+    }
+  }
+  sr[threadIdx.x] = acc_r;
+  sf[threadIdx.x] = acc_f;
+  __syncthreads();
+  for (int o = MG_BLOCK / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < (unsigned)o) {
+      sr[threadIdx.x] += sr[threadIdx.x + o];
+      sf[threadIdx.x] += sf[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    a.part[blockIdx.x] = sr[0];
+    a.part[MG_PART + blockIdx.x] = sf[0];
+  }
+}
+
+// stopping test: |r| <= eps |F| (|F| taken at the first correction)
+__global__ void __launch_bounds__(MG_BLOCK) k_check(Ctl ctl, const double* part, int nblk, int first, double eps,
+                                                   int maxit, double* scal) {
+  if ((ctl.gctl && ctl.gctl[1]) || ctl.mctl[0]) return;
+  __shared__ double sr[MG_BLOCK], sf[MG_BLOCK];
+  double r = 0.0, f = 0.0;
+  for (int i = threadIdx.x; i < nblk; i += MG_BLOCK) {
+    r += part[i];
+    f += part[MG_PART + i];
+  }
+  sr[threadIdx.x] = r;
+  sf[threadIdx.x] = f;
+  __syncthreads();
+  for (int o = MG_BLOCK / 2; o > 0; o >>= 1) {
+    if (threadIdx.x < (unsigned)o) {
+      sr[threadIdx.x] += sr[threadIdx.x + o];
+      sf[threadIdx.x] += sf[threadIdx.x + o];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    if (first) scal[0] = sqrt(sf[0]);
+    const double nr = sqrt(sr[0]);
+    const double nf = scal[0];
+    const double rel = nf > 0.0 ? nr / nf : 0.0;
+    scal[1] = rel;
+    if (rel <= eps || nf == 0.0 || ctl.mctl[1] >= maxit) ctl.mctl[0] = 1;
+  }
+}
+
+// v += e, interior only
+template <typename T>
+__global__ void __launch_bounds__(MG_BLOCK) k_update(Ctl ctl, int d, int N, int n1, const T* e, double* v) {
+  if (skip(ctl)) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t m = d == 3 ? (int64_t)(N - 1) * (N - 1) * (N - 1) : (int64_t)(N - 1) * (N - 1);
+  if (t >= m) return;
+  const int64_t idx = node_of(d, n1, t, N);
+  v[idx] = v[idx] + (double)e[idx];
+}
+
+// v = 0 on the box boundary (the outer residual reads v's boundary nodes;
+// the caller's buffer may hold box data there)
+__global__ void __launch_bounds__(MG_BLOCK) k_zero_boundary(Ctl ctl, int d, int n1, double* v) {
+  if (ctl.gctl && ctl.gctl[1]) return;
+  const int64_t face = d == 3 ? (int64_t)n1 * n1 : (int64_t)n1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= 2 * d * face) return;
+  const int f = (int)(t / face);          // axis f / 2, side f % 2
+  const int64_t r = t % face;
+  const int ax = f >> 1;
+  const int side = (f & 1) ? n1 - 1 : 0;
+  int c[3] = {0, 0, 0};
+  int o[2] = {(int)(r % n1), (int)(r / n1)};
+  int q = 0;
+  for (int a = 0; a < d; ++a) c[a] = a == ax ? side : o[q++];
+  v[c[0] + (int64_t)n1 * (c[1] + (int64_t)n1 * c[2])] = 0.0;
+}
+
+__global__ void k_count(Ctl ctl) {
+  if ((ctl.gctl && ctl.gctl[1]) || ctl.mctl[0]) return;
+  ctl.mctl[1] += 1;
+}
+
+__global__ void k_start(Ctl ctl) {
+  if (ctl.gctl && ctl.gctl[1]) return;
+  ctl.mctl[0] = 0;
+  ctl.mctl[1] = 0;
+}
+
+// right-hand side of the matvec: F = -sum over cut neighbours Q of
+// A_PQ (C^(reg P) - C^(reg Q))(x_Q) at the irregular nodes (the nodes are
+// fixed per plan; F is zero elsewhere)
+__global__ void __launch_bounds__(MG_BLOCK) k_scatter(const int* gctl, int64_t n_irr, int maxpairs, const int* irr,
+                                                     const double* PA, const int* PE1, const int* PE2,
+                                                     const double* Cv, double* F) {
+  if (gctl && gctl[1]) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= n_irr) return;
+  double s = 0.0;
+  for (int m = 0; m < maxpairs; ++m) {
+    const double cf = PA[t * maxpairs + m];
+    if (cf == 0.0) break;
+    const int e1 = PE1[t * maxpairs + m], e2 = PE2[t * maxpairs + m];
+    const double c1 = e1 >= 0 ? Cv[e1] : 0.0, c2 = e2 >= 0 ? Cv[e2] : 0.0;
+    s -= cf * (c1 - c2);
+  }
+  F[irr[t]] = s;
+}
+
+inline unsigned nblk(int64_t n, int b = MG_BLOCK) { return (unsigned)((n + b - 1) / b); }
+
+template <typename T>
+Hier<T> make_hier(const kfbi_plan* pl) {
+  Hier<T> H;
+  H.d = pl->g.d;
+  H.L = pl->mg_L;
+  H.lc = pl->mg_lc;
+  for (int l = 0; l < H.L; ++l) {
+    Lev<T>& L = H.lv[l];
+    L.N = pl->g.N >> l;
+    L.n1 = L.N + 1;
+    L.d = H.d;
+    L.off = pl->mg_off[l];
+    for (int i = 0; i < 27; ++i) L.c[i] = (T)pl->mg_c[l][i];
+    L.coef = (T)(pl->mg_w[l] / pl->mg_c[l][13]);   // central coefficient: offset (0,0,0)
+    L.inva = (T)(1.0 / pl->mg_c[l][13]);
+  }
+  return H;
+}
+
+template <typename T>
+size_t coarse_lds(const Hier<T>& H) {
+  size_t tot = 0;
+  for (int l = H.lc; l < H.L; ++l) {
+    const size_t n1 = (size_t)H.lv[l].n1;
+    tot += 3 * (H.d == 3 ? n1 * n1 * n1 : n1 * n1);
+  }
+  return tot * sizeof(T);
+}
+
+template <typename T>
+void vcycle(kfbi_plan* pl, const Hier<T>& H, Ctl ctl) {
+  T* u = (T*)pl->mg_u;
+  T* tb = (T*)pl->mg_t;
+  T* f = (T*)pl->mg_f;
+  hipStream_t st = pl->stream;
+  auto interior = [&](int l) -> int64_t {
+    const int64_t m = H.lv[l].N - 1;
+    return H.d == 3 ? m * m * m : m * m;
+  };
+  for (int l = 0; l < H.lc; ++l) {
+    const unsigned g = nblk(interior(l));
+    hipLaunchKernelGGL((k_smooth<T>), dim3(g), dim3(MG_BLOCK), 0, st, ctl, H.lv[l], (const T*)nullptr, f, tb);
+    hipLaunchKernelGGL((k_smooth<T>), dim3(g), dim3(MG_BLOCK), 0, st, ctl, H.lv[l], (const T*)tb, f, u);
+    hipLaunchKernelGGL((k_resid<T>), dim3(g), dim3(MG_BLOCK), 0, st, ctl, H.lv[l], (const T*)u, f, tb);
+    hipLaunchKernelGGL((k_restrict<T>), dim3(nblk(interior(l + 1))), dim3(MG_BLOCK), 0, st, ctl, H.lv[l],
+                       H.lv[l + 1], (const T*)tb, f);
+  }
+  hipLaunchKernelGGL((k_coarse_cycle<T>), dim3(1), dim3(LDS_BLOCK), coarse_lds(H), st, ctl, H, (const T*)f, u);
+  for (int l = H.lc - 1; l >= 0; --l) {
+    const unsigned g = nblk(interior(l));
+    hipLaunchKernelGGL((k_prolong<T>), dim3(g), dim3(MG_BLOCK), 0, st, ctl, H.lv[l], H.lv[l + 1], (const T*)u, u);
+    hipLaunchKernelGGL((k_smooth<T>), dim3(g), dim3(MG_BLOCK), 0, st, ctl, H.lv[l], (const T*)u, f, tb);
+    hipLaunchKernelGGL((k_smooth<T>), dim3(g), dim3(MG_BLOCK), 0, st, ctl, H.lv[l], (const T*)tb, f, u);
+  }
+}
+
+template <typename T>
+void solve_t(kfbi_plan* pl, const double* F, double* v) {
+  Hier<T> H = make_hier<T>(pl);
+  Ctl ctl{pl->ctl_active, pl->mg_ctl};
+  hipStream_t st = pl->stream;
+  const GridDesc& g = pl->g;
+  const int64_t m = g.d == 3 ? (int64_t)(g.N - 1) * (g.N - 1) * (g.N - 1) : (int64_t)(g.N - 1) * (g.N - 1);
+  unsigned gout = nblk(m);
+  if (gout > (unsigned)MG_PART) gout = MG_PART;
+  OuterArgs oa;
+  oa.ctl = ctl;
+  oa.d = g.d;
+  oa.N = g.N;
+  oa.n1 = g.n1;
+  for (int i = 0; i < 27; ++i) oa.c[i] = pl->mg_c[0][i];
+  oa.F = F;
+  oa.v = v;
+  oa.part = pl->mg_part;
+  hipLaunchKernelGGL(k_start, dim3(1), dim3(1), 0, st, ctl);
+  {
+    const int64_t nb = 2 * g.d * (g.d == 3 ? (int64_t)g.n1 * g.n1 : (int64_t)g.n1);
+    hipLaunchKernelGGL(k_zero_boundary, dim3(nblk(nb)), dim3(MG_BLOCK), 0, st, ctl, g.d, g.n1, v);
+  }
+  for (int it = 0; it < pl->mg_maxit; ++it) {
+    oa.first = it == 0 ? 1 : 0;
+    hipLaunchKernelGGL((k_outer_resid<T>), dim3(gout), dim3(MG_BLOCK), 0, st, oa, (T*)pl->mg_f);
+    hipLaunchKernelGGL(k_check, dim3(1), dim3(MG_BLOCK), 0, st, ctl, (const double*)pl->mg_part, (int)gout,
+                       oa.first, pl->mg_eps, pl->mg_maxit, pl->mg_scal);
+    vcycle<T>(pl, H, ctl);
+    hipLaunchKernelGGL((k_update<T>), dim3(nblk(m)), dim3(MG_BLOCK), 0, st, ctl, g.d, g.N, g.n1,
+                       (const T*)pl->mg_u, v);
+    hipLaunchKernelGGL(k_count, dim3(1), dim3(1), 0, st, ctl);
+  }
+  // residual of the final iterate (the stopping value reported)
+  oa.first = 0;
+  hipLaunchKernelGGL((k_outer_resid<T>), dim3(gout), dim3(MG_BLOCK), 0, st, oa, (T*)pl->mg_f);
+  hipLaunchKernelGGL(k_check, dim3(1), dim3(MG_BLOCK), 0, st, ctl, (const double*)pl->mg_part, (int)gout, 0,
+                     pl->mg_eps, pl->mg_maxit, pl->mg_scal);
+}
+
+double jacobi_weight(const double* c, int d) {
+  // range of lambda(theta)/a over the high frequencies on a 64^d sample grid
+  const int S = 64;
+  const double a = c[13];
+  double lo = 1e300, hi = -1e300;
+  const int nz = d == 3 ? S : 1;
+  for (int k2 = 1; k2 <= nz; ++k2)
+    for (int k1 = 1; k1 <= S; ++k1)
+      for (int k0 = 1; k0 <= S; ++k0) {
+        const double t0 = M_PI * k0 / S, t1 = M_PI * k1 / S, t2 = d == 3 ? M_PI * k2 / S : 0.0;
+        double tm = t0 > t1 ? t0 : t1;
+        if (d == 3 && t2 > tm) tm = t2;
+        if (tm < M_PI / 2) continue;
+        double lam = 0.0;
+        const int zr = d == 3 ? 1 : 0;
+        for (int o2 = -zr; o2 <= zr; ++o2)
+          for (int o1 = -1; o1 <= 1; ++o1)
+            for (int o0 = -1; o0 <= 1; ++o0) {
+              const double cf = c[(o0 + 1) + 3 * (o1 + 1) + 9 * (o2 + 1)];
+              if (cf != 0.0) lam += cf * cos(o0 * t0 + o1 * t1 + o2 * t2);
+            }
+        const double rho = lam / a;
+        lo = rho < lo ? rho : lo;
+        hi = rho > hi ? rho : hi;
+      }
+  return 2.0 / (lo + hi);
+}
+
+}  // namespace
+
+// stencil of A_h (operator.hip)
+void kfbi_stencil_A(const GridDesc& g, double* A27);
+
+kfbi_status mg_configure(kfbi_plan* pl, int solver, double eps, int maxit) {
+  pl->box_solver = solver;
+  pl->mg_eps = eps;
+  pl->mg_maxit = maxit;
+  if (solver == KFBI_BOX_FFT) return KFBI_OK;
+  const GridDesc& g = pl->g;
+  int L = 0;
+  for (int n = g.N; n >= 2; n >>= 1) ++L;
+  if (L > KFBI_MG_MAXL) {
+    kfbi_set_error("grid too large for the multigrid hierarchy (N = %d)", g.N);
+    return KFBI_E_INVALID;
+  }
+  pl->mg_L = L;
+  const int cut = g.d == 3 ? 8 : 32;
+  int lc = 0;
+  while (lc < L && (g.N >> lc) > cut) ++lc;
+  pl->mg_lc = lc;
+  int64_t tot = 0;
+  for (int l = 0; l < L; ++l) {
+    const int64_t n1 = (g.N >> l) + 1;
+    pl->mg_off[l] = tot;
+    tot += g.d == 3 ? n1 * n1 * n1 : n1 * n1;
+    GridDesc gl = g;
+    gl.N = g.N >> l;
+    gl.n1 = gl.N + 1;
+    gl.h = g.h * (double)(1 << l);
+    kfbi_stencil_A(gl, pl->mg_c[l]);
+    pl->mg_w[l] = jacobi_weight(pl->mg_c[l], g.d);
+  }
+  const size_t es = solver == KFBI_BOX_MG32 ? sizeof(float) : sizeof(double);
+  if (tot * (int64_t)es > pl->mg_bytes) {
+    if (pl->mg_u) (void)hipFree(pl->mg_u);
+    if (pl->mg_t) (void)hipFree(pl->mg_t);
+    if (pl->mg_f) (void)hipFree(pl->mg_f);
+    pl->mg_u = pl->mg_t = pl->mg_f = nullptr;
+    pl->mg_bytes = 0;
+    const size_t b = (size_t)tot * es;
+    if (hipMalloc(&pl->mg_u, b) != hipSuccess || hipMalloc(&pl->mg_t, b) != hipSuccess ||
+        hipMalloc(&pl->mg_f, b) != hipSuccess) {
+      (void)hipGetLastError();
+      kfbi_set_error("device allocation of the multigrid levels failed");
+      return KFBI_E_OOM;
+    }
+    pl->mg_bytes = (int64_t)b;
+  }
+  // zero boundaries once; the kernels only write interiors
+  HIPCHK(hipMemsetAsync(pl->mg_u, 0, (size_t)pl->mg_bytes, pl->stream));
+  HIPCHK(hipMemsetAsync(pl->mg_t, 0, (size_t)pl->mg_bytes, pl->stream));
+  HIPCHK(hipMemsetAsync(pl->mg_f, 0, (size_t)pl->mg_bytes, pl->stream));
+  if (!pl->mg_part) {
+    if (hipMalloc((void**)&pl->mg_part, sizeof(double) * 2 * MG_PART) != hipSuccess ||
+        hipMalloc((void**)&pl->mg_ctl, sizeof(int) * 4) != hipSuccess ||
+        hipMalloc((void**)&pl->mg_scal, sizeof(double) * 4) != hipSuccess) {
+      (void)hipGetLastError();
+      kfbi_set_error("device allocation of the multigrid control failed");
+      return KFBI_E_OOM;
+    }
+    HIPCHK(hipMemsetAsync(pl->mg_ctl, 0, sizeof(int) * 4, pl->stream));
+    HIPCHK(hipMemsetAsync(pl->mg_scal, 0, sizeof(double) * 4, pl->stream));
+  }
+  if (!pl->Fmg) {
+    if (hipMalloc((void**)&pl->Fmg, sizeof(double) * g.n_nodes) != hipSuccess) {
+      (void)hipGetLastError();
+      kfbi_set_error("device allocation of the multigrid right-hand side failed");
+      return KFBI_E_OOM;
+    }
+  }
+  HIPCHK(hipMemsetAsync(pl->Fmg, 0, sizeof(double) * g.n_nodes, pl->stream));
+  // the in-LDS coarse cycle must fit one workgroup
+  size_t lds = pl->box_solver == KFBI_BOX_MG32 ? coarse_lds(make_hier<float>(pl)) : coarse_lds(make_hier<double>(pl));
+  if (lds > 65536) {
+    kfbi_set_error("multigrid coarse levels exceed the LDS budget");
+    return KFBI_E_INVALID;
+  }
+  HIPCHK(hipStreamSynchronize(pl->stream));
+  return KFBI_OK;
+}
+
+void mg_solve(kfbi_plan* pl, const double* F, double* v) {
+  if (pl->box_solver == KFBI_BOX_MG32)
+    solve_t<float>(pl, F, v);
+  else
+    solve_t<double>(pl, F, v);
+}
+
+void mg_matvec_rhs(kfbi_plan* pl) {
+  if (pl->n_irr == 0) return;
+  hipLaunchKernelGGL(k_scatter, dim3(nblk(pl->n_irr)), dim3(MG_BLOCK), 0, pl->stream, pl->ctl_active, pl->n_irr,
+                     pl->maxpairs, pl->irr, pl->PA, pl->PE1, pl->PE2, pl->Cv, pl->Fmg);
+}

@@ -879,6 +879,11 @@ kfbi_status op_fold(kfbi_plan* pl) {
   return KFBI_OK;
 }
 
+void kfbi_stencil_A(const GridDesc& g, double* A27) {
+  Stencil S = make_stencil(g);
+  for (int i = 0; i < 27; ++i) A27[i] = S.A[i];
+}
+
 // the BIE operator (S2-S5) with the folded maps: the corrected right-hand
 // side is formed inside the first box-solve pass, the correction values
 // inside the interpolation
@@ -886,7 +891,12 @@ void op_matvec(kfbi_plan* pl, const double* psi, double* Apsi) {
   if (pl->n_corr > 0)
     hipLaunchKernelGGL(k_centry<16>, dim3(nb(pl->n_corr * 16)), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_corr,
                        pl->nF, pl->FI, pl->FW, psi, pl->Cv, pl->ctl_active, pl->V, pl->n_dof);
-  dst_solve_corrections(pl, psi, pl->vbuf);
+  if (pl->box_solver == KFBI_BOX_FFT) {
+    dst_solve_corrections(pl, psi, pl->vbuf);
+  } else {
+    mg_matvec_rhs(pl);
+    mg_solve(pl, pl->Fmg, pl->vbuf);
+  }
   launch_interp(pl, pl->vbuf, nullptr, psi, nullptr, nullptr, Apsi);
 }
 

@@ -68,6 +68,9 @@ ABI = {
     "kfbi_rhs": ([ctypes.c_void_p, ctypes.POINTER(Data), c_double_p], ctypes.c_int),
     "kfbi_solve": ([ctypes.c_void_p, ctypes.POINTER(Data), ctypes.POINTER(Opts), c_double_p, c_double_p,
                     ctypes.POINTER(Info)], ctypes.c_int),
+    "kfbi_plan_set_box_solver": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int], ctypes.c_int),
+    "kfbi_plan_box_stats": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
+                            ctypes.c_int),
     "kfbi_plan_profile": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
     "kfbi_plan_timing": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                           ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
@@ -170,6 +173,22 @@ class Plan:
             self.close()
         except Exception:
             pass
+
+    # ------------------------------------------------------------------ box solver
+    BOX_SOLVERS = {"fft": 0, "mg64": 1, "mg32": 2}
+
+    def set_box_solver(self, solver="fft", eps_in=1e-12, max_cycles=40):
+        """Box solver of every later solve: "fft" (exact), "mg64" or "mg32"
+        (multigrid V-cycles in FP64 / FP32 inside FP64 defect correction to
+        |F - A v| <= eps_in |F|)."""
+        _check(load().kfbi_plan_set_box_solver(self._h, self.BOX_SOLVERS[solver], float(eps_in), int(max_cycles)))
+        self.box_solver = solver
+
+    def box_stats(self):
+        """(corrections, relative residual) of the last multigrid box solve."""
+        c, r = ctypes.c_int32(), ctypes.c_double()
+        _check(load().kfbi_plan_box_stats(self._h, ctypes.byref(c), ctypes.byref(r)))
+        return c.value, r.value
 
     # ------------------------------------------------------------------ tracing
     def profile(self, enable=True):
