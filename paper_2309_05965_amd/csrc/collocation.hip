@@ -52,117 +52,154 @@ struct FactorArgs {
   int* flags;
 };
 
-__global__ void __launch_bounds__(64) k_factor(FactorArgs a) {
-  const int n = a.T.n;
+// row j of M (lane j) in the order [PDE | Dirichlet | Neumann], written to
+// row[0..n) (LDS)
+__device__ __forceinline__ void assemble_row(const FactorArgs& a, int64_t c, int j, double* row) {
   const int d = a.T.d;
-  const int64_t c = blockIdx.x;
-  const int lane = threadIdx.x;
-  __shared__ double A[KFBI_MAXC][2 * KFBI_MAXC + 1];
-  __shared__ double colsum[KFBI_MAXC];
-  __shared__ int piv;
   const GridDesc& g = a.g;
   const double h = g.h;
   const int s = a.d2s[c];
   const double* P = a.spos + (int64_t)s * d;
-  if (lane < n) {
-    const int j = lane;
-    double xi[3] = {0.0, 0.0, 0.0}, nv[3] = {0.0, 0.0, 0.0};
-    int kind;   // 0 PDE, 1 Dirichlet, 2 Neumann
-    if (j < a.T.nP) {
-      kind = 0;
-      for (int ax = 0; ax < d; ++ax) xi[ax] = (double)a.T.offP[j][ax];
-    } else if (j < a.T.nP + a.T.nD) {
-      kind = 1;
-      int q = a.stD[c * a.T.nD + (j - a.T.nP)];
-      for (int ax = 0; ax < d; ++ax) xi[ax] = (a.spos[(int64_t)q * d + ax] - P[ax]) / h;
-    } else {
-      kind = 2;
-      int q = a.stN[c * a.T.nN + (j - a.T.nP - a.T.nD)];
+  double xi[3] = {0.0, 0.0, 0.0}, nv[3] = {0.0, 0.0, 0.0};
+  int kind;   // 0 PDE, 1 Dirichlet, 2 Neumann
+  if (j < a.T.nP) {
+    kind = 0;
+    for (int ax = 0; ax < d; ++ax) xi[ax] = (double)a.T.offP[j][ax];
+  } else if (j < a.T.nP + a.T.nD) {
+    kind = 1;
+    int q = a.stD[c * a.T.nD + (j - a.T.nP)];
+    for (int ax = 0; ax < d; ++ax) xi[ax] = (a.spos[(int64_t)q * d + ax] - P[ax]) / h;
+  } else {
+    kind = 2;
+    int q = a.stN[c * a.T.nN + (j - a.T.nP - a.T.nD)];
+    for (int ax = 0; ax < d; ++ax) {
+      xi[ax] = (a.spos[(int64_t)q * d + ax] - P[ax]) / h;
+      nv[ax] = a.snrm[(int64_t)q * d + ax];
+    }
+  }
+  const double kh2 = g.kappa * h * h;
+  for (int al = 0; al < a.T.n; ++al) {
+    const int* e = a.T.E[al];
+    double v;
+    if (kind == 1) {
+      v = 1.0;
+      for (int ax = 0; ax < d; ++ax) v *= ipow(xi[ax], e[ax]);
+    } else if (kind == 2) {
+      v = 0.0;
       for (int ax = 0; ax < d; ++ax) {
-        xi[ax] = (a.spos[(int64_t)q * d + ax] - P[ax]) / h;
-        nv[ax] = a.snrm[(int64_t)q * d + ax];
+        if (e[ax] == 0) continue;
+        double t = (double)e[ax];
+        for (int b = 0; b < d; ++b) t *= ipow(xi[b], b == ax ? e[b] - 1 : e[b]);
+        v += nv[ax] * t;
       }
-    }
-    const double kh2 = g.kappa * h * h;
-    for (int al = 0; al < n; ++al) {
-      const int* e = a.T.E[al];
-      double v;
-      if (kind == 1) {
-        v = 1.0;
-        for (int ax = 0; ax < d; ++ax) v *= ipow(xi[ax], e[ax]);
-      } else if (kind == 2) {
-        v = 0.0;
-        for (int ax = 0; ax < d; ++ax) {
-          if (e[ax] == 0) continue;
-          double t = (double)e[ax];
-          for (int b = 0; b < d; ++b) t *= ipow(xi[b], b == ax ? e[b] - 1 : e[b]);
-          v += nv[ax] * t;
-        }
-      } else {
-        double lap = 0.0, val = 1.0;
-        for (int ax = 0; ax < d; ++ax) val *= ipow(xi[ax], e[ax]);
-        for (int ax = 0; ax < d; ++ax) {
-          if (e[ax] < 2) continue;
-          double t = (double)(e[ax] * (e[ax] - 1));
-          for (int b = 0; b < d; ++b) t *= ipow(xi[b], b == ax ? e[b] - 2 : e[b]);
-          lap += t;
-        }
-        v = lap - kh2 * val;
+    } else {
+      double lap = 0.0, val = 1.0;
+      for (int ax = 0; ax < d; ++ax) val *= ipow(xi[ax], e[ax]);
+      for (int ax = 0; ax < d; ++ax) {
+        if (e[ax] < 2) continue;
+        double t = (double)(e[ax] * (e[ax] - 1));
+        for (int b = 0; b < d; ++b) t *= ipow(xi[b], b == ax ? e[b] - 2 : e[b]);
+        lap += t;
       }
-      A[j][al] = v;
-      A[j][n + al] = al == j ? 1.0 : 0.0;
+      v = lap - kh2 * val;
     }
+    row[al] = v;
   }
+}
+
+// value of x in lane l (l uniform across the wavefront)
+__device__ __forceinline__ double lane_value(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+__device__ __forceinline__ double wave_max(double v) {
+  for (int off = 32; off > 0; off >>= 1) v = fmax(v, __shfl_xor(v, off, 64));
+  return v;
+}
+
+// One wavefront per centre, lane j holds row j of M in registers and the
+// inverse is formed in place (Gauss-Jordan).  Partial pivoting: at step k
+// the pivot is the unused row with the largest |entry| in column k (lowest
+// lane on ties); rows are not swapped.  The pivot lane scales its row
+// (column k becomes 1/pivot) and the other lanes read it lane to lane and
+// eliminate.  With p_k the pivot lane of step k, lane p_a ends up holding
+// row a of the inverse with its column j at position p_j.
+template <int NC>
+__global__ void __launch_bounds__(64) k_factor(FactorArgs a) {
+  const int64_t c = blockIdx.x;
+  const int lane = threadIdx.x;
+  const bool live = lane < NC;
+  __shared__ double Ms[NC][NC + 1];
+  __shared__ int pvt[NC];
+  __shared__ double prow[NC];
+  if (live) assemble_row(a, c, lane, Ms[lane]);
   __syncthreads();
-  {
-    double* mt = a.MT + c * (int64_t)n * n;
-    for (int idx = lane; idx < n * n; idx += 64) {
-      int al = idx / n, j = idx % n;
-      mt[idx] = A[j][al];
-    }
-  }
-  // 1-norm of M (max column sum)
-  if (lane < n) {
-    double t = 0.0;
-    for (int i = 0; i < n; ++i) t += fabs(A[i][lane]);
-    colsum[lane] = t;
-  }
-  __syncthreads();
+  // M^T (for the refinement of U) and the 1-norm of M (max column sum),
+  // both read from LDS
+  double* mt = a.MT + c * (int64_t)NC * NC;
+  for (int idx = lane; idx < NC * NC; idx += 64) mt[idx] = Ms[idx % NC][idx / NC];
   double normM = 0.0;
-  for (int i = 0; i < n; ++i) normM = fmax(normM, colsum[i]);
+  if (live)
+    for (int j = 0; j < NC; ++j) normM += fabs(Ms[j][lane]);
+  normM = wave_max(normM);
+  double row[NC];
+#pragma unroll
+  for (int al = 0; al < NC; ++al) row[al] = live ? Ms[lane][al] : 0.0;
+  bool used = !live;
+  int myk = -1;
   bool singular = false;
-  for (int k = 0; k < n; ++k) {
-    if (lane == 0) {
-      int p = k;
-      double best = fabs(A[k][k]);
-      for (int i = k + 1; i < n; ++i)
-        if (fabs(A[i][k]) > best) {
-          best = fabs(A[i][k]);
-          p = i;
-        }
-      piv = p;
-    }
-    __syncthreads();
-    int p = piv;
-    if (p != k)
-      for (int m = lane; m < 2 * n; m += 64) {
-        double t = A[k][m];
-        A[k][m] = A[p][m];
-        A[p][m] = t;
+#pragma unroll 1
+  for (int k = 0; k < NC; ++k) {
+    // column k of this lane's row (k is not a compile-time index)
+    double rk = 0.0;
+#pragma unroll
+    for (int m = 0; m < NC; ++m) rk = m == k ? row[m] : rk;
+    // pivot search: (|value|, lane), larger value wins, lower lane on ties
+    double best = used ? -1.0 : fabs(rk);
+    int bl = lane;
+    for (int off = 32; off > 0; off >>= 1) {
+      const double ob = __shfl_xor(best, off, 64);
+      const int ol = __shfl_xor(bl, off, 64);
+      if (ob > best || (ob == best && ol < bl)) {
+        best = ob;
+        bl = ol;
       }
-    __syncthreads();
-    double pv = A[k][k];
-    if (pv == 0.0 || !isfinite(pv)) {
+    }
+    if (!(best > 0.0) || !isfinite(best)) {
       singular = true;
       break;
     }
+    const int pl = __builtin_amdgcn_readfirstlane(bl);
+    if (lane == 0) pvt[k] = pl;
+    if (lane == pl) {
+      const double ri = 1.0 / rk;
+#pragma unroll
+      for (int m = 0; m < NC; ++m) row[m] = m == k ? ri : row[m] * ri;
+      used = true;
+      myk = k;
+    }
+    if (lane == pl) {
+#pragma unroll
+      for (int m = 0; m < NC; ++m) prow[m] = row[m];
+    }
     __syncthreads();
-    for (int m = lane; m < 2 * n; m += 64) A[k][m] = A[k][m] / pv;
-    __syncthreads();
-    if (lane < n && lane != k) {
-      double f = A[lane][k];
-      if (f != 0.0)
-        for (int m = 0; m < 2 * n; ++m) A[lane][m] -= f * A[k][m];
+    const double f = (lane != pl && live) ? rk : 0.0;
+#pragma unroll
+    for (int m0 = 0; m0 < NC; m0 += 8) {
+#pragma unroll
+      for (int m = m0; m < NC && m < m0 + 8; ++m) {
+        const double pr = prow[m];
+        if (lane != pl && live) {
+          if (m == k)
+            row[m] = -(f * pr);
+          else
+            row[m] -= f * pr;
+        }
+      }
+      __builtin_amdgcn_sched_barrier(0);
     }
     __syncthreads();
   }
@@ -173,24 +210,35 @@ __global__ void __launch_bounds__(64) k_factor(FactorArgs a) {
     }
     return;
   }
-  if (lane < n) {
-    double t = 0.0;
-    for (int i = 0; i < n; ++i) t += fabs(A[i][n + lane]);
-    colsum[lane] = t;
-  }
+  // the in-place result back to LDS: Ms[lane][j] = Minv[myk][p_j]
   __syncthreads();
+  if (live) {
+#pragma unroll
+    for (int j = 0; j < NC; ++j) Ms[lane][j] = row[j];
+  }
+  __shared__ int rowof[NC];       // lane holding row alpha of the inverse
+  if (live) rowof[myk] = lane;
+  __syncthreads();
+  // 1-norm of the inverse (column sums are invariant under the row and
+  // column permutation of the in-place result)
+  double normI = 0.0;
+  if (live)
+    for (int i = 0; i < NC; ++i) normI += fabs(Ms[i][lane]);
+  normI = wave_max(normI);
   if (lane == 0) {
-    double ni = 0.0;
-    for (int i = 0; i < n; ++i) ni = fmax(ni, colsum[i]);
-    double cn = normM * ni;
+    const double cn = normM * normI;
     a.cond[c] = cn;
     if (!(cn <= 1e10)) atomicOr(a.flags, FLAG_SINGULAR);
   }
-  // Minv[alpha][j] = A[alpha][n + j]  ->  MinvT[c][j][alpha]
-  double* out = a.MinvT + c * (int64_t)n * n;
-  for (int idx = lane; idx < n * n; idx += 64) {
-    int j = idx / n, al = idx % n;
-    out[idx] = A[al][n + j];
+  // MinvT[c][j][alpha] = Minv[alpha][j]; column j of Minv is column q of
+  // the in-place result with p_q = j
+  __shared__ int colof[NC];
+  if (live) colof[pvt[lane]] = lane;
+  __syncthreads();
+  double* out = a.MinvT + c * (int64_t)NC * NC;
+  for (int idx = lane; idx < NC * NC; idx += 64) {
+    const int j = idx / NC, al = idx % NC;
+    out[idx] = Ms[rowof[al]][colof[j]];
   }
 }
 
@@ -232,7 +280,15 @@ kfbi_status colloc_factor(kfbi_plan* pl) {
   HIPCHK(hipMemsetAsync(pl->d_flags, 0, sizeof(int), pl->stream));
   FactorArgs a{pl->g, T, pl->n_dof, pl->d2s, pl->s_pos, pl->s_nrm, pl->stD, pl->stN, pl->MinvT, pl->MT,
                pl->cond, pl->d_flags};
-  hipLaunchKernelGGL(k_factor, dim3((unsigned)pl->n_dof), dim3(64), 0, pl->stream, a);
+  switch (T.n) {
+    case 6: hipLaunchKernelGGL(k_factor<6>, dim3((unsigned)pl->n_dof), dim3(64), 0, pl->stream, a); break;
+    case 10: hipLaunchKernelGGL(k_factor<10>, dim3((unsigned)pl->n_dof), dim3(64), 0, pl->stream, a); break;
+    case 15: hipLaunchKernelGGL(k_factor<15>, dim3((unsigned)pl->n_dof), dim3(64), 0, pl->stream, a); break;
+    case 35: hipLaunchKernelGGL(k_factor<35>, dim3((unsigned)pl->n_dof), dim3(64), 0, pl->stream, a); break;
+    default:
+      kfbi_set_error("no collocation kernel for %d coefficients", T.n);
+      return KFBI_E_INVALID;
+  }
   HIPCHK(hipGetLastError());
   HIPCHK(hipMemcpyAsync(pl->h_pinned + 1, pl->d_flags, sizeof(int), hipMemcpyDeviceToHost, pl->stream));
   HIPCHK(hipStreamSynchronize(pl->stream));

@@ -30,7 +30,7 @@
 namespace {
 
 constexpr int MG_BLOCK = 256;
-constexpr int MG_PART = 1024;            // partial sums of the outer residual
+constexpr int MG_PART = 8192;            // partial sums of the outer residual (per block)
 constexpr int LDS_BLOCK = 1024;          // threads of the in-LDS coarse cycle
 
 template <typename T>
@@ -55,14 +55,17 @@ struct Ctl {
 
 __device__ __forceinline__ bool skip(const Ctl& c) { return (c.gctl && c.gctl[1]) || c.mctl[0]; }
 
-__device__ __forceinline__ int64_t node_of(int d, int n1, int64_t t, int N) {
-  const int m = N - 1;
-  int i = (int)(t % m) + 1;
-  int64_t r = t / m;
-  if (d == 2) return i + (int64_t)n1 * (r + 1);
-  int j = (int)(r % m) + 1;
-  int k = (int)(r / m) + 1;
-  return i + (int64_t)n1 * (j + (int64_t)n1 * k);
+// grid index of interior node t (x fastest); grids have at most 1025^3
+// nodes, so 32-bit arithmetic is exact
+__device__ __forceinline__ int64_t node_of(int d, int n1, int64_t t64, int N) {
+  const unsigned m = (unsigned)(N - 1);
+  const unsigned t = (unsigned)t64;
+  const unsigned r = t / m;
+  const unsigned i = t - r * m + 1;
+  if (d == 2) return (int64_t)(i + (unsigned)n1 * (r + 1));
+  const unsigned k = r / m;
+  const unsigned j = r - k * m + 1;
+  return (int64_t)(i + (unsigned)n1 * (j + (unsigned)n1 * (k + 1)));
 }
 
 template <typename T, typename S>
@@ -138,48 +141,173 @@ __device__ __forceinline__ void coords(int d, int n1, int64_t idx, int& i0, int&
 }
 
 // ---------------------------------------------------------------- global kernels
-template <typename T>
-__global__ void __launch_bounds__(MG_BLOCK) k_smooth(Ctl ctl, Lev<T> L, const T* uin, const T* f, T* uout) {
-  if (skip(ctl)) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t m = L.d == 3 ? (int64_t)(L.N - 1) * (L.N - 1) * (L.N - 1) : (int64_t)(L.N - 1) * (L.N - 1);
-  if (t >= m) return;
-  op_smooth(L, uin ? uin + L.off : nullptr, f + L.off, uout + L.off, node_of(L.d, L.n1, t, L.N));
-}
+// Stencil sweeps of the fine levels.  A workgroup owns a tile of the plane
+// transverse to the marching axis (3D: 64 x 4 nodes in x-y, marching along
+// z; 2D: 256 nodes along x, marching along y) and a chunk of KZ planes; the
+// planes z-1, z, z+1 of the stencil input (with a one-node halo) rotate
+// through LDS, so every input value is read from memory about once.
+enum { SW_SMOOTH = 0, SW_SMOOTH2 = 1, SW_RESID = 2, SW_OUTER = 3 };
 
-template <typename T>
-__global__ void __launch_bounds__(MG_BLOCK) k_resid(Ctl ctl, Lev<T> L, const T* u, const T* f, T* r) {
-  if (skip(ctl)) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  const int64_t m = L.d == 3 ? (int64_t)(L.N - 1) * (L.N - 1) * (L.N - 1) : (int64_t)(L.N - 1) * (L.N - 1);
-  if (t >= m) return;
-  op_resid(L, u + L.off, f + L.off, r + L.off, node_of(L.d, L.n1, t, L.N));
+template <typename TS, typename TO>
+struct SweepArgs {
+  int N, n1, KZ;
+  TS c[27];
+  TS coef;           // omega / a
+  const TS* s;       // stencil input (u, or f for SW_SMOOTH2, or v for SW_OUTER)
+  const TS* f;       // right-hand side (F for SW_OUTER)
+  TO* out;
+  double* part;      // SW_OUTER: per-block sums of r^2 (and F^2 at part + MG_PART)
+};
+
+template <int D>
+struct Tile {
+  static constexpr int TX = D == 3 ? 64 : 256;
+  static constexpr int TY = D == 3 ? 4 : 1;
+  static constexpr int PX = TX + 2;
+  static constexpr int PY = D == 3 ? TY + 2 : 1;
+  static constexpr int PL = PX * PY;
+};
+
+// modes: SW_SMOOTH   out = u + coef (f - A u)
+//        SW_SMOOTH2  two sweeps from zero in one: u1 = coef f,
+//                    out = u1 + coef (f - A u1) = coef f + coef (f - coef A f)
+//        SW_RESID    out = f - A u
+//        SW_OUTER    r = F - A v (FP64), out = (TO) r, sums of r^2, F^2
+template <typename TS, typename TO, int D, int MODE>
+__global__ void __launch_bounds__(256) k_sweep(Ctl ctl, SweepArgs<TS, TO> a) {
+  using TT = Tile<D>;
+  constexpr int NL = (TT::PL + 255) / 256;     // plane elements per thread
+  __shared__ TS pl[3][TT::PL];
+  __shared__ double red[MODE == SW_OUTER ? 2 : 1][MODE == SW_OUTER ? 256 : 1];
+  double acc_r = 0.0, acc_f = 0.0;
+  const bool active = !skip(ctl);
+  if (active) {
+    const int m = a.N - 1, n1 = a.n1;
+    const int lx = threadIdx.x % TT::TX, ly = threadIdx.x / TT::TX;
+    const int x0 = blockIdx.x * TT::TX;
+    const int y0 = D == 3 ? blockIdx.y * TT::TY : 0;
+    const int z0 = (D == 3 ? blockIdx.z : blockIdx.y) * a.KZ;
+    const int z1 = z0 + a.KZ < m ? z0 + a.KZ : m;
+    // plane gz into registers (this thread's NL elements), then into LDS
+    auto fetch = [&](int gz, TS* r) {
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        const int px = i % TT::PX, py = i / TT::PX;
+        const int gx = x0 + px, gy = y0 + py;
+        TS v = 0;
+        if (i < TT::PL && gx <= a.N && (D == 2 || gy <= a.N))
+          v = a.s[D == 3 ? gx + n1 * (gy + n1 * gz) : gx + n1 * gz];
+        r[q] = v;
+      }
+    };
+    auto store = [&](const TS* r, TS* buf) {
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        if (i < TT::PL) buf[i] = r[q];
+      }
+    };
+    TS rg[NL];
+    fetch(z0, rg);
+    store(rg, pl[z0 % 3]);
+    fetch(z0 + 1, rg);
+    store(rg, pl[(z0 + 1) % 3]);
+    fetch(z0 + 2, rg);
+    const int ix = x0 + lx, iy = y0 + ly;
+    const bool own = ix < m && (D == 2 || iy < m);
+    const int cc = D == 3 ? (ly + 1) * TT::PX + (lx + 1) : lx + 1;
+    for (int iz = z0; iz < z1; ++iz) {
+      store(rg, pl[(iz + 2) % 3]);
+      __syncthreads();
+      // the next plane's loads are in flight while this plane is computed
+      if (iz + 1 < z1) fetch(iz + 3, rg);
+      if (own) {
+        const TS* P[3] = {pl[iz % 3], pl[(iz + 1) % 3], pl[(iz + 2) % 3]};
+        TS s = 0;
+        if (D == 3) {
+#pragma unroll
+          for (int o2 = 0; o2 < 3; ++o2)
+#pragma unroll
+            for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+              for (int o0 = 0; o0 < 3; ++o0) {
+                const TS cf = a.c[o0 + 3 * o1 + 9 * o2];
+                if (cf != (TS)0) s += cf * P[o2][cc + (o1 - 1) * TT::PX + (o0 - 1)];
+              }
+        } else {
+#pragma unroll
+          for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+            for (int o0 = 0; o0 < 3; ++o0) {
+              const TS cf = a.c[o0 + 3 * o1 + 9];
+              if (cf != (TS)0) s += cf * P[o1][cc + (o0 - 1)];
+            }
+        }
+        const int gz = iz + 1;
+        const int idx = D == 3 ? (ix + 1) + n1 * ((iy + 1) + n1 * gz) : (ix + 1) + n1 * gz;
+        const TS ctr = P[1][cc];
+        if (MODE == SW_SMOOTH) {
+          a.out[idx] = (TO)(ctr + a.coef * (a.f[idx] - s));
+        } else if (MODE == SW_SMOOTH2) {
+          const TS u1 = a.coef * ctr;
+          a.out[idx] = (TO)(u1 + a.coef * (ctr - a.coef * s));
+        } else if (MODE == SW_RESID) {
+          a.out[idx] = (TO)(a.f[idx] - s);
+        } else {
+          const double Fv = (double)a.f[idx];
+          const double r = Fv - (double)s;
+          a.out[idx] = (TO)r;
+          acc_r += r * r;
+          acc_f += Fv * Fv;
+        }
+      }
+      __syncthreads();
+    }
+  }
+  if (MODE == SW_OUTER) {
+    red[0][threadIdx.x] = acc_r;
+    red[1][threadIdx.x] = acc_f;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < (unsigned)o) {
+        red[0][threadIdx.x] += red[0][threadIdx.x + o];
+        red[1][threadIdx.x] += red[1][threadIdx.x + o];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+      a.part[b] = red[0][0];
+      a.part[MG_PART + b] = red[1][0];
+    }
+  }
 }
 
 // coarse right-hand side f_c = R r_f (coarse level C, fine level Fl)
 template <typename T>
 __global__ void __launch_bounds__(MG_BLOCK) k_restrict(Ctl ctl, Lev<T> Fl, Lev<T> C, const T* r, T* f) {
   if (skip(ctl)) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t m = C.d == 3 ? (int64_t)(C.N - 1) * (C.N - 1) * (C.N - 1) : (int64_t)(C.N - 1) * (C.N - 1);
-  if (t >= m) return;
-  const int64_t idx = node_of(C.d, C.n1, t, C.N);
-  int I0, I1, I2;
-  coords(C.d, C.n1, idx, I0, I1, I2);
-  f[C.off + idx] = op_restrict<T>(C.d, Fl.n1, r + Fl.off, I0, I1, I2);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t idx = node_of(C.d, C.n1, t, C.N);
+    int I0, I1, I2;
+    coords(C.d, C.n1, idx, I0, I1, I2);
+    f[C.off + idx] = op_restrict<T>(C.d, Fl.n1, r + Fl.off, I0, I1, I2);
+  }
 }
 
 // u_f += P e_c at the fine interior
 template <typename T>
 __global__ void __launch_bounds__(MG_BLOCK) k_prolong(Ctl ctl, Lev<T> Fl, Lev<T> C, const T* e, T* u) {
   if (skip(ctl)) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t m = Fl.d == 3 ? (int64_t)(Fl.N - 1) * (Fl.N - 1) * (Fl.N - 1) : (int64_t)(Fl.N - 1) * (Fl.N - 1);
-  if (t >= m) return;
-  const int64_t idx = node_of(Fl.d, Fl.n1, t, Fl.N);
-  int i0, i1, i2;
-  coords(Fl.d, Fl.n1, idx, i0, i1, i2);
-  u[Fl.off + idx] += op_prolong<T>(Fl.d, C.n1, e + C.off, i0, i1, i2);
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t idx = node_of(Fl.d, Fl.n1, t, Fl.N);
+    int i0, i1, i2;
+    coords(Fl.d, Fl.n1, idx, i0, i1, i2);
+    u[Fl.off + idx] += op_prolong<T>(Fl.d, C.n1, e + C.off, i0, i1, i2);
+  }
 }
 
 // levels lc .. L-1 of one V(2,2) cycle in LDS, one workgroup: f_lc in, u_lc out
@@ -282,7 +410,8 @@ struct OuterArgs {
   double* part;       // [2][MG_PART]
 };
 
-// r = F - A_h v (FP64) -> f_0 = (T) r; per-block sums of r^2 (and F^2)
+// first correction (v = 0): v <- 0, f_0 = (T) F; per-block sums of F^2
+// (later corrections use the SW_OUTER sweep)
 template <typename T>
 __global__ void __launch_bounds__(MG_BLOCK) k_outer_resid(OuterArgs a, T* f0) {
   __shared__ double sr[MG_BLOCK], sf[MG_BLOCK];
@@ -292,13 +421,8 @@ __global__ void __launch_bounds__(MG_BLOCK) k_outer_resid(OuterArgs a, T* f0) {
     for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
       const int64_t idx = node_of(a.d, a.n1, t, a.N);
       const double Fv = a.F[idx];
-      double r;
-      if (a.first) {
-        r = Fv;
-        a.v[idx] = 0.0;
-      } else {
-        r = Fv - apply_A<double, double>(a.c, a.d, a.n1, a.v, idx);
-      }
+      const double r = Fv;     // first correction: v = 0
+      a.v[idx] = 0.0;
       f0[idx] = (T)r;
       acc_r += r * r;
       acc_f += Fv * Fv;
@@ -354,11 +478,12 @@ __global__ void __launch_bounds__(MG_BLOCK) k_check(Ctl ctl, const double* part,
 template <typename T>
 __global__ void __launch_bounds__(MG_BLOCK) k_update(Ctl ctl, int d, int N, int n1, const T* e, double* v) {
   if (skip(ctl)) return;
-  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const int64_t m = d == 3 ? (int64_t)(N - 1) * (N - 1) * (N - 1) : (int64_t)(N - 1) * (N - 1);
-  if (t >= m) return;
-  const int64_t idx = node_of(d, n1, t, N);
-  v[idx] = v[idx] + (double)e[idx];
+  if (blockIdx.x == 0 && threadIdx.x == 0) ctl.mctl[1] += 1;   // one more correction applied
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
+    const int64_t idx = node_of(d, n1, t, N);
+    v[idx] = v[idx] + (double)e[idx];
+  }
 }
 
 // v = 0 on the box boundary (the outer residual reads v's boundary nodes;
@@ -377,11 +502,6 @@ __global__ void __launch_bounds__(MG_BLOCK) k_zero_boundary(Ctl ctl, int d, int 
   int q = 0;
   for (int a = 0; a < d; ++a) c[a] = a == ax ? side : o[q++];
   v[c[0] + (int64_t)n1 * (c[1] + (int64_t)n1 * c[2])] = 0.0;
-}
-
-__global__ void k_count(Ctl ctl) {
-  if ((ctl.gctl && ctl.gctl[1]) || ctl.mctl[0]) return;
-  ctl.mctl[1] += 1;
 }
 
 __global__ void k_start(Ctl ctl) {
@@ -411,6 +531,12 @@ __global__ void __launch_bounds__(MG_BLOCK) k_scatter(const int* gctl, int64_t n
 }
 
 inline unsigned nblk(int64_t n, int b = MG_BLOCK) { return (unsigned)((n + b - 1) / b); }
+// grid of an elementwise grid-stride kernel: enough workgroups to fill the
+// chip, few enough that a launch skipped by the control word is cheap
+inline unsigned gsblk(int64_t n) {
+  unsigned b = nblk(n);
+  return b > 4096u ? 4096u : b;
+}
 
 template <typename T>
 Hier<T> make_hier(const kfbi_plan* pl) {
@@ -441,6 +567,59 @@ size_t coarse_lds(const Hier<T>& H) {
   return tot * sizeof(T);
 }
 
+struct SweepGeom {
+  dim3 grid;
+  int KZ;
+  int blocks;
+};
+
+// tiles of the transverse plane x chunks of KZ planes, about 1024 workgroups
+template <int D>
+SweepGeom sweep_geom(int N) {
+  using TT = Tile<D>;
+  const int m = N - 1;
+  const int tx = (m + TT::TX - 1) / TT::TX;
+  const int ty = D == 3 ? (m + TT::TY - 1) / TT::TY : 1;
+  const int cols = tx * ty;
+  int chunks = 4096 / cols;
+  if (chunks < 1) chunks = 1;
+  int KZ = (m + chunks - 1) / chunks;
+  const int kmin = D == 3 ? 8 : 8;
+  if (KZ < kmin) KZ = kmin;
+  if (KZ > m) KZ = m;
+  chunks = (m + KZ - 1) / KZ;
+  SweepGeom g;
+  g.grid = D == 3 ? dim3(tx, ty, chunks) : dim3(tx, chunks, 1);
+  g.KZ = KZ;
+  g.blocks = cols * chunks;
+  return g;
+}
+
+template <typename TS, typename TO, int MODE>
+void sweep(kfbi_plan* pl, Ctl ctl, int N, const TS* c27, TS coef, const TS* src, const TS* f, TO* out,
+           int* nblocks = nullptr) {
+  SweepArgs<TS, TO> a;
+  a.N = N;
+  a.n1 = N + 1;
+  for (int i = 0; i < 27; ++i) a.c[i] = c27[i];
+  a.coef = coef;
+  a.s = src;
+  a.f = f;
+  a.out = out;
+  a.part = pl->mg_part;
+  if (pl->g.d == 3) {
+    SweepGeom g = sweep_geom<3>(N);
+    a.KZ = g.KZ;
+    hipLaunchKernelGGL((k_sweep<TS, TO, 3, MODE>), g.grid, dim3(256), 0, pl->stream, ctl, a);
+    if (nblocks) *nblocks = g.blocks;
+  } else {
+    SweepGeom g = sweep_geom<2>(N);
+    a.KZ = g.KZ;
+    hipLaunchKernelGGL((k_sweep<TS, TO, 2, MODE>), g.grid, dim3(256), 0, pl->stream, ctl, a);
+    if (nblocks) *nblocks = g.blocks;
+  }
+}
+
 template <typename T>
 void vcycle(kfbi_plan* pl, const Hier<T>& H, Ctl ctl) {
   T* u = (T*)pl->mg_u;
@@ -452,19 +631,21 @@ void vcycle(kfbi_plan* pl, const Hier<T>& H, Ctl ctl) {
     return H.d == 3 ? m * m * m : m * m;
   };
   for (int l = 0; l < H.lc; ++l) {
-    const unsigned g = nblk(interior(l));
-    hipLaunchKernelGGL((k_smooth<T>), dim3(g), dim3(MG_BLOCK), 0, st, ctl, H.lv[l], (const T*)nullptr, f, tb);
-    hipLaunchKernelGGL((k_smooth<T>), dim3(g), dim3(MG_BLOCK), 0, st, ctl, H.lv[l], (const T*)tb, f, u);
-    hipLaunchKernelGGL((k_resid<T>), dim3(g), dim3(MG_BLOCK), 0, st, ctl, H.lv[l], (const T*)u, f, tb);
-    hipLaunchKernelGGL((k_restrict<T>), dim3(nblk(interior(l + 1))), dim3(MG_BLOCK), 0, st, ctl, H.lv[l],
+    const Lev<T>& L = H.lv[l];
+    const int64_t o = L.off;
+    sweep<T, T, SW_SMOOTH2>(pl, ctl, L.N, L.c, L.coef, f + o, f + o, u + o);
+    sweep<T, T, SW_RESID>(pl, ctl, L.N, L.c, L.coef, u + o, f + o, tb + o);
+    hipLaunchKernelGGL((k_restrict<T>), dim3(gsblk(interior(l + 1))), dim3(MG_BLOCK), 0, st, ctl, H.lv[l],
                        H.lv[l + 1], (const T*)tb, f);
   }
   hipLaunchKernelGGL((k_coarse_cycle<T>), dim3(1), dim3(LDS_BLOCK), coarse_lds(H), st, ctl, H, (const T*)f, u);
   for (int l = H.lc - 1; l >= 0; --l) {
-    const unsigned g = nblk(interior(l));
-    hipLaunchKernelGGL((k_prolong<T>), dim3(g), dim3(MG_BLOCK), 0, st, ctl, H.lv[l], H.lv[l + 1], (const T*)u, u);
-    hipLaunchKernelGGL((k_smooth<T>), dim3(g), dim3(MG_BLOCK), 0, st, ctl, H.lv[l], (const T*)u, f, tb);
-    hipLaunchKernelGGL((k_smooth<T>), dim3(g), dim3(MG_BLOCK), 0, st, ctl, H.lv[l], (const T*)tb, f, u);
+    const Lev<T>& L = H.lv[l];
+    const int64_t o = L.off;
+    hipLaunchKernelGGL((k_prolong<T>), dim3(gsblk(interior(l))), dim3(MG_BLOCK), 0, st, ctl, H.lv[l], H.lv[l + 1],
+                       (const T*)u, u);
+    sweep<T, T, SW_SMOOTH>(pl, ctl, L.N, L.c, L.coef, u + o, f + o, tb + o);
+    sweep<T, T, SW_SMOOTH>(pl, ctl, L.N, L.c, L.coef, tb + o, f + o, u + o);
   }
 }
 
@@ -486,25 +667,29 @@ void solve_t(kfbi_plan* pl, const double* F, double* v) {
   oa.F = F;
   oa.v = v;
   oa.part = pl->mg_part;
+  oa.first = 1;
   hipLaunchKernelGGL(k_start, dim3(1), dim3(1), 0, st, ctl);
   {
     const int64_t nb = 2 * g.d * (g.d == 3 ? (int64_t)g.n1 * g.n1 : (int64_t)g.n1);
     hipLaunchKernelGGL(k_zero_boundary, dim3(nblk(nb)), dim3(MG_BLOCK), 0, st, ctl, g.d, g.n1, v);
   }
+  T* f0 = (T*)pl->mg_f;
   for (int it = 0; it < pl->mg_maxit; ++it) {
-    oa.first = it == 0 ? 1 : 0;
-    hipLaunchKernelGGL((k_outer_resid<T>), dim3(gout), dim3(MG_BLOCK), 0, st, oa, (T*)pl->mg_f);
-    hipLaunchKernelGGL(k_check, dim3(1), dim3(MG_BLOCK), 0, st, ctl, (const double*)pl->mg_part, (int)gout,
-                       oa.first, pl->mg_eps, pl->mg_maxit, pl->mg_scal);
+    int nb_part = (int)gout;
+    if (it == 0)
+      hipLaunchKernelGGL((k_outer_resid<T>), dim3(gout), dim3(MG_BLOCK), 0, st, oa, f0);
+    else
+      sweep<double, T, SW_OUTER>(pl, ctl, g.N, pl->mg_c[0], 0.0, v, F, f0, &nb_part);
+    hipLaunchKernelGGL(k_check, dim3(1), dim3(MG_BLOCK), 0, st, ctl, (const double*)pl->mg_part, nb_part,
+                       it == 0 ? 1 : 0, pl->mg_eps, pl->mg_maxit, pl->mg_scal);
     vcycle<T>(pl, H, ctl);
-    hipLaunchKernelGGL((k_update<T>), dim3(nblk(m)), dim3(MG_BLOCK), 0, st, ctl, g.d, g.N, g.n1,
+    hipLaunchKernelGGL((k_update<T>), dim3(gsblk(m)), dim3(MG_BLOCK), 0, st, ctl, g.d, g.N, g.n1,
                        (const T*)pl->mg_u, v);
-    hipLaunchKernelGGL(k_count, dim3(1), dim3(1), 0, st, ctl);
   }
   // residual of the final iterate (the stopping value reported)
-  oa.first = 0;
-  hipLaunchKernelGGL((k_outer_resid<T>), dim3(gout), dim3(MG_BLOCK), 0, st, oa, (T*)pl->mg_f);
-  hipLaunchKernelGGL(k_check, dim3(1), dim3(MG_BLOCK), 0, st, ctl, (const double*)pl->mg_part, (int)gout, 0,
+  int nb_part = 0;
+  sweep<double, T, SW_OUTER>(pl, ctl, g.N, pl->mg_c[0], 0.0, v, F, f0, &nb_part);
+  hipLaunchKernelGGL(k_check, dim3(1), dim3(MG_BLOCK), 0, st, ctl, (const double*)pl->mg_part, nb_part, 0,
                      pl->mg_eps, pl->mg_maxit, pl->mg_scal);
 }
 
