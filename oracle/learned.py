@@ -1,0 +1,146 @@
+"""Learned warm start for GMRES (oracle side): interface-sample features,
+the spherical-harmonic transfer between samples and DOFs, and the MLP with
+its mean-squared-error gradient.
+
+TEST INFRASTRUCTURE ONLY (see oracle/__init__.py).
+
+The KFBI solve starts GMRES from an initial density (Alg. 1 Step 2); the
+zero start is the default.  The learned start predicts the density from the
+interface and jump data:
+  samples   s_i, i < 1024, a Fibonacci lattice on the unit sphere, mapped to
+            the ellipsoid x_i = c + Q diag(a) s_i;
+  features  per sample: position (3), outward unit normal (3), mean
+            curvature (1), g1(x_i), g2(x_i): 9 values, flattened in sample
+            order to one 9216-vector;
+  network   MLP 9216 -> 256 -> 256 -> 256 -> 1024, ReLU on the hidden
+            layers, bf16 operands with wider accumulation; output = the
+            density at the samples divided by a fixed output scale;
+  transfer  least-squares fit of real spherical harmonics of degree <= 8 in
+            the body-frame direction diag(1/a) Q^T (x - c) / | . | (81
+            functions) to the sample values, evaluated at the DOFs;
+  targets   the solved density psi* at the DOFs, fitted the same way and
+            evaluated at the samples.
+"""
+import numpy as np
+import scipy.special
+
+LMAX = 8
+
+
+def sample_points(geom, S):
+    c, a, Q = geom
+    return np.asarray(c)[None, :] + (np.asarray(S) * np.asarray(a)[None, :]) @ np.asarray(Q).T
+
+
+def body_coords(geom, X):
+    c, a, Q = geom
+    return (np.asarray(X) - np.asarray(c)[None, :]) @ np.asarray(Q)
+
+
+def normals_and_curvature(geom, X):
+    """Outward unit normal and mean curvature (average of the principal
+    curvatures, 1/r on a sphere) of H = sum (X_j / a_j)^2 - 1 at X."""
+    c, a, Q = geom
+    a = np.asarray(a)
+    Xb = body_coords(geom, X)
+    g = 2.0 * Xb / a ** 2                     # body-frame gradient
+    hess = 2.0 / a ** 2                        # diagonal of the Hessian
+    ng = np.linalg.norm(g, axis=1)
+    n = (g @ np.asarray(Q).T) / ng[:, None]
+    kappa = (ng ** 2 * hess.sum() - (g * g * hess[None, :]).sum(axis=1)) / (2.0 * ng ** 3)
+    return n, kappa
+
+
+def features(geom, jumps_fn, S):
+    """(n, 9) features at the samples; jumps_fn(X) -> (g1, g2)."""
+    X = sample_points(geom, S)
+    n, kappa = normals_and_curvature(geom, X)
+    g1, g2 = jumps_fn(X)
+    return np.concatenate([X, n, kappa[:, None], np.asarray(g1)[:, None], np.asarray(g2)[:, None]], axis=1)
+
+
+def real_sh(dirs, lmax=LMAX):
+    """Real orthonormal spherical harmonics at unit directions (n, 3), index
+    l^2 + l + m: m > 0 -> sqrt2 (-1)^m Re Y_l^m, m < 0 -> sqrt2 (-1)^m Im
+    Y_l^|m|, m = 0 -> Y_l^0 (scipy's complex Y_l^m with the Condon-Shortley
+    phase, so these carry none)."""
+    d = np.asarray(dirs, dtype=np.float64)
+    d = d / np.linalg.norm(d, axis=1, keepdims=True)
+    theta = np.arccos(np.clip(d[:, 2], -1.0, 1.0))
+    phi = np.arctan2(d[:, 1], d[:, 0])
+    out = np.zeros((d.shape[0], (lmax + 1) ** 2))
+    for l in range(lmax + 1):
+        for m in range(-l, l + 1):
+            Y = scipy.special.sph_harm_y(l, abs(m), theta, phi)
+            if m > 0:
+                v = np.sqrt(2.0) * (-1) ** m * Y.real
+            elif m < 0:
+                v = np.sqrt(2.0) * (-1) ** m * Y.imag
+            else:
+                v = Y.real
+            out[:, l * l + l + m] = v
+    return out
+
+
+def sh_fit(dirs, values, lmax=LMAX):
+    """Least-squares coefficients of real SH of degree <= lmax."""
+    Y = real_sh(dirs, lmax)
+    coef, *_ = np.linalg.lstsq(Y, np.asarray(values, dtype=np.float64), rcond=None)
+    return coef
+
+
+def transfer_to_dofs(geom, S, psi_s, dof_pos, lmax=LMAX):
+    """Density at the DOFs from its values at the samples."""
+    coef = sh_fit(S, psi_s, lmax)
+    return real_sh(body_coords(geom, dof_pos) / np.asarray(geom[1])[None, :], lmax) @ coef
+
+
+def sample_density(geom, S, dof_pos, psi_dof, lmax=LMAX):
+    """Density at the samples from its values at the DOFs."""
+    coef = sh_fit(body_coords(geom, dof_pos) / np.asarray(geom[1])[None, :], psi_dof, lmax)
+    return real_sh(S, lmax) @ coef
+
+
+# ---------------------------------------------------------------- MLP
+def bf16(x):
+    """Round to the nearest bfloat16 (ties to even), returned as float64."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = (u + 0x7FFF + ((u >> 16) & 1)) & 0xFFFF0000
+    return u.astype(np.uint32).view(np.float32).astype(np.float64)
+
+
+def mlp_forward(Ws, bs, X, emulate=True):
+    """Activations [a_0 = X, a_1, ..., a_L] and pre-activations z_l; hidden
+    layers ReLU, last layer linear.  With emulate, the GEMM operands (inputs,
+    weights, hidden activations) are rounded to bf16 as on the GPU."""
+    r = bf16 if emulate else (lambda t: np.asarray(t, dtype=np.float64))
+    a = [np.asarray(X, dtype=np.float64)]
+    zs = []
+    for l, (W, b) in enumerate(zip(Ws, bs)):
+        z = r(a[-1]) @ r(W) + np.asarray(b, dtype=np.float64)[None, :]
+        zs.append(z)
+        a.append(np.maximum(z, 0.0) if l < len(Ws) - 1 else z)
+    return a, zs
+
+
+def mlp_loss_grad(Ws, bs, X, Yt, emulate=True):
+    """L = mean (out - Yt)^2 over all entries, and (dL/dW_l, dL/db_l).
+    With emulate the backward GEMM operands (activations, weights and the
+    back-propagated gradients) are rounded to bf16 like the GPU's."""
+    r = bf16 if emulate else (lambda t: np.asarray(t, dtype=np.float64))
+    a, zs = mlp_forward(Ws, bs, X, emulate)
+    out = a[-1]
+    n = out.size
+    diff = out - np.asarray(Yt, dtype=np.float64)
+    loss = float(np.sum(diff * diff) / n)
+    dz = 2.0 * diff / n
+    gW = [None] * len(Ws)
+    gb = [None] * len(Ws)
+    for l in range(len(Ws) - 1, -1, -1):
+        gW[l] = r(a[l]).T @ r(dz)
+        gb[l] = dz.sum(axis=0)
+        if l > 0:
+            da = r(dz) @ r(Ws[l]).T
+            dz = da * (zs[l - 1] > 0.0)
+    return loss, gW, gb

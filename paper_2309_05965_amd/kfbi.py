@@ -282,3 +282,14 @@ def device_data(plan, prob, sol):
     dev = plan.device
     return {k: torch.from_numpy(v.reshape(-1).copy() if k != "ftilde" else v.copy()).to(dev).contiguous()
             for k, v in data.items()}
+
+
+def device_jump_data(plan, jumps):
+    """Config-5 data (jumps only; fhat, ftilde and gB zero) at the plan's
+    surface points, as device tensors (input generation)."""
+    from . import workloads as W
+    pos = plan.export("surf_pos").cpu().numpy()
+    g1, g2 = W.jump_values(jumps, pos)
+    dev = plan.device
+    return {"g1": torch.from_numpy(g1).to(dev).contiguous(), "g2": torch.from_numpy(g2).to(dev).contiguous(),
+            "ftilde": None, "fhat": None, "gB": None}

@@ -259,3 +259,60 @@ def exact_density(prob, sol, dof_pos, dof_nrm, dof_iface):
         dn = sum((np.asarray(gk[a]) - np.asarray(g0[a])) * n[:, a] for a in range(n.shape[1]))
         out = np.where(k == kk, dn, out)
     return out
+
+
+# ----------------------------------------------------------------------------
+# learned warm start: random ellipsoids with random Fourier jump data
+# ----------------------------------------------------------------------------
+N_SAMPLES = 1024
+N_MODES = 8
+
+
+def fourier_wavevectors():
+    """k_m = (pi/2) (m & 1, (m >> 1) & 1, (m >> 2) & 1), m = 0..7."""
+    return np.array([[(m >> b) & 1 for b in range(3)] for m in range(N_MODES)], dtype=np.float64) * (math.pi / 2)
+
+
+def config5(seed, N=128):
+    """One learned-warm-start problem: an ellipsoid centred at the origin with
+    semi-axes ~ U(0.3, 0.7) and orientation Q from the QR factorisation of a
+    3x3 standard normal matrix (columns signed so that diag(R) > 0), box
+    [-1, 1]^3, 4th order, kappa 0, beta_in 1, beta_out 100, fhat = 0, gB = 0,
+    and jumps g_j(x) = sum_m a_jm cos(k_m . x) + b_jm sin(k_m . x), j = 1, 2,
+    a, b ~ N(0, 1).  Returns (prob, geom, jumps) with geom = (centre,
+    axes, Q) and jumps = (a, b) of shape (2, 8) each."""
+    rng = np.random.default_rng(seed)
+    axes = rng.uniform(0.3, 0.7, size=3)
+    G = rng.standard_normal((3, 3))
+    Q, R = np.linalg.qr(G)
+    Q = Q * np.sign(np.diag(R))[None, :]
+    a = rng.standard_normal((2, N_MODES))
+    b = rng.standard_normal((2, N_MODES))
+    centre = np.zeros(3)
+    prob = problem(3, 4, N, -1.0, 1.0, 1.0, 100.0, 0.0, [ellipsoid3d(centre, axes, Q)])
+    return prob, (centre, axes, Q), (a, b)
+
+
+def jump_values(jumps, X):
+    """(g1, g2) at points X (n, 3)."""
+    a, b = jumps
+    ph = np.asarray(X, dtype=np.float64) @ fourier_wavevectors().T      # (n, 8)
+    c, s = np.cos(ph), np.sin(ph)
+    return c @ a[0] + s @ b[0], c @ a[1] + s @ b[1]
+
+
+def fibonacci_sphere(n=N_SAMPLES):
+    """Fibonacci lattice on the unit sphere: z_i = 1 - (2i+1)/n,
+    phi_i = i pi (3 - sqrt 5)."""
+    i = np.arange(n, dtype=np.float64)
+    z = 1.0 - (2.0 * i + 1.0) / n
+    r = np.sqrt(1.0 - z * z)
+    ph = i * math.pi * (3.0 - math.sqrt(5.0))
+    return np.stack([r * np.cos(ph), r * np.sin(ph), z], axis=1)
+
+
+def jump_data(prob, jumps, surf_pos):
+    """Solver data of a config-5 problem at the solver's surface points."""
+    g1, g2 = jump_values(jumps, surf_pos)
+    N, d = prob["N"], prob["dim"]
+    return {"g1": g1, "g2": g2, "ftilde": None, "fhat": None, "gB": None}
