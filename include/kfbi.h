@@ -183,7 +183,8 @@ enum {
   KFBI_EXPORT_PDE_PTS = 9,
   KFBI_EXPORT_IRREGULAR = 10,
   KFBI_EXPORT_CORR = 11,
-  KFBI_EXPORT_COND = 12
+  KFBI_EXPORT_COND = 12,
+  KFBI_EXPORT_DOF_POS = 13
 };
 kfbi_status kfbi_plan_export(const kfbi_plan* plan, int which, void* dst, int64_t bytes);
 
@@ -255,6 +256,64 @@ kfbi_status kfbi_plan_profile(kfbi_plan* plan, int enable);
 kfbi_status kfbi_plan_timing(kfbi_plan* plan, int64_t* solves, int64_t* launches, double* ms);
 
 kfbi_status kfbi_plan_destroy(kfbi_plan* plan);
+
+/* ----------------------------------------------------------------------
+ * Learned initial density for GMRES (Alg. 1 Step 2 gives GMRES an initial
+ * guess; this predicts one).  All pointers are device pointers ordered on
+ * the given stream (the plan's stream for the plan calls); the MLP object
+ * and its buffers are library-owned.
+ * -------------------------------------------------------------------- */
+typedef struct kfbi_mlp kfbi_mlp;
+
+/* MLP widths[0] -> widths[1] -> ... -> widths[n_layers], ReLU after every
+ * layer but the last.  Weights are bf16 copies of fp32 master weights
+ * (all zero until kfbi_mlp_set_params); GEMMs accumulate in fp32.
+ * Parameter pack (fp32): for each layer W_l [widths[l] x widths[l+1]]
+ * row-major, then b_l [widths[l+1]]. */
+kfbi_status kfbi_mlp_create(int n_layers, const int* widths, void* stream, kfbi_mlp** out);
+kfbi_status kfbi_mlp_sizes(const kfbi_mlp* mlp, int64_t* n_params);
+/* Copy a parameter pack in (resets the Adam state) or out. */
+kfbi_status kfbi_mlp_set_params(kfbi_mlp* mlp, const float* params);
+kfbi_status kfbi_mlp_get_params(const kfbi_mlp* mlp, float* params);
+/* Y [B x widths[L]] = MLP(X [B x widths[0]]), fp32 in and out. */
+kfbi_status kfbi_mlp_forward(kfbi_mlp* mlp, const float* X, int B, float* Y);
+/* loss = mean over all entries of (MLP(X) - Yt)^2 (device float) and its
+ * gradient with respect to the parameter pack (grads may be NULL). */
+kfbi_status kfbi_mlp_loss_grad(kfbi_mlp* mlp, const float* X, const float* Yt, int B, float* loss,
+                               float* grads);
+/* One Adam step (beta 0.9 / 0.999, eps 1e-8, bias-corrected) on the same
+ * loss; loss of the batch before the step written to *loss (device). */
+kfbi_status kfbi_mlp_train_step(kfbi_mlp* mlp, const float* X, const float* Yt, int B, float lr, float* loss);
+kfbi_status kfbi_mlp_destroy(kfbi_mlp* mlp);
+
+/* C [M x N] (fp32, row stride ldc) = op(A) op(B) with bf16 operands (raw
+ * 16-bit storage) and fp32 accumulation on the matrix cores.  transA = 0:
+ * A is [M x K] (row stride lda); 1: A is [K x M].  transB = 0: B is
+ * [K x N]; 1: B is [N x K].  Both transposed is rejected. */
+kfbi_status kfbi_gemm_bf16(int transA, int transB, int M, int N, int K, const uint16_t* A, int lda,
+                           const uint16_t* B, int ldb, float* C, int ldc, void* stream);
+
+/* Features of ns interface samples for P ellipsoids: geom [P][15] =
+ * centre (3), semi-axes (3), orientation Q row-major (9); jumps [P][32] =
+ * a[j][m] (16) then b[j][m] (16) of g_j(x) = sum_m a_jm cos(k_m . x) +
+ * b_jm sin(k_m . x), k_m = (pi/2)(m & 1, (m >> 1) & 1, (m >> 2) & 1);
+ * S [ns][3] unit directions, sample i at x = c + Q diag(a) S_i.
+ * X [P][ns][9] = (x, outward normal, mean curvature, g1, g2), fp32. */
+kfbi_status kfbi_ellipsoid_features(const double* geom, const double* jumps, int P, const double* S, int ns,
+                                    void* stream, float* X);
+/* Density at the plan's DOFs from values at the samples: least-squares
+ * fit of the 81 real spherical harmonics of degree <= 8 in the body-frame
+ * direction diag(1/a) Q^T (x - c) to scale * psi_s (ns >= 81), evaluated
+ * at the DOFs.  geom [15] as above (device); psi_dof [n_dof]. */
+kfbi_status kfbi_sh_transfer(kfbi_plan* plan, const double* geom, const double* S, int ns, const float* psi_s,
+                             double scale, double* psi_dof);
+/* Density at the samples from values at the DOFs (the same fit from the
+ * DOFs, n_dof >= 81), times scale, fp32. */
+kfbi_status kfbi_sh_sample(kfbi_plan* plan, const double* geom, const double* psi_dof, const double* S, int ns,
+                           double scale, float* psi_s);
+/* The 81 real orthonormal spherical harmonics (no Condon-Shortley phase,
+ * index l^2 + l + m) at n directions: Y [81][n]. */
+kfbi_status kfbi_real_sh(const double* dirs, int n, void* stream, double* Y);
 
 /* Thread-local message of the last failing call (never NULL). */
 const char* kfbi_last_error(void);

@@ -508,6 +508,11 @@ __global__ void k_corr_table(int64_t n, const int* k, const int* node, const int
   out[e * 3 + 1] = node[e];
   out[e * 3 + 2] = own[e];
 }
+__global__ void k_dof_pos(int64_t n, int d, const int* d2s, const double* spos, double* out) {
+  int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (e >= n * d) return;
+  out[e] = spos[(int64_t)d2s[e / d] * d + e % d];
+}
 }  // namespace
 
 extern "C" kfbi_status kfbi_plan_export(const kfbi_plan* pl_c, int which, void* dst, int64_t bytes) {
@@ -530,6 +535,7 @@ extern "C" kfbi_status kfbi_plan_export(const kfbi_plan* pl_c, int which, void* 
     case KFBI_EXPORT_COND: src = pl->cond; need = pl->n_dof * 8; break;
     case KFBI_EXPORT_PDE_PTS: need = pl->n_dof * pl->nP * d * 8; break;
     case KFBI_EXPORT_CORR: need = pl->n_corr * 3 * 4; break;
+    case KFBI_EXPORT_DOF_POS: need = pl->n_dof * d * 8; break;
     default:
       kfbi_set_error("unknown export table %d", which);
       return KFBI_E_INVALID;
@@ -541,6 +547,12 @@ extern "C" kfbi_status kfbi_plan_export(const kfbi_plan* pl_c, int which, void* 
   if (need == 0) return KFBI_OK;
   if (src) {
     HIPCHK(hipMemcpyAsync(dst, src, (size_t)need, hipMemcpyDeviceToDevice, pl->stream));
+    return KFBI_OK;
+  }
+  if (which == KFBI_EXPORT_DOF_POS) {
+    hipLaunchKernelGGL(k_dof_pos, dim3((unsigned)((pl->n_dof * d + 255) / 256)), dim3(256), 0, pl->stream,
+                       pl->n_dof, d, pl->d2s, pl->s_pos, (double*)dst);
+    HIPCHK(hipGetLastError());
     return KFBI_OK;
   }
   if (which == KFBI_EXPORT_CORR) {

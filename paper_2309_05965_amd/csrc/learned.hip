@@ -1,0 +1,814 @@
+// Steps S10 / S11 -- learned initial density for GMRES (Alg. 1 Step 2).
+//
+// A small MLP maps features of 1024 interface samples (position, outward
+// normal, mean curvature, g1, g2) to the density at the samples; a
+// least-squares fit of real spherical harmonics (degree <= 8, body-frame
+// direction of the ellipsoid) carries it to the DOFs.  Training minimises
+// the mean squared error against densities the solver itself produced,
+// with hand-written bf16 MFMA GEMMs (v_mfma_f32_16x16x32_bf16, fp32
+// accumulation) for the forward and backward passes and Adam on fp32
+// master weights.
+#include <math.h>
+#include <stdint.h>
+
+#include <vector>
+
+#include "kfbi_internal.h"
+
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef float f32x4 __attribute__((ext_vector_type(4)));
+
+namespace {
+
+// ---------------------------------------------------------------- bf16
+__device__ __forceinline__ uint16_t to_bf16(float f) {
+  uint32_t u = __float_as_uint(f);
+  if ((u & 0x7f800000u) == 0x7f800000u) return (uint16_t)((u >> 16) | ((u & 0xffffu) ? 0x40u : 0u));
+  u += 0x7fffu + ((u >> 16) & 1u);          // round to nearest, ties to even
+  return (uint16_t)(u >> 16);
+}
+
+__device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float((uint32_t)h << 16); }
+
+// ---------------------------------------------------------------- GEMM
+// C[M x N] = op(A) op(B), bf16 operands, fp32 accumulation.
+//   A: AT = false -> stored [M x K] (row stride lda), AT = true -> [K x M]
+//   B: BT = false -> stored [K x N] (row stride ldb), BT = true -> [N x K]
+// Epilogue per element (row r, column c): v = acc (+ bias[c]); if mask,
+// v = z[r, c] > 0 ? v : 0 (ReLU derivative of a stored pre-activation);
+// written to Cf (fp32) as is and to Cb (bf16) after max(v, 0) when relu_b,
+// row stride ldc.  Workgroup tile 64 x 64 (four wavefronts of 32 x 32, each
+// 2 x 2 MFMA 16 x 16 tiles), K step 32 through LDS.
+constexpr int GBM = 64, GBN = 64, GBK = 32, GPAD = 8;
+
+struct GemmArgs {
+  int M, N, K, lda, ldb, ldc;
+  const uint16_t* A;
+  const uint16_t* B;
+  const float* bias;
+  const float* z;       // mask source (ldc stride) or null
+  int relu_b;           // bf16 output is max(v, 0)
+  float* Cf;
+  uint16_t* Cb;
+};
+
+template <bool AT, bool BT>
+__global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
+  __shared__ __attribute__((aligned(16))) uint16_t As[GBM][GBK + GPAD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[GBN][GBK + GPAD];
+  const int t = threadIdx.x;
+  const int lane = t & 63, wave = t >> 6;
+  const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
+  const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  f32x4 acc[2][2];
+  for (int i = 0; i < 2; ++i)
+    for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
+  for (int k0 = 0; k0 < g.K; k0 += GBK) {
+    // ---- A tile -> As[m][k]
+    if (!AT) {
+      const int r = t >> 2, kc = (t & 3) * 8;
+      const int gm = m0 + r;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int gk = k0 + kc + i;
+        As[r][kc + i] = (gm < g.M && gk < g.K) ? g.A[(int64_t)gm * g.lda + gk] : (uint16_t)0;
+      }
+    } else {
+      const int kk = t >> 3, mc = (t & 7) * 8;
+      const int gk = k0 + kk;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int gm = m0 + mc + i;
+        As[mc + i][kk] = (gm < g.M && gk < g.K) ? g.A[(int64_t)gk * g.lda + gm] : (uint16_t)0;
+      }
+    }
+    // ---- B tile -> Bs[n][k]
+    if (BT) {
+      const int r = t >> 2, kc = (t & 3) * 8;
+      const int gn = n0 + r;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int gk = k0 + kc + i;
+        Bs[r][kc + i] = (gn < g.N && gk < g.K) ? g.B[(int64_t)gn * g.ldb + gk] : (uint16_t)0;
+      }
+    } else {
+      const int kk = t >> 3, nc = (t & 7) * 8;
+      const int gk = k0 + kk;
+#pragma unroll
+      for (int i = 0; i < 8; ++i) {
+        const int gn = n0 + nc + i;
+        Bs[nc + i][kk] = (gn < g.N && gk < g.K) ? g.B[(int64_t)gk * g.ldb + gn] : (uint16_t)0;
+      }
+    }
+    __syncthreads();
+    const int ko = (lane >> 4) * 8;
+    bf16x8 a[2], b[2];
+#pragma unroll
+    for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[wr + 16 * i + (lane & 15)][ko]);
+#pragma unroll
+    for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wc + 16 * j + (lane & 15)][ko]);
+#pragma unroll
+    for (int i = 0; i < 2; ++i)
+#pragma unroll
+      for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    __syncthreads();
+  }
+#pragma unroll
+  for (int i = 0; i < 2; ++i)
+#pragma unroll
+    for (int j = 0; j < 2; ++j)
+#pragma unroll
+      for (int r = 0; r < 4; ++r) {
+        const int row = m0 + wr + 16 * i + 4 * (lane >> 4) + r;
+        const int col = n0 + wc + 16 * j + (lane & 15);
+        if (row >= g.M || col >= g.N) continue;
+        float v = acc[i][j][r];
+        if (g.bias) v += g.bias[col];
+        const int64_t o = (int64_t)row * g.ldc + col;
+        if (g.z) v = g.z[o] > 0.f ? v : 0.f;
+        if (g.Cf) g.Cf[o] = v;
+        if (g.Cb) g.Cb[o] = to_bf16(g.relu_b && v < 0.f ? 0.f : v);
+      }
+}
+
+// ---------------------------------------------------------------- elementwise
+__global__ void k_to_bf16(int64_t n, const float* x, uint16_t* y) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i < n) y[i] = to_bf16(x[i]);
+}
+
+// output gradient of L = mean (o - y)^2: dz = 2 (o - y) / n (fp32 and bf16)
+// and per-block sums of (o - y)^2
+__global__ void __launch_bounds__(256) k_mse(int64_t n, const float* o, const float* y, float* dz,
+                                             uint16_t* dzb, double* part) {
+  __shared__ double red[256];
+  double acc = 0.0;
+  for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < n; i += (int64_t)gridDim.x * blockDim.x) {
+    const float d = o[i] - y[i];
+    acc += (double)d * (double)d;
+    const float gz = 2.f * d / (float)n;
+    dz[i] = gz;
+    dzb[i] = to_bf16(gz);
+  }
+  red[threadIdx.x] = acc;
+  __syncthreads();
+  for (int s = 128; s > 0; s >>= 1) {
+    if (threadIdx.x < (unsigned)s) red[threadIdx.x] += red[threadIdx.x + s];
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) part[blockIdx.x] = red[0];
+}
+
+__global__ void k_loss_final(int nb, int64_t n, const double* part, float* loss) {
+  if (threadIdx.x != 0) return;
+  double s = 0.0;
+  for (int i = 0; i < nb; ++i) s += part[i];
+  *loss = (float)(s / (double)n);
+}
+
+// db[c] = sum over rows of dz[r, c]
+__global__ void k_colsum(int rows, int cols, const float* dz, float* db) {
+  int c = blockIdx.x * blockDim.x + threadIdx.x;
+  if (c >= cols) return;
+  float s = 0.f;
+  for (int r = 0; r < rows; ++r) s += dz[(int64_t)r * cols + c];
+  db[c] = s;
+}
+
+// Adam on fp32 masters; bf16 copies of the weight matrices are refreshed
+struct AdamArgs {
+  int64_t n;
+  float lr, b1, b2, eps, c1, c2;   // c1 = 1 - b1^t, c2 = 1 - b2^t
+  float *w, *m, *v;
+  const float* g;
+  const int64_t* bf_index;         // position in the bf16 copy (-1 for biases)
+  uint16_t* wb;
+};
+
+__global__ void k_adam(AdamArgs a) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= a.n) return;
+  const float g = a.g[i];
+  const float m = a.b1 * a.m[i] + (1.f - a.b1) * g;
+  const float v = a.b2 * a.v[i] + (1.f - a.b2) * g * g;
+  a.m[i] = m;
+  a.v[i] = v;
+  const float w = a.w[i] - a.lr * (m / a.c1) / (sqrtf(v / a.c2) + a.eps);
+  a.w[i] = w;
+  const int64_t j = a.bf_index[i];
+  if (j >= 0) a.wb[j] = to_bf16(w);
+}
+
+__global__ void k_refresh_bf16(int64_t n, const float* w, const int64_t* bf_index, uint16_t* wb) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  const int64_t j = bf_index[i];
+  if (j >= 0) wb[j] = to_bf16(w[i]);
+}
+
+// ---------------------------------------------------------------- features
+// geometry per problem: c (3), semi-axes a (3), Q row-major (9); jumps per
+// problem: a[j][m] (16) then b[j][m] (16), j = 0 (g1), 1 (g2), m < 8 with
+// k_m = (pi/2) (m & 1, (m >> 1) & 1, (m >> 2) & 1)
+__device__ __forceinline__ void jump_at(const double* J, const double* x, double& g1, double& g2) {
+  g1 = 0.0;
+  g2 = 0.0;
+  for (int m = 0; m < 8; ++m) {
+    const double ph = 0.5 * M_PI * ((double)(m & 1) * x[0] + (double)((m >> 1) & 1) * x[1] + (double)((m >> 2) & 1) * x[2]);
+    const double cp = cos(ph), sp = sin(ph);
+    g1 += J[m] * cp + J[16 + m] * sp;
+    g2 += J[8 + m] * cp + J[24 + m] * sp;
+  }
+}
+
+__global__ void k_features(int P, int ns, const double* geom, const double* jumps, const double* S, float* X) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)P * ns) return;
+  const int p = (int)(t / ns), i = (int)(t % ns);
+  const double* G = geom + 15 * (int64_t)p;
+  const double* a = G + 3;
+  const double* Q = G + 6;
+  double Xb[3], x[3], gb[3], n[3];
+  for (int k = 0; k < 3; ++k) Xb[k] = a[k] * S[3 * (int64_t)i + k];
+  for (int r = 0; r < 3; ++r) x[r] = G[r] + Q[3 * r] * Xb[0] + Q[3 * r + 1] * Xb[1] + Q[3 * r + 2] * Xb[2];
+  double hs = 0.0, ng2 = 0.0, ghg = 0.0;
+  for (int k = 0; k < 3; ++k) {
+    const double hk = 2.0 / (a[k] * a[k]);
+    gb[k] = hk * Xb[k];
+    hs += hk;
+    ng2 += gb[k] * gb[k];
+    ghg += gb[k] * gb[k] * hk;
+  }
+  const double ng = sqrt(ng2);
+  for (int r = 0; r < 3; ++r) n[r] = (Q[3 * r] * gb[0] + Q[3 * r + 1] * gb[1] + Q[3 * r + 2] * gb[2]) / ng;
+  const double kappa = (ng2 * hs - ghg) / (2.0 * ng2 * ng);
+  double g1, g2;
+  jump_at(jumps + 32 * (int64_t)p, x, g1, g2);
+  float* o = X + (int64_t)p * ns * 9 + (int64_t)i * 9;
+  o[0] = (float)x[0];
+  o[1] = (float)x[1];
+  o[2] = (float)x[2];
+  o[3] = (float)n[0];
+  o[4] = (float)n[1];
+  o[5] = (float)n[2];
+  o[6] = (float)kappa;
+  o[7] = (float)g1;
+  o[8] = (float)g2;
+}
+
+// ---------------------------------------------------------------- spherical harmonics
+constexpr int SH_L = 8;
+constexpr int SH_N = (SH_L + 1) * (SH_L + 1);
+
+// real orthonormal spherical harmonics (no Condon-Shortley phase) of the
+// direction d (not necessarily unit), index l^2 + l + m
+__device__ void real_sh(const double* d, double* Y) {
+  const double r = sqrt(d[0] * d[0] + d[1] * d[1] + d[2] * d[2]);
+  const double ct = d[2] / r;
+  const double st = sqrt(fmax(0.0, 1.0 - ct * ct));
+  double cphi = 1.0, sphi = 0.0;
+  const double rho = sqrt(d[0] * d[0] + d[1] * d[1]);
+  if (rho > 0.0) {
+    cphi = d[0] / rho;
+    sphi = d[1] / rho;
+  }
+  double cm[SH_L + 1], sm[SH_L + 1];
+  cm[0] = 1.0;
+  sm[0] = 0.0;
+  for (int m = 1; m <= SH_L; ++m) {
+    cm[m] = cm[m - 1] * cphi - sm[m - 1] * sphi;
+    sm[m] = sm[m - 1] * cphi + cm[m - 1] * sphi;
+  }
+  // normalised associated Legendre values Q_l^m = N_lm P_l^m(ct), m <= l
+  double qmm = 0.5 / sqrt(M_PI);          // Q_0^0
+  for (int m = 0; m <= SH_L; ++m) {
+    if (m > 0) qmm = qmm * st * sqrt((2.0 * m + 1.0) / (2.0 * m));
+    double q2 = 0.0, q1 = qmm;
+    for (int l = m; l <= SH_L; ++l) {
+      double q;
+      if (l == m) {
+        q = qmm;
+      } else if (l == m + 1) {
+        q = ct * sqrt(2.0 * m + 3.0) * qmm;
+      } else {
+        const double al = sqrt((4.0 * l * l - 1.0) / ((double)l * l - (double)m * m));
+        const double bl = sqrt((((double)(l - 1) * (l - 1)) - (double)m * m) / (4.0 * (l - 1) * (l - 1) - 1.0));
+        q = al * (ct * q1 - bl * q2);
+      }
+      if (l > m) {
+        q2 = q1;
+        q1 = q;
+      }
+      if (m == 0) {
+        Y[l * l + l] = q;
+      } else {
+        Y[l * l + l + m] = sqrt(2.0) * q * cm[m];
+        Y[l * l + l - m] = sqrt(2.0) * q * sm[m];
+      }
+    }
+  }
+}
+
+// body-frame direction diag(1/a) Q^T (x - c) of a point x
+__device__ __forceinline__ void body_dir(const double* G, const double* x, double* d) {
+  const double* a = G + 3;
+  const double* Q = G + 6;
+  double dx[3] = {x[0] - G[0], x[1] - G[1], x[2] - G[2]};
+  for (int k = 0; k < 3; ++k) d[k] = (Q[k] * dx[0] + Q[3 + k] * dx[1] + Q[6 + k] * dx[2]) / a[k];
+}
+
+// partial normal equations of a least-squares SH fit: per block, sums over
+// its points of Y Y^T (81 x 81) and Y v (81).  Points are either unit
+// directions (dirs) or positions mapped to body-frame directions (pos + G).
+constexpr int FIT_PTS = 64;
+
+__global__ void __launch_bounds__(256) k_sh_normal(int n, const double* dirs, const double* pos, const double* G,
+                                                   const double* vals, const float* valsf, double scale,
+                                                   double* part) {
+  __shared__ double Ys[FIT_PTS][SH_N];
+  __shared__ double vs[FIT_PTS];
+  const int p0 = blockIdx.x * FIT_PTS;
+  const int np = n - p0 < FIT_PTS ? n - p0 : FIT_PTS;
+  for (int q = threadIdx.x; q < np; q += blockDim.x) {
+    double d[3];
+    if (dirs) {
+      for (int k = 0; k < 3; ++k) d[k] = dirs[3 * (int64_t)(p0 + q) + k];
+    } else {
+      body_dir(G, pos + 3 * (int64_t)(p0 + q), d);
+    }
+    real_sh(d, Ys[q]);
+    vs[q] = vals ? vals[p0 + q] : scale * (double)valsf[p0 + q];
+  }
+  __syncthreads();
+  double* out = part + (int64_t)blockIdx.x * (SH_N * SH_N + SH_N);
+  for (int e = threadIdx.x; e < SH_N * SH_N + SH_N; e += blockDim.x) {
+    double s = 0.0;
+    if (e < SH_N * SH_N) {
+      const int i = e / SH_N, j = e % SH_N;
+      for (int q = 0; q < np; ++q) s += Ys[q][i] * Ys[q][j];
+    } else {
+      const int i = e - SH_N * SH_N;
+      for (int q = 0; q < np; ++q) s += Ys[q][i] * vs[q];
+    }
+    out[e] = s;
+  }
+}
+
+// sum of the partial normal equations (fixed order) and Cholesky solve,
+// one workgroup: coef = (Y^T Y)^-1 Y^T v
+__global__ void __launch_bounds__(256) k_sh_solve(int nblk, const double* part, double* coef) {
+  __shared__ double A[SH_N][SH_N + 1];
+  __shared__ double b[SH_N];
+  for (int e = threadIdx.x; e < SH_N * SH_N + SH_N; e += blockDim.x) {
+    double s = 0.0;
+    for (int k = 0; k < nblk; ++k) s += part[(int64_t)k * (SH_N * SH_N + SH_N) + e];
+    if (e < SH_N * SH_N)
+      A[e / SH_N][e % SH_N] = s;
+    else
+      b[e - SH_N * SH_N] = s;
+  }
+  __syncthreads();
+  // right-looking Cholesky, A = L L^T (lower triangle)
+  for (int k = 0; k < SH_N; ++k) {
+    if (threadIdx.x == 0) A[k][k] = sqrt(A[k][k]);
+    __syncthreads();
+    for (int i = k + 1 + threadIdx.x; i < SH_N; i += blockDim.x) A[i][k] /= A[k][k];
+    __syncthreads();
+    for (int e = threadIdx.x; e < (SH_N - k - 1) * (SH_N - k - 1); e += blockDim.x) {
+      const int i = k + 1 + e / (SH_N - k - 1), j = k + 1 + e % (SH_N - k - 1);
+      if (j <= i) A[i][j] -= A[i][k] * A[j][k];
+    }
+    __syncthreads();
+  }
+  if (threadIdx.x == 0) {
+    for (int i = 0; i < SH_N; ++i) {       // L y = b
+      double s = b[i];
+      for (int j = 0; j < i; ++j) s -= A[i][j] * b[j];
+      b[i] = s / A[i][i];
+    }
+    for (int i = SH_N - 1; i >= 0; --i) {  // L^T x = y
+      double s = b[i];
+      for (int j = i + 1; j < SH_N; ++j) s -= A[j][i] * b[j];
+      b[i] = s / A[i][i];
+    }
+    for (int i = 0; i < SH_N; ++i) coef[i] = b[i];
+  }
+}
+
+// values of the SH expansion at points (unit directions or body-frame
+// directions of positions): out double and/or float (times oscale)
+__global__ void k_sh_eval(int n, const double* dirs, const double* pos, const double* G, const double* coef,
+                          double* out, float* outf, double oscale) {
+  int q = blockIdx.x * blockDim.x + threadIdx.x;
+  if (q >= n) return;
+  double d[3];
+  if (dirs) {
+    for (int k = 0; k < 3; ++k) d[k] = dirs[3 * (int64_t)q + k];
+  } else {
+    body_dir(G, pos + 3 * (int64_t)q, d);
+  }
+  double Y[SH_N];
+  real_sh(d, Y);
+  double s = 0.0;
+  for (int i = 0; i < SH_N; ++i) s += Y[i] * coef[i];
+  if (out) out[q] = s;
+  if (outf) outf[q] = (float)(s * oscale);
+}
+
+inline unsigned nbl(int64_t n, int b = 256) { return (unsigned)((n + b - 1) / b); }
+
+}  // namespace
+
+// ======================================================================== MLP object
+struct kfbi_mlp {
+  hipStream_t stream;
+  int L;                              // layers
+  std::vector<int> w;                 // widths, L + 1
+  int64_t n_params, n_wbf;
+  std::vector<int64_t> off_w, off_b, off_wb;   // offsets in the fp32 pack / bf16 copy
+  float *p, *m, *v, *g;               // fp32 master, Adam moments, gradient
+  uint16_t* wb;                       // bf16 weight copies
+  int64_t* bf_index;
+  int64_t step;
+  // activations for a batch of up to cap rows
+  int cap;
+  std::vector<uint16_t*> a_b;         // bf16 inputs of every layer (L)
+  std::vector<float*> z;              // fp32 pre-activations (L)
+  float *dz, *da;
+  uint16_t* dzb;
+  double* part;
+};
+
+namespace {
+
+template <typename T>
+kfbi_status dalloc_t(T** p, int64_t n) {
+  *p = nullptr;
+  if (hipMalloc((void**)p, (size_t)(n < 1 ? 1 : n) * sizeof(T)) != hipSuccess) {
+    (void)hipGetLastError();
+    kfbi_set_error("device allocation of %lld bytes failed", (long long)(n * sizeof(T)));
+    return KFBI_E_OOM;
+  }
+  return KFBI_OK;
+}
+
+template <typename T>
+void dfree_t(T*& p) {
+  if (p) (void)hipFree(p);
+  p = nullptr;
+}
+
+void free_batch(kfbi_mlp* h) {
+  for (auto& x : h->a_b) dfree_t(x);
+  for (auto& x : h->z) dfree_t(x);
+  dfree_t(h->dz);
+  dfree_t(h->da);
+  dfree_t(h->dzb);
+  dfree_t(h->part);
+  h->cap = 0;
+}
+
+kfbi_status ensure_batch(kfbi_mlp* h, int B) {
+  if (B <= h->cap) return KFBI_OK;
+  free_batch(h);
+  int maxw = 0;
+  for (int x : h->w) maxw = x > maxw ? x : maxw;
+  for (int l = 0; l < h->L; ++l) {
+    KCHK(dalloc_t(&h->a_b[l], (int64_t)B * h->w[l]));
+    KCHK(dalloc_t(&h->z[l], (int64_t)B * h->w[l + 1]));
+  }
+  KCHK(dalloc_t(&h->dz, (int64_t)B * maxw));
+  KCHK(dalloc_t(&h->da, (int64_t)B * maxw));
+  KCHK(dalloc_t(&h->dzb, (int64_t)B * maxw));
+  KCHK(dalloc_t(&h->part, 1024));
+  h->cap = B;
+  return KFBI_OK;
+}
+
+template <bool AT, bool BT>
+void gemm(hipStream_t st, int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B, int ldb,
+          const float* bias, const float* z, int relu_b, float* Cf, uint16_t* Cb, int ldc) {
+  GemmArgs g{M, N, K, lda, ldb, ldc, A, B, bias, z, relu_b, Cf, Cb};
+  dim3 grid((unsigned)((N + GBN - 1) / GBN), (unsigned)((M + GBM - 1) / GBM));
+  hipLaunchKernelGGL((k_gemm<AT, BT>), grid, dim3(256), 0, st, g);
+}
+
+// forward pass of B rows; X fp32 [B x w0]; the output is z[L-1]
+void forward(kfbi_mlp* h, const float* X, int B) {
+  hipStream_t st = h->stream;
+  hipLaunchKernelGGL(k_to_bf16, dim3(nbl((int64_t)B * h->w[0])), dim3(256), 0, st, (int64_t)B * h->w[0], X,
+                     h->a_b[0]);
+  for (int l = 0; l < h->L; ++l) {
+    const bool last = l == h->L - 1;
+    // z_l = a_l W_l + b_l (fp32, kept for the backward mask) and
+    // a_{l+1} = relu(z_l) (bf16, the next layer's operand)
+    gemm<false, false>(st, B, h->w[l + 1], h->w[l], h->a_b[l], h->w[l], h->wb + h->off_wb[l], h->w[l + 1],
+                       h->p + h->off_b[l], nullptr, 1, h->z[l], last ? nullptr : h->a_b[l + 1], h->w[l + 1]);
+  }
+}
+
+// loss and gradient into h->g; loss (device float)
+void backward(kfbi_mlp* h, const float* Yt, int B, float* loss) {
+  hipStream_t st = h->stream;
+  const int L = h->L;
+  const int64_t no = (int64_t)B * h->w[L];
+  unsigned nbk = nbl(no);
+  if (nbk > 1024) nbk = 1024;
+  hipLaunchKernelGGL(k_mse, dim3(nbk), dim3(256), 0, st, no, h->z[L - 1], Yt, h->dz, h->dzb, h->part);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, (int)nbk, no, (const double*)h->part, loss);
+  for (int l = L - 1; l >= 0; --l) {
+    const int in = h->w[l], out = h->w[l + 1];
+    // dW_l = a_l^T dz (fp32 into the gradient pack), db_l = column sums of dz
+    gemm<true, false>(st, in, out, B, h->a_b[l], in, h->dzb, out, nullptr, nullptr, 0, h->g + h->off_w[l], nullptr,
+                      out);
+    hipLaunchKernelGGL(k_colsum, dim3(nbl(out)), dim3(256), 0, st, B, out, (const float*)h->dz, h->g + h->off_b[l]);
+    if (l > 0) {
+      // dz_{l-1} = (dz W_l^T) masked by z_{l-1} > 0
+      gemm<false, true>(st, B, in, out, h->dzb, out, h->wb + h->off_wb[l], out, nullptr, h->z[l - 1], 0, h->da,
+                        nullptr, in);
+      std::swap(h->dz, h->da);
+      hipLaunchKernelGGL(k_to_bf16, dim3(nbl((int64_t)B * in)), dim3(256), 0, st, (int64_t)B * in,
+                         (const float*)h->dz, h->dzb);
+    }
+  }
+}
+
+}  // namespace
+
+extern "C" kfbi_status kfbi_mlp_create(int n_layers, const int* widths, void* stream, kfbi_mlp** out) {
+  if (!out || !widths || n_layers < 1 || n_layers > 16) {
+    kfbi_set_error("mlp needs 1..16 layers and a width list");
+    return KFBI_E_INVALID;
+  }
+  for (int i = 0; i <= n_layers; ++i)
+    if (widths[i] < 1 || widths[i] > (1 << 20)) {
+      kfbi_set_error("mlp width %d out of range", widths[i]);
+      return KFBI_E_INVALID;
+    }
+  kfbi_mlp* h = new (std::nothrow) kfbi_mlp();
+  if (!h) return KFBI_E_OOM;
+  h->stream = (hipStream_t)stream;
+  h->L = n_layers;
+  h->w.assign(widths, widths + n_layers + 1);
+  int64_t np = 0, nb = 0;
+  for (int l = 0; l < n_layers; ++l) {
+    h->off_w.push_back(np);
+    np += (int64_t)widths[l] * widths[l + 1];
+    h->off_b.push_back(np);
+    np += widths[l + 1];
+    h->off_wb.push_back(nb);
+    nb += (int64_t)widths[l] * widths[l + 1];
+  }
+  h->n_params = np;
+  h->n_wbf = nb;
+  h->a_b.assign(n_layers, nullptr);
+  h->z.assign(n_layers, nullptr);
+  kfbi_status st = KFBI_OK;
+  if ((st = dalloc_t(&h->p, np)) || (st = dalloc_t(&h->m, np)) || (st = dalloc_t(&h->v, np)) ||
+      (st = dalloc_t(&h->g, np)) || (st = dalloc_t(&h->wb, nb)) || (st = dalloc_t(&h->bf_index, np))) {
+    kfbi_mlp_destroy(h);
+    return st;
+  }
+  std::vector<int64_t> idx((size_t)np, -1);
+  for (int l = 0; l < n_layers; ++l)
+    for (int64_t i = 0; i < (int64_t)widths[l] * widths[l + 1]; ++i) idx[(size_t)(h->off_w[l] + i)] = h->off_wb[l] + i;
+  if (hipMemcpy(h->bf_index, idx.data(), sizeof(int64_t) * np, hipMemcpyHostToDevice) != hipSuccess ||
+      hipMemset(h->p, 0, sizeof(float) * np) != hipSuccess || hipMemset(h->m, 0, sizeof(float) * np) != hipSuccess ||
+      hipMemset(h->v, 0, sizeof(float) * np) != hipSuccess || hipMemset(h->wb, 0, 2 * nb) != hipSuccess) {
+    (void)hipGetLastError();
+    kfbi_set_error("mlp initialisation copy failed");
+    kfbi_mlp_destroy(h);
+    return KFBI_E_DEVICE;
+  }
+  *out = h;
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_mlp_sizes(const kfbi_mlp* h, int64_t* n_params) {
+  if (!h || !n_params) {
+    kfbi_set_error("mlp is NULL");
+    return KFBI_E_INVALID;
+  }
+  *n_params = h->n_params;
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_mlp_set_params(kfbi_mlp* h, const float* params) {
+  if (!h || !params) {
+    kfbi_set_error("mlp or params is NULL");
+    return KFBI_E_INVALID;
+  }
+  HIPCHK(hipMemcpyAsync(h->p, params, sizeof(float) * h->n_params, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipMemsetAsync(h->m, 0, sizeof(float) * h->n_params, h->stream));
+  HIPCHK(hipMemsetAsync(h->v, 0, sizeof(float) * h->n_params, h->stream));
+  hipLaunchKernelGGL(k_refresh_bf16, dim3(nbl(h->n_params)), dim3(256), 0, h->stream, h->n_params,
+                     (const float*)h->p, (const int64_t*)h->bf_index, h->wb);
+  h->step = 0;
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_mlp_get_params(const kfbi_mlp* h, float* params) {
+  if (!h || !params) {
+    kfbi_set_error("mlp or params is NULL");
+    return KFBI_E_INVALID;
+  }
+  HIPCHK(hipMemcpyAsync(params, h->p, sizeof(float) * h->n_params, hipMemcpyDeviceToDevice, h->stream));
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_mlp_forward(kfbi_mlp* h, const float* X, int B, float* Y) {
+  if (!h || !X || !Y || B < 1) {
+    kfbi_set_error("mlp forward needs X, Y and B >= 1");
+    return KFBI_E_INVALID;
+  }
+  KCHK(ensure_batch(h, B));
+  forward(h, X, B);
+  HIPCHK(hipMemcpyAsync(Y, h->z[h->L - 1], sizeof(float) * (size_t)B * h->w[h->L], hipMemcpyDeviceToDevice,
+                        h->stream));
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_mlp_loss_grad(kfbi_mlp* h, const float* X, const float* Yt, int B, float* loss,
+                                          float* grads) {
+  if (!h || !X || !Yt || !loss || B < 1) {
+    kfbi_set_error("mlp loss_grad needs X, Yt, loss and B >= 1");
+    return KFBI_E_INVALID;
+  }
+  KCHK(ensure_batch(h, B));
+  forward(h, X, B);
+  backward(h, Yt, B, loss);
+  if (grads)
+    HIPCHK(hipMemcpyAsync(grads, h->g, sizeof(float) * h->n_params, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_mlp_train_step(kfbi_mlp* h, const float* X, const float* Yt, int B, float lr,
+                                           float* loss) {
+  if (!h || !X || !Yt || !loss || B < 1 || !(lr > 0.f)) {
+    kfbi_set_error("mlp train_step needs X, Yt, loss, B >= 1 and lr > 0");
+    return KFBI_E_INVALID;
+  }
+  KCHK(ensure_batch(h, B));
+  forward(h, X, B);
+  backward(h, Yt, B, loss);
+  h->step += 1;
+  AdamArgs a;
+  a.n = h->n_params;
+  a.lr = lr;
+  a.b1 = 0.9f;
+  a.b2 = 0.999f;
+  a.eps = 1e-8f;
+  a.c1 = (float)(1.0 - pow(0.9, (double)h->step));
+  a.c2 = (float)(1.0 - pow(0.999, (double)h->step));
+  a.w = h->p;
+  a.m = h->m;
+  a.v = h->v;
+  a.g = h->g;
+  a.bf_index = h->bf_index;
+  a.wb = h->wb;
+  hipLaunchKernelGGL(k_adam, dim3(nbl(h->n_params)), dim3(256), 0, h->stream, a);
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_mlp_destroy(kfbi_mlp* h) {
+  if (!h) return KFBI_OK;
+  free_batch(h);
+  dfree_t(h->p);
+  dfree_t(h->m);
+  dfree_t(h->v);
+  dfree_t(h->g);
+  dfree_t(h->wb);
+  dfree_t(h->bf_index);
+  delete h;
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_gemm_bf16(int transA, int transB, int M, int N, int K, const uint16_t* A, int lda,
+                                      const uint16_t* B, int ldb, float* C, int ldc, void* stream) {
+  if (M < 1 || N < 1 || K < 1 || !A || !B || !C) {
+    kfbi_set_error("gemm needs positive sizes and buffers");
+    return KFBI_E_INVALID;
+  }
+  hipStream_t st = (hipStream_t)stream;
+  if (!transA && !transB)
+    gemm<false, false>(st, M, N, K, A, lda, B, ldb, nullptr, nullptr, 0, C, nullptr, ldc);
+  else if (transA && !transB)
+    gemm<true, false>(st, M, N, K, A, lda, B, ldb, nullptr, nullptr, 0, C, nullptr, ldc);
+  else if (!transA && transB)
+    gemm<false, true>(st, M, N, K, A, lda, B, ldb, nullptr, nullptr, 0, C, nullptr, ldc);
+  else {
+    kfbi_set_error("gemm: both operands transposed is not supported");
+    return KFBI_E_INVALID;
+  }
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+// ======================================================================== features and transfer
+extern "C" kfbi_status kfbi_ellipsoid_features(const double* geom, const double* jumps, int P, const double* S,
+                                               int ns, void* stream, float* X) {
+  if (!geom || !jumps || !S || !X || P < 1 || ns < 1) {
+    kfbi_set_error("features need geometry, jumps, samples and outputs");
+    return KFBI_E_INVALID;
+  }
+  hipLaunchKernelGGL(k_features, dim3(nbl((int64_t)P * ns)), dim3(256), 0, (hipStream_t)stream, P, ns, geom, jumps,
+                     S, X);
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+namespace {
+kfbi_status sh_fit_eval(hipStream_t st, int n_in, const double* dirs_in, const double* pos_in, const double* G,
+                        const double* vals, const float* valsf, double vscale, int n_out, const double* dirs_out,
+                        const double* pos_out, double* out, float* outf, double oscale) {
+  const int nblk = (n_in + FIT_PTS - 1) / FIT_PTS;
+  double *part = nullptr, *coef = nullptr;
+  KCHK(dalloc_t(&part, (int64_t)nblk * (SH_N * SH_N + SH_N)));
+  if (dalloc_t(&coef, SH_N) != KFBI_OK) {
+    dfree_t(part);
+    return KFBI_E_OOM;
+  }
+  hipLaunchKernelGGL(k_sh_normal, dim3(nblk), dim3(256), 0, st, n_in, dirs_in, pos_in, G, vals, valsf, vscale, part);
+  hipLaunchKernelGGL(k_sh_solve, dim3(1), dim3(256), 0, st, nblk, (const double*)part, coef);
+  hipLaunchKernelGGL(k_sh_eval, dim3(nbl(n_out)), dim3(256), 0, st, n_out, dirs_out, pos_out, G,
+                     (const double*)coef, out, outf, oscale);
+  hipError_t e = hipStreamSynchronize(st);
+  dfree_t(part);
+  dfree_t(coef);
+  if (e != hipSuccess) {
+    kfbi_set_error("HIP error %s in the spherical-harmonic fit", hipGetErrorString(e));
+    return KFBI_E_DEVICE;
+  }
+  return KFBI_OK;
+}
+}  // namespace
+
+extern "C" kfbi_status kfbi_sh_transfer(kfbi_plan* pl, const double* geom, const double* S, int ns,
+                                        const float* psi_s, double scale, double* psi_dof) {
+  if (!pl || !pl->ready || !geom || !S || !psi_s || !psi_dof || ns < (SH_N)) {
+    kfbi_set_error("transfer needs a ready plan, geometry, >= 81 samples and outputs");
+    return KFBI_E_INVALID;
+  }
+  if (pl->g.d != 3) {
+    kfbi_set_error("the spherical-harmonic transfer is defined in 3D");
+    return KFBI_E_INVALID;
+  }
+  // DOF positions: the surface table gathered through d2s
+  double* dpos = nullptr;
+  KCHK(dalloc_t(&dpos, 3 * pl->n_dof));
+  KCHK(kfbi_plan_export(pl, KFBI_EXPORT_DOF_POS, dpos, (int64_t)sizeof(double) * 3 * pl->n_dof));
+  kfbi_status st = sh_fit_eval(pl->stream, ns, S, nullptr, geom, nullptr, psi_s, scale, (int)pl->n_dof, nullptr,
+                               dpos, psi_dof, nullptr, 1.0);
+  dfree_t(dpos);
+  return st;
+}
+
+extern "C" kfbi_status kfbi_sh_sample(kfbi_plan* pl, const double* geom, const double* psi_dof, const double* S,
+                                      int ns, double scale, float* psi_s) {
+  if (!pl || !pl->ready || !geom || !S || !psi_s || !psi_dof || ns < 1 || pl->n_dof < SH_N) {
+    kfbi_set_error("sampling needs a ready plan with >= 81 DOFs, geometry, samples and outputs");
+    return KFBI_E_INVALID;
+  }
+  if (pl->g.d != 3) {
+    kfbi_set_error("the spherical-harmonic transfer is defined in 3D");
+    return KFBI_E_INVALID;
+  }
+  double* dpos = nullptr;
+  KCHK(dalloc_t(&dpos, 3 * pl->n_dof));
+  KCHK(kfbi_plan_export(pl, KFBI_EXPORT_DOF_POS, dpos, (int64_t)sizeof(double) * 3 * pl->n_dof));
+  kfbi_status st = sh_fit_eval(pl->stream, (int)pl->n_dof, nullptr, dpos, geom, psi_dof, nullptr, 1.0, ns, S,
+                               nullptr, nullptr, psi_s, scale);
+  dfree_t(dpos);
+  return st;
+}
+
+extern "C" kfbi_status kfbi_real_sh(const double* dirs, int n, void* stream, double* Y) {
+  if (!dirs || !Y || n < 1) {
+    kfbi_set_error("real_sh needs directions and output");
+    return KFBI_E_INVALID;
+  }
+  // evaluate each basis function as an expansion with a unit coefficient
+  double* coef = nullptr;
+  KCHK(dalloc_t(&coef, SH_N));
+  hipStream_t st = (hipStream_t)stream;
+  std::vector<double> e(SH_N, 0.0);
+  kfbi_status rs = KFBI_OK;
+  for (int i = 0; i < SH_N && rs == KFBI_OK; ++i) {
+    e.assign(SH_N, 0.0);
+    e[i] = 1.0;
+    if (hipMemcpyAsync(coef, e.data(), sizeof(double) * SH_N, hipMemcpyHostToDevice, st) != hipSuccess) {
+      rs = KFBI_E_DEVICE;
+      break;
+    }
+    hipLaunchKernelGGL(k_sh_eval, dim3(nbl(n)), dim3(256), 0, st, n, dirs, (const double*)nullptr,
+                       (const double*)nullptr, (const double*)coef, Y + (int64_t)i * n, (float*)nullptr, 1.0);
+    if (hipStreamSynchronize(st) != hipSuccess) rs = KFBI_E_DEVICE;
+  }
+  dfree_t(coef);
+  if (rs != KFBI_OK) kfbi_set_error("real_sh failed");
+  return rs;
+}

@@ -19,7 +19,7 @@ STATUS = {0: "OK", 1: "INVALID", 2: "UNRESOLVED", 3: "SINGULAR", 4: "NOT_CONVERG
           5: "NONFINITE", 6: "DEVICE", 7: "OOM"}
 EXPORT = {"region": 0, "surf_pos": 1, "surf_nrm": 2, "surf_meta": 3, "dof_surf": 4,
           "stencil_d": 5, "stencil_n": 6, "ext_idx": 7, "ext_w": 8, "pde_pts": 9,
-          "irregular": 10, "corr": 11, "cond": 12}
+          "irregular": 10, "corr": 11, "cond": 12, "dof_pos": 13}
 
 c_double_p = ctypes.c_void_p
 
@@ -75,6 +75,27 @@ ABI = {
     "kfbi_plan_timing": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                           ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "kfbi_plan_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "kfbi_mlp_create": ([ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
+                         ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "kfbi_mlp_sizes": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
+    "kfbi_mlp_set_params": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "kfbi_mlp_get_params": ([ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "kfbi_mlp_forward": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "kfbi_mlp_loss_grad": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                            ctypes.c_void_p], ctypes.c_int),
+    "kfbi_mlp_train_step": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_float,
+                             ctypes.c_void_p], ctypes.c_int),
+    "kfbi_mlp_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "kfbi_gemm_bf16": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                        ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p],
+                       ctypes.c_int),
+    "kfbi_ellipsoid_features": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_int,
+                                 ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "kfbi_sh_transfer": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p,
+                          ctypes.c_double, ctypes.c_void_p], ctypes.c_int),
+    "kfbi_sh_sample": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
+                        ctypes.c_double, ctypes.c_void_p], ctypes.c_int),
+    "kfbi_real_sh": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "kfbi_last_error": ([], ctypes.c_char_p),
 }
 
@@ -213,7 +234,7 @@ class Plan:
             "stencil_n": ((s.n_dof, s.n_neu), torch.int32), "ext_idx": ((s.n_surf, p), torch.int32),
             "ext_w": ((s.n_surf, p), torch.float64), "pde_pts": ((s.n_dof, s.n_pde, d), torch.float64),
             "irregular": ((s.n_irregular,), torch.int32), "corr": ((s.n_corr, 3), torch.int32),
-            "cond": ((s.n_dof,), torch.float64),
+            "cond": ((s.n_dof,), torch.float64), "dof_pos": ((s.n_dof, d), torch.float64),
         }
         shape, dt = shapes[name]
         out = torch.empty(shape, dtype=dt, device=self.device)

@@ -1,0 +1,131 @@
+"""Learned initial density on the GPU against the oracle (runs on an
+MI355X): the bf16 MFMA GEMM, the MLP forward and gradient, the sample
+features, the spherical-harmonic basis and transfers, and the effect of a
+trained network on GMRES."""
+import numpy as np
+import pytest
+
+torch = pytest.importorskip("torch")
+
+pytestmark = pytest.mark.gpu
+
+from oracle import learned as OL  # noqa: E402
+from paper_2309_05965_amd import workloads as W  # noqa: E402
+
+
+def bf16_bits(x):
+    """bf16 bit patterns (round to nearest even) of a float array, as int16."""
+    f = np.asarray(x, dtype=np.float32)
+    u = f.view(np.uint32).astype(np.uint64)
+    u = ((u + 0x7FFF + ((u >> 16) & 1)) >> 16).astype(np.uint16)
+    return torch.from_numpy(u.view(np.int16)).cuda()
+
+
+@pytest.mark.parametrize("shape", [(70, 50, 45), (64, 64, 32), (256, 256, 9216), (130, 1024, 256)])
+@pytest.mark.parametrize("ta,tb", [(False, False), (True, False), (False, True)])
+def test_gemm_bf16_matches_float64_of_rounded_operands(shape, ta, tb):
+    from paper_2309_05965_amd import learned
+    M, N, K = shape
+    rng = np.random.default_rng(M + N + K)
+    A = rng.standard_normal((K, M) if ta else (M, K))
+    B = rng.standard_normal((N, K) if tb else (K, N))
+    C = learned.gemm_bf16(bf16_bits(A), bf16_bits(B), ta, tb).cpu().numpy()
+    Ar, Br = OL.bf16(A), OL.bf16(B)
+    ref = (Ar.T if ta else Ar) @ (Br.T if tb else Br)
+    scale = np.abs(Ar.T if ta else Ar) @ np.abs(Br.T if tb else Br)
+    assert np.max(np.abs(C - ref) / scale) < 1e-6
+
+
+def test_real_sh_matches_oracle():
+    from paper_2309_05965_amd import learned
+    d = np.random.default_rng(0).standard_normal((300, 3))
+    d[0] = [0.0, 0.0, 1.0]
+    d[1] = [0.0, 0.0, -2.0]
+    Y = learned.real_sh(torch.from_numpy(d).cuda()).cpu().numpy().T
+    assert np.max(np.abs(Y - OL.real_sh(d))) < 1e-12
+
+
+def test_features_match_oracle():
+    from paper_2309_05965_amd import learned
+    S = W.fibonacci_sphere()
+    geoms, jumps, ref = [], [], []
+    for seed in (1, 2, 3):
+        prob, geom, jmp = W.config5(seed, N=64)
+        geoms.append(learned.pack_geometry(geom))
+        jumps.append(learned.pack_jumps(jmp))
+        ref.append(OL.features(geom, lambda X, j=jmp: W.jump_values(j, X), S).reshape(-1))
+    X = learned.features(torch.tensor(np.array(geoms)).cuda(), torch.tensor(np.array(jumps)).cuda(),
+                         torch.from_numpy(S).cuda()).cpu().numpy()
+    ref = np.array(ref)
+    assert np.max(np.abs(X - ref) / (1 + np.abs(ref))) < 1e-6
+
+
+def test_transfers_match_oracle():
+    from paper_2309_05965_amd import kfbi, learned
+    prob, geom, jmp = W.config5(4, N=64)
+    gp = kfbi.Plan(prob)
+    S = W.fibonacci_sphere()
+    dof_pos = gp.export("dof_pos").cpu().numpy()
+    rng = np.random.default_rng(5)
+    psi_s = rng.standard_normal(S.shape[0]).astype(np.float32)
+    g = torch.tensor(learned.pack_geometry(geom)).cuda()
+    St = torch.from_numpy(S).cuda()
+    out = learned.transfer(gp, g, St, torch.from_numpy(psi_s).cuda(), 2.0).cpu().numpy()
+    ref = OL.transfer_to_dofs(geom, S, 2.0 * psi_s.astype(np.float64), dof_pos)
+    assert np.max(np.abs(out - ref)) < 1e-9 * (1 + np.max(np.abs(ref)))
+    psi_d = rng.standard_normal(gp.n_dof)
+    out = learned.sample(gp, g, torch.from_numpy(psi_d).cuda(), St, 0.5).cpu().numpy()
+    ref = 0.5 * OL.sample_density(geom, S, dof_pos, psi_d)
+    assert np.max(np.abs(out - ref)) < 1e-5 * (1 + np.max(np.abs(ref)))
+
+
+def _small_mlp(widths, seed):
+    from paper_2309_05965_amd import learned
+    m = learned.MLP(widths)
+    rng = np.random.default_rng(seed)
+    p = np.zeros(m.n_params, dtype=np.float32)
+    Ws, bs = [], []
+    for ow, (a, b), ob, nb in m.layout():
+        Wl = (rng.standard_normal((a, b)) * np.sqrt(2.0 / a)).astype(np.float32)
+        bl = (rng.standard_normal(b) * 0.1).astype(np.float32)
+        p[ow:ow + a * b] = Wl.ravel()
+        p[ob:ob + nb] = bl
+        Ws.append(Wl.astype(np.float64))
+        bs.append(bl.astype(np.float64))
+    m.set_params(torch.from_numpy(p).cuda())
+    return m, Ws, bs
+
+
+@pytest.mark.parametrize("widths,B", [((40, 24, 24, 16), 20), ((9216, 256, 256, 256, 1024), 64)])
+def test_mlp_forward_and_gradient_match_oracle(widths, B):
+    m, Ws, bs = _small_mlp(widths, 7)
+    rng = np.random.default_rng(8)
+    X = rng.standard_normal((B, widths[0])).astype(np.float32)
+    Y = rng.standard_normal((B, widths[-1])).astype(np.float32)
+    Xt, Yt = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    out = m.forward(Xt).cpu().numpy()
+    a, _ = OL.mlp_forward(Ws, bs, X, emulate=True)
+    assert np.max(np.abs(out - a[-1])) <= 2e-2 * np.max(np.abs(a[-1]))
+    loss, g = m.loss_grad(Xt, Yt)
+    lref, gW, gb = OL.mlp_loss_grad(Ws, bs, X, Y, emulate=True)
+    assert float(loss.item()) == pytest.approx(lref, rel=1e-3)
+    g = g.cpu().numpy()
+    for l, (ow, (i, o), ob, nb) in enumerate(m.layout()):
+        dW = g[ow:ow + i * o].reshape(i, o)
+        db = g[ob:ob + nb]
+        assert np.linalg.norm(dW - gW[l]) <= 2e-2 * np.linalg.norm(gW[l])
+        assert np.linalg.norm(db - gb[l]) <= 2e-2 * np.linalg.norm(gb[l])
+
+
+def test_training_reduces_the_loss():
+    m, _, _ = _small_mlp((32, 64, 64, 8), 3)
+    rng = np.random.default_rng(4)
+    X = rng.standard_normal((256, 32)).astype(np.float32)
+    T = rng.standard_normal((32, 8)) / 6
+    Y = np.tanh(X @ T).astype(np.float32)
+    Xt, Yt = torch.from_numpy(X).cuda(), torch.from_numpy(Y).cuda()
+    first = m.loss_grad(Xt, Yt)[0].item()
+    for _ in range(300):
+        m.train_step(Xt, Yt, 3e-3)
+    last = m.loss_grad(Xt, Yt)[0].item()
+    assert last < 0.1 * first
