@@ -301,6 +301,11 @@ kfbi_status kfbi_gemm_bf16(int transA, int transB, int M, int N, int K, const ui
  * X [P][ns][9] = (x, outward normal, mean curvature, g1, g2), fp32. */
 kfbi_status kfbi_ellipsoid_features(const double* geom, const double* jumps, int P, const double* S, int ns,
                                     void* stream, float* X);
+/* Training-data augmentation from the linearity of the density in the
+ * jump data: in place, for every example r < B, the g1 and g2 features of
+ * its ns samples in X [B][ns][9] and its target row Y [B][nout] are
+ * multiplied by alpha[r]. */
+kfbi_status kfbi_scale_jumps(float* X, float* Y, const float* alpha, int B, int ns, int nout, void* stream);
 /* Density at the plan's DOFs from values at the samples: least-squares
  * fit of the 81 real spherical harmonics of degree <= 8 in the body-frame
  * direction diag(1/a) Q^T (x - c) to scale * psi_s (ns >= 81), evaluated

@@ -206,6 +206,21 @@ __global__ void k_refresh_bf16(int64_t n, const float* w, const int64_t* bf_inde
   if (j >= 0) wb[j] = to_bf16(w[i]);
 }
 
+// data augmentation by the linearity of the density in the jump data: the
+// g1, g2 features (columns 7, 8 of every sample) and the target row of
+// example r are multiplied by alpha[r]
+__global__ void k_scale_jumps(int B, int ns, int nout, const float* alpha, float* X, float* Y) {
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t nx = (int64_t)B * ns * 2;
+  if (t < nx) {
+    const int64_t r = t / (2 * ns), q = t % (2 * ns);
+    X[r * ns * 9 + (q >> 1) * 9 + 7 + (q & 1)] *= alpha[r];
+  } else if (t < nx + (int64_t)B * nout) {
+    const int64_t u = t - nx;
+    Y[u] *= alpha[u / nout];
+  }
+}
+
 // ---------------------------------------------------------------- features
 // geometry per problem: c (3), semi-axes a (3), Q row-major (9); jumps per
 // problem: a[j][m] (16) then b[j][m] (16), j = 0 (g1), 1 (g2), m < 8 with
@@ -709,6 +724,18 @@ extern "C" kfbi_status kfbi_gemm_bf16(int transA, int transB, int M, int N, int 
 }
 
 // ======================================================================== features and transfer
+extern "C" kfbi_status kfbi_scale_jumps(float* X, float* Y, const float* alpha, int B, int ns, int nout,
+                                        void* stream) {
+  if (!X || !Y || !alpha || B < 1 || ns < 1 || nout < 1) {
+    kfbi_set_error("scale_jumps needs features, targets, factors and sizes");
+    return KFBI_E_INVALID;
+  }
+  const int64_t n = (int64_t)B * ns * 2 + (int64_t)B * nout;
+  hipLaunchKernelGGL(k_scale_jumps, dim3(nbl(n)), dim3(256), 0, (hipStream_t)stream, B, ns, nout, alpha, X, Y);
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
 extern "C" kfbi_status kfbi_ellipsoid_features(const double* geom, const double* jumps, int P, const double* S,
                                                int ns, void* stream, float* X) {
   if (!geom || !jumps || !S || !X || P < 1 || ns < 1) {

@@ -95,6 +95,8 @@ ABI = {
                           ctypes.c_double, ctypes.c_void_p], ctypes.c_int),
     "kfbi_sh_sample": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int,
                         ctypes.c_double, ctypes.c_void_p], ctypes.c_int),
+    "kfbi_scale_jumps": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                          ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "kfbi_real_sh": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "kfbi_last_error": ([], ctypes.c_char_p),
 }

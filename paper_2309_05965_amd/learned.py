@@ -149,3 +149,8 @@ def real_sh(dirs):
     Y = torch.empty((81, dirs.shape[0]), dtype=torch.float64, device=dirs.device)
     _check(kfbi.load().kfbi_real_sh(_p(dirs), dirs.shape[0], _stream(dirs.device), _p(Y)))
     return Y
+
+
+def scale_jumps(X, Y, alpha, ns=W.N_SAMPLES):
+    """In place: jump features and targets of example r times alpha[r]."""
+    _check(kfbi.load().kfbi_scale_jumps(_p(X), _p(Y), _p(alpha), X.shape[0], ns, Y.shape[1], _stream(X.device)))

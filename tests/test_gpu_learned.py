@@ -129,3 +129,44 @@ def test_training_reduces_the_loss():
         m.train_step(Xt, Yt, 3e-3)
     last = m.loss_grad(Xt, Yt)[0].item()
     assert last < 0.1 * first
+
+
+def test_pretrained_warm_start_gains_on_heldout_seeds():
+    """The network trained on 20,000 solver densities (N = 128 ellipsoids)
+    predicts held-out densities to ~20% and saves GMRES iterations against
+    the zero start and the control g2 / (beta_in + beta_out); the solve
+    still reaches the tolerance."""
+    from paper_2309_05965_amd import kfbi, learned, warmstart
+    model = warmstart.load_pretrained()
+    S = learned.samples()
+    zero, ctrl_it, learn, err_l, err_c = [], [], [], [], []
+    plan = None
+    for seed in range(1_000_100, 1_000_116):
+        prob, geom, jmp = W.config5(seed, 128)
+        try:
+            if plan is None:
+                plan = kfbi.Plan(prob)
+            else:
+                plan.setup(prob)
+        except kfbi.KfbiError:
+            plan = None
+            continue
+        d = kfbi.device_jump_data(plan, jmp)
+        ref, _, _ = plan.solve(d, tol=1e-11)
+        _, _, iz = plan.solve(d, tol=1e-8)
+        dsurf = plan.export("dof_surf").long()
+        ctrl = (d["g2"][dsurf] / (prob["beta_in"] + prob["beta_out"])).contiguous()
+        _, _, ic = plan.solve(d, tol=1e-8, psi0=ctrl)
+        p0 = warmstart.predict(model, plan, geom, jmp, S)
+        _, _, il = plan.solve(d, tol=1e-8, psi0=p0)
+        assert il["status"] == 0 and il["true_rel_res"] < 2e-8
+        zero.append(iz["iters"])
+        ctrl_it.append(ic["iters"])
+        learn.append(il["iters"])
+        err_l.append(float(((p0 - ref).norm() / ref.norm()).item()))
+        err_c.append(float(((ctrl - ref).norm() / ref.norm()).item()))
+    print("iters zero %.2f control %.2f learned %.2f; density error control %.2f learned %.2f"
+          % (np.mean(zero), np.mean(ctrl_it), np.mean(learn), np.mean(err_c), np.mean(err_l)))
+    assert len(zero) >= 12
+    assert np.mean(err_l) < 0.35 < np.mean(err_c)
+    assert np.mean(learn) < np.mean(zero)
