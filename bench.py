@@ -29,6 +29,10 @@ import numpy as np  # noqa: E402
 
 METRIC = "KFBI solves/s at 1e-8 rel residual: plain FP64 vs FP32-MG+learned warm start"
 HBM_PEAK_GBS = 8000.0
+# HBM bytes per k_dst launch on this workload (mean over the three passes),
+# from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's counts
+# (profiles/k_dst_star512_hbm_counters.md); null once k_dst changes
+K_DST_TRAFFIC_BYTES = 9.71e6
 
 
 def parse():
@@ -39,6 +43,9 @@ def parse():
     ap.add_argument("--N", type=int, default=512)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--copy-calibration", action="store_true",
+                    help="end with one plain 256 MiB device copy (reference for HBM counters)")
     ap.add_argument("--cpu-seconds", type=float, default=15.0)
     return ap.parse_args()
 
@@ -65,6 +72,82 @@ def cpu_baseline(N, tol, budget):
     return {"value": n / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
             "sample": "%d whole solves of the same 512^2 workload (geometry, collocation, data, "
                       "GMRES to 1e-8, final solve) in %.1f s, NumPy/SciPy FP64, 1 thread" % (n, el)}
+
+
+def time_solves(fn, reps):
+    import torch
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(reps):
+        fn()
+    torch.cuda.synchronize()
+    return reps / (time.perf_counter() - t0)
+
+
+def forms_config2(plan, prob, data, tol, reps):
+    """Solves/s of the star workload with each box solver (set-up included)."""
+    out = {}
+    for name, solver, eps in (("fp64_mg_eps1e-12", "mg64", 1e-12), ("fp32_mg_eps1e-10", "mg32", 1e-10)):
+        plan.set_box_solver(solver, eps_in=eps, max_cycles=16)
+
+        def step():
+            plan.setup(prob)
+            plan.solve(data, tol=tol)
+        step()
+        out[name] = time_solves(step, reps)
+    plan.set_box_solver("fft")
+    return out
+
+
+def forms_config5(tol, reps, n_problems=4):
+    """The ellipsoid workload of the learned start (128^3, beta 1/100) on
+    held-out seeds: plain FP64 (FP64 multigrid to 1e-12, zero start),
+    mixed + learned (FP32 multigrid in FP64 defect correction to 1e-10,
+    learned start), and the FFT forms, solves/s with set-up and prediction
+    inside the timed solve."""
+    import torch
+    from paper_2309_05965_amd import kfbi, learned, warmstart
+    from paper_2309_05965_amd import workloads as W
+    model = warmstart.load_pretrained()
+    S = learned.samples()
+    probs = []
+    for seed in range(1_000_200, 1_000_200 + 16):
+        prob, geom, jmp = W.config5(seed, 128)
+        try:
+            pl = kfbi.Plan(prob)
+        except kfbi.KfbiError:
+            continue
+        probs.append((prob, geom, jmp, pl, kfbi.device_jump_data(pl, jmp)))
+        if len(probs) == n_problems:
+            break
+    res, iters = {}, {}
+    for name, solver, eps, learned_start in (("fp64_mg_zero_start", "mg64", 1e-12, False),
+                                              ("fp32_mg_learned_start", "mg32", 1e-10, True),
+                                              ("fp64_fft_zero_start", "fft", 0.0, False),
+                                              ("fp64_fft_learned_start", "fft", 0.0, True)):
+        its = []
+
+        def run():
+            its.clear()
+            for prob, geom, jmp, pl, d in probs:
+                pl.setup(prob)
+                psi0 = warmstart.predict(model, pl, geom, jmp, S) if learned_start else None
+                _, _, info = pl.solve(d, tol=tol, psi0=psi0)
+                its.append(info["iters"])
+        for prob, geom, jmp, pl, d in probs:
+            pl.set_box_solver(solver, eps_in=eps if eps > 0 else 1e-12, max_cycles=16)
+        run()
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            run()
+        torch.cuda.synchronize()
+        res[name] = reps * len(probs) / (time.perf_counter() - t0)
+        iters[name] = float(np.mean(its))
+    res["gmres_iters_mean"] = iters
+    res["mixed_learned_over_plain"] = res["fp32_mg_learned_start"] / res["fp64_mg_zero_start"]
+    res["problems"] = len(probs)
+    return res
 
 
 def main():
@@ -146,16 +229,28 @@ def main():
             "peak": HBM_PEAK_GBS,
             "unit": "GB/s",
             "frac": achieved / HBM_PEAK_GBS,
-            "traffic": None,
+            "traffic": K_DST_TRAFFIC_BYTES if N == 512 else None,
             "avg_launch_us": avg_launch_s * 1e6,
             "algorithmic_bytes_per_launch": bytes_per_launch,
             "timing": "HIP events around %d back-to-back box solves (%d k_dst launches) after the timed region"
                       % (solves, launches),
         },
     }
+    if not args.no_forms:
+        # the other forms of the metric, measured after the timed region
+        out["forms"] = {
+            "star512": dict(fp64_fft=out["value"], **forms_config2(plan, prob, data, args.tol, 5)),
+            "ellipsoid128_learned_workload": forms_config5(args.tol, 2),
+        }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, args.tol, args.cpu_seconds)
     print(json.dumps(out), flush=True)
+    if args.copy_calibration:
+        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        torch.cuda.synchronize()
+        dst.copy_(src)
+        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":
