@@ -258,6 +258,42 @@ kfbi_status kfbi_plan_timing(kfbi_plan* plan, int64_t* solves, int64_t* launches
 kfbi_status kfbi_plan_destroy(kfbi_plan* plan);
 
 /* ----------------------------------------------------------------------
+ * Many independent problems (batched solves).  Each problem is a
+ * kfbi_problem whose data are a manufactured solution evaluated on the
+ * device at the plan's own query points:
+ *   KFBI_MANU_STAR2D   u_in = cos 2x e^y, u_out = x^2 - y^3 (2D)
+ *   KFBI_MANU_TORUS3D  u_in = sin x sin y sin z, u_out = e^(x+y+z)/10 (3D)
+ * (fhat_s = Lap u_s - kappa u_s, g1 = [u], g2 = [beta d_n u], gB = u_out).
+ * -------------------------------------------------------------------- */
+enum { KFBI_MANU_STAR2D = 1, KFBI_MANU_TORUS3D = 2 };
+
+/* Data of a manufactured solution at a ready plan's query points, written
+ * on the plan's stream: g1, g2 [n_surf], ftilde [n_dof][n_pde],
+ * fhat [n_iface+1][n_nodes], gB [n_nodes]. */
+kfbi_status kfbi_plan_manufactured_data(kfbi_plan* plan, int kind, double* g1, double* g2, double* ftilde,
+                                        double* fhat, double* gB);
+
+typedef struct kfbi_batch kfbi_batch;
+/* A batch of n problems (copied) with their manufactured-solution kinds,
+ * solved by n_workers (1..16) host threads, each with its own stream and
+ * one plan per grid shape (created on first use, re-set-up for every
+ * problem).  Device of the calling thread. */
+kfbi_status kfbi_batch_create(const kfbi_problem* probs, const int* manu, int n, int n_workers,
+                              kfbi_batch** out);
+/* Number of problems and sum of their node counts (the length of u_all). */
+kfbi_status kfbi_batch_sizes(const kfbi_batch* batch, int64_t* n_problems, int64_t* total_nodes);
+/* Solve every problem (Alg. 1, zero start, opts->tol / max_iter): workers
+ * take problems in order of decreasing node count.  u_all (device, may be
+ * NULL): the solutions concatenated in problem order, (N_i+1)^d values
+ * each.  infos (host, [n]) and seconds (host, [n], may be NULL: wall time
+ * of each problem on its worker, set-up included) are filled for every
+ * problem; returns KFBI_OK only if every problem is OK, else the first
+ * failure's status with its message.  The densities are not kept. */
+kfbi_status kfbi_batch_solve(kfbi_batch* batch, const kfbi_opts* opts, double* u_all, kfbi_info* infos,
+                             double* seconds);
+kfbi_status kfbi_batch_destroy(kfbi_batch* batch);
+
+/* ----------------------------------------------------------------------
  * Learned initial density for GMRES (Alg. 1 Step 2 gives GMRES an initial
  * guess; this predicts one).  All pointers are device pointers ordered on
  * the given stream (the plan's stream for the plan calls); the MLP object

@@ -16,7 +16,7 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "kfbi")
 LIB = os.path.join(HERE, "libkfbi.so")
-SOURCES = ["geometry.hip", "collocation.hip", "operator.hip", "dst.hip", "mg.hip", "gmres.hip", "learned.hip", "api.hip"]
+SOURCES = ["geometry.hip", "collocation.hip", "operator.hip", "dst.hip", "mg.hip", "gmres.hip", "learned.hip", "batch.hip", "api.hip"]
 ARCH = os.environ.get("KFBI_OFFLOAD_ARCH", "gfx950")
 
 

@@ -13,6 +13,8 @@
 void kfbi_pde_lattice(int d, int p, int (*off)[3], int* n);
 void kfbi_dn_lattice(int D, int m, int (*off)[2], int* n);
 
+std::shared_mutex kfbi_capture_mutex;
+
 namespace {
 
 thread_local char g_err[512] = "no error";
@@ -335,6 +337,7 @@ kfbi_status ensure_graph(kfbi_plan* pl) {
                       (uint64_t)(uintptr_t)pl->PA ^ (uint64_t)(uintptr_t)pl->GI ^ (uint64_t)(uintptr_t)pl->mg_u};
   if (pl->graph_exec && pl->graph4_exec && memcmp(key, pl->graph_key, sizeof(key)) == 0) return KFBI_OK;
   destroy_graphs(pl);
+  std::unique_lock<std::shared_mutex> lock(kfbi_capture_mutex);
   for (int v = 0; v < 2; ++v) {
     const int iters = v == 0 ? 1 : 4;
     HIPCHK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
@@ -409,6 +412,7 @@ extern "C" const char* kfbi_last_error(void) { return g_err; }
 
 // ---------------------------------------------------------------- plan
 extern "C" kfbi_status kfbi_plan_create(const kfbi_problem* prob, void* stream, kfbi_plan** out) {
+  std::shared_lock<std::shared_mutex> lock(kfbi_capture_mutex);
   if (!out) {
     kfbi_set_error("out is NULL");
     return KFBI_E_INVALID;
@@ -447,6 +451,7 @@ extern "C" kfbi_status kfbi_plan_create(const kfbi_problem* prob, void* stream, 
 }
 
 extern "C" kfbi_status kfbi_plan_setup(kfbi_plan* pl, const kfbi_problem* prob) {
+  std::shared_lock<std::shared_mutex> lock(kfbi_capture_mutex);
   if (!pl) {
     kfbi_set_error("plan is NULL");
     return KFBI_E_INVALID;
@@ -483,6 +488,7 @@ extern "C" kfbi_status kfbi_plan_sizes(const kfbi_plan* pl, kfbi_sizes* out) {
 
 extern "C" kfbi_status kfbi_plan_destroy(kfbi_plan* pl) {
   if (!pl) return KFBI_OK;
+  std::shared_lock<std::shared_mutex> lock(kfbi_capture_mutex);
   if (pl->stream) (void)hipStreamSynchronize(pl->stream);
   else (void)hipDeviceSynchronize();
   free_plan(pl);
@@ -565,7 +571,7 @@ extern "C" kfbi_status kfbi_plan_export(const kfbi_plan* pl_c, int which, void* 
   kfbi_pde_lattice(d, pl->g.p, offP, &nP);
   int* doff;
   KCHK(dalloc(&doff, 3 * KFBI_MAXP));
-  HIPCHK(hipMemcpy(doff, offP, sizeof(offP), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpyAsync(doff, offP, sizeof(offP), hipMemcpyHostToDevice, pl->stream));
   int64_t n = pl->n_dof * nP;
   hipLaunchKernelGGL(k_pde_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pl->stream, pl->n_dof, d, nP,
                      pl->g.h, pl->d2s, pl->s_pos, doff, (double*)dst);
@@ -598,6 +604,7 @@ extern "C" kfbi_status kfbi_plan_set_box_solver(kfbi_plan* pl, int solver, doubl
     return KFBI_E_INVALID;
   }
   destroy_graphs(pl);
+  std::shared_lock<std::shared_mutex> lock(kfbi_capture_mutex);
   return mg_configure(pl, solver, eps_in, max_cycles);
 }
 
@@ -609,8 +616,9 @@ extern "C" kfbi_status kfbi_plan_box_stats(kfbi_plan* pl, int32_t* cycles, doubl
     int h[2];
     double sc[2];
     HIPCHK(hipStreamSynchronize(pl->stream));
-    HIPCHK(hipMemcpy(h, pl->mg_ctl, sizeof(h), hipMemcpyDeviceToHost));
-    HIPCHK(hipMemcpy(sc, pl->mg_scal, sizeof(sc), hipMemcpyDeviceToHost));
+    HIPCHK(hipMemcpyAsync(h, pl->mg_ctl, sizeof(h), hipMemcpyDeviceToHost, pl->stream));
+    HIPCHK(hipMemcpyAsync(sc, pl->mg_scal, sizeof(sc), hipMemcpyDeviceToHost, pl->stream));
+    HIPCHK(hipStreamSynchronize(pl->stream));
     c = h[1];
     r = sc[1];
   }
@@ -733,7 +741,10 @@ extern "C" kfbi_status kfbi_solve(kfbi_plan* pl, const kfbi_data* data, const kf
     return KFBI_E_INVALID;
   }
   double tol = opts->tol > 0.0 ? opts->tol : 1e-10;
-  KCHK(ensure_gmres(pl, m));
+  {
+    std::shared_lock<std::shared_mutex> lock(kfbi_capture_mutex);
+    KCHK(ensure_gmres(pl, m));
+  }
   // the solve runs on the plan's private stream (graph launches need a
   // capturable stream), ordered after and before the caller's stream
   hipStream_t user = pl->stream;

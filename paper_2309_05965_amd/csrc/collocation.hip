@@ -294,7 +294,8 @@ kfbi_status colloc_factor(kfbi_plan* pl) {
   HIPCHK(hipStreamSynchronize(pl->stream));
   // largest condition number (host reduction of a small array)
   std::vector<double> cond((size_t)pl->n_dof);
-  HIPCHK(hipMemcpy(cond.data(), pl->cond, sizeof(double) * pl->n_dof, hipMemcpyDeviceToHost));
+  HIPCHK(hipMemcpyAsync(cond.data(), pl->cond, sizeof(double) * pl->n_dof, hipMemcpyDeviceToHost, pl->stream));
+  HIPCHK(hipStreamSynchronize(pl->stream));
   double cm = 0.0;
   for (double v : cond) cm = v > cm || v != v ? v : cm;
   pl->cond_max = cm;

@@ -361,8 +361,9 @@ kfbi_status dst_init(kfbi_plan* pl) {
     double sn = sin((double)k * M_PI / (2.0 * N));
     eig[k] = -4.0 / (pl->g.h * pl->g.h) * sn * sn;
   }
-  HIPCHK(hipMemcpy(pl->tw, tw.data(), sizeof(double) * 2 * M, hipMemcpyHostToDevice));
-  HIPCHK(hipMemcpy(pl->eig1, eig.data(), sizeof(double) * (N + 1), hipMemcpyHostToDevice));
+  HIPCHK(hipMemcpyAsync(pl->tw, tw.data(), sizeof(double) * 2 * M, hipMemcpyHostToDevice, pl->stream));
+  HIPCHK(hipMemcpyAsync(pl->eig1, eig.data(), sizeof(double) * (N + 1), hipMemcpyHostToDevice, pl->stream));
+  HIPCHK(hipStreamSynchronize(pl->stream));
   int lds = (int)(sizeof(double2) * 2 * (size_t)(tile_lines(M) / 2) * (M + (pad_shift(M) == 3 ? M / 8 : 0)));
   if (lds > 65536) {
     kfbi_set_error("box solver LDS footprint too large (N = %d)", N);

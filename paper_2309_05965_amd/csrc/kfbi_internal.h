@@ -5,6 +5,8 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
+#include <mutex>
+#include <shared_mutex>
 #include <string>
 #include <vector>
 
@@ -179,6 +181,12 @@ void op_bie_rhs(kfbi_plan* pl, const double* g2, const double* dn_in, const doub
 // dst.hip (step S3)
 kfbi_status dst_init(kfbi_plan* pl);
 void dst_solve(kfbi_plan* pl, const double* F, double* v);
+// Graph capture takes this exclusively; plan creation, set-up, buffer
+// growth and destruction (allocations, frees and host copies, which may
+// synchronise with other streams) take it shared, so several host threads
+// can drive their own plans while one of them captures.
+extern std::shared_mutex kfbi_capture_mutex;
+
 kfbi_status mg_configure(kfbi_plan* pl, int solver, double eps, int maxit);
 void mg_solve(kfbi_plan* pl, const double* F, double* v);
 void mg_matvec_rhs(kfbi_plan* pl);

@@ -75,6 +75,14 @@ ABI = {
     "kfbi_plan_timing": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                           ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "kfbi_plan_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "kfbi_plan_manufactured_data": ([ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 5, ctypes.c_int),
+    "kfbi_batch_create": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
+                           ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "kfbi_batch_sizes": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
+                         ctypes.c_int),
+    "kfbi_batch_solve": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
+                         ctypes.c_int),
+    "kfbi_batch_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "kfbi_mlp_create": ([ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
                          ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "kfbi_mlp_sizes": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64)], ctypes.c_int),
@@ -316,3 +324,63 @@ def device_jump_data(plan, jumps):
     dev = plan.device
     return {"g1": torch.from_numpy(g1).to(dev).contiguous(), "g2": torch.from_numpy(g2).to(dev).contiguous(),
             "ftilde": None, "fhat": None, "gB": None}
+
+
+MANU = {"star2d": 1, "torus3d": 2}
+
+
+def manufactured_data(plan, kind):
+    """Manufactured-solution data at the plan's query points, generated on
+    the device (kind "star2d" or "torus3d")."""
+    s = plan.sizes
+    K = plan.prob["n_iface"] if "n_iface" in plan.prob else len(plan.prob["ifaces"])
+    z = lambda n: torch.empty(n, dtype=torch.float64, device=plan.device)
+    d = {"g1": z(s.n_surf), "g2": z(s.n_surf), "ftilde": z(s.n_dof * s.n_pde), "fhat": z((K + 1) * s.n_nodes),
+         "gB": z(s.n_nodes)}
+    _check(load().kfbi_plan_manufactured_data(plan._h, MANU[kind], *[_ptr(d[k]) for k in
+                                                                      ("g1", "g2", "ftilde", "fhat", "gB")]))
+    return d
+
+
+class Batch:
+    """Many independent problems solved by a pool of workers (threads with
+    their own streams and plans)."""
+
+    def __init__(self, probs, kinds, workers=4):
+        lib = load()
+        self.n = len(probs)
+        arr = (Problem * self.n)(*[problem_struct(p) for p in probs])
+        self._arr = arr
+        km = (ctypes.c_int * self.n)(*[MANU[k] for k in kinds])
+        h = ctypes.c_void_p()
+        _check(lib.kfbi_batch_create(ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(km, ctypes.c_void_p), self.n,
+                                     int(workers), ctypes.byref(h)))
+        self._h = h
+        a, b = ctypes.c_int64(), ctypes.c_int64()
+        _check(lib.kfbi_batch_sizes(self._h, ctypes.byref(a), ctypes.byref(b)))
+        self.total_nodes = b.value
+
+    def solve(self, tol=1e-8, max_iter=300, keep_u=False, raise_on_fail=True):
+        lib = load()
+        u = torch.zeros(self.total_nodes, dtype=torch.float64, device="cuda") if keep_u else None
+        infos = (Info * self.n)()
+        secs = (ctypes.c_double * self.n)()
+        o = Opts(tol, max_iter, 0)
+        torch.cuda.synchronize()
+        st = lib.kfbi_batch_solve(self._h, ctypes.byref(o), _ptr(u), ctypes.cast(infos, ctypes.c_void_p),
+                                  ctypes.cast(secs, ctypes.c_void_p))
+        if st != 0 and raise_on_fail:
+            raise KfbiError(st, lib.kfbi_last_error().decode())
+        info = [{"iters": x.iters, "status": x.status, "true_rel_res": x.true_rel_res} for x in infos]
+        return u, info, list(secs)
+
+    def close(self):
+        if getattr(self, "_h", None):
+            load().kfbi_batch_destroy(self._h)
+            self._h = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
