@@ -150,6 +150,30 @@ def forms_config5(tol, reps, n_problems=4):
     return res
 
 
+def forms_batch(workers=(1, 8)):
+    """The 512-problem batch of random stars (N in {64, 128, 256, 512},
+    beta_in log-uniform 1e-2..1e2): problems/s over the whole batch (the
+    under-resolved stars fail fast in set-up and are counted)."""
+    import torch
+    from paper_2309_05965_amd import kfbi
+    from paper_2309_05965_amd import workloads as W
+    probs = [p for p, _ in W.config4_batch(512)]
+    out = {}
+    for w in workers:
+        b = kfbi.Batch(probs, ["star2d"] * len(probs), workers=w)
+        b.solve(tol=1e-8, raise_on_fail=False)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        _, info, _ = b.solve(tol=1e-8, raise_on_fail=False)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
+        ok = sum(1 for i in info if i["status"] == 0)
+        out["workers_%d" % w] = {"problems_per_s": len(probs) / el, "solved_per_s": ok / el, "solved": ok,
+                                 "unresolved": len(probs) - ok}
+        b.close()
+    return out
+
+
 def main():
     args = parse()
     if args.gpus != 1:
@@ -241,6 +265,7 @@ def main():
         out["forms"] = {
             "star512": dict(fp64_fft=out["value"], **forms_config2(plan, prob, data, args.tol, 5)),
             "ellipsoid128_learned_workload": forms_config5(args.tol, 2),
+            "batch512_random_stars": forms_batch(),
         }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, args.tol, args.cpu_seconds)
