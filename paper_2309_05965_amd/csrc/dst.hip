@@ -169,8 +169,9 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
     for (int m = threadIdx.x; m < M; m += blockDim.x) tl[m] = a.tw[m];
     tw = tl;
   }
-  const int tile = blockIdx.x % a.tiles_u;
-  const int w = blockIdx.x / a.tiles_u + 1;         // remaining interior coordinate (3D)
+  const int bid = kfbi_xcd_block(blockIdx.x, gridDim.x);
+  const int tile = bid % a.tiles_u;
+  const int w = bid / a.tiles_u + 1;                // remaining interior coordinate (3D)
   const int u0 = 1 + tile * TL;                     // first tile coordinate
   const int nl = N - 1;
   const int total = TL * nl;

@@ -201,3 +201,13 @@ void gm_true_residual(kfbi_plan* pl, const double* b, const double* Ax, double* 
 __host__ __device__ inline int kfbi_ncoef(int d, int p) {
   return d == 2 ? (p + 1) * (p + 2) / 2 : (p + 1) * (p + 2) * (p + 3) / 6;
 }
+
+// The work groups of a launch are dealt to the chip's 8 XCDs in turn (group
+// b runs on XCD b mod 8) and every XCD has an L2 of its own.  This maps b to
+// a logical index under which each XCD takes one contiguous range, so that
+// neighbouring tiles, which share cache lines, meet in the same L2.  A
+// bijection of [0, nb) for every nb.
+__device__ __forceinline__ int kfbi_xcd_block(int b, int nb) {
+  const int q = nb >> 3, r = nb & 7, x = b & 7;
+  return x * q + (x < r ? x : r) + (b >> 3);
+}

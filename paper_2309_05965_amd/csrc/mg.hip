@@ -184,9 +184,14 @@ __global__ void __launch_bounds__(256) k_sweep(Ctl ctl, SweepArgs<TS, TO> a) {
   if (active) {
     const int m = a.N - 1, n1 = a.n1;
     const int lx = threadIdx.x % TT::TX, ly = threadIdx.x / TT::TX;
-    const int x0 = blockIdx.x * TT::TX;
-    const int y0 = D == 3 ? blockIdx.y * TT::TY : 0;
-    const int z0 = (D == 3 ? blockIdx.z : blockIdx.y) * a.KZ;
+    // tiles in XCD-contiguous order: the halo rows a tile shares with its
+    // neighbours are then fetched once into that XCD's L2
+    const int nbx = gridDim.x, nby = gridDim.y;
+    const int lb = kfbi_xcd_block(blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z), nbx * nby * gridDim.z);
+    const int bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
+    const int x0 = bx * TT::TX;
+    const int y0 = D == 3 ? by * TT::TY : 0;
+    const int z0 = (D == 3 ? bz : by) * a.KZ;
     const int z1 = z0 + a.KZ < m ? z0 + a.KZ : m;
     // plane gz into registers (this thread's NL elements), then into LDS
     auto fetch = [&](int gz, TS* r) {
