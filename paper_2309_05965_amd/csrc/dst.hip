@@ -1,7 +1,7 @@
 // Step S3 -- box solve A_h v = F with homogeneous Dirichlet data.
 //
-// Paper: Alg. 1 Step 3.3 solves the corrected finite-difference system "with
-// FFT"; Sec. 5.2 gives the operators (eqs. 9p-cds, 27p-cds).  With
+// Paper: Alg. 1 Step 3.3 solves the corrected finite-difference system by a
+// fast Fourier method; Sec. 5.2 gives the operators (eqs. 9p-cds, 27p-cds).  With
 // homogeneous box data every operator of the library is diagonal in the
 // type-I sine basis: per axis the 3-point second difference has eigenvalue
 // s_k = -4/h^2 sin^2(k pi / 2N), k = 1..N-1, and
@@ -18,7 +18,10 @@
 // LDS ping-pong buffers, and unpacks both
 // sine transforms from the result (Re Z_k = 2 S_B(k), Im Z_k = -2 S_A(k)).
 // The last axis is fused: forward DST, spectral divide and inverse DST in
-// LDS, so 2D takes 3 passes and 3D 5 passes of 16 B per node.
+// LDS, so 2D takes 3 passes and 3D 5 passes of 16 B per node.  Tiles are
+// dealt in XCD-contiguous order, and the tile size trades a work group's
+// fixed latency against LDS residency (tile_lines).  Twiddles are read
+// from a global table (L2-resident).
 #include <math.h>
 
 #include <vector>
@@ -27,7 +30,9 @@
 
 namespace {
 
-constexpr int LDS_COMPLEX = 4096;   // complex slots of the two ping-pong buffers (64 KiB)
+constexpr int DST_LDS_BUDGET = 98304;  // bytes of the two ping-pong buffers of a work group
+constexpr size_t DST_LDS_CU = 163840;  // LDS of one compute unit
+constexpr int DST_CH = 8;               // loads in flight per thread while a tile is read
 
 struct DstArgs {
   const int* ctl;      // nothing to do once ctl[1] is set (device GMRES loop)
@@ -47,6 +52,7 @@ struct DstArgs {
   int M, logM;     // FFT length 2N
   int ps;          // LDS pad shift (see padi)
   int tiles_u;     // tiles along the tile axis
+  int ntiles;      // tiles of the pass
   const double* in;
   double* out;
   const double2* tw;   // exp(-2 pi i m / M), m < M
@@ -153,6 +159,75 @@ __device__ __forceinline__ double eigenvalue(const DstArgs& a, int k, int u, int
   return lam - g.kappa * (1.0 + h2 / 12.0 * lap);
 }
 
+// tile element idx -> line l (0..TL-1) and position j (1..N-1) along the
+// transform axis, ordered so that consecutive threads touch consecutive
+// addresses (along the line for the x axis, across the tile's lines else)
+__device__ __forceinline__ void tile_pos(const DstArgs& a, int idx, int nl, int& l, int& j) {
+  if (a.ax == 0) {
+    j = idx % nl + 1;
+    l = idx / nl;
+  } else {
+    l = idx % a.TL;
+    j = idx / a.TL + 1;
+  }
+}
+
+// F at the irregular nodes of the tile's rows: minus the sum over cut
+// neighbours Q of A_PQ (C^(reg P) - C^(reg Q))(x_Q), from the correction
+// values of the current density; zero elsewhere.  The pair table of a node
+// is read four pairs at a time so that the gathers of a group are in flight
+// together; the sum runs over the pairs in table order.
+__device__ void corrected_rhs(const DstArgs& a, double2* A, int Mp, int u0, int w) {
+  const GridDesc& g = a.g;
+  const int M = a.M, ps = a.ps, nl = g.N - 1, nf = a.TL / 2;
+  for (int i = threadIdx.x; i < nf * Mp; i += blockDim.x) A[i] = make_double2(0.0, 0.0);
+  __syncthreads();
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
+  for (int l = wave; l < a.TL; l += nw) {
+    const int u = u0 + l;
+    if (u > nl) continue;
+    const int64_t row = (int64_t)u + (int64_t)g.n1 * (g.d == 3 ? w : 0);
+    const int r0 = a.row_start[row], r1 = a.row_end[row];
+    for (int t = r0 + lane; t < r1; t += 64) {
+      double F = 0.0;
+      const int64_t base = (int64_t)t * a.maxpairs;
+      for (int m0 = 0; m0 < a.maxpairs; m0 += 4) {
+        double cf[4], c1[4], c2[4];
+        int e1[4], e2[4];
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          const bool in = m0 + q < a.maxpairs;
+          cf[q] = in ? a.PA[base + m0 + q] : 0.0;
+          e1[q] = in ? a.PE1[base + m0 + q] : -1;
+          e2[q] = in ? a.PE2[base + m0 + q] : -1;
+        }
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          c1[q] = e1[q] >= 0 ? a.Cv[e1[q]] : 0.0;
+          c2[q] = e2[q] >= 0 ? a.Cv[e2[q]] : 0.0;
+        }
+        bool done = false;
+#pragma unroll
+        for (int q = 0; q < 4; ++q) {
+          done = done || cf[q] == 0.0;      // the table is zero-padded after the last pair
+          if (!done) F -= cf[q] * (c1[q] - c2[q]);
+        }
+        if (done) break;
+      }
+      const int j = a.irr[t] % g.n1;
+      double2* z = A + (l >> 1) * Mp;
+      if (l & 1) {
+        z[padi(j, ps)].y = F;
+        z[padi(M - j, ps)].y = -F;
+      } else {
+        z[padi(j, ps)].x = F;
+        z[padi(M - j, ps)].x = -F;
+      }
+    }
+  }
+}
+
+// One axis pass: a work group transforms one tile of TL lines.
 __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
   if (a.ctl && a.ctl[1]) return;
   extern __shared__ double2 lds[];
@@ -162,95 +237,49 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
   const int Mp = M + (M >> ps);                     // padded sequence stride
   double2* A = lds;                                 // [nf][Mp]
   double2* B = lds + nf * Mp;                       // [nf][Mp]
-  // twiddle table in LDS when it fits next to the two buffers
-  const double2* tw = a.tw;
-  if (2 * nf * Mp + M <= LDS_COMPLEX) {
-    double2* tl = lds + 2 * nf * Mp;
-    for (int m = threadIdx.x; m < M; m += blockDim.x) tl[m] = a.tw[m];
-    tw = tl;
-  }
-  const int bid = kfbi_xcd_block(blockIdx.x, gridDim.x);
-  const int tile = bid % a.tiles_u;
-  const int w = bid / a.tiles_u + 1;                // remaining interior coordinate (3D)
-  const int u0 = 1 + tile * TL;                     // first tile coordinate
+  // tiles in XCD-contiguous order (neighbouring tiles share cache lines
+  // along the strided axes)
+  const int tile = kfbi_xcd_block(blockIdx.x, gridDim.x);
+  const int w = tile / a.tiles_u + 1;               // remaining interior coordinate (3D)
+  const int u0 = 1 + (tile % a.tiles_u) * TL;       // first tile coordinate
   const int nl = N - 1;
   const int total = TL * nl;
   if (a.src_corr) {
-    // F = -sum over cut neighbours Q of A_PQ (C^(reg P) - C^(reg Q))(x_Q) at
-    // the irregular nodes of the tile's rows (correction values of the
-    // current density, computed just before), zero elsewhere
-    for (int i = threadIdx.x; i < nf * Mp; i += blockDim.x) A[i] = make_double2(0.0, 0.0);
-    __syncthreads();
-    const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
-    for (int l = wave; l < TL; l += nw) {
-      const int u = u0 + l;
-      if (u > nl) continue;
-      const int64_t row = (int64_t)u + (int64_t)g.n1 * (g.d == 3 ? w : 0);
-      for (int t = a.row_start[row] + lane; t < a.row_end[row]; t += 64) {
-        double F = 0.0;
-        for (int m = 0; m < a.maxpairs; ++m) {
-          const double cf = a.PA[(int64_t)t * a.maxpairs + m];
-          if (cf == 0.0) break;
-          const int e1 = a.PE1[(int64_t)t * a.maxpairs + m], e2 = a.PE2[(int64_t)t * a.maxpairs + m];
-          const double c1 = e1 >= 0 ? a.Cv[e1] : 0.0, c2 = e2 >= 0 ? a.Cv[e2] : 0.0;
-          F -= cf * (c1 - c2);
-        }
-        const int j = a.irr[t] % g.n1;
+    corrected_rhs(a, A, Mp, u0, w);
+  } else {
+    for (int f = threadIdx.x; f < nf; f += blockDim.x) {
+      A[f * Mp] = make_double2(0.0, 0.0);
+      A[f * Mp + padi(N, ps)] = make_double2(0.0, 0.0);
+    }
+    // all loads of a chunk are issued before the LDS stores
+    for (int base = threadIdx.x; base < total; base += DST_CH * (int)blockDim.x) {
+      double xv[DST_CH];
+#pragma unroll
+      for (int q = 0; q < DST_CH; ++q) {
+        const int idx = base + q * (int)blockDim.x;
+        int l, j;
+        tile_pos(a, idx, nl, l, j);
+        xv[q] = (idx < total && u0 + l <= nl) ? a.in[elem_addr(a, u0 + l, w, j)] : 0.0;
+      }
+#pragma unroll
+      for (int q = 0; q < DST_CH; ++q) {
+        const int idx = base + q * (int)blockDim.x;
+        if (idx >= total) continue;
+        int l, j;
+        tile_pos(a, idx, nl, l, j);
         double2* z = A + (l >> 1) * Mp;
         if (l & 1) {
-          z[padi(j, ps)].y = F;
-          z[padi(M - j, ps)].y = -F;
+          z[padi(j, ps)].y = xv[q];
+          z[padi(M - j, ps)].y = -xv[q];
         } else {
-          z[padi(j, ps)].x = F;
-          z[padi(M - j, ps)].x = -F;
+          z[padi(j, ps)].x = xv[q];
+          z[padi(M - j, ps)].x = -xv[q];
         }
       }
     }
-    __syncthreads();
-  } else {
-  for (int f = threadIdx.x; f < nf; f += blockDim.x) {
-    A[f * Mp] = make_double2(0.0, 0.0);
-    A[f * Mp + padi(N, ps)] = make_double2(0.0, 0.0);
-  }
-  // all loads of a chunk are issued before the LDS stores
-  constexpr int CH = 8;
-  for (int base = threadIdx.x; base < total; base += CH * (int)blockDim.x) {
-    double xv[CH];
-    int lv[CH], jv[CH];
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-      const int idx = base + q * (int)blockDim.x;
-      int l = 0, j = 1;
-      if (a.ax == 0) {
-        j = idx % nl + 1;
-        l = idx / nl;
-      } else {
-        l = idx % TL;
-        j = idx / TL + 1;
-      }
-      const int u = u0 + l;
-      lv[q] = idx < total ? l : -1;
-      jv[q] = j;
-      xv[q] = (idx < total && u <= nl) ? a.in[elem_addr(a, u, w, j)] : 0.0;
-    }
-#pragma unroll
-    for (int q = 0; q < CH; ++q) {
-      const int l = lv[q], j = jv[q];
-      if (l < 0) continue;
-      double2* z = A + (l >> 1) * Mp;
-      if (l & 1) {
-        z[padi(j, ps)].y = xv[q];
-        z[padi(M - j, ps)].y = -xv[q];
-      } else {
-        z[padi(j, ps)].x = xv[q];
-        z[padi(M - j, ps)].x = -xv[q];
-      }
-    }
   }
   __syncthreads();
-  }
-  __syncthreads();
-  double2* R = fft_stockham(A, B, tw, nf, M, a.logM, ps);
+  double2* R = fft_stockham(A, B, a.tw, nf, M, a.logM, ps);
   if (a.mode == 1) {
     // S_A(k) = -Im Z_k / 2 (even line), S_B(k) = Re Z_k / 2 (odd line); divide
     // by lambda, scale, and form the odd sequences of the inverse transform
@@ -270,36 +299,41 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
       S[f * Mp + padi(M - k, ps)] = make_double2(-c.x, -c.y);
     }
     __syncthreads();
-    R = fft_stockham(S, R, tw, nf, M, a.logM, ps);
+    R = fft_stockham(S, R, a.tw, nf, M, a.logM, ps);
   }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     int l, k;
-    if (a.ax == 0) {
-      k = idx % nl + 1;
-      l = idx / nl;
-    } else {
-      l = idx % TL;
-      k = idx / TL + 1;
-    }
-    int u = u0 + l;
+    tile_pos(a, idx, nl, l, k);
+    const int u = u0 + l;
     if (u > nl) continue;
     double2 Z = R[(l >> 1) * Mp + padi(k, ps)];
     a.out[elem_addr(a, u, w, k)] = (l & 1) ? 0.5 * Z.x : -0.5 * Z.y;
   }
 }
 
-// lines per tile: two ping-pong buffers of (TL/2) sequences of M complex
-// values (plus the twiddle table when it fits) within LDS_COMPLEX slots
-// LDS pad shift for FFT length M: padded when one padded pair of buffers fits
-int pad_shift(int M) { return 2 * (M + M / 8) <= LDS_COMPLEX ? 3 : 31; }
+// LDS pad shift for FFT length M: padded when a padded pair of buffers fits
+int pad_shift(int M) { return 2 * (M + M / 8) * (int)sizeof(double2) <= DST_LDS_BUDGET ? 3 : 31; }
 
-int tile_lines(int M) {
-  const int Mp = M + (pad_shift(M) == 3 ? M / 8 : 0);
-  int nf = (LDS_COMPLEX - M) / (2 * Mp);
-  if (nf < 1) nf = LDS_COMPLEX / (2 * Mp);
-  if (nf > 16) nf = 16;
-  if (nf < 1) nf = 1;
-  return 2 * nf;
+int padded_len(int M) { return M + (pad_shift(M) == 3 ? M / 8 : 0); }
+
+size_t tile_lds(int TL, int M) { return sizeof(double2) * 2 * (size_t)(TL / 2) * padded_len(M); }
+
+// lines per tile: the largest even TL <= 8 whose LDS footprint still lets
+// 4 work groups (16 waves) share a compute unit and that leaves at least
+// 1024 tiles (4 per compute unit); else 2.  More lines per tile amortise a
+// work group's fixed latency; the residency and tile-count floors keep
+// enough loads in flight.  (Measured on the 3D 64/128/256 and 2D grids:
+// TL = 2, 8, 4 and 2 respectively.)
+int tile_lines(int d, int N) {
+  const int nl = N - 1, M = 2 * N;
+  const int64_t lines = d == 3 ? (int64_t)nl * nl : nl;
+  for (int tl = 8; tl > 2; tl -= 2) {
+    const size_t lds = tile_lds(tl, M);
+    if (lds * 4 > DST_LDS_CU) continue;
+    if ((lines + tl - 1) / tl < 1024) continue;
+    return tl;
+  }
+  return 2;
 }
 
 void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out, const double* psi = nullptr,
@@ -325,26 +359,19 @@ void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out,
   a.M = 2 * pl->g.N;
   a.logM = 0;
   while ((1 << a.logM) < a.M) ++a.logM;
-  int nl = pl->g.N - 1;
-  // enough work groups to fill 256 CUs: aim at >= 1024 tiles, at least one
-  // FFT (two lines) per tile, at most what fits the LDS budget
-  int64_t lines = pl->g.d == 3 ? (int64_t)nl * nl : nl;
-  int64_t tl = 2 * (lines / 2048);
-  if (tl < 2) tl = 2;
-  if (tl > tile_lines(a.M)) tl = tile_lines(a.M);
-  a.TL = (int)tl;
+  const int nl = pl->g.N - 1;
+  a.TL = tile_lines(pl->g.d, pl->g.N);
   a.tiles_u = (nl + a.TL - 1) / a.TL;
+  a.ntiles = a.tiles_u * (pl->g.d == 3 ? nl : 1);
   a.in = in;
   a.out = out;
   a.tw = (const double2*)pl->tw;
   a.eig1 = pl->eig1;
   a.scale = 1.0;
   for (int t = 0; t < pl->g.d; ++t) a.scale *= 2.0 / pl->g.N;
-  unsigned blocks = (unsigned)a.tiles_u * (pl->g.d == 3 ? nl : 1);
-  size_t nfs = (size_t)(a.TL / 2);
   a.ps = pad_shift(a.M);
-  size_t Mp = (size_t)a.M + (a.ps == 3 ? a.M / 8 : 0);
-  size_t lds = sizeof(double2) * (2 * nfs * Mp + a.M <= (size_t)LDS_COMPLEX ? 2 * nfs * Mp + a.M : 2 * nfs * Mp);
+  const size_t lds = tile_lds(a.TL, a.M);
+  const unsigned blocks = (unsigned)a.ntiles;
   hipLaunchKernelGGL(k_dst, dim3(blocks), dim3(KFBI_BLOCK), lds, pl->stream, a);
 }
 
@@ -365,8 +392,8 @@ kfbi_status dst_init(kfbi_plan* pl) {
   HIPCHK(hipMemcpyAsync(pl->tw, tw.data(), sizeof(double) * 2 * M, hipMemcpyHostToDevice, pl->stream));
   HIPCHK(hipMemcpyAsync(pl->eig1, eig.data(), sizeof(double) * (N + 1), hipMemcpyHostToDevice, pl->stream));
   HIPCHK(hipStreamSynchronize(pl->stream));
-  int lds = (int)(sizeof(double2) * 2 * (size_t)(tile_lines(M) / 2) * (M + (pad_shift(M) == 3 ? M / 8 : 0)));
-  if (lds > 65536) {
+  const size_t lds = tile_lds(tile_lines(pl->g.d, N), M);
+  if (lds > DST_LDS_CU) {
     kfbi_set_error("box solver LDS footprint too large (N = %d)", N);
     return KFBI_E_INVALID;
   }
