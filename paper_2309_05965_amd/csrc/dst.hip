@@ -30,29 +30,24 @@
 
 namespace {
 
-constexpr int DST_LDS_BUDGET = 98304;  // bytes of the two ping-pong buffers of a work group
 constexpr size_t DST_LDS_CU = 163840;  // LDS of one compute unit
 constexpr int DST_CH = 8;               // loads in flight per thread while a tile is read
+constexpr int PS = 3;                   // LDS pad shift (see padi)
 
 struct DstArgs {
   const int* ctl;      // nothing to do once ctl[1] is set (device GMRES loop)
   // source of the first pass of the matvec: the corrected right-hand side,
-  // zero except at the irregular nodes, built here from the density
+  // zero except at the irregular nodes, built here from the correction
+  // values of the density
   int src_corr;
-  const double* psi;   // density (or V[ctl[0]] in the device GMRES loop)
-  const double* Vb;
-  int64_t n_dof;
   const int *row_start, *row_end, *irr, *PE1, *PE2;
   const double *PA, *Cv;
-  int maxpairs, nF;
+  int maxpairs;
   GridDesc g;
   int ax;          // transform axis
   int mode;        // 0: DST; 1: DST, divide by lambda and scale, DST
   int TL;          // lines per tile (even)
-  int M, logM;     // FFT length 2N
-  int ps;          // LDS pad shift (see padi)
   int tiles_u;     // tiles along the tile axis
-  int ntiles;      // tiles of the pass
   const double* in;
   double* out;
   const double2* tw;   // exp(-2 pi i m / M), m < M
@@ -60,72 +55,104 @@ struct DstArgs {
   double scale;        // (2/N)^d
 };
 
-// LDS layout of a sequence: element i at i + (i >> ps), one pad slot per
-// 2^ps 16-byte elements (ps = 3 when the padded tile fits, else ps = 31, no
-// padding), so the strided writes of the early Stockham stages spread over
-// the banks
-__device__ __forceinline__ int padi(int i, int ps) { return i + (i >> ps); }
+// LDS layout of a sequence: element i at i + (i >> PS), one pad slot per 8
+// 16-byte elements, so the strided writes of the early Stockham stages
+// spread over the banks
+__device__ __forceinline__ int padi(int i) { return i + (i >> PS); }
+
+constexpr int padded_len(int M) { return M + (M >> PS); }
 
 __device__ __forceinline__ double2 cmul(double2 a, double2 b) {
   return make_double2(a.x * b.x - a.y * b.y, a.x * b.y + a.y * b.x);
 }
 
-// nf forward DFTs of length M = 2^logM (natural order in, natural order out)
-// by self-sorting Stockham stages, radix 4 then one radix 2 if logM is odd:
-// stage with span Ns reads x[j + r M/R], twiddles by exp(-2 pi i r k/(R Ns)),
-// k = j mod Ns, and writes y[(j - k) R + k + r Ns].  Returns the buffer that
-// holds the result (a or b).
-__device__ double2* fft_stockham(double2* a, double2* b, const double2* __restrict__ tw, int nf, int M,
-                                 int logM, int ps) {
-  const int Mp = M + (M >> ps);    // padded sequence stride
-  int Ns = 1, lNs = 0;
-  while (Ns < M) {
-    if (4 * Ns <= M) {
-      const int lQ = logM - 2, Q = 1 << lQ;
-      const int tsh = logM - 2 - lNs;             // twiddle step M / (4 Ns)
-      for (int t = threadIdx.x; t < (nf << lQ); t += blockDim.x) {
-        const int f = t >> lQ, j = t & (Q - 1), k = j & (Ns - 1);
-        const double2* x = a + f * Mp;
-        double2* y = b + f * Mp;
-        double2 v0 = x[padi(j, ps)], v1 = x[padi(j + Q, ps)], v2 = x[padi(j + 2 * Q, ps)], v3 = x[padi(j + 3 * Q, ps)];
-        const int st = k << tsh;
-        v1 = cmul(v1, tw[st]);
-        v2 = cmul(v2, tw[2 * st]);
-        v3 = cmul(v3, tw[3 * st]);
-        double2 t0 = make_double2(v0.x + v2.x, v0.y + v2.y), t1 = make_double2(v0.x - v2.x, v0.y - v2.y);
-        double2 t2 = make_double2(v1.x + v3.x, v1.y + v3.y), t3 = make_double2(v1.x - v3.x, v1.y - v3.y);
-        const int d = ((j - k) << 2) + k;
-        y[padi(d, ps)] = make_double2(t0.x + t2.x, t0.y + t2.y);
-        y[padi(d + Ns, ps)] = make_double2(t1.x + t3.y, t1.y - t3.x);
-        y[padi(d + 2 * Ns, ps)] = make_double2(t0.x - t2.x, t0.y - t2.y);
-        y[padi(d + 3 * Ns, ps)] = make_double2(t1.x - t3.y, t1.y + t3.x);
+// Stockham FFT of length M = 2^LOGM: radix-4 stages s = 0..LOGM/2-1 (span
+// Ns = 4^s), then one radix-2 stage if LOGM is odd.  A stage with span Ns
+// reads x[j + r M/R], twiddles by exp(-2 pi i r k/(R Ns)), k = j mod Ns,
+// and writes y[(j - k) R + k + r Ns].  With 256 threads, t = threadIdx.x +
+// 256 i, the k of a radix-4 stage is threadIdx.x mod Ns for every i (Ns <=
+// 256 for M <= 2048), so a thread's twiddles are fixed per stage and are
+// read once, into registers, before the tile arrives.  Only the closing
+// radix-2 stage of M = 2048 (Ns = 1024) cycles through four.
+template <int LOGM>
+struct Twiddles {
+  static constexpr int M = 1 << LOGM, NS4 = LOGM / 2;
+  static constexpr int N2 = (LOGM & 1) ? (M / 2 > KFBI_BLOCK ? M / 2 / KFBI_BLOCK : 1) : 1;
+  double2 w4[NS4 > 1 ? NS4 - 1 : 1][3];   // stages 1..NS4-1 (stage 0: k = 0, unit twiddles)
+  double2 w2[N2];
+
+  __device__ __forceinline__ void load(const double2* __restrict__ tw) {
+#pragma unroll
+    for (int s = 1; s < NS4; ++s) {
+      const int st = ((int)threadIdx.x & ((1 << (2 * s)) - 1)) << (LOGM - 2 - 2 * s);
+      w4[s - 1][0] = tw[st];
+      w4[s - 1][1] = tw[2 * st];
+      w4[s - 1][2] = tw[3 * st];
+    }
+    if (LOGM & 1) {
+#pragma unroll
+      for (int r = 0; r < N2; ++r) w2[r] = tw[((int)threadIdx.x + KFBI_BLOCK * r) & (M / 2 - 1)];
+    }
+  }
+};
+
+// nf forward DFTs of length M (natural order in and out) in the LDS
+// buffers a and b; returns the one that holds the result
+template <int LOGM>
+__device__ double2* fft_stockham(double2* a, double2* b, const Twiddles<LOGM>& T, int nf) {
+  constexpr int M = 1 << LOGM, Mp = padded_len(M), NS4 = LOGM / 2;
+#pragma unroll
+  for (int s = 0; s < NS4; ++s) {
+    const int Ns = 1 << (2 * s);
+    constexpr int lQ = LOGM - 2, Q = 1 << lQ;
+    for (int t = threadIdx.x; t < (nf << lQ); t += KFBI_BLOCK) {
+      const int f = t >> lQ, j = t & (Q - 1), k = j & (Ns - 1);
+      const double2* x = a + f * Mp;
+      double2* y = b + f * Mp;
+      double2 v0 = x[padi(j)], v1 = x[padi(j + Q)], v2 = x[padi(j + 2 * Q)], v3 = x[padi(j + 3 * Q)];
+      if (s > 0) {
+        v1 = cmul(v1, T.w4[s - 1][0]);
+        v2 = cmul(v2, T.w4[s - 1][1]);
+        v3 = cmul(v3, T.w4[s - 1][2]);
       }
-      Ns <<= 2;
-      lNs += 2;
-    } else {
-      const int lQ = logM - 1, Q = 1 << lQ;
-      const int tsh = logM - 1 - lNs;
-      for (int t = threadIdx.x; t < (nf << lQ); t += blockDim.x) {
-        const int f = t >> lQ, j = t & (Q - 1), k = j & (Ns - 1);
-        const double2* x = a + f * Mp;
-        double2* y = b + f * Mp;
-        double2 v0 = x[padi(j, ps)], v1 = cmul(x[padi(j + Q, ps)], tw[k << tsh]);
-        const int d = ((j - k) << 1) + k;
-        y[padi(d, ps)] = make_double2(v0.x + v1.x, v0.y + v1.y);
-        y[padi(d + Ns, ps)] = make_double2(v0.x - v1.x, v0.y - v1.y);
-      }
-      Ns <<= 1;
-      lNs += 1;
+      double2 t0 = make_double2(v0.x + v2.x, v0.y + v2.y), t1 = make_double2(v0.x - v2.x, v0.y - v2.y);
+      double2 t2 = make_double2(v1.x + v3.x, v1.y + v3.y), t3 = make_double2(v1.x - v3.x, v1.y - v3.y);
+      const int d = ((j - k) << 2) + k;
+      y[padi(d)] = make_double2(t0.x + t2.x, t0.y + t2.y);
+      y[padi(d + Ns)] = make_double2(t1.x + t3.y, t1.y - t3.x);
+      y[padi(d + 2 * Ns)] = make_double2(t0.x - t2.x, t0.y - t2.y);
+      y[padi(d + 3 * Ns)] = make_double2(t1.x - t3.y, t1.y + t3.x);
     }
     __syncthreads();
-    double2* t = a;
+    double2* tmp = a;
     a = b;
-    b = t;
+    b = tmp;
+  }
+  if (LOGM & 1) {
+    // span Ns = M/2: k = j, output positions j and j + M/2
+    constexpr int lQ = LOGM - 1, Q = 1 << lQ, N2 = Twiddles<LOGM>::N2;
+    for (int t0 = threadIdx.x; t0 < (nf << lQ); t0 += KFBI_BLOCK * N2) {
+#pragma unroll
+      for (int r = 0; r < N2; ++r) {
+        const int t = t0 + KFBI_BLOCK * r;
+        if (t >= (nf << lQ)) break;
+        const int f = t >> lQ, j = t & (Q - 1);
+        const double2* x = a + f * Mp;
+        double2* y = b + f * Mp;
+        const double2 v0 = x[padi(j)], v1 = cmul(x[padi(j + Q)], T.w2[r]);
+        y[padi(j)] = make_double2(v0.x + v1.x, v0.y + v1.y);
+        y[padi(j + Q)] = make_double2(v0.x - v1.x, v0.y - v1.y);
+      }
+    }
+    __syncthreads();
+    double2* tmp = a;
+    a = b;
+    b = tmp;
   }
   return a;
 }
 
-// address of element j (1..N-1 along the axis) of the line at tile
+// address of element j (0..N along the axis) of the line at tile
 // coordinate u and remaining coordinate w
 __device__ __forceinline__ int64_t elem_addr(const DstArgs& a, int u, int w, int j) {
   const GridDesc& g = a.g;
@@ -140,22 +167,22 @@ __device__ __forceinline__ int64_t elem_addr(const DstArgs& a, int u, int w, int
   return (int64_t)c[0] + (int64_t)g.n1 * ((int64_t)c[1] + (int64_t)g.n1 * c[2]);
 }
 
-__device__ __forceinline__ double eigenvalue(const DstArgs& a, int k, int u, int w) {
-  const GridDesc& g = a.g;
-  double sv[3] = {0.0, 0.0, 0.0};
-  int ua = a.ax == 0 ? 1 : 0;
-  sv[a.ax] = a.eig1[k];
-  sv[ua] = a.eig1[u];
-  if (g.d == 3) sv[3 - a.ax - ua] = a.eig1[w];
-  double h2 = g.h * g.h;
-  double lap = 0.0, pr = 0.0;
-  for (int t = 0; t < g.d; ++t) {
-    lap += sv[t];
-    for (int t2 = t + 1; t2 < g.d; ++t2) pr += sv[t] * sv[t2];
+// lambda from the 1D eigenvalues s_k (k along the transform axis), s_u and,
+// in 3D, s_w
+__device__ __forceinline__ double eigenvalue(const GridDesc& g, double sk, double su, double sw) {
+  const double h2 = g.h * g.h;
+  double lap, pr, tri = 0.0;
+  if (g.d == 2) {
+    lap = sk + su;
+    pr = sk * su;
+  } else {
+    lap = sk + su + sw;
+    pr = sk * su + sk * sw + su * sw;
+    tri = sk * su * sw;
   }
   if (g.order == 2) return lap - g.kappa;
   double lam = lap + h2 / 6.0 * pr;
-  if (g.d == 3) lam += h2 * h2 / 48.0 * sv[0] * sv[1] * sv[2];
+  if (g.d == 3) lam += h2 * h2 / 48.0 * tri;
   return lam - g.kappa * (1.0 + h2 / 12.0 * lap);
 }
 
@@ -177,9 +204,11 @@ __device__ __forceinline__ void tile_pos(const DstArgs& a, int idx, int nl, int&
 // values of the current density; zero elsewhere.  The pair table of a node
 // is read four pairs at a time so that the gathers of a group are in flight
 // together; the sum runs over the pairs in table order.
-__device__ void corrected_rhs(const DstArgs& a, double2* A, int Mp, int u0, int w) {
+template <int M>
+__device__ void corrected_rhs(const DstArgs& a, double2* A, int u0, int w) {
   const GridDesc& g = a.g;
-  const int M = a.M, ps = a.ps, nl = g.N - 1, nf = a.TL / 2;
+  constexpr int Mp = padded_len(M);
+  const int nl = g.N - 1, nf = a.TL / 2;
   for (int i = threadIdx.x; i < nf * Mp; i += blockDim.x) A[i] = make_double2(0.0, 0.0);
   __syncthreads();
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -217,24 +246,31 @@ __device__ void corrected_rhs(const DstArgs& a, double2* A, int Mp, int u0, int 
       const int j = a.irr[t] % g.n1;
       double2* z = A + (l >> 1) * Mp;
       if (l & 1) {
-        z[padi(j, ps)].y = F;
-        z[padi(M - j, ps)].y = -F;
+        z[padi(j)].y = F;
+        z[padi(M - j)].y = -F;
       } else {
-        z[padi(j, ps)].x = F;
-        z[padi(M - j, ps)].x = -F;
+        z[padi(j)].x = F;
+        z[padi(M - j)].x = -F;
       }
     }
   }
 }
 
-// One axis pass: a work group transforms one tile of TL lines.
+// LDS of a work group: the two ping-pong buffers
+size_t tile_lds(int TL, int N) { return sizeof(double2) * 2 * (size_t)(TL / 2) * padded_len(2 * N); }
+
+// One axis pass (MODE 0: DST; MODE 1: DST, divide by lambda and scale, DST):
+// a work group transforms one tile of TL lines, FFT length M = 2N =
+// 2^LOGM.  Every global load the tile needs -- the input, the thread's
+// twiddles and (MODE 1) the 1D eigenvalues -- is issued up front, so the
+// work group waits on HBM once before its FFT stages.
+template <int LOGM, int MODE>
 __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
   if (a.ctl && a.ctl[1]) return;
+  constexpr int M = 1 << LOGM, N = M / 2, Mp = padded_len(M);
   extern __shared__ double2 lds[];
   const GridDesc& g = a.g;
-  const int N = g.N, M = a.M, TL = a.TL, nf = TL / 2;
-  const int ps = a.ps;
-  const int Mp = M + (M >> ps);                     // padded sequence stride
+  const int TL = a.TL, nf = TL / 2;
   double2* A = lds;                                 // [nf][Mp]
   double2* B = lds + nf * Mp;                       // [nf][Mp]
   // tiles in XCD-contiguous order (neighbouring tiles share cache lines
@@ -242,81 +278,97 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
   const int tile = kfbi_xcd_block(blockIdx.x, gridDim.x);
   const int w = tile / a.tiles_u + 1;               // remaining interior coordinate (3D)
   const int u0 = 1 + (tile % a.tiles_u) * TL;       // first tile coordinate
-  const int nl = N - 1;
+  constexpr int nl = N - 1;
   const int total = TL * nl;
+  Twiddles<LOGM> T;
+  T.load(a.tw);
+  // MODE 1: s_k for this thread's k = threadIdx.x + 256 q, s_u of the
+  // tile's lines and s_w
+  constexpr int NE = MODE == 1 ? (N + KFBI_BLOCK - 1) / KFBI_BLOCK : 1;
+  double sk[NE], su[8], sw = 0.0;
+  if (MODE == 1) {
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int k = threadIdx.x + q * KFBI_BLOCK;
+      sk[q] = k <= nl ? a.eig1[k] : 0.0;
+    }
+#pragma unroll
+    for (int l = 0; l < 8; ++l) su[l] = a.eig1[(l < TL && u0 + l <= nl) ? u0 + l : 1];
+    if (g.d == 3) sw = a.eig1[w];
+  }
   if (a.src_corr) {
-    corrected_rhs(a, A, Mp, u0, w);
+    corrected_rhs<M>(a, A, u0, w);
   } else {
     for (int f = threadIdx.x; f < nf; f += blockDim.x) {
       A[f * Mp] = make_double2(0.0, 0.0);
-      A[f * Mp + padi(N, ps)] = make_double2(0.0, 0.0);
+      A[f * Mp + padi(N)] = make_double2(0.0, 0.0);
     }
     // all loads of a chunk are issued before the LDS stores
-    for (int base = threadIdx.x; base < total; base += DST_CH * (int)blockDim.x) {
+    for (int base = threadIdx.x; base < total; base += DST_CH * KFBI_BLOCK) {
       double xv[DST_CH];
 #pragma unroll
       for (int q = 0; q < DST_CH; ++q) {
-        const int idx = base + q * (int)blockDim.x;
+        const int idx = base + q * KFBI_BLOCK;
         int l, j;
         tile_pos(a, idx, nl, l, j);
         xv[q] = (idx < total && u0 + l <= nl) ? a.in[elem_addr(a, u0 + l, w, j)] : 0.0;
       }
 #pragma unroll
       for (int q = 0; q < DST_CH; ++q) {
-        const int idx = base + q * (int)blockDim.x;
+        const int idx = base + q * KFBI_BLOCK;
         if (idx >= total) continue;
         int l, j;
         tile_pos(a, idx, nl, l, j);
         double2* z = A + (l >> 1) * Mp;
         if (l & 1) {
-          z[padi(j, ps)].y = xv[q];
-          z[padi(M - j, ps)].y = -xv[q];
+          z[padi(j)].y = xv[q];
+          z[padi(M - j)].y = -xv[q];
         } else {
-          z[padi(j, ps)].x = xv[q];
-          z[padi(M - j, ps)].x = -xv[q];
+          z[padi(j)].x = xv[q];
+          z[padi(M - j)].x = -xv[q];
         }
       }
     }
   }
   __syncthreads();
-  double2* R = fft_stockham(A, B, a.tw, nf, M, a.logM, ps);
-  if (a.mode == 1) {
+  double2* R = fft_stockham<LOGM>(A, B, T, nf);
+  if (MODE == 1) {
     // S_A(k) = -Im Z_k / 2 (even line), S_B(k) = Re Z_k / 2 (odd line); divide
-    // by lambda, scale, and form the odd sequences of the inverse transform
+    // by lambda, scale, and form the odd sequences of the inverse transform.
+    // Lines past the grid (u > N-1) carry zeros and take s_u = s_1, a
+    // nonzero lambda, so they stay zero.
     double2* S = R == A ? B : A;
     for (int f = threadIdx.x; f < nf; f += blockDim.x) {
       S[f * Mp] = make_double2(0.0, 0.0);
-      S[f * Mp + padi(N, ps)] = make_double2(0.0, 0.0);
+      S[f * Mp + padi(N)] = make_double2(0.0, 0.0);
     }
-    for (int idx = threadIdx.x; idx < nf * nl; idx += blockDim.x) {
-      int f = idx / nl, k = idx % nl + 1;
-      double2 Z = R[f * Mp + padi(k, ps)];
-      int uA = u0 + 2 * f, uB = uA + 1;
-      double lamA = eigenvalue(a, k, uA <= nl ? uA : 1, w);
-      double lamB = eigenvalue(a, k, uB <= nl ? uB : 1, w);
-      double2 c = make_double2(a.scale * (-0.5 * Z.y) / lamA, a.scale * (0.5 * Z.x) / lamB);
-      S[f * Mp + padi(k, ps)] = c;
-      S[f * Mp + padi(M - k, ps)] = make_double2(-c.x, -c.y);
+#pragma unroll
+    for (int q = 0; q < NE; ++q) {
+      const int k = threadIdx.x + q * KFBI_BLOCK;
+      if (k < 1 || k > nl) continue;
+#pragma unroll
+      for (int f = 0; f < 4; ++f) {
+        if (f >= nf) break;
+        const double2 Z = R[f * Mp + padi(k)];
+        const double lamA = eigenvalue(g, sk[q], su[2 * f], sw);
+        const double lamB = eigenvalue(g, sk[q], su[2 * f + 1], sw);
+        const double2 c = make_double2(a.scale * (-0.5 * Z.y) / lamA, a.scale * (0.5 * Z.x) / lamB);
+        S[f * Mp + padi(k)] = c;
+        S[f * Mp + padi(M - k)] = make_double2(-c.x, -c.y);
+      }
     }
     __syncthreads();
-    R = fft_stockham(S, R, a.tw, nf, M, a.logM, ps);
+    R = fft_stockham<LOGM>(S, R, T, nf);
   }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     int l, k;
     tile_pos(a, idx, nl, l, k);
     const int u = u0 + l;
     if (u > nl) continue;
-    double2 Z = R[(l >> 1) * Mp + padi(k, ps)];
+    const double2 Z = R[(l >> 1) * Mp + padi(k)];
     a.out[elem_addr(a, u, w, k)] = (l & 1) ? 0.5 * Z.x : -0.5 * Z.y;
   }
 }
-
-// LDS pad shift for FFT length M: padded when a padded pair of buffers fits
-int pad_shift(int M) { return 2 * (M + M / 8) * (int)sizeof(double2) <= DST_LDS_BUDGET ? 3 : 31; }
-
-int padded_len(int M) { return M + (pad_shift(M) == 3 ? M / 8 : 0); }
-
-size_t tile_lds(int TL, int M) { return sizeof(double2) * 2 * (size_t)(TL / 2) * padded_len(M); }
 
 // lines per tile: the largest even TL <= 8 whose LDS footprint still lets
 // 4 work groups (16 waves) share a compute unit and that leaves at least
@@ -325,25 +377,28 @@ size_t tile_lds(int TL, int M) { return sizeof(double2) * 2 * (size_t)(TL / 2) *
 // enough loads in flight.  (Measured on the 3D 64/128/256 and 2D grids:
 // TL = 2, 8, 4 and 2 respectively.)
 int tile_lines(int d, int N) {
-  const int nl = N - 1, M = 2 * N;
+  const int nl = N - 1;
   const int64_t lines = d == 3 ? (int64_t)nl * nl : nl;
   for (int tl = 8; tl > 2; tl -= 2) {
-    const size_t lds = tile_lds(tl, M);
-    if (lds * 4 > DST_LDS_CU) continue;
+    if (tile_lds(tl, N) * 4 > DST_LDS_CU) continue;
     if ((lines + tl - 1) / tl < 1024) continue;
     return tl;
   }
   return 2;
 }
 
-void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out, const double* psi = nullptr,
-                 bool src_corr = false) {
+template <int LOGM>
+void launch_t(const DstArgs& a, unsigned blocks, size_t lds, hipStream_t st) {
+  if (a.mode == 1)
+    hipLaunchKernelGGL((k_dst<LOGM, 1>), dim3(blocks), dim3(KFBI_BLOCK), lds, st, a);
+  else
+    hipLaunchKernelGGL((k_dst<LOGM, 0>), dim3(blocks), dim3(KFBI_BLOCK), lds, st, a);
+}
+
+void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out, bool src_corr = false) {
   DstArgs a;
   a.ctl = pl->ctl_active;
   a.src_corr = src_corr ? 1 : 0;
-  a.psi = psi;
-  a.Vb = pl->V;
-  a.n_dof = pl->n_dof;
   a.row_start = pl->row_start;
   a.row_end = pl->row_end;
   a.irr = pl->irr;
@@ -352,27 +407,30 @@ void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out,
   a.PA = pl->PA;
   a.Cv = pl->Cv;
   a.maxpairs = pl->maxpairs;
-  a.nF = pl->nF;
   a.g = pl->g;
   a.ax = ax;
   a.mode = mode;
-  a.M = 2 * pl->g.N;
-  a.logM = 0;
-  while ((1 << a.logM) < a.M) ++a.logM;
-  const int nl = pl->g.N - 1;
-  a.TL = tile_lines(pl->g.d, pl->g.N);
+  const int N = pl->g.N, nl = N - 1;
+  a.TL = tile_lines(pl->g.d, N);
   a.tiles_u = (nl + a.TL - 1) / a.TL;
-  a.ntiles = a.tiles_u * (pl->g.d == 3 ? nl : 1);
   a.in = in;
   a.out = out;
   a.tw = (const double2*)pl->tw;
   a.eig1 = pl->eig1;
   a.scale = 1.0;
-  for (int t = 0; t < pl->g.d; ++t) a.scale *= 2.0 / pl->g.N;
-  a.ps = pad_shift(a.M);
-  const size_t lds = tile_lds(a.TL, a.M);
-  const unsigned blocks = (unsigned)a.ntiles;
-  hipLaunchKernelGGL(k_dst, dim3(blocks), dim3(KFBI_BLOCK), lds, pl->stream, a);
+  for (int t = 0; t < pl->g.d; ++t) a.scale *= 2.0 / N;
+  const unsigned blocks = (unsigned)(a.tiles_u * (pl->g.d == 3 ? nl : 1));
+  const size_t lds = tile_lds(a.TL, N);
+  switch (N) {   // N is a power of two in [8, 1024]
+    case 8: launch_t<4>(a, blocks, lds, pl->stream); break;
+    case 16: launch_t<5>(a, blocks, lds, pl->stream); break;
+    case 32: launch_t<6>(a, blocks, lds, pl->stream); break;
+    case 64: launch_t<7>(a, blocks, lds, pl->stream); break;
+    case 128: launch_t<8>(a, blocks, lds, pl->stream); break;
+    case 256: launch_t<9>(a, blocks, lds, pl->stream); break;
+    case 512: launch_t<10>(a, blocks, lds, pl->stream); break;
+    default: launch_t<11>(a, blocks, lds, pl->stream); break;
+  }
 }
 
 }  // namespace
@@ -392,8 +450,8 @@ kfbi_status dst_init(kfbi_plan* pl) {
   HIPCHK(hipMemcpyAsync(pl->tw, tw.data(), sizeof(double) * 2 * M, hipMemcpyHostToDevice, pl->stream));
   HIPCHK(hipMemcpyAsync(pl->eig1, eig.data(), sizeof(double) * (N + 1), hipMemcpyHostToDevice, pl->stream));
   HIPCHK(hipStreamSynchronize(pl->stream));
-  const size_t lds = tile_lds(tile_lines(pl->g.d, N), M);
-  if (lds > DST_LDS_CU) {
+  const size_t lds = tile_lds(tile_lines(pl->g.d, N), N);
+  if (N < 8 || N > 1024 || (N & (N - 1)) || lds > DST_LDS_CU) {
     kfbi_set_error("box solver LDS footprint too large (N = %d)", N);
     return KFBI_E_INVALID;
   }
@@ -432,11 +490,11 @@ void dst_solve(kfbi_plan* pl, const double* F, double* v) {
 // inside the first pass (no right-hand-side array)
 void dst_solve_corrections(kfbi_plan* pl, const double* psi, double* v) {
   if (pl->g.d == 2) {
-    launch_pass(pl, 0, 0, nullptr, pl->T1, psi, true);
+    launch_pass(pl, 0, 0, nullptr, pl->T1, true);
     launch_pass(pl, 1, 1, pl->T1, pl->T2);
     launch_pass(pl, 0, 0, pl->T2, v);
   } else {
-    launch_pass(pl, 0, 0, nullptr, pl->T1, psi, true);
+    launch_pass(pl, 0, 0, nullptr, pl->T1, true);
     launch_pass(pl, 1, 0, pl->T1, pl->T2);
     launch_pass(pl, 2, 1, pl->T2, pl->T1);
     launch_pass(pl, 1, 0, pl->T1, pl->T2);
