@@ -138,6 +138,7 @@ void free_plan(kfbi_plan* pl) {
   dfree(pl->tw);
   dfree(pl->eig1);
   dfree(pl->V);
+  dfree(pl->gm_part);
   dfree(pl->Hm);
   dfree(pl->gv);
   dfree(pl->cs);
@@ -284,8 +285,11 @@ kfbi_status need_ready(const kfbi_plan* pl) {
 kfbi_status ensure_gmres(kfbi_plan* pl, int m) {
   if (m <= pl->gm_cap && pl->n_dof <= pl->gm_n && pl->V) return KFBI_OK;
   dfree(pl->V);
+  dfree(pl->gm_part);
   int mm = m > pl->gm_cap ? m : pl->gm_cap;
   KCHK(dalloc(&pl->V, (int64_t)(mm + 1) * pl->cap_dof));
+  pl->gm_pb = gm_part_blocks(pl->cap_dof);
+  KCHK(dalloc(&pl->gm_part, (int64_t)3 * pl->gm_pb * (mm + 2)));
   pl->gm_cap = mm;
   pl->gm_n = pl->cap_dof;
   return KFBI_OK;

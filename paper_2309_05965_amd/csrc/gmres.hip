@@ -35,11 +35,24 @@ __global__ void __launch_bounds__(GB) k_start(int64_t n, const double* b, const 
                                              double* gv, double* scal, int* ctl, double tol, int maxit) {
   __shared__ double sh[GB];
   double sb = 0.0, sr = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += GB) {
-    double r = Ax0 ? b[i] - Ax0[i] : b[i];
-    V[i] = r;
-    sb += b[i] * b[i];
-    sr += r * r;
+  // eight elements per thread per round, loads issued before the stores
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += 8 * GB) {
+    double bv[8], av[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t i = i0 + (int64_t)q * GB;
+      bv[q] = i < n ? b[i] : 0.0;
+      av[q] = (i < n && Ax0) ? Ax0[i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t i = i0 + (int64_t)q * GB;
+      if (i >= n) continue;
+      const double r = Ax0 ? bv[q] - av[q] : bv[q];
+      V[i] = r;
+      sb += bv[q] * bv[q];
+      sr += r * r;
+    }
   }
   double nb = sqrt(block_sum(sb, sh));
   double beta = sqrt(block_sum(sr, sh));
@@ -59,98 +72,325 @@ __global__ void __launch_bounds__(GB) k_start(int64_t n, const double* b, const 
 }
 
 // Arnoldi step j: w = V[j+1] (holds A V[j]) is orthogonalised against
-// V[0..j] by classical Gram-Schmidt applied twice (CGS2: the j+1 dot
-// products of a pass are computed concurrently, one wavefront per basis
-// vector, with fixed-order wave reductions), then normalised; the Givens
-// rotations are applied to column j.
+// V[0..j] by classical Gram-Schmidt applied twice (CGS2), then normalised;
+// the Givens rotations are applied to column j.  Every reduction runs in a
+// fixed order, so the step is bitwise reproducible.
 __device__ __forceinline__ double wave_reduce(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
 }
 
-__global__ void __launch_bounds__(GB) k_arnoldi(int64_t n, int* ctl, int ldh, double* V, double* Hm, double* cs,
-                                               double* sn, double* gv, double* scal) {
+// Givens rotations of Hessenberg column j held in hs[0..j+1] (hs[j+1] =
+// |w|): the previous rotations (lcs, lsn) are applied in order, rotation j
+// is formed and applied to g; the residual estimate |g_{j+1}|, the
+// breakdown flag and the control word are updated.  One thread.
+__device__ void givens_column(int j, double* hs, const double* lcs, const double* lsn, double* cs, double* sn,
+                              double* gv, double* scal, int* ctl, bool breakdown) {
+  for (int i = 0; i < j; ++i) {
+    double t = lcs[i] * hs[i] + lsn[i] * hs[i + 1];
+    hs[i + 1] = -lsn[i] * hs[i] + lcs[i] * hs[i + 1];
+    hs[i] = t;
+  }
+  double den = hypot(hs[j], hs[j + 1]);
+  double cj = hs[j] / den, sj = hs[j + 1] / den;
+  cs[j] = cj;
+  sn[j] = sj;
+  hs[j] = den;
+  hs[j + 1] = 0.0;
+  double gj = gv[j];
+  gv[j + 1] = -sj * gj;
+  gv[j] = cj * gj;
+  double res = fabs(-sj * gj);
+  scal[0] = res;
+  scal[2] = breakdown ? 1.0 : 0.0;
+  ctl[2] = j + 1;
+  ctl[0] = j + 1;
+  ctl[1] = (res <= scal[3] * scal[1] || breakdown || j + 1 >= ctl[3]) ? 1 : 0;
+}
+
+// Sum over the 64 lanes of eight per-lane values p[0..7] by a transposing
+// butterfly: at xor distance 32, 16 and 8 each lane keeps half of its
+// values and adds the partner's half, then three plain steps finish one
+// value.  Lane l ends with the total of value 4 b5 + 2 b4 + b3 (b = bits of
+// l); 10 shuffles instead of 48.  Fixed order, so reproducible.
+__device__ __forceinline__ double wave_reduce8(const double (&p)[8], int lane) {
+  const bool h32 = lane & 32, h16 = lane & 16, h8 = lane & 8;
+  double a[4], b[2];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double send = h32 ? p[q] : p[q + 4];
+    const double keep = h32 ? p[q + 4] : p[q];
+    a[q] = keep + __shfl_xor(send, 32, 64);
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const double send = h16 ? a[q] : a[q + 2];
+    const double keep = h16 ? a[q + 2] : a[q];
+    b[q] = keep + __shfl_xor(send, 16, 64);
+  }
+  double c;
+  {
+    const double send = h8 ? b[0] : b[1];
+    const double keep = h8 ? b[1] : b[0];
+    c = keep + __shfl_xor(send, 8, 64);
+  }
+  for (int off = 4; off > 0; off >>= 1) c += __shfl_xor(c, off, 64);
+  return c;
+}
+
+__device__ __forceinline__ int wave_reduce8_index(int lane) {
+  return ((lane & 32) ? 4 : 0) + ((lane & 16) ? 2 : 0) + ((lane & 8) ? 1 : 0);
+}
+
+// Single work group (n <= 8192): w is staged in LDS for the whole step.
+// A pass computes the j+1 dot products one wavefront per basis vector
+// (lanes over the elements, eight loads of V in flight per lane, w from
+// LDS, fixed-order wave reduction), then every thread updates its elements
+// of w in LDS, eight basis vectors per round.
+constexpr int ARN1_MAXN = 8192;
+__global__ void __launch_bounds__(GB) k_arnoldi1(int64_t n, int* ctl, int ldh, double* V, double* Hm, double* cs,
+                                                double* sn, double* gv, double* scal) {
+  __shared__ double wl[ARN1_MAXN];
   __shared__ double hp[KFBI_GMRES_MAX + 1];
-  __shared__ double hs[KFBI_GMRES_MAX + 1];
+  __shared__ double hs[KFBI_GMRES_MAX + 2];
+  __shared__ double lcs[KFBI_GMRES_MAX], lsn[KFBI_GMRES_MAX];
   __shared__ double red[GB / 64];
   if (ctl[1]) return;
   const int j = ctl[0];
+  const int nn = (int)n;
   const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
   double* w = V + (int64_t)(j + 1) * n;
-  double* hcol = Hm + (int64_t)j * ldh;
+  for (int t0 = threadIdx.x; t0 < nn; t0 += 8 * GB) {
+    double x[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) x[q] = t0 + q * GB < nn ? w[t0 + q * GB] : 0.0;
+#pragma unroll
+    for (int q = 0; q < 8; ++q)
+      if (t0 + q * GB < nn) wl[t0 + q * GB] = x[q];
+  }
+  for (int i = threadIdx.x; i < j; i += GB) {
+    lcs[i] = cs[i];
+    lsn[i] = sn[i];
+  }
+  __syncthreads();
   for (int pass = 0; pass < 2; ++pass) {
-    // one wavefront per basis vector: h_i = <w, V_i>; four independent
-    // partial sums per lane keep several loads in flight
     for (int i = wave; i <= j; i += GB / 64) {
       const double* vi = V + (int64_t)i * n;
-      double s0 = 0.0, s1 = 0.0, s2 = 0.0, s3 = 0.0;
-      int64_t t = lane;
-      for (; t + 192 < n; t += 256) {
-        s0 += w[t] * vi[t];
-        s1 += w[t + 64] * vi[t + 64];
-        s2 += w[t + 128] * vi[t + 128];
-        s3 += w[t + 192] * vi[t + 192];
+      double acc[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) acc[q] = 0.0;
+      for (int t0 = lane; t0 < nn; t0 += 8 * 64) {
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int t = t0 + 64 * q;
+          if (t < nn) acc[q] += wl[t] * vi[t];
+        }
       }
-      for (; t < n; t += 64) s0 += w[t] * vi[t];
-      double sacc = wave_reduce((s0 + s1) + (s2 + s3));
+      const double sacc = wave_reduce(((acc[0] + acc[1]) + (acc[2] + acc[3])) + ((acc[4] + acc[5]) + (acc[6] + acc[7])));
       if (lane == 0) hp[i] = sacc;
     }
     __syncthreads();
     for (int i = threadIdx.x; i <= j; i += GB) hs[i] = pass == 0 ? hp[i] : hs[i] + hp[i];
-    for (int64_t t = threadIdx.x; t < n; t += GB) {
-      double v = w[t];
-#pragma unroll 8
-      for (int i = 0; i <= j; ++i) v -= hp[i] * V[(int64_t)i * n + t];
-      w[t] = v;
+    for (int t = threadIdx.x; t < nn; t += GB) {
+      double v = wl[t];
+      for (int i0 = 0; i0 <= j; i0 += 8) {
+        double x[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) x[q] = i0 + q <= j ? V[(int64_t)(i0 + q) * n + t] : 0.0;
+#pragma unroll
+        for (int q = 0; q < 8; ++q)
+          if (i0 + q <= j) v -= hp[i0 + q] * x[q];
+      }
+      wl[t] = v;
     }
     __syncthreads();
   }
   double sq = 0.0;
-  for (int64_t t = threadIdx.x; t < n; t += GB) sq += w[t] * w[t];
+  for (int t = threadIdx.x; t < nn; t += GB) sq += wl[t] * wl[t];
   sq = wave_reduce(sq);
   if (lane == 0) red[wave] = sq;
   __syncthreads();
   double tot = 0.0;
   for (int wv = 0; wv < GB / 64; ++wv) tot += red[wv];
-  double hn = sqrt(tot);
-  bool breakdown = !(hn > 0.0);
-  if (!breakdown) {
-    double inv = 1.0 / hn;
-    for (int64_t t = threadIdx.x; t < n; t += GB) w[t] = w[t] * inv;
+  const double hn = sqrt(tot);
+  const bool breakdown = !(hn > 0.0);
+  const double inv = breakdown ? 1.0 : 1.0 / hn;
+  for (int t = threadIdx.x; t < nn; t += GB) w[t] = breakdown ? wl[t] : wl[t] * inv;
+  if (threadIdx.x == 0) {
+    hs[j + 1] = hn;
+    givens_column(j, hs, lcs, lsn, cs, sn, gv, scal, ctl, breakdown);
   }
-  // Givens rotations of column j, in LDS (the previous rotations are read in
-  // parallel first; the recurrence itself is sequential)
+  __syncthreads();
+  double* hcol = Hm + (int64_t)j * ldh;
+  for (int i = threadIdx.x; i <= j + 1; i += GB) hcol[i] = hs[i];
+}
+
+// Many work groups (large n): work group b owns w[b*AC .. b*AC + AC), AE
+// elements per thread, and a step is four kernels.  Partial sums go to
+// part[3][B][L] (L = gm_cap + 2); each consumer reduces them over b in a
+// fixed order.  The first kernel copies (j, done) into ctl[4..5] for the
+// last one, whose work group 0 advances ctl[0..3].
+constexpr int AB = 256;          // threads per work group
+constexpr int AE = 2;            // elements per thread
+constexpr int AC = AB * AE;      // elements per work group
+
+__device__ __forceinline__ int64_t arn_elem(int r) {
+  return (int64_t)blockIdx.x * AC + threadIdx.x + (int64_t)AB * r;
+}
+
+// partial dot products of the work group's w (registers) with V[0..j] into
+// out[0..j]
+__device__ void arn_partial_dots(int64_t n, int j, const double* V, const double (&wr)[AE], double* out) {
+  __shared__ double red[AB / 64][16];
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  for (int i0 = 0; i0 <= j; i0 += 16) {
+    double p[2][8];
+#pragma unroll
+    for (int q = 0; q < 16; ++q) p[q >> 3][q & 7] = 0.0;
+#pragma unroll
+    for (int r = 0; r < AE; ++r) {
+      const int64_t t = arn_elem(r);
+      if (t < n) {
+#pragma unroll
+        for (int q = 0; q < 16; ++q)
+          if (i0 + q <= j) p[q >> 3][q & 7] += wr[r] * V[(int64_t)(i0 + q) * n + t];
+      }
+    }
+#pragma unroll
+    for (int hq = 0; hq < 2; ++hq) {
+      const double sq = wave_reduce8(p[hq], lane);
+      if ((lane & 7) == 0) red[wave][8 * hq + wave_reduce8_index(lane)] = sq;
+    }
+    __syncthreads();
+    if (threadIdx.x < 16 && i0 + (int)threadIdx.x <= j)
+      out[i0 + threadIdx.x] = ((red[0][threadIdx.x] + red[1][threadIdx.x]) + red[2][threadIdx.x]) + red[3][threadIdx.x];
+    __syncthreads();
+  }
+}
+
+// h[i] = sum over b of part[b*L + i], i <= j, into LDS.  Thread t takes i =
+// i0 + t mod 32 and every eighth b from t / 32, so the loads of all b are
+// in flight together; the eight group sums are then added in order.
+__device__ void arn_reduce(int j, int B, int L, const double* part, double* h) {
+  __shared__ double tmp[8][32];
+  const int ii = threadIdx.x & 31, g = threadIdx.x >> 5;
+  for (int i0 = 0; i0 <= j; i0 += 32) {
+    const int i = i0 + ii;
+    double s = 0.0;
+    if (i <= j)
+      for (int b = g; b < B; b += 8) s += part[(int64_t)b * L + i];
+    tmp[g][ii] = s;
+    __syncthreads();
+    if (threadIdx.x < 32 && i <= j) {
+      double t = 0.0;
+      for (int q = 0; q < 8; ++q) t += tmp[q][ii];
+      h[i] = t;
+    }
+    __syncthreads();
+  }
+}
+
+__global__ void __launch_bounds__(AB) k_arn_dots(int64_t n, int* ctl, const double* V, double* part, int L) {
+  if (blockIdx.x == 0 && threadIdx.x == 0) {
+    ctl[4] = ctl[0];
+    ctl[5] = ctl[1];
+  }
+  if (ctl[1]) return;
+  const int j = ctl[0];
+  const double* w = V + (int64_t)(j + 1) * n;
+  double wr[AE];
+#pragma unroll
+  for (int r = 0; r < AE; ++r) {
+    const int64_t t = arn_elem(r);
+    wr[r] = t < n ? w[t] : 0.0;
+  }
+  arn_partial_dots(n, j, V, wr, part + (int64_t)blockIdx.x * L);
+}
+
+// PASS 0: w -= V h1, then the partial dots of the new w (second pass);
+// PASS 1: w -= V h2, then the partial sum of w^2
+template <int PASS>
+__global__ void __launch_bounds__(AB) k_arn_update(int64_t n, const int* ctl, double* V, const double* pin,
+                                                  double* pout, int L, int B) {
+  __shared__ double h[KFBI_GMRES_MAX + 1];
+  __shared__ double red[AB / 64];
+  if (ctl[1]) return;
+  const int j = ctl[0];
+  double* w = V + (int64_t)(j + 1) * n;
+  double wr[AE];
+#pragma unroll
+  for (int r = 0; r < AE; ++r) {
+    const int64_t t = arn_elem(r);
+    wr[r] = t < n ? w[t] : 0.0;
+  }
+  arn_reduce(j, B, L, pin, h);
+  for (int i0 = 0; i0 <= j; i0 += 8) {
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      if (i0 + q > j) break;
+      const double hq = h[i0 + q];
+#pragma unroll
+      for (int r = 0; r < AE; ++r) {
+        const int64_t t = arn_elem(r);
+        if (t < n) wr[r] -= hq * V[(int64_t)(i0 + q) * n + t];
+      }
+    }
+  }
+#pragma unroll
+  for (int r = 0; r < AE; ++r) {
+    const int64_t t = arn_elem(r);
+    if (t < n) w[t] = wr[r];
+  }
+  if (PASS == 0) {
+    arn_partial_dots(n, j, V, wr, pout + (int64_t)blockIdx.x * L);
+  } else {
+    double sq = 0.0;
+#pragma unroll
+    for (int r = 0; r < AE; ++r) sq += wr[r] * wr[r];
+    sq = wave_reduce(sq);
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = sq;
+    __syncthreads();
+    if (threadIdx.x == 0) pout[(int64_t)blockIdx.x * L] = ((red[0] + red[1]) + red[2]) + red[3];
+  }
+}
+
+// |w| from the partial sums, w /= |w|; work group 0 forms the Hessenberg
+// column h1 + h2, |w| and applies the Givens rotations
+__global__ void __launch_bounds__(AB) k_arn_finish(int64_t n, int* ctl, int ldh, double* V, double* Hm, double* cs,
+                                                  double* sn, double* gv, double* scal, const double* part, int L,
+                                                  int B, int PB) {
+  __shared__ double hs[KFBI_GMRES_MAX + 2];
+  __shared__ double h2[KFBI_GMRES_MAX + 1];
   __shared__ double lcs[KFBI_GMRES_MAX], lsn[KFBI_GMRES_MAX];
-  for (int i = threadIdx.x; i < j; i += GB) {
+  if (ctl[5]) return;
+  const int j = ctl[4];
+  __shared__ double nrm[1];
+  arn_reduce(0, B, L, part + (int64_t)2 * PB * L, nrm);
+  const double hn = sqrt(nrm[0]);
+  const bool breakdown = !(hn > 0.0);
+  const double inv = breakdown ? 1.0 : 1.0 / hn;
+  double* w = V + (int64_t)(j + 1) * n;
+#pragma unroll
+  for (int r = 0; r < AE; ++r) {
+    const int64_t t = arn_elem(r);
+    if (t < n && !breakdown) w[t] = w[t] * inv;
+  }
+  if (blockIdx.x != 0) return;
+  arn_reduce(j, B, L, part, hs);
+  arn_reduce(j, B, L, part + (int64_t)PB * L, h2);
+  for (int i = threadIdx.x; i <= j; i += AB) hs[i] += h2[i];
+  for (int i = threadIdx.x; i < j; i += AB) {
     lcs[i] = cs[i];
     lsn[i] = sn[i];
   }
-  if (threadIdx.x == 0) hs[j + 1] = hn;
   __syncthreads();
   if (threadIdx.x == 0) {
-    for (int i = 0; i < j; ++i) {
-      double t = lcs[i] * hs[i] + lsn[i] * hs[i + 1];
-      hs[i + 1] = -lsn[i] * hs[i] + lcs[i] * hs[i + 1];
-      hs[i] = t;
-    }
-    double den = hypot(hs[j], hs[j + 1]);
-    double cj = hs[j] / den, sj = hs[j + 1] / den;
-    cs[j] = cj;
-    sn[j] = sj;
-    hs[j] = den;
-    hs[j + 1] = 0.0;
-    double gj = gv[j];
-    gv[j + 1] = -sj * gj;
-    gv[j] = cj * gj;
-    double res = fabs(-sj * gj);
-    scal[0] = res;
-    scal[2] = breakdown ? 1.0 : 0.0;
-    ctl[2] = j + 1;
-    ctl[0] = j + 1;
-    ctl[1] = (res <= scal[3] * scal[1] || breakdown || j + 1 >= ctl[3]) ? 1 : 0;
+    hs[j + 1] = hn;
+    givens_column(j, hs, lcs, lsn, cs, sn, gv, scal, ctl, breakdown);
   }
   __syncthreads();
-  for (int i = threadIdx.x; i <= j + 1; i += GB) hcol[i] = hs[i];
+  double* hcol = Hm + (int64_t)j * ldh;
+  for (int i = threadIdx.x; i <= j + 1; i += AB) hcol[i] = hs[i];
 }
 
 // y = H^{-1} g (upper triangular, k x k), then x = x0 + V^T y.  The
@@ -196,10 +436,20 @@ __global__ void k_combine(int64_t n, int k, const double* V, const double* y, do
 __global__ void __launch_bounds__(GB) k_resid(int64_t n, const double* b, const double* Ax, double* out) {
   __shared__ double sh[GB];
   double sr = 0.0, sb = 0.0;
-  for (int64_t i = threadIdx.x; i < n; i += GB) {
-    double r = b[i] - Ax[i];
-    sr += r * r;
-    sb += b[i] * b[i];
+  for (int64_t i0 = threadIdx.x; i0 < n; i0 += 8 * GB) {
+    double bv[8], av[8];
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const int64_t i = i0 + (int64_t)q * GB;
+      bv[q] = i < n ? b[i] : 0.0;
+      av[q] = i < n ? Ax[i] : 0.0;
+    }
+#pragma unroll
+    for (int q = 0; q < 8; ++q) {
+      const double r = bv[q] - av[q];
+      sr += r * r;
+      sb += bv[q] * bv[q];
+    }
   }
   double a = block_sum(sr, sh);
   double c = block_sum(sb, sh);
@@ -216,10 +466,29 @@ void gm_residual_start(kfbi_plan* pl, const double* b, const double* Ax0, int us
                      pl->gv, pl->scal, pl->ctl, tol, maxit);
 }
 
+// one work group up to 8192 unknowns (the step is latency-bound there);
+// beyond, the basis is read by many compute units
 void gm_arnoldi(kfbi_plan* pl) {
-  hipLaunchKernelGGL(k_arnoldi, dim3(1), dim3(GB), 0, pl->stream, pl->n_dof, pl->ctl, pl->gm_cap + 1, pl->V, pl->Hm,
-                     pl->cs, pl->sn, pl->gv, pl->scal);
+  const int64_t n = pl->n_dof;
+  const int ldh = pl->gm_cap + 1;
+  hipStream_t st = pl->stream;
+  if (n <= ARN1_MAXN) {
+    hipLaunchKernelGGL(k_arnoldi1, dim3(1), dim3(GB), 0, st, n, pl->ctl, ldh, pl->V, pl->Hm, pl->cs, pl->sn,
+                       pl->gv, pl->scal);
+  } else {
+    const int B = (int)((n + AC - 1) / AC), L = pl->gm_cap + 2, PB = pl->gm_pb;
+    double* p1 = pl->gm_part;
+    double* p2 = p1 + (int64_t)PB * L;
+    double* p3 = p2 + (int64_t)PB * L;
+    hipLaunchKernelGGL(k_arn_dots, dim3(B), dim3(AB), 0, st, n, pl->ctl, pl->V, p1, L);
+    hipLaunchKernelGGL(k_arn_update<0>, dim3(B), dim3(AB), 0, st, n, pl->ctl, pl->V, p1, p2, L, B);
+    hipLaunchKernelGGL(k_arn_update<1>, dim3(B), dim3(AB), 0, st, n, pl->ctl, pl->V, p2, p3, L, B);
+    hipLaunchKernelGGL(k_arn_finish, dim3(B), dim3(AB), 0, st, n, pl->ctl, ldh, pl->V, pl->Hm, pl->cs, pl->sn,
+                       pl->gv, pl->scal, pl->gm_part, L, B, PB);
+  }
 }
+
+int gm_part_blocks(int64_t n) { return (int)((n + AC - 1) / AC); }
 
 void gm_update(kfbi_plan* pl, int k, double* x, int use_x0) {
   if (k > 0) hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(256), 0, pl->stream, k, pl->gm_cap + 1, pl->Hm, pl->gv,

@@ -92,6 +92,8 @@ struct kfbi_plan {
   // GMRES
   double *V, *Hm, *gv, *cs, *sn, *work, *work2, *bvec, *scal;
   int gm_cap;
+  double* gm_part;               // Arnoldi partial sums [3][gm_pb][gm_cap + 2]
+  int gm_pb;
   int64_t gm_n;
   // folded operators of the matvec (set-up products of the inverses with the
   // density extension): C at entry e = sum_t FW[e][t] psi[FI[e][t]],
@@ -194,6 +196,7 @@ void dst_solve_corrections(kfbi_plan* pl, const double* psi, double* v);
 // gmres.hip (step S6)
 void gm_residual_start(kfbi_plan* pl, const double* b, const double* Ax0, int use_x0, double tol, int maxit);
 void gm_arnoldi(kfbi_plan* pl);
+int gm_part_blocks(int64_t n);
 void gm_update(kfbi_plan* pl, int k, double* x, int use_x0);
 void gm_true_residual(kfbi_plan* pl, const double* b, const double* Ax, double* out2);
 
