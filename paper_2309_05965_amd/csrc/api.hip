@@ -681,9 +681,13 @@ kfbi_status solve_body(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* op
   double nb = pl->h_dpinned[1];
   double res_prev = pl->h_dpinned[0];
   int k_prev = 0;
-  // Steps 3-4: launch captured iterations in batches; the batch length is
-  // predicted from the observed convergence rate
-  int launched = 0, batch = 4;
+  // Steps 3-4: launch captured iterations in batches.  The first batch is
+  // the previous solve's iteration count on this plan (at least 4; the
+  // iterations after convergence are skipped on the device, so an
+  // over-long batch costs a few microseconds while a short one costs a
+  // host round trip), later batches are predicted from the observed
+  // convergence rate
+  int launched = 0, batch = pl->last_iters > 4 ? (pl->last_iters < 64 ? pl->last_iters : 64) : 4;
   while (!pl->h_ctl[1] && launched < m) {
     int B = batch < m - launched ? batch : m - launched;
     for (int b = 0; b + 4 <= B; b += 4) HIPCHK(hipGraphLaunch(pl->graph4_exec, st));
@@ -704,6 +708,7 @@ kfbi_status solve_body(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* op
     k_prev = k;
   }
   const int k = pl->h_ctl[2];
+  pl->last_iters = k;
   const double est = nb > 0.0 ? pl->h_dpinned[0] / nb : 0.0;
   const bool conv = pl->h_ctl[1] && (nb == 0.0 || pl->h_dpinned[0] <= tol * nb || pl->h_dpinned[2] != 0.0);
   gm_update(pl, k, psi, opts->use_x0);

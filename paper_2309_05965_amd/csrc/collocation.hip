@@ -33,12 +33,6 @@ struct CollocTables {
   int offP[KFBI_MAXP][3];     // PDE lattice
 };
 
-__device__ __forceinline__ double ipow(double x, int e) {
-  double r = 1.0;
-  for (int i = 0; i < e; ++i) r *= x;
-  return r;
-}
-
 struct FactorArgs {
   GridDesc g;
   CollocTables T;
@@ -52,53 +46,102 @@ struct FactorArgs {
   int* flags;
 };
 
+// dimension and degree of a coefficient count (6, 10, 15, 35)
+constexpr int dim_of(int nc) { return nc == 10 || nc == 35 ? 3 : 2; }
+constexpr int deg_of(int nc) { return nc == 15 || nc == 35 ? 4 : 2; }
+
+// monomial exponents in graded order, the same order as kfbi_exponents
+template <int D, int P>
+struct Exponents {
+  int e[KFBI_MAXC][3];
+  constexpr Exponents() : e{} {
+    int n = 0;
+    for (int m = 0; m <= P; ++m) {
+      if (D == 2) {
+        for (int j = 0; j <= m; ++j) {
+          e[n][0] = m - j;
+          e[n][1] = j;
+          e[n][2] = 0;
+          ++n;
+        }
+      } else {
+        for (int x = m; x >= 0; --x)
+          for (int y = m - x; y >= 0; --y) {
+            e[n][0] = x;
+            e[n][1] = y;
+            e[n][2] = m - x - y;
+            ++n;
+          }
+      }
+    }
+  }
+};
+
 // row j of M (lane j) in the order [PDE | Dirichlet | Neumann], written to
-// row[0..n) (LDS)
+// row[0..NC) (LDS).  Powers xi^e are formed once per row by repeated
+// multiplication (the same products, in the same order, as a per-entry
+// power loop), and the exponents are compile-time constants, so every
+// column is straight-line code.
+template <int NC>
 __device__ __forceinline__ void assemble_row(const FactorArgs& a, int64_t c, int j, double* row) {
-  const int d = a.T.d;
+  constexpr int D = dim_of(NC), P = deg_of(NC);
+  constexpr Exponents<D, P> EX{};
   const GridDesc& g = a.g;
   const double h = g.h;
   const int s = a.d2s[c];
-  const double* P = a.spos + (int64_t)s * d;
+  const double* Pc = a.spos + (int64_t)s * D;
   double xi[3] = {0.0, 0.0, 0.0}, nv[3] = {0.0, 0.0, 0.0};
   int kind;   // 0 PDE, 1 Dirichlet, 2 Neumann
   if (j < a.T.nP) {
     kind = 0;
-    for (int ax = 0; ax < d; ++ax) xi[ax] = (double)a.T.offP[j][ax];
+    for (int ax = 0; ax < D; ++ax) xi[ax] = (double)a.T.offP[j][ax];
   } else if (j < a.T.nP + a.T.nD) {
     kind = 1;
     int q = a.stD[c * a.T.nD + (j - a.T.nP)];
-    for (int ax = 0; ax < d; ++ax) xi[ax] = (a.spos[(int64_t)q * d + ax] - P[ax]) / h;
+    for (int ax = 0; ax < D; ++ax) xi[ax] = (a.spos[(int64_t)q * D + ax] - Pc[ax]) / h;
   } else {
     kind = 2;
     int q = a.stN[c * a.T.nN + (j - a.T.nP - a.T.nD)];
-    for (int ax = 0; ax < d; ++ax) {
-      xi[ax] = (a.spos[(int64_t)q * d + ax] - P[ax]) / h;
-      nv[ax] = a.snrm[(int64_t)q * d + ax];
+    for (int ax = 0; ax < D; ++ax) {
+      xi[ax] = (a.spos[(int64_t)q * D + ax] - Pc[ax]) / h;
+      nv[ax] = a.snrm[(int64_t)q * D + ax];
     }
   }
+  double pw[D][P + 1];
+#pragma unroll
+  for (int ax = 0; ax < D; ++ax) {
+    pw[ax][0] = 1.0;
+#pragma unroll
+    for (int e = 1; e <= P; ++e) pw[ax][e] = pw[ax][e - 1] * xi[ax];
+  }
   const double kh2 = g.kappa * h * h;
-  for (int al = 0; al < a.T.n; ++al) {
-    const int* e = a.T.E[al];
+#pragma unroll
+  for (int al = 0; al < NC; ++al) {
     double v;
     if (kind == 1) {
       v = 1.0;
-      for (int ax = 0; ax < d; ++ax) v *= ipow(xi[ax], e[ax]);
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) v *= pw[ax][EX.e[al][ax]];
     } else if (kind == 2) {
       v = 0.0;
-      for (int ax = 0; ax < d; ++ax) {
-        if (e[ax] == 0) continue;
-        double t = (double)e[ax];
-        for (int b = 0; b < d; ++b) t *= ipow(xi[b], b == ax ? e[b] - 1 : e[b]);
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) {
+        if (EX.e[al][ax] == 0) continue;
+        double t = (double)EX.e[al][ax];
+#pragma unroll
+        for (int b = 0; b < D; ++b) t *= pw[b][b == ax ? EX.e[al][b] - 1 : EX.e[al][b]];
         v += nv[ax] * t;
       }
     } else {
       double lap = 0.0, val = 1.0;
-      for (int ax = 0; ax < d; ++ax) val *= ipow(xi[ax], e[ax]);
-      for (int ax = 0; ax < d; ++ax) {
-        if (e[ax] < 2) continue;
-        double t = (double)(e[ax] * (e[ax] - 1));
-        for (int b = 0; b < d; ++b) t *= ipow(xi[b], b == ax ? e[b] - 2 : e[b]);
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) val *= pw[ax][EX.e[al][ax]];
+#pragma unroll
+      for (int ax = 0; ax < D; ++ax) {
+        if (EX.e[al][ax] < 2) continue;
+        double t = (double)(EX.e[al][ax] * (EX.e[al][ax] - 1));
+#pragma unroll
+        for (int b = 0; b < D; ++b) t *= pw[b][b == ax ? EX.e[al][b] - 2 : EX.e[al][b]];
         lap += t;
       }
       v = lap - kh2 * val;
@@ -123,9 +166,10 @@ __device__ __forceinline__ double wave_max(double v) {
 // One wavefront per centre, lane j holds row j of M in registers and the
 // inverse is formed in place (Gauss-Jordan).  Partial pivoting: at step k
 // the pivot is the unused row with the largest |entry| in column k (lowest
-// lane on ties); rows are not swapped.  The pivot lane scales its row
-// (column k becomes 1/pivot) and the other lanes read it lane to lane and
-// eliminate.  With p_k the pivot lane of step k, lane p_a ends up holding
+// lane on ties: a max reduction, then the first lane of the ballot of lanes
+// holding it); rows are not swapped.  The pivot lane scales its row
+// (column k becomes 1/pivot) and the other lanes read it lane to lane
+// (readlane, no LDS round trip or barrier) and eliminate.  With p_k the pivot lane of step k, lane p_a ends up holding
 // row a of the inverse with its column j at position p_j.
 template <int NC>
 __global__ void __launch_bounds__(64) k_factor(FactorArgs a) {
@@ -134,8 +178,7 @@ __global__ void __launch_bounds__(64) k_factor(FactorArgs a) {
   const bool live = lane < NC;
   __shared__ double Ms[NC][NC + 1];
   __shared__ int pvt[NC];
-  __shared__ double prow[NC];
-  if (live) assemble_row(a, c, lane, Ms[lane]);
+  if (live) assemble_row<NC>(a, c, lane, Ms[lane]);
   __syncthreads();
   // M^T (for the refinement of U) and the 1-norm of M (max column sum),
   // both read from LDS
@@ -151,28 +194,25 @@ __global__ void __launch_bounds__(64) k_factor(FactorArgs a) {
   bool used = !live;
   int myk = -1;
   bool singular = false;
-#pragma unroll 1
+  // the lanes that hold rows: the pivot search reduces over W lanes
+  constexpr int W = NC <= 16 ? 16 : (NC <= 32 ? 32 : 64);
+  constexpr int KU = NC <= 16 ? NC : 1;   // unrolled steps: small systems only (registers)
+#pragma unroll KU
   for (int k = 0; k < NC; ++k) {
-    // column k of this lane's row (k is not a compile-time index)
+    // column k of this lane's row
     double rk = 0.0;
 #pragma unroll
     for (int m = 0; m < NC; ++m) rk = m == k ? row[m] : rk;
-    // pivot search: (|value|, lane), larger value wins, lower lane on ties
-    double best = used ? -1.0 : fabs(rk);
-    int bl = lane;
-    for (int off = 32; off > 0; off >>= 1) {
-      const double ob = __shfl_xor(best, off, 64);
-      const int ol = __shfl_xor(bl, off, 64);
-      if (ob > best || (ob == best && ol < bl)) {
-        best = ob;
-        bl = ol;
-      }
-    }
-    if (!(best > 0.0) || !isfinite(best)) {
+    // pivot: the largest |value| among unused rows, the lowest lane on ties
+    const double best = used ? -1.0 : fabs(rk);
+    double mx = best;
+    for (int off = W / 2; off > 0; off >>= 1) mx = fmax(mx, __shfl_xor(mx, off, 64));
+    mx = lane_value(mx, 0);
+    if (!(mx > 0.0) || !isfinite(mx)) {
       singular = true;
       break;
     }
-    const int pl = __builtin_amdgcn_readfirstlane(bl);
+    const int pl = __ffsll((unsigned long long)__ballot(best == mx)) - 1;
     if (lane == 0) pvt[k] = pl;
     if (lane == pl) {
       const double ri = 1.0 / rk;
@@ -181,27 +221,18 @@ __global__ void __launch_bounds__(64) k_factor(FactorArgs a) {
       used = true;
       myk = k;
     }
-    if (lane == pl) {
-#pragma unroll
-      for (int m = 0; m < NC; ++m) prow[m] = row[m];
-    }
-    __syncthreads();
+    // the scaled pivot row, lane to lane, eight entries at a time
     const double f = (lane != pl && live) ? rk : 0.0;
 #pragma unroll
     for (int m0 = 0; m0 < NC; m0 += 8) {
+      double pr[8];
 #pragma unroll
-      for (int m = m0; m < NC && m < m0 + 8; ++m) {
-        const double pr = prow[m];
-        if (lane != pl && live) {
-          if (m == k)
-            row[m] = -(f * pr);
-          else
-            row[m] -= f * pr;
-        }
+      for (int m = m0; m < NC && m < m0 + 8; ++m) pr[m - m0] = lane_value(row[m], pl);
+      if (lane != pl && live) {
+#pragma unroll
+        for (int m = m0; m < NC && m < m0 + 8; ++m) row[m] = m == k ? -(f * pr[m - m0]) : row[m] - f * pr[m - m0];
       }
-      __builtin_amdgcn_sched_barrier(0);
     }
-    __syncthreads();
   }
   if (singular) {
     if (lane == 0) {

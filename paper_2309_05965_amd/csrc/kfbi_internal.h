@@ -92,6 +92,7 @@ struct kfbi_plan {
   // GMRES
   double *V, *Hm, *gv, *cs, *sn, *work, *work2, *bvec, *scal;
   int gm_cap;
+  int last_iters;                // GMRES iterations of the plan's previous solve
   double* gm_part;               // Arnoldi partial sums [3][gm_pb][gm_cap + 2]
   int gm_pb;
   int64_t gm_n;
