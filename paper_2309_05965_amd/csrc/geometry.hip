@@ -25,7 +25,7 @@
 
 namespace {
 
-constexpr int CMP_IT = 16;
+constexpr int CMP_IT = 4;     // items per thread of a compaction block (more blocks, shorter serial chains)
 constexpr int CMP_CH = KFBI_BLOCK * CMP_IT;
 constexpr int BISECT_STEPS = 52;
 constexpr int MARGIN = 3;

@@ -493,14 +493,20 @@ __global__ void k_fold_dof(FoldArgs a) {
 
 // the centre's own polynomial in its interpolation: TI[c] = sum over the
 // block nodes outside the centre's region of IW * monomials(xi_b), and its
-// fold HW with the Neumann columns of the inverse and the extension
+// fold HW with the Neumann columns of the inverse and the extension.  A
+// group of FOLD_G lanes per centre: the lanes split the block nodes, the
+// partial sums of T are combined by a fixed butterfly, and the lanes then
+// split the nN * P folded weights.
+constexpr int FOLD_G = 32;
 template <int D, int P>
-__global__ void k_fold_own(FoldArgs a) {
+__global__ void __launch_bounds__(KFBI_BLOCK) k_fold_own(FoldArgs a) {
   constexpr int NC = ncoef_t<D, P>();
   constexpr int Q1 = P + 1;
   constexpr int NBK = D == 3 ? Q1 * Q1 * Q1 : Q1 * Q1;
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= a.n_dof) return;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = t / FOLD_G;
+  const int lane = (int)(t % FOLD_G);
+  if (c >= a.n_dof) return;   // whole groups leave together
   const GridDesc& g = a.g;
   const int s = a.d2s[c];
   const int k = a.meta[(int64_t)s * 5 + 3];
@@ -511,7 +517,7 @@ __global__ void k_fold_own(FoldArgs a) {
   double T[NC];
 #pragma unroll
   for (int al = 0; al < NC; ++al) T[al] = 0.0;
-  for (int b = 0; b < NBK; ++b) {
+  for (int b = lane; b < NBK; b += FOLD_G) {
     const int bb[3] = {b % Q1, (b / Q1) % Q1, b / (Q1 * Q1)};
     const int64_t Q = ravel(g, st[0] + bb[0], st[1] + bb[1], st[2] + bb[2]);
     if (a.region[Q] == k) continue;
@@ -525,20 +531,25 @@ __global__ void k_fold_own(FoldArgs a) {
     for (int al = 0; al < NC; ++al) T[al] += w * phi[al];
   }
 #pragma unroll
-  for (int al = 0; al < NC; ++al) a.TI[c * NC + al] = T[al];
+  for (int off = FOLD_G / 2; off > 0; off >>= 1) {
+#pragma unroll
+    for (int al = 0; al < NC; ++al) T[al] += __shfl_xor(T[al], off, FOLD_G);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int al = 0; al < NC; ++al) a.TI[c * NC + al] = T[al];
+  }
   const double* Mi = a.MinvT + c * (int64_t)NC * NC;
-  for (int j = 0; j < a.nN; ++j) {
+  for (int q = lane; q < a.nN * P; q += FOLD_G) {
+    const int j = q / P, m = q % P;
     const double* col = Mi + (int64_t)(a.nP + a.nD + j) * NC;
     double sacc = 0.0;
 #pragma unroll
     for (int al = 0; al < NC; ++al) sacc += T[al] * col[al];
     const double rn = g.h * sacc;
     const int sN = a.stN[c * a.nN + j];
-#pragma unroll
-    for (int m = 0; m < P; ++m) {
-      const int idx = a.ext_idx[(int64_t)sN * P + m];
-      a.HW[c * a.nF + (int64_t)j * P + m] = idx >= 0 ? rn * a.ext_w[(int64_t)sN * P + m] : 0.0;
-    }
+    const int idx = a.ext_idx[(int64_t)sN * P + m];
+    a.HW[c * a.nF + (int64_t)j * P + m] = idx >= 0 ? rn * a.ext_w[(int64_t)sN * P + m] : 0.0;
   }
 }
 
@@ -864,7 +875,7 @@ kfbi_status op_fold(kfbi_plan* pl) {
   }
   hipLaunchKernelGGL(k_fold_dof, dim3(nb(pl->n_dof * nbk)), dim3(KFBI_BLOCK), 0, pl->stream, A);
   {
-    dim3 gr(nb(pl->n_dof)), bl(KFBI_BLOCK);
+    dim3 gr(nb(pl->n_dof * FOLD_G)), bl(KFBI_BLOCK);
     if (g.d == 2 && g.p == 2) hipLaunchKernelGGL((k_fold_own<2, 2>), gr, bl, 0, pl->stream, A);
     if (g.d == 2 && g.p == 4) hipLaunchKernelGGL((k_fold_own<2, 4>), gr, bl, 0, pl->stream, A);
     if (g.d == 3 && g.p == 2) hipLaunchKernelGGL((k_fold_own<3, 2>), gr, bl, 0, pl->stream, A);
