@@ -265,7 +265,8 @@ kfbi_status run_setup(kfbi_plan* pl) {
   HIPCHK(hipMemsetAsync(pl->Fm, 0, sizeof(double) * pl->g.n_nodes, pl->stream));
   HIPCHK(hipMemsetAsync(pl->vbuf, 0, sizeof(double) * pl->g.n_nodes, pl->stream));
   if (pl->Fmg) HIPCHK(hipMemsetAsync(pl->Fmg, 0, sizeof(double) * pl->g.n_nodes, pl->stream));
-  HIPCHK(hipStreamSynchronize(pl->stream));
+  // everything after the set-up is ordered behind it on the plan's stream
+  HIPCHK(hipGetLastError());
   pl->ready = true;
   return KFBI_OK;
 }

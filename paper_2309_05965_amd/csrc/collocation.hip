@@ -321,10 +321,10 @@ kfbi_status colloc_factor(kfbi_plan* pl) {
       return KFBI_E_INVALID;
   }
   HIPCHK(hipGetLastError());
-  HIPCHK(hipMemcpyAsync(pl->h_pinned + 1, pl->d_flags, sizeof(int), hipMemcpyDeviceToHost, pl->stream));
-  HIPCHK(hipStreamSynchronize(pl->stream));
-  // largest condition number (host reduction of a small array)
+  // flags and condition numbers in one host wait; the largest condition
+  // number is a host reduction of a small array
   std::vector<double> cond((size_t)pl->n_dof);
+  HIPCHK(hipMemcpyAsync(pl->h_pinned + 1, pl->d_flags, sizeof(int), hipMemcpyDeviceToHost, pl->stream));
   HIPCHK(hipMemcpyAsync(cond.data(), pl->cond, sizeof(double) * pl->n_dof, hipMemcpyDeviceToHost, pl->stream));
   HIPCHK(hipStreamSynchronize(pl->stream));
   double cm = 0.0;

@@ -1266,15 +1266,16 @@ kfbi_status geo_setup(kfbi_plan* pl) {
   // regions
   hipLaunchKernelGGL(k_regions, dim3(nblk(g.n_nodes)), dim3(KFBI_BLOCK), 0, st,
                      RegionArgs{g, L, pl->region, pl->d_flags});
+  // the region flags travel with the first compaction count (one host
+  // wait); the candidate count reads the regions only
   HIPCHK(hipMemcpyAsync(pl->h_pinned + 1, pl->d_flags, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  if (pl->h_pinned[1]) return kfbi_flags_status(pl->h_pinned[1]);
 
   // candidates: (segment, interface) items with a sign change
   int64_t n_items = pl->n_seg * g.K;
   CandPred cp{g, pl->region};
   int64_t nc;
   KCHK(compact_count_flags(pl, n_items, cp, &nc));
+  if (pl->h_pinned[1]) return kfbi_flags_status(pl->h_pinned[1]);
   if (nc == 0) {
     kfbi_set_error("no grid segment crosses an interface");
     return KFBI_E_INVALID;
