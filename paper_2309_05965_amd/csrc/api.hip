@@ -676,29 +676,34 @@ kfbi_status solve_body(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* op
   if (opts->use_x0) matvec_impl(pl, psi, pl->work);
   gm_residual_start(pl, pl->bvec, pl->work, opts->use_x0, tol, m);
   KCHK(ensure_graph(pl));
-  HIPCHK(hipMemcpyAsync(pl->h_ctl, pl->ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipMemcpyAsync(pl->h_dpinned, pl->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  double nb = pl->h_dpinned[1];
-  double res_prev = pl->h_dpinned[0];
+  // Steps 3-4: launch captured iterations in batches, reading the control
+  // word back between batches.  The first batch goes out without a host
+  // wait (after convergence or a zero right-hand side every kernel of a
+  // captured iteration returns at once); its length is the previous
+  // solve's iteration count on this plan (at least 4: an over-long batch
+  // costs a few microseconds, a short one a host round trip).  Later
+  // batches are predicted from the observed convergence rate.
+  int launched = 0;
+  int batch = pl->last_iters > 4 ? (pl->last_iters < 64 ? pl->last_iters : 64) : 4;
+  double nb = 0.0, res_prev = 0.0;
   int k_prev = 0;
-  // Steps 3-4: launch captured iterations in batches.  The first batch is
-  // the previous solve's iteration count on this plan (at least 4; the
-  // iterations after convergence are skipped on the device, so an
-  // over-long batch costs a few microseconds while a short one costs a
-  // host round trip), later batches are predicted from the observed
-  // convergence rate
-  int launched = 0, batch = pl->last_iters > 4 ? (pl->last_iters < 64 ? pl->last_iters : 64) : 4;
-  while (!pl->h_ctl[1] && launched < m) {
-    int B = batch < m - launched ? batch : m - launched;
+  bool first = true;
+  for (;;) {
+    const int B = batch < m - launched ? batch : m - launched;
     for (int b = 0; b + 4 <= B; b += 4) HIPCHK(hipGraphLaunch(pl->graph4_exec, st));
     for (int b = 0; b < B % 4; ++b) HIPCHK(hipGraphLaunch(pl->graph_exec, st));
     launched += B;
     HIPCHK(hipMemcpyAsync(pl->h_ctl, pl->ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(pl->h_dpinned, pl->scal, 4 * sizeof(double), hipMemcpyDeviceToHost, st));
+    HIPCHK(hipMemcpyAsync(pl->h_dpinned, pl->scal, 7 * sizeof(double), hipMemcpyDeviceToHost, st));
     HIPCHK(hipStreamSynchronize(st));
-    int k = pl->h_ctl[2];
-    double res = pl->h_dpinned[0];
+    if (first) {
+      nb = pl->h_dpinned[1];
+      res_prev = pl->h_dpinned[6];
+      first = false;
+    }
+    if (pl->h_ctl[1] || launched >= m) break;
+    const int k = pl->h_ctl[2];
+    const double res = pl->h_dpinned[0];
     batch = 4;
     if (k > k_prev && res > 0.0 && res < res_prev && res_prev > 0.0) {
       double rate = pow(res / res_prev, 1.0 / (double)(k - k_prev));

@@ -28,7 +28,8 @@ __device__ double block_sum(double v, double* sh) {
   return t;
 }
 
-// r0 = b - A x0 (or b); beta = |r0|; V0 = r0 / beta; g0 = beta; scal[1] = |b|.
+// r0 = b - A x0 (or b); beta = |r0|; V0 = r0 / beta; g0 = beta; scal[1] = |b|,
+// scal[6] = beta (kept: scal[0] becomes the running residual estimate).
 // Initialises the control word ctl = [j = 0, done, k = 0, max_iter] and the
 // stopping threshold scal[3] = tol.
 __global__ void __launch_bounds__(GB) k_start(int64_t n, const double* b, const double* Ax0, double* V,
@@ -61,6 +62,7 @@ __global__ void __launch_bounds__(GB) k_start(int64_t n, const double* b, const 
   if (threadIdx.x == 0) {
     gv[0] = beta;
     scal[0] = beta;
+    scal[6] = beta;
     scal[1] = nb;
     scal[2] = 0.0;
     scal[3] = tol;
