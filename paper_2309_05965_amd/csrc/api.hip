@@ -158,6 +158,7 @@ void free_plan(kfbi_plan* pl) {
   dfree(pl->TI);
   dfree(pl->IE2);
   dfree(pl->PA);
+  dfree(pl->Firr);
   dfree(pl->PE1);
   dfree(pl->PE2);
   dfree(pl->EI);

@@ -42,6 +42,7 @@ struct DstArgs {
   int src_corr;
   const int *row_start, *row_end, *irr, *PE1, *PE2;
   const double *PA, *Cv;
+  const double* Firr;  // F at the irregular nodes, precomputed (long pair tables), or null
   int maxpairs;
   GridDesc g;
   int ax;          // transform axis
@@ -220,7 +221,8 @@ __device__ void corrected_rhs(const DstArgs& a, double2* A, int u0, int w) {
     for (int t = r0 + lane; t < r1; t += 64) {
       double F = 0.0;
       const int64_t base = (int64_t)t * a.maxpairs;
-      for (int m0 = 0; m0 < a.maxpairs; m0 += 4) {
+      if (a.Firr) F = a.Firr[t];
+      for (int m0 = 0; !a.Firr && m0 < a.maxpairs; m0 += 4) {
         double cf[4], c1[4], c2[4];
         int e1[4], e2[4];
 #pragma unroll
@@ -406,6 +408,7 @@ void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out,
   a.PE2 = pl->PE2;
   a.PA = pl->PA;
   a.Cv = pl->Cv;
+  a.Firr = kfbi_irr_rhs_used(pl) ? pl->Firr : nullptr;
   a.maxpairs = pl->maxpairs;
   a.g = pl->g;
   a.ax = ax;

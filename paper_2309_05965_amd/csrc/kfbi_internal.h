@@ -107,6 +107,7 @@ struct kfbi_plan {
   double* TI;                    // [n_dof][nC] sum over the block nodes outside the
                                  // centre's region of IW * monomials (own polynomial)
   double* Cv;                    // [n_corr] correction values of the current matvec
+  double* Firr;                  // [n_irr] corrected right-hand side at the irregular nodes (many pairs)
   int* IB;                       // [n_dof] first node of the interpolation block
   int* IE2;                      // [n_dof][(q+1)^d] entry of C^(reg q) at block nodes
                                  // inside another interface, -1 elsewhere
@@ -205,6 +206,10 @@ void gm_true_residual(kfbi_plan* pl, const double* b, const double* Ax, double* 
 __host__ __device__ inline int kfbi_ncoef(int d, int p) {
   return d == 2 ? (p + 1) * (p + 2) / 2 : (p + 1) * (p + 2) * (p + 3) / 6;
 }
+
+// the FFT matvec precomputes F at the irregular nodes (one 32-lane group
+// per node) when the pair tables are long (3D, 4th order: up to 26 pairs)
+inline bool kfbi_irr_rhs_used(const kfbi_plan* pl) { return pl->maxpairs > 8 && pl->maxpairs <= 32; }
 
 // The work groups of a launch are dealt to the chip's 8 XCDs in turn (group
 // b runs on XCD b mod 8) and every XCD has an L2 of its own.  This maps b to

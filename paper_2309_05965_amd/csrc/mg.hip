@@ -68,6 +68,22 @@ __device__ __forceinline__ int64_t node_of(int d, int n1, int64_t t64, int N) {
   return (int64_t)(i + (unsigned)n1 * (j + (unsigned)n1 * (k + 1)));
 }
 
+// coordinates (i, j, k) of interior node t (32-bit arithmetic, as node_of)
+__device__ __forceinline__ void node_ijk(int d, int64_t t64, int N, int& i, int& j, int& k) {
+  const unsigned m = (unsigned)(N - 1);
+  const unsigned t = (unsigned)t64;
+  const unsigned r = t / m;
+  i = (int)(t - r * m + 1);
+  if (d == 2) {
+    j = (int)(r + 1);
+    k = 0;
+    return;
+  }
+  const unsigned q = r / m;
+  j = (int)(r - q * m + 1);
+  k = (int)(q + 1);
+}
+
 template <typename T, typename S>
 __device__ __forceinline__ S apply_A(const S* c, int d, int n1, const T* u, int64_t idx) {
   S s = 0;
@@ -213,20 +229,38 @@ __global__ void __launch_bounds__(256) k_sweep(Ctl ctl, SweepArgs<TS, TO> a) {
         if (i < TT::PL) buf[i] = r[q];
       }
     };
-    TS rg[NL];
-    fetch(z0, rg);
-    store(rg, pl[z0 % 3]);
-    fetch(z0 + 1, rg);
-    store(rg, pl[(z0 + 1) % 3]);
-    fetch(z0 + 2, rg);
+    // own output node of plane gz (right-hand side value)
     const int ix = x0 + lx, iy = y0 + ly;
     const bool own = ix < m && (D == 2 || iy < m);
+    constexpr bool NEEDF = MODE != SW_SMOOTH2;
+    auto fetch_f = [&](int gz) -> TS {
+      if (!NEEDF || !own) return (TS)0;
+      return a.f[D == 3 ? (ix + 1) + n1 * ((iy + 1) + n1 * gz) : (ix + 1) + n1 * gz];
+    };
+    // two planes in flight: while plane iz+1 is computed, the stencil input
+    // of planes iz+3 and iz+4 and the right-hand side of planes iz+2 and
+    // iz+3 are being loaded
+    TS rA[NL], rB[NL] = {};
+    fetch(z0, rA);
+    store(rA, pl[z0 % 3]);
+    fetch(z0 + 1, rA);
+    store(rA, pl[(z0 + 1) % 3]);
+    fetch(z0 + 2, rA);
+    TS fA = fetch_f(z0 + 1), fB = (TS)0;
+    if (z0 + 1 < z1) {
+      fetch(z0 + 3, rB);
+      fB = fetch_f(z0 + 2);
+    }
     const int cc = D == 3 ? (ly + 1) * TT::PX + (lx + 1) : lx + 1;
     for (int iz = z0; iz < z1; ++iz) {
-      store(rg, pl[(iz + 2) % 3]);
+      store(rA, pl[(iz + 2) % 3]);
       __syncthreads();
-      // the next plane's loads are in flight while this plane is computed
-      if (iz + 1 < z1) fetch(iz + 3, rg);
+      TS rC[NL] = {};
+      TS fC = (TS)0;
+      if (iz + 2 < z1) {
+        fetch(iz + 4, rC);
+        fC = fetch_f(iz + 3);
+      }
       if (own) {
         const TS* P[3] = {pl[iz % 3], pl[(iz + 1) % 3], pl[(iz + 2) % 3]};
         TS s = 0;
@@ -253,14 +287,14 @@ __global__ void __launch_bounds__(256) k_sweep(Ctl ctl, SweepArgs<TS, TO> a) {
         const int idx = D == 3 ? (ix + 1) + n1 * ((iy + 1) + n1 * gz) : (ix + 1) + n1 * gz;
         const TS ctr = P[1][cc];
         if (MODE == SW_SMOOTH) {
-          a.out[idx] = (TO)(ctr + a.coef * (a.f[idx] - s));
+          a.out[idx] = (TO)(ctr + a.coef * (fA - s));
         } else if (MODE == SW_SMOOTH2) {
           const TS u1 = a.coef * ctr;
           a.out[idx] = (TO)(u1 + a.coef * (ctr - a.coef * s));
         } else if (MODE == SW_RESID) {
-          a.out[idx] = (TO)(a.f[idx] - s);
+          a.out[idx] = (TO)(fA - s);
         } else {
-          const double Fv = (double)a.f[idx];
+          const double Fv = (double)fA;
           const double r = Fv - (double)s;
           a.out[idx] = (TO)r;
           acc_r += r * r;
@@ -268,6 +302,152 @@ __global__ void __launch_bounds__(256) k_sweep(Ctl ctl, SweepArgs<TS, TO> a) {
         }
       }
       __syncthreads();
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        rA[q] = rB[q];
+        rB[q] = rC[q];
+      }
+      fA = fB;
+      fB = fC;
+    }
+  }
+  if (MODE == SW_OUTER) {
+    red[0][threadIdx.x] = acc_r;
+    red[1][threadIdx.x] = acc_f;
+    __syncthreads();
+    for (int o = 128; o > 0; o >>= 1) {
+      if (threadIdx.x < (unsigned)o) {
+        red[0][threadIdx.x] += red[0][threadIdx.x + o];
+        red[1][threadIdx.x] += red[1][threadIdx.x + o];
+      }
+      __syncthreads();
+    }
+    if (threadIdx.x == 0) {
+      const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
+      a.part[b] = red[0][0];
+      a.part[MG_PART + b] = red[1][0];
+    }
+  }
+}
+
+// 3D sweeps, 2.5D blocking.  A workgroup owns a tile of 32 NX (x) by 8 (y)
+// nodes of the transverse plane and a chunk of KZ planes; each thread owns
+// NX consecutive x nodes of one row.  Input planes stream through two LDS
+// buffers (one barrier per plane, the next plane's loads in flight during
+// the current plane's arithmetic).  Each input plane p is read from LDS
+// once: the thread's 3 x (NX+2) window gives the three in-plane sums
+//   Q_o2(p) = sum over (o0, o1) of c[o0 + 3 o1 + 9 o2] u(x+o0-1, y+o1-1, p),
+// and out(z) = (Q_0(z-1) + Q_1(z)) + Q_2(z+1) is complete when plane z+1
+// has been read.  Same modes as k_sweep.
+constexpr int S3_TY = 8;
+template <int NX>
+struct Tile3 {
+  static constexpr int TX = 32 * NX;
+  static constexpr int PX = TX + 2, PY = S3_TY + 2;
+  static constexpr int PXS = (PX + 3) / 4 * 4;        // LDS row stride (16-byte aligned rows)
+  static constexpr int PL = PX * PY;                  // loaded elements per plane
+  static constexpr int NL = (PL + 255) / 256;
+};
+
+template <typename TS, typename TO, int MODE, int NX>
+__global__ void __launch_bounds__(256) k_sweep3(Ctl ctl, SweepArgs<TS, TO> a) {
+  using TT = Tile3<NX>;
+  __shared__ TS pl[2][TT::PY * TT::PXS];
+  __shared__ double red[MODE == SW_OUTER ? 2 : 1][MODE == SW_OUTER ? 256 : 1];
+  double acc_r = 0.0, acc_f = 0.0;
+  if (!skip(ctl)) {
+    const int m = a.N - 1, n1 = a.n1;
+    const int tx = threadIdx.x & 31, ty = threadIdx.x >> 5;
+    const int nbx = gridDim.x, nby = gridDim.y;
+    const int lb = kfbi_xcd_block(blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z), nbx * nby * gridDim.z);
+    const int bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
+    const int x0 = bx * TT::TX, y0 = by * S3_TY, z0 = bz * a.KZ;
+    const int z1 = z0 + a.KZ < m ? z0 + a.KZ : m;
+    // output nodes (x0 + NX tx + j + 1, y0 + ty + 1, z), z0 < z <= z1
+    const int oy = y0 + ty + 1;
+    const bool rowok = oy <= m;
+    auto fetch = [&](int gz, TS* r) {
+#pragma unroll
+      for (int q = 0; q < TT::NL; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        const int px = i % TT::PX, py = i / TT::PX;
+        const int gx = x0 + px, gy = y0 + py;
+        r[q] = (i < TT::PL && gx <= a.N && gy <= a.N) ? a.s[gx + (int64_t)n1 * (gy + (int64_t)n1 * gz)] : (TS)0;
+      }
+    };
+    auto store = [&](const TS* r, TS* buf) {
+#pragma unroll
+      for (int q = 0; q < TT::NL; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        if (i < TT::PL) buf[(i / TT::PX) * TT::PXS + i % TT::PX] = r[q];
+      }
+    };
+    constexpr bool NEEDF = MODE != SW_SMOOTH2;
+    auto fetch_f = [&](int gz, TS* fv) {
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        const int ox = x0 + NX * tx + j + 1;
+        fv[j] = (NEEDF && rowok && ox <= m) ? a.f[ox + (int64_t)n1 * (oy + (int64_t)n1 * gz)] : (TS)0;
+      }
+    };
+    TS cur[TT::NL], nxt[TT::NL];
+    TS acc0[NX], acc1[NX], ctr0[NX], ctr1[NX], f0[NX], f1[NX];
+#pragma unroll
+    for (int j = 0; j < NX; ++j) acc0[j] = acc1[j] = ctr0[j] = ctr1[j] = f0[j] = f1[j] = (TS)0;
+    fetch(z0, cur);
+    for (int p = z0; p <= z1 + 1; ++p) {
+      TS* buf = pl[p & 1];
+      store(cur, buf);
+      __syncthreads();
+      if (p + 1 <= z1 + 1) fetch(p + 1, nxt);
+      // right-hand side of the output emitted at the next plane (z = p)
+      TS fn[NX];
+      if (p >= z0 + 1 && p <= z1) fetch_f(p, fn);
+      // in-plane window of this thread: rows ty..ty+2, columns NX tx .. NX tx + NX + 1
+      TS w[3][NX + 2];
+#pragma unroll
+      for (int r = 0; r < 3; ++r)
+#pragma unroll
+        for (int k = 0; k < NX + 2; ++k) w[r][k] = buf[(ty + r) * TT::PXS + NX * tx + k];
+#pragma unroll
+      for (int j = 0; j < NX; ++j) {
+        TS q0 = 0, q1 = 0, q2 = 0;
+#pragma unroll
+        for (int o1 = 0; o1 < 3; ++o1)
+#pragma unroll
+          for (int o0 = 0; o0 < 3; ++o0) {
+            const TS u = w[o1][j + o0];
+            q0 += a.c[o0 + 3 * o1] * u;
+            q1 += a.c[o0 + 3 * o1 + 9] * u;
+            q2 += a.c[o0 + 3 * o1 + 18] * u;
+          }
+        const int ox = x0 + NX * tx + j + 1;
+        if (p >= z0 + 2 && rowok && ox <= m) {
+          // out(p - 1) = (Q_0(p-2) + Q_1(p-1)) + Q_2(p)
+          const TS sv = acc1[j] + q2;
+          const int64_t idx = ox + (int64_t)n1 * (oy + (int64_t)n1 * (p - 1));
+          if (MODE == SW_SMOOTH) {
+            a.out[idx] = (TO)(ctr1[j] + a.coef * (f1[j] - sv));
+          } else if (MODE == SW_SMOOTH2) {
+            const TS u1 = a.coef * ctr1[j];
+            a.out[idx] = (TO)(u1 + a.coef * (ctr1[j] - a.coef * sv));
+          } else if (MODE == SW_RESID) {
+            a.out[idx] = (TO)(f1[j] - sv);
+          } else {
+            const double Fv = (double)f1[j];
+            const double r = Fv - (double)sv;
+            a.out[idx] = (TO)r;
+            acc_r += r * r;
+            acc_f += Fv * Fv;
+          }
+        }
+        acc1[j] = acc0[j] + q1;
+        acc0[j] = q0;
+        ctr1[j] = w[1][j + 1];
+        f1[j] = fn[j];
+      }
+#pragma unroll
+      for (int q = 0; q < TT::NL; ++q) cur[q] = nxt[q];
     }
   }
   if (MODE == SW_OUTER) {
@@ -295,9 +475,9 @@ __global__ void __launch_bounds__(MG_BLOCK) k_restrict(Ctl ctl, Lev<T> Fl, Lev<T
   if (skip(ctl)) return;
   const int64_t m = C.d == 3 ? (int64_t)(C.N - 1) * (C.N - 1) * (C.N - 1) : (int64_t)(C.N - 1) * (C.N - 1);
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t idx = node_of(C.d, C.n1, t, C.N);
     int I0, I1, I2;
-    coords(C.d, C.n1, idx, I0, I1, I2);
+    node_ijk(C.d, t, C.N, I0, I1, I2);
+    const int64_t idx = I0 + (int64_t)C.n1 * (I1 + (int64_t)C.n1 * I2);
     f[C.off + idx] = op_restrict<T>(C.d, Fl.n1, r + Fl.off, I0, I1, I2);
   }
 }
@@ -308,9 +488,9 @@ __global__ void __launch_bounds__(MG_BLOCK) k_prolong(Ctl ctl, Lev<T> Fl, Lev<T>
   if (skip(ctl)) return;
   const int64_t m = Fl.d == 3 ? (int64_t)(Fl.N - 1) * (Fl.N - 1) * (Fl.N - 1) : (int64_t)(Fl.N - 1) * (Fl.N - 1);
   for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t idx = node_of(Fl.d, Fl.n1, t, Fl.N);
     int i0, i1, i2;
-    coords(Fl.d, Fl.n1, idx, i0, i1, i2);
+    node_ijk(Fl.d, t, Fl.N, i0, i1, i2);
+    const int64_t idx = i0 + (int64_t)Fl.n1 * (i1 + (int64_t)Fl.n1 * i2);
     u[Fl.off + idx] += op_prolong<T>(Fl.d, C.n1, e + C.off, i0, i1, i2);
   }
 }
@@ -483,12 +663,12 @@ __global__ void __launch_bounds__(MG_BLOCK) k_check(Ctl ctl, const double* part,
 template <typename T>
 __global__ void __launch_bounds__(MG_BLOCK) k_update(Ctl ctl, int d, int N, int n1, const T* e, double* v) {
   if (skip(ctl)) return;
-  const int64_t m = d == 3 ? (int64_t)(N - 1) * (N - 1) * (N - 1) : (int64_t)(N - 1) * (N - 1);
+  // every node, boundary included: the correction is zero on the box
+  // boundary (the level arrays never write it), so a plain stream
+  const int64_t m = d == 3 ? (int64_t)n1 * n1 * n1 : (int64_t)n1 * n1;
   if (blockIdx.x == 0 && threadIdx.x == 0) ctl.mctl[1] += 1;   // one more correction applied
-  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x) {
-    const int64_t idx = node_of(d, n1, t, N);
-    v[idx] = v[idx] + (double)e[idx];
-  }
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < m; t += (int64_t)gridDim.x * blockDim.x)
+    v[t] = v[t] + (double)e[t];
 }
 
 // v = 0 on the box boundary (the outer residual reads v's boundary nodes;
@@ -600,6 +780,28 @@ SweepGeom sweep_geom(int N) {
   return g;
 }
 
+// 3D: tiles of 64 x 8 nodes (2 x nodes per thread) x chunks of KZ >= 4
+// planes, about 2048 workgroups (measured at 128^3 and 256^3, FP32 and
+// FP64), never more than the MG_PART partial-sum slots
+constexpr int S3_NX = 2;
+inline SweepGeom sweep3_geom(int N) {
+  const int m = N - 1;
+  const int tx = (m + 32 * S3_NX - 1) / (32 * S3_NX), ty = (m + S3_TY - 1) / S3_TY;
+  const int tiles = tx * ty;
+  int chunks = 2048 / tiles;
+  if (chunks < 1) chunks = 1;
+  int KZ = (m + chunks - 1) / chunks;
+  if (KZ < 4) KZ = 4;
+  if (KZ > m) KZ = m;
+  while ((int64_t)tiles * ((m + KZ - 1) / KZ) > MG_PART) KZ *= 2;
+  if (KZ > m) KZ = m;
+  SweepGeom g;
+  g.KZ = KZ;
+  g.grid = dim3(tx, ty, (m + KZ - 1) / KZ);
+  g.blocks = tiles * ((m + KZ - 1) / KZ);
+  return g;
+}
+
 template <typename TS, typename TO, int MODE>
 void sweep(kfbi_plan* pl, Ctl ctl, int N, const TS* c27, TS coef, const TS* src, const TS* f, TO* out,
            int* nblocks = nullptr) {
@@ -613,9 +815,9 @@ void sweep(kfbi_plan* pl, Ctl ctl, int N, const TS* c27, TS coef, const TS* src,
   a.out = out;
   a.part = pl->mg_part;
   if (pl->g.d == 3) {
-    SweepGeom g = sweep_geom<3>(N);
+    SweepGeom g = sweep3_geom(N);
     a.KZ = g.KZ;
-    hipLaunchKernelGGL((k_sweep<TS, TO, 3, MODE>), g.grid, dim3(256), 0, pl->stream, ctl, a);
+    hipLaunchKernelGGL((k_sweep3<TS, TO, MODE, S3_NX>), g.grid, dim3(256), 0, pl->stream, ctl, a);
     if (nblocks) *nblocks = g.blocks;
   } else {
     SweepGeom g = sweep_geom<2>(N);

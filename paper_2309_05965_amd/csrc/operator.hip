@@ -616,6 +616,34 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_centry(int64_t n_corr, int nF, c
   if (lane == 0) Cv[e] = s;
 }
 
+// F at every irregular node from the correction values of the current
+// density: F = -sum over the node's cut neighbours Q of A_PQ (C^(reg P) -
+// C^(reg Q))(x_Q).  One group of 32 lanes per node, lane m takes pair m
+// (up to 26 in 3D), the group sum is a fixed butterfly; used where the pair
+// table is long (3D, 4th order), so that the first box-solve pass reads one
+// value per irregular node instead of walking the pairs.
+constexpr int IRR_G = 32;
+__global__ void __launch_bounds__(KFBI_BLOCK) k_irr_rhs(int64_t n_irr, int maxpairs, const double* PA, const int* PE1,
+                                                       const int* PE2, const double* Cv, double* Firr,
+                                                       const int* ctl) {
+  if (ctl && ctl[1]) return;
+  const int64_t t = ((int64_t)blockIdx.x * blockDim.x + threadIdx.x) / IRR_G;
+  const int m = (int)(threadIdx.x % IRR_G);
+  if (t >= n_irr) return;   // whole groups leave together
+  double v = 0.0;
+  if (m < maxpairs) {
+    const int64_t o = t * maxpairs + m;
+    const double cf = PA[o];
+    if (cf != 0.0) {
+      const int e1 = PE1[o], e2 = PE2[o];
+      const double c1 = e1 >= 0 ? Cv[e1] : 0.0, c2 = e2 >= 0 ? Cv[e2] : 0.0;
+      v = cf * (c1 - c2);
+    }
+  }
+  for (int off = IRR_G / 2; off > 0; off >>= 1) v += __shfl_xor(v, off, IRR_G);
+  if (m == 0) Firr[t] = -v;
+}
+
 struct InterpArgs {
   const int* ctl;        // GMRES iteration on the device: psi = V[j], output V[j + 1], j = ctl[0]
   double* Vb;
@@ -818,6 +846,7 @@ kfbi_status op_fold(kfbi_plan* pl) {
     KCHK(regrow(&pl->PA, cap * pl->maxpairs));
     KCHK(regrow(&pl->PE1, cap * pl->maxpairs));
     KCHK(regrow(&pl->PE2, cap * pl->maxpairs));
+    KCHK(regrow(&pl->Firr, cap));
     pl->cap_fold_irr = cap;
   }
   int64_t nrows = g.d == 3 ? (int64_t)g.n1 * g.n1 : g.n1;
@@ -903,6 +932,9 @@ void op_matvec(kfbi_plan* pl, const double* psi, double* Apsi) {
     hipLaunchKernelGGL(k_centry<16>, dim3(nb(pl->n_corr * 16)), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_corr,
                        pl->nF, pl->FI, pl->FW, psi, pl->Cv, pl->ctl_active, pl->V, pl->n_dof);
   if (pl->box_solver == KFBI_BOX_FFT) {
+    if (kfbi_irr_rhs_used(pl) && pl->n_irr > 0)
+      hipLaunchKernelGGL(k_irr_rhs, dim3(nb(pl->n_irr * IRR_G)), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_irr,
+                         pl->maxpairs, pl->PA, pl->PE1, pl->PE2, pl->Cv, pl->Firr, pl->ctl_active);
     dst_solve_corrections(pl, psi, pl->vbuf);
   } else {
     mg_matvec_rhs(pl);
