@@ -134,14 +134,11 @@ __device__ __forceinline__ T op_prolong(int d, int n1c, const T* e, int i0, int 
   const int p0 = i0 & 1, p1 = i1 & 1, p2 = d == 3 ? (i2 & 1) : 0;
   const int I0 = i0 >> 1, I1 = i1 >> 1, I2 = d == 3 ? (i2 >> 1) : 0;
   T s = 0;
-  int cnt = 0;
   for (int c2 = 0; c2 <= p2; ++c2)
     for (int c1 = 0; c1 <= p1; ++c1)
-      for (int c0 = 0; c0 <= p0; ++c0) {
-        s += e[(I0 + c0) + (int64_t)n1c * ((I1 + c1) + (int64_t)n1c * (I2 + c2))];
-        ++cnt;
-      }
-  return s / (T)cnt;
+      for (int c0 = 0; c0 <= p0; ++c0) s += e[(I0 + c0) + (int64_t)n1c * ((I1 + c1) + (int64_t)n1c * (I2 + c2))];
+  // the average of 2^(p0+p1+p2) values: the reciprocal is exact
+  return s * ((T)1 / (T)(1 << (p0 + p1 + p2)));
 }
 
 __device__ __forceinline__ void coords(int d, int n1, int64_t idx, int& i0, int& i1, int& i2) {
