@@ -101,10 +101,12 @@ def forms_config2(plan, prob, data, tol, reps):
 
 def forms_config5(tol, reps, n_problems=4):
     """The ellipsoid workload of the learned start (128^3, beta 1/100) on
-    held-out seeds: plain FP64 (FP64 multigrid to 1e-12, zero start),
-    mixed + learned (FP32 multigrid in FP64 defect correction to 1e-10,
-    learned start), and the FFT forms, solves/s with set-up and prediction
-    inside the timed solve."""
+    held-out seeds, solves/s with set-up and prediction inside the timed
+    solve.  Plain FP64: FP64 multigrid to 1e-12, zero start.  Mixed +
+    learned: FP32 multigrid in FP64 defect correction to 1e-10, the inner
+    tolerance relaxed inside GMRES (relax 0.1, inexact Krylov), learned
+    start.  The other forms separate the three ingredients; the FFT forms
+    use the paper's exact box solve."""
     import torch
     from paper_2309_05965_amd import kfbi, learned, warmstart
     from paper_2309_05965_amd import workloads as W
@@ -120,22 +122,29 @@ def forms_config5(tol, reps, n_problems=4):
         probs.append((prob, geom, jmp, pl, kfbi.device_jump_data(pl, jmp)))
         if len(probs) == n_problems:
             break
-    res, iters = {}, {}
-    for name, solver, eps, learned_start in (("fp64_mg_zero_start", "mg64", 1e-12, False),
-                                              ("fp32_mg_learned_start", "mg32", 1e-10, True),
-                                              ("fp64_fft_zero_start", "fft", 0.0, False),
-                                              ("fp64_fft_learned_start", "fft", 0.0, True)):
-        its = []
+    res, iters, tres = {}, {}, {}
+    for name, solver, eps, relax, learned_start in (
+            ("fp64_mg_zero_start", "mg64", 1e-12, 0.0, False),
+            ("fp32_mg_relaxed_learned_start", "mg32", 1e-10, 0.1, True),
+            ("fp32_mg_relaxed_zero_start", "mg32", 1e-10, 0.1, False),
+            ("fp64_mg_relaxed_zero_start", "mg64", 1e-12, 0.1, False),
+            ("fp32_mg_learned_start", "mg32", 1e-10, 0.0, True),
+            ("fp64_fft_zero_start", "fft", 0.0, 0.0, False),
+            ("fp64_fft_learned_start", "fft", 0.0, 0.0, True)):
+        its, trs = [], []
 
         def run():
             its.clear()
+            trs.clear()
             for prob, geom, jmp, pl, d in probs:
                 pl.setup(prob)
                 psi0 = warmstart.predict(model, pl, geom, jmp, S) if learned_start else None
                 _, _, info = pl.solve(d, tol=tol, psi0=psi0)
                 its.append(info["iters"])
+                trs.append(info["true_rel_res"])
         for prob, geom, jmp, pl, d in probs:
             pl.set_box_solver(solver, eps_in=eps if eps > 0 else 1e-12, max_cycles=16)
+            pl.set_box_relaxation(relax)
         run()
         torch.cuda.synchronize()
         t0 = time.perf_counter()
@@ -144,8 +153,10 @@ def forms_config5(tol, reps, n_problems=4):
         torch.cuda.synchronize()
         res[name] = reps * len(probs) / (time.perf_counter() - t0)
         iters[name] = float(np.mean(its))
+        tres[name] = float(np.max(trs))
     res["gmres_iters_mean"] = iters
-    res["mixed_learned_over_plain"] = res["fp32_mg_learned_start"] / res["fp64_mg_zero_start"]
+    res["true_rel_res_max"] = tres
+    res["mixed_learned_over_plain"] = res["fp32_mg_relaxed_learned_start"] / res["fp64_mg_zero_start"]
     res["problems"] = len(probs)
     return res
 

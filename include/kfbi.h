@@ -204,6 +204,19 @@ kfbi_status kfbi_plan_export(const kfbi_plan* plan, int which, void* dst, int64_
 enum { KFBI_BOX_FFT = 0, KFBI_BOX_MG64 = 1, KFBI_BOX_MG32 = 2 };
 kfbi_status kfbi_plan_set_box_solver(kfbi_plan* plan, int solver, double eps_in, int max_cycles);
 
+/* Relaxed multigrid tolerance inside GMRES (inexact Krylov; not in the
+ * paper, whose box solve is exact): with relax > 0, the box solve of the
+ * matvec at GMRES step j stops at
+ *   eps_j = min(1e-2, max(eps_in, relax * tol * |b| / |r_j|)),
+ * |r_j| the current GMRES residual estimate, |b| the right-hand side norm
+ * and tol the solve's tolerance, all read on the device from the GMRES
+ * control data, so the captured iterations stay valid.  The right-hand
+ * side, the final solve and the true-residual matvec keep eps_in; the
+ * reported true residual judges the result.  relax = 0 (the default)
+ * turns it off; no effect with the FFT solver.  Returns KFBI_E_INVALID for
+ * a negative or non-finite relax. */
+kfbi_status kfbi_plan_set_box_relaxation(kfbi_plan* plan, double relax);
+
 /* Corrections used by, and relative residual |F - A_h v| / |F| reached in,
  * the last multigrid box solve of the plan (synchronises the plan's
  * stream).  For the FFT solver both are 0. */
@@ -349,7 +362,10 @@ kfbi_status kfbi_scale_jumps(float* X, float* Y, const float* alpha, int B, int 
 kfbi_status kfbi_sh_transfer(kfbi_plan* plan, const double* geom, const double* S, int ns, const float* psi_s,
                              double scale, double* psi_dof);
 /* Density at the samples from values at the DOFs (the same fit from the
- * DOFs, n_dof >= 81), times scale, fp32. */
+ * DOFs, n_dof >= 81), times scale, fp32.
+ * Both transfers are ordered on the plan's stream without a host wait and
+ * use a workspace the plan keeps (grown on demand, freed with the plan);
+ * concurrent transfers on one plan are not allowed. */
 kfbi_status kfbi_sh_sample(kfbi_plan* plan, const double* geom, const double* psi_dof, const double* S, int ns,
                            double scale, float* psi_s);
 /* The 81 real orthonormal spherical harmonics (no Condon-Shortley phase,

@@ -159,6 +159,7 @@ void free_plan(kfbi_plan* pl) {
   dfree(pl->IE2);
   dfree(pl->PA);
   dfree(pl->Firr);
+  dfree(pl->sh_ws);
   dfree(pl->PE1);
   dfree(pl->PE2);
   dfree(pl->EI);
@@ -614,6 +615,16 @@ extern "C" kfbi_status kfbi_plan_set_box_solver(kfbi_plan* pl, int solver, doubl
   return mg_configure(pl, solver, eps_in, max_cycles);
 }
 
+extern "C" kfbi_status kfbi_plan_set_box_relaxation(kfbi_plan* pl, double relax) {
+  KCHK(need_ready(pl));
+  if (!(relax >= 0.0) || !isfinite(relax)) {
+    kfbi_set_error("relaxation factor must be finite and >= 0 (got %g)", relax);
+    return KFBI_E_INVALID;
+  }
+  pl->mg_relax = relax;   // read on the device at every solve: the graphs stay valid
+  return KFBI_OK;
+}
+
 extern "C" kfbi_status kfbi_plan_box_stats(kfbi_plan* pl, int32_t* cycles, double* rel_res) {
   KCHK(need_ready(pl));
   int c = 0;
@@ -667,25 +678,21 @@ extern "C" kfbi_status kfbi_rhs(kfbi_plan* pl, const kfbi_data* data, double* b)
 }
 
 namespace {
-kfbi_status solve_body(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* opts, double* psi, double* u_out,
-                       kfbi_info* info, int m, double tol) {
+// Steps 3-4 after gm_residual_start: launch captured iterations in batches,
+// reading the control word back between batches.  The first batch goes
+// out without a host wait (after convergence or a zero right-hand side
+// every kernel of a captured iteration returns at once); later batches are
+// predicted from the observed convergence rate.
+struct GmresOut {
+  int k;
+  double est;
+  bool conv;
+};
+
+kfbi_status gmres_run(kfbi_plan* pl, double tol, int m, int first_batch, GmresOut* o) {
   hipStream_t st = pl->stream;
-  // Step 1: right-hand side
-  simple_solve_impl(pl, data->g1, nullptr, data->ftilde, data->fhat, data->gB, pl->vsbuf, pl->dn_in, pl->dn_out);
-  op_bie_rhs(pl, data->g2, pl->dn_in, pl->dn_out, pl->bvec);
-  // Step 2: initial residual and control word
-  if (opts->use_x0) matvec_impl(pl, psi, pl->work);
-  gm_residual_start(pl, pl->bvec, pl->work, opts->use_x0, tol, m);
-  KCHK(ensure_graph(pl));
-  // Steps 3-4: launch captured iterations in batches, reading the control
-  // word back between batches.  The first batch goes out without a host
-  // wait (after convergence or a zero right-hand side every kernel of a
-  // captured iteration returns at once); its length is the previous
-  // solve's iteration count on this plan (at least 4: an over-long batch
-  // costs a few microseconds, a short one a host round trip).  Later
-  // batches are predicted from the observed convergence rate.
   int launched = 0;
-  int batch = pl->last_iters > 4 ? (pl->last_iters < 64 ? pl->last_iters : 64) : 4;
+  int batch = first_batch;
   double nb = 0.0, res_prev = 0.0;
   int k_prev = 0;
   bool first = true;
@@ -714,28 +721,78 @@ kfbi_status solve_body(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* op
     res_prev = res;
     k_prev = k;
   }
-  const int k = pl->h_ctl[2];
-  pl->last_iters = k;
-  const double est = nb > 0.0 ? pl->h_dpinned[0] / nb : 0.0;
-  const bool conv = pl->h_ctl[1] && (nb == 0.0 || pl->h_dpinned[0] <= tol * nb || pl->h_dpinned[2] != 0.0);
-  gm_update(pl, k, psi, opts->use_x0);
-  // final solve u = w(g1, E psi, ftilde, fhat, gB)
-  op_extend(pl, psi, pl->aS);
-  simple_solve_impl(pl, data->g1, pl->aS, data->ftilde, data->fhat, data->gB, u_out ? u_out : pl->vsbuf,
-                    pl->dn_in, pl->dn_out);
-  // true residual with a fresh matvec
+  o->k = pl->h_ctl[2];
+  o->est = nb > 0.0 ? pl->h_dpinned[0] / nb : 0.0;
+  o->conv = pl->h_ctl[1] && (nb == 0.0 || pl->h_dpinned[0] <= tol * nb || pl->h_dpinned[2] != 0.0);
+  return KFBI_OK;
+}
+
+// |b - A psi| / |b| with a fresh full-accuracy matvec
+kfbi_status true_residual(kfbi_plan* pl, const double* psi, double* tr) {
+  hipStream_t st = pl->stream;
   matvec_impl(pl, psi, pl->work2);
   gm_true_residual(pl, pl->bvec, pl->work2, pl->scal + 4);
   HIPCHK(hipMemcpyAsync(pl->h_dpinned + 4, pl->scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
   HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
-  double tr = pl->h_dpinned[5] > 0.0 ? sqrt(pl->h_dpinned[4] / pl->h_dpinned[5]) : 0.0;
-  kfbi_status s = conv ? KFBI_OK : KFBI_E_NOT_CONVERGED;
-  if (!isfinite(tr) || !isfinite(est)) s = KFBI_E_NONFINITE;
+  *tr = pl->h_dpinned[5] > 0.0 ? sqrt(pl->h_dpinned[4] / pl->h_dpinned[5]) : 0.0;
+  return KFBI_OK;
+}
+
+// the relaxation factor the captured iterations read (GMRES scal[7])
+kfbi_status set_relax_word(kfbi_plan* pl, double r) {
+  pl->h_dpinned[7] = r;
+  HIPCHK(hipMemcpyAsync(pl->scal + 7, pl->h_dpinned + 7, sizeof(double), hipMemcpyHostToDevice, pl->stream));
+  return KFBI_OK;
+}
+
+kfbi_status solve_body(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* opts, double* psi, double* u_out,
+                       kfbi_info* info, int m, double tol) {
+  // Step 1: right-hand side
+  simple_solve_impl(pl, data->g1, nullptr, data->ftilde, data->fhat, data->gB, pl->vsbuf, pl->dn_in, pl->dn_out);
+  op_bie_rhs(pl, data->g2, pl->dn_in, pl->dn_out, pl->bvec);
+  const bool relax = pl->mg_relax > 0.0 && pl->box_solver != KFBI_BOX_FFT;
+  KCHK(set_relax_word(pl, relax ? pl->mg_relax : 0.0));
+  // Step 2: initial residual and control word
+  if (opts->use_x0) matvec_impl(pl, psi, pl->work);
+  gm_residual_start(pl, pl->bvec, pl->work, opts->use_x0, tol, m);
+  KCHK(ensure_graph(pl));
+  // Steps 3-4; the first batch is the previous solve's iteration count on
+  // this plan (at least 4: an over-long batch costs a few microseconds, a
+  // short one a host round trip)
+  GmresOut o;
+  KCHK(gmres_run(pl, tol, m, pl->last_iters > 4 ? (pl->last_iters < 64 ? pl->last_iters : 64) : 4, &o));
+  gm_update(pl, o.k, psi, opts->use_x0);
+  double tr = 0.0;
+  KCHK(true_residual(pl, psi, &tr));
+  int k = o.k;
+  // with a relaxed inner tolerance the GMRES estimate can run ahead of the
+  // true residual: if it misses tol, continue from psi with full-accuracy
+  // box solves until it meets it
+  if (relax && o.conv && tr > tol && k < m) {
+    KCHK(set_relax_word(pl, 0.0));
+    matvec_impl(pl, psi, pl->work);
+    gm_residual_start(pl, pl->bvec, pl->work, 1, tol, m - k);
+    GmresOut o2;
+    KCHK(gmres_run(pl, tol, m - k, 4, &o2));
+    gm_update(pl, o2.k, psi, 1);
+    KCHK(true_residual(pl, psi, &tr));
+    k += o2.k;
+    o.est = o2.est;
+    o.conv = o2.conv;
+  }
+  pl->last_iters = k;
+  // final solve u = w(g1, E psi, ftilde, fhat, gB)
+  op_extend(pl, psi, pl->aS);
+  simple_solve_impl(pl, data->g1, pl->aS, data->ftilde, data->fhat, data->gB, u_out ? u_out : pl->vsbuf,
+                    pl->dn_in, pl->dn_out);
+  HIPCHK(hipGetLastError());
+  kfbi_status s = o.conv ? KFBI_OK : KFBI_E_NOT_CONVERGED;
+  if (!isfinite(tr) || !isfinite(o.est)) s = KFBI_E_NONFINITE;
   if (info) {
     info->iters = k;
     info->status = s;
-    info->est_rel_res = est;
+    info->est_rel_res = o.est;
     info->true_rel_res = tr;
   }
   if (s == KFBI_E_NOT_CONVERGED) kfbi_set_error("GMRES did not reach tol %g in %d iterations", tol, m);

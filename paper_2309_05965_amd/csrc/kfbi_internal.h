@@ -107,6 +107,8 @@ struct kfbi_plan {
   double* TI;                    // [n_dof][nC] sum over the block nodes outside the
                                  // centre's region of IW * monomials (own polynomial)
   double* Cv;                    // [n_corr] correction values of the current matvec
+  double* sh_ws;                 // spherical-harmonic transfer workspace (learned start)
+  int64_t sh_ws_cap;
   double* Firr;                  // [n_irr] corrected right-hand side at the irregular nodes (many pairs)
   int* IB;                       // [n_dof] first node of the interpolation block
   int* IE2;                      // [n_dof][(q+1)^d] entry of C^(reg q) at block nodes
@@ -129,6 +131,7 @@ struct kfbi_plan {
   int64_t mg_bytes;
   double* mg_part;               // partial sums of the outer residual
   int* mg_ctl;                   // [done, corrections]
+  double mg_relax;               // inexact-Krylov relaxation of eps inside GMRES (0: off)
   double* mg_scal;               // [|F|, last relative residual]
   double* Fmg;                   // matvec right-hand side (full grid), zero off the irregular nodes
   // GMRES iteration on the device: control word [j, done, k, max_iter] and a

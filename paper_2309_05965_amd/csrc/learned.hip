@@ -749,27 +749,34 @@ extern "C" kfbi_status kfbi_ellipsoid_features(const double* geom, const double*
 }
 
 namespace {
-kfbi_status sh_fit_eval(hipStream_t st, int n_in, const double* dirs_in, const double* pos_in, const double* G,
-                        const double* vals, const float* valsf, double vscale, int n_out, const double* dirs_out,
-                        const double* pos_out, double* out, float* outf, double oscale) {
+// part [nblk][SH_N^2 + SH_N] and coef [SH_N] in ws (at least sh_ws_len(n_in) values)
+int64_t sh_ws_len(int n_in) {
   const int nblk = (n_in + FIT_PTS - 1) / FIT_PTS;
-  double *part = nullptr, *coef = nullptr;
-  KCHK(dalloc_t(&part, (int64_t)nblk * (SH_N * SH_N + SH_N)));
-  if (dalloc_t(&coef, SH_N) != KFBI_OK) {
-    dfree_t(part);
-    return KFBI_E_OOM;
-  }
+  return (int64_t)nblk * (SH_N * SH_N + SH_N) + SH_N;
+}
+
+void sh_fit_eval(hipStream_t st, double* ws, int n_in, const double* dirs_in, const double* pos_in,
+                 const double* G, const double* vals, const float* valsf, double vscale, int n_out,
+                 const double* dirs_out, const double* pos_out, double* out, float* outf, double oscale) {
+  const int nblk = (n_in + FIT_PTS - 1) / FIT_PTS;
+  double* part = ws;
+  double* coef = ws + (int64_t)nblk * (SH_N * SH_N + SH_N);
   hipLaunchKernelGGL(k_sh_normal, dim3(nblk), dim3(256), 0, st, n_in, dirs_in, pos_in, G, vals, valsf, vscale, part);
   hipLaunchKernelGGL(k_sh_solve, dim3(1), dim3(256), 0, st, nblk, (const double*)part, coef);
   hipLaunchKernelGGL(k_sh_eval, dim3(nbl(n_out)), dim3(256), 0, st, n_out, dirs_out, pos_out, G,
                      (const double*)coef, out, outf, oscale);
-  hipError_t e = hipStreamSynchronize(st);
-  dfree_t(part);
-  dfree_t(coef);
-  if (e != hipSuccess) {
-    kfbi_set_error("HIP error %s in the spherical-harmonic fit", hipGetErrorString(e));
-    return KFBI_E_DEVICE;
+}
+
+// the plan's transfer workspace (grown, never shrunk; freed with the plan)
+kfbi_status sh_workspace(kfbi_plan* pl, int64_t need, double** ws) {
+  if (need > pl->sh_ws_cap) {
+    if (pl->sh_ws) (void)hipFree(pl->sh_ws);
+    pl->sh_ws = nullptr;
+    pl->sh_ws_cap = 0;
+    KCHK(dalloc_t(&pl->sh_ws, need));
+    pl->sh_ws_cap = need;
   }
+  *ws = pl->sh_ws;
   return KFBI_OK;
 }
 }  // namespace
@@ -784,14 +791,17 @@ extern "C" kfbi_status kfbi_sh_transfer(kfbi_plan* pl, const double* geom, const
     kfbi_set_error("the spherical-harmonic transfer is defined in 3D");
     return KFBI_E_INVALID;
   }
-  // DOF positions: the surface table gathered through d2s
-  double* dpos = nullptr;
-  KCHK(dalloc_t(&dpos, 3 * pl->n_dof));
+  // workspace: DOF positions (the surface table gathered through d2s), then
+  // the fit's partial normal equations and coefficients; everything stays
+  // ordered on the plan's stream
+  double* ws = nullptr;
+  KCHK(sh_workspace(pl, 3 * pl->n_dof + sh_ws_len(ns), &ws));
+  double* dpos = ws;
   KCHK(kfbi_plan_export(pl, KFBI_EXPORT_DOF_POS, dpos, (int64_t)sizeof(double) * 3 * pl->n_dof));
-  kfbi_status st = sh_fit_eval(pl->stream, ns, S, nullptr, geom, nullptr, psi_s, scale, (int)pl->n_dof, nullptr,
-                               dpos, psi_dof, nullptr, 1.0);
-  dfree_t(dpos);
-  return st;
+  sh_fit_eval(pl->stream, ws + 3 * pl->n_dof, ns, S, nullptr, geom, nullptr, psi_s, scale, (int)pl->n_dof, nullptr,
+              dpos, psi_dof, nullptr, 1.0);
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
 }
 
 extern "C" kfbi_status kfbi_sh_sample(kfbi_plan* pl, const double* geom, const double* psi_dof, const double* S,
@@ -804,13 +814,14 @@ extern "C" kfbi_status kfbi_sh_sample(kfbi_plan* pl, const double* geom, const d
     kfbi_set_error("the spherical-harmonic transfer is defined in 3D");
     return KFBI_E_INVALID;
   }
-  double* dpos = nullptr;
-  KCHK(dalloc_t(&dpos, 3 * pl->n_dof));
+  double* ws = nullptr;
+  KCHK(sh_workspace(pl, 3 * pl->n_dof + sh_ws_len((int)pl->n_dof), &ws));
+  double* dpos = ws;
   KCHK(kfbi_plan_export(pl, KFBI_EXPORT_DOF_POS, dpos, (int64_t)sizeof(double) * 3 * pl->n_dof));
-  kfbi_status st = sh_fit_eval(pl->stream, (int)pl->n_dof, nullptr, dpos, geom, psi_dof, nullptr, 1.0, ns, S,
-                               nullptr, nullptr, psi_s, scale);
-  dfree_t(dpos);
-  return st;
+  sh_fit_eval(pl->stream, ws + 3 * pl->n_dof, (int)pl->n_dof, nullptr, dpos, geom, psi_dof, nullptr, 1.0, ns, S,
+              nullptr, nullptr, psi_s, scale);
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
 }
 
 extern "C" kfbi_status kfbi_real_sh(const double* dirs, int n, void* stream, double* Y) {

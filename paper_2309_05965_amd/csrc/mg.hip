@@ -626,10 +626,24 @@ __global__ void __launch_bounds__(MG_BLOCK) k_outer_resid(OuterArgs a, T* f0) {
   }
 }
 
-// stopping test: |r| <= eps |F| (|F| taken at the first correction)
+// stopping test: |r| <= eps |F| (|F| taken at the first correction).
+// Relaxed inner tolerance inside a captured GMRES iteration: the box solve
+// of the matvec at GMRES step j only needs an accuracy in proportion to
+// tol |b| / |r_j| (inexact Krylov), so eps becomes relax tol |b| / |r_j|
+// from the GMRES scalars (gs[0] = |r_j| estimate, gs[1] = |b|, gs[3] =
+// tol, gs[7] = relax, 0 for off), clamped to [eps, 1e-2].
 __global__ void __launch_bounds__(MG_BLOCK) k_check(Ctl ctl, const double* part, int nblk, int first, double eps,
-                                                   int maxit, double* scal) {
+                                                   int maxit, double* scal, const double* gs) {
   if ((ctl.gctl && ctl.gctl[1]) || ctl.mctl[0]) return;
+  const double relax = (ctl.gctl && gs) ? gs[7] : 0.0;
+  if (relax > 0.0) {
+    const double rj = gs[0], nb = gs[1], tol = gs[3];
+    if (rj > 0.0 && nb > 0.0) {
+      double e = relax * tol * nb / rj;
+      if (e > 1e-2) e = 1e-2;
+      if (e > eps) eps = e;
+    }
+  }
   __shared__ double sr[MG_BLOCK], sf[MG_BLOCK];
   double r = 0.0, f = 0.0;
   for (int i = threadIdx.x; i < nblk; i += MG_BLOCK) {
@@ -885,7 +899,7 @@ void solve_t(kfbi_plan* pl, const double* F, double* v) {
     else
       sweep<double, T, SW_OUTER>(pl, ctl, g.N, pl->mg_c[0], 0.0, v, F, f0, &nb_part);
     hipLaunchKernelGGL(k_check, dim3(1), dim3(MG_BLOCK), 0, st, ctl, (const double*)pl->mg_part, nb_part,
-                       it == 0 ? 1 : 0, pl->mg_eps, pl->mg_maxit, pl->mg_scal);
+                       it == 0 ? 1 : 0, pl->mg_eps, pl->mg_maxit, pl->mg_scal, (const double*)pl->scal);
     vcycle<T>(pl, H, ctl);
     hipLaunchKernelGGL((k_update<T>), dim3(gsblk(m)), dim3(MG_BLOCK), 0, st, ctl, g.d, g.N, g.n1,
                        (const T*)pl->mg_u, v);
@@ -894,7 +908,7 @@ void solve_t(kfbi_plan* pl, const double* F, double* v) {
   int nb_part = 0;
   sweep<double, T, SW_OUTER>(pl, ctl, g.N, pl->mg_c[0], 0.0, v, F, f0, &nb_part);
   hipLaunchKernelGGL(k_check, dim3(1), dim3(MG_BLOCK), 0, st, ctl, (const double*)pl->mg_part, nb_part, 0,
-                     pl->mg_eps, pl->mg_maxit, pl->mg_scal);
+                     pl->mg_eps, pl->mg_maxit, pl->mg_scal, (const double*)pl->scal);
 }
 
 double jacobi_weight(const double* c, int d) {

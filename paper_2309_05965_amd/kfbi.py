@@ -69,6 +69,7 @@ ABI = {
     "kfbi_solve": ([ctypes.c_void_p, ctypes.POINTER(Data), ctypes.POINTER(Opts), c_double_p, c_double_p,
                     ctypes.POINTER(Info)], ctypes.c_int),
     "kfbi_plan_set_box_solver": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_double, ctypes.c_int], ctypes.c_int),
+    "kfbi_plan_set_box_relaxation": ([ctypes.c_void_p, ctypes.c_double], ctypes.c_int),
     "kfbi_plan_box_stats": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int32), ctypes.POINTER(ctypes.c_double)],
                             ctypes.c_int),
     "kfbi_plan_profile": ([ctypes.c_void_p, ctypes.c_int], ctypes.c_int),
@@ -214,6 +215,12 @@ class Plan:
         |F - A v| <= eps_in |F|)."""
         _check(load().kfbi_plan_set_box_solver(self._h, self.BOX_SOLVERS[solver], float(eps_in), int(max_cycles)))
         self.box_solver = solver
+
+    def set_box_relaxation(self, relax):
+        """Relax the multigrid tolerance inside GMRES (inexact Krylov):
+        eps_j = min(1e-2, max(eps_in, relax tol |b| / |r_j|)); 0 turns it off."""
+        _check(load().kfbi_plan_set_box_relaxation(self._h, float(relax)))
+        self.box_relax = float(relax)
 
     def box_stats(self):
         """(corrections, relative residual) of the last multigrid box solve."""
