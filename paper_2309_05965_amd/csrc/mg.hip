@@ -32,6 +32,7 @@ namespace {
 constexpr int MG_BLOCK = 256;
 constexpr int MG_PART = 8192;            // partial sums of the outer residual (per block)
 constexpr int LDS_BLOCK = 1024;          // threads of the in-LDS coarse cycle
+constexpr size_t MG_LDS_MAX = 163840;     // LDS of one compute unit
 
 template <typename T>
 struct Lev {
@@ -957,7 +958,22 @@ kfbi_status mg_configure(kfbi_plan* pl, int solver, double eps, int maxit) {
     return KFBI_E_INVALID;
   }
   pl->mg_L = L;
-  const int cut = g.d == 3 ? 8 : 32;
+  // the levels with N <= cut run inside one workgroup (LDS): the largest
+  // cut whose three arrays per level fit the LDS of a compute unit (the
+  // small global levels are launch-bound; 16^3 and 64^2 fit in FP64)
+  const size_t es_lds = solver == KFBI_BOX_MG32 ? sizeof(float) : sizeof(double);
+  int cut = g.d == 3 ? 8 : 32;
+  for (int c = cut * 2; c >= cut; c /= 2) {
+    size_t tot = 0;
+    for (int n = c; n >= 2; n >>= 1) {
+      const size_t n1 = (size_t)n + 1;
+      tot += 3 * (g.d == 3 ? n1 * n1 * n1 : n1 * n1);
+    }
+    if (tot * es_lds <= MG_LDS_MAX) {
+      cut = c;
+      break;
+    }
+  }
   int lc = 0;
   while (lc < L && (g.N >> lc) > cut) ++lc;
   pl->mg_lc = lc;
@@ -1014,7 +1030,7 @@ kfbi_status mg_configure(kfbi_plan* pl, int solver, double eps, int maxit) {
   HIPCHK(hipMemsetAsync(pl->Fmg, 0, sizeof(double) * g.n_nodes, pl->stream));
   // the in-LDS coarse cycle must fit one workgroup
   size_t lds = pl->box_solver == KFBI_BOX_MG32 ? coarse_lds(make_hier<float>(pl)) : coarse_lds(make_hier<double>(pl));
-  if (lds > 65536) {
+  if (lds > MG_LDS_MAX) {
     kfbi_set_error("multigrid coarse levels exceed the LDS budget");
     return KFBI_E_INVALID;
   }
