@@ -84,7 +84,6 @@ void free_plan(kfbi_plan* pl) {
   dfree(pl->region);
   dfree(pl->need);
   dfree(pl->Cg);
-  dfree(pl->Fm);
   dfree(pl->Fs);
   dfree(pl->T1);
   dfree(pl->T2);
@@ -132,6 +131,7 @@ void free_plan(kfbi_plan* pl) {
   dfree(pl->cell_count);
   dfree(pl->cell_start);
   dfree(pl->cell_items);
+  dfree(pl->cell_cursor);
   dfree(pl->blk);
   dfree(pl->blk_total);
   dfree(pl->d_flags);
@@ -213,11 +213,11 @@ kfbi_status alloc_fixed(kfbi_plan* pl) {
   KCHK(dalloc(&pl->region, n));
   KCHK(dalloc(&pl->need, (int64_t)g.K * n));
   KCHK(dalloc(&pl->Cg, (int64_t)g.K * n));
-  KCHK(dalloc(&pl->Fm, n));
   KCHK(dalloc(&pl->Fs, n));
   KCHK(dalloc(&pl->T1, n));
   KCHK(dalloc(&pl->T2, n));
   KCHK(dalloc(&pl->vbuf, n));
+  HIPCHK(hipMemset(pl->vbuf, 0, sizeof(double) * n));   // box boundary: never written again
   KCHK(dalloc(&pl->vsbuf, n));
   KCHK(dalloc(&pl->flags8, pl->n_seg * g.K > n ? pl->n_seg * g.K : n));
   KCHK(dalloc(&pl->EI, (int64_t)g.K * n));
@@ -229,6 +229,7 @@ kfbi_status alloc_fixed(kfbi_plan* pl) {
   int64_t nkeys = (int64_t)g.K * pl->ncell;
   KCHK(dalloc(&pl->cell_count, nkeys + 1));
   KCHK(dalloc(&pl->cell_start, nkeys + 1));
+  KCHK(dalloc(&pl->cell_cursor, nkeys + 1));
   KCHK(dalloc(&pl->blk_total, 4));
   KCHK(dalloc(&pl->d_flags, 4));
   KCHK(dalloc(&pl->tw, 4 * g.N));
@@ -262,10 +263,7 @@ kfbi_status run_setup(kfbi_plan* pl) {
   KCHK(geo_setup(pl));
   KCHK(colloc_factor(pl));
   KCHK(op_fold(pl));
-  // the matvec right-hand side is zero away from the irregular nodes and the
-  // matvec grid solution is zero on the box boundary
-  HIPCHK(hipMemsetAsync(pl->Fm, 0, sizeof(double) * pl->g.n_nodes, pl->stream));
-  HIPCHK(hipMemsetAsync(pl->vbuf, 0, sizeof(double) * pl->g.n_nodes, pl->stream));
+  // the multigrid matvec right-hand side is zero away from the irregular nodes
   if (pl->Fmg) HIPCHK(hipMemsetAsync(pl->Fmg, 0, sizeof(double) * pl->g.n_nodes, pl->stream));
   // everything after the set-up is ordered behind it on the plan's stream
   HIPCHK(hipGetLastError());
@@ -319,12 +317,12 @@ void simple_solve_impl(kfbi_plan* pl, const double* a, const double* b, const do
 void matvec_impl(kfbi_plan* pl, const double* psi, double* Apsi) { op_matvec(pl, psi, Apsi); }
 
 void destroy_graphs(kfbi_plan* pl) {
-  if (pl->graph_exec) (void)hipGraphExecDestroy(pl->graph_exec);
-  if (pl->graph) (void)hipGraphDestroy(pl->graph);
-  if (pl->graph4_exec) (void)hipGraphExecDestroy(pl->graph4_exec);
-  if (pl->graph4) (void)hipGraphDestroy(pl->graph4);
-  pl->graph_exec = pl->graph4_exec = nullptr;
-  pl->graph = pl->graph4 = nullptr;
+  for (int v = 0; v < KFBI_NGRAPH; ++v) {
+    if (pl->graph_execs[v]) (void)hipGraphExecDestroy(pl->graph_execs[v]);
+    if (pl->graphs[v]) (void)hipGraphDestroy(pl->graphs[v]);
+    pl->graph_execs[v] = nullptr;
+    pl->graphs[v] = nullptr;
+  }
 }
 
 // Graphs of one and of four GMRES iterations (matvec of V[j] into V[j+1],
@@ -342,11 +340,13 @@ kfbi_status ensure_graph(kfbi_plan* pl) {
                       (uint64_t)(uintptr_t)pl->ext_idx, (uint64_t)(uintptr_t)pl->irr,
                       (uint64_t)(uintptr_t)pl->ce_node, (uint64_t)pl->gm_cap, (uint64_t)(uintptr_t)pl->d2s,
                       (uint64_t)(uintptr_t)pl->PA ^ (uint64_t)(uintptr_t)pl->GI ^ (uint64_t)(uintptr_t)pl->mg_u};
-  if (pl->graph_exec && pl->graph4_exec && memcmp(key, pl->graph_key, sizeof(key)) == 0) return KFBI_OK;
+  if (pl->graph_execs[KFBI_NGRAPH - 1] && memcmp(key, pl->graph_key, sizeof(key)) == 0) return KFBI_OK;
   destroy_graphs(pl);
   std::unique_lock<std::shared_mutex> lock(kfbi_capture_mutex);
-  for (int v = 0; v < 2; ++v) {
-    const int iters = v == 0 ? 1 : 4;
+  // every graph launch costs a few microseconds of idle time at its
+  // boundaries, so a batch is sent as few graphs as its binary digits
+  for (int v = 0; v < KFBI_NGRAPH; ++v) {
+    const int iters = 1 << v;
     HIPCHK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
     pl->ctl_active = pl->ctl;
     for (int it = 0; it < iters; ++it) {
@@ -363,13 +363,8 @@ kfbi_status ensure_graph(kfbi_plan* pl) {
       (void)hipGraphDestroy(gr);
       return kfbi_hip_status(e, "hipGraphInstantiate");
     }
-    if (v == 0) {
-      pl->graph = gr;
-      pl->graph_exec = ex;
-    } else {
-      pl->graph4 = gr;
-      pl->graph4_exec = ex;
-    }
+    pl->graphs[v] = gr;
+    pl->graph_execs[v] = ex;
   }
   memcpy(pl->graph_key, key, sizeof(key));
   return KFBI_OK;
@@ -432,6 +427,7 @@ extern "C" kfbi_status kfbi_plan_create(const kfbi_problem* prob, void* stream, 
     return KFBI_E_OOM;
   }
   memset((void*)pl, 0, sizeof(*pl));
+  pl->relax_word = NAN;
   pl->prob = *prob;
   pl->g = make_grid(*prob);
   pl->stream = (hipStream_t)stream;
@@ -698,8 +694,10 @@ kfbi_status gmres_run(kfbi_plan* pl, double tol, int m, int first_batch, GmresOu
   bool first = true;
   for (;;) {
     const int B = batch < m - launched ? batch : m - launched;
-    for (int b = 0; b + 4 <= B; b += 4) HIPCHK(hipGraphLaunch(pl->graph4_exec, st));
-    for (int b = 0; b < B % 4; ++b) HIPCHK(hipGraphLaunch(pl->graph_exec, st));
+    const int big = 1 << (KFBI_NGRAPH - 1);
+    for (int b = 0; b + big <= B; b += big) HIPCHK(hipGraphLaunch(pl->graph_execs[KFBI_NGRAPH - 1], st));
+    for (int v = KFBI_NGRAPH - 2; v >= 0; --v)
+      if ((B % big) & (1 << v)) HIPCHK(hipGraphLaunch(pl->graph_execs[v], st));
     launched += B;
     HIPCHK(hipMemcpyAsync(pl->h_ctl, pl->ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
     HIPCHK(hipMemcpyAsync(pl->h_dpinned, pl->scal, 7 * sizeof(double), hipMemcpyDeviceToHost, st));
@@ -741,6 +739,8 @@ kfbi_status true_residual(kfbi_plan* pl, const double* psi, double* tr) {
 
 // the relaxation factor the captured iterations read (GMRES scal[7])
 kfbi_status set_relax_word(kfbi_plan* pl, double r) {
+  if (r == pl->relax_word) return KFBI_OK;    // unchanged on the device
+  pl->relax_word = r;
   pl->h_dpinned[7] = r;
   HIPCHK(hipMemcpyAsync(pl->scal + 7, pl->h_dpinned + 7, sizeof(double), hipMemcpyHostToDevice, pl->stream));
   return KFBI_OK;

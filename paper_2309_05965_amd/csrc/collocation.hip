@@ -308,7 +308,8 @@ kfbi_status colloc_factor(kfbi_plan* pl) {
     kfbi_set_error("collocation sizes inconsistent (%d %d %d %d)", T.n, T.nP, T.nD, T.nN);
     return KFBI_E_INVALID;
   }
-  HIPCHK(hipMemsetAsync(pl->d_flags, 0, sizeof(int), pl->stream));
+  // the status flags are zero here: the geometry set-up clears them and
+  // returns an error if any is set
   FactorArgs a{pl->g, T, pl->n_dof, pl->d2s, pl->s_pos, pl->s_nrm, pl->stD, pl->stN, pl->MinvT, pl->MT,
                pl->cond, pl->d_flags};
   switch (T.n) {

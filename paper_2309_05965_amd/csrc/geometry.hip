@@ -547,9 +547,13 @@ struct SurfEmit {
   }
 };
 
-__global__ void k_lines(int64_t n, int64_t L, const int* meta, int* ls, int* le) {
+// line CSR of the surface table; also resets the surface-to-DOF map (-1)
+// and the stencil-use flags of every surface point
+__global__ void k_lines(int64_t n, int64_t L, const int* meta, int* ls, int* le, int* s2d, uint8_t* s_need) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  s2d[i] = -1;
+  s_need[i] = 0;
   int64_t key = (int64_t)meta[i * 5] * L + meta[i * 5 + 1];
   int64_t kp = i > 0 ? (int64_t)meta[(i - 1) * 5] * L + meta[(i - 1) * 5 + 1] : -1;
   int64_t kn = i + 1 < n ? (int64_t)meta[(i + 1) * 5] * L + meta[(i + 1) * 5 + 1] : -1;
@@ -1122,6 +1126,37 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_owner(OwnerArgs a) {
   if (lane == 0) a.owner[e] = best;
 }
 
+// ---------------------------------------------------------------- resets
+// Up to 12 device arrays set to a value in one launch: int arrays to v, byte
+// arrays (v = 0 only) to zero.  blockIdx.y selects the array.
+struct FillItem {
+  void* p;
+  int64_t n;
+  int v;
+  int bytes;   // 1: uint8 elements (zeroed), 0: int elements
+};
+struct FillList {
+  FillItem it[12];
+  int n;
+  void add(int* p, int64_t cnt, int v) { it[n++] = FillItem{p, cnt, v, 0}; }
+  void add_bytes(uint8_t* p, int64_t cnt) { it[n++] = FillItem{p, cnt, 0, 1}; }
+};
+
+__global__ void k_fill_many(FillList L) {
+  const FillItem f = L.it[blockIdx.y];
+  const int64_t stride = (int64_t)gridDim.x * blockDim.x;
+  if (f.bytes) {
+    // whole 32-bit words, then the tail bytes (allocations are 256-byte aligned)
+    uint32_t* w = (uint32_t*)f.p;
+    const int64_t nw = f.n >> 2;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < nw; i += stride) w[i] = 0u;
+    if (blockIdx.x == 0 && threadIdx.x < (f.n & 3)) ((uint8_t*)f.p)[(nw << 2) + threadIdx.x] = 0;
+  } else {
+    int* a = (int*)f.p;
+    for (int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; i < f.n; i += stride) a[i] = f.v;
+  }
+}
+
 // ---------------------------------------------------------------- host helpers
 inline unsigned nblk(int64_t n, int b = KFBI_BLOCK) { return (unsigned)((n + b - 1) / b); }
 
@@ -1262,7 +1297,27 @@ kfbi_status geo_setup(kfbi_plan* pl) {
     L.kind[k] = pl->prob.iface[k].kind;
     for (int j = 0; j < KFBI_LS_NPARAM; ++j) L.p[k][j] = pl->prob.iface[k].p[j];
   }
-  HIPCHK(hipMemsetAsync(pl->d_flags, 0, sizeof(int), st));
+  // every grid-sized table that the set-up fills sparsely starts from its
+  // reset value: one launch instead of a memset each
+  {
+    const int64_t nkeys = (int64_t)g.K * pl->ncell;
+    const int64_t nrows = g.d == 3 ? (int64_t)g.n1 * g.n1 : g.n1;
+    FillList F;
+    F.n = 0;
+    F.add(pl->d_flags, 1, 0);
+    F.add(pl->line_start, pl->n_lines, 0);
+    F.add(pl->line_end, pl->n_lines, 0);
+    F.add(pl->cell_count, nkeys + 1, 0);
+    F.add(pl->cell_cursor, nkeys + 1, 0);
+    F.add(pl->EI, (int64_t)g.K * g.n_nodes, -1);
+    F.add(pl->row_start, nrows, 0);
+    F.add(pl->row_end, nrows, 0);
+    F.add_bytes(pl->need, (int64_t)g.K * g.n_nodes);
+    int64_t most = 0;
+    for (int i = 0; i < F.n; ++i) most = F.it[i].n > most ? F.it[i].n : most;
+    const int64_t gx = (most + 4 * KFBI_BLOCK - 1) / (4 * KFBI_BLOCK);
+    hipLaunchKernelGGL(k_fill_many, dim3((unsigned)(gx < 2048 ? gx : 2048), (unsigned)F.n), dim3(KFBI_BLOCK), 0, st, F);
+  }
   // regions
   hipLaunchKernelGGL(k_regions, dim3(nblk(g.n_nodes)), dim3(KFBI_BLOCK), 0, st,
                      RegionArgs{g, L, pl->region, pl->d_flags});
@@ -1322,10 +1377,8 @@ kfbi_status geo_setup(kfbi_plan* pl) {
   compact_emit(pl, nc, ap, SurfEmit{g.d, pl->c_pos, pl->c_nrm, pl->c_r, pl->c_lid, pl->c_seg, pl->c_k,
                                     pl->s_pos, pl->s_nrm, pl->s_meta});
   int64_t L1 = g.d == 2 ? g.n1 : (int64_t)g.n1 * g.n1;
-  HIPCHK(hipMemsetAsync(pl->line_start, 0, sizeof(int) * pl->n_lines, st));
-  HIPCHK(hipMemsetAsync(pl->line_end, 0, sizeof(int) * pl->n_lines, st));
   hipLaunchKernelGGL(k_lines, dim3(nblk(ns)), dim3(KFBI_BLOCK), 0, st, ns, L1, pl->s_meta, pl->line_start,
-                     pl->line_end);
+                     pl->line_end, pl->s2d, pl->s_need);
 
   // primary points
   PrimPred pp{pl->s_meta};
@@ -1354,7 +1407,6 @@ kfbi_status geo_setup(kfbi_plan* pl) {
     pl->cap_dof = cap;
   }
   pl->n_dof = nd;
-  HIPCHK(hipMemsetAsync(pl->s2d, 0xff, sizeof(int) * ns, st));
   compact_emit(pl, ns, pp, PrimEmit{pl->d2s, pl->s2d});
 
   // collocation stencils
@@ -1375,7 +1427,6 @@ kfbi_status geo_setup(kfbi_plan* pl) {
   }
   shift_list(g.d, offs, lat.shN, &lat.nSN);
   SurfView S{g, pl->s_pos, pl->s_nrm, pl->s_meta, pl->line_start, pl->line_end, L1};
-  HIPCHK(hipMemsetAsync(pl->s_need, 0, ns, st));
   hipLaunchKernelGGL(k_stencils, dim3(nblk(nd * STG)), dim3(KFBI_BLOCK), 0, st,
                      StencilArgs{S, lat, nd, pl->d2s, pl->stD, pl->stN, pl->s_need, pl->d_flags});
   hipLaunchKernelGGL(k_extension, dim3(nblk(ns * EXG)), dim3(KFBI_BLOCK), 0, st,
@@ -1395,7 +1446,6 @@ kfbi_status geo_setup(kfbi_plan* pl) {
   compact_emit(pl, g.n_nodes, NeedPred{pl->flags8}, IdxEmit{pl->irr});
 
   // correction entries
-  HIPCHK(hipMemsetAsync(pl->need, 0, (size_t)g.K * g.n_nodes, st));
   if (ni > 0)
     hipLaunchKernelGGL(k_need_irr, dim3(nblk(ni)), dim3(KFBI_BLOCK), 0, st, g, ni, pl->irr, pl->region,
                        pl->need);
@@ -1417,7 +1467,6 @@ kfbi_status geo_setup(kfbi_plan* pl) {
 
   // closest centres: bin the centres of every interface on a 2h lattice
   int64_t nkeys = (int64_t)g.K * pl->ncell;
-  HIPCHK(hipMemsetAsync(pl->cell_count, 0, sizeof(int) * (nkeys + 1), st));
   BinArgs ba{g, nd, pl->ncell_axis, pl->ncell, pl->d2s, pl->s_pos, pl->s_meta, pl->cell_count, nullptr};
   hipLaunchKernelGGL(k_bin_count, dim3(nblk(nd)), dim3(KFBI_BLOCK), 0, st, ba);
   {
@@ -1428,11 +1477,8 @@ kfbi_status geo_setup(kfbi_plan* pl) {
     hipLaunchKernelGGL(k_scan_apply, dim3((unsigned)nbs), dim3(KFBI_BLOCK), 0, st, nkeys, pl->cell_count,
                        pl->cell_start, pl->blk);
   }
-  KCHK(ensure_blk(pl, nkeys));
-  int* cursor = pl->blk;   // scan scratch reused as per-cell cursor
-  HIPCHK(hipMemsetAsync(cursor, 0, sizeof(int) * nkeys, st));
   ba.items = pl->cell_items;
-  hipLaunchKernelGGL(k_bin_fill, dim3(nblk(nd)), dim3(KFBI_BLOCK), 0, st, ba, pl->cell_start, cursor);
+  hipLaunchKernelGGL(k_bin_fill, dim3(nblk(nd)), dim3(KFBI_BLOCK), 0, st, ba, pl->cell_start, pl->cell_cursor);
   if (ne > 0)
     hipLaunchKernelGGL(k_owner, dim3(nblk(ne * OWG)), dim3(KFBI_BLOCK), 0, st,
                        OwnerArgs{g, ne, pl->ncell_axis, pl->ncell, pl->ce_k, pl->ce_node, pl->d2s, pl->s_pos,

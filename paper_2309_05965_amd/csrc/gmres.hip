@@ -227,6 +227,161 @@ __global__ void __launch_bounds__(GB) k_arnoldi1(int64_t n, int* ctl, int ldh, d
   for (int i = threadIdx.x; i <= j + 1; i += GB) hcol[i] = hs[i];
 }
 
+// value of x in lane l (l uniform across the wavefront)
+__device__ __forceinline__ double lane_value(double x, int l) {
+  const long long b = __double_as_longlong(x);
+  const int lo = __builtin_amdgcn_readlane((int)(b & 0xffffffffLL), l);
+  const int hi = __builtin_amdgcn_readlane((int)(b >> 32), l);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+// Single work group, small n (n <= GB E): thread t holds elements t + GB r
+// (r < E) of w and of the basis vectors V[0..JR-1] in registers for the
+// whole step, so those are read from memory once, all loads in flight
+// together; vectors JR..j (long runs) are read from memory in each phase.
+// A dot phase forms per-thread products and sums eight vectors at a time
+// over the wavefront (transposing butterfly) into per-wavefront partials in
+// LDS (one buffer per pass, so a single barrier per pass); every wavefront
+// then adds the 16 partials of coefficient i < 64 in lane i and the update
+// takes the coefficients from those lanes (readlane), with no further
+// barrier.  Coefficients from 64 on are summed from LDS where used.
+template <int E, int JR>
+__global__ void __launch_bounds__(GB) k_arnoldi_reg(int64_t n, int* ctl, int ldh, double* V, double* Hm, double* cs,
+                                                   double* sn, double* gv, double* scal) {
+  static_assert(JR % 8 == 0 && JR <= 64, "register vectors: a multiple of 8, at most 64");
+  __shared__ double red[2][GB / 64][KFBI_GMRES_MAX];
+  __shared__ double hs[KFBI_GMRES_MAX + 2];
+  __shared__ double lcs[KFBI_GMRES_MAX], lsn[KFBI_GMRES_MAX];
+  __shared__ double rn[GB / 64];
+  if (ctl[1]) return;
+  const int j = ctl[0];
+  const int nn = (int)n;
+  const int lane = threadIdx.x & 63, wave = threadIdx.x >> 6;
+  double* w = V + (int64_t)(j + 1) * n;
+  double wr[E], vr[JR][E];
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int t = threadIdx.x + GB * r;
+    wr[r] = t < nn ? w[t] : 0.0;
+  }
+#pragma unroll
+  for (int i = 0; i < JR; ++i)
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      const int t = threadIdx.x + GB * r;
+      vr[i][r] = (i <= j && t < nn) ? V[(int64_t)i * n + t] : 0.0;
+    }
+  for (int i = threadIdx.x; i < j; i += GB) {
+    lcs[i] = cs[i];
+    lsn[i] = sn[i];
+  }
+#pragma unroll
+  for (int pass = 0; pass < 2; ++pass) {
+    double(*rp)[KFBI_GMRES_MAX] = red[pass];
+#pragma unroll
+    for (int i0 = 0; i0 < JR; i0 += 8) {
+      if (i0 > j) break;
+      double p[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        double a = 0.0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) a += vr[i0 + q][r] * wr[r];
+        p[q] = a;
+      }
+      const double s = wave_reduce8(p, lane);
+      if ((lane & 7) == 0) rp[wave][i0 + wave_reduce8_index(lane)] = s;
+    }
+    for (int i0 = JR; i0 <= j; i0 += 8) {
+      double p[8];
+#pragma unroll
+      for (int q = 0; q < 8; ++q) {
+        double a = 0.0;
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          const int t = threadIdx.x + GB * r;
+          if (i0 + q <= j && t < nn) a += V[(int64_t)(i0 + q) * n + t] * wr[r];
+        }
+        p[q] = a;
+      }
+      const double s = wave_reduce8(p, lane);
+      if ((lane & 7) == 0 && i0 + wave_reduce8_index(lane) <= j) rp[wave][i0 + wave_reduce8_index(lane)] = s;
+    }
+    __syncthreads();
+    double h0 = 0.0;                   // lane l: coefficient l of this pass
+    if (lane <= j)
+      for (int wv = 0; wv < GB / 64; ++wv) h0 += rp[wv][lane];
+    if (wave == 0)
+      for (int i = lane; i <= j; i += 64) {
+        double s = h0;
+        if (i != lane) {
+          s = 0.0;
+          for (int wv = 0; wv < GB / 64; ++wv) s += rp[wv][i];
+        }
+        hs[i] = pass == 0 ? s : hs[i] + s;
+      }
+#pragma unroll
+    for (int r = 0; r < E; ++r) {
+      double x = wr[r];
+#pragma unroll
+      for (int i = 0; i < JR; ++i)
+        if (i <= j) x -= lane_value(h0, i) * vr[i][r];
+      wr[r] = x;
+    }
+    for (int i0 = JR; i0 <= j; i0 += 8) {
+#pragma unroll
+      for (int r = 0; r < E; ++r) {
+        const int t = threadIdx.x + GB * r;
+        double y[8];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) y[q] = (i0 + q <= j && t < nn) ? V[(int64_t)(i0 + q) * n + t] : 0.0;
+        double x = wr[r];
+#pragma unroll
+        for (int q = 0; q < 8; ++q) {
+          const int i = i0 + q;
+          if (i > j) break;
+          double hv;
+          if (i < 64) {
+            hv = lane_value(h0, i);
+          } else {
+            hv = 0.0;
+            for (int wv = 0; wv < GB / 64; ++wv) hv += rp[wv][i];
+          }
+          x -= hv * y[q];
+        }
+        wr[r] = x;
+      }
+    }
+  }
+  double sq = 0.0;
+#pragma unroll
+  for (int r = 0; r < E; ++r) sq += wr[r] * wr[r];
+  sq = wave_reduce(sq);
+  if (lane == 0) rn[wave] = sq;
+  __syncthreads();
+  double tot = 0.0;
+  for (int wv = 0; wv < GB / 64; ++wv) tot += rn[wv];
+  const double hn = sqrt(tot);
+  const bool breakdown = !(hn > 0.0);
+  const double inv = breakdown ? 1.0 : 1.0 / hn;
+#pragma unroll
+  for (int r = 0; r < E; ++r) {
+    const int t = threadIdx.x + GB * r;
+    if (t < nn) w[t] = breakdown ? wr[r] : wr[r] * inv;
+  }
+  if (wave == 0) {
+    if (lane == 0) {
+      hs[j + 1] = hn;
+      givens_column(j, hs, lcs, lsn, cs, sn, gv, scal, ctl, breakdown);
+    }
+    __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+    __builtin_amdgcn_wave_barrier();
+    __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
+    double* hcol = Hm + (int64_t)j * ldh;
+    for (int i = lane; i <= j + 1; i += 64) hcol[i] = hs[i];
+  }
+}
+
 // Many work groups (large n): work group b owns w[b*AC .. b*AC + AC), AE
 // elements per thread, and a step is four kernels.  Partial sums go to
 // part[3][B][L] (L = gm_cap + 2); each consumer reduces them over b in a
@@ -468,13 +623,20 @@ void gm_residual_start(kfbi_plan* pl, const double* b, const double* Ax0, int us
                      pl->gv, pl->scal, pl->ctl, tol, maxit);
 }
 
-// one work group up to 8192 unknowns (the step is latency-bound there);
-// beyond, the basis is read by many compute units
+// one work group up to 8192 unknowns (the step is latency-bound there),
+// with the basis in registers up to 2048; beyond, the basis is read by many
+// compute units
 void gm_arnoldi(kfbi_plan* pl) {
   const int64_t n = pl->n_dof;
   const int ldh = pl->gm_cap + 1;
   hipStream_t st = pl->stream;
-  if (n <= ARN1_MAXN) {
+  if (n <= GB) {
+    hipLaunchKernelGGL((k_arnoldi_reg<1, 32>), dim3(1), dim3(GB), 0, st, n, pl->ctl, ldh, pl->V, pl->Hm, pl->cs,
+                       pl->sn, pl->gv, pl->scal);
+  } else if (n <= 2 * GB) {
+    hipLaunchKernelGGL((k_arnoldi_reg<2, 16>), dim3(1), dim3(GB), 0, st, n, pl->ctl, ldh, pl->V, pl->Hm, pl->cs,
+                       pl->sn, pl->gv, pl->scal);
+  } else if (n <= ARN1_MAXN) {
     hipLaunchKernelGGL(k_arnoldi1, dim3(1), dim3(GB), 0, st, n, pl->ctl, ldh, pl->V, pl->Hm, pl->cs, pl->sn,
                        pl->gv, pl->scal);
   } else {

@@ -19,6 +19,7 @@
 #define KFBI_MAXN 10       // max Neumann points
 #define KFBI_GMRES_MAX 512
 #define KFBI_MG_MAXL 12    // multigrid levels (N <= 2048)
+#define KFBI_NGRAPH 5      // captured GMRES graphs of 1, 2, 4, 8 and 16 iterations
 
 // device-side status bits (OR-ed into plan->d_flags)
 enum {
@@ -56,7 +57,8 @@ struct kfbi_plan {
   int8_t* region;
   uint8_t* need;                 // [K][n_nodes] correction-entry flags
   double* Cg;                    // [K][n_nodes] correction values
-  double *Fm, *Fs, *T1, *T2, *vbuf, *vsbuf;
+  double *Fs, *T1, *T2, *vbuf, *vsbuf;   // simple-solve RHS, box-solve pass buffers, grid solutions
+                                 // (vbuf's box boundary stays zero: the box solves write interior nodes)
   // candidates
   int *c_r, *c_lid, *c_seg, *c_k, *c_ina;
   double *c_pos, *c_nrm;
@@ -80,6 +82,7 @@ struct kfbi_plan {
   int *ce_k, *ce_node, *ce_owner;
   // closest-centre bins
   int *cell_count, *cell_start, *cell_items;
+  int* cell_cursor;              // per-cell fill cursor of the binning
   // scan scratch
   uint8_t* flags8;               // predicate per item, max(d N (N+1)^(d-1) K, n_nodes)
   int *blk, *blk_total;
@@ -132,16 +135,17 @@ struct kfbi_plan {
   double* mg_part;               // partial sums of the outer residual
   int* mg_ctl;                   // [done, corrections]
   double mg_relax;               // inexact-Krylov relaxation of eps inside GMRES (0: off)
+  double relax_word;             // host copy of the factor last written to GMRES scal[7] (NaN: none)
   double* mg_scal;               // [|F|, last relative residual]
   double* Fmg;                   // matvec right-hand side (full grid), zero off the irregular nodes
   // GMRES iteration on the device: control word [j, done, k, max_iter] and a
-  // captured graph of one iteration (matvec + Arnoldi step)
+  // captured graphs of 2^g iterations (matvec + Arnoldi step each)
   int* ctl;
   const int* ctl_active;         // non-null while the iteration is captured
   hipStream_t gstream;           // private stream of kfbi_solve (graph launches)
   hipEvent_t ev_in, ev_out;
-  hipGraph_t graph, graph4;
-  hipGraphExec_t graph_exec, graph4_exec;     // one and four iterations
+  hipGraph_t graphs[KFBI_NGRAPH];
+  hipGraphExec_t graph_execs[KFBI_NGRAPH];  // graph g runs 2^g iterations
   uint64_t graph_key[20];
   int* h_ctl;
   // box-solve event timing

@@ -849,10 +849,8 @@ kfbi_status op_fold(kfbi_plan* pl) {
     KCHK(regrow(&pl->Firr, cap));
     pl->cap_fold_irr = cap;
   }
-  int64_t nrows = g.d == 3 ? (int64_t)g.n1 * g.n1 : g.n1;
-  HIPCHK(hipMemsetAsync(pl->EI, 0xff, sizeof(int) * (size_t)g.K * g.n_nodes, pl->stream));
-  HIPCHK(hipMemsetAsync(pl->row_start, 0, sizeof(int) * nrows, pl->stream));
-  HIPCHK(hipMemsetAsync(pl->row_end, 0, sizeof(int) * nrows, pl->stream));
+  // EI (all -1), row_start and row_end (all 0) were cleared at the start of
+  // the geometry set-up
   if (pl->n_corr > 0)
     hipLaunchKernelGGL(k_entry_map, dim3(nb(pl->n_corr)), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_corr, g.n_nodes,
                        pl->ce_k, pl->ce_node, pl->EI);
