@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <chrono>
 #include <new>
 
 #include "kfbi_internal.h"
@@ -182,6 +183,8 @@ void free_plan(kfbi_plan* pl) {
   pl->h_ctl = nullptr;
   if (pl->h_pinned) (void)hipHostFree(pl->h_pinned);
   if (pl->h_dpinned) (void)hipHostFree(pl->h_dpinned);
+  if (pl->mbox) (void)hipHostFree(pl->mbox);
+  pl->mbox = nullptr;
   pl->h_pinned = nullptr;
   pl->h_dpinned = nullptr;
 }
@@ -247,6 +250,11 @@ kfbi_status alloc_fixed(kfbi_plan* pl) {
     kfbi_set_error("pinned host allocation failed");
     return KFBI_E_OOM;
   }
+  if (hipHostMalloc((void**)&pl->mbox, sizeof(KfbiMailbox), 0) != hipSuccess) {
+    kfbi_set_error("pinned host allocation failed");
+    return KFBI_E_OOM;
+  }
+  memset((void*)pl->mbox, 0, sizeof(KfbiMailbox));
   if (hipHostMalloc((void**)&pl->h_ctl, 16 * sizeof(int), 0) != hipSuccess) {
     kfbi_set_error("pinned host allocation failed");
     return KFBI_E_OOM;
@@ -371,6 +379,68 @@ kfbi_status ensure_graph(kfbi_plan* pl) {
 }
 
 }  // namespace
+
+// ---------------------------------------------------------------- device posts
+namespace {
+__global__ void __launch_bounds__(1024) k_post(PostReq r, KfbiMailbox* mb, unsigned seq) {
+  __shared__ double red[16];
+  double mx = 0.0;
+  if (r.nmax > 0) {
+    for (int64_t i = threadIdx.x; i < r.nmax; i += 1024) {
+      const double v = r.maxsrc[i];
+      mx = (v > mx || v != v) ? v : mx;
+    }
+    for (int off = 32; off > 0; off >>= 1) {
+      const double v = __shfl_xor(mx, off, 64);
+      mx = (v > mx || v != v) ? v : mx;
+    }
+    if ((threadIdx.x & 63) == 0) red[threadIdx.x >> 6] = mx;
+    __syncthreads();
+  }
+  if (threadIdx.x != 0) return;
+  for (int i = 0; i < r.ni; ++i)
+    __hip_atomic_store(&mb->iv[i], *r.isrc[i], __ATOMIC_RELAXED, __HIP_MEMORY_SCOPE_SYSTEM);
+  for (int i = 0; i < r.nd; ++i)
+    __hip_atomic_store(&mb->dv[i], (unsigned long long)__double_as_longlong(*r.dsrc[i]), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  if (r.nmax > 0) {
+    double m = 0.0;
+    for (int w = 0; w < 16; ++w) m = (red[w] > m || red[w] != red[w]) ? red[w] : m;
+    __hip_atomic_store(&mb->dv[r.nd], (unsigned long long)__double_as_longlong(m), __ATOMIC_RELAXED,
+                       __HIP_MEMORY_SCOPE_SYSTEM);
+  }
+  __hip_atomic_store(&mb->seq, seq, __ATOMIC_RELEASE, __HIP_MEMORY_SCOPE_SYSTEM);
+}
+}  // namespace
+
+kfbi_status kfbi_post_wait(kfbi_plan* pl, const PostReq& r, int* iout, double* dout) {
+  if (r.ni > 8 || r.nd > 8 || (r.nmax > 0 && r.nd > 7)) {
+    kfbi_set_error("post request too large");
+    return KFBI_E_INVALID;
+  }
+  const unsigned seq = ++pl->mseq == 0 ? ++pl->mseq : pl->mseq;
+  hipLaunchKernelGGL(k_post, dim3(1), dim3(1024), 0, pl->stream, r, pl->mbox, seq);
+  HIPCHK(hipGetLastError());
+  const auto t0 = std::chrono::steady_clock::now();
+  for (long s = 1;; ++s) {
+    if (__atomic_load_n(&pl->mbox->seq, __ATOMIC_ACQUIRE) == seq) break;
+    if ((s & 1023) == 0 && std::chrono::steady_clock::now() - t0 > std::chrono::milliseconds(2)) {
+      HIPCHK(hipStreamSynchronize(pl->stream));
+      if (__atomic_load_n(&pl->mbox->seq, __ATOMIC_ACQUIRE) != seq) {
+        kfbi_set_error("device values were not posted");
+        return KFBI_E_DEVICE;
+      }
+      break;
+    }
+  }
+  for (int i = 0; i < r.ni; ++i) iout[i] = __atomic_load_n(&pl->mbox->iv[i], __ATOMIC_RELAXED);
+  const int nd = r.nd + (r.nmax > 0 ? 1 : 0);
+  for (int i = 0; i < nd; ++i) {
+    const unsigned long long b = __atomic_load_n(&pl->mbox->dv[i], __ATOMIC_RELAXED);
+    memcpy(&dout[i], &b, 8);
+  }
+  return KFBI_OK;
+}
 
 // ---------------------------------------------------------------- errors
 void kfbi_set_error(const char* fmt, ...) {
@@ -699,9 +769,14 @@ kfbi_status gmres_run(kfbi_plan* pl, double tol, int m, int first_batch, GmresOu
     for (int v = KFBI_NGRAPH - 2; v >= 0; --v)
       if ((B % big) & (1 << v)) HIPCHK(hipGraphLaunch(pl->graph_execs[v], st));
     launched += B;
-    HIPCHK(hipMemcpyAsync(pl->h_ctl, pl->ctl, 4 * sizeof(int), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipMemcpyAsync(pl->h_dpinned, pl->scal, 7 * sizeof(double), hipMemcpyDeviceToHost, st));
-    HIPCHK(hipStreamSynchronize(st));
+    {
+      PostReq q{};
+      q.ni = 4;
+      for (int i = 0; i < 4; ++i) q.isrc[i] = pl->ctl + i;
+      q.nd = 7;
+      for (int i = 0; i < 7; ++i) q.dsrc[i] = pl->scal + i;
+      KCHK(kfbi_post_wait(pl, q, pl->h_ctl, pl->h_dpinned));
+    }
     if (first) {
       nb = pl->h_dpinned[1];
       res_prev = pl->h_dpinned[6];
@@ -730,9 +805,11 @@ kfbi_status true_residual(kfbi_plan* pl, const double* psi, double* tr) {
   hipStream_t st = pl->stream;
   matvec_impl(pl, psi, pl->work2);
   gm_true_residual(pl, pl->bvec, pl->work2, pl->scal + 4);
-  HIPCHK(hipMemcpyAsync(pl->h_dpinned + 4, pl->scal + 4, 2 * sizeof(double), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
-  HIPCHK(hipGetLastError());
+  PostReq q{};
+  q.nd = 2;
+  q.dsrc[0] = pl->scal + 4;
+  q.dsrc[1] = pl->scal + 5;
+  KCHK(kfbi_post_wait(pl, q, nullptr, pl->h_dpinned + 4));
   *tr = pl->h_dpinned[5] > 0.0 ? sqrt(pl->h_dpinned[4] / pl->h_dpinned[5]) : 0.0;
   return KFBI_OK;
 }

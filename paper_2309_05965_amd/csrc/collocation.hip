@@ -322,15 +322,16 @@ kfbi_status colloc_factor(kfbi_plan* pl) {
       return KFBI_E_INVALID;
   }
   HIPCHK(hipGetLastError());
-  // flags and condition numbers in one host wait; the largest condition
-  // number is a host reduction of a small array
-  std::vector<double> cond((size_t)pl->n_dof);
-  HIPCHK(hipMemcpyAsync(pl->h_pinned + 1, pl->d_flags, sizeof(int), hipMemcpyDeviceToHost, pl->stream));
-  HIPCHK(hipMemcpyAsync(cond.data(), pl->cond, sizeof(double) * pl->n_dof, hipMemcpyDeviceToHost, pl->stream));
-  HIPCHK(hipStreamSynchronize(pl->stream));
+  // flags and the largest condition number (a NaN wins) in one host wait
+  PostReq q{};
+  q.ni = 1;
+  q.isrc[0] = pl->d_flags;
+  q.maxsrc = pl->cond;
+  q.nmax = pl->n_dof;
+  int fl = 0;
   double cm = 0.0;
-  for (double v : cond) cm = v > cm || v != v ? v : cm;
+  KCHK(kfbi_post_wait(pl, q, &fl, &cm));
   pl->cond_max = cm;
-  if (pl->h_pinned[1]) return kfbi_flags_status(pl->h_pinned[1]);
+  if (fl) return kfbi_flags_status(fl);
   return KFBI_OK;
 }

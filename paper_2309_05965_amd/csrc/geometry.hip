@@ -1193,37 +1193,46 @@ inline int64_t headroom(int64_t n) { return n + n / 4 + 64; }
 
 kfbi_status ensure_blk(kfbi_plan* pl, int64_t nb) { return grow(&pl->blk, &pl->cap_blk, nb + 1); }
 
+// the scanned total (and, if flags is given, the status flags) to the host
+kfbi_status post_count(kfbi_plan* pl, int64_t* count, int* flags) {
+  PostReq q{};
+  q.ni = flags ? 2 : 1;
+  q.isrc[0] = pl->blk_total;
+  q.isrc[1] = pl->d_flags;
+  int v[2] = {0, 0};
+  KCHK(kfbi_post_wait(pl, q, v, nullptr));
+  *count = v[0];
+  if (flags) *flags = v[1];
+  return KFBI_OK;
+}
+
 template <class Pred>
-kfbi_status compact_count(kfbi_plan* pl, int64_t n, Pred pred, int64_t* count) {
+kfbi_status compact_count(kfbi_plan* pl, int64_t n, Pred pred, int64_t* count, int* flags = nullptr) {
   int64_t nb = (n + CMP_CH - 1) / CMP_CH;
   if (nb == 0) {
     *count = 0;
+    if (flags) *flags = 0;
     return KFBI_OK;
   }
   KCHK(ensure_blk(pl, nb));
   hipLaunchKernelGGL(k_count<Pred>, dim3((unsigned)nb), dim3(KFBI_BLOCK), 0, pl->stream, n, pred, pl->blk);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, pl->stream, pl->blk, nb, pl->blk_total);
-  HIPCHK(hipMemcpyAsync(pl->h_pinned, pl->blk_total, sizeof(int), hipMemcpyDeviceToHost, pl->stream));
-  HIPCHK(hipStreamSynchronize(pl->stream));
-  *count = pl->h_pinned[0];
-  return KFBI_OK;
+  return post_count(pl, count, flags);
 }
 
 template <class Pred>
-kfbi_status compact_count_flags(kfbi_plan* pl, int64_t n, Pred pred, int64_t* count) {
+kfbi_status compact_count_flags(kfbi_plan* pl, int64_t n, Pred pred, int64_t* count, int* flags = nullptr) {
   int64_t nb = (n + CMP_CH - 1) / CMP_CH;
   if (nb == 0) {
     *count = 0;
+    if (flags) *flags = 0;
     return KFBI_OK;
   }
   KCHK(ensure_blk(pl, nb));
   hipLaunchKernelGGL(k_count_flags<Pred>, dim3((unsigned)nb), dim3(KFBI_BLOCK), 0, pl->stream, n, pred, pl->blk,
                      pl->flags8);
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, pl->stream, pl->blk, nb, pl->blk_total);
-  HIPCHK(hipMemcpyAsync(pl->h_pinned, pl->blk_total, sizeof(int), hipMemcpyDeviceToHost, pl->stream));
-  HIPCHK(hipStreamSynchronize(pl->stream));
-  *count = pl->h_pinned[0];
-  return KFBI_OK;
+  return post_count(pl, count, flags);
 }
 
 template <class Pred, class Emit>
@@ -1323,14 +1332,13 @@ kfbi_status geo_setup(kfbi_plan* pl) {
                      RegionArgs{g, L, pl->region, pl->d_flags});
   // the region flags travel with the first compaction count (one host
   // wait); the candidate count reads the regions only
-  HIPCHK(hipMemcpyAsync(pl->h_pinned + 1, pl->d_flags, sizeof(int), hipMemcpyDeviceToHost, st));
-
   // candidates: (segment, interface) items with a sign change
   int64_t n_items = pl->n_seg * g.K;
   CandPred cp{g, pl->region};
   int64_t nc;
-  KCHK(compact_count_flags(pl, n_items, cp, &nc));
-  if (pl->h_pinned[1]) return kfbi_flags_status(pl->h_pinned[1]);
+  int rflags = 0;
+  KCHK(compact_count_flags(pl, n_items, cp, &nc, &rflags));
+  if (rflags) return kfbi_flags_status(rflags);
   if (nc == 0) {
     kfbi_set_error("no grid segment crosses an interface");
     return KFBI_E_INVALID;
@@ -1483,10 +1491,13 @@ kfbi_status geo_setup(kfbi_plan* pl) {
     hipLaunchKernelGGL(k_owner, dim3(nblk(ne * OWG)), dim3(KFBI_BLOCK), 0, st,
                        OwnerArgs{g, ne, pl->ncell_axis, pl->ncell, pl->ce_k, pl->ce_node, pl->d2s, pl->s_pos,
                                  pl->cell_start, pl->cell_count, pl->cell_items, pl->ce_owner, pl->d_flags});
-  HIPCHK(hipMemcpyAsync(pl->h_pinned + 1, pl->d_flags, sizeof(int), hipMemcpyDeviceToHost, st));
-  HIPCHK(hipStreamSynchronize(st));
   HIPCHK(hipGetLastError());
-  if (pl->h_pinned[1]) return kfbi_flags_status(pl->h_pinned[1]);
+  PostReq q{};
+  q.ni = 1;
+  q.isrc[0] = pl->d_flags;
+  int fl = 0;
+  KCHK(kfbi_post_wait(pl, q, &fl, nullptr));
+  if (fl) return kfbi_flags_status(fl);
   return KFBI_OK;
 }
 

@@ -38,6 +38,25 @@ struct GridDesc {           // plain-value grid/problem description for kernels
   int64_t n_nodes;
 };
 
+// Pinned host block that the device posts small results into (k_post): the
+// values, then the sequence word with a system-scope release store.
+struct KfbiMailbox {
+  unsigned seq;
+  int iv[8];
+  unsigned long long dv[9];      // bit patterns of doubles
+};
+
+// What k_post copies: up to 8 ints and 8 doubles from device memory and,
+// if nmax > 0, the maximum of maxsrc[0..nmax) (a NaN wins) as double nd.
+struct PostReq {
+  const int* isrc[8];
+  int ni;
+  const double* dsrc[8];
+  int nd;
+  const double* maxsrc;
+  int64_t nmax;
+};
+
 struct kfbi_plan {
   kfbi_problem prob;
   GridDesc g;
@@ -148,6 +167,8 @@ struct kfbi_plan {
   hipGraphExec_t graph_execs[KFBI_NGRAPH];  // graph g runs 2^g iterations
   uint64_t graph_key[20];
   int* h_ctl;
+  KfbiMailbox* mbox;             // pinned; see kfbi_post_wait
+  unsigned mseq;
   // box-solve event timing
   int prof_on;
   std::vector<hipEvent_t>* prof_ev;
@@ -172,6 +193,13 @@ kfbi_status kfbi_flags_status(int flags);
   } while (0)
 
 // ---------------------------------------------------------------- launchers
+// api.hip: enqueue k_post on the plan's stream and wait for its values by
+// spinning on the pinned sequence word (a few microseconds sooner than a
+// device-to-host copy and a stream synchronisation); after 2 ms of spinning
+// it falls back to a stream synchronisation, which also reports a device
+// error.  iout / dout receive r.ni ints and r.nd (+1 with a maximum) doubles.
+kfbi_status kfbi_post_wait(kfbi_plan* pl, const PostReq& r, int* iout, double* dout);
+
 // geometry.hip (step S0)
 kfbi_status geo_setup(kfbi_plan* pl);
 // collocation.hip (step S1)
