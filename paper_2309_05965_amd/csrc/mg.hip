@@ -41,7 +41,44 @@ struct Lev {
   T c[27];           // A_l on the 3^d cube, index (o0+1) + 3 (o1+1) + 9 (o2+1)
   T coef;            // omega_l / a_l
   T inva;            // 1 / a_l
+  int star;          // only the centre and axis neighbours are nonzero (2nd order)
 };
+
+// sum of c[q] val(o) over the 3^D cube (index q = (o0+1) + 3 (o1+1) + 9 (o2+1),
+// 2D on the o2 = 0 plane) in the order of q; with star only the centre and
+// axis terms, which are the nonzero ones then.  No data-dependent branch:
+// a skipped zero coefficient adds +0, so the full form equals the sum
+// over the nonzero terms for finite values.
+template <int D, typename S, typename F>
+__device__ __forceinline__ S stencil_sum(const S* c, bool star, F val) {
+  S s = 0;
+  if (star) {
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+      const int o0 = q % 3 - 1, o1 = (q / 3) % 3 - 1, o2 = q / 9 - 1;
+      if (D == 2 && o2 != 0) continue;
+      if ((o0 != 0) + (o1 != 0) + (o2 != 0) > 1) continue;
+      s += c[q] * val(o0, o1, o2);
+    }
+  } else {
+#pragma unroll
+    for (int q = 0; q < 27; ++q) {
+      const int o0 = q % 3 - 1, o1 = (q / 3) % 3 - 1, o2 = q / 9 - 1;
+      if (D == 2 && o2 != 0) continue;
+      s += c[q] * val(o0, o1, o2);
+    }
+  }
+  return s;
+}
+
+// star test of a 27-entry stencil (host)
+inline int stencil_is_star(const double* c) {
+  for (int q = 0; q < 27; ++q) {
+    const int o0 = q % 3 - 1, o1 = (q / 3) % 3 - 1, o2 = q / 9 - 1;
+    if ((o0 != 0) + (o1 != 0) + (o2 != 0) > 1 && c[q] != 0.0) return 0;
+  }
+  return 1;
+}
 
 template <typename T>
 struct Hier {
@@ -83,33 +120,6 @@ __device__ __forceinline__ void node_ijk(int d, int64_t t64, int N, int& i, int&
   const unsigned q = r / m;
   j = (int)(r - q * m + 1);
   k = (int)(q + 1);
-}
-
-template <typename T, typename S>
-__device__ __forceinline__ S apply_A(const S* c, int d, int n1, const T* u, int64_t idx) {
-  S s = 0;
-  const int zr = d == 3 ? 1 : 0;
-  for (int o2 = -zr; o2 <= zr; ++o2)
-    for (int o1 = -1; o1 <= 1; ++o1)
-      for (int o0 = -1; o0 <= 1; ++o0) {
-        const S cf = c[(o0 + 1) + 3 * (o1 + 1) + 9 * (o2 + 1)];
-        if (cf != (S)0) s += cf * (S)u[idx + o0 + (int64_t)n1 * (o1 + (int64_t)n1 * o2)];
-      }
-  return s;
-}
-
-// per-node operations shared by the global-memory and the in-LDS cycle
-template <typename T>
-__device__ __forceinline__ void op_smooth(const Lev<T>& L, const T* uin, const T* f, T* uout, int64_t idx) {
-  if (uin)
-    uout[idx] = uin[idx] + L.coef * (f[idx] - apply_A<T, T>(L.c, L.d, L.n1, uin, idx));
-  else
-    uout[idx] = L.coef * f[idx];
-}
-
-template <typename T>
-__device__ __forceinline__ void op_resid(const Lev<T>& L, const T* u, const T* f, T* r, int64_t idx) {
-  r[idx] = f[idx] - apply_A<T, T>(L.c, L.d, L.n1, u, idx);
 }
 
 // coarse value at coarse interior node I from the fine residual r
@@ -167,6 +177,7 @@ struct SweepArgs {
   int N, n1, KZ;
   TS c[27];
   TS coef;           // omega / a
+  int star;          // only centre and axis coefficients nonzero
   const TS* s;       // stencil input (u, or f for SW_SMOOTH2, or v for SW_OUTER)
   const TS* f;       // right-hand side (F for SW_OUTER)
   TO* out;
@@ -261,26 +272,9 @@ __global__ void __launch_bounds__(256) k_sweep(Ctl ctl, SweepArgs<TS, TO> a) {
       }
       if (own) {
         const TS* P[3] = {pl[iz % 3], pl[(iz + 1) % 3], pl[(iz + 2) % 3]};
-        TS s = 0;
-        if (D == 3) {
-#pragma unroll
-          for (int o2 = 0; o2 < 3; ++o2)
-#pragma unroll
-            for (int o1 = 0; o1 < 3; ++o1)
-#pragma unroll
-              for (int o0 = 0; o0 < 3; ++o0) {
-                const TS cf = a.c[o0 + 3 * o1 + 9 * o2];
-                if (cf != (TS)0) s += cf * P[o2][cc + (o1 - 1) * TT::PX + (o0 - 1)];
-              }
-        } else {
-#pragma unroll
-          for (int o1 = 0; o1 < 3; ++o1)
-#pragma unroll
-            for (int o0 = 0; o0 < 3; ++o0) {
-              const TS cf = a.c[o0 + 3 * o1 + 9];
-              if (cf != (TS)0) s += cf * P[o1][cc + (o0 - 1)];
-            }
-        }
+        const TS s = stencil_sum<D, TS>(a.c, a.star != 0, [&](int o0, int o1, int o2) {
+          return D == 3 ? P[o2 + 1][cc + o1 * TT::PX + o0] : P[o1 + 1][cc + o0];
+        });
         const int gz = iz + 1;
         const int idx = D == 3 ? (ix + 1) + n1 * ((iy + 1) + n1 * gz) : (ix + 1) + n1 * gz;
         const TS ctr = P[1][cc];
@@ -493,92 +487,141 @@ __global__ void __launch_bounds__(MG_BLOCK) k_prolong(Ctl ctl, Lev<T> Fl, Lev<T>
   }
 }
 
-// levels lc .. L-1 of one V(2,2) cycle in LDS, one workgroup: f_lc in, u_lc out
-template <typename T>
+// levels lc .. L-1 of one V(2,2) cycle in LDS, one workgroup: f_lc in, u_lc out.
+// The dimension is a template parameter, so the stencil loops unroll with
+// 32-bit LDS offsets; each thread keeps the grid indices of its (at most
+// CC_MAX) interior nodes of a level for all the level's operations.  The
+// operations and their order are those of the global-memory cycle.
+constexpr int CC_MAX = 4;
+
+template <typename T, int D>
+__device__ __forceinline__ T lds_apply(const Lev<T>& L, const T* u, int idx) {
+  const int n1 = L.n1;
+  return stencil_sum<D, T>(L.c, L.star != 0, [&](int o0, int o1, int o2) { return u[idx + o0 + n1 * (o1 + n1 * o2)]; });
+}
+
+// grid indices (and coordinates) of this thread's interior nodes of a level
+// with N intervals; -1 marks an empty slot
+template <int D>
+__device__ __forceinline__ void lds_nodes(int N, int n1, int (&idx)[CC_MAX], int (&ci)[CC_MAX][3]) {
+  const unsigned m = (unsigned)(N - 1);
+  const unsigned mt = D == 3 ? m * m * m : m * m;
+#pragma unroll
+  for (int k = 0; k < CC_MAX; ++k) {
+    const unsigned t = threadIdx.x + (unsigned)(k * LDS_BLOCK);
+    idx[k] = -1;
+    ci[k][0] = ci[k][1] = ci[k][2] = 0;
+    if (t < mt) {
+      const unsigned r = t / m;
+      const int i = (int)(t - r * m + 1);
+      int j, kk = 0;
+      if (D == 2) {
+        j = (int)(r + 1);
+      } else {
+        const unsigned q = r / m;
+        j = (int)(r - q * m + 1);
+        kk = (int)(q + 1);
+      }
+      ci[k][0] = i;
+      ci[k][1] = j;
+      ci[k][2] = kk;
+      idx[k] = i + n1 * (j + n1 * kk);
+    }
+  }
+}
+
+template <typename T, int D>
 __global__ void __launch_bounds__(LDS_BLOCK) k_coarse_cycle(Ctl ctl, Hier<T> H, const T* fg, T* ug) {
   if (skip(ctl)) return;
   extern __shared__ unsigned char smem[];
   T* base = reinterpret_cast<T*>(smem);
-  // per level three arrays u, t, f of (N_l+1)^d, packed level after level
-  int64_t loff[KFBI_MG_MAXL];
-  int64_t tot = 0;
+  // per level three arrays u, t, f of (N_l+1)^D, packed level after level
+  int loff[KFBI_MG_MAXL];
+  int tot = 0;
   for (int l = H.lc; l < H.L; ++l) {
-    const int64_t n = H.d == 3 ? (int64_t)H.lv[l].n1 * H.lv[l].n1 * H.lv[l].n1 : (int64_t)H.lv[l].n1 * H.lv[l].n1;
+    const int n1 = H.lv[l].n1;
     loff[l] = tot;
-    tot += 3 * n;
+    tot += 3 * (D == 3 ? n1 * n1 * n1 : n1 * n1);
   }
-  for (int64_t i = threadIdx.x; i < tot; i += blockDim.x) base[i] = (T)0;
-  __syncthreads();
   {
     const Lev<T>& L = H.lv[H.lc];
-    const int64_t n = H.d == 3 ? (int64_t)L.n1 * L.n1 * L.n1 : (int64_t)L.n1 * L.n1;
-    T* f = base + loff[H.lc] + 2 * n;
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) f[i] = fg[L.off + i];
+    const int n = D == 3 ? L.n1 * L.n1 * L.n1 : L.n1 * L.n1;
+    const int f0 = loff[H.lc] + 2 * n;   // f of the first level: loaded, everything else zero
+    for (int i = threadIdx.x; i < tot; i += LDS_BLOCK)
+      base[i] = (i >= f0 && i < f0 + n) ? fg[L.off + (i - f0)] : (T)0;
   }
   __syncthreads();
-  auto arr = [&](int l, int which) -> T* {
-    const Lev<T>& L = H.lv[l];
-    const int64_t n = H.d == 3 ? (int64_t)L.n1 * L.n1 * L.n1 : (int64_t)L.n1 * L.n1;
-    return base + loff[l] + which * n;
-  };
-  auto interior = [&](int l) -> int64_t {
-    const int m = H.lv[l].N - 1;
-    return H.d == 3 ? (int64_t)m * m * m : (int64_t)m * m;
-  };
+  int idx[CC_MAX], ci[CC_MAX][3];
   // descend
   for (int l = H.lc; l < H.L; ++l) {
     const Lev<T>& L = H.lv[l];
-    T *u = arr(l, 0), *tb = arr(l, 1), *f = arr(l, 2);
-    const int64_t m = interior(l);
+    const int n = D == 3 ? L.n1 * L.n1 * L.n1 : L.n1 * L.n1;
+    T *u = base + loff[l], *tb = u + n, *f = u + 2 * n;
     if (L.N == 2) {
-      for (int64_t t = threadIdx.x; t < m; t += blockDim.x) {
-        const int64_t idx = node_of(H.d, L.n1, t, L.N);
-        u[idx] = f[idx] * L.inva;
+      if (threadIdx.x == 0) {
+        const int c = 1 + L.n1 * (1 + (D == 3 ? L.n1 : 0));
+        u[c] = f[c] * L.inva;
       }
       __syncthreads();
       break;
     }
-    for (int64_t t = threadIdx.x; t < m; t += blockDim.x) op_smooth<T>(L, nullptr, f, tb, node_of(H.d, L.n1, t, L.N));
+    lds_nodes<D>(L.N, L.n1, idx, ci);
+#pragma unroll
+    for (int k = 0; k < CC_MAX; ++k)
+      if (idx[k] >= 0) tb[idx[k]] = L.coef * f[idx[k]];
     __syncthreads();
-    for (int64_t t = threadIdx.x; t < m; t += blockDim.x) op_smooth<T>(L, tb, f, u, node_of(H.d, L.n1, t, L.N));
+#pragma unroll
+    for (int k = 0; k < CC_MAX; ++k)
+      if (idx[k] >= 0) {
+        const int x = idx[k];
+        u[x] = tb[x] + L.coef * (f[x] - lds_apply<T, D>(L, tb, x));
+      }
     __syncthreads();
-    for (int64_t t = threadIdx.x; t < m; t += blockDim.x) op_resid<T>(L, u, f, tb, node_of(H.d, L.n1, t, L.N));
+#pragma unroll
+    for (int k = 0; k < CC_MAX; ++k)
+      if (idx[k] >= 0) tb[idx[k]] = f[idx[k]] - lds_apply<T, D>(L, u, idx[k]);
     __syncthreads();
     const Lev<T>& C = H.lv[l + 1];
-    T* fc = arr(l + 1, 2);
-    const int64_t mc = interior(l + 1);
-    for (int64_t t = threadIdx.x; t < mc; t += blockDim.x) {
-      const int64_t idx = node_of(H.d, C.n1, t, C.N);
-      int I0, I1, I2;
-      coords(H.d, C.n1, idx, I0, I1, I2);
-      fc[idx] = op_restrict<T>(H.d, L.n1, tb, I0, I1, I2);
-    }
+    const int nc = D == 3 ? C.n1 * C.n1 * C.n1 : C.n1 * C.n1;
+    T* fc = base + loff[l + 1] + 2 * nc;
+    lds_nodes<D>(C.N, C.n1, idx, ci);
+#pragma unroll
+    for (int k = 0; k < CC_MAX; ++k)
+      if (idx[k] >= 0) fc[idx[k]] = op_restrict<T>(D, L.n1, tb, ci[k][0], ci[k][1], ci[k][2]);
     __syncthreads();
   }
   // ascend
   for (int l = H.L - 2; l >= H.lc; --l) {
     const Lev<T>& L = H.lv[l];
     const Lev<T>& C = H.lv[l + 1];
-    T *u = arr(l, 0), *tb = arr(l, 1), *f = arr(l, 2);
-    const T* ec = arr(l + 1, 0);
-    const int64_t m = interior(l);
-    for (int64_t t = threadIdx.x; t < m; t += blockDim.x) {
-      const int64_t idx = node_of(H.d, L.n1, t, L.N);
-      int i0, i1, i2;
-      coords(H.d, L.n1, idx, i0, i1, i2);
-      u[idx] += op_prolong<T>(H.d, C.n1, ec, i0, i1, i2);
-    }
+    const int n = D == 3 ? L.n1 * L.n1 * L.n1 : L.n1 * L.n1;
+    T *u = base + loff[l], *tb = u + n, *f = u + 2 * n;
+    const T* ec = base + loff[l + 1];
+    lds_nodes<D>(L.N, L.n1, idx, ci);
+#pragma unroll
+    for (int k = 0; k < CC_MAX; ++k)
+      if (idx[k] >= 0) u[idx[k]] += op_prolong<T>(D, C.n1, ec, ci[k][0], ci[k][1], ci[k][2]);
     __syncthreads();
-    for (int64_t t = threadIdx.x; t < m; t += blockDim.x) op_smooth<T>(L, u, f, tb, node_of(H.d, L.n1, t, L.N));
+#pragma unroll
+    for (int k = 0; k < CC_MAX; ++k)
+      if (idx[k] >= 0) {
+        const int x = idx[k];
+        tb[x] = u[x] + L.coef * (f[x] - lds_apply<T, D>(L, u, x));
+      }
     __syncthreads();
-    for (int64_t t = threadIdx.x; t < m; t += blockDim.x) op_smooth<T>(L, tb, f, u, node_of(H.d, L.n1, t, L.N));
+#pragma unroll
+    for (int k = 0; k < CC_MAX; ++k)
+      if (idx[k] >= 0) {
+        const int x = idx[k];
+        u[x] = tb[x] + L.coef * (f[x] - lds_apply<T, D>(L, tb, x));
+      }
     __syncthreads();
   }
   {
     const Lev<T>& L = H.lv[H.lc];
-    const int64_t n = H.d == 3 ? (int64_t)L.n1 * L.n1 * L.n1 : (int64_t)L.n1 * L.n1;
-    const T* u = arr(H.lc, 0);
-    for (int64_t i = threadIdx.x; i < n; i += blockDim.x) ug[L.off + i] = u[i];
+    const int n = D == 3 ? L.n1 * L.n1 * L.n1 : L.n1 * L.n1;
+    const T* u = base + loff[H.lc];
+    for (int i = threadIdx.x; i < n; i += LDS_BLOCK) ug[L.off + i] = u[i];
   }
 }
 
@@ -750,6 +793,7 @@ Hier<T> make_hier(const kfbi_plan* pl) {
     for (int i = 0; i < 27; ++i) L.c[i] = (T)pl->mg_c[l][i];
     L.coef = (T)(pl->mg_w[l] / pl->mg_c[l][13]);   // central coefficient: offset (0,0,0)
     L.inva = (T)(1.0 / pl->mg_c[l][13]);
+    L.star = stencil_is_star(pl->mg_c[l]);
   }
   return H;
 }
@@ -820,7 +864,12 @@ void sweep(kfbi_plan* pl, Ctl ctl, int N, const TS* c27, TS coef, const TS* src,
   SweepArgs<TS, TO> a;
   a.N = N;
   a.n1 = N + 1;
-  for (int i = 0; i < 27; ++i) a.c[i] = c27[i];
+  double cd[27];
+  for (int i = 0; i < 27; ++i) {
+    a.c[i] = c27[i];
+    cd[i] = (double)c27[i];
+  }
+  a.star = stencil_is_star(cd);
   a.coef = coef;
   a.s = src;
   a.f = f;
@@ -857,7 +906,10 @@ void vcycle(kfbi_plan* pl, const Hier<T>& H, Ctl ctl) {
     hipLaunchKernelGGL((k_restrict<T>), dim3(gsblk(interior(l + 1))), dim3(MG_BLOCK), 0, st, ctl, H.lv[l],
                        H.lv[l + 1], (const T*)tb, f);
   }
-  hipLaunchKernelGGL((k_coarse_cycle<T>), dim3(1), dim3(LDS_BLOCK), coarse_lds(H), st, ctl, H, (const T*)f, u);
+  if (H.d == 3)
+    hipLaunchKernelGGL((k_coarse_cycle<T, 3>), dim3(1), dim3(LDS_BLOCK), coarse_lds(H), st, ctl, H, (const T*)f, u);
+  else
+    hipLaunchKernelGGL((k_coarse_cycle<T, 2>), dim3(1), dim3(LDS_BLOCK), coarse_lds(H), st, ctl, H, (const T*)f, u);
   for (int l = H.lc - 1; l >= 0; --l) {
     const Lev<T>& L = H.lv[l];
     const int64_t o = L.off;
@@ -969,7 +1021,8 @@ kfbi_status mg_configure(kfbi_plan* pl, int solver, double eps, int maxit) {
       const size_t n1 = (size_t)n + 1;
       tot += 3 * (g.d == 3 ? n1 * n1 * n1 : n1 * n1);
     }
-    if (tot * es_lds <= MG_LDS_MAX) {
+    const size_t mi = (size_t)(c - 1) * (c - 1) * (g.d == 3 ? (size_t)(c - 1) : 1);
+    if (tot * es_lds <= MG_LDS_MAX && mi <= (size_t)CC_MAX * LDS_BLOCK) {
       cut = c;
       break;
     }
