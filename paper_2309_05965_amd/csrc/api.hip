@@ -337,23 +337,30 @@ void destroy_graphs(kfbi_plan* pl) {
 // Arnoldi step),
 // captured on the private stream; every kernel reads j and the stop flag
 // from the device control word.  Rebuilt when buffers or sizes change.
+// graphs of 1, 2, .. 2^(n-1) iterations: all of them for the FFT box solver
+// (an iteration takes tens of microseconds, so launch gaps count); one for
+// multigrid, whose iterations run hundreds of kernels (the gaps do not
+// count, and large graphs are slow to capture and instantiate)
+int graph_count(const kfbi_plan* pl) { return pl->box_solver == KFBI_BOX_FFT ? KFBI_NGRAPH : 1; }
+
 kfbi_status ensure_graph(kfbi_plan* pl) {
   uint64_t bi, bo, ka;
   memcpy(&bi, &pl->g.beta_in, 8);
   memcpy(&bo, &pl->g.beta_out, 8);
   memcpy(&ka, &pl->g.kappa, 8);
-  uint64_t key[20] = {bi, bo, ka, (uint64_t)pl->box_solver * 1000003u + (uint64_t)pl->mg_maxit,(uint64_t)pl->n_dof, (uint64_t)pl->n_surf, (uint64_t)pl->n_corr, (uint64_t)pl->n_irr,
+  uint64_t key[20] = {bi, bo, ka, (uint64_t)pl->box_solver * 1000003u + (uint64_t)(pl->mg_run_cap > 0 ? pl->mg_run_cap : pl->mg_maxit),(uint64_t)pl->n_dof, (uint64_t)pl->n_surf, (uint64_t)pl->n_corr, (uint64_t)pl->n_irr,
                       (uint64_t)(uintptr_t)pl->V, (uint64_t)(uintptr_t)pl->psiS, (uint64_t)(uintptr_t)pl->Cg,
                       (uint64_t)(uintptr_t)pl->FI, (uint64_t)(uintptr_t)pl->IW, (uint64_t)(uintptr_t)pl->stN,
                       (uint64_t)(uintptr_t)pl->ext_idx, (uint64_t)(uintptr_t)pl->irr,
                       (uint64_t)(uintptr_t)pl->ce_node, (uint64_t)pl->gm_cap, (uint64_t)(uintptr_t)pl->d2s,
                       (uint64_t)(uintptr_t)pl->PA ^ (uint64_t)(uintptr_t)pl->GI ^ (uint64_t)(uintptr_t)pl->mg_u};
-  if (pl->graph_execs[KFBI_NGRAPH - 1] && memcmp(key, pl->graph_key, sizeof(key)) == 0) return KFBI_OK;
+  const int ng = graph_count(pl);
+  if (pl->graph_execs[ng - 1] && memcmp(key, pl->graph_key, sizeof(key)) == 0) return KFBI_OK;
   destroy_graphs(pl);
   std::unique_lock<std::shared_mutex> lock(kfbi_capture_mutex);
   // every graph launch costs a few microseconds of idle time at its
   // boundaries, so a batch is sent as few graphs as its binary digits
-  for (int v = 0; v < KFBI_NGRAPH; ++v) {
+  for (int v = 0; v < ng; ++v) {
     const int iters = 1 << v;
     HIPCHK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
     pl->ctl_active = pl->ctl;
@@ -764,9 +771,10 @@ kfbi_status gmres_run(kfbi_plan* pl, double tol, int m, int first_batch, GmresOu
   bool first = true;
   for (;;) {
     const int B = batch < m - launched ? batch : m - launched;
-    const int big = 1 << (KFBI_NGRAPH - 1);
-    for (int b = 0; b + big <= B; b += big) HIPCHK(hipGraphLaunch(pl->graph_execs[KFBI_NGRAPH - 1], st));
-    for (int v = KFBI_NGRAPH - 2; v >= 0; --v)
+    const int ng = graph_count(pl);
+    const int big = 1 << (ng - 1);
+    for (int b = 0; b + big <= B; b += big) HIPCHK(hipGraphLaunch(pl->graph_execs[ng - 1], st));
+    for (int v = ng - 2; v >= 0; --v)
       if ((B % big) & (1 << v)) HIPCHK(hipGraphLaunch(pl->graph_execs[v], st));
     launched += B;
     {
@@ -809,7 +817,12 @@ kfbi_status true_residual(kfbi_plan* pl, const double* psi, double* tr) {
   q.nd = 2;
   q.dsrc[0] = pl->scal + 4;
   q.dsrc[1] = pl->scal + 5;
-  KCHK(kfbi_post_wait(pl, q, nullptr, pl->h_dpinned + 4));
+  if (pl->box_solver != KFBI_BOX_FFT) {
+    q.ni = 2;
+    q.isrc[0] = pl->mg_ctl + 2;
+    q.isrc[1] = pl->mg_ctl + 3;
+  }
+  KCHK(kfbi_post_wait(pl, q, pl->h_pinned + 2, pl->h_dpinned + 4));
   *tr = pl->h_dpinned[5] > 0.0 ? sqrt(pl->h_dpinned[4] / pl->h_dpinned[5]) : 0.0;
   return KFBI_OK;
 }
@@ -823,8 +836,39 @@ kfbi_status set_relax_word(kfbi_plan* pl, double r) {
   return KFBI_OK;
 }
 
+kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* opts, double* psi, double* u_out,
+                        kfbi_info* info, int m, double tol);
+
 kfbi_status solve_body(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* opts, double* psi, double* u_out,
                        kfbi_info* info, int m, double tol) {
+  // Multigrid box solves inside a solve run at most mg_cap_eff corrections:
+  // the captured iterations enqueue every correction up to the cap and the
+  // ones after convergence return at once, each still costing a launch.
+  // The cap is the most corrections any box solve of the previous solve
+  // needed plus 2 (the count hardly varies with the right-hand side); a
+  // box solve stopped by it above its tolerance restores the configured
+  // cap for the next solves.
+  const bool mg = pl->box_solver != KFBI_BOX_FFT;
+  if (mg) {
+    pl->mg_run_cap = pl->mg_cap_eff > 0 ? pl->mg_cap_eff : pl->mg_maxit;
+    HIPCHK(hipMemsetAsync(pl->mg_ctl + 2, 0, 2 * sizeof(int), pl->stream));
+  }
+  kfbi_status s = solve_steps(pl, data, opts, psi, u_out, info, m, tol);
+  if (mg) {
+    if (s == KFBI_OK || s == KFBI_E_NOT_CONVERGED) {
+      const int most = pl->h_pinned[2], hit = pl->h_pinned[3];
+      if (hit > 0)
+        pl->mg_cap_eff = pl->mg_maxit;
+      else if (most > 0)
+        pl->mg_cap_eff = most + 2 < pl->mg_maxit ? most + 2 : pl->mg_maxit;
+    }
+    pl->mg_run_cap = 0;
+  }
+  return s;
+}
+
+kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* opts, double* psi, double* u_out,
+                        kfbi_info* info, int m, double tol) {
   // Step 1: right-hand side
   simple_solve_impl(pl, data->g1, nullptr, data->ftilde, data->fhat, data->gB, pl->vsbuf, pl->dn_in, pl->dn_out);
   op_bie_rhs(pl, data->g2, pl->dn_in, pl->dn_out, pl->bvec);

@@ -152,7 +152,10 @@ struct kfbi_plan {
   void *mg_u, *mg_t, *mg_f;      // level arrays (float or double), boundaries zero
   int64_t mg_bytes;
   double* mg_part;               // partial sums of the outer residual
-  int* mg_ctl;                   // [done, corrections]
+  int* mg_ctl;                   // [done, corrections, most corrections since the solve began,
+                                 //  box solves stopped by the cap above eps]
+  int mg_cap_eff;                // cap used inside kfbi_solve: observed need + 2 (0: unknown)
+  int mg_run_cap;                // cap of the box solves being enqueued (0: mg_maxit)
   double mg_relax;               // inexact-Krylov relaxation of eps inside GMRES (0: off)
   double relax_word;             // host copy of the factor last written to GMRES scal[7] (NaN: none)
   double* mg_scal;               // [|F|, last relative residual]

@@ -710,7 +710,12 @@ __global__ void __launch_bounds__(MG_BLOCK) k_check(Ctl ctl, const double* part,
     const double nf = scal[0];
     const double rel = nf > 0.0 ? nr / nf : 0.0;
     scal[1] = rel;
-    if (rel <= eps || nf == 0.0 || ctl.mctl[1] >= maxit) ctl.mctl[0] = 1;
+    const bool conv = rel <= eps || nf == 0.0;
+    if (conv || ctl.mctl[1] >= maxit) {
+      ctl.mctl[0] = 1;
+      if (ctl.mctl[1] > ctl.mctl[2]) ctl.mctl[2] = ctl.mctl[1];
+      if (!conv) ctl.mctl[3] += 1;
+    }
   }
 }
 
@@ -945,14 +950,15 @@ void solve_t(kfbi_plan* pl, const double* F, double* v) {
     hipLaunchKernelGGL(k_zero_boundary, dim3(nblk(nb)), dim3(MG_BLOCK), 0, st, ctl, g.d, g.n1, v);
   }
   T* f0 = (T*)pl->mg_f;
-  for (int it = 0; it < pl->mg_maxit; ++it) {
+  const int cap = pl->mg_run_cap > 0 ? pl->mg_run_cap : pl->mg_maxit;
+  for (int it = 0; it < cap; ++it) {
     int nb_part = (int)gout;
     if (it == 0)
       hipLaunchKernelGGL((k_outer_resid<T>), dim3(gout), dim3(MG_BLOCK), 0, st, oa, f0);
     else
       sweep<double, T, SW_OUTER>(pl, ctl, g.N, pl->mg_c[0], 0.0, v, F, f0, &nb_part);
     hipLaunchKernelGGL(k_check, dim3(1), dim3(MG_BLOCK), 0, st, ctl, (const double*)pl->mg_part, nb_part,
-                       it == 0 ? 1 : 0, pl->mg_eps, pl->mg_maxit, pl->mg_scal, (const double*)pl->scal);
+                       it == 0 ? 1 : 0, pl->mg_eps, cap, pl->mg_scal, (const double*)pl->scal);
     vcycle<T>(pl, H, ctl);
     hipLaunchKernelGGL((k_update<T>), dim3(gsblk(m)), dim3(MG_BLOCK), 0, st, ctl, g.d, g.N, g.n1,
                        (const T*)pl->mg_u, v);
@@ -961,7 +967,7 @@ void solve_t(kfbi_plan* pl, const double* F, double* v) {
   int nb_part = 0;
   sweep<double, T, SW_OUTER>(pl, ctl, g.N, pl->mg_c[0], 0.0, v, F, f0, &nb_part);
   hipLaunchKernelGGL(k_check, dim3(1), dim3(MG_BLOCK), 0, st, ctl, (const double*)pl->mg_part, nb_part, 0,
-                     pl->mg_eps, pl->mg_maxit, pl->mg_scal, (const double*)pl->scal);
+                     pl->mg_eps, cap, pl->mg_scal, (const double*)pl->scal);
 }
 
 double jacobi_weight(const double* c, int d) {
@@ -1001,6 +1007,8 @@ kfbi_status mg_configure(kfbi_plan* pl, int solver, double eps, int maxit) {
   pl->box_solver = solver;
   pl->mg_eps = eps;
   pl->mg_maxit = maxit;
+  pl->mg_cap_eff = 0;
+  pl->mg_run_cap = 0;
   if (solver == KFBI_BOX_FFT) return KFBI_OK;
   const GridDesc& g = pl->g;
   int L = 0;

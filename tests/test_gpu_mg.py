@@ -163,3 +163,36 @@ def test_relaxed_inner_tolerance(case):
     assert i2["iters"] == i0["iters"]
     with pytest.raises(kfbi.KfbiError):
         gp.set_box_relaxation(-1.0)
+
+
+@pytest.mark.parametrize("case", ["c2_128", "sphere_32"])
+def test_adaptive_cycle_cap(case):
+    """Inside kfbi_solve the defect-correction loop is enqueued up to the
+    most corrections the previous solve needed plus 2, not the configured
+    maximum.  Converged box solves do the same corrections under either
+    cap, so the second solve (adapted cap) equals the first (configured cap
+    40) bit for bit; a cap that stops the box solves above their tolerance
+    still gives a finished solve, after which the configured cap is used
+    again and the original result comes back."""
+    from paper_2309_05965_amd import kfbi
+    if case == "c2_128":
+        prob, sol = W.config2(128)
+    else:
+        prob, sol = (W.problem(3, 4, 32, -1.0, 1.0, 1.0, 5.0, 0.5, [W.sphere3d(0.03, -0.02, 0.01, 0.52)]),
+                     {0: W.f_exp3, 1: W.f_sin3})
+    gp = kfbi.Plan(prob)
+    data = kfbi.device_data(gp, prob, sol)
+    gp.set_box_solver("mg32", eps_in=1e-10, max_cycles=40)
+    p0, u0, i0 = gp.solve(data, tol=1e-8)
+    p1, u1, i1 = gp.solve(data, tol=1e-8)
+    p2, u2, i2 = gp.solve(data, tol=1e-8)
+    assert i0["status"] == 0 and i0["iters"] == i1["iters"] == i2["iters"]
+    assert torch.equal(p0, p1) and torch.equal(u0, u1) and torch.equal(p0, p2)
+    # a cap of 3 corrections stops every full-accuracy box solve early
+    gp.set_box_solver("mg32", eps_in=1e-10, max_cycles=3)
+    _, _, i3 = gp.solve(data, tol=1e-8, raise_on_fail=False)
+    assert i3["iters"] >= 1
+    gp.set_box_solver("mg32", eps_in=1e-10, max_cycles=40)
+    p4, u4, _ = gp.solve(data, tol=1e-8)
+    p5, u5, _ = gp.solve(data, tol=1e-8)
+    assert torch.equal(p4, p0) and torch.equal(p5, p0) and torch.equal(u5, u0)
