@@ -103,10 +103,13 @@ def forms_config5(tol, reps, n_problems=4):
     """The ellipsoid workload of the learned start (128^3, beta 1/100) on
     held-out seeds, solves/s with set-up and prediction inside the timed
     solve.  Plain FP64: FP64 multigrid to 1e-12, zero start.  Mixed +
-    learned: FP32 multigrid in FP64 defect correction to 1e-10, the inner
-    tolerance relaxed inside GMRES (relax 0.1, inexact Krylov), learned
-    start.  The other forms separate the three ingredients; the FFT forms
-    use the paper's exact box solve."""
+    learned: FP32 multigrid in FP64 defect correction to tol / 10, the inner
+    tolerance relaxed inside GMRES (relax 0.1, inexact Krylov; the true
+    residual of a full-accuracy matvec is checked and a continuation pass
+    takes over if it misses tol), learned start.  The other forms separate
+    the ingredients (eps_in 1e-10 is the stricter setting); the FFT
+    forms use the paper's exact box solve.  Two untimed passes first: the
+    multigrid cycle cap adapts after a plan's first solve."""
     import torch
     from paper_2309_05965_amd import kfbi, learned, warmstart
     from paper_2309_05965_amd import workloads as W
@@ -125,9 +128,10 @@ def forms_config5(tol, reps, n_problems=4):
     res, iters, tres = {}, {}, {}
     for name, solver, eps, relax, learned_start in (
             ("fp64_mg_zero_start", "mg64", 1e-12, 0.0, False),
-            ("fp32_mg_relaxed_learned_start", "mg32", 1e-10, 0.1, True),
-            ("fp32_mg_relaxed_zero_start", "mg32", 1e-10, 0.1, False),
-            ("fp64_mg_relaxed_zero_start", "mg64", 1e-12, 0.1, False),
+            ("fp32_mg_relaxed_learned_start", "mg32", 0.1 * tol, 0.1, True),
+            ("fp32_mg_relaxed_zero_start", "mg32", 0.1 * tol, 0.1, False),
+            ("fp64_mg_relaxed_zero_start", "mg64", 0.1 * tol, 0.1, False),
+            ("fp32_mg_relaxed_eps1e-10_learned_start", "mg32", 1e-10, 0.1, True),
             ("fp32_mg_learned_start", "mg32", 1e-10, 0.0, True),
             ("fp64_fft_zero_start", "fft", 0.0, 0.0, False),
             ("fp64_fft_learned_start", "fft", 0.0, 0.0, True)):
@@ -145,6 +149,7 @@ def forms_config5(tol, reps, n_problems=4):
         for prob, geom, jmp, pl, d in probs:
             pl.set_box_solver(solver, eps_in=eps if eps > 0 else 1e-12, max_cycles=16)
             pl.set_box_relaxation(relax)
+        run()
         run()
         torch.cuda.synchronize()
         t0 = time.perf_counter()

@@ -129,9 +129,11 @@ def test_kfbi_solve_with_fp32_multigrid(case):
 
 
 @pytest.mark.parametrize("case", ["c2_128", "sphere_32"])
-def test_relaxed_inner_tolerance(case):
+@pytest.mark.parametrize("eps,relax", [(1e-10, 0.1), (1e-9, 0.1)])
+def test_relaxed_inner_tolerance(case, eps, relax):
     """Inexact Krylov: with the multigrid tolerance relaxed inside GMRES
-    (relax 0.1) the solve still meets the GMRES tolerance in the true
+    (relax 0.1 with eps_in 1e-10, or with eps_in = tol / 10) the
+    solve still meets the GMRES tolerance in the true
     residual of a fresh full-accuracy matvec (a continuation pass without
     relaxation takes over when the relaxed iterations stop short of it;
     the high-contrast star needs it), with at most a few more iterations
@@ -147,7 +149,8 @@ def test_relaxed_inner_tolerance(case):
     data = kfbi.device_data(gp, prob, sol)
     gp.set_box_solver("mg32", eps_in=1e-10, max_cycles=40)
     _, u0, i0 = gp.solve(data, tol=1e-8)
-    gp.set_box_relaxation(0.1)
+    gp.set_box_solver("mg32", eps_in=eps, max_cycles=40)
+    gp.set_box_relaxation(relax)
     _, u1, i1 = gp.solve(data, tol=1e-8)
     print("%s: iters %d -> %d, true residual %.2e -> %.2e" % (case, i0["iters"], i1["iters"],
                                                                 i0["true_rel_res"], i1["true_rel_res"]))
@@ -158,6 +161,7 @@ def test_relaxed_inner_tolerance(case):
     err1 = np.max(np.abs(u1.cpu().numpy() - ue.ravel()))
     print("  error against the exact solution %.3e -> %.3e" % (err0, err1))
     assert err1 <= 1.1 * err0             # discretisation error unchanged
+    gp.set_box_solver("mg32", eps_in=1e-10, max_cycles=40)
     gp.set_box_relaxation(0.0)
     _, _, i2 = gp.solve(data, tol=1e-8)
     assert i2["iters"] == i0["iters"]
