@@ -220,7 +220,7 @@ kfbi_status alloc_fixed(kfbi_plan* pl) {
   KCHK(dalloc(&pl->T1, n));
   KCHK(dalloc(&pl->T2, n));
   KCHK(dalloc(&pl->vbuf, n));
-  HIPCHK(hipMemset(pl->vbuf, 0, sizeof(double) * n));   // box boundary: never written again
+  HIPCHK(hipMemsetAsync(pl->vbuf, 0, sizeof(double) * n, pl->stream));   // box boundary: never written again
   KCHK(dalloc(&pl->vsbuf, n));
   KCHK(dalloc(&pl->flags8, pl->n_seg * g.K > n ? pl->n_seg * g.K : n));
   KCHK(dalloc(&pl->EI, (int64_t)g.K * n));
@@ -337,11 +337,17 @@ void destroy_graphs(kfbi_plan* pl) {
 // Arnoldi step),
 // captured on the private stream; every kernel reads j and the stop flag
 // from the device control word.  Rebuilt when buffers or sizes change.
-// graphs of 1, 2, .. 2^(n-1) iterations: all of them for the FFT box solver
-// (an iteration takes tens of microseconds, so launch gaps count); one for
-// multigrid, whose iterations run hundreds of kernels (the gaps do not
-// count, and large graphs are slow to capture and instantiate)
-int graph_count(const kfbi_plan* pl) { return pl->box_solver == KFBI_BOX_FFT ? KFBI_NGRAPH : 1; }
+// Graph v runs 2^v iterations.  Each graph launch costs a few microseconds
+// of idle time at its boundaries, so a batch is sent as few graphs as
+// possible, but capturing and instantiating a graph costs about as much as
+// launching its kernels, so a graph set is only worth it when the key is
+// reused: the first solve with a key captures the graphs of 1 and 4
+// iterations, later solves all (FFT box solver).  Multigrid iterations run
+// hundreds of kernels, so the gaps do not count: one graph of 1 iteration.
+bool graph_wanted(const kfbi_plan* pl, int v) {
+  if (pl->box_solver != KFBI_BOX_FFT) return v == 0;
+  return pl->graph_uses > 0 || v == 0 || v == 2;
+}
 
 kfbi_status ensure_graph(kfbi_plan* pl) {
   uint64_t bi, bo, ka;
@@ -354,13 +360,21 @@ kfbi_status ensure_graph(kfbi_plan* pl) {
                       (uint64_t)(uintptr_t)pl->ext_idx, (uint64_t)(uintptr_t)pl->irr,
                       (uint64_t)(uintptr_t)pl->ce_node, (uint64_t)pl->gm_cap, (uint64_t)(uintptr_t)pl->d2s,
                       (uint64_t)(uintptr_t)pl->PA ^ (uint64_t)(uintptr_t)pl->GI ^ (uint64_t)(uintptr_t)pl->mg_u};
-  const int ng = graph_count(pl);
-  if (pl->graph_execs[ng - 1] && memcmp(key, pl->graph_key, sizeof(key)) == 0) return KFBI_OK;
-  destroy_graphs(pl);
+  if (!pl->graph_execs[0] || memcmp(key, pl->graph_key, sizeof(key)) != 0) {
+    destroy_graphs(pl);
+    pl->graph_uses = 0;
+    memcpy(pl->graph_key, key, sizeof(key));
+  }
+  bool want[KFBI_NGRAPH], missing = false;
+  for (int v = 0; v < KFBI_NGRAPH; ++v) {
+    want[v] = graph_wanted(pl, v) && !pl->graph_execs[v];
+    missing = missing || want[v];
+  }
+  ++pl->graph_uses;
+  if (!missing) return KFBI_OK;
   std::unique_lock<std::shared_mutex> lock(kfbi_capture_mutex);
-  // every graph launch costs a few microseconds of idle time at its
-  // boundaries, so a batch is sent as few graphs as its binary digits
-  for (int v = 0; v < ng; ++v) {
+  for (int v = 0; v < KFBI_NGRAPH; ++v) {
+    if (!want[v]) continue;
     const int iters = 1 << v;
     HIPCHK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
     pl->ctl_active = pl->ctl;
@@ -381,7 +395,6 @@ kfbi_status ensure_graph(kfbi_plan* pl) {
     pl->graphs[v] = gr;
     pl->graph_execs[v] = ex;
   }
-  memcpy(pl->graph_key, key, sizeof(key));
   return KFBI_OK;
 }
 
@@ -771,11 +784,11 @@ kfbi_status gmres_run(kfbi_plan* pl, double tol, int m, int first_batch, GmresOu
   bool first = true;
   for (;;) {
     const int B = batch < m - launched ? batch : m - launched;
-    const int ng = graph_count(pl);
-    const int big = 1 << (ng - 1);
-    for (int b = 0; b + big <= B; b += big) HIPCHK(hipGraphLaunch(pl->graph_execs[ng - 1], st));
-    for (int v = ng - 2; v >= 0; --v)
-      if ((B % big) & (1 << v)) HIPCHK(hipGraphLaunch(pl->graph_execs[v], st));
+    // largest captured graphs first (graph 0 always exists)
+    int left = B;
+    for (int v = KFBI_NGRAPH - 1; v >= 0; --v)
+      if (pl->graph_execs[v])
+        for (; left >= (1 << v); left -= 1 << v) HIPCHK(hipGraphLaunch(pl->graph_execs[v], st));
     launched += B;
     {
       PostReq q{};

@@ -238,18 +238,23 @@ __device__ __forceinline__ double lane_value(double x, int l) {
 // Single work group, small n (n <= GB E): thread t holds elements t + GB r
 // (r < E) of w and of the basis vectors V[0..JR-1] in registers for the
 // whole step, so those are read from memory once, all loads in flight
-// together; vectors JR..j (long runs) are read from memory in each phase.
-// A dot phase forms per-thread products and sums eight vectors at a time
-// over the wavefront (transposing butterfly) into per-wavefront partials in
-// LDS (one buffer per pass, so a single barrier per pass); every wavefront
-// then adds the 16 partials of coefficient i < 64 in lane i and the update
-// takes the coefficients from those lanes (readlane), with no further
-// barrier.  Coefficients from 64 on are summed from LDS where used.
+// together; vectors JR..j (long runs) are read from memory when used.
+// The coefficients are formed in chunks of 64 basis vectors: per-thread
+// products, a sum of eight vectors at a time over the wavefront
+// (transposing butterfly) into per-wavefront partials in LDS (two buffers
+// used in turn, so one barrier per chunk), then every wavefront adds the 16
+// partials of coefficient c0 + l in lane l and the update takes them from
+// there (readlane).  Up to 64 basis vectors (every run seen in practice)
+// this is exactly CGS2; beyond, each chunk is applied before the next
+// one's coefficients are formed (block Gram-Schmidt over chunks).  The LDS
+// footprint stays small (28 KB).
+constexpr int ARN_CH = 64;
+
 template <int E, int JR>
 __global__ void __launch_bounds__(GB) k_arnoldi_reg(int64_t n, int* ctl, int ldh, double* V, double* Hm, double* cs,
                                                    double* sn, double* gv, double* scal) {
-  static_assert(JR % 8 == 0 && JR <= 64, "register vectors: a multiple of 8, at most 64");
-  __shared__ double red[2][GB / 64][KFBI_GMRES_MAX];
+  static_assert(JR % 8 == 0 && JR <= ARN_CH, "register vectors: a multiple of 8, at most one chunk");
+  __shared__ double red[2][GB / 64][ARN_CH];
   __shared__ double hs[KFBI_GMRES_MAX + 2];
   __shared__ double lcs[KFBI_GMRES_MAX], lsn[KFBI_GMRES_MAX];
   __shared__ double rn[GB / 64];
@@ -275,81 +280,71 @@ __global__ void __launch_bounds__(GB) k_arnoldi_reg(int64_t n, int* ctl, int ldh
     lcs[i] = cs[i];
     lsn[i] = sn[i];
   }
-#pragma unroll
+  int buf = 0;
   for (int pass = 0; pass < 2; ++pass) {
-    double(*rp)[KFBI_GMRES_MAX] = red[pass];
+    for (int c0 = 0; c0 <= j; c0 += ARN_CH) {
+      double(*rp)[ARN_CH] = red[buf];
+      buf ^= 1;
+      const int c1 = c0 + ARN_CH - 1 < j ? c0 + ARN_CH - 1 : j;   // last coefficient of the chunk
+      if (c0 == 0) {
 #pragma unroll
-    for (int i0 = 0; i0 < JR; i0 += 8) {
-      if (i0 > j) break;
-      double p[8];
+        for (int i0 = 0; i0 < JR; i0 += 8) {
+          if (i0 > j) break;
+          double p[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        double a = 0.0;
+          for (int q = 0; q < 8; ++q) {
+            double acc = 0.0;
 #pragma unroll
-        for (int r = 0; r < E; ++r) a += vr[i0 + q][r] * wr[r];
-        p[q] = a;
+            for (int r = 0; r < E; ++r) acc += vr[i0 + q][r] * wr[r];
+            p[q] = acc;
+          }
+          const double sv = wave_reduce8(p, lane);
+          if ((lane & 7) == 0) rp[wave][i0 + wave_reduce8_index(lane)] = sv;
+        }
       }
-      const double s = wave_reduce8(p, lane);
-      if ((lane & 7) == 0) rp[wave][i0 + wave_reduce8_index(lane)] = s;
-    }
-    for (int i0 = JR; i0 <= j; i0 += 8) {
-      double p[8];
+      for (int i0 = c0 == 0 ? JR : c0; i0 <= c1; i0 += 8) {
+        double p[8];
 #pragma unroll
-      for (int q = 0; q < 8; ++q) {
-        double a = 0.0;
+        for (int q = 0; q < 8; ++q) {
+          double acc = 0.0;
+#pragma unroll
+          for (int r = 0; r < E; ++r) {
+            const int t = threadIdx.x + GB * r;
+            if (i0 + q <= c1 && t < nn) acc += V[(int64_t)(i0 + q) * n + t] * wr[r];
+          }
+          p[q] = acc;
+        }
+        const double sv = wave_reduce8(p, lane);
+        if ((lane & 7) == 0 && i0 + wave_reduce8_index(lane) <= c1) rp[wave][i0 - c0 + wave_reduce8_index(lane)] = sv;
+      }
+      __syncthreads();
+      double h0 = 0.0;                 // lane l: coefficient c0 + l of this pass
+      if (c0 + lane <= c1)
+        for (int wv = 0; wv < GB / 64; ++wv) h0 += rp[wv][lane];
+      if (wave == 0 && c0 + lane <= c1) hs[c0 + lane] = pass == 0 ? h0 : hs[c0 + lane] + h0;
+      if (c0 == 0) {
+#pragma unroll
+        for (int r = 0; r < E; ++r) {
+          double x = wr[r];
+#pragma unroll
+          for (int i = 0; i < JR; ++i)
+            if (i <= j) x -= lane_value(h0, i) * vr[i][r];
+          wr[r] = x;
+        }
+      }
+      for (int i0 = c0 == 0 ? JR : c0; i0 <= c1; i0 += 8) {
 #pragma unroll
         for (int r = 0; r < E; ++r) {
           const int t = threadIdx.x + GB * r;
-          if (i0 + q <= j && t < nn) a += V[(int64_t)(i0 + q) * n + t] * wr[r];
+          double y[8];
+#pragma unroll
+          for (int q = 0; q < 8; ++q) y[q] = (i0 + q <= c1 && t < nn) ? V[(int64_t)(i0 + q) * n + t] : 0.0;
+          double x = wr[r];
+#pragma unroll
+          for (int q = 0; q < 8; ++q)
+            if (i0 + q <= c1) x -= lane_value(h0, i0 + q - c0) * y[q];
+          wr[r] = x;
         }
-        p[q] = a;
-      }
-      const double s = wave_reduce8(p, lane);
-      if ((lane & 7) == 0 && i0 + wave_reduce8_index(lane) <= j) rp[wave][i0 + wave_reduce8_index(lane)] = s;
-    }
-    __syncthreads();
-    double h0 = 0.0;                   // lane l: coefficient l of this pass
-    if (lane <= j)
-      for (int wv = 0; wv < GB / 64; ++wv) h0 += rp[wv][lane];
-    if (wave == 0)
-      for (int i = lane; i <= j; i += 64) {
-        double s = h0;
-        if (i != lane) {
-          s = 0.0;
-          for (int wv = 0; wv < GB / 64; ++wv) s += rp[wv][i];
-        }
-        hs[i] = pass == 0 ? s : hs[i] + s;
-      }
-#pragma unroll
-    for (int r = 0; r < E; ++r) {
-      double x = wr[r];
-#pragma unroll
-      for (int i = 0; i < JR; ++i)
-        if (i <= j) x -= lane_value(h0, i) * vr[i][r];
-      wr[r] = x;
-    }
-    for (int i0 = JR; i0 <= j; i0 += 8) {
-#pragma unroll
-      for (int r = 0; r < E; ++r) {
-        const int t = threadIdx.x + GB * r;
-        double y[8];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) y[q] = (i0 + q <= j && t < nn) ? V[(int64_t)(i0 + q) * n + t] : 0.0;
-        double x = wr[r];
-#pragma unroll
-        for (int q = 0; q < 8; ++q) {
-          const int i = i0 + q;
-          if (i > j) break;
-          double hv;
-          if (i < 64) {
-            hv = lane_value(h0, i);
-          } else {
-            hv = 0.0;
-            for (int wv = 0; wv < GB / 64; ++wv) hv += rp[wv][i];
-          }
-          x -= hv * y[q];
-        }
-        wr[r] = x;
       }
     }
   }

@@ -169,6 +169,7 @@ struct kfbi_plan {
   hipGraph_t graphs[KFBI_NGRAPH];
   hipGraphExec_t graph_execs[KFBI_NGRAPH];  // graph g runs 2^g iterations
   uint64_t graph_key[20];
+  int graph_uses;                // solves run with the current graph key
   int* h_ctl;
   KfbiMailbox* mbox;             // pinned; see kfbi_post_wait
   unsigned mseq;
