@@ -185,6 +185,8 @@ void free_plan(kfbi_plan* pl) {
   if (pl->h_dpinned) (void)hipHostFree(pl->h_dpinned);
   if (pl->mbox) (void)hipHostFree(pl->mbox);
   pl->mbox = nullptr;
+  if (pl->h_log) (void)hipHostFree(pl->h_log);
+  pl->h_log = nullptr;
   pl->h_pinned = nullptr;
   pl->h_dpinned = nullptr;
 }
@@ -255,6 +257,10 @@ kfbi_status alloc_fixed(kfbi_plan* pl) {
     return KFBI_E_OOM;
   }
   memset((void*)pl->mbox, 0, sizeof(KfbiMailbox));
+  if (hipHostMalloc((void**)&pl->h_log, (KFBI_GMRES_MAX + 2) * sizeof(int), 0) != hipSuccess) {
+    kfbi_set_error("pinned host allocation failed");
+    return KFBI_E_OOM;
+  }
   if (hipHostMalloc((void**)&pl->h_ctl, 16 * sizeof(int), 0) != hipSuccess) {
     kfbi_set_error("pinned host allocation failed");
     return KFBI_E_OOM;
@@ -331,6 +337,46 @@ void destroy_graphs(kfbi_plan* pl) {
     pl->graph_execs[v] = nullptr;
     pl->graphs[v] = nullptr;
   }
+  for (int c = 0; c <= KFBI_MG_CAPS; ++c) {
+    if (pl->mg_gexec[c]) (void)hipGraphExecDestroy(pl->mg_gexec[c]);
+    if (pl->mg_graph[c]) (void)hipGraphDestroy(pl->mg_graph[c]);
+    pl->mg_gexec[c] = nullptr;
+    pl->mg_graph[c] = nullptr;
+  }
+}
+
+// cap of the box solve of GMRES iteration j under relaxation: one more
+// correction than the plan's previous solve needed there; 0 means the
+// plan-wide cap (no record, relaxation off, or beyond the captured caps)
+int iteration_cap(const kfbi_plan* pl, int j) {
+  if (pl->box_solver == KFBI_BOX_FFT || !(pl->relax_word > 0.0) || j >= pl->log_n) return 0;
+  const int full = pl->mg_run_cap > 0 ? pl->mg_run_cap : pl->mg_maxit;
+  int c = pl->log_prev[j] + 1;
+  if (c > full) c = full;
+  return c >= 1 && c <= KFBI_MG_CAPS && c < full ? c : 0;
+}
+
+// one captured iteration (matvec + Arnoldi step)
+kfbi_status capture_iterations(kfbi_plan* pl, int iters, hipGraph_t* gr_out, hipGraphExec_t* ex_out) {
+  HIPCHK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
+  pl->ctl_active = pl->ctl;
+  for (int it = 0; it < iters; ++it) {
+    op_matvec(pl, nullptr, nullptr);
+    gm_arnoldi(pl);
+  }
+  pl->ctl_active = nullptr;
+  hipGraph_t gr = nullptr;
+  hipError_t e = hipStreamEndCapture(pl->stream, &gr);
+  if (e != hipSuccess) return kfbi_hip_status(e, "hipStreamEndCapture");
+  hipGraphExec_t ex = nullptr;
+  e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+  if (e != hipSuccess) {
+    (void)hipGraphDestroy(gr);
+    return kfbi_hip_status(e, "hipGraphInstantiate");
+  }
+  *gr_out = gr;
+  *ex_out = ex;
+  return KFBI_OK;
 }
 
 // Graphs of one and of four GMRES iterations (matvec of V[j] into V[j+1],
@@ -370,30 +416,23 @@ kfbi_status ensure_graph(kfbi_plan* pl) {
     want[v] = graph_wanted(pl, v) && !pl->graph_execs[v];
     missing = missing || want[v];
   }
+  bool wantc[KFBI_MG_CAPS + 1] = {};
+  for (int j = 0; j < pl->log_n; ++j) {
+    const int c = iteration_cap(pl, j);
+    if (c > 0 && !pl->mg_gexec[c]) missing = wantc[c] = true;
+  }
   ++pl->graph_uses;
   if (!missing) return KFBI_OK;
   std::unique_lock<std::shared_mutex> lock(kfbi_capture_mutex);
-  for (int v = 0; v < KFBI_NGRAPH; ++v) {
-    if (!want[v]) continue;
-    const int iters = 1 << v;
-    HIPCHK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
-    pl->ctl_active = pl->ctl;
-    for (int it = 0; it < iters; ++it) {
-      op_matvec(pl, nullptr, nullptr);
-      gm_arnoldi(pl);
-    }
-    pl->ctl_active = nullptr;
-    hipGraph_t gr = nullptr;
-    hipError_t e = hipStreamEndCapture(pl->stream, &gr);
-    if (e != hipSuccess) return kfbi_hip_status(e, "hipStreamEndCapture");
-    hipGraphExec_t ex = nullptr;
-    e = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
-    if (e != hipSuccess) {
-      (void)hipGraphDestroy(gr);
-      return kfbi_hip_status(e, "hipGraphInstantiate");
-    }
-    pl->graphs[v] = gr;
-    pl->graph_execs[v] = ex;
+  for (int v = 0; v < KFBI_NGRAPH; ++v)
+    if (want[v]) KCHK(capture_iterations(pl, 1 << v, &pl->graphs[v], &pl->graph_execs[v]));
+  const int run_cap = pl->mg_run_cap;
+  for (int c = 1; c <= KFBI_MG_CAPS; ++c) {
+    if (!wantc[c]) continue;
+    pl->mg_run_cap = c;
+    const kfbi_status cs = capture_iterations(pl, 1, &pl->mg_graph[c], &pl->mg_gexec[c]);
+    pl->mg_run_cap = run_cap;
+    KCHK(cs);
   }
   return KFBI_OK;
 }
@@ -784,11 +823,19 @@ kfbi_status gmres_run(kfbi_plan* pl, double tol, int m, int first_batch, GmresOu
   bool first = true;
   for (;;) {
     const int B = batch < m - launched ? batch : m - launched;
-    // largest captured graphs first (graph 0 always exists)
-    int left = B;
-    for (int v = KFBI_NGRAPH - 1; v >= 0; --v)
-      if (pl->graph_execs[v])
-        for (; left >= (1 << v); left -= 1 << v) HIPCHK(hipGraphLaunch(pl->graph_execs[v], st));
+    if (iteration_cap(pl, launched) > 0) {
+      // relaxed multigrid: each iteration with its own correction cap
+      for (int b = 0; b < B; ++b) {
+        const int c = iteration_cap(pl, launched + b);
+        HIPCHK(hipGraphLaunch(c > 0 && pl->mg_gexec[c] ? pl->mg_gexec[c] : pl->graph_execs[0], st));
+      }
+    } else {
+      // largest captured graphs first (graph 0 always exists)
+      int left = B;
+      for (int v = KFBI_NGRAPH - 1; v >= 0; --v)
+        if (pl->graph_execs[v])
+          for (; left >= (1 << v); left -= 1 << v) HIPCHK(hipGraphLaunch(pl->graph_execs[v], st));
+    }
     launched += B;
     {
       PostReq q{};
@@ -874,6 +921,11 @@ kfbi_status solve_body(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* op
         pl->mg_cap_eff = pl->mg_maxit;
       else if (most > 0)
         pl->mg_cap_eff = most + 2 < pl->mg_maxit ? most + 2 : pl->mg_maxit;
+      // per-iteration record of the relaxed pass; a cap hit drops it
+      pl->log_n = 0;
+      if (hit == 0)
+        for (int j = 0; j < pl->log_k; ++j) pl->log_prev[j] = pl->h_log[j];
+      if (hit == 0) pl->log_n = pl->log_k;
     }
     pl->mg_run_cap = 0;
   }
@@ -897,6 +949,12 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
   GmresOut o;
   KCHK(gmres_run(pl, tol, m, pl->last_iters > 4 ? (pl->last_iters < 64 ? pl->last_iters : 64) : 4, &o));
   gm_update(pl, o.k, psi, opts->use_x0);
+  pl->log_k = 0;
+  if (relax && o.k > 0) {
+    // corrections per iteration of this pass, read after the true residual's wait
+    HIPCHK(hipMemcpyAsync(pl->h_log, pl->mg_ctl + 4, sizeof(int) * o.k, hipMemcpyDeviceToHost, pl->stream));
+    pl->log_k = o.k;
+  }
   double tr = 0.0;
   KCHK(true_residual(pl, psi, &tr));
   int k = o.k;

@@ -20,6 +20,7 @@
 #define KFBI_GMRES_MAX 512
 #define KFBI_MG_MAXL 12    // multigrid levels (N <= 2048)
 #define KFBI_NGRAPH 5      // captured GMRES graphs of 1, 2, 4, 8 and 16 iterations
+#define KFBI_MG_CAPS 16    // per-iteration multigrid caps captured as graphs of their own
 
 // device-side status bits (OR-ed into plan->d_flags)
 enum {
@@ -153,9 +154,18 @@ struct kfbi_plan {
   int64_t mg_bytes;
   double* mg_part;               // partial sums of the outer residual
   int* mg_ctl;                   // [done, corrections, most corrections since the solve began,
-                                 //  box solves stopped by the cap above eps]
+                                 //  box solves stopped by the cap above eps, then per GMRES
+                                 //  iteration j the corrections of its box solve at 4 + j]
   int mg_cap_eff;                // cap used inside kfbi_solve: observed need + 2 (0: unknown)
   int mg_run_cap;                // cap of the box solves being enqueued (0: mg_maxit)
+  // relaxed multigrid inside GMRES: iteration j of a solve runs at most
+  // log_prev[j] + 1 corrections, log_prev[j] being what it needed in the
+  // plan's previous solve (log_n iterations recorded; 0: none)
+  int log_prev[KFBI_GMRES_MAX + 2];
+  int log_n, log_k;
+  int* h_log;                    // pinned copy of the device log
+  hipGraph_t mg_graph[KFBI_MG_CAPS + 1];
+  hipGraphExec_t mg_gexec[KFBI_MG_CAPS + 1];   // one iteration, at most c corrections
   double mg_relax;               // inexact-Krylov relaxation of eps inside GMRES (0: off)
   double relax_word;             // host copy of the factor last written to GMRES scal[7] (NaN: none)
   double* mg_scal;               // [|F|, last relative residual]

@@ -715,6 +715,7 @@ __global__ void __launch_bounds__(MG_BLOCK) k_check(Ctl ctl, const double* part,
       ctl.mctl[0] = 1;
       if (ctl.mctl[1] > ctl.mctl[2]) ctl.mctl[2] = ctl.mctl[1];
       if (!conv) ctl.mctl[3] += 1;
+      if (ctl.gctl) ctl.mctl[4 + ctl.gctl[0]] = ctl.mctl[1];   // corrections of GMRES iteration j
     }
   }
 }
@@ -1009,6 +1010,7 @@ kfbi_status mg_configure(kfbi_plan* pl, int solver, double eps, int maxit) {
   pl->mg_maxit = maxit;
   pl->mg_cap_eff = 0;
   pl->mg_run_cap = 0;
+  pl->log_n = 0;
   if (solver == KFBI_BOX_FFT) return KFBI_OK;
   const GridDesc& g = pl->g;
   int L = 0;
@@ -1072,13 +1074,13 @@ kfbi_status mg_configure(kfbi_plan* pl, int solver, double eps, int maxit) {
   HIPCHK(hipMemsetAsync(pl->mg_f, 0, (size_t)pl->mg_bytes, pl->stream));
   if (!pl->mg_part) {
     if (hipMalloc((void**)&pl->mg_part, sizeof(double) * 2 * MG_PART) != hipSuccess ||
-        hipMalloc((void**)&pl->mg_ctl, sizeof(int) * 4) != hipSuccess ||
+        hipMalloc((void**)&pl->mg_ctl, sizeof(int) * (4 + KFBI_GMRES_MAX + 2)) != hipSuccess ||
         hipMalloc((void**)&pl->mg_scal, sizeof(double) * 4) != hipSuccess) {
       (void)hipGetLastError();
       kfbi_set_error("device allocation of the multigrid control failed");
       return KFBI_E_OOM;
     }
-    HIPCHK(hipMemsetAsync(pl->mg_ctl, 0, sizeof(int) * 4, pl->stream));
+    HIPCHK(hipMemsetAsync(pl->mg_ctl, 0, sizeof(int) * (4 + KFBI_GMRES_MAX + 2), pl->stream));
     HIPCHK(hipMemsetAsync(pl->mg_scal, 0, sizeof(double) * 4, pl->stream));
   }
   if (!pl->Fmg) {

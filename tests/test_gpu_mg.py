@@ -200,3 +200,30 @@ def test_adaptive_cycle_cap(case):
     p4, u4, _ = gp.solve(data, tol=1e-8)
     p5, u5, _ = gp.solve(data, tol=1e-8)
     assert torch.equal(p4, p0) and torch.equal(p5, p0) and torch.equal(u5, u0)
+
+
+@pytest.mark.parametrize("case", ["c2_128", "sphere_32"])
+def test_relaxed_iteration_caps(case):
+    """With the relaxed tolerance, GMRES iteration j of a solve enqueues one
+    more correction than iteration j of the plan's previous solve needed
+    (each iteration with a graph of its own cap).  Box solves that converge
+    within their cap do the same corrections as under the plan-wide cap, so
+    repeated relaxed solves agree bit for bit with the first one."""
+    from paper_2309_05965_amd import kfbi
+    if case == "c2_128":
+        prob, sol = W.config2(128)
+    else:
+        prob, sol = (W.problem(3, 4, 32, -1.0, 1.0, 1.0, 5.0, 0.5, [W.sphere3d(0.03, -0.02, 0.01, 0.52)]),
+                     {0: W.f_exp3, 1: W.f_sin3})
+    gp = kfbi.Plan(prob)
+    data = kfbi.device_data(gp, prob, sol)
+    gp.set_box_solver("mg32", eps_in=1e-9, max_cycles=40)
+    gp.set_box_relaxation(0.1)
+    p0, u0, i0 = gp.solve(data, tol=1e-8)
+    p1, u1, i1 = gp.solve(data, tol=1e-8)
+    p2, u2, i2 = gp.solve(data, tol=1e-8)
+    p3, u3, i3 = gp.solve(data, tol=1e-8)
+    assert i0["status"] == 0 and i0["true_rel_res"] < 1e-8
+    assert i0["iters"] == i1["iters"] == i2["iters"] == i3["iters"]
+    for p, u in ((p1, u1), (p2, u2), (p3, u3)):
+        assert torch.equal(p, p0) and torch.equal(u, u0)
