@@ -321,8 +321,7 @@ void simple_solve_impl(kfbi_plan* pl, const double* a, const double* b, const do
                        const double* fhat, const double* gB, double* v, double* dn_in, double* dn_out) {
   op_coefficients(pl, a, b, ftilde);
   op_correction_values(pl);
-  op_rhs_base(pl, fhat, gB, pl->Fs);
-  op_rhs_correct(pl, pl->Fs, false);
+  op_rhs_base(pl, fhat, gB, pl->Fs, true);   // corrected at the irregular nodes in the same pass
   box_solve_any(pl, pl->Fs, v);
   op_boundary(pl, gB, v);
   op_normal_derivatives(pl, v, dn_in, dn_out, nullptr);

@@ -222,7 +222,7 @@ kfbi_status colloc_factor(kfbi_plan* pl);
 void op_extend(kfbi_plan* pl, const double* psi, double* psiS);
 void op_coefficients(kfbi_plan* pl, const double* a, const double* b, const double* ftilde);
 void op_correction_values(kfbi_plan* pl);
-void op_rhs_base(kfbi_plan* pl, const double* fhat, const double* gB, double* F);
+void op_rhs_base(kfbi_plan* pl, const double* fhat, const double* gB, double* F, bool corrected = false);
 void op_rhs_correct(kfbi_plan* pl, double* F, bool overwrite);
 void op_boundary(kfbi_plan* pl, const double* gB, double* v);
 void op_normal_derivatives(kfbi_plan* pl, const double* v, double* dn_in, double* dn_out,

@@ -272,9 +272,12 @@ struct RhsArgs {
   const int8_t* region;
   const double *fhat, *gB;
   double* F;
+  const double* Cg;   // non-null: the correction of k_rhs_correct is added in the same pass
 };
 
-// F(P) = B_h fhat_{reg P}(P) - sum_{Q on the box boundary} A_PQ gB(Q)
+// F(P) = B_h fhat_{reg P}(P) - sum_{Q on the box boundary} A_PQ gB(Q); with
+// Cg, plus at the irregular nodes the correction -sum over cut neighbours Q
+// of A_PQ (C^(reg P) - C^(reg Q))(Q), summed as k_rhs_correct sums it
 __global__ void k_rhs_base(RhsArgs a) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   const GridDesc& g = a.g;
@@ -299,6 +302,24 @@ __global__ void k_rhs_base(RhsArgs a) {
           if (bd) s -= a.S.A[idx] * a.gB[Q];
         }
       }
+  if (a.Cg) {
+    const int rp = a.region[i];
+    double corr = 0.0;
+    bool cut = false;
+    for (int o2 = -zr; o2 <= zr; ++o2)
+      for (int o1 = -1; o1 <= 1; ++o1)
+        for (int o0 = -1; o0 <= 1; ++o0) {
+          const int idx = (o0 + 1) + 3 * (o1 + 1) + 9 * (o2 + 1);
+          const double w = a.S.A[idx];
+          if (w == 0.0 || (o0 == 0 && o1 == 0 && o2 == 0)) continue;
+          const int64_t Q = ravel(g, c[0] + o0, c[1] + o1, c[2] + o2);
+          const int rq = a.region[Q];
+          if (rq == rp) continue;
+          cut = true;
+          corr -= w * (Cval(a.Cg, g.n_nodes, rp, Q) - Cval(a.Cg, g.n_nodes, rq, Q));
+        }
+    if (cut) s = s + corr;
+  }
   a.F[i] = s;
 }
 
@@ -741,8 +762,8 @@ void op_correction_values(kfbi_plan* pl) {
   hipLaunchKernelGGL(k_corr_values, dim3(nb(pl->n_corr)), dim3(KFBI_BLOCK), 0, pl->stream, A);
 }
 
-void op_rhs_base(kfbi_plan* pl, const double* fhat, const double* gB, double* F) {
-  RhsArgs A{pl->g, make_stencil(pl->g), pl->region, fhat, gB, F};
+void op_rhs_base(kfbi_plan* pl, const double* fhat, const double* gB, double* F, bool corrected) {
+  RhsArgs A{pl->g, make_stencil(pl->g), pl->region, fhat, gB, F, corrected && pl->n_irr > 0 ? pl->Cg : nullptr};
   hipLaunchKernelGGL(k_rhs_base, dim3(nb(pl->g.n_nodes)), dim3(KFBI_BLOCK), 0, pl->stream, A);
 }
 
