@@ -173,6 +173,10 @@ __device__ __forceinline__ double wave_max(double v) {
 // row a of the inverse with its column j at position p_j.
 template <int NC>
 __global__ void __launch_bounds__(64) k_factor(FactorArgs a) {
+  // a geometry status flag (unresolved stencil, extension or owner) means the
+  // stencil tables may hold no valid point: nothing to factor, the host
+  // reports the flag after this kernel
+  if (*a.flags) return;
   const int64_t c = blockIdx.x;
   const int lane = threadIdx.x;
   const bool live = lane < NC;
@@ -308,8 +312,9 @@ kfbi_status colloc_factor(kfbi_plan* pl) {
     kfbi_set_error("collocation sizes inconsistent (%d %d %d %d)", T.n, T.nP, T.nD, T.nN);
     return KFBI_E_INVALID;
   }
-  // the status flags are zero here: the geometry set-up clears them and
-  // returns an error if any is set
+  // the status flags hold the geometry's (cleared at its start, read back
+  // here together with the factorisation's): k_factor does nothing if one
+  // is set
   FactorArgs a{pl->g, T, pl->n_dof, pl->d2s, pl->s_pos, pl->s_nrm, pl->stD, pl->stN, pl->MinvT, pl->MT,
                pl->cond, pl->d_flags};
   switch (T.n) {

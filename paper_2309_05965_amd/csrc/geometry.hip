@@ -1502,13 +1502,10 @@ kfbi_status geo_setup(kfbi_plan* pl) {
     hipLaunchKernelGGL(k_owner, dim3(nblk(ne * OWG)), dim3(KFBI_BLOCK), 0, st,
                        OwnerArgs{g, ne, pl->ncell_axis, pl->ncell, pl->ce_k, pl->ce_node, pl->d2s, pl->s_pos,
                                  pl->cell_start, pl->cell_count, pl->cell_items, pl->ce_owner, pl->d_flags});
+  // the flags of the stencil, extension and owner searches are read back with
+  // the collocation's (one host wait); the factorisation skips its work when
+  // one is set
   HIPCHK(hipGetLastError());
-  PostReq q{};
-  q.ni = 1;
-  q.isrc[0] = pl->d_flags;
-  int fl = 0;
-  KCHK(kfbi_post_wait(pl, q, &fl, nullptr));
-  if (fl) return kfbi_flags_status(fl);
   return KFBI_OK;
 }
 
