@@ -165,6 +165,8 @@ void free_plan(kfbi_plan* pl) {
   dfree(pl->PE2);
   dfree(pl->EI);
   dfree(pl->flags8);
+  dfree(pl->flags8b);
+  dfree(pl->blk2);
   dfree(pl->row_start);
   dfree(pl->row_end);
   if (pl->prof_ev) {
@@ -226,6 +228,7 @@ kfbi_status alloc_fixed(kfbi_plan* pl) {
   KCHK(dalloc(&pl->vsbuf, n));
   KCHK(dalloc(&pl->flags8, pl->n_seg * g.K > n ? pl->n_seg * g.K : n));
   KCHK(dalloc(&pl->EI, (int64_t)g.K * n));
+  KCHK(dalloc(&pl->flags8b, n));
   int64_t nrows = g.d == 3 ? (int64_t)g.n1 * g.n1 : g.n1;
   KCHK(dalloc(&pl->row_start, nrows));
   KCHK(dalloc(&pl->row_end, nrows));

@@ -1246,6 +1246,22 @@ kfbi_status compact_count_flags(kfbi_plan* pl, int64_t n, Pred pred, int64_t* co
   return post_count(pl, count, flags);
 }
 
+// count (storing the predicate in flags) and scan into blk, total -> *tot,
+// without a host wait
+template <class Pred>
+void enqueue_count_flags(kfbi_plan* pl, int64_t n, Pred pred, int* blk, uint8_t* flags, int* tot) {
+  const int64_t nb = (n + CMP_CH - 1) / CMP_CH;
+  hipLaunchKernelGGL(k_count_flags<Pred>, dim3((unsigned)nb), dim3(KFBI_BLOCK), 0, pl->stream, n, pred, blk, flags);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, pl->stream, blk, nb, tot);
+}
+
+template <class Pred, class Emit>
+void compact_emit_with(kfbi_plan* pl, int64_t n, Pred pred, Emit emit, int* blk) {
+  int64_t nb = (n + CMP_CH - 1) / CMP_CH;
+  if (nb == 0) return;
+  hipLaunchKernelGGL((k_emit<Pred, Emit>), dim3((unsigned)nb), dim3(KFBI_BLOCK), 0, pl->stream, n, pred, emit, blk);
+}
+
 template <class Pred, class Emit>
 void compact_emit(kfbi_plan* pl, int64_t n, Pred pred, Emit emit) {
   int64_t nb = (n + CMP_CH - 1) / CMP_CH;
@@ -1344,12 +1360,37 @@ kfbi_status geo_setup(kfbi_plan* pl) {
   // the region flags travel with the first compaction count (one host
   // wait); the candidate count reads the regions only
   // candidates: (segment, interface) items with a sign change
+  // the irregular nodes depend on the regions only: they are counted in the
+  // same host wait
   int64_t n_items = pl->n_seg * g.K;
   CandPred cp{g, pl->region};
-  int64_t nc;
-  int rflags = 0;
-  KCHK(compact_count_flags(pl, n_items, cp, &nc, &rflags));
-  if (rflags) return kfbi_flags_status(rflags);
+  IrrPred ip{g, pl->region};
+  int64_t nc, ni;
+  {
+    const int64_t nbc = (n_items + CMP_CH - 1) / CMP_CH, nbi = (g.n_nodes + CMP_CH - 1) / CMP_CH;
+    KCHK(ensure_blk(pl, nbc));
+    KCHK(grow(&pl->blk2, &pl->cap_blk2, nbi + 1));
+    enqueue_count_flags(pl, n_items, cp, pl->blk, pl->flags8, pl->blk_total);
+    enqueue_count_flags(pl, g.n_nodes, ip, pl->blk2, pl->flags8b, pl->blk_total + 1);
+    PostReq q{};
+    q.ni = 3;
+    q.isrc[0] = pl->blk_total;
+    q.isrc[1] = pl->blk_total + 1;
+    q.isrc[2] = pl->d_flags;
+    int v[3] = {0, 0, 0};
+    KCHK(kfbi_post_wait(pl, q, v, nullptr));
+    nc = v[0];
+    ni = v[1];
+    if (v[2]) return kfbi_flags_status(v[2]);
+  }
+  if (ni > pl->cap_irr) {
+    int64_t cap = headroom(ni);
+    pl->cap_irr = 0;
+    KCHK(realloc_n(&pl->irr, cap));
+    pl->cap_irr = cap;
+  }
+  pl->n_irr = ni;
+  compact_emit_with(pl, g.n_nodes, NeedPred{pl->flags8b}, IdxEmit{pl->irr}, pl->blk2);
   if (nc == 0) {
     kfbi_set_error("no grid segment crosses an interface");
     return KFBI_E_INVALID;
@@ -1450,19 +1491,6 @@ kfbi_status geo_setup(kfbi_plan* pl) {
                      StencilArgs{S, lat, nd, pl->d2s, pl->stD, pl->stN, pl->s_need, pl->d_flags});
   hipLaunchKernelGGL(k_extension, dim3(nblk(ns * EXG)), dim3(KFBI_BLOCK), 0, st,
                      ExtArgs{S, ns, pl->s2d, pl->s_need, pl->ext_idx, pl->ext_w, pl->d_flags});
-
-  // irregular nodes
-  IrrPred ip{g, pl->region};
-  int64_t ni;
-  KCHK(compact_count_flags(pl, g.n_nodes, ip, &ni));
-  if (ni > pl->cap_irr) {
-    int64_t cap = headroom(ni);
-    pl->cap_irr = 0;
-    KCHK(realloc_n(&pl->irr, cap));
-    pl->cap_irr = cap;
-  }
-  pl->n_irr = ni;
-  compact_emit(pl, g.n_nodes, NeedPred{pl->flags8}, IdxEmit{pl->irr});
 
   // correction entries
   if (ni > 0)

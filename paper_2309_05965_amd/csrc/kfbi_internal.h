@@ -107,6 +107,9 @@ struct kfbi_plan {
   uint8_t* flags8;               // predicate per item, max(d N (N+1)^(d-1) K, n_nodes)
   int *blk, *blk_total;
   int64_t cap_blk;
+  uint8_t* flags8b;              // irregular-node predicate per node (compacted beside the candidates)
+  int* blk2;                     // scan scratch of that compaction
+  int64_t cap_blk2;
   int* d_flags;
   int* h_pinned;                 // pinned host scratch for counts
   double* h_dpinned;
