@@ -479,9 +479,23 @@ kfbi_status kfbi_post_wait(kfbi_plan* pl, const PostReq& r, int* iout, double* d
     kfbi_set_error("post request too large");
     return KFBI_E_INVALID;
   }
-  const unsigned seq = ++pl->mseq == 0 ? ++pl->mseq : pl->mseq;
-  hipLaunchKernelGGL(k_post, dim3(1), dim3(1024), 0, pl->stream, r, pl->mbox, seq);
+  unsigned seq = 0;
+  KCHK(kfbi_post_launch(pl, r, &seq));
+  return kfbi_post_collect(pl, r, seq, iout, dout);
+}
+
+kfbi_status kfbi_post_launch(kfbi_plan* pl, const PostReq& r, unsigned* seq) {
+  if (r.ni > 8 || r.nd > 8 || (r.nmax > 0 && r.nd > 7)) {
+    kfbi_set_error("post request too large");
+    return KFBI_E_INVALID;
+  }
+  *seq = ++pl->mseq == 0 ? ++pl->mseq : pl->mseq;
+  hipLaunchKernelGGL(k_post, dim3(1), dim3(1024), 0, pl->stream, r, pl->mbox, *seq);
   HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+kfbi_status kfbi_post_collect(kfbi_plan* pl, const PostReq& r, unsigned seq, int* iout, double* dout) {
   const auto t0 = std::chrono::steady_clock::now();
   for (long s = 1;; ++s) {
     if (__atomic_load_n(&pl->mbox->seq, __ATOMIC_ACQUIRE) == seq) break;
@@ -871,8 +885,10 @@ kfbi_status gmres_run(kfbi_plan* pl, double tol, int m, int first_batch, GmresOu
 }
 
 // |b - A psi| / |b| with a fresh full-accuracy matvec
-kfbi_status true_residual(kfbi_plan* pl, const double* psi, double* tr) {
-  hipStream_t st = pl->stream;
+// with `then`, work enqueued after the residual's kernels and before the
+// host waits for them
+template <class Then>
+kfbi_status true_residual(kfbi_plan* pl, const double* psi, double* tr, Then then) {
   matvec_impl(pl, psi, pl->work2);
   gm_true_residual(pl, pl->bvec, pl->work2, pl->scal + 4);
   PostReq q{};
@@ -884,9 +900,16 @@ kfbi_status true_residual(kfbi_plan* pl, const double* psi, double* tr) {
     q.isrc[0] = pl->mg_ctl + 2;
     q.isrc[1] = pl->mg_ctl + 3;
   }
-  KCHK(kfbi_post_wait(pl, q, pl->h_pinned + 2, pl->h_dpinned + 4));
+  unsigned seq = 0;
+  KCHK(kfbi_post_launch(pl, q, &seq));
+  then();
+  KCHK(kfbi_post_collect(pl, q, seq, pl->h_pinned + 2, pl->h_dpinned + 4));
   *tr = pl->h_dpinned[5] > 0.0 ? sqrt(pl->h_dpinned[4] / pl->h_dpinned[5]) : 0.0;
   return KFBI_OK;
+}
+
+kfbi_status true_residual(kfbi_plan* pl, const double* psi, double* tr) {
+  return true_residual(pl, psi, tr, [] {});
 }
 
 // the relaxation factor the captured iterations read (GMRES scal[7])
@@ -957,8 +980,19 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
     HIPCHK(hipMemcpyAsync(pl->h_log, pl->mg_ctl + 4, sizeof(int) * o.k, hipMemcpyDeviceToHost, pl->stream));
     pl->log_k = o.k;
   }
+  // final solve u = w(g1, E psi, ftilde, fhat, gB): without relaxation psi
+  // is final here, so it is enqueued before the host waits for the true
+  // residual
+  double* u = u_out ? u_out : pl->vsbuf;
+  auto final_solve = [&] {
+    op_extend(pl, psi, pl->aS);
+    simple_solve_impl(pl, data->g1, pl->aS, data->ftilde, data->fhat, data->gB, u, pl->dn_in, pl->dn_out);
+  };
   double tr = 0.0;
-  KCHK(true_residual(pl, psi, &tr));
+  if (relax)
+    KCHK(true_residual(pl, psi, &tr));
+  else
+    KCHK(true_residual(pl, psi, &tr, final_solve));
   int k = o.k;
   // with a relaxed inner tolerance the GMRES estimate can run ahead of the
   // true residual: if it misses tol, continue from psi with full-accuracy
@@ -976,10 +1010,7 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
     o.conv = o2.conv;
   }
   pl->last_iters = k;
-  // final solve u = w(g1, E psi, ftilde, fhat, gB)
-  op_extend(pl, psi, pl->aS);
-  simple_solve_impl(pl, data->g1, pl->aS, data->ftilde, data->fhat, data->gB, u_out ? u_out : pl->vsbuf,
-                    pl->dn_in, pl->dn_out);
+  if (relax) final_solve();
   HIPCHK(hipGetLastError());
   kfbi_status s = o.conv ? KFBI_OK : KFBI_E_NOT_CONVERGED;
   if (!isfinite(tr) || !isfinite(o.est)) s = KFBI_E_NONFINITE;

@@ -216,6 +216,10 @@ kfbi_status kfbi_flags_status(int flags);
 // it falls back to a stream synchronisation, which also reports a device
 // error.  iout / dout receive r.ni ints and r.nd (+1 with a maximum) doubles.
 kfbi_status kfbi_post_wait(kfbi_plan* pl, const PostReq& r, int* iout, double* dout);
+// the two halves of kfbi_post_wait: enqueue k_post (returns its sequence
+// number), and wait for it (other work may be enqueued in between)
+kfbi_status kfbi_post_launch(kfbi_plan* pl, const PostReq& r, unsigned* seq);
+kfbi_status kfbi_post_collect(kfbi_plan* pl, const PostReq& r, unsigned seq, int* iout, double* dout);
 
 // geometry.hip (step S0)
 kfbi_status geo_setup(kfbi_plan* pl);
