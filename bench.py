@@ -203,6 +203,10 @@ def main():
 
     torch.cuda.set_device(0)
     prob, sol = W.config2(args.N)
+    # the plan lives on a stream of its own (a caller's non-default stream is
+    # used for the solve as it is; on the default stream the library orders a
+    # private stream before and after every solve with events)
+    torch.cuda.set_stream(torch.cuda.Stream())
     plan = kfbi.Plan(prob)
     data = kfbi.device_data(plan, prob, sol)          # inputs resident in HBM
     u = torch.zeros(plan.n_nodes, dtype=torch.float64, device="cuda")

@@ -252,9 +252,14 @@ kfbi_status kfbi_rhs(kfbi_plan* plan, const kfbi_data* data, double* b);
 /* Full solve (Alg. 1): b, GMRES on kfbi_matvec to opts->tol, then
  * u = w(g1, E psi, ftilde, fhat, gB).  psi_inout [n_dof] (initial guess if
  * opts->use_x0, density on return); u_out [n_nodes] (may be NULL).
- * Synchronises the plan's stream once per GMRES iteration.  Returns
- * KFBI_E_NOT_CONVERGED (with psi and u of the last iterate) if max_iter is
- * reached. */
+ * The host waits for the device a few times per solve (between batches of
+ * captured GMRES iterations and for the true residual).  The iterations run
+ * as captured HIP graphs: on a plan created with a stream of the caller's
+ * own they are captured and launched on that stream; on a default stream
+ * (NULL, legacy or per-thread) the solve runs on a private stream of the
+ * plan, ordered after and before the caller's stream by events (which costs
+ * a few tens of microseconds per solve).  Returns KFBI_E_NOT_CONVERGED (with
+ * psi and u of the last iterate) if max_iter is reached. */
 kfbi_status kfbi_solve(kfbi_plan* plan, const kfbi_data* data, const kfbi_opts* opts,
                        double* psi_inout, double* u_out, kfbi_info* info);
 

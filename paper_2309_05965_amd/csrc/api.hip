@@ -1043,9 +1043,12 @@ extern "C" kfbi_status kfbi_solve(kfbi_plan* pl, const kfbi_data* data, const kf
     std::shared_lock<std::shared_mutex> lock(kfbi_capture_mutex);
     KCHK(ensure_gmres(pl, m));
   }
-  // the solve runs on the plan's private stream (graph launches need a
-  // capturable stream), ordered after and before the caller's stream
+  // graph capture needs a stream other than the default ones: a caller's
+  // own stream is used as it is; for a default stream the solve runs on the
+  // plan's private stream, ordered after and before the caller's by events
   hipStream_t user = pl->stream;
+  if (user != nullptr && user != hipStreamLegacy && user != hipStreamPerThread)
+    return solve_body(pl, data, opts, psi, u_out, info, m, tol);
   HIPCHK(hipEventRecord(pl->ev_in, user));
   HIPCHK(hipStreamWaitEvent(pl->gstream, pl->ev_in, 0));
   pl->stream = pl->gstream;

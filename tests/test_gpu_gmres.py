@@ -75,3 +75,23 @@ def test_device_gmres_matches_host_gmres(name):
     assert np.max(np.abs(p - psi_h)) <= 1e-9 * np.max(np.abs(psi_h))
     assert info["true_rel_res"] < 1e-10
     assert torch.equal(psi, psi2)                 # bitwise reproducible
+
+
+def test_solve_on_caller_stream():
+    """A plan made on a caller's own stream solves on that stream (graph
+    capture included, no private stream); the result equals the solve of a
+    plan made on the default stream bit for bit."""
+    from paper_2309_05965_amd import kfbi
+    prob, sol = W.config2(256)
+    p0 = kfbi.Plan(prob)
+    d0 = kfbi.device_data(p0, prob, sol)
+    psi0, u0, i0 = p0.solve(d0, tol=1e-10)
+    s = torch.cuda.Stream()
+    with torch.cuda.stream(s):
+        p1 = kfbi.Plan(prob)
+        psi1, u1, i1 = p1.solve(d0, tol=1e-10)
+        psi2, u2, i2 = p1.solve(d0, tol=1e-10)
+    s.synchronize()
+    assert i1["status"] == 0 and i1["iters"] == i0["iters"] == i2["iters"]
+    assert torch.equal(psi1, psi0) and torch.equal(u1, u0)
+    assert torch.equal(psi2, psi0) and torch.equal(u2, u0)
