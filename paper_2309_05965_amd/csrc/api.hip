@@ -167,6 +167,7 @@ void free_plan(kfbi_plan* pl) {
   dfree(pl->flags8);
   dfree(pl->flags8b);
   dfree(pl->blk2);
+  dfree(pl->blk3);
   dfree(pl->row_start);
   dfree(pl->row_end);
   if (pl->prof_ev) {

@@ -577,6 +577,29 @@ struct PrimPred {
   __device__ bool operator()(int64_t i) const { return meta[i * 5 + 4] != 0; }
 };
 
+// the primary test of SurfEmit (family r equals the first axis of largest
+// |normal component|) on an accepted candidate, before the surface table
+// exists
+__device__ __forceinline__ bool cand_primary(int d, const double* cnrm, const int* r, int64_t i) {
+  double best = -1.0;
+  int arg = 0;
+  for (int ax = 0; ax < d; ++ax) {
+    const double v = fabs(cnrm[i * d + ax]);
+    if (ax == 0 || v > best) {
+      best = v;
+      arg = ax;
+    }
+  }
+  return arg == r[i];
+}
+
+struct PrimCandPred {
+  int d;
+  const int *acc, *r;
+  const double* cnrm;
+  __device__ bool operator()(int64_t i) const { return acc[i] != 0 && cand_primary(d, cnrm, r, i); }
+};
+
 struct PrimEmit {
   int *d2s, *s2d;
   __device__ void operator()(int64_t i, int o) const {
@@ -940,14 +963,17 @@ __device__ __forceinline__ int block_start(const GridDesc& g, double x) {
   return st;
 }
 
-__global__ void k_need_blocks(GridDesc g, int64_t n_dof, const int* d2s, const double* spos,
-                              const int* meta, const int8_t* region, uint8_t* need) {
-  int64_t c = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
-  if (c >= n_dof) return;
-  int s = d2s[c];
-  int k = meta[(int64_t)s * 5 + 3];
+// correction entries needed by the interpolation blocks: for every centre
+// (a primary candidate, before the surface table is compacted) the nodes of
+// its (q+1)^d block that lie inside another interface need that
+// interface's correction (the centre's own side uses its own polynomial)
+__global__ void k_need_blocks_cand(GridDesc g, int64_t nc, const int* acc, const int* r, const int* ck,
+                                   const double* cpos, const double* cnrm, const int8_t* region, uint8_t* need) {
+  int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= nc || !acc[i] || !cand_primary(g.d, cnrm, r, i)) return;
+  int k = ck[i];
   int st[3] = {0, 0, 0};
-  for (int ax = 0; ax < g.d; ++ax) st[ax] = block_start(g, spos[(int64_t)s * g.d + ax]);
+  for (int ax = 0; ax < g.d; ++ax) st[ax] = block_start(g, cpos[i * g.d + ax]);
   int q1 = g.p + 1;
   int nz = g.d == 3 ? q1 : 1;
   for (int b2 = 0; b2 < nz; ++b2)
@@ -956,8 +982,6 @@ __global__ void k_need_blocks(GridDesc g, int64_t n_dof, const int* d2s, const d
         int cc[3] = {st[0] + b0, st[1] + b1, st[2] + b2};
         int64_t Q = ravel(g, cc);
         int rq = region[Q];
-        // the centre's own side is corrected with its own polynomial; only
-        // nodes inside another interface need that interface's C
         if (rq != k && rq != 0) need[(int64_t)(rq - 1) * g.n_nodes + Q] = 1;
       }
 }
@@ -1255,6 +1279,13 @@ void enqueue_count_flags(kfbi_plan* pl, int64_t n, Pred pred, int* blk, uint8_t*
   hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, pl->stream, blk, nb, tot);
 }
 
+template <class Pred>
+void enqueue_count(kfbi_plan* pl, int64_t n, Pred pred, int* blk, int* tot) {
+  const int64_t nb = (n + CMP_CH - 1) / CMP_CH;
+  hipLaunchKernelGGL(k_count<Pred>, dim3((unsigned)nb), dim3(KFBI_BLOCK), 0, pl->stream, n, pred, blk);
+  hipLaunchKernelGGL(k_scan, dim3(1), dim3(1024), 0, pl->stream, blk, nb, tot);
+}
+
 template <class Pred, class Emit>
 void compact_emit_with(kfbi_plan* pl, int64_t n, Pred pred, Emit emit, int* blk) {
   int64_t nb = (n + CMP_CH - 1) / CMP_CH;
@@ -1415,10 +1446,37 @@ kfbi_status geo_setup(kfbi_plan* pl) {
                      BisectArgs{g, L, nc, pl->c_r, pl->c_lid, pl->c_seg, pl->c_k, pl->c_ina, pl->c_pos,
                                 pl->c_nrm, pl->c_acc});
 
-  // surface table
+  // surface points, centres and correction entries are counted in one host
+  // wait, all from the candidates: accepted ones (surface table), accepted
+  // primary ones (centres), and the (interface, node) entries that the
+  // irregular nodes and the centres' interpolation blocks need
   AccPred ap{pl->c_acc};
-  int64_t ns;
-  KCHK(compact_count(pl, nc, ap, &ns));
+  PrimCandPred pcp{g.d, pl->c_acc, pl->c_r, pl->c_nrm};
+  NeedPred np{pl->need};
+  const int64_t n_need = (int64_t)g.K * g.n_nodes;
+  int64_t ns, nd, ne;
+  {
+    const int64_t nbc = (nc + CMP_CH - 1) / CMP_CH, nbn = (n_need + CMP_CH - 1) / CMP_CH;
+    KCHK(ensure_blk(pl, nbc));
+    KCHK(grow(&pl->blk2, &pl->cap_blk2, nbn + 1));
+    KCHK(grow(&pl->blk3, &pl->cap_blk3, nbc + 1));
+    enqueue_count(pl, nc, ap, pl->blk, pl->blk_total);
+    enqueue_count(pl, nc, pcp, pl->blk3, pl->blk_total + 1);
+    if (ni > 0)
+      hipLaunchKernelGGL(k_need_irr, dim3(nblk(ni)), dim3(KFBI_BLOCK), 0, st, g, ni, pl->irr, pl->region,
+                         pl->need);
+    hipLaunchKernelGGL(k_need_blocks_cand, dim3(nblk(nc)), dim3(KFBI_BLOCK), 0, st, g, nc, pl->c_acc, pl->c_r,
+                       pl->c_k, pl->c_pos, pl->c_nrm, pl->region, pl->need);
+    enqueue_count(pl, n_need, np, pl->blk2, pl->blk_total + 2);
+    PostReq q{};
+    q.ni = 3;
+    for (int i = 0; i < 3; ++i) q.isrc[i] = pl->blk_total + i;
+    int v[3] = {0, 0, 0};
+    KCHK(kfbi_post_wait(pl, q, v, nullptr));
+    ns = v[0];
+    nd = v[1];
+    ne = v[2];
+  }
   if (ns > pl->cap_surf) {
     int64_t cap = headroom(ns);
     pl->cap_surf = 0;
@@ -1440,10 +1498,9 @@ kfbi_status geo_setup(kfbi_plan* pl) {
   hipLaunchKernelGGL(k_lines, dim3(nblk(ns)), dim3(KFBI_BLOCK), 0, st, ns, L1, pl->s_meta, pl->line_start,
                      pl->line_end, pl->s2d, pl->s_need);
 
-  // primary points
+  // primary points (their count is known: the scan over the surface table
+  // only places them)
   PrimPred pp{pl->s_meta};
-  int64_t nd;
-  KCHK(compact_count(pl, ns, pp, &nd));
   if (nd == 0) {
     kfbi_set_error("no primary surface points");
     return KFBI_E_INVALID;
@@ -1467,6 +1524,7 @@ kfbi_status geo_setup(kfbi_plan* pl) {
     pl->cap_dof = cap;
   }
   pl->n_dof = nd;
+  if (ns > 0) enqueue_count(pl, ns, pp, pl->blk, pl->blk_total + 3);
   compact_emit(pl, ns, pp, PrimEmit{pl->d2s, pl->s2d});
 
   // collocation stencils
@@ -1492,15 +1550,7 @@ kfbi_status geo_setup(kfbi_plan* pl) {
   hipLaunchKernelGGL(k_extension, dim3(nblk(ns * EXG)), dim3(KFBI_BLOCK), 0, st,
                      ExtArgs{S, ns, pl->s2d, pl->s_need, pl->ext_idx, pl->ext_w, pl->d_flags});
 
-  // correction entries
-  if (ni > 0)
-    hipLaunchKernelGGL(k_need_irr, dim3(nblk(ni)), dim3(KFBI_BLOCK), 0, st, g, ni, pl->irr, pl->region,
-                       pl->need);
-  hipLaunchKernelGGL(k_need_blocks, dim3(nblk(nd)), dim3(KFBI_BLOCK), 0, st, g, nd, pl->d2s, pl->s_pos,
-                     pl->s_meta, pl->region, pl->need);
-  NeedPred np{pl->need};
-  int64_t ne;
-  KCHK(compact_count(pl, (int64_t)g.K * g.n_nodes, np, &ne));
+  // correction entries (counted above; the scan is in blk2)
   if (ne > pl->cap_corr) {
     int64_t cap = headroom(ne);
     pl->cap_corr = 0;
@@ -1510,7 +1560,7 @@ kfbi_status geo_setup(kfbi_plan* pl) {
     pl->cap_corr = cap;
   }
   pl->n_corr = ne;
-  compact_emit(pl, (int64_t)g.K * g.n_nodes, np, CorrEmit{g.n_nodes, pl->ce_k, pl->ce_node});
+  compact_emit_with(pl, n_need, np, CorrEmit{g.n_nodes, pl->ce_k, pl->ce_node}, pl->blk2);
 
   // closest centres: bin the centres of every interface on a 2h lattice
   int64_t nkeys = (int64_t)g.K * pl->ncell;

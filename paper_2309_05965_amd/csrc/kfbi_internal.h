@@ -108,8 +108,10 @@ struct kfbi_plan {
   int *blk, *blk_total;
   int64_t cap_blk;
   uint8_t* flags8b;              // irregular-node predicate per node (compacted beside the candidates)
-  int* blk2;                     // scan scratch of that compaction
+  int* blk2;                     // scan scratch of that compaction and of the correction entries
   int64_t cap_blk2;
+  int* blk3;                     // scan scratch of the centre count over the candidates
+  int64_t cap_blk3;
   int* d_flags;
   int* h_pinned;                 // pinned host scratch for counts
   double* h_dpinned;
