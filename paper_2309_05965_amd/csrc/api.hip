@@ -280,7 +280,10 @@ kfbi_status run_setup(kfbi_plan* pl) {
   pl->ready = false;
   KCHK(geo_setup(pl));
   KCHK(colloc_factor(pl));
+  // the folds go out before the host waits for the collocation's status
+  // (they do nothing when a status flag is set)
   KCHK(op_fold(pl));
+  KCHK(colloc_finish(pl));
   // the multigrid matvec right-hand side is zero away from the irregular nodes
   if (pl->Fmg) HIPCHK(hipMemsetAsync(pl->Fmg, 0, sizeof(double) * pl->g.n_nodes, pl->stream));
   // everything after the set-up is ordered behind it on the plan's stream

@@ -327,15 +327,21 @@ kfbi_status colloc_factor(kfbi_plan* pl) {
       return KFBI_E_INVALID;
   }
   HIPCHK(hipGetLastError());
-  // flags and the largest condition number (a NaN wins) in one host wait
-  PostReq q{};
+  // flags and the largest condition number (a NaN wins): posted now, read
+  // by colloc_finish after the folds have been enqueued
+  PostReq& q = pl->colloc_req;
+  q = PostReq{};
   q.ni = 1;
   q.isrc[0] = pl->d_flags;
   q.maxsrc = pl->cond;
   q.nmax = pl->n_dof;
+  return kfbi_post_launch(pl, q, &pl->colloc_seq);
+}
+
+kfbi_status colloc_finish(kfbi_plan* pl) {
   int fl = 0;
   double cm = 0.0;
-  KCHK(kfbi_post_wait(pl, q, &fl, &cm));
+  KCHK(kfbi_post_collect(pl, pl->colloc_req, pl->colloc_seq, &fl, &cm));
   pl->cond_max = cm;
   if (fl) return kfbi_flags_status(fl);
   return KFBI_OK;

@@ -187,6 +187,8 @@ struct kfbi_plan {
   int graph_uses;                // solves run with the current graph key
   int* h_ctl;
   KfbiMailbox* mbox;             // pinned; see kfbi_post_wait
+  PostReq colloc_req;            // the collocation's status post, collected after the folds are enqueued
+  unsigned colloc_seq;
   unsigned mseq;
   // box-solve event timing
   int prof_on;
@@ -226,7 +228,8 @@ kfbi_status kfbi_post_collect(kfbi_plan* pl, const PostReq& r, unsigned seq, int
 // geometry.hip (step S0)
 kfbi_status geo_setup(kfbi_plan* pl);
 // collocation.hip (step S1)
-kfbi_status colloc_factor(kfbi_plan* pl);
+kfbi_status colloc_factor(kfbi_plan* pl);      // enqueues the factorisation and its status post
+kfbi_status colloc_finish(kfbi_plan* pl);      // waits for that post: status flags, largest condition number
 // operator.hip (steps S2, S4, S5 and right-hand sides)
 void op_extend(kfbi_plan* pl, const double* psi, double* psiS);
 void op_coefficients(kfbi_plan* pl, const double* a, const double* b, const double* ftilde);

@@ -402,6 +402,7 @@ struct FoldArgs {
   const int8_t* region;
   const double *spos, *snrm, *MinvT, *ext_w;
   int *FI, *GI, *IB, *IE2, *PE1, *PE2;
+  const int* flags;    // status flags: the folds do nothing when one is set (the tables may be invalid)
   double *FW, *GW, *HW, *IW, *TI, *PA;
   Stencil S;
 };
@@ -414,6 +415,7 @@ __global__ void k_entry_map(int64_t n_corr, int64_t n_nodes, const int* ck, cons
 
 template <int D, int P>
 __global__ void k_fold_corr(FoldArgs a) {
+  if (*a.flags) return;
   constexpr int NC = ncoef_t<D, P>();
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (e >= a.n_corr) return;
@@ -446,6 +448,7 @@ __global__ void k_fold_corr(FoldArgs a) {
 }
 
 __global__ void k_fold_dof(FoldArgs a) {
+  if (*a.flags) return;
   const GridDesc& g = a.g;
   const int q = g.p, q1 = q + 1;
   const int nbk = g.d == 3 ? q1 * q1 * q1 : q1 * q1;
@@ -521,6 +524,7 @@ __global__ void k_fold_dof(FoldArgs a) {
 constexpr int FOLD_G = 32;
 template <int D, int P>
 __global__ void __launch_bounds__(KFBI_BLOCK) k_fold_own(FoldArgs a) {
+  if (*a.flags) return;
   constexpr int NC = ncoef_t<D, P>();
   constexpr int Q1 = P + 1;
   constexpr int NBK = D == 3 ? Q1 * Q1 * Q1 : Q1 * Q1;
@@ -577,6 +581,7 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_fold_own(FoldArgs a) {
 // cut neighbours of every irregular node: stencil coefficient and the
 // entries of C^(reg P) and C^(reg Q) at the neighbour (Sec. 5.2 remark)
 __global__ void k_fold_pairs(FoldArgs a) {
+  if (*a.flags) return;
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= a.n_irr) return;
   const GridDesc& g = a.g;
@@ -914,6 +919,7 @@ kfbi_status op_fold(kfbi_plan* pl) {
   A.TI = pl->TI;
   A.PA = pl->PA;
   A.S = make_stencil(g);
+  A.flags = pl->d_flags;
   if (pl->n_corr > 0) {
     dim3 gr(nb(pl->n_corr)), bl(KFBI_BLOCK);
     if (g.d == 2 && g.p == 2) hipLaunchKernelGGL((k_fold_corr<2, 2>), gr, bl, 0, pl->stream, A);
