@@ -832,9 +832,23 @@ struct GmresOut {
   int k;
   double est;
   bool conv;
+  bool spec_ok;     // the work of `spec` ran on the final iterate
 };
 
-kfbi_status gmres_run(kfbi_plan* pl, double tol, int m, int first_batch, GmresOut* o) {
+// Work enqueued behind the first batch of iterations on the guess that the
+// batch converges: `before` ahead of the state post (its values ride on the
+// post: the true residual), `after` behind it (the final solve).  If the
+// batch did not converge the work is simply redone later.
+struct GmresSpec {
+  bool active = false;
+  void (*before)(void*) = nullptr;
+  void (*after)(void*) = nullptr;
+  void* ctx = nullptr;
+};
+
+kfbi_status gmres_run(kfbi_plan* pl, double tol, int m, int first_batch, GmresOut* o,
+                      const GmresSpec& spec = GmresSpec()) {
+  o->spec_ok = false;
   hipStream_t st = pl->stream;
   int launched = 0;
   int batch = first_batch;
@@ -857,19 +871,38 @@ kfbi_status gmres_run(kfbi_plan* pl, double tol, int m, int first_batch, GmresOu
           for (; left >= (1 << v); left -= 1 << v) HIPCHK(hipGraphLaunch(pl->graph_execs[v], st));
     }
     launched += B;
+    const bool sp = first && spec.active;
     {
       PostReq q{};
       q.ni = 4;
       for (int i = 0; i < 4; ++i) q.isrc[i] = pl->ctl + i;
-      q.nd = 7;
+      q.nd = 7;    // scal[4], scal[5]: the true residual's sums when speculating
       for (int i = 0; i < 7; ++i) q.dsrc[i] = pl->scal + i;
-      KCHK(kfbi_post_wait(pl, q, pl->h_ctl, pl->h_dpinned));
+      if (sp) {
+        spec.before(spec.ctx);
+        if (pl->box_solver != KFBI_BOX_FFT) {
+          q.ni = 6;
+          q.isrc[4] = pl->mg_ctl + 2;
+          q.isrc[5] = pl->mg_ctl + 3;
+        }
+      }
+      unsigned seq = 0;
+      KCHK(kfbi_post_launch(pl, q, &seq));
+      if (sp) spec.after(spec.ctx);
+      int iv[6] = {0, 0, 0, 0, 0, 0};
+      KCHK(kfbi_post_collect(pl, q, seq, iv, pl->h_dpinned));
+      for (int i = 0; i < 4; ++i) pl->h_ctl[i] = iv[i];
+      if (sp && q.ni == 6) {
+        pl->h_pinned[2] = iv[4];
+        pl->h_pinned[3] = iv[5];
+      }
     }
     if (first) {
       nb = pl->h_dpinned[1];
       res_prev = pl->h_dpinned[6];
       first = false;
     }
+    if (sp && pl->h_ctl[1]) o->spec_ok = true;
     if (pl->h_ctl[1] || launched >= m) break;
     const int k = pl->h_ctl[2];
     const double res = pl->h_dpinned[0];
@@ -961,6 +994,23 @@ kfbi_status solve_body(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* op
   return s;
 }
 
+// status and info of a finished solve (k iterations, true residual tr)
+kfbi_status solve_report(kfbi_plan* pl, kfbi_info* info, const GmresOut& o, int k, double tr, double tol, int m) {
+  pl->last_iters = k;
+  HIPCHK(hipGetLastError());
+  kfbi_status s = o.conv ? KFBI_OK : KFBI_E_NOT_CONVERGED;
+  if (!isfinite(tr) || !isfinite(o.est)) s = KFBI_E_NONFINITE;
+  if (info) {
+    info->iters = k;
+    info->status = s;
+    info->est_rel_res = o.est;
+    info->true_rel_res = tr;
+  }
+  if (s == KFBI_E_NOT_CONVERGED) kfbi_set_error("GMRES did not reach tol %g in %d iterations", tol, m);
+  if (s == KFBI_E_NONFINITE) kfbi_set_error("non-finite residual");
+  return s;
+}
+
 kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* opts, double* psi, double* u_out,
                         kfbi_info* info, int m, double tol) {
   // Step 1: right-hand side
@@ -975,8 +1025,39 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
   // Steps 3-4; the first batch is the previous solve's iteration count on
   // this plan (at least 4: an over-long batch costs a few microseconds, a
   // short one a host round trip)
+  // final solve u = w(g1, E psi, ftilde, fhat, gB)
+  double* u = u_out ? u_out : pl->vsbuf;
+  auto final_solve = [&] {
+    op_extend(pl, psi, pl->aS);
+    simple_solve_impl(pl, data->g1, pl->aS, data->ftilde, data->fhat, data->gB, u, pl->dn_in, pl->dn_out);
+  };
+  // Without relaxation and from a zero start, on a graph key already solved
+  // with (a repeated problem, so the first batch, sized to the previous
+  // iteration count, usually converges), the update, the true residual and
+  // the final solve go out right behind the first batch: a solve that
+  // converges within it waits on the host once; otherwise they are redone
+  // after convergence.
+  struct SpecCtx {
+    kfbi_plan* pl;
+    double* psi;
+    decltype(final_solve)* fin;
+  } sc{pl, psi, &final_solve};
+  GmresSpec spec;
+  spec.active = !relax && !opts->use_x0 && pl->graph_uses > 1;
+  spec.ctx = &sc;
+  spec.before = [](void* c) {
+    SpecCtx* x = (SpecCtx*)c;
+    gm_update_device(x->pl, x->psi, 0);
+    matvec_impl(x->pl, x->psi, x->pl->work2);
+    gm_true_residual(x->pl, x->pl->bvec, x->pl->work2, x->pl->scal + 4);
+  };
+  spec.after = [](void* c) { (*((SpecCtx*)c)->fin)(); };
   GmresOut o;
-  KCHK(gmres_run(pl, tol, m, pl->last_iters > 4 ? (pl->last_iters < 64 ? pl->last_iters : 64) : 4, &o));
+  KCHK(gmres_run(pl, tol, m, pl->last_iters > 4 ? (pl->last_iters < 64 ? pl->last_iters : 64) : 4, &o, spec));
+  if (o.spec_ok) {
+    const double tr = pl->h_dpinned[5] > 0.0 ? sqrt(pl->h_dpinned[4] / pl->h_dpinned[5]) : 0.0;
+    return solve_report(pl, info, o, o.k, tr, tol, m);
+  }
   gm_update(pl, o.k, psi, opts->use_x0);
   pl->log_k = 0;
   if (relax && o.k > 0) {
@@ -984,14 +1065,8 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
     HIPCHK(hipMemcpyAsync(pl->h_log, pl->mg_ctl + 4, sizeof(int) * o.k, hipMemcpyDeviceToHost, pl->stream));
     pl->log_k = o.k;
   }
-  // final solve u = w(g1, E psi, ftilde, fhat, gB): without relaxation psi
-  // is final here, so it is enqueued before the host waits for the true
-  // residual
-  double* u = u_out ? u_out : pl->vsbuf;
-  auto final_solve = [&] {
-    op_extend(pl, psi, pl->aS);
-    simple_solve_impl(pl, data->g1, pl->aS, data->ftilde, data->fhat, data->gB, u, pl->dn_in, pl->dn_out);
-  };
+  // without relaxation psi is final here: the final solve is enqueued
+  // before the host waits for the true residual
   double tr = 0.0;
   if (relax)
     KCHK(true_residual(pl, psi, &tr));
@@ -1013,20 +1088,8 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
     o.est = o2.est;
     o.conv = o2.conv;
   }
-  pl->last_iters = k;
   if (relax) final_solve();
-  HIPCHK(hipGetLastError());
-  kfbi_status s = o.conv ? KFBI_OK : KFBI_E_NOT_CONVERGED;
-  if (!isfinite(tr) || !isfinite(o.est)) s = KFBI_E_NONFINITE;
-  if (info) {
-    info->iters = k;
-    info->status = s;
-    info->est_rel_res = o.est;
-    info->true_rel_res = tr;
-  }
-  if (s == KFBI_E_NOT_CONVERGED) kfbi_set_error("GMRES did not reach tol %g in %d iterations", tol, m);
-  if (s == KFBI_E_NONFINITE) kfbi_set_error("non-finite residual");
-  return s;
+  return solve_report(pl, info, o, k, tr, tol, m);
 }
 }  // namespace
 

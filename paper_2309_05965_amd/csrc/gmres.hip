@@ -548,9 +548,14 @@ __global__ void __launch_bounds__(AB) k_arn_finish(int64_t n, int* ctl, int ldh,
 // y = H^{-1} g (upper triangular, k x k), then x = x0 + V^T y.  The
 // triangle is staged in LDS (k <= 64) so the sequential back substitution
 // reads no global memory.
-__global__ void __launch_bounds__(256) k_trisolve(int k, int ldh, const double* Hm, const double* gv, double* y) {
+// kdev non-null: the iteration count is read from the device (the
+// GMRES control word), so the update can be enqueued before the host knows it
+__global__ void __launch_bounds__(256) k_trisolve(int k, const int* kdev, int ldh, const double* Hm, const double* gv,
+                                                 double* y) {
   __shared__ double H[64][65];
   __shared__ double gl[64];
+  if (kdev) k = *kdev;
+  if (k <= 0) return;
   if (k <= 64) {
     for (int t = threadIdx.x; t < k * k; t += blockDim.x) {
       int m = t / k, i = t % k;      // column m, row i
@@ -577,9 +582,10 @@ __global__ void __launch_bounds__(256) k_trisolve(int k, int ldh, const double* 
   }
 }
 
-__global__ void k_combine(int64_t n, int k, const double* V, const double* y, double* x, int use_x0) {
+__global__ void k_combine(int64_t n, int k, const int* kdev, const double* V, const double* y, double* x, int use_x0) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (i >= n) return;
+  if (kdev) k = *kdev;
   double s = use_x0 ? x[i] : 0.0;
   for (int m = 0; m < k; ++m) s += V[(int64_t)m * n + i] * y[m];
   x[i] = s;
@@ -650,11 +656,20 @@ void gm_arnoldi(kfbi_plan* pl) {
 int gm_part_blocks(int64_t n) { return (int)((n + AC - 1) / AC); }
 
 void gm_update(kfbi_plan* pl, int k, double* x, int use_x0) {
-  if (k > 0) hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(256), 0, pl->stream, k, pl->gm_cap + 1, pl->Hm, pl->gv,
-                                pl->scal + 8);
+  if (k > 0) hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(256), 0, pl->stream, k, nullptr, pl->gm_cap + 1, pl->Hm,
+                                pl->gv, pl->scal + 8);
   unsigned nbk = (unsigned)((pl->n_dof + KFBI_BLOCK - 1) / KFBI_BLOCK);
-  hipLaunchKernelGGL(k_combine, dim3(nbk), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_dof, k, pl->V, pl->scal + 8, x,
-                     use_x0);
+  hipLaunchKernelGGL(k_combine, dim3(nbk), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_dof, k, nullptr, pl->V,
+                     pl->scal + 8, x, use_x0);
+}
+
+// the same with the iteration count taken from the device control word
+void gm_update_device(kfbi_plan* pl, double* x, int use_x0) {
+  hipLaunchKernelGGL(k_trisolve, dim3(1), dim3(256), 0, pl->stream, 0, pl->ctl + 2, pl->gm_cap + 1, pl->Hm, pl->gv,
+                     pl->scal + 8);
+  unsigned nbk = (unsigned)((pl->n_dof + KFBI_BLOCK - 1) / KFBI_BLOCK);
+  hipLaunchKernelGGL(k_combine, dim3(nbk), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_dof, 0, pl->ctl + 2, pl->V,
+                     pl->scal + 8, x, use_x0);
 }
 
 void gm_true_residual(kfbi_plan* pl, const double* b, const double* Ax, double* out2) {

@@ -261,6 +261,7 @@ void gm_residual_start(kfbi_plan* pl, const double* b, const double* Ax0, int us
 void gm_arnoldi(kfbi_plan* pl);
 int gm_part_blocks(int64_t n);
 void gm_update(kfbi_plan* pl, int k, double* x, int use_x0);
+void gm_update_device(kfbi_plan* pl, double* x, int use_x0);
 void gm_true_residual(kfbi_plan* pl, const double* b, const double* Ax, double* out2);
 
 // ---------------------------------------------------------------- device helpers
