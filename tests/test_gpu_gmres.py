@@ -95,3 +95,26 @@ def test_solve_on_caller_stream():
     assert i1["status"] == 0 and i1["iters"] == i0["iters"] == i2["iters"]
     assert torch.equal(psi1, psi0) and torch.equal(u1, u0)
     assert torch.equal(psi2, psi0) and torch.equal(u2, u0)
+
+
+def test_speculative_tail_short_first_batch():
+    """On a plan solved before, the update, true residual and final solve go
+    out behind the first GMRES batch, sized to the previous iteration count.
+    When that batch is too short (a tighter tolerance than last time) the
+    speculative work is redone after convergence: the result equals a fresh
+    plan's bit for bit, and so does a repeat at the same tolerance."""
+    from paper_2309_05965_amd import kfbi
+    prob, sol = W.config2(128)
+    ref = kfbi.Plan(prob)
+    d = kfbi.device_data(ref, prob, sol)
+    psi_r, u_r, i_r = ref.solve(d, tol=1e-12)
+    gp = kfbi.Plan(prob)
+    _, _, i_lo = gp.solve(d, tol=1e-6)
+    _, _, _ = gp.solve(d, tol=1e-6)            # key reused from here on
+    psi1, u1, i1 = gp.solve(d, tol=1e-12)      # first batch too short
+    psi2, u2, i2 = gp.solve(d, tol=1e-12)      # first batch long enough
+    assert i_lo["iters"] < i_r["iters"]
+    assert i1["iters"] == i2["iters"] == i_r["iters"]
+    assert i1["true_rel_res"] == i_r["true_rel_res"] and i2["true_rel_res"] == i_r["true_rel_res"]
+    for p, u in ((psi1, u1), (psi2, u2)):
+        assert torch.equal(p, psi_r) and torch.equal(u, u_r)
