@@ -263,6 +263,9 @@ class Plan:
     def _zeros(self, n):
         return torch.zeros(n, dtype=torch.float64, device=self.device)
 
+    def _empty(self, n):
+        return torch.empty(n, dtype=torch.float64, device=self.device)
+
     # ------------------------------------------------------------------ operators
     def box_solve(self, F):
         v = self._zeros(self.n_nodes)
@@ -295,8 +298,9 @@ class Plan:
 
     def solve(self, data, tol=1e-10, max_iter=200, psi0=None, u_out=None, raise_on_fail=True):
         """Full KFBI solve; returns (psi, u, info dict)."""
-        psi = self._zeros(self.n_dof) if psi0 is None else psi0.clone()
-        u = self._zeros(self.n_nodes) if u_out is None else u_out
+        # every entry of psi (from a zero start) and of u is written by the solve
+        psi = self._empty(self.n_dof) if psi0 is None else psi0.clone()
+        u = self._empty(self.n_nodes) if u_out is None else u_out
         ds = self.data_struct(data)
         o = Opts(tol, max_iter, 0 if psi0 is None else 1)
         info = Info()
