@@ -26,7 +26,10 @@
  *    unless stated, and all work is ordered on the stream given to
  *    kfbi_plan_create.  Functions return after enqueueing work, except
  *    where a count or a convergence test needs the device (plan set-up,
- *    kfbi_solve), which synchronise the plan's stream.
+ *    kfbi_solve): those wait for the values they need, which a small
+ *    kernel writes into pinned host memory, not for the whole stream, so
+ *    work they enqueue after their last wait (the set-up's operator folds,
+ *    the solve's final solve) may still run when they return.
  *  - Grid arrays have (N+1)^d entries in node order i0 + (N+1) i1
  *    (+ (N+1)^2 i2) (x fastest); node x_i = lo + i h, h = (hi - lo)/N.
  *  - Surface arrays are indexed by the surface-point table of the plan
@@ -252,8 +255,11 @@ kfbi_status kfbi_rhs(kfbi_plan* plan, const kfbi_data* data, double* b);
 /* Full solve (Alg. 1): b, GMRES on kfbi_matvec to opts->tol, then
  * u = w(g1, E psi, ftilde, fhat, gB).  psi_inout [n_dof] (initial guess if
  * opts->use_x0, density on return); u_out [n_nodes] (may be NULL).
- * The host waits for the device a few times per solve (between batches of
- * captured GMRES iterations and for the true residual).  The iterations run
+ * The host waits for the device between batches of captured GMRES
+ * iterations and for the true residual; on a plan solved before (same graph
+ * key), without relaxation and from a zero start, the update, the true
+ * residual and the final solve are enqueued behind the first batch, so a
+ * solve that converges within it waits once.  The iterations run
  * as captured HIP graphs: on a plan created with a stream of the caller's
  * own they are captured and launched on that stream; on a default stream
  * (NULL, legacy or per-thread) the solve runs on a private stream of the
