@@ -131,6 +131,83 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
       }
 }
 
+// ---------------------------------------------------------------- few-row products
+// For a batch of at most GV_BMAX rows the 64 x 64 MFMA tiles leave almost
+// the whole chip idle (one tile row, K looped serially), so the forward pass
+// splits K instead: workgroup (x, y) multiplies the rows by a GV_KC-row
+// slab y of W for 256 columns x, fp32 accumulation of bf16 products, and
+// writes one partial per (row, column, slab); a second kernel sums the
+// slabs in a fixed order and applies the GEMM epilogue.  W row-major
+// [K x N], N and the row stride multiples of 8 (16-byte loads).
+constexpr int GV_BMAX = 4, GV_COLS = 256, GV_KC = 64;
+
+__global__ void __launch_bounds__(256) k_gemv_part(int B, int N, int K, const uint16_t* A, int lda,
+                                                   const uint16_t* W, int ldw, float* part) {
+  __shared__ float red[8][GV_BMAX][GV_COLS];
+  const int t = threadIdx.x, cg = t & 31, rg = t >> 5;
+  const int c0 = blockIdx.x * GV_COLS + cg * 8;
+  const int k0 = blockIdx.y * GV_KC;
+  const int k1 = K - k0 < GV_KC ? K : k0 + GV_KC;
+  float acc[GV_BMAX][8];
+#pragma unroll
+  for (int b = 0; b < GV_BMAX; ++b)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) acc[b][i] = 0.f;
+  if (c0 < N) {
+    for (int k = k0 + rg; k < k1; k += 8) {
+      const uint4 w = *reinterpret_cast<const uint4*>(W + (int64_t)k * ldw + c0);
+      const uint32_t wu[4] = {w.x, w.y, w.z, w.w};
+      float wf[8];
+#pragma unroll
+      for (int i = 0; i < 4; ++i) {
+        wf[2 * i] = __uint_as_float(wu[i] << 16);
+        wf[2 * i + 1] = __uint_as_float(wu[i] & 0xffff0000u);
+      }
+#pragma unroll
+      for (int b = 0; b < GV_BMAX; ++b) {
+        if (b < B) {
+          const float a = from_bf16(A[(int64_t)b * lda + k]);
+#pragma unroll
+          for (int i = 0; i < 8; ++i) acc[b][i] = fmaf(a, wf[i], acc[b][i]);
+        }
+      }
+    }
+  }
+#pragma unroll
+  for (int b = 0; b < GV_BMAX; ++b)
+#pragma unroll
+    for (int i = 0; i < 8; ++i) red[rg][b][cg * 8 + i] = acc[b][i];
+  __syncthreads();
+  const int nch = gridDim.y;
+  for (int e = t; e < B * GV_COLS; e += 256) {
+    const int b = e / GV_COLS, c = e % GV_COLS;
+    const int col = blockIdx.x * GV_COLS + c;
+    if (col >= N) continue;
+    float s = 0.f;
+#pragma unroll
+    for (int r = 0; r < 8; ++r) s += red[r][b][c];
+    part[((int64_t)b * N + col) * nch + blockIdx.y] = s;
+  }
+}
+
+// out[o] (o = row * N + column) = sum of the slabs (one wavefront per
+// output, fixed order) + bias; epilogue as in k_gemm (row stride N)
+__global__ void __launch_bounds__(256) k_gemv_sum(int BN, int N, int nch, const float* part, const float* bias,
+                                                  int relu_b, float* Cf, uint16_t* Cb) {
+  const int o = blockIdx.x * 4 + (threadIdx.x >> 6), lane = threadIdx.x & 63;
+  if (o >= BN) return;
+  const float* p = part + (int64_t)o * nch;
+  float s = 0.f;
+  for (int q = lane; q < nch; q += 64) s += p[q];
+#pragma unroll
+  for (int d = 32; d >= 1; d >>= 1) s += __shfl_xor(s, d);
+  if (lane == 0) {
+    const float v = bias ? s + bias[o % N] : s;
+    if (Cf) Cf[o] = v;
+    if (Cb) Cb[o] = to_bf16(relu_b && v < 0.f ? 0.f : v);
+  }
+}
+
 // ---------------------------------------------------------------- elementwise
 __global__ void k_to_bf16(int64_t n, const float* x, uint16_t* y) {
   int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -332,82 +409,184 @@ __device__ __forceinline__ void body_dir(const double* G, const double* x, doubl
   for (int k = 0; k < 3; ++k) d[k] = (Q[k] * dx[0] + Q[3 + k] * dx[1] + Q[6 + k] * dx[2]) / a[k];
 }
 
-// partial normal equations of a least-squares SH fit: per block, sums over
-// its points of Y Y^T (81 x 81) and Y v (81).  Points are either unit
-// directions (dirs) or positions mapped to body-frame directions (pos + G).
+// partial normal equations of a least-squares SH fit, Y^T Y c = Y^T v: the
+// lower triangle of Y^T Y (row-major, i >= j) followed by Y^T v, SH_E
+// entries.  Workgroup (g, y) sums over the point tiles g, g + G, g + 2G, ...
+// (G = gridDim.x) the entries y * FIT_EB ... of that list, four per thread.
+// Points are either unit directions (dirs) or positions mapped to
+// body-frame directions (pos + G).
 constexpr int FIT_PTS = 64;
+constexpr int FIT_EB = 1024;
+constexpr int FIT_NB = 64;                       // at most this many point groups
+constexpr int SH_T = SH_N * (SH_N + 1) / 2;
+constexpr int SH_E = SH_T + SH_N;
+constexpr int SH_EP = (SH_E + 255) / 256 * 256;  // partial stride (whole 256-entry rows)
+
+// (i, j), i >= j, of entry e of the row-major lower triangle
+__device__ __forceinline__ void tri_index(int e, int& i, int& j) {
+  int r = (int)((sqrt(8.0 * e + 1.0) - 1.0) * 0.5);
+  while (r * (r + 1) / 2 > e) --r;
+  while ((r + 1) * (r + 2) / 2 <= e) ++r;
+  i = r;
+  j = e - r * (r + 1) / 2;
+}
 
 __global__ void __launch_bounds__(256) k_sh_normal(int n, const double* dirs, const double* pos, const double* G,
                                                    const double* vals, const float* valsf, double scale,
                                                    double* part) {
-  __shared__ double Ys[FIT_PTS][SH_N];
-  __shared__ double vs[FIT_PTS];
-  const int p0 = blockIdx.x * FIT_PTS;
-  const int np = n - p0 < FIT_PTS ? n - p0 : FIT_PTS;
-  for (int q = threadIdx.x; q < np; q += blockDim.x) {
-    double d[3];
-    if (dirs) {
-      for (int k = 0; k < 3; ++k) d[k] = dirs[3 * (int64_t)(p0 + q) + k];
-    } else {
-      body_dir(G, pos + 3 * (int64_t)(p0 + q), d);
+  __shared__ double Ys[FIT_PTS][SH_N + 1];       // column SH_N holds v
+  int ei[4], ej[4];
+  double s[4];
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = blockIdx.y * FIT_EB + u * 256 + threadIdx.x;
+    s[u] = 0.0;
+    ei[u] = -1;
+    ej[u] = 0;
+    if (e < SH_T) {
+      tri_index(e, ei[u], ej[u]);
+    } else if (e < SH_E) {
+      ei[u] = e - SH_T;
+      ej[u] = SH_N;
     }
-    real_sh(d, Ys[q]);
-    vs[q] = vals ? vals[p0 + q] : scale * (double)valsf[p0 + q];
   }
-  __syncthreads();
-  double* out = part + (int64_t)blockIdx.x * (SH_N * SH_N + SH_N);
-  for (int e = threadIdx.x; e < SH_N * SH_N + SH_N; e += blockDim.x) {
-    double s = 0.0;
-    if (e < SH_N * SH_N) {
-      const int i = e / SH_N, j = e % SH_N;
-      for (int q = 0; q < np; ++q) s += Ys[q][i] * Ys[q][j];
-    } else {
-      const int i = e - SH_N * SH_N;
-      for (int q = 0; q < np; ++q) s += Ys[q][i] * vs[q];
+  for (int p0 = blockIdx.x * FIT_PTS; p0 < n; p0 += gridDim.x * FIT_PTS) {
+    const int np = n - p0 < FIT_PTS ? n - p0 : FIT_PTS;
+    __syncthreads();
+    for (int q = threadIdx.x; q < np; q += blockDim.x) {
+      double d[3];
+      if (dirs) {
+        for (int k = 0; k < 3; ++k) d[k] = dirs[3 * (int64_t)(p0 + q) + k];
+      } else {
+        body_dir(G, pos + 3 * (int64_t)(p0 + q), d);
+      }
+      real_sh(d, Ys[q]);
+      Ys[q][SH_N] = vals ? vals[p0 + q] : scale * (double)valsf[p0 + q];
     }
-    out[e] = s;
+    __syncthreads();
+#pragma unroll
+    for (int u = 0; u < 4; ++u)
+      if (ei[u] >= 0)
+        for (int q = 0; q < np; ++q) s[u] += Ys[q][ei[u]] * Ys[q][ej[u]];
+  }
+#pragma unroll
+  for (int u = 0; u < 4; ++u) {
+    const int e = blockIdx.y * FIT_EB + u * 256 + threadIdx.x;
+    if (e < SH_EP) part[(int64_t)blockIdx.x * SH_EP + e] = s[u];
   }
 }
 
-// sum of the partial normal equations (fixed order) and Cholesky solve,
-// one workgroup: coef = (Y^T Y)^-1 Y^T v
-__global__ void __launch_bounds__(256) k_sh_solve(int nblk, const double* part, double* coef) {
+__device__ __forceinline__ double lane_bcast(double v, int l) {
+  const long long u = __double_as_longlong(v);
+  const unsigned lo = (unsigned)__builtin_amdgcn_readlane((int)(u & 0xffffffffll), l);
+  const unsigned hi = (unsigned)__builtin_amdgcn_readlane((int)(u >> 32), l);
+  return __longlong_as_double((long long)(((unsigned long long)hi << 32) | lo));
+}
+
+// sum of the nb partial normal equations (fixed order), then the solve of
+// the 81 x 81 symmetric positive definite system in one workgroup:
+// right-looking LDL^T elimination (one barrier per pivot; each of 64 row
+// slots x 4 column phases updates its share of the trailing lower
+// triangle and the right-hand side), then back substitution with
+// L^T D on wavefront 0 (rows in lanes, the solved unknown broadcast from
+// its lane).  coef = (Y^T Y)^-1 Y^T v
+__global__ void __launch_bounds__(256) k_sh_solve(int nb, const double* part, double* coef) {
   __shared__ double A[SH_N][SH_N + 1];
   __shared__ double b[SH_N];
-  for (int e = threadIdx.x; e < SH_N * SH_N + SH_N; e += blockDim.x) {
-    double s = 0.0;
-    for (int k = 0; k < nblk; ++k) s += part[(int64_t)k * (SH_N * SH_N + SH_N) + e];
-    if (e < SH_N * SH_N)
-      A[e / SH_N][e % SH_N] = s;
-    else
-      b[e - SH_N * SH_N] = s;
+  __shared__ double cb[2][SH_N];
+  constexpr int EPT = SH_EP / 256;
+  const int t = threadIdx.x;
+  double s[EPT];
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) s[u] = 0.0;
+  // whole rows of the padded partials, two groups per pass so that their
+  // loads are in flight together (the padding entries are zeros)
+  int g = 0;
+  for (; g + 1 < nb; g += 2) {
+    const double* p0 = part + (int64_t)g * SH_EP + t;
+    double v0[EPT], v1[EPT];
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) {
+      v0[u] = p0[u * 256];
+      v1[u] = p0[SH_EP + u * 256];
+    }
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) s[u] += v0[u] + v1[u];
+  }
+  if (g < nb) {
+    const double* p0 = part + (int64_t)g * SH_EP + t;
+#pragma unroll
+    for (int u = 0; u < EPT; ++u) s[u] += p0[u * 256];
+  }
+#pragma unroll
+  for (int u = 0; u < EPT; ++u) {
+    const int e = u * 256 + t;
+    if (e < SH_T) {
+      int i, j;
+      tri_index(e, i, j);
+      A[i][j] = s[u];
+    } else if (e < SH_E) {
+      b[e - SH_T] = s[u];
+    }
+  }
+  // pivot column k is also kept in cb[k & 1] (a separate array, so its
+  // reads do not wait on the trailing update's stores); after pivot k,
+  // A[i][k] (i > k) holds L[i][k] d_k and b the forward-substituted
+  // right-hand side; the diagonal holds d
+  __syncthreads();
+  if (t < SH_N) cb[0][t] = A[t][0];
+  const int r = t >> 2, c = t & 3;
+  for (int k = 0; k < SH_N; ++k) {
+    __syncthreads();
+    const double* ck = cb[k & 1];
+    double* cn = cb[(k + 1) & 1];
+    const double inv = 1.0 / ck[k];
+    const double bk = b[k];
+    for (int i = k + 1 + r; i < SH_N; i += 64) {
+      const double f = ck[i] * inv;
+      double* Ai = A[i];
+      // columns j0, j0 + 4, ... <= i, eight at a time: the loads of a
+      // chunk are unconditional (column clamped to i, in the row) and all
+      // issued before its stores, which are the only guarded accesses
+      const int j0 = k + 1 + c;
+      const int nj = j0 <= i ? (i - j0) / 4 + 1 : 0;
+      double first = 0.0;
+      for (int m = 0; m < nj; m += 8) {
+        double av[8], cv[8];
+#pragma unroll
+        for (int u = 0; u < 8; ++u) {
+          const int j = min(j0 + 4 * (m + u), i);
+          av[u] = Ai[j];
+          cv[u] = ck[j];
+        }
+#pragma unroll
+        for (int u = 0; u < 8; ++u)
+          if (m + u < nj) {
+            const double v = av[u] - f * cv[u];
+            Ai[j0 + 4 * (m + u)] = v;
+            if (m + u == 0) first = v;
+          }
+      }
+      if (c == 0) {
+        cn[i] = first;
+        b[i] -= f * bk;
+      }
+    }
   }
   __syncthreads();
-  // right-looking Cholesky, A = L L^T (lower triangle)
-  for (int k = 0; k < SH_N; ++k) {
-    if (threadIdx.x == 0) A[k][k] = sqrt(A[k][k]);
-    __syncthreads();
-    for (int i = k + 1 + threadIdx.x; i < SH_N; i += blockDim.x) A[i][k] /= A[k][k];
-    __syncthreads();
-    for (int e = threadIdx.x; e < (SH_N - k - 1) * (SH_N - k - 1); e += blockDim.x) {
-      const int i = k + 1 + e / (SH_N - k - 1), j = k + 1 + e % (SH_N - k - 1);
-      if (j <= i) A[i][j] -= A[i][k] * A[j][k];
-    }
-    __syncthreads();
+  if (t >= 64) return;
+  // x_i = (y_i - sum_{j > i} A[j][i] x_j) / d_i, lanes own rows t and t + 64
+  const int i0 = t, i1 = t + 64;
+  const bool h1 = i1 < SH_N;
+  double a0 = b[i0], a1 = h1 ? b[i1] : 0.0;
+  const double r0 = 1.0 / A[i0][i0], r1 = h1 ? 1.0 / A[i1][i1] : 0.0;
+  for (int j = SH_N - 1; j > 0; --j) {
+    const double xj = lane_bcast(j >= 64 ? a1 * r1 : a0 * r0, j & 63);
+    if (i0 < j) a0 -= A[j][i0] * xj;
+    if (h1 && i1 < j) a1 -= A[j][i1] * xj;
   }
-  if (threadIdx.x == 0) {
-    for (int i = 0; i < SH_N; ++i) {       // L y = b
-      double s = b[i];
-      for (int j = 0; j < i; ++j) s -= A[i][j] * b[j];
-      b[i] = s / A[i][i];
-    }
-    for (int i = SH_N - 1; i >= 0; --i) {  // L^T x = y
-      double s = b[i];
-      for (int j = i + 1; j < SH_N; ++j) s -= A[j][i] * b[j];
-      b[i] = s / A[i][i];
-    }
-    for (int i = 0; i < SH_N; ++i) coef[i] = b[i];
-  }
+  coef[i0] = a0 * r0;
+  if (h1) coef[i1] = a1 * r1;
 }
 
 // values of the SH expansion at points (unit directions or body-frame
@@ -452,6 +631,7 @@ struct kfbi_mlp {
   float *dz, *da;
   uint16_t* dzb;
   double* part;
+  float* gv;                          // slab partials of the few-row forward
 };
 
 namespace {
@@ -480,6 +660,7 @@ void free_batch(kfbi_mlp* h) {
   dfree_t(h->da);
   dfree_t(h->dzb);
   dfree_t(h->part);
+  dfree_t(h->gv);
   h->cap = 0;
 }
 
@@ -496,6 +677,12 @@ kfbi_status ensure_batch(kfbi_mlp* h, int B) {
   KCHK(dalloc_t(&h->da, (int64_t)B * maxw));
   KCHK(dalloc_t(&h->dzb, (int64_t)B * maxw));
   KCHK(dalloc_t(&h->part, 1024));
+  int64_t gv = 0;
+  for (int l = 0; l < h->L; ++l) {
+    const int64_t n = (int64_t)GV_BMAX * h->w[l + 1] * ((h->w[l] + GV_KC - 1) / GV_KC);
+    gv = n > gv ? n : gv;
+  }
+  KCHK(dalloc_t(&h->gv, gv));
   h->cap = B;
   return KFBI_OK;
 }
@@ -517,8 +704,18 @@ void forward(kfbi_mlp* h, const float* X, int B) {
     const bool last = l == h->L - 1;
     // z_l = a_l W_l + b_l (fp32, kept for the backward mask) and
     // a_{l+1} = relu(z_l) (bf16, the next layer's operand)
-    gemm<false, false>(st, B, h->w[l + 1], h->w[l], h->a_b[l], h->w[l], h->wb + h->off_wb[l], h->w[l + 1],
-                       h->p + h->off_b[l], nullptr, 1, h->z[l], last ? nullptr : h->a_b[l + 1], h->w[l + 1]);
+    const int K = h->w[l], N = h->w[l + 1];
+    if (B <= GV_BMAX && N % 8 == 0 && h->off_wb[l] % 8 == 0) {
+      const int nch = (K + GV_KC - 1) / GV_KC;
+      hipLaunchKernelGGL(k_gemv_part, dim3((unsigned)((N + GV_COLS - 1) / GV_COLS), (unsigned)nch), dim3(256), 0, st,
+                         B, N, K, (const uint16_t*)h->a_b[l], K, (const uint16_t*)(h->wb + h->off_wb[l]), N, h->gv);
+      hipLaunchKernelGGL(k_gemv_sum, dim3(nbl((int64_t)B * N, 4)), dim3(256), 0, st, B * N, N, nch,
+                         (const float*)h->gv, (const float*)(h->p + h->off_b[l]), 1, h->z[l],
+                         last ? nullptr : h->a_b[l + 1]);
+    } else {
+      gemm<false, false>(st, B, N, K, h->a_b[l], K, h->wb + h->off_wb[l], N, h->p + h->off_b[l], nullptr, 1, h->z[l],
+                         last ? nullptr : h->a_b[l + 1], N);
+    }
   }
 }
 
@@ -749,20 +946,23 @@ extern "C" kfbi_status kfbi_ellipsoid_features(const double* geom, const double*
 }
 
 namespace {
-// part [nblk][SH_N^2 + SH_N] and coef [SH_N] in ws (at least sh_ws_len(n_in) values)
-int64_t sh_ws_len(int n_in) {
-  const int nblk = (n_in + FIT_PTS - 1) / FIT_PTS;
-  return (int64_t)nblk * (SH_N * SH_N + SH_N) + SH_N;
+// part [groups][SH_EP] and coef [SH_N] in ws (at least sh_ws_len(n_in) values)
+int sh_groups(int n_in) {
+  const int g = (n_in + FIT_PTS - 1) / FIT_PTS;
+  return g < FIT_NB ? g : FIT_NB;
 }
+
+int64_t sh_ws_len(int n_in) { return (int64_t)sh_groups(n_in) * SH_EP + SH_N; }
 
 void sh_fit_eval(hipStream_t st, double* ws, int n_in, const double* dirs_in, const double* pos_in,
                  const double* G, const double* vals, const float* valsf, double vscale, int n_out,
                  const double* dirs_out, const double* pos_out, double* out, float* outf, double oscale) {
-  const int nblk = (n_in + FIT_PTS - 1) / FIT_PTS;
+  const int ng = sh_groups(n_in);
   double* part = ws;
-  double* coef = ws + (int64_t)nblk * (SH_N * SH_N + SH_N);
-  hipLaunchKernelGGL(k_sh_normal, dim3(nblk), dim3(256), 0, st, n_in, dirs_in, pos_in, G, vals, valsf, vscale, part);
-  hipLaunchKernelGGL(k_sh_solve, dim3(1), dim3(256), 0, st, nblk, (const double*)part, coef);
+  double* coef = ws + (int64_t)ng * SH_EP;
+  hipLaunchKernelGGL(k_sh_normal, dim3(ng, (SH_E + FIT_EB - 1) / FIT_EB), dim3(256), 0, st, n_in, dirs_in, pos_in, G,
+                     vals, valsf, vscale, part);
+  hipLaunchKernelGGL(k_sh_solve, dim3(1), dim3(256), 0, st, ng, (const double*)part, coef);
   hipLaunchKernelGGL(k_sh_eval, dim3(nbl(n_out)), dim3(256), 0, st, n_out, dirs_out, pos_out, G,
                      (const double*)coef, out, outf, oscale);
 }

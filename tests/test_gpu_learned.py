@@ -96,7 +96,8 @@ def _small_mlp(widths, seed):
     return m, Ws, bs
 
 
-@pytest.mark.parametrize("widths,B", [((40, 24, 24, 16), 20), ((9216, 256, 256, 256, 1024), 64)])
+@pytest.mark.parametrize("widths,B", [((40, 24, 24, 16), 20), ((9216, 256, 256, 256, 1024), 64),
+                                      ((40, 24, 24, 16), 3), ((9216, 256, 256, 256, 1024), 1)])
 def test_mlp_forward_and_gradient_match_oracle(widths, B):
     m, Ws, bs = _small_mlp(widths, 7)
     rng = np.random.default_rng(8)
