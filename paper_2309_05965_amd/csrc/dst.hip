@@ -268,7 +268,10 @@ size_t tile_lds(int TL, int N) { return sizeof(double2) * 2 * (size_t)(TL / 2) *
 // work group waits on HBM once before its FFT stages.
 template <int LOGM, int MODE>
 __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
-  if (a.ctl && a.ctl[1]) return;
+  // the converged flag is read first but tested only once the tile's loads
+  // are in flight, so its latency overlaps theirs (a skipped pass has only
+  // read and staged in LDS)
+  const int stop = a.ctl ? a.ctl[1] : 0;
   constexpr int M = 1 << LOGM, N = M / 2, Mp = padded_len(M);
   extern __shared__ double2 lds[];
   const GridDesc& g = a.g;
@@ -333,6 +336,7 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
     }
   }
   __syncthreads();
+  if (stop) return;
   double2* R = fft_stockham<LOGM>(A, B, T, nf);
   if (MODE == 1) {
     // S_A(k) = -Im Z_k / 2 (even line), S_B(k) = Re Z_k / 2 (odd line); divide

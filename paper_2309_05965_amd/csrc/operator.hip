@@ -628,16 +628,34 @@ template <int G>
 __global__ void __launch_bounds__(KFBI_BLOCK) k_centry(int64_t n_corr, int nF, const int* FI, const double* FW,
                                                       const double* psi, double* Cv, const int* ctl,
                                                       const double* Vb, int64_t n_dof) {
+  // the iteration state is read first and used only after the entry's
+  // first index / weight loads are issued (they do not depend on it)
+  int stop = 0;
+  int64_t jv = 0;
   if (ctl) {
-    if (ctl[1]) return;
-    psi = Vb + (int64_t)ctl[0] * n_dof;
+    stop = ctl[1];
+    jv = ctl[0];
   }
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t e = t / G;
   int lane = (int)(t % G);
   if (e >= n_corr) return;
+  constexpr int PRE = 2;
+  int fi[PRE];
+  double fw[PRE];
+#pragma unroll
+  for (int u = 0; u < PRE; ++u) {
+    const int q = lane + u * G;
+    fi[u] = q < nF ? FI[e * nF + q] : 0;
+    fw[u] = q < nF ? FW[e * nF + q] : 0.0;
+  }
+  if (stop) return;
+  if (ctl) psi = Vb + jv * n_dof;
   double s = 0.0;
-  for (int q = lane; q < nF; q += G) s += FW[e * nF + q] * psi[FI[e * nF + q]];
+#pragma unroll
+  for (int u = 0; u < PRE; ++u)
+    if (lane + u * G < nF) s += fw[u] * psi[fi[u]];
+  for (int q = lane + PRE * G; q < nF; q += G) s += FW[e * nF + q] * psi[FI[e * nF + q]];
   for (int off = G / 2; off > 0; off >>= 1) s += __shfl_xor(s, off, G);
   if (lane == 0) Cv[e] = s;
 }
@@ -688,10 +706,13 @@ struct InterpArgs {
 // one group of G lanes per centre: sum_b IW[c][b] vtilde(b), then the combine
 template <int G>
 __global__ void __launch_bounds__(KFBI_BLOCK) k_interp(InterpArgs a) {
+  // the iteration state is read first and used only after the box-solution
+  // sum (which does not depend on it) has its loads in flight
+  int stop = 0;
+  int64_t jv = 0;
   if (a.ctl) {
-    if (a.ctl[1]) return;
-    a.psi = a.Vb + (int64_t)a.ctl[0] * a.n_dof;
-    a.Apsi = a.Vb + (int64_t)(a.ctl[0] + 1) * a.n_dof;
+    stop = a.ctl[1];
+    jv = a.ctl[0];
   }
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t c = t / G;
@@ -716,6 +737,11 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_interp(InterpArgs a) {
       if (e2 >= 0) vt -= a.Cv[e2];
     }
     acc += w[b] * vt;
+  }
+  if (stop) return;
+  if (a.ctl) {
+    a.psi = a.Vb + jv * a.n_dof;
+    a.Apsi = a.Vb + (jv + 1) * a.n_dof;
   }
   // the centre's own polynomial at the block nodes outside its region
   double dnC = 0.0;
