@@ -153,6 +153,121 @@ __device__ double2* fft_stockham(double2* a, double2* b, const Twiddles<LOGM>& T
   return a;
 }
 
+// ---------------------------------------------------------------- four-step FFT, M = 1024
+// One sequence per work group (TL = 2) of length 1024 = 16 x 64, x[64 n1 +
+// n2] -> X[k1 + 16 k2]: 64 DFTs of length 16 over n1, a quad of lanes per
+// n2 (each lane a radix-4 over n1 = c + 4m, then a radix-4 across the quad
+// exchanged by DPP), the twiddle w^(n2 k1), one transpose through LDS, then
+// 16 DFTs of length 64 over n2, a 16-lane row per k1 (each lane a radix-4
+// over n2 = d + 16m, then a 16-point DFT across the row as two radix-4
+// steps exchanged by DPP).  Each cross-lane radix-4 is two radix-2 steps
+// with one exchange each, its outputs in bit-reversed lane order.  Two LDS round trips and two barriers instead of
+// the five of the radix-4 Stockham stages; w = exp(-2 pi i / 1024).
+constexpr int DPP_QX1 = 0xB1, DPP_QX2 = 0x4E, DPP_QX3 = 0x1B;   // quad_perm: lane i ^ 1, i ^ 2, i ^ 3
+constexpr int DPP_ROR8 = 0x128;                                 // row_ror:8: lane i ^ 8 of the row
+constexpr int DPP_MIRROR = 0x140;                               // row_mirror: lane 15 - i of the row
+
+template <int CTRL>
+__device__ __forceinline__ double dpp_d(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+
+template <int CTRL>
+__device__ __forceinline__ double2 dpp2(double2 v) {
+  return make_double2(dpp_d<CTRL>(v.x), dpp_d<CTRL>(v.y));
+}
+
+// radix-4 DFT of four values held by one lane, natural order
+__device__ __forceinline__ void dft4(double2 (&v)[4]) {
+  const double2 s0 = make_double2(v[0].x + v[2].x, v[0].y + v[2].y), d0 = make_double2(v[0].x - v[2].x, v[0].y - v[2].y);
+  const double2 s1 = make_double2(v[1].x + v[3].x, v[1].y + v[3].y), d1 = make_double2(v[1].x - v[3].x, v[1].y - v[3].y);
+  v[0] = make_double2(s0.x + s1.x, s0.y + s1.y);
+  v[1] = make_double2(d0.x + d1.y, d0.y - d1.x);
+  v[2] = make_double2(s0.x - s1.x, s0.y - s1.y);
+  v[3] = make_double2(d0.x - d1.y, d0.y + d1.x);
+}
+
+// radix-2 step between a lane and its partner u (the DPP-exchanged value):
+// the lower lane of the pair keeps v + u, the upper one u - v (a multiply
+// by -1 is exact, so both are the correctly rounded sum / difference)
+__device__ __forceinline__ double2 bfly(double2 v, double2 u, bool upper) {
+  const double sg = upper ? -1.0 : 1.0;
+  return make_double2(fma(v.x, sg, u.x), fma(v.y, sg, u.y));
+}
+
+// v (-i) where m
+__device__ __forceinline__ double2 mi_if(double2 v, bool m) { return m ? make_double2(v.y, -v.x) : v; }
+
+// a 4-point DFT across the lanes g = 0..3 of a group as two radix-2 steps
+// (partners g ^ 2, then g ^ 1); lane g ends with output bit-reversed g
+__device__ __forceinline__ int brev2(int g) { return ((g & 1) << 1) | (g >> 1); }
+
+// the thread's fixed twiddles
+struct Tw4 {
+  double2 q[3];   // w^(64 c k), k = 1..3
+  double2 t[4];   // w^(n2 (k + 4 brev2(c))), k = 0..3
+  double2 r[3];   // w^(16 d k), k = 1..3
+  double2 s;      // w^(64 d0 brev2(d1))
+  __device__ __forceinline__ void load(const double2* __restrict__ tw) {
+    const int th = threadIdx.x, n2 = th >> 2, c = th & 3, d = th & 15;
+#pragma unroll
+    for (int k = 1; k < 4; ++k) {
+      q[k - 1] = tw[64 * c * k];
+      r[k - 1] = tw[16 * d * k];
+    }
+#pragma unroll
+    for (int k = 0; k < 4; ++k) t[k] = tw[n2 * (k + 4 * brev2(c))];
+    s = tw[64 * (d & 3) * brev2(d >> 2)];
+  }
+};
+
+// forward DFT of the sequence in a (natural order, padded layout); b is
+// scratch; the result is in a
+__device__ double2* fft1024_4step(double2* a, double2* b, const Tw4& T) {
+  const int th = threadIdx.x;
+  {
+    const int n2 = th >> 2, c = th & 3;
+    double2 v[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = a[padi(64 * (c + 4 * m) + n2)];
+    dft4(v);
+#pragma unroll
+    for (int k = 1; k < 4; ++k) v[k] = cmul(v[k], T.q[k - 1]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      double2 y = mi_if(bfly(v[k], dpp2<DPP_QX2>(v[k]), c & 2), c == 3);
+      y = bfly(y, dpp2<DPP_QX1>(y), c & 1);
+      b[padi(64 * (k + 4 * brev2(c)) + n2)] = cmul(y, T.t[k]);
+    }
+  }
+  __syncthreads();
+  {
+    const int k1 = th >> 4, d = th & 15, d0 = d & 3, d1 = d >> 2;
+    double2 v[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = b[padi(64 * k1 + d + 16 * m)];
+    dft4(v);
+#pragma unroll
+    for (int k = 1; k < 4; ++k) v[k] = cmul(v[k], T.r[k - 1]);
+#pragma unroll
+    for (int k = 0; k < 4; ++k) {
+      // across d1 (row lanes d ^ 8, then d ^ 4 = mirror, quad ^ 3, ^ 8), then
+      // across d0 (the quad: ^ 2, then ^ 1)
+      double2 y = mi_if(bfly(v[k], dpp2<DPP_ROR8>(v[k]), d1 & 2), d1 == 3);
+      y = bfly(y, dpp2<DPP_ROR8>(dpp2<DPP_QX3>(dpp2<DPP_MIRROR>(y))), d1 & 1);
+      y = cmul(y, T.s);
+      y = mi_if(bfly(y, dpp2<DPP_QX2>(y), d0 & 2), d0 == 3);
+      y = bfly(y, dpp2<DPP_QX1>(y), d0 & 1);
+      a[padi(k1 + 16 * (k + 4 * (brev2(d1) + 4 * brev2(d0))))] = y;
+    }
+  }
+  __syncthreads();
+  return a;
+}
+
 // address of element j (0..N along the axis) of the line at tile
 // coordinate u and remaining coordinate w
 __device__ __forceinline__ int64_t elem_addr(const DstArgs& a, int u, int w, int j) {
@@ -266,8 +381,9 @@ size_t tile_lds(int TL, int N) { return sizeof(double2) * 2 * (size_t)(TL / 2) *
 // 2^LOGM.  Every global load the tile needs -- the input, the thread's
 // twiddles and (MODE 1) the 1D eigenvalues -- is issued up front, so the
 // work group waits on HBM once before its FFT stages.
-template <int LOGM, int MODE>
+template <int LOGM, int MODE, bool FS>
 __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
+  static_assert(!FS || LOGM == 10, "the four-step FFT is written for M = 1024");
   // the converged flag is read first but tested only once the tile's loads
   // are in flight, so its latency overlaps theirs (a skipped pass has only
   // read and staged in LDS)
@@ -286,7 +402,11 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
   constexpr int nl = N - 1;
   const int total = TL * nl;
   Twiddles<LOGM> T;
-  T.load(a.tw);
+  Tw4 T4;
+  if constexpr (FS)
+    T4.load(a.tw);
+  else
+    T.load(a.tw);
   // MODE 1: s_k for this thread's k = threadIdx.x + 256 q, s_u of the
   // tile's lines and s_w
   constexpr int NE = MODE == 1 ? (N + KFBI_BLOCK - 1) / KFBI_BLOCK : 1;
@@ -337,7 +457,11 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
   }
   __syncthreads();
   if (stop) return;
-  double2* R = fft_stockham<LOGM>(A, B, T, nf);
+  double2* R;
+  if constexpr (FS)
+    R = fft1024_4step(A, B, T4);
+  else
+    R = fft_stockham<LOGM>(A, B, T, nf);
   if (MODE == 1) {
     // S_A(k) = -Im Z_k / 2 (even line), S_B(k) = Re Z_k / 2 (odd line); divide
     // by lambda, scale, and form the odd sequences of the inverse transform.
@@ -364,7 +488,10 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
       }
     }
     __syncthreads();
-    R = fft_stockham<LOGM>(S, R, T, nf);
+    if constexpr (FS)
+      R = fft1024_4step(S, R, T4);
+    else
+      R = fft_stockham<LOGM>(S, R, T, nf);
   }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     int l, k;
@@ -395,10 +522,21 @@ int tile_lines(int d, int N) {
 
 template <int LOGM>
 void launch_t(const DstArgs& a, unsigned blocks, size_t lds, hipStream_t st) {
+  // one sequence of 1024 per work group: the four-step FFT (256 threads, one
+  // per radix-4 of each step)
+  if constexpr (LOGM == 10) {
+    if (a.TL == 2 && KFBI_BLOCK == 256) {
+      if (a.mode == 1)
+        hipLaunchKernelGGL((k_dst<10, 1, true>), dim3(blocks), dim3(KFBI_BLOCK), lds, st, a);
+      else
+        hipLaunchKernelGGL((k_dst<10, 0, true>), dim3(blocks), dim3(KFBI_BLOCK), lds, st, a);
+      return;
+    }
+  }
   if (a.mode == 1)
-    hipLaunchKernelGGL((k_dst<LOGM, 1>), dim3(blocks), dim3(KFBI_BLOCK), lds, st, a);
+    hipLaunchKernelGGL((k_dst<LOGM, 1, false>), dim3(blocks), dim3(KFBI_BLOCK), lds, st, a);
   else
-    hipLaunchKernelGGL((k_dst<LOGM, 0>), dim3(blocks), dim3(KFBI_BLOCK), lds, st, a);
+    hipLaunchKernelGGL((k_dst<LOGM, 0, false>), dim3(blocks), dim3(KFBI_BLOCK), lds, st, a);
 }
 
 void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out, bool src_corr = false) {
