@@ -165,7 +165,7 @@ __device__ double2* fft_stockham(double2* a, double2* b, const Twiddles<LOGM>& T
 // the five of the radix-4 Stockham stages; w = exp(-2 pi i / 1024).
 constexpr int DPP_QX1 = 0xB1, DPP_QX2 = 0x4E, DPP_QX3 = 0x1B;   // quad_perm: lane i ^ 1, i ^ 2, i ^ 3
 constexpr int DPP_ROR8 = 0x128;                                 // row_ror:8: lane i ^ 8 of the row
-constexpr int DPP_MIRROR = 0x140;                               // row_mirror: lane 15 - i of the row
+constexpr int DPP_HMIRROR = 0x141;                              // row_half_mirror: lane i ^ 7 of the row
 
 template <int CTRL>
 __device__ __forceinline__ double dpp_d(double v) {
@@ -254,10 +254,10 @@ __device__ double2* fft1024_4step(double2* a, double2* b, const Tw4& T) {
     for (int k = 1; k < 4; ++k) v[k] = cmul(v[k], T.r[k - 1]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      // across d1 (row lanes d ^ 8, then d ^ 4 = mirror, quad ^ 3, ^ 8), then
+      // across d1 (row lanes d ^ 8, then d ^ 4 = half mirror, quad ^ 3), then
       // across d0 (the quad: ^ 2, then ^ 1)
       double2 y = mi_if(bfly(v[k], dpp2<DPP_ROR8>(v[k]), d1 & 2), d1 == 3);
-      y = bfly(y, dpp2<DPP_ROR8>(dpp2<DPP_QX3>(dpp2<DPP_MIRROR>(y))), d1 & 1);
+      y = bfly(y, dpp2<DPP_QX3>(dpp2<DPP_HMIRROR>(y)), d1 & 1);
       y = cmul(y, T.s);
       y = mi_if(bfly(y, dpp2<DPP_QX2>(y), d0 & 2), d0 == 3);
       y = bfly(y, dpp2<DPP_QX1>(y), d0 & 1);
