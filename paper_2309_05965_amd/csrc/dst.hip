@@ -224,31 +224,35 @@ struct Tw4 {
   }
 };
 
-// forward DFT of the sequence in a (natural order, padded layout); b is
-// scratch; the result is in a
-__device__ double2* fft1024_4step(double2* a, double2* b, const Tw4& T) {
+// the output index of value q (0..3) of this thread after step 2
+__device__ __forceinline__ int fs_out_index(int q) {
+  const int th = threadIdx.x, k1 = th >> 4, d = th & 15;
+  return k1 + 16 * (q + 4 * (brev2(d >> 2) + 4 * brev2(d & 3)));
+}
+
+// forward DFT of the 1024-point sequence whose elements 64 (c + 4m) + n2,
+// m = 0..3, this thread holds in v (n2 = thread / 4, c = thread mod 4); x
+// is the LDS transpose buffer; y[q] = X[fs_out_index(q)].  Ends with no
+// barrier after the reads of x.
+__device__ __forceinline__ void fft1024_regs(double2 (&v)[4], double2* x, const Tw4& T, double2 (&y)[4]) {
   const int th = threadIdx.x;
   {
     const int n2 = th >> 2, c = th & 3;
-    double2 v[4];
-#pragma unroll
-    for (int m = 0; m < 4; ++m) v[m] = a[padi(64 * (c + 4 * m) + n2)];
     dft4(v);
 #pragma unroll
     for (int k = 1; k < 4; ++k) v[k] = cmul(v[k], T.q[k - 1]);
 #pragma unroll
     for (int k = 0; k < 4; ++k) {
-      double2 y = mi_if(bfly(v[k], dpp2<DPP_QX2>(v[k]), c & 2), c == 3);
-      y = bfly(y, dpp2<DPP_QX1>(y), c & 1);
-      b[padi(64 * (k + 4 * brev2(c)) + n2)] = cmul(y, T.t[k]);
+      double2 z = mi_if(bfly(v[k], dpp2<DPP_QX2>(v[k]), c & 2), c == 3);
+      z = bfly(z, dpp2<DPP_QX1>(z), c & 1);
+      x[padi(64 * (k + 4 * brev2(c)) + n2)] = cmul(z, T.t[k]);
     }
   }
   __syncthreads();
   {
     const int k1 = th >> 4, d = th & 15, d0 = d & 3, d1 = d >> 2;
-    double2 v[4];
 #pragma unroll
-    for (int m = 0; m < 4; ++m) v[m] = b[padi(64 * k1 + d + 16 * m)];
+    for (int m = 0; m < 4; ++m) v[m] = x[padi(64 * k1 + d + 16 * m)];
     dft4(v);
 #pragma unroll
     for (int k = 1; k < 4; ++k) v[k] = cmul(v[k], T.r[k - 1]);
@@ -256,14 +260,25 @@ __device__ double2* fft1024_4step(double2* a, double2* b, const Tw4& T) {
     for (int k = 0; k < 4; ++k) {
       // across d1 (row lanes d ^ 8, then d ^ 4 = half mirror, quad ^ 3), then
       // across d0 (the quad: ^ 2, then ^ 1)
-      double2 y = mi_if(bfly(v[k], dpp2<DPP_ROR8>(v[k]), d1 & 2), d1 == 3);
-      y = bfly(y, dpp2<DPP_QX3>(dpp2<DPP_HMIRROR>(y)), d1 & 1);
-      y = cmul(y, T.s);
-      y = mi_if(bfly(y, dpp2<DPP_QX2>(y), d0 & 2), d0 == 3);
-      y = bfly(y, dpp2<DPP_QX1>(y), d0 & 1);
-      a[padi(k1 + 16 * (k + 4 * (brev2(d1) + 4 * brev2(d0))))] = y;
+      double2 z = mi_if(bfly(v[k], dpp2<DPP_ROR8>(v[k]), d1 & 2), d1 == 3);
+      z = bfly(z, dpp2<DPP_QX3>(dpp2<DPP_HMIRROR>(z)), d1 & 1);
+      z = cmul(z, T.s);
+      z = mi_if(bfly(z, dpp2<DPP_QX2>(z), d0 & 2), d0 == 3);
+      y[k] = bfly(z, dpp2<DPP_QX1>(z), d0 & 1);
     }
   }
+}
+
+// forward DFT of the sequence in a (natural order, padded layout); b is
+// scratch; the result is in a
+__device__ double2* fft1024_4step(double2* a, double2* b, const Tw4& T) {
+  const int th = threadIdx.x, n2 = th >> 2, c = th & 3;
+  double2 v[4], y[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) v[m] = a[padi(64 * (c + 4 * m) + n2)];
+  fft1024_regs(v, b, T, y);
+#pragma unroll
+  for (int q = 0; q < 4; ++q) a[padi(fs_out_index(q))] = y[q];
   __syncthreads();
   return a;
 }
@@ -503,6 +518,88 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
   }
 }
 
+// One axis pass over two lines of 511 interior nodes (N = 512, TL = 2,
+// sequences of M = 1024) with the four-step FFT and no staging: each thread
+// loads the four elements of the odd extension its first step needs
+// straight from global memory (z[j] = (A_j, B_j), z[M - j] = -z[j], z[0] =
+// z[N] = 0 for the tile's lines A and B), and stores the sine coefficients
+// of the four outputs it ends with straight to global memory.  MODE 1
+// divides those outputs by the eigenvalues, writes the odd extension of the
+// divided spectrum to LDS and transforms it again.  The values equal those
+// of k_dst<10, MODE, true> bit for bit (same arithmetic in the same order).
+template <int MODE>
+__global__ void __launch_bounds__(KFBI_BLOCK) k_dst1024(DstArgs a) {
+  const int stop = a.ctl ? a.ctl[1] : 0;
+  constexpr int M = 1024, N = 512, nl = N - 1, Mp = padded_len(M);
+  __shared__ double2 S[MODE == 1 ? Mp : 1];   // divided spectrum (MODE 1)
+  __shared__ double2 X[Mp];                   // transpose buffer
+  const GridDesc& g = a.g;
+  const int tile = kfbi_xcd_block(blockIdx.x, gridDim.x);
+  const int w = tile / a.tiles_u + 1;
+  const int u0 = 1 + (tile % a.tiles_u) * 2;
+  const bool hasB = u0 + 1 <= nl;
+  const int th = threadIdx.x, n2 = th >> 2, c = th & 3;
+  Tw4 T;
+  T.load(a.tw);
+  double xa[4], xb[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const int j = 64 * (c + 4 * m) + n2;
+    const int jj = j < N ? j : M - j;
+    const bool ok = jj >= 1 && jj <= nl;
+    xa[m] = ok ? a.in[elem_addr(a, u0, w, jj)] : 0.0;
+    xb[m] = ok && hasB ? a.in[elem_addr(a, u0 + 1, w, jj)] : 0.0;
+  }
+  int kk[4];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) kk[q] = fs_out_index(q);
+  double sk[4], suA = 0.0, suB = 0.0, sw = 0.0;
+  if (MODE == 1) {
+#pragma unroll
+    for (int q = 0; q < 4; ++q) sk[q] = (kk[q] >= 1 && kk[q] <= nl) ? a.eig1[kk[q]] : 0.0;
+    suA = a.eig1[u0];
+    suB = a.eig1[hasB ? u0 + 1 : 1];
+    if (g.d == 3) sw = a.eig1[w];
+  }
+  if (stop) return;
+  double2 v[4], y[4];
+#pragma unroll
+  for (int m = 0; m < 4; ++m) {
+    const bool lower = 64 * (c + 4 * m) + n2 < N;
+    v[m] = lower ? make_double2(xa[m], xb[m]) : make_double2(-xa[m], -xb[m]);
+  }
+  fft1024_regs(v, X, T, y);
+  if (MODE == 1) {
+    // S_A(k) = -Im Z_k / 2, S_B(k) = Re Z_k / 2, divided by lambda and
+    // scaled, as the odd sequence of the inverse transform
+    if (th == 0) {
+      S[padi(0)] = make_double2(0.0, 0.0);
+      S[padi(N)] = make_double2(0.0, 0.0);
+    }
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = kk[q];
+      if (k < 1 || k > nl) continue;
+      const double lamA = eigenvalue(g, sk[q], suA, sw);
+      const double lamB = eigenvalue(g, sk[q], suB, sw);
+      const double2 cf = make_double2(a.scale * (-0.5 * y[q].y) / lamA, a.scale * (0.5 * y[q].x) / lamB);
+      S[padi(k)] = cf;
+      S[padi(M - k)] = make_double2(-cf.x, -cf.y);
+    }
+    __syncthreads();
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = S[padi(64 * (c + 4 * m) + n2)];
+    fft1024_regs(v, X, T, y);
+  }
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const int k = kk[q];
+    if (k < 1 || k > nl) continue;
+    a.out[elem_addr(a, u0, w, k)] = -0.5 * y[q].y;
+    if (hasB) a.out[elem_addr(a, u0 + 1, w, k)] = 0.5 * y[q].x;
+  }
+}
+
 // lines per tile: the largest even TL <= 8 whose LDS footprint still lets
 // 4 work groups (16 waves) share a compute unit and that leaves at least
 // 1024 tiles (4 per compute unit); else 2.  More lines per tile amortise a
@@ -565,6 +662,13 @@ void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out,
   a.scale = 1.0;
   for (int t = 0; t < pl->g.d; ++t) a.scale *= 2.0 / N;
   const unsigned blocks = (unsigned)(a.tiles_u * (pl->g.d == 3 ? nl : 1));
+  if (N == 512 && a.TL == 2 && !src_corr && KFBI_BLOCK == 256) {
+    if (mode == 1)
+      hipLaunchKernelGGL(k_dst1024<1>, dim3(blocks), dim3(KFBI_BLOCK), 0, pl->stream, a);
+    else
+      hipLaunchKernelGGL(k_dst1024<0>, dim3(blocks), dim3(KFBI_BLOCK), 0, pl->stream, a);
+    return;
+  }
   const size_t lds = tile_lds(a.TL, N);
   switch (N) {   // N is a power of two in [8, 1024]
     case 8: launch_t<4>(a, blocks, lds, pl->stream); break;
