@@ -269,20 +269,6 @@ __device__ __forceinline__ void fft1024_regs(double2 (&v)[4], double2* x, const 
   }
 }
 
-// forward DFT of the sequence in a (natural order, padded layout); b is
-// scratch; the result is in a
-__device__ double2* fft1024_4step(double2* a, double2* b, const Tw4& T) {
-  const int th = threadIdx.x, n2 = th >> 2, c = th & 3;
-  double2 v[4], y[4];
-#pragma unroll
-  for (int m = 0; m < 4; ++m) v[m] = a[padi(64 * (c + 4 * m) + n2)];
-  fft1024_regs(v, b, T, y);
-#pragma unroll
-  for (int q = 0; q < 4; ++q) a[padi(fs_out_index(q))] = y[q];
-  __syncthreads();
-  return a;
-}
-
 // address of element j (0..N along the axis) of the line at tile
 // coordinate u and remaining coordinate w
 __device__ __forceinline__ int64_t elem_addr(const DstArgs& a, int u, int w, int j) {
@@ -398,7 +384,7 @@ size_t tile_lds(int TL, int N) { return sizeof(double2) * 2 * (size_t)(TL / 2) *
 // work group waits on HBM once before its FFT stages.
 template <int LOGM, int MODE, bool FS>
 __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
-  static_assert(!FS || LOGM == 10, "the four-step FFT is written for M = 1024");
+  static_assert(!FS || (LOGM == 10 && MODE == 0), "the four-step FFT is written for M = 1024, one transform");
   // the converged flag is read first but tested only once the tile's loads
   // are in flight, so its latency overlaps theirs (a skipped pass has only
   // read and staged in LDS)
@@ -472,11 +458,24 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
   }
   __syncthreads();
   if (stop) return;
-  double2* R;
-  if constexpr (FS)
-    R = fft1024_4step(A, B, T4);
-  else
-    R = fft_stockham<LOGM>(A, B, T, nf);
+  if constexpr (FS) {
+    // one sequence (nf = 1): the four-step FFT from the staged tile, the
+    // sine coefficients stored straight from its registers
+    const int th = threadIdx.x, n2 = th >> 2, c = th & 3;
+    double2 v[4], y[4];
+#pragma unroll
+    for (int m = 0; m < 4; ++m) v[m] = A[padi(64 * (c + 4 * m) + n2)];
+    fft1024_regs(v, B, T4, y);
+#pragma unroll
+    for (int q = 0; q < 4; ++q) {
+      const int k = fs_out_index(q);
+      if (k < 1 || k > nl) continue;
+      a.out[elem_addr(a, u0, w, k)] = -0.5 * y[q].y;
+      if (u0 + 1 <= nl) a.out[elem_addr(a, u0 + 1, w, k)] = 0.5 * y[q].x;
+    }
+    return;
+  }
+  double2* R = fft_stockham<LOGM>(A, B, T, nf);
   if (MODE == 1) {
     // S_A(k) = -Im Z_k / 2 (even line), S_B(k) = Re Z_k / 2 (odd line); divide
     // by lambda, scale, and form the odd sequences of the inverse transform.
@@ -503,10 +502,7 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
       }
     }
     __syncthreads();
-    if constexpr (FS)
-      R = fft1024_4step(S, R, T4);
-    else
-      R = fft_stockham<LOGM>(S, R, T, nf);
+    R = fft_stockham<LOGM>(S, R, T, nf);
   }
   for (int idx = threadIdx.x; idx < total; idx += blockDim.x) {
     int l, k;
@@ -525,8 +521,7 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
 // z[N] = 0 for the tile's lines A and B), and stores the sine coefficients
 // of the four outputs it ends with straight to global memory.  MODE 1
 // divides those outputs by the eigenvalues, writes the odd extension of the
-// divided spectrum to LDS and transforms it again.  The values equal those
-// of k_dst<10, MODE, true> bit for bit (same arithmetic in the same order).
+// divided spectrum to LDS and transforms it again.
 template <int MODE>
 __global__ void __launch_bounds__(KFBI_BLOCK) k_dst1024(DstArgs a) {
   const int stop = a.ctl ? a.ctl[1] : 0;
@@ -619,14 +614,11 @@ int tile_lines(int d, int N) {
 
 template <int LOGM>
 void launch_t(const DstArgs& a, unsigned blocks, size_t lds, hipStream_t st) {
-  // one sequence of 1024 per work group: the four-step FFT (256 threads, one
-  // per radix-4 of each step)
+  // one sequence of 1024 per work group (the corrected right-hand side's
+  // pass; the others go to k_dst1024): the four-step FFT
   if constexpr (LOGM == 10) {
-    if (a.TL == 2 && KFBI_BLOCK == 256) {
-      if (a.mode == 1)
-        hipLaunchKernelGGL((k_dst<10, 1, true>), dim3(blocks), dim3(KFBI_BLOCK), lds, st, a);
-      else
-        hipLaunchKernelGGL((k_dst<10, 0, true>), dim3(blocks), dim3(KFBI_BLOCK), lds, st, a);
+    if (a.TL == 2 && a.mode == 0 && KFBI_BLOCK == 256) {
+      hipLaunchKernelGGL((k_dst<10, 0, true>), dim3(blocks), dim3(KFBI_BLOCK), lds, st, a);
       return;
     }
   }
