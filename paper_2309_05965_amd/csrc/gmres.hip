@@ -242,22 +242,22 @@ __device__ __forceinline__ double lane_value(double x, int l) {
 // The coefficients are formed in chunks of 64 basis vectors: per-thread
 // products, a sum of eight vectors at a time over the wavefront
 // (transposing butterfly) into per-wavefront partials in LDS (two buffers
-// used in turn, so one barrier per chunk), then every wavefront adds the 16
-// partials of coefficient c0 + l in lane l and the update takes them from
+// used in turn, so one barrier per chunk), then every wavefront adds the
+// NT / 64 partials of coefficient c0 + l in lane l and the update takes them from
 // there (readlane).  Up to 64 basis vectors (every run seen in practice)
 // this is exactly CGS2; beyond, each chunk is applied before the next
 // one's coefficients are formed (block Gram-Schmidt over chunks).  The LDS
 // footprint stays small (28 KB).
 constexpr int ARN_CH = 64;
 
-template <int E, int JR>
-__global__ void __launch_bounds__(GB) k_arnoldi_reg(int64_t n, int* ctl, int ldh, double* V, double* Hm, double* cs,
+template <int E, int JR, int NT>
+__global__ void __launch_bounds__(NT) k_arnoldi_reg(int64_t n, int* ctl, int ldh, double* V, double* Hm, double* cs,
                                                    double* sn, double* gv, double* scal) {
   static_assert(JR % 8 == 0 && JR <= ARN_CH, "register vectors: a multiple of 8, at most one chunk");
-  __shared__ double red[2][GB / 64][ARN_CH];
+  __shared__ double red[2][NT / 64][ARN_CH];
   __shared__ double hs[KFBI_GMRES_MAX + 2];
   __shared__ double lcs[KFBI_GMRES_MAX], lsn[KFBI_GMRES_MAX];
-  __shared__ double rn[GB / 64];
+  __shared__ double rn[NT / 64];
   if (ctl[1]) return;
   const int j = ctl[0];
   const int nn = (int)n;
@@ -266,17 +266,17 @@ __global__ void __launch_bounds__(GB) k_arnoldi_reg(int64_t n, int* ctl, int ldh
   double wr[E], vr[JR][E];
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const int t = threadIdx.x + GB * r;
+    const int t = threadIdx.x + NT * r;
     wr[r] = t < nn ? w[t] : 0.0;
   }
 #pragma unroll
   for (int i = 0; i < JR; ++i)
 #pragma unroll
     for (int r = 0; r < E; ++r) {
-      const int t = threadIdx.x + GB * r;
+      const int t = threadIdx.x + NT * r;
       vr[i][r] = (i <= j && t < nn) ? V[(int64_t)i * n + t] : 0.0;
     }
-  for (int i = threadIdx.x; i < j; i += GB) {
+  for (int i = threadIdx.x; i < j; i += NT) {
     lcs[i] = cs[i];
     lsn[i] = sn[i];
   }
@@ -309,7 +309,7 @@ __global__ void __launch_bounds__(GB) k_arnoldi_reg(int64_t n, int* ctl, int ldh
           double acc = 0.0;
 #pragma unroll
           for (int r = 0; r < E; ++r) {
-            const int t = threadIdx.x + GB * r;
+            const int t = threadIdx.x + NT * r;
             if (i0 + q <= c1 && t < nn) acc += V[(int64_t)(i0 + q) * n + t] * wr[r];
           }
           p[q] = acc;
@@ -320,7 +320,7 @@ __global__ void __launch_bounds__(GB) k_arnoldi_reg(int64_t n, int* ctl, int ldh
       __syncthreads();
       double h0 = 0.0;                 // lane l: coefficient c0 + l of this pass
       if (c0 + lane <= c1)
-        for (int wv = 0; wv < GB / 64; ++wv) h0 += rp[wv][lane];
+        for (int wv = 0; wv < NT / 64; ++wv) h0 += rp[wv][lane];
       if (wave == 0 && c0 + lane <= c1) hs[c0 + lane] = pass == 0 ? h0 : hs[c0 + lane] + h0;
       if (c0 == 0) {
 #pragma unroll
@@ -335,7 +335,7 @@ __global__ void __launch_bounds__(GB) k_arnoldi_reg(int64_t n, int* ctl, int ldh
       for (int i0 = c0 == 0 ? JR : c0; i0 <= c1; i0 += 8) {
 #pragma unroll
         for (int r = 0; r < E; ++r) {
-          const int t = threadIdx.x + GB * r;
+          const int t = threadIdx.x + NT * r;
           double y[8];
 #pragma unroll
           for (int q = 0; q < 8; ++q) y[q] = (i0 + q <= c1 && t < nn) ? V[(int64_t)(i0 + q) * n + t] : 0.0;
@@ -355,13 +355,13 @@ __global__ void __launch_bounds__(GB) k_arnoldi_reg(int64_t n, int* ctl, int ldh
   if (lane == 0) rn[wave] = sq;
   __syncthreads();
   double tot = 0.0;
-  for (int wv = 0; wv < GB / 64; ++wv) tot += rn[wv];
+  for (int wv = 0; wv < NT / 64; ++wv) tot += rn[wv];
   const double hn = sqrt(tot);
   const bool breakdown = !(hn > 0.0);
   const double inv = breakdown ? 1.0 : 1.0 / hn;
 #pragma unroll
   for (int r = 0; r < E; ++r) {
-    const int t = threadIdx.x + GB * r;
+    const int t = threadIdx.x + NT * r;
     if (t < nn) w[t] = breakdown ? wr[r] : wr[r] * inv;
   }
   if (wave == 0) {
@@ -632,10 +632,15 @@ void gm_arnoldi(kfbi_plan* pl) {
   const int ldh = pl->gm_cap + 1;
   hipStream_t st = pl->stream;
   if (n <= GB) {
-    hipLaunchKernelGGL((k_arnoldi_reg<1, 32>), dim3(1), dim3(GB), 0, st, n, pl->ctl, ldh, pl->V, pl->Hm, pl->cs,
+    hipLaunchKernelGGL((k_arnoldi_reg<1, 32, GB>), dim3(1), dim3(GB), 0, st, n, pl->ctl, ldh, pl->V, pl->Hm, pl->cs,
                        pl->sn, pl->gv, pl->scal);
+  } else if (n <= 5 * 256) {
+    // four wavefronts, five elements each: a quarter of the cross-wave
+    // reduction traffic and barrier width of sixteen
+    hipLaunchKernelGGL((k_arnoldi_reg<5, 16, 256>), dim3(1), dim3(256), 0, st, n, pl->ctl, ldh, pl->V, pl->Hm,
+                       pl->cs, pl->sn, pl->gv, pl->scal);
   } else if (n <= 2 * GB) {
-    hipLaunchKernelGGL((k_arnoldi_reg<2, 16>), dim3(1), dim3(GB), 0, st, n, pl->ctl, ldh, pl->V, pl->Hm, pl->cs,
+    hipLaunchKernelGGL((k_arnoldi_reg<2, 16, GB>), dim3(1), dim3(GB), 0, st, n, pl->ctl, ldh, pl->V, pl->Hm, pl->cs,
                        pl->sn, pl->gv, pl->scal);
   } else if (n <= ARN1_MAXN) {
     hipLaunchKernelGGL(k_arnoldi1, dim3(1), dim3(GB), 0, st, n, pl->ctl, ldh, pl->V, pl->Hm, pl->cs, pl->sn,
