@@ -631,12 +631,19 @@ void gm_arnoldi(kfbi_plan* pl) {
   const int64_t n = pl->n_dof;
   const int ldh = pl->gm_cap + 1;
   hipStream_t st = pl->stream;
-  if (n <= GB) {
-    hipLaunchKernelGGL((k_arnoldi_reg<1, 32, GB>), dim3(1), dim3(GB), 0, st, n, pl->ctl, ldh, pl->V, pl->Hm, pl->cs,
-                       pl->sn, pl->gv, pl->scal);
+  // the fewest wavefronts whose registers hold the thread's elements of w
+  // and of the first basis vectors: the step is bound by its cross-wave
+  // reductions and barriers, which shrink with the wavefront count
+  if (n <= 256) {
+    hipLaunchKernelGGL((k_arnoldi_reg<1, 32, 256>), dim3(1), dim3(256), 0, st, n, pl->ctl, ldh, pl->V, pl->Hm,
+                       pl->cs, pl->sn, pl->gv, pl->scal);
+  } else if (n <= 512) {
+    hipLaunchKernelGGL((k_arnoldi_reg<2, 32, 256>), dim3(1), dim3(256), 0, st, n, pl->ctl, ldh, pl->V, pl->Hm,
+                       pl->cs, pl->sn, pl->gv, pl->scal);
+  } else if (n <= GB) {
+    hipLaunchKernelGGL((k_arnoldi_reg<2, 32, 512>), dim3(1), dim3(512), 0, st, n, pl->ctl, ldh, pl->V, pl->Hm,
+                       pl->cs, pl->sn, pl->gv, pl->scal);
   } else if (n <= 5 * 256) {
-    // four wavefronts, five elements each: a quarter of the cross-wave
-    // reduction traffic and barrier width of sixteen
     hipLaunchKernelGGL((k_arnoldi_reg<5, 16, 256>), dim3(1), dim3(256), 0, st, n, pl->ctl, ldh, pl->V, pl->Hm,
                        pl->cs, pl->sn, pl->gv, pl->scal);
   } else if (n <= 2 * GB) {
