@@ -32,7 +32,7 @@ HBM_PEAK_GBS = 8000.0
 # HBM bytes per k_dst launch on this workload (mean over the three passes),
 # from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's counts
 # (profiles/k_dst_star512_hbm_counters.md); null once k_dst changes
-K_DST_TRAFFIC_BYTES = 4.721e6
+K_DST_TRAFFIC_BYTES = 4.670e6
 
 
 def parse():
