@@ -77,6 +77,54 @@ __global__ void __launch_bounds__(GB) k_start(int64_t n, const double* b, const 
 // V[0..j] by classical Gram-Schmidt applied twice (CGS2), then normalised;
 // the Givens rotations are applied to column j.  Every reduction runs in a
 // fixed order, so the step is bitwise reproducible.
+// DPP moves within a 16-lane row (register to register, no LDS): lane
+// i ^ 1, i ^ 2 (quad permutes), i ^ 8 (row_ror:8), i ^ 7 (row_half_mirror)
+template <int CTRL>
+__device__ __forceinline__ double row_dpp(double v) {
+  const long long u = __double_as_longlong(v);
+  const int lo = __builtin_amdgcn_update_dpp(0, (int)u, CTRL, 0xf, 0xf, false);
+  const int hi = __builtin_amdgcn_update_dpp(0, (int)(u >> 32), CTRL, 0xf, 0xf, false);
+  return __longlong_as_double(((long long)hi << 32) | (long long)(unsigned)lo);
+}
+constexpr int RD_X1 = 0xB1, RD_X2 = 0x4E, RD_X3 = 0x1B, RD_X8 = 0x128, RD_X7 = 0x141;
+__device__ __forceinline__ double row_x4(double v) { return row_dpp<RD_X3>(row_dpp<RD_X7>(v)); }   // lane i ^ 4
+
+// eight sums over the 16 lanes of a row by a transposing butterfly of DPP
+// moves: lanes 2k and 2k + 1 of the row end with the row's sum of p[k'],
+// k' = row_reduce8_index(lane)
+__device__ __forceinline__ double row_reduce8(const double (&p)[8], int lane) {
+  const bool h8 = lane & 8, h4 = lane & 4, h2 = lane & 2;
+  double a[4], b[2];
+#pragma unroll
+  for (int q = 0; q < 4; ++q) {
+    const double send = h8 ? p[q] : p[q + 4];
+    const double keep = h8 ? p[q + 4] : p[q];
+    a[q] = keep + row_dpp<RD_X8>(send);
+  }
+#pragma unroll
+  for (int q = 0; q < 2; ++q) {
+    const double send = h4 ? a[q] : a[q + 2];
+    const double keep = h4 ? a[q + 2] : a[q];
+    b[q] = keep + row_x4(send);
+  }
+  const double send = h2 ? b[0] : b[1];
+  const double keep = h2 ? b[1] : b[0];
+  const double c = keep + row_dpp<RD_X2>(send);
+  return c + row_dpp<RD_X1>(c);
+}
+
+__device__ __forceinline__ int row_reduce8_index(int lane) {
+  return ((lane & 8) ? 4 : 0) + ((lane & 4) ? 2 : 0) + ((lane & 2) ? 1 : 0);
+}
+
+// sum over the 16 lanes of a row (every lane of the row ends with it)
+__device__ __forceinline__ double row_reduce(double v) {
+  v += row_dpp<RD_X8>(v);
+  v += row_x4(v);
+  v += row_dpp<RD_X2>(v);
+  return v + row_dpp<RD_X1>(v);
+}
+
 __device__ __forceinline__ double wave_reduce(double v) {
   for (int off = 32; off > 0; off >>= 1) v += __shfl_xor(v, off, 64);
   return v;
@@ -254,10 +302,13 @@ template <int E, int JR, int NT>
 __global__ void __launch_bounds__(NT) k_arnoldi_reg(int64_t n, int* ctl, int ldh, double* V, double* Hm, double* cs,
                                                    double* sn, double* gv, double* scal) {
   static_assert(JR % 8 == 0 && JR <= ARN_CH, "register vectors: a multiple of 8, at most one chunk");
-  __shared__ double red[2][NT / 64][ARN_CH];
+  // partials per row of 16 lanes (up to 512 threads) or per wavefront
+  constexpr bool ROWS = NT <= 512;
+  constexpr int NP = ROWS ? NT / 16 : NT / 64;
+  __shared__ double red[2][NP][ARN_CH];
   __shared__ double hs[KFBI_GMRES_MAX + 2];
   __shared__ double lcs[KFBI_GMRES_MAX], lsn[KFBI_GMRES_MAX];
-  __shared__ double rn[NT / 64];
+  __shared__ double rn[NP];
   if (ctl[1]) return;
   const int j = ctl[0];
   const int nn = (int)n;
@@ -298,8 +349,13 @@ __global__ void __launch_bounds__(NT) k_arnoldi_reg(int64_t n, int* ctl, int ldh
             for (int r = 0; r < E; ++r) acc += vr[i0 + q][r] * wr[r];
             p[q] = acc;
           }
-          const double sv = wave_reduce8(p, lane);
-          if ((lane & 7) == 0) rp[wave][i0 + wave_reduce8_index(lane)] = sv;
+          if (ROWS) {
+            const double sv = row_reduce8(p, lane);
+            if ((lane & 1) == 0) rp[4 * wave + (lane >> 4)][i0 + row_reduce8_index(lane)] = sv;
+          } else {
+            const double sv = wave_reduce8(p, lane);
+            if ((lane & 7) == 0) rp[wave][i0 + wave_reduce8_index(lane)] = sv;
+          }
         }
       }
       for (int i0 = c0 == 0 ? JR : c0; i0 <= c1; i0 += 8) {
@@ -314,13 +370,19 @@ __global__ void __launch_bounds__(NT) k_arnoldi_reg(int64_t n, int* ctl, int ldh
           }
           p[q] = acc;
         }
-        const double sv = wave_reduce8(p, lane);
-        if ((lane & 7) == 0 && i0 + wave_reduce8_index(lane) <= c1) rp[wave][i0 - c0 + wave_reduce8_index(lane)] = sv;
+        if (ROWS) {
+          const double sv = row_reduce8(p, lane);
+          if ((lane & 1) == 0 && i0 + row_reduce8_index(lane) <= c1)
+            rp[4 * wave + (lane >> 4)][i0 - c0 + row_reduce8_index(lane)] = sv;
+        } else {
+          const double sv = wave_reduce8(p, lane);
+          if ((lane & 7) == 0 && i0 + wave_reduce8_index(lane) <= c1) rp[wave][i0 - c0 + wave_reduce8_index(lane)] = sv;
+        }
       }
       __syncthreads();
       double h0 = 0.0;                 // lane l: coefficient c0 + l of this pass
       if (c0 + lane <= c1)
-        for (int wv = 0; wv < NT / 64; ++wv) h0 += rp[wv][lane];
+        for (int wv = 0; wv < NP; ++wv) h0 += rp[wv][lane];
       if (wave == 0 && c0 + lane <= c1) hs[c0 + lane] = pass == 0 ? h0 : hs[c0 + lane] + h0;
       if (c0 == 0) {
 #pragma unroll
@@ -351,11 +413,16 @@ __global__ void __launch_bounds__(NT) k_arnoldi_reg(int64_t n, int* ctl, int ldh
   double sq = 0.0;
 #pragma unroll
   for (int r = 0; r < E; ++r) sq += wr[r] * wr[r];
-  sq = wave_reduce(sq);
-  if (lane == 0) rn[wave] = sq;
+  if (ROWS) {
+    sq = row_reduce(sq);
+    if ((lane & 15) == 0) rn[4 * wave + (lane >> 4)] = sq;
+  } else {
+    sq = wave_reduce(sq);
+    if (lane == 0) rn[wave] = sq;
+  }
   __syncthreads();
   double tot = 0.0;
-  for (int wv = 0; wv < NT / 64; ++wv) tot += rn[wv];
+  for (int wv = 0; wv < NP; ++wv) tot += rn[wv];
   const double hn = sqrt(tot);
   const bool breakdown = !(hn > 0.0);
   const double inv = breakdown ? 1.0 : 1.0 / hn;
