@@ -337,6 +337,11 @@ void simple_solve_impl(kfbi_plan* pl, const double* a, const double* b, const do
 void matvec_impl(kfbi_plan* pl, const double* psi, double* Apsi) { op_matvec(pl, psi, Apsi); }
 
 void destroy_graphs(kfbi_plan* pl) {
+  if (pl->graph_xe) (void)hipGraphExecDestroy(pl->graph_xe);
+  if (pl->graph_x) (void)hipGraphDestroy(pl->graph_x);
+  pl->graph_xe = nullptr;
+  pl->graph_x = nullptr;
+  pl->graph_xn = 0;
   for (int v = 0; v < KFBI_NGRAPH; ++v) {
     if (pl->graph_execs[v]) (void)hipGraphExecDestroy(pl->graph_execs[v]);
     if (pl->graphs[v]) (void)hipGraphDestroy(pl->graphs[v]);
@@ -864,8 +869,13 @@ kfbi_status gmres_run(kfbi_plan* pl, double tol, int m, int first_batch, GmresOu
         HIPCHK(hipGraphLaunch(c > 0 && pl->mg_gexec[c] ? pl->mg_gexec[c] : pl->graph_execs[0], st));
       }
     } else {
+      // the graph of exactly B iterations if there is one, else the
       // largest captured graphs first (graph 0 always exists)
       int left = B;
+      if (pl->graph_xe && B == pl->graph_xn) {
+        HIPCHK(hipGraphLaunch(pl->graph_xe, st));
+        left = 0;
+      }
       for (int v = KFBI_NGRAPH - 1; v >= 0; --v)
         if (pl->graph_execs[v])
           for (; left >= (1 << v); left -= 1 << v) HIPCHK(hipGraphLaunch(pl->graph_execs[v], st));
@@ -1053,7 +1063,21 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
   };
   spec.after = [](void* c) { (*((SpecCtx*)c)->fin)(); };
   GmresOut o;
-  KCHK(gmres_run(pl, tol, m, pl->last_iters > 4 ? (pl->last_iters < 64 ? pl->last_iters : 64) : 4, &o, spec));
+  const int fb = pl->last_iters > 4 ? (pl->last_iters < 64 ? pl->last_iters : 64) : 4;
+  // a key solved with more than once (a repeated problem): its first batch,
+  // when no power of two, as one graph instead of several (each graph
+  // launch idles the GPU for a few microseconds)
+  if (pl->box_solver == KFBI_BOX_FFT && pl->graph_uses > 1 && (fb & (fb - 1)) != 0 && pl->graph_xn != fb) {
+    if (pl->graph_xe) HIPCHK(hipStreamSynchronize(pl->stream));   // no launch of the old one in flight
+    if (pl->graph_xe) (void)hipGraphExecDestroy(pl->graph_xe);
+    if (pl->graph_x) (void)hipGraphDestroy(pl->graph_x);
+    pl->graph_xe = nullptr;
+    pl->graph_x = nullptr;
+    pl->graph_xn = 0;
+    KCHK(capture_iterations(pl, fb, &pl->graph_x, &pl->graph_xe));
+    pl->graph_xn = fb;
+  }
+  KCHK(gmres_run(pl, tol, m, fb, &o, spec));
   if (o.spec_ok) {
     const double tr = pl->h_dpinned[5] > 0.0 ? sqrt(pl->h_dpinned[4] / pl->h_dpinned[5]) : 0.0;
     return solve_report(pl, info, o, o.k, tr, tol, m);

@@ -183,6 +183,9 @@ struct kfbi_plan {
   hipEvent_t ev_in, ev_out;
   hipGraph_t graphs[KFBI_NGRAPH];
   hipGraphExec_t graph_execs[KFBI_NGRAPH];  // graph g runs 2^g iterations
+  hipGraph_t graph_x;            // graph_xn iterations (a repeated first batch that is no power of two)
+  hipGraphExec_t graph_xe;
+  int graph_xn;
   uint64_t graph_key[20];
   int graph_uses;                // solves run with the current graph key
   int* h_ctl;
