@@ -123,6 +123,19 @@ def test_box_solve_extreme_sizes(N):
     assert rel(v[1:N, 1:N], ref) < 1e-11
 
 
+@pytest.mark.parametrize("N", [64, 128])
+def test_box_solve_3d_tiles(N):
+    """3D box solves with two and with eight lines per work group (N = 64: TL = 2;
+    N = 128: four 256-point sequences per work group)."""
+    from paper_2309_05965_amd import kfbi
+    prob = W.problem(3, 4, N, -1.0, 1.0, 1.0, 5.0, 0.5, [W.sphere3d(0.03, -0.02, 0.01, 0.52)])
+    gp = kfbi.Plan(prob)
+    F = np.random.default_rng(N + 7).standard_normal((N + 1,) * 3)
+    v = host(gp.box_solve(dev(F))).reshape(F.shape)
+    ref = fd.dst_solve(F[1:N, 1:N, 1:N], 3, 4, N, 2.0 / N, 0.5)
+    assert rel(v[1:N, 1:N, 1:N], ref) < 1e-11
+
+
 @pytest.mark.parametrize("name", list(CASES))
 def test_simple_solve(name):
     prob, sol, gp, op = case(name)
