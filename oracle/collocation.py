@@ -33,6 +33,16 @@ def _pow(x, e):
     """x**e for an integer array e >= 0 by repeated multiplication
     1 * x * x * ... (elementwise; x**0 = 1, and x**e = 0 for e < 0, which
     only occurs multiplied by a zero factor)."""
+    x = np.asarray(x, dtype=np.float64)
+    e = np.asarray(e)
+    if e.ndim == 1 and x.ndim >= 1 and x.shape[-1] == 1:
+        # one column of bases, one row of exponents: the same products from
+        # a table of the bases' powers 1, 1*x, (1*x)*x, ...
+        tab = [np.ones(x.shape[:-1])]
+        for _ in range(int(e.max(initial=0))):
+            tab.append(tab[-1] * x[..., 0])
+        T = np.stack(tab, axis=-1)
+        return np.where(e >= 0, T[..., np.maximum(e, 0)], 0.0)
     e = np.broadcast_to(e, np.broadcast_shapes(np.shape(x), np.shape(e)))
     x = np.broadcast_to(x, e.shape)
     r = np.where(e >= 0, 1.0, 0.0)

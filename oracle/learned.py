@@ -144,3 +144,17 @@ def mlp_loss_grad(Ws, bs, X, Yt, emulate=True):
             da = r(dz) @ r(Ws[l]).T
             dz = da * (zs[l - 1] > 0.0)
     return loss, gW, gb
+
+
+def adam_step(params, grads, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):
+    """One Adam update (Kingma & Ba, Algorithm 1) on float64 copies:
+    m <- b1 m + (1 - b1) g, v <- b2 v + (1 - b2) g^2,
+    mhat = m / (1 - b1^t), vhat = v / (1 - b2^t),
+    theta <- theta - lr mhat / (sqrt(vhat) + eps); t counts from 1.
+    Returns (params, m, v)."""
+    g = np.asarray(grads, dtype=np.float64)
+    m = b1 * np.asarray(m, dtype=np.float64) + (1.0 - b1) * g
+    v = b2 * np.asarray(v, dtype=np.float64) + (1.0 - b2) * g * g
+    mhat = m / (1.0 - b1 ** t)
+    vhat = v / (1.0 - b2 ** t)
+    return np.asarray(params, dtype=np.float64) - lr * mhat / (np.sqrt(vhat) + eps), m, v

@@ -1068,6 +1068,8 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
   // when no power of two, as one graph instead of several (each graph
   // launch idles the GPU for a few microseconds)
   if (pl->box_solver == KFBI_BOX_FFT && pl->graph_uses > 1 && (fb & (fb - 1)) != 0 && pl->graph_xn != fb) {
+    // like every capture, exclusive of other threads' set-up and allocations
+    std::unique_lock<std::shared_mutex> lock(kfbi_capture_mutex);
     if (pl->graph_xe) HIPCHK(hipStreamSynchronize(pl->stream));   // no launch of the old one in flight
     if (pl->graph_xe) (void)hipGraphExecDestroy(pl->graph_xe);
     if (pl->graph_x) (void)hipGraphDestroy(pl->graph_x);

@@ -157,6 +157,32 @@ def config3(N=128):
     return prob, {0: f_exp3, 1: f_sin3, 2: f_sin3}
 
 
+def two_circles(order=4, N=64, gap=0.5, kappa=0.4):
+    """Two disjoint circles (radii 0.27, 0.21) in [-1, 1]^2 whose closest
+    points are gap * h apart along a direction 0.35 rad from the x axis;
+    beta 1/3.  A gap below one grid spacing puts stencil neighbours inside
+    both interiors (the multi-crossing case of the corrected scheme)."""
+    h = 2.0 / N
+    r1, r2 = 0.27, 0.21
+    c1 = (-0.3, 0.013)
+    dist = r1 + r2 + gap * h
+    c2 = (c1[0] + dist * math.cos(0.35), c1[1] + dist * math.sin(0.35))
+    return problem(2, order, N, -1.0, 1.0, 1.0, 3.0, kappa,
+                   [ellipse2d(c1[0], c1[1], r1, r1), ellipse2d(c2[0], c2[1], r2, r2)])
+
+
+def two_spheres(N=64, gap=0.5, order=4, kappa=0.3):
+    """Two disjoint spheres (radii 0.33, 0.27) in [-1, 1]^3, closest points
+    gap * h apart; beta 1/4."""
+    h = 2.0 / N
+    r1, r2 = 0.33, 0.27
+    c1 = np.array([-0.31, 0.021, -0.017])
+    u = np.array([math.cos(0.3) * math.cos(0.2), math.sin(0.3) * math.cos(0.2), math.sin(0.2)])
+    c2 = c1 + (r1 + r2 + gap * h) * u
+    return problem(3, order, N, -1.0, 1.0, 1.0, 4.0, kappa,
+                   [sphere3d(*c1.tolist(), r1), sphere3d(*c2.tolist(), r2)])
+
+
 def config4_batch(n=512, seed=SEED_BATCH):
     """Random stars r(t) = 0.4 + sum_{k=2..8} a_k cos(k t + p_k),
     a_k ~ U(0, 0.04), p_k ~ U(0, 2 pi), log10 beta_in ~ U(-2, 2), beta_out = 1,

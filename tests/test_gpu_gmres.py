@@ -21,9 +21,10 @@ def sphere(N):
 
 
 CASES = {
-    "c2_512": lambda: W.config2(512),        # ~1.0e3 unknowns: 2 per thread
-    "sphere_64": lambda: sphere(64),         # ~3.5e3: 4 per thread
-    "torus_64": lambda: W.config3(64),       # ~7.6e3: 8 per thread
+    "c2_512": lambda: W.config2(512),        # 1,038 unknowns: 5 per thread, 4 wavefronts
+    "c1_1024": lambda: W.config1(1024),      # 1280 < n <= 2048: 2 per thread, 16 wavefronts
+    "sphere_64": lambda: sphere(64),         # ~3.5e3: one work group, w in LDS
+    "torus_64": lambda: W.config3(64),       # ~6.1e3: one work group, w in LDS
     "sphere_128": lambda: sphere(128),       # ~1.4e4: many work groups
 }
 
