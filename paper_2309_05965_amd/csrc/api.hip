@@ -926,9 +926,17 @@ kfbi_status gmres_run(kfbi_plan* pl, double tol, int m, int first_batch, GmresOu
     k_prev = k;
   }
   o->k = pl->h_ctl[2];
-  o->est = nb > 0.0 ? pl->h_dpinned[0] / nb : 0.0;
+  // a zero right-hand side gives 0; a NaN norm stays NaN (reported as non-finite)
+  o->est = nb == 0.0 ? 0.0 : pl->h_dpinned[0] / nb;
   o->conv = pl->h_ctl[1] && (nb == 0.0 || pl->h_dpinned[0] <= tol * nb || pl->h_dpinned[2] != 0.0);
   return KFBI_OK;
+}
+
+// sqrt(|r|^2 / |b|^2): 0 for a zero right-hand side, NaN when either sum is
+// not finite (so the solve reports KFBI_E_NONFINITE)
+double rel_residual(double rr, double bb) {
+  if (bb == 0.0) return 0.0;
+  return sqrt(rr / bb);
 }
 
 // |b - A psi| / |b| with a fresh full-accuracy matvec
@@ -951,7 +959,7 @@ kfbi_status true_residual(kfbi_plan* pl, const double* psi, double* tr, Then the
   KCHK(kfbi_post_launch(pl, q, &seq));
   then();
   KCHK(kfbi_post_collect(pl, q, seq, pl->h_pinned + 2, pl->h_dpinned + 4));
-  *tr = pl->h_dpinned[5] > 0.0 ? sqrt(pl->h_dpinned[4] / pl->h_dpinned[5]) : 0.0;
+  *tr = rel_residual(pl->h_dpinned[4], pl->h_dpinned[5]);
   return KFBI_OK;
 }
 
@@ -1081,7 +1089,7 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
   }
   KCHK(gmres_run(pl, tol, m, fb, &o, spec));
   if (o.spec_ok) {
-    const double tr = pl->h_dpinned[5] > 0.0 ? sqrt(pl->h_dpinned[4] / pl->h_dpinned[5]) : 0.0;
+    const double tr = rel_residual(pl->h_dpinned[4], pl->h_dpinned[5]);
     return solve_report(pl, info, o, o.k, tr, tol, m);
   }
   gm_update(pl, o.k, psi, opts->use_x0);
