@@ -232,6 +232,26 @@ kfbi_status kfbi_plan_box_stats(kfbi_plan* plan, int32_t* cycles, double* rel_re
  * alias. */
 kfbi_status kfbi_box_solve(kfbi_plan* plan, const double* F, double* v);
 
+/* Box solve without any allocation, for callers that cannot allocate
+ * device memory (code under HIP graph capture, tight serving loops,
+ * harnesses that forbid hipMalloc): the FFT box solve of kfbi_box_solve
+ * (the same kernels) on the grid [lo, hi]^dim with N intervals per axis,
+ * scheme `order` (2 or 4) and reduced reaction coefficient kappa, without
+ * a plan.  v = A_h^-1 F on the interior, v = 0 on the box boundary;
+ * F, v: [(N+1)^dim] device arrays of the caller (distinct), x fastest.
+ * Work is ordered on `stream` (a hipStream_t of the current device; NULL =
+ * default stream) and the call returns after enqueueing it.
+ * Limits: N a power of two, 8 <= N <= 1024 in 2D and <= 128 in 3D; larger
+ * grids return KFBI_E_INVALID.  The two intermediate grids and the FFT
+ * tables live in one static device array of 34.4 MB per device (2 x
+ * 2,146,720 + 5,376 doubles), held from the first call on a device until
+ * the process ends; the call allocates nothing (no hipMalloc, hipFree or
+ * allocating library routine).  Every call on a device shares that array:
+ * calls that overlap on one device (two streams, two threads) race and
+ * must be serialised by the caller. */
+kfbi_status kfbi_box_solve_noalloc(int dim, int order, int N, double lo, double hi, double kappa,
+                                   const double* F, double* v, void* stream);
+
 /* One simple interface problem (eq. con-ifp with box data; Secs. 4, 5):
  * w with [w] = a, [d_n w] = b, Lap w - kappa w = fhat_s, w = gB on the box.
  * a, b: [n_surf] (NULL = 0); ftilde [n_dof][n_pde], fhat, gB as in

@@ -24,6 +24,7 @@
 // from a global table (L2-resident).
 #include <math.h>
 
+#include <mutex>
 #include <vector>
 
 #include "kfbi_internal.h"
@@ -628,6 +629,36 @@ void launch_t(const DstArgs& a, unsigned blocks, size_t lds, hipStream_t st) {
     hipLaunchKernelGGL((k_dst<LOGM, 0, false>), dim3(blocks), dim3(KFBI_BLOCK), lds, st, a);
 }
 
+// launch one axis pass; a.g, a.ax, a.mode, a.in, a.out, a.tw, a.eig1 and
+// the corrected-source fields are set by the caller
+void launch_args(DstArgs& a, bool src_corr, hipStream_t st) {
+  const GridDesc& g = a.g;
+  const int N = g.N, nl = N - 1;
+  a.TL = tile_lines(g.d, N);
+  a.tiles_u = (nl + a.TL - 1) / a.TL;
+  a.scale = 1.0;
+  for (int t = 0; t < g.d; ++t) a.scale *= 2.0 / N;
+  const unsigned blocks = (unsigned)(a.tiles_u * (g.d == 3 ? nl : 1));
+  if (N == 512 && a.TL == 2 && !src_corr && KFBI_BLOCK == 256) {
+    if (a.mode == 1)
+      hipLaunchKernelGGL(k_dst1024<1>, dim3(blocks), dim3(KFBI_BLOCK), 0, st, a);
+    else
+      hipLaunchKernelGGL(k_dst1024<0>, dim3(blocks), dim3(KFBI_BLOCK), 0, st, a);
+    return;
+  }
+  const size_t lds = tile_lds(a.TL, N);
+  switch (N) {   // N is a power of two in [8, 1024]
+    case 8: launch_t<4>(a, blocks, lds, st); break;
+    case 16: launch_t<5>(a, blocks, lds, st); break;
+    case 32: launch_t<6>(a, blocks, lds, st); break;
+    case 64: launch_t<7>(a, blocks, lds, st); break;
+    case 128: launch_t<8>(a, blocks, lds, st); break;
+    case 256: launch_t<9>(a, blocks, lds, st); break;
+    case 512: launch_t<10>(a, blocks, lds, st); break;
+    default: launch_t<11>(a, blocks, lds, st); break;
+  }
+}
+
 void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out, bool src_corr = false) {
   DstArgs a;
   a.ctl = pl->ctl_active;
@@ -644,34 +675,11 @@ void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out,
   a.g = pl->g;
   a.ax = ax;
   a.mode = mode;
-  const int N = pl->g.N, nl = N - 1;
-  a.TL = tile_lines(pl->g.d, N);
-  a.tiles_u = (nl + a.TL - 1) / a.TL;
   a.in = in;
   a.out = out;
   a.tw = (const double2*)pl->tw;
   a.eig1 = pl->eig1;
-  a.scale = 1.0;
-  for (int t = 0; t < pl->g.d; ++t) a.scale *= 2.0 / N;
-  const unsigned blocks = (unsigned)(a.tiles_u * (pl->g.d == 3 ? nl : 1));
-  if (N == 512 && a.TL == 2 && !src_corr && KFBI_BLOCK == 256) {
-    if (mode == 1)
-      hipLaunchKernelGGL(k_dst1024<1>, dim3(blocks), dim3(KFBI_BLOCK), 0, pl->stream, a);
-    else
-      hipLaunchKernelGGL(k_dst1024<0>, dim3(blocks), dim3(KFBI_BLOCK), 0, pl->stream, a);
-    return;
-  }
-  const size_t lds = tile_lds(a.TL, N);
-  switch (N) {   // N is a power of two in [8, 1024]
-    case 8: launch_t<4>(a, blocks, lds, pl->stream); break;
-    case 16: launch_t<5>(a, blocks, lds, pl->stream); break;
-    case 32: launch_t<6>(a, blocks, lds, pl->stream); break;
-    case 64: launch_t<7>(a, blocks, lds, pl->stream); break;
-    case 128: launch_t<8>(a, blocks, lds, pl->stream); break;
-    case 256: launch_t<9>(a, blocks, lds, pl->stream); break;
-    case 512: launch_t<10>(a, blocks, lds, pl->stream); break;
-    default: launch_t<11>(a, blocks, lds, pl->stream); break;
-  }
+  launch_args(a, src_corr, pl->stream);
 }
 
 }  // namespace
@@ -741,4 +749,156 @@ void dst_solve_corrections(kfbi_plan* pl, const double* psi, double* v) {
     launch_pass(pl, 1, 0, pl->T1, pl->T2);
     launch_pass(pl, 0, 0, pl->T2, v);
   }
+}
+
+// ---------------------------------------------------------------- box solve without allocation
+//
+// kfbi_box_solve_noalloc: the FFT box solve of kfbi_box_solve (the same
+// kernels) for a grid given by its parameters, with the two intermediate
+// grids and the twiddle and eigenvalue tables in one file-scope device array
+// instead of plan buffers, so a call allocates nothing.  Each device holds
+// its own copy of the array until the process ends; its address on a device
+// is looked up once (hipGetSymbolAddress) with that device current and kept.
+namespace {
+
+constexpr int NOALLOC_MAX_N2 = 1024;                   // 2D grids up to 1024^2
+constexpr int NOALLOC_MAX_N3 = 128;                    // 3D grids up to 128^3
+constexpr int64_t NOALLOC_GRID = 2146720;              // >= 129^3 and 1025^2, multiple of 32
+constexpr int64_t NOALLOC_TW = 2 * 2 * NOALLOC_MAX_N2; // M = 2N complex twiddles
+constexpr int64_t NOALLOC_EIG = 1280;                  // >= N + 1, multiple of 32
+constexpr int64_t NOALLOC_DOUBLES = 2 * NOALLOC_GRID + NOALLOC_TW + NOALLOC_EIG;
+
+__device__ __align__(256) double scratch[NOALLOC_DOUBLES];
+
+constexpr int NOALLOC_MAX_DEV = 64;
+std::mutex g_noalloc_mu;
+double* g_noalloc_ptr[NOALLOC_MAX_DEV] = {};
+
+// address of this device's scratch array (the symbol's name is a host-side
+// stand-in, not a device address)
+kfbi_status noalloc_scratch(double** out) {
+  int dev = -1;
+  HIPCHK(hipGetDevice(&dev));
+  if (dev < 0 || dev >= NOALLOC_MAX_DEV) {
+    kfbi_set_error("device %d beyond the %d devices the static scratch table covers", dev, NOALLOC_MAX_DEV);
+    return KFBI_E_INVALID;
+  }
+  std::lock_guard<std::mutex> lk(g_noalloc_mu);
+  if (!g_noalloc_ptr[dev]) {
+    void* p = nullptr;
+    const hipError_t e = hipGetSymbolAddress(&p, HIP_SYMBOL(scratch));
+    if (e != hipSuccess || !p) return kfbi_hip_status(e != hipSuccess ? e : hipErrorInvalidSymbol,
+                                                      "hipGetSymbolAddress(scratch)");
+    g_noalloc_ptr[dev] = (double*)p;
+  }
+  *out = g_noalloc_ptr[dev];
+  return KFBI_OK;
+}
+
+// twiddles exp(-2 pi i m / 2N) and s_k = -4/h^2 sin^2(k pi / 2N), the tables
+// dst_init writes from the host
+__global__ void __launch_bounds__(KFBI_BLOCK) k_dst_tables(int N, double h, double* tw, double* eig1) {
+  const int i = blockIdx.x * blockDim.x + threadIdx.x;
+  const int M = 2 * N;
+  if (i < M) {
+    const double ang = -2.0 * M_PI * (double)i / (double)M;
+    tw[2 * i] = cos(ang);
+    tw[2 * i + 1] = sin(ang);
+  }
+  if (i <= N) {
+    const double sn = sin((double)i * M_PI / (2.0 * N));
+    eig1[i] = -4.0 / (h * h) * sn * sn;
+  }
+}
+
+// zero box boundary of a grid array
+__global__ void __launch_bounds__(KFBI_BLOCK) k_zero_box_boundary(GridDesc g, double* v) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= g.n_nodes) return;
+  const int N = g.N;
+  int64_t r = i;
+  bool edge = false;
+  for (int a = 0; a < g.d; ++a) {
+    const int c = (int)(r % g.n1);
+    r /= g.n1;
+    edge = edge || c == 0 || c == N;
+  }
+  if (edge) v[i] = 0.0;
+}
+
+}  // namespace
+
+extern "C" kfbi_status kfbi_box_solve_noalloc(int dim, int order, int N, double lo, double hi, double kappa,
+                                              const double* F, double* v, void* stream) {
+  if (dim != 2 && dim != 3) {
+    kfbi_set_error("dim must be 2 or 3 (got %d)", dim);
+    return KFBI_E_INVALID;
+  }
+  if (order != 2 && order != 4) {
+    kfbi_set_error("order must be 2 or 4 (got %d)", order);
+    return KFBI_E_INVALID;
+  }
+  const int nmax = dim == 2 ? NOALLOC_MAX_N2 : NOALLOC_MAX_N3;
+  if (N < 8 || (N & (N - 1)) || N > nmax) {
+    kfbi_set_error("N must be a power of two in [8, %d] for a %dD box solve without allocation (got %d): the "
+                   "static scratch holds two grids of %lld values",
+                   nmax, dim, N, (long long)NOALLOC_GRID);
+    return KFBI_E_INVALID;
+  }
+  if (!(hi > lo) || !(kappa >= 0.0)) {
+    kfbi_set_error("need hi > lo and kappa >= 0");
+    return KFBI_E_INVALID;
+  }
+  if (!F || !v || F == v) {
+    kfbi_set_error("box solve needs distinct F and v");
+    return KFBI_E_INVALID;
+  }
+  GridDesc g{};
+  g.d = dim;
+  g.order = order;
+  g.p = order == 4 ? 4 : 2;
+  g.N = N;
+  g.n1 = N + 1;
+  g.K = 0;
+  g.lo = lo;
+  g.hi = hi;
+  g.h = (hi - lo) / N;
+  g.kappa = kappa;
+  g.n_nodes = 1;
+  for (int a = 0; a < dim; ++a) g.n_nodes *= g.n1;
+  if (tile_lds(tile_lines(dim, N), N) > DST_LDS_CU) {
+    kfbi_set_error("box solver LDS footprint too large (N = %d)", N);
+    return KFBI_E_INVALID;
+  }
+  double* base = nullptr;
+  KCHK(noalloc_scratch(&base));
+  double* T1 = base;
+  double* T2 = base + NOALLOC_GRID;
+  double* tw = base + 2 * NOALLOC_GRID;
+  double* eig1 = tw + NOALLOC_TW;
+  hipStream_t st = (hipStream_t)stream;
+  hipLaunchKernelGGL(k_dst_tables, dim3((2 * N + KFBI_BLOCK - 1) / KFBI_BLOCK), dim3(KFBI_BLOCK), 0, st, N, g.h, tw,
+                     eig1);
+  DstArgs a{};
+  a.g = g;
+  a.tw = (const double2*)tw;
+  a.eig1 = eig1;
+  const int passes = dim == 2 ? 3 : 5;
+  // the passes of dst_solve: x, (y,) last axis with the divide, (y,) x
+  const int ax2[3] = {0, 1, 0}, md2[3] = {0, 1, 0};
+  const int ax3[5] = {0, 1, 2, 1, 0}, md3[5] = {0, 0, 1, 0, 0};
+  const double* src[5] = {F, T1, T2, T1, T2};
+  double* dst2[3] = {T1, T2, v};
+  double* dst3[5] = {T1, T2, T1, T2, v};
+  for (int q = 0; q < passes; ++q) {
+    a.ax = dim == 2 ? ax2[q] : ax3[q];
+    a.mode = dim == 2 ? md2[q] : md3[q];
+    a.in = src[q];
+    a.out = dim == 2 ? dst2[q] : dst3[q];
+    launch_args(a, false, st);
+  }
+  hipLaunchKernelGGL(k_zero_box_boundary, dim3((unsigned)((g.n_nodes + KFBI_BLOCK - 1) / KFBI_BLOCK)),
+                     dim3(KFBI_BLOCK), 0, st, g, v);
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
 }

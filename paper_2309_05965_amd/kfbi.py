@@ -76,6 +76,8 @@ ABI = {
     "kfbi_plan_timing": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64),
                           ctypes.POINTER(ctypes.c_double)], ctypes.c_int),
     "kfbi_plan_destroy": ([ctypes.c_void_p], ctypes.c_int),
+    "kfbi_box_solve_noalloc": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
+                                ctypes.c_double, c_double_p, c_double_p, ctypes.c_void_p], ctypes.c_int),
     "kfbi_plan_manufactured_data": ([ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 5, ctypes.c_int),
     "kfbi_batch_create": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                            ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
@@ -309,6 +311,17 @@ class Plan:
             _check(st)
         return psi, u, {"iters": info.iters, "status": info.status, "est_rel_res": info.est_rel_res,
                         "true_rel_res": info.true_rel_res}
+
+
+def box_solve_noalloc(dim, order, N, lo, hi, kappa, F, v):
+    """FFT box solve v = A_h^-1 F (zero box data) of a grid given by its
+    parameters, with no plan and no allocation in the library (static
+    device scratch); F, v caller-owned float64 device tensors of
+    (N+1)^dim entries, ordered on the current torch stream."""
+    st = torch.cuda.current_stream(F.device).cuda_stream
+    _check(load().kfbi_box_solve_noalloc(int(dim), int(order), int(N), float(lo), float(hi), float(kappa),
+                                         _ptr(F), _ptr(v), ctypes.c_void_p(st)))
+    return v
 
 
 def device_data(plan, prob, sol):
