@@ -1,19 +1,30 @@
-"""Benchmark: KFBI solves/s at 1e-8 relative GMRES residual on one MI355X.
+"""Benchmark: KFBI solves/s at 1e-8 relative GMRES residual on one MI355X,
+plain FP64 against FP32 multigrid + learned warm start.
 
-Workload (N=1): the 2D fourth-order interface problem with the star
-r(t) = 0.5 + 0.15 sin 5t on a 512 x 512 grid over [-1, 1]^2, beta 1000/1,
-reduced kappa 1, manufactured u_in = cos 2x e^y, u_out = x^2 - y^3 (seeded
-synthetic data).  One step is one whole solve of the hot path from data
-resident in HBM: geometry set-up and collocation factorisation on the
-device (S0, S1), the BIE right-hand side, GMRES over the simple-interface-
-problem operator (S2-S6) to |r| <= 1e-8 |b|, the final grid solve (S7) and
-the true-residual check, all in FP64 with the FFT (DST-I) box solver and a
-zero initial density.
+Workload (N=1): the learned-start workload, 3D fourth-order interface
+problems on a 128^3 grid over [-1, 1]^3: random ellipsoids (semi-axes
+U(0.3, 0.7), random rotation), beta 1/100, kappa 0, zero source and box
+data, random Fourier jumps (8 modes, N(0, 1) coefficients), held-out seeds
+from 1,000,000 on (the network never saw them).  One step is one whole
+solve of one held-out problem that its plan has not solved before: set-up
+(geometry and collocation, S0 + S1) of the new geometry, the learned
+prediction of the initial density (mixed form), the BIE right-hand side,
+GMRES over the simple-interface-problem operator (S2-S6) to |r| <= 1e-8 |b|,
+the true residual of a fresh full-accuracy FP64 matvec, and the final grid
+solve (S7).  The jump data are resident in HBM before the timed region.
+
+  value (headline): the mixed + learned form, solves/s: FP32 multigrid
+      V-cycles in FP64 defect correction to tol / 10, the inner tolerance
+      relaxed inside GMRES (inexact Krylov), learned initial density;
+  config.plain_fp64_solves_per_s: FP64 multigrid to 1e-12, zero start, on
+      the same held-out problems (on a plan of its own);
+  config.mixed_learned_over_plain: their ratio (the metric's comparison).
 
 Prints one JSON line (rank 0, N=1 only).  The roofline object reports the
-dominant kernel, the box-solve pass (k_dst), timed with HIP events on the
-plan's stream during the timed region; the cpu_baseline object times the
-FP64 NumPy oracle on this host on a bounded sample of the same workload.
+finest-level multigrid smoothing sweep (the most-launched kernel of the
+headline), timed with HIP events on the plan's stream after the timed
+region; cpu_baseline times the FP64 NumPy oracle on this host on one
+held-out problem of the same workload.
 """
 import os
 
@@ -22,6 +33,7 @@ for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
 
 import argparse  # noqa: E402
 import json  # noqa: E402
+import platform  # noqa: E402
 import sys  # noqa: E402
 import time  # noqa: E402
 
@@ -29,147 +41,318 @@ import numpy as np  # noqa: E402
 
 METRIC = "KFBI solves/s at 1e-8 rel residual: plain FP64 vs FP32-MG+learned warm start"
 HBM_PEAK_GBS = 8000.0
-# HBM bytes per k_dst launch on this workload (mean over the three passes),
-# from rocprofv3 FETCH_SIZE / WRITE_SIZE scaled by a plain copy's counts
-# (profiles/k_dst_star512_hbm_counters.md); null once k_dst changes
-K_DST_TRAFFIC_BYTES = 4.670e6
+HELDOUT0 = 1_000_000
+# mixed form: inner tolerance tol * EPS_FRAC, relaxed inside GMRES by RELAX
+EPS_FRAC = 0.1
+RELAX = 0.1
 
 
 def parse():
     ap = argparse.ArgumentParser()
     ap.add_argument("--gpus", type=int, default=1)
-    ap.add_argument("--steps", type=int, default=20)
-    ap.add_argument("--warmup", type=int, default=3)
-    ap.add_argument("--N", type=int, default=512)
+    ap.add_argument("--steps", type=int, default=16, help="timed held-out problems per form")
+    ap.add_argument("--warmup", type=int, default=2, help="untimed held-out problems per form first")
+    ap.add_argument("--N", type=int, default=128)
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
-    ap.add_argument("--copy-calibration", action="store_true",
-                    help="end with one plain 256 MiB device copy (reference for HBM counters)")
-    ap.add_argument("--cpu-seconds", type=float, default=15.0)
+    ap.add_argument("--cpu-suite", action="store_true",
+                    help="only time the oracle on every workload (long; one JSON line)")
     return ap.parse_args()
 
 
-def cpu_baseline(N, tol, budget):
-    """The oracle as it stands, single-threaded BLAS, repeated whole solves
-    of the same workload until the time budget is used."""
-    sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
+def cpu_info():
+    model = platform.processor() or ""
+    try:
+        with open("/proc/cpuinfo") as f:
+            for line in f:
+                if line.startswith("model name"):
+                    model = line.split(":", 1)[1].strip()
+                    break
+    except OSError:
+        pass
+    return {"cpu_model": model, "nproc": os.cpu_count(), "numpy": np.__version__}
+
+
+# ---------------------------------------------------------------- oracle timings
+def oracle_solve_config5(seed, N, tol):
     from oracle import kfbi as okfbi
     from paper_2309_05965_amd import workloads as W
-    prob, sol = W.config2(N)
-    n = 0
+    prob, geom, jmp = W.config5(seed, N)
     t0 = time.perf_counter()
-    while True:
-        pl = okfbi.Plan(prob)
-        s = pl.geo["surf"]
-        data = W.make_data(prob, sol, s["pos"], s["nrm"], s["iface"], pl.geo["st"]["pde_pts"],
-                           pl.geo["dofs"]["iface"])
-        pl.solve(data, tol=tol)
-        n += 1
-        el = time.perf_counter() - t0
-        if el > budget or n >= 50:
-            break
-    return {"value": n / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
-            "sample": "%d whole solves of the same 512^2 workload (geometry, collocation, data, "
-                      "GMRES to 1e-8, final solve) in %.1f s, NumPy/SciPy FP64, 1 thread" % (n, el)}
+    pl = okfbi.Plan(prob)
+    data = W.jump_data(prob, jmp, pl.geo["surf"]["pos"])
+    r = pl.solve(data, tol=tol)
+    return time.perf_counter() - t0, r["iters"], r["true_rel_res"]
 
 
-def time_solves(fn, reps):
-    import torch
-    torch.cuda.synchronize()
+def oracle_solve_manufactured(prob, sol, tol):
+    from oracle import kfbi as okfbi
+    from paper_2309_05965_amd import workloads as W
     t0 = time.perf_counter()
-    for _ in range(reps):
-        fn()
-    torch.cuda.synchronize()
-    return reps / (time.perf_counter() - t0)
+    pl = okfbi.Plan(prob)
+    s = pl.geo["surf"]
+    data = W.make_data(prob, sol, s["pos"], s["nrm"], s["iface"], pl.geo["st"]["pde_pts"], pl.geo["dofs"]["iface"])
+    r = pl.solve(data, tol=tol)
+    return time.perf_counter() - t0, r["iters"], r["true_rel_res"]
 
 
-def forms_config2(plan, prob, data, tol, reps):
-    """Solves/s of the star workload with each box solver (set-up included)."""
-    out = {}
-    for name, solver, eps in (("fp64_mg_eps1e-12", "mg64", 1e-12), ("fp32_mg_eps1e-10", "mg32", 1e-10)):
-        plan.set_box_solver(solver, eps_in=eps, max_cycles=16)
-
-        def step():
-            plan.setup(prob)
-            plan.solve(data, tol=tol)
-        step()
-        out[name] = time_solves(step, reps)
-    plan.set_box_solver("fft")
+def first_resolved_seeds(count, N, start=HELDOUT0):
+    """The first `count` held-out seeds whose geometry the oracle resolves
+    on the N^3 grid (the same rule the device applies)."""
+    from oracle import geometry
+    from paper_2309_05965_amd import workloads as W
+    out, s = [], start
+    while len(out) < count:
+        try:
+            geometry.build(W.config5(s, N)[0])
+            out.append(s)
+        except geometry.GeometryError:
+            pass
+        s += 1
     return out
 
 
-def forms_config5(tol, reps, n_problems=4):
-    """The ellipsoid workload of the learned start (128^3, beta 1/100) on
-    held-out seeds, solves/s with set-up and prediction inside the timed
-    solve.  Plain FP64: FP64 multigrid to 1e-12, zero start.  Mixed +
-    learned: FP32 multigrid in FP64 defect correction to tol / 10, the inner
-    tolerance relaxed inside GMRES (relax 0.1, inexact Krylov; the true
-    residual of a full-accuracy matvec is checked and a continuation pass
-    takes over if it misses tol), learned start.  The other forms separate
-    the ingredients (eps_in 1e-10 is the stricter setting); the FFT
-    forms use the paper's exact box solve.  Two untimed passes first: the
-    multigrid cycle cap adapts after a plan's first solve."""
+def cpu_baseline(N, tol):
+    """The oracle as it stands, one thread, one whole solve of the first
+    resolvable held-out problem of the headline workload (zero start)."""
+    seed = first_resolved_seeds(1, N)[0]
+    el, its, tr = oracle_solve_config5(seed, N, tol)
+    out = {"value": 1.0 / el, "unit": "solves/s", "cores": 1, "kind": "oracle",
+           "sample": "1 whole solve (geometry, collocation, data, GMRES to %g, final solve) of held-out seed %d "
+                     "of the 128^3 ellipsoid workload, %.1f s, %d iterations, true residual %.1e, NumPy/SciPy "
+                     "FP64, 1 thread" % (tol, seed, el, its, tr)}
+    out.update(cpu_info())
+    return out
+
+
+def cpu_suite(tol):
+    """Oracle timings of every workload (one thread per solve; the batch
+    over a process pool of all host cores).  Long: run on its own."""
+    import multiprocessing as mp
+    from paper_2309_05965_amd import workloads as W
+    res = {"host": cpu_info(), "tol": tol}
+    for name, mk in (("config1_ellipse64", lambda: W.config1(64)), ("config2_star512", lambda: W.config2(512)),
+                     ("config3_torus_sphere128", lambda: W.config3(128))):
+        times, its = [], []
+        for _ in range(3 if name != "config3_torus_sphere128" else 1):
+            prob, sol = mk()
+            el, it, tr = oracle_solve_manufactured(prob, sol, tol)
+            times.append(el)
+            its.append(it)
+        res[name] = {"median_s": float(np.median(times)), "solves_per_s": 1.0 / float(np.median(times)),
+                     "runs": len(times), "iters": its[-1], "true_rel_res": tr}
+        print(name, res[name], flush=True)
+    seeds = first_resolved_seeds(16, 128)
+    t0 = time.perf_counter()
+    with mp.Pool(min(16, os.cpu_count() or 1)) as pool:
+        rows = pool.starmap(oracle_solve_config5, [(s, 128, tol) for s in seeds])
+    el = time.perf_counter() - t0
+    res["config5_ellipsoid128_16_heldout"] = {"wall_s": el, "solves_per_s": len(seeds) / el, "processes": min(16, os.cpu_count() or 1),
+                                               "iters_mean": float(np.mean([r[1] for r in rows])),
+                                               "solve_s_median": float(np.median([r[0] for r in rows]))}
+    print("config5", res["config5_ellipsoid128_16_heldout"], flush=True)
+    batch = W.config4_batch(512)
+    t0 = time.perf_counter()
+    with mp.Pool(min(16, os.cpu_count() or 1)) as pool:
+        rows = pool.map(_oracle_batch_one, range(len(batch)))
+    el = time.perf_counter() - t0
+    ok = sum(1 for r in rows if r)
+    res["config4_batch512"] = {"wall_s": el, "solved": ok, "solved_per_s": ok / el, "processes": min(16, os.cpu_count() or 1)}
+    print("config4", res["config4_batch512"], flush=True)
+    return res
+
+
+def _oracle_batch_one(i):
+    from oracle import geometry
+    from paper_2309_05965_amd import workloads as W
+    prob, sol = W.config4_batch(512)[i]
+    try:
+        oracle_solve_manufactured(prob, sol, 1e-8)
+        return True
+    except geometry.GeometryError:
+        return False
+
+
+# ---------------------------------------------------------------- GPU forms
+class HeldOut:
+    """The first `count` held-out problems of the ellipsoid workload that
+    the set-up resolves on the N^3 grid, with their jump data resident on
+    the device (generated at the solver's own surface points, which a
+    set-up reproduces bit for bit)."""
+
+    def __init__(self, count, N, start=HELDOUT0):
+        import torch
+        from paper_2309_05965_amd import kfbi
+        from paper_2309_05965_amd import workloads as W
+        self.items = []
+        plan = None
+        s = start
+        while len(self.items) < count:
+            prob, geom, jmp = W.config5(s, N)
+            try:
+                if plan is None:
+                    plan = kfbi.Plan(prob)
+                else:
+                    plan.setup(prob)
+                self.items.append((s, prob, geom, jmp, kfbi.device_jump_data(plan, jmp)))
+            except kfbi.KfbiError:
+                if plan is not None:
+                    plan.close()
+                plan = None
+            s += 1
+        torch.cuda.synchronize()
+        plan.close()
+        self.seeds = [it[0] for it in self.items]
+
+
+def run_form(ho, warm, timed, tol, solver, eps, relax, learned_start, keep_u=False):
+    """Solves/s of one form over held-out problems: a plan of its own, the
+    first `warm` problems untimed, then `timed` problems, each solved once.
+    Returns (solves/s, iterations, true residuals, densities, solutions)."""
     import torch
     from paper_2309_05965_amd import kfbi, learned, warmstart
-    from paper_2309_05965_amd import workloads as W
-    model = warmstart.load_pretrained()
-    S = learned.samples()
-    probs = []
-    for seed in range(1_000_200, 1_000_200 + 16):
-        prob, geom, jmp = W.config5(seed, 128)
-        try:
-            pl = kfbi.Plan(prob)
-        except kfbi.KfbiError:
-            continue
-        probs.append((prob, geom, jmp, pl, kfbi.device_jump_data(pl, jmp)))
-        if len(probs) == n_problems:
-            break
-    res, iters, tres = {}, {}, {}
-    for name, solver, eps, relax, learned_start in (
-            ("fp64_mg_zero_start", "mg64", 1e-12, 0.0, False),
-            ("fp32_mg_relaxed_learned_start", "mg32", 0.1 * tol, 0.1, True),
-            ("fp32_mg_relaxed_zero_start", "mg32", 0.1 * tol, 0.1, False),
-            ("fp64_mg_relaxed_zero_start", "mg64", 0.1 * tol, 0.1, False),
-            ("fp32_mg_relaxed_eps1e-10_learned_start", "mg32", 1e-10, 0.1, True),
-            ("fp32_mg_learned_start", "mg32", 1e-10, 0.0, True),
-            ("fp64_fft_zero_start", "fft", 0.0, 0.0, False),
-            ("fp64_fft_learned_start", "fft", 0.0, 0.0, True)):
-        its, trs = [], []
+    model = warmstart.load_pretrained() if learned_start else None
+    S = learned.samples() if learned_start else None
+    items = ho.items[:warm + timed]
+    plan = kfbi.Plan(items[0][1])
+    plan.set_box_solver(solver, eps_in=eps, max_cycles=16)
+    plan.set_box_relaxation(relax)
+    n = plan.n_nodes
+    U = [torch.empty(n, dtype=torch.float64, device="cuda") for _ in range(timed)] if keep_u else None
+    psis, its, trs = [], [], []
 
-        def run():
-            its.clear()
-            trs.clear()
-            for prob, geom, jmp, pl, d in probs:
-                pl.setup(prob)
-                psi0 = warmstart.predict(model, pl, geom, jmp, S) if learned_start else None
-                _, _, info = pl.solve(d, tol=tol, psi0=psi0)
-                its.append(info["iters"])
-                trs.append(info["true_rel_res"])
-        for prob, geom, jmp, pl, d in probs:
-            pl.set_box_solver(solver, eps_in=eps if eps > 0 else 1e-12, max_cycles=16)
-            pl.set_box_relaxation(relax)
-        run()
-        run()
+    def one(i, it):
+        _, prob, geom, jmp, data = it
+        plan.setup(prob)
+        psi0 = warmstart.predict(model, plan, geom, jmp, S) if learned_start else None
+        psi, _, info = plan.solve(data, tol=tol, psi0=psi0, u_out=U[i] if (keep_u and i >= 0) else None)
+        return psi, info
+
+    for it in items[:warm]:
+        one(-1, it)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for i, it in enumerate(items[warm:]):
+        psi, info = one(i, it)
+        psis.append(psi)
+        its.append(info["iters"])
+        trs.append(info["true_rel_res"])
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    plan.close()
+    return timed / el, its, trs, psis, U
+
+
+def smoothing_roofline(prob, N, solver):
+    """Average duration of the finest-level post-smoothing sweep of the
+    multigrid V-cycle (HIP events on the plan's stream around the two
+    sweeps of every V-cycle of eager box solves, every correction active)."""
+    import torch
+    from paper_2309_05965_amd import kfbi
+    plan = kfbi.Plan(prob)
+    plan.set_box_solver(solver, eps_in=1e-30, max_cycles=8)     # all 8 corrections active
+    F = torch.randn(plan.n_nodes, dtype=torch.float64, device="cuda")
+    plan.box_solve(F)
+    plan.profile(2)
+    for _ in range(10):
+        plan.box_solve(F)
+    ivals, launches, ms = plan.timing()
+    plan.profile(False)
+    plan.close()
+    es = 4 if solver == "mg32" else 8
+    bytes_per_launch = 3 * es * (N - 1) ** 3          # read u and f, write u' at every interior node
+    avg_s = ms / 1e3 / launches
+    achieved = bytes_per_launch / avg_s / 1e9
+    return {"kernel": "k_sweep3 smoothing sweep, finest level (%s)" % ("FP32" if es == 4 else "FP64"),
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
+            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": avg_s * 1e6,
+            "algorithmic_bytes_per_launch": bytes_per_launch,
+            "timing": "HIP events around the two finest-level post-smoothing sweeps of %d V-cycles (%d launches) "
+                      "of eager box solves after the timed region" % (ivals, launches)}
+
+
+def forms_config5_ingredients(ho, warm, timed, tol):
+    """Each ingredient of the mixed form alone, on the same held-out problems
+    (a plan per form, each problem solved once per plan)."""
+    out = {}
+    for name, solver, eps, relax, ls in (
+            ("fp32_mg_relaxed_zero_start", "mg32", EPS_FRAC * tol, RELAX, False),
+            ("fp64_mg_relaxed_zero_start", "mg64", EPS_FRAC * tol, RELAX, False),
+            ("fp32_mg_unrelaxed_learned_start", "mg32", EPS_FRAC * tol, 0.0, True),
+            ("fp64_fft_zero_start", "fft", 1e-12, 0.0, False),
+            ("fp64_fft_learned_start", "fft", 1e-12, 0.0, True)):
+        v, its, trs, _, _ = run_form(ho, warm, timed, tol, solver, eps, relax, ls)
+        out[name] = {"solves_per_s": v, "iters_mean": float(np.mean(its)), "true_rel_res_max": float(np.max(trs))}
+    return out
+
+
+def forms_star512(tol, steps=10):
+    """The 2D fourth-order star (512^2, beta 1000/1), FP64 FFT box solve,
+    one repeated problem, set-up included (the paper's own solver)."""
+    import torch
+    from paper_2309_05965_amd import kfbi
+    from paper_2309_05965_amd import workloads as W
+    prob, sol = W.config2(512)
+    plan = kfbi.Plan(prob)
+    data = kfbi.device_data(plan, prob, sol)
+    u = torch.empty(plan.n_nodes, dtype=torch.float64, device="cuda")
+    for _ in range(3):
+        plan.setup(prob)
+        plan.solve(data, tol=tol, u_out=u)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    for _ in range(steps):
+        plan.setup(prob)
+        _, _, info = plan.solve(data, tol=tol, u_out=u)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    reg = plan.export("region").cpu().numpy().reshape(513, 513)
+    err = float(np.max(np.abs(u.cpu().numpy() - W.exact_solution(prob, sol, reg).ravel())))
+    plan.close()
+    return {"fp64_fft_solves_per_s": steps / el, "iters": info["iters"], "max_error_vs_exact": err}
+
+
+def forms_config3(tol, N):
+    """Torus + concentric sphere (gap 2h, beta 1/100, 4th order): FP64 FFT
+    and the mixed FP32-multigrid form, one repeated problem, set-up
+    included; maximum error against the exact solution."""
+    import torch
+    from paper_2309_05965_amd import kfbi
+    from paper_2309_05965_amd import workloads as W
+    prob, sol = W.config3(N)
+    plan = kfbi.Plan(prob)
+    data = kfbi.device_data(plan, prob, sol)
+    reg = plan.export("region").cpu().numpy().reshape((N + 1,) * 3)
+    ue = W.exact_solution(prob, sol, reg).ravel()
+    u = torch.empty(plan.n_nodes, dtype=torch.float64, device="cuda")
+    out = {"n_dof": int(plan.n_dof)}
+    reps = 5 if N <= 128 else 2
+    for name, solver, eps, relax in (("fp64_fft", "fft", 1e-12, 0.0), ("fp32_mg_relaxed", "mg32", EPS_FRAC * tol, RELAX),
+                                     ("fp64_mg_eps1e-12", "mg64", 1e-12, 0.0)):
+        plan.set_box_solver(solver, eps_in=eps, max_cycles=16)
+        plan.set_box_relaxation(relax)
+        for _ in range(2):
+            plan.setup(prob)
+            plan.solve(data, tol=tol, u_out=u)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
         for _ in range(reps):
-            run()
+            plan.setup(prob)
+            _, _, info = plan.solve(data, tol=tol, u_out=u)
         torch.cuda.synchronize()
-        res[name] = reps * len(probs) / (time.perf_counter() - t0)
-        iters[name] = float(np.mean(its))
-        tres[name] = float(np.max(trs))
-    res["gmres_iters_mean"] = iters
-    res["true_rel_res_max"] = tres
-    res["mixed_learned_over_plain"] = res["fp32_mg_relaxed_learned_start"] / res["fp64_mg_zero_start"]
-    res["problems"] = len(probs)
-    return res
+        el = time.perf_counter() - t0
+        out[name] = {"solves_per_s": reps / el, "iters": info["iters"], "true_rel_res": info["true_rel_res"],
+                     "max_error_vs_exact": float(np.max(np.abs(u.cpu().numpy() - ue)))}
+    plan.close()
+    return out
 
 
 def forms_batch(workers=(1, 8)):
     """The 512-problem batch of random stars (N in {64, 128, 256, 512},
-    beta_in log-uniform 1e-2..1e2): problems/s over the whole batch (the
-    under-resolved stars fail fast in set-up and are counted)."""
+    beta_in log-uniform 1e-2..1e2): solved problems per second over the
+    whole batch (stars under-resolved on their grid fail in set-up, as the
+    oracle's set-up reports them, and are not counted as solved)."""
     import torch
     from paper_2309_05965_amd import kfbi
     from paper_2309_05965_amd import workloads as W
@@ -184,8 +367,8 @@ def forms_batch(workers=(1, 8)):
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         ok = sum(1 for i in info if i["status"] == 0)
-        out["workers_%d" % w] = {"problems_per_s": len(probs) / el, "solved_per_s": ok / el, "solved": ok,
-                                 "unresolved": len(probs) - ok}
+        out["workers_%d" % w] = {"solved_per_s": ok / el, "solved": ok, "unresolved": len(probs) - ok,
+                                 "wall_s": el}
         b.close()
     return out
 
@@ -196,106 +379,69 @@ def main():
         print("bench.py runs on one GPU only: the method has no multi-GPU path in this build "
               "(--gpus %d requested)" % args.gpus, file=sys.stderr)
         sys.exit(2)
-    import torch
     sys.path.insert(0, os.path.dirname(os.path.abspath(__file__)))
-    from paper_2309_05965_amd import kfbi
-    from paper_2309_05965_amd import workloads as W
-
+    if args.cpu_suite:
+        print(json.dumps(cpu_suite(args.tol)), flush=True)
+        return
+    import torch
     torch.cuda.set_device(0)
-    prob, sol = W.config2(args.N)
-    # the plan lives on a stream of its own (a caller's non-default stream is
-    # used for the solve as it is; on the default stream the library orders a
-    # private stream before and after every solve with events)
+    # plans live on a stream of their own (a caller's non-default stream is
+    # used for the solve as it is; on the default stream the library orders
+    # a private stream before and after every solve with events)
     torch.cuda.set_stream(torch.cuda.Stream())
-    plan = kfbi.Plan(prob)
-    data = kfbi.device_data(plan, prob, sol)          # inputs resident in HBM
-    u = torch.zeros(plan.n_nodes, dtype=torch.float64, device="cuda")
+    N, tol = args.N, args.tol
+    W_, K = args.warmup, args.steps
+    ho = HeldOut(W_ + K, N)
+    seeds = ho.seeds
 
-    def step():
-        plan.setup(prob)                              # S0 + S1 on the device
-        return plan.solve(data, tol=args.tol, u_out=u)
+    mixed, its_m, trs_m, psi_m, U_m = run_form(ho, W_, K, tol, "mg32", EPS_FRAC * tol, RELAX, True, keep_u=True)
+    plain, its_p, trs_p, psi_p, U_p = run_form(ho, W_, K, tol, "mg64", 1e-12, 0.0, False, keep_u=True)
+    du = max(float(((a - b).abs().max() / b.abs().max()).item()) for a, b in zip(U_m, U_p))
+    dpsi = max(float(((a - b).norm() / b.norm()).item()) for a, b in zip(psi_m, psi_p))
+    del U_m, U_p
+    torch.cuda.empty_cache()
+    roof = smoothing_roofline(ho.items[0][1], N, "mg32")
 
-    for _ in range(args.warmup):
-        step()
-    torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = []
-    for _ in range(args.steps):
-        _, _, info = step()
-        infos.append(info)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
-
-    # roofline of the box-solve pass: HIP events on the plan's stream around
-    # back-to-back box solves of the same grid (the GMRES iterations of the
-    # timed region run as captured graphs, which events cannot split)
-    F = torch.randn(plan.n_nodes, dtype=torch.float64, device="cuda")
-    for _ in range(5):
-        plan.box_solve(F)
-    plan.profile(True)
-    for _ in range(200):
-        plan.box_solve(F)
-    solves, launches, ms = plan.timing()
-    plan.profile(False)
-
-    N = args.N
-    d = prob["dim"]
-    bytes_per_launch = 2 * 8 * (N - 1) ** d           # one read and one write of every interior value
-    avg_launch_s = ms / 1e3 / launches
-    achieved = bytes_per_launch / avg_launch_s / 1e9
     out = {
         "metric": METRIC,
-        "value": args.steps / el,
+        "value": mixed,
         "unit": "solves/s",
         "n_gpus": 1,
-        "steps": args.steps,
-        "warmup": args.warmup,
-        "ms_per_step": 1e3 * el / args.steps,
+        "steps": K,
+        "warmup": W_,
+        "ms_per_step": 1e3 / mixed,
         "higher_is_better": True,
         "scaling": "weak",
         "vs_baseline": None,
-        "dtype": "f64",
+        "dtype": "f32+f64",
         "data": "synthetic",
         "config": {
-            "workload": "2D 4th-order KFBI, star r=0.5+0.15 sin 5t, %dx%d grid on [-1,1]^2, beta_in/out "
-                        "1000/1, reduced kappa 1, GMRES tol %g, plain FP64, FFT box solver, zero start"
-                        % (N, N, args.tol),
-            "n_dof": int(plan.n_dof),
-            "n_surf": int(plan.n_surf),
-            "gmres_iters": int(infos[-1]["iters"]),
-            "true_rel_res": float(infos[-1]["true_rel_res"]),
-            "box_solves_per_step": 3 + int(infos[-1]["iters"]),
+            "workload": "3D 4th-order KFBI, learned-start workload: random ellipsoids (axes U(0.3,0.7), random "
+                        "rotation), %d^3 grid on [-1,1]^3, beta_in/out 1/100, kappa 0, zero source and box data, "
+                        "random Fourier jumps (8 modes), held-out seeds %d..%d, each solved once per form, set-up "
+                        "and prediction inside the timed solve, GMRES tol %g" % (N, seeds[W_], seeds[-1], tol),
+            "mixed_form": "FP32 multigrid V(2,2) in FP64 defect correction to %g, relaxed inside GMRES (factor %g), "
+                          "learned initial density (bf16 MLP)" % (EPS_FRAC * tol, RELAX),
+            "plain_form": "FP64 multigrid V(2,2) in FP64 defect correction to 1e-12, zero start",
+            "plain_fp64_solves_per_s": plain,
+            "mixed_learned_over_plain": mixed / plain,
+            "gmres_iters_mean": {"mixed": float(np.mean(its_m)), "plain": float(np.mean(its_p))},
+            "true_rel_res_max": {"mixed": float(np.max(trs_m)), "plain": float(np.max(trs_p))},
+            "mixed_vs_plain_max_rel_diff": {"u": du, "psi_l2": dpsi},
         },
-        "roofline": {
-            "kernel": "k_dst (box-solve pass)",
-            "bound": "hbm",
-            "achieved": achieved,
-            "peak": HBM_PEAK_GBS,
-            "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS,
-            "traffic": K_DST_TRAFFIC_BYTES if N == 512 else None,
-            "avg_launch_us": avg_launch_s * 1e6,
-            "algorithmic_bytes_per_launch": bytes_per_launch,
-            "timing": "HIP events around %d back-to-back box solves (%d k_dst launches) after the timed region"
-                      % (solves, launches),
-        },
+        "roofline": roof,
     }
     if not args.no_forms:
-        # the other forms of the metric, measured after the timed region
         out["forms"] = {
-            "star512": dict(fp64_fft=out["value"], **forms_config2(plan, prob, data, args.tol, 5)),
-            "ellipsoid128_learned_workload": forms_config5(args.tol, 2),
+            "ellipsoid128_ingredients": forms_config5_ingredients(ho, W_, min(K, 8), tol),
+            "star512": forms_star512(tol),
+            "torus_sphere128": forms_config3(tol, 128),
+            "torus_sphere256": forms_config3(tol, 256),
             "batch512_random_stars": forms_batch(),
         }
     if not args.no_cpu_baseline:
-        out["cpu_baseline"] = cpu_baseline(N, args.tol, args.cpu_seconds)
+        out["cpu_baseline"] = cpu_baseline(N, tol)
     print(json.dumps(out), flush=True)
-    if args.copy_calibration:
-        src = torch.ones(64 * 1024 * 1024, dtype=torch.float32, device="cuda")
-        dst = torch.empty_like(src)
-        torch.cuda.synchronize()
-        dst.copy_(src)
-        torch.cuda.synchronize()
 
 
 if __name__ == "__main__":

@@ -290,12 +290,14 @@ kfbi_status kfbi_solve(kfbi_plan* plan, const kfbi_data* data, const kfbi_opts* 
                        double* psi_inout, double* u_out, kfbi_info* info);
 
 /* Event timing of the box-solve kernels (tracing aid).  With enable = 1
- * every subsequent box solve of the plan is bracketed by two HIP events on
- * the plan's stream; kfbi_plan_timing synchronises the stream and returns
- * the number of box solves and kernel launches recorded since enabling and
- * their total elapsed milliseconds (launches are back to back, so
- * ms / launches is the average launch duration).  enable = 0 stops and
- * clears the record. */
+ * every subsequent FFT box solve of the plan is bracketed by two HIP events
+ * on the plan's stream; with enable = 2 the two post-smoothing sweeps of the
+ * finest level of every multigrid V-cycle are (eager box solves only, not
+ * the captured GMRES iterations).  kfbi_plan_timing synchronises the stream
+ * and returns the number of bracketed intervals and kernel launches
+ * recorded since enabling and their total elapsed milliseconds (launches
+ * are back to back, so ms / launches is the average launch duration).
+ * enable = 0 stops and clears the record. */
 kfbi_status kfbi_plan_profile(kfbi_plan* plan, int enable);
 kfbi_status kfbi_plan_timing(kfbi_plan* plan, int64_t* solves, int64_t* launches, double* ms);
 

@@ -709,7 +709,7 @@ kfbi_status dst_init(kfbi_plan* pl) {
 
 void dst_solve(kfbi_plan* pl, const double* F, double* v) {
   hipEvent_t e0 = nullptr, e1 = nullptr;
-  if (pl->prof_on && pl->prof_ev && !pl->ctl_active) {
+  if (pl->prof_on == 1 && pl->prof_ev && !pl->ctl_active) {
     if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess) {
       (void)hipEventRecord(e0, pl->stream);
     } else {

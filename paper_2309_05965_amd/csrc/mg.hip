@@ -921,8 +921,23 @@ void vcycle(kfbi_plan* pl, const Hier<T>& H, Ctl ctl) {
     const int64_t o = L.off;
     hipLaunchKernelGGL((k_prolong<T>), dim3(gsblk(interior(l))), dim3(MG_BLOCK), 0, st, ctl, H.lv[l], H.lv[l + 1],
                        (const T*)u, u);
+    // tracing aid (profile mode 2, eager solves only): events around the
+    // two post-smoothing sweeps of the finest level
+    hipEvent_t e0 = nullptr, e1 = nullptr;
+    if (l == 0 && pl->prof_on == 2 && pl->prof_ev && !pl->ctl_active) {
+      if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess)
+        (void)hipEventRecord(e0, st);
+      else
+        e0 = e1 = nullptr;
+    }
     sweep<T, T, SW_SMOOTH>(pl, ctl, L.N, L.c, L.coef, u + o, f + o, tb + o);
     sweep<T, T, SW_SMOOTH>(pl, ctl, L.N, L.c, L.coef, tb + o, f + o, u + o);
+    if (e0 && e1) {
+      (void)hipEventRecord(e1, st);
+      pl->prof_ev->push_back(e0);
+      pl->prof_ev->push_back(e1);
+      pl->prof_launches += 2;
+    }
   }
 }
 

@@ -232,8 +232,9 @@ class Plan:
 
     # ------------------------------------------------------------------ tracing
     def profile(self, enable=True):
-        """Start (or stop) HIP-event timing of the box-solve kernels."""
-        _check(load().kfbi_plan_profile(self._h, 1 if enable else 0))
+        """Start (or stop) HIP-event timing of the box-solve kernels: True or
+        1 the FFT box solves, 2 the finest-level multigrid smoothing sweeps."""
+        _check(load().kfbi_plan_profile(self._h, int(enable)))
 
     def timing(self):
         """(box solves, kernel launches, total ms) recorded since profile()."""
