@@ -193,17 +193,21 @@ kfbi_status kfbi_plan_export(const kfbi_plan* plan, int which, void* dst, int64_
 
 /* Box solver of the plan (Alg. 1 Step 3.3; the paper uses the FFT):
  *   KFBI_BOX_FFT   exact solve by the type-I sine transform (default);
- *   KFBI_BOX_MG64  multigrid: FP64 V(2,2) cycles (damped Jacobi, full
- *                  weighting, linear interpolation, rediscretised coarse
- *                  operators) inside FP64 defect correction;
- *   KFBI_BOX_MG32  the same V-cycles in FP32 inside the FP64 defect
- *                  correction (residual r = F - A_h v always in FP64).
+ *   KFBI_BOX_MG64  multigrid: FP64 two-grid cycles (two damped-Jacobi
+ *                  steps before and after the coarse correction, full
+ *                  weighting, linear interpolation, the operator
+ *                  rediscretised on the grid N/2 and solved there exactly
+ *                  by the sine transform in FP64) inside FP64 defect
+ *                  correction; needs N >= 16;
+ *   KFBI_BOX_MG32  the same cycles with the fine-grid work in FP32 inside
+ *                  the FP64 defect correction (residual r = F - A_h v
+ *                  always in FP64, the coarse solve in FP64).
  * The multigrid loop stops when |F - A_h v|_2 <= eps_in |F|_2 or after
  * max_cycles corrections (1..64).  Every later box solve, simple solve,
  * matvec and solve of the plan uses this solver; a re-setup keeps it.
- * Allocates the level arrays (about (2^d/(2^d-1)) 3 n_nodes values) on
+ * Allocates three fine grids (FP32 or FP64) and four coarse FP64 grids on
  * the first multigrid request.  Returns KFBI_E_INVALID for an unknown
- * solver, eps_in <= 0 or max_cycles out of range. */
+ * solver, eps_in <= 0, max_cycles out of range or N < 16. */
 enum { KFBI_BOX_FFT = 0, KFBI_BOX_MG64 = 1, KFBI_BOX_MG32 = 2 };
 kfbi_status kfbi_plan_set_box_solver(kfbi_plan* plan, int solver, double eps_in, int max_cycles);
 

@@ -9,36 +9,29 @@ paper solves it with the FFT; multigrid is the other solver of that step
 named for the GPU build, and its converged result has a plain definition:
 the same A_h^-1 F that fd.dst_solve computes exactly.
 
-Multigrid (textbook geometric MG, written out plainly):
-  levels      N_l = N / 2^l down to N_l = 2 (one interior node), the same
-              compact operator rediscretised with h_l = 2^l h and the same
-              reduced kappa;
-  smoother    damped Jacobi u <- u + (omega_l / a_l) (f - A_l u), a_l the
-              central stencil coefficient, omega_l = 2 / (rho_lo + rho_hi)
-              with [rho_lo, rho_hi] the range of the symbol lambda(theta)/a_l
-              over the high frequencies (max_k theta_k >= pi/2), sampled on a
-              64^d grid of theta in (0, pi];
+Multigrid (a textbook two-grid method, written out plainly):
+  levels      the fine grid N and the coarse grid N/2, the same compact
+              operator rediscretised with h_c = 2 h and the same reduced
+              kappa;
+  smoother    damped Jacobi u <- u + (omega / a) (f - A u), a the central
+              stencil coefficient, omega = 2 / (rho_lo + rho_hi) with
+              [rho_lo, rho_hi] the range of the symbol lambda(theta)/a over
+              the high frequencies (max_k theta_k >= pi/2), sampled on a 64^d
+              grid of theta in (0, pi];
   restriction full weighting, the tensor product of (1/4, 1/2, 1/4) about the
-              fine node 2I;
-  prolongation (bi/tri)linear interpolation, P = 2^d R^T;
-  coarsest    the single interior node is solved exactly, u = f / a_l;
-  cycle       V(nu1, nu2) from a zero initial guess.
+              fine node 2I, formed in the inner precision and taken to FP64;
+  coarse      the coarse system solved exactly in FP64: the rediscretised
+              operator is diagonal in the type-I sine basis (fd.dst_solve);
+  prolongation (bi/tri)linear interpolation of the FP64 coarse correction,
+              P = 2^d R^T, rounded to the inner precision and added;
+  cycle       nu1 pre-smoothing steps from a zero initial guess, the coarse
+              correction, nu2 post-smoothing steps: (nu1, nu2) = (2, 2).
 Defect correction: r = F - A_h v in FP64; stop when |r|_2 <= eps |F|_2;
 otherwise e = (cycles V-cycles on r in the inner precision), v <- v + e.
 """
 import numpy as np
 
 from . import fd
-
-
-def levels(N):
-    """Grid sizes N, N/2, ..., 2 (N a power of two >= 2)."""
-    out = []
-    n = N
-    while n >= 2:
-        out.append(n)
-        n //= 2
-    return out
 
 
 def central(st):
@@ -116,32 +109,38 @@ def prolong(e):
 
 
 class Hierarchy:
-    """Operators, central coefficients and Jacobi weights of every level."""
+    """Fine operator, its central coefficient and Jacobi weight, and the
+    coarse grid of the two-grid cycle."""
 
     def __init__(self, d, order, N, h, kappa, dtype=np.float64):
-        self.d = d
+        self.d, self.order, self.N, self.h, self.kappa = d, order, N, h, kappa
         self.dtype = np.dtype(dtype)
-        self.Ns = levels(N)
-        self.ops, self.a, self.w = [], [], []
-        for l, n in enumerate(self.Ns):
-            A, _ = fd.stencils(d, order, h * 2 ** l, kappa)
-            self.ops.append(A)
-            self.a.append(central(A))
-            self.w.append(jacobi_weight(A, d)[0])
+        A, _ = fd.stencils(d, order, h, kappa)
+        self.ops = [A]
+        self.a = central(A)
+        self.w = jacobi_weight(A, d)[0]
+        self.Nc = N // 2
+        self.hc = 2.0 * h
 
-    def vcycle(self, f, l=0, nu=(2, 2)):
-        """One V(nu1, nu2) cycle on level l from a zero initial guess."""
+    def coarse_solve(self, fc):
+        """A_c^-1 f_c on the coarse interior (FP64, zero boundary)."""
+        d, Nc = self.d, self.Nc
+        ec = np.zeros((Nc + 1,) * d)
+        ec[(slice(1, Nc),) * d] = fd.dst_solve(fc[(slice(1, Nc),) * d], d, self.order, Nc, self.hc, self.kappa)
+        return ec
+
+    def vcycle(self, f, nu=(2, 2)):
+        """One two-grid cycle (nu1, nu2) from a zero initial guess, in the
+        inner precision, with the coarse correction in FP64."""
         dt = self.dtype.type
-        A, a, w = self.ops[l], self.a[l], self.w[l]
-        if self.Ns[l] == 2:
-            return (f / dt(a)).astype(self.dtype) * _interior_mask(f)
+        A, a, w = self.ops[0], self.a, self.w
         u = np.zeros_like(f)
         for _ in range(nu[0]):
             u = u + dt(w / a) * (f - apply_full(A, u))
             u = u * _interior_mask(u)
         r = (f - apply_full(A, u)) * _interior_mask(f)
-        ec = self.vcycle(restrict(r), l + 1, nu)
-        u = u + prolong(ec)
+        ec = self.coarse_solve(restrict(r).astype(np.float64))
+        u = u + prolong(ec).astype(self.dtype)
         for _ in range(nu[1]):
             u = u + dt(w / a) * (f - apply_full(A, u))
             u = u * _interior_mask(u)
@@ -155,7 +154,7 @@ def _interior_mask(u):
 
 
 def solve(F, d, order, N, h, kappa, eps=1e-12, inner=np.float64, cycles=1, nu=(2, 2), maxit=100):
-    """Defect correction around V-cycles in the inner precision.
+    """Defect correction around two-grid cycles in the inner precision.
     F: interior right-hand side ((N-1)^d).  Returns (v interior, outer
     iterations, relative residual history)."""
     hier = Hierarchy(d, order, N, h, kappa, inner)
@@ -174,6 +173,6 @@ def solve(F, d, order, N, h, kappa, eps=1e-12, inner=np.float64, cycles=1, nu=(2
         e = np.zeros_like(r, dtype=hier.dtype)
         ri = r.astype(hier.dtype)
         for _ in range(cycles):
-            e = e + hier.vcycle(ri - apply_full(hier.ops[0], e), 0, nu)
+            e = e + hier.vcycle(ri - apply_full(hier.ops[0], e), nu)
         v = v + e.astype(np.float64)
     return v[(slice(1, N),) * d], it, hist

@@ -115,6 +115,12 @@ void free_plan(kfbi_plan* pl) {
   if (pl->mg_u) (void)hipFree(pl->mg_u);
   if (pl->mg_t) (void)hipFree(pl->mg_t);
   if (pl->mg_f) (void)hipFree(pl->mg_f);
+  dfree(pl->mg_Fc);
+  dfree(pl->mg_Uc);
+  dfree(pl->mg_T1c);
+  dfree(pl->mg_T2c);
+  dfree(pl->mg_twc);
+  dfree(pl->mg_eigc);
   dfree(pl->mg_part);
   dfree(pl->mg_ctl);
   dfree(pl->mg_scal);
@@ -983,11 +989,14 @@ kfbi_status solve_body(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* op
                        kfbi_info* info, int m, double tol) {
   // Multigrid box solves inside a solve run at most mg_cap_eff corrections:
   // the captured iterations enqueue every correction up to the cap and the
-  // ones after convergence return at once, each still costing a launch.
+  // ones after convergence return at once, each still costing its launches.
   // The cap is the most corrections any box solve of the previous solve
-  // needed plus 2 (the count hardly varies with the right-hand side); a
-  // box solve stopped by it above its tolerance restores the configured
-  // cap for the next solves.
+  // needed plus 1 (the count hardly varies with the right-hand side); a
+  // box solve to eps_in stopped by it above its tolerance raises it by 2
+  // for the next solves.  Relaxed GMRES iterations run with caps of their
+  // own (the previous solve's count of that iteration plus 1), and their
+  // record is kept across solves: an iteration that hit its cap records the
+  // cap, so the next solve's cap for it is one higher.
   const bool mg = pl->box_solver != KFBI_BOX_FFT;
   if (mg) {
     pl->mg_run_cap = pl->mg_cap_eff > 0 ? pl->mg_cap_eff : pl->mg_maxit;
@@ -997,15 +1006,14 @@ kfbi_status solve_body(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* op
   if (mg) {
     if (s == KFBI_OK || s == KFBI_E_NOT_CONVERGED) {
       const int most = pl->h_pinned[2], hit = pl->h_pinned[3];
+      const int run = pl->mg_run_cap > 0 ? pl->mg_run_cap : pl->mg_maxit;
       if (hit > 0)
-        pl->mg_cap_eff = pl->mg_maxit;
+        pl->mg_cap_eff = run + 2 < pl->mg_maxit ? run + 2 : pl->mg_maxit;
       else if (most > 0)
-        pl->mg_cap_eff = most + 2 < pl->mg_maxit ? most + 2 : pl->mg_maxit;
-      // per-iteration record of the relaxed pass; a cap hit drops it
-      pl->log_n = 0;
-      if (hit == 0)
-        for (int j = 0; j < pl->log_k; ++j) pl->log_prev[j] = pl->h_log[j];
-      if (hit == 0) pl->log_n = pl->log_k;
+        pl->mg_cap_eff = most + 1 < pl->mg_maxit ? most + 1 : pl->mg_maxit;
+      // per-iteration record of the relaxed pass
+      for (int j = 0; j < pl->log_k; ++j) pl->log_prev[j] = pl->h_log[j];
+      pl->log_n = pl->log_k;
     }
     pl->mg_run_cap = 0;
   }

@@ -37,6 +37,7 @@ constexpr int PS = 3;                   // LDS pad shift (see padi)
 
 struct DstArgs {
   const int* ctl;      // nothing to do once ctl[1] is set (device GMRES loop)
+  const int* mctl;     // nor once mctl[0] is set (converged multigrid loop, coarse solves)
   // source of the first pass of the matvec: the corrected right-hand side,
   // zero except at the irregular nodes, built here from the correction
   // values of the density
@@ -386,9 +387,12 @@ size_t tile_lds(int TL, int N) { return sizeof(double2) * 2 * (size_t)(TL / 2) *
 template <int LOGM, int MODE, bool FS>
 __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
   static_assert(!FS || (LOGM == 10 && MODE == 0), "the four-step FFT is written for M = 1024, one transform");
-  // the converged flag is read first but tested only once the tile's loads
-  // are in flight, so its latency overlaps theirs (a skipped pass has only
-  // read and staged in LDS)
+  // a converged multigrid loop skips most of its coarse solves: tested
+  // before any load
+  if (a.mctl && a.mctl[0]) return;
+  // the GMRES converged flag is read first but tested only once the tile's
+  // loads are in flight, so its latency overlaps theirs (a skipped pass has
+  // only read and staged in LDS)
   const int stop = a.ctl ? a.ctl[1] : 0;
   constexpr int M = 1 << LOGM, N = M / 2, Mp = padded_len(M);
   extern __shared__ double2 lds[];
@@ -525,6 +529,7 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
 // divided spectrum to LDS and transforms it again.
 template <int MODE>
 __global__ void __launch_bounds__(KFBI_BLOCK) k_dst1024(DstArgs a) {
+  if (a.mctl && a.mctl[0]) return;
   const int stop = a.ctl ? a.ctl[1] : 0;
   constexpr int M = 1024, N = 512, nl = N - 1, Mp = padded_len(M);
   __shared__ double2 S[MODE == 1 ? Mp : 1];   // divided spectrum (MODE 1)
@@ -605,6 +610,9 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst1024(DstArgs a) {
 int tile_lines(int d, int N) {
   const int nl = N - 1;
   const int64_t lines = d == 3 ? (int64_t)nl * nl : nl;
+  // 64^3 (the coarse grid of the 128^3 two-grid cycle): two 128-point
+  // sequences per work group instead of one (993 tiles)
+  if (d == 3 && N == 64) return 4;
   for (int tl = 8; tl > 2; tl -= 2) {
     if (tile_lds(tl, N) * 4 > DST_LDS_CU) continue;
     if ((lines + tl - 1) / tl < 1024) continue;
@@ -662,6 +670,7 @@ void launch_args(DstArgs& a, bool src_corr, hipStream_t st) {
 void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out, bool src_corr = false) {
   DstArgs a;
   a.ctl = pl->ctl_active;
+  a.mctl = nullptr;
   a.src_corr = src_corr ? 1 : 0;
   a.row_start = pl->row_start;
   a.row_end = pl->row_end;
@@ -684,18 +693,47 @@ void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out,
 
 }  // namespace
 
-kfbi_status dst_init(kfbi_plan* pl) {
-  int N = pl->g.N, M = 2 * N;
-  std::vector<double> tw((size_t)2 * M), eig((size_t)N + 1);
+void dst_host_tables(int N, double h, double* tw, double* eig1) {
+  const int M = 2 * N;
   for (int m = 0; m < M; ++m) {
-    double ang = -2.0 * M_PI * (double)m / (double)M;
+    const double ang = -2.0 * M_PI * (double)m / (double)M;
     tw[2 * m] = cos(ang);
     tw[2 * m + 1] = sin(ang);
   }
   for (int k = 0; k <= N; ++k) {
-    double sn = sin((double)k * M_PI / (2.0 * N));
-    eig[k] = -4.0 / (pl->g.h * pl->g.h) * sn * sn;
+    const double sn = sin((double)k * M_PI / (2.0 * N));
+    eig1[k] = -4.0 / (h * h) * sn * sn;
   }
+}
+
+void dst_solve_grid(const GridDesc& g, const double* tw, const double* eig1, double* T1, double* T2,
+                    const double* F, double* v, const int* ctl, const int* mctl, hipStream_t st) {
+  DstArgs a{};
+  a.ctl = ctl;
+  a.mctl = mctl;
+  a.g = g;
+  a.tw = (const double2*)tw;
+  a.eig1 = eig1;
+  // the passes of dst_solve: x, (y,) last axis with the divide, (y,) x
+  const int n = g.d == 2 ? 3 : 5;
+  const int ax2[3] = {0, 1, 0}, md2[3] = {0, 1, 0};
+  const int ax3[5] = {0, 1, 2, 1, 0}, md3[5] = {0, 0, 1, 0, 0};
+  const double* src[5] = {F, T1, T2, T1, T2};
+  double* dst2[3] = {T1, T2, v};
+  double* dst3[5] = {T1, T2, T1, T2, v};
+  for (int q = 0; q < n; ++q) {
+    a.ax = g.d == 2 ? ax2[q] : ax3[q];
+    a.mode = g.d == 2 ? md2[q] : md3[q];
+    a.in = src[q];
+    a.out = g.d == 2 ? dst2[q] : dst3[q];
+    launch_args(a, false, st);
+  }
+}
+
+kfbi_status dst_init(kfbi_plan* pl) {
+  int N = pl->g.N, M = 2 * N;
+  std::vector<double> tw((size_t)2 * M), eig((size_t)N + 1);
+  dst_host_tables(N, pl->g.h, tw.data(), eig.data());
   HIPCHK(hipMemcpyAsync(pl->tw, tw.data(), sizeof(double) * 2 * M, hipMemcpyHostToDevice, pl->stream));
   HIPCHK(hipMemcpyAsync(pl->eig1, eig.data(), sizeof(double) * (N + 1), hipMemcpyHostToDevice, pl->stream));
   HIPCHK(hipStreamSynchronize(pl->stream));
@@ -879,24 +917,7 @@ extern "C" kfbi_status kfbi_box_solve_noalloc(int dim, int order, int N, double 
   hipStream_t st = (hipStream_t)stream;
   hipLaunchKernelGGL(k_dst_tables, dim3((2 * N + KFBI_BLOCK - 1) / KFBI_BLOCK), dim3(KFBI_BLOCK), 0, st, N, g.h, tw,
                      eig1);
-  DstArgs a{};
-  a.g = g;
-  a.tw = (const double2*)tw;
-  a.eig1 = eig1;
-  const int passes = dim == 2 ? 3 : 5;
-  // the passes of dst_solve: x, (y,) last axis with the divide, (y,) x
-  const int ax2[3] = {0, 1, 0}, md2[3] = {0, 1, 0};
-  const int ax3[5] = {0, 1, 2, 1, 0}, md3[5] = {0, 0, 1, 0, 0};
-  const double* src[5] = {F, T1, T2, T1, T2};
-  double* dst2[3] = {T1, T2, v};
-  double* dst3[5] = {T1, T2, T1, T2, v};
-  for (int q = 0; q < passes; ++q) {
-    a.ax = dim == 2 ? ax2[q] : ax3[q];
-    a.mode = dim == 2 ? md2[q] : md3[q];
-    a.in = src[q];
-    a.out = dim == 2 ? dst2[q] : dst3[q];
-    launch_args(a, false, st);
-  }
+  dst_solve_grid(g, tw, eig1, T1, T2, F, v, nullptr, nullptr, st);
   hipLaunchKernelGGL(k_zero_box_boundary, dim3((unsigned)((g.n_nodes + KFBI_BLOCK - 1) / KFBI_BLOCK)),
                      dim3(KFBI_BLOCK), 0, st, g, v);
   HIPCHK(hipGetLastError());

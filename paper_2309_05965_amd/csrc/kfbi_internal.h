@@ -18,7 +18,6 @@
 #define KFBI_MAXD 15       // max Dirichlet points
 #define KFBI_MAXN 10       // max Neumann points
 #define KFBI_GMRES_MAX 512
-#define KFBI_MG_MAXL 12    // multigrid levels (N <= 2048)
 #define KFBI_NGRAPH 5      // captured GMRES graphs of 1, 2, 4, 8 and 16 iterations
 #define KFBI_MG_CAPS 16    // per-iteration multigrid caps captured as graphs of their own
 
@@ -151,12 +150,15 @@ struct kfbi_plan {
   int box_solver;
   double mg_eps;
   int mg_maxit;
-  int mg_L, mg_lc;               // levels; first level run in LDS
-  int64_t mg_off[KFBI_MG_MAXL];  // element offset of each level
-  double mg_c[KFBI_MG_MAXL][27]; // A_l on the 3^d cube
-  double mg_w[KFBI_MG_MAXL];     // Jacobi weights
-  void *mg_u, *mg_t, *mg_f;      // level arrays (float or double), boundaries zero
+  double mg_c[27];                // A_h on the 3^d cube (fine grid)
+  double mg_w;                   // Jacobi weight of the fine grid
+  void *mg_u, *mg_t, *mg_f;      // fine-grid arrays (float or double), boundaries zero
   int64_t mg_bytes;
+  // coarse grid N/2 of the two-grid cycle, solved exactly by the sine
+  // transform in FP64: right-hand side, solution, two pass buffers, tables
+  GridDesc mg_gc;
+  double *mg_Fc, *mg_Uc, *mg_T1c, *mg_T2c, *mg_twc, *mg_eigc;
+  int64_t mg_nc;                 // (N/2 + 1)^d the coarse arrays hold
   double* mg_part;               // partial sums of the outer residual
   int* mg_ctl;                   // [done, corrections, most corrections since the solve began,
                                  //  box solves stopped by the cap above eps, then per GMRES
@@ -256,6 +258,14 @@ void dst_solve(kfbi_plan* pl, const double* F, double* v);
 extern std::shared_mutex kfbi_capture_mutex;
 
 kfbi_status mg_configure(kfbi_plan* pl, int solver, double eps, int maxit);
+// exact solve A_h v = F (zero box data) of the grid g by the sine transform
+// with the given tables and pass buffers; skipped when ctl[1] (GMRES
+// converged) or mctl[0] (multigrid converged) is set
+void dst_solve_grid(const GridDesc& g, const double* tw, const double* eig1, double* T1, double* T2,
+                    const double* F, double* v, const int* ctl, const int* mctl, hipStream_t st);
+// twiddles exp(-2 pi i m / 2N) (m < 2N, interleaved re, im) and the 1D
+// eigenvalues s_k = -4/h^2 sin^2(k pi / 2N) (k <= N) of the sine transform
+void dst_host_tables(int N, double h, double* tw, double* eig1);
 void mg_solve(kfbi_plan* pl, const double* F, double* v);
 void mg_matvec_rhs(kfbi_plan* pl);
 void dst_solve_corrections(kfbi_plan* pl, const double* psi, double* v);

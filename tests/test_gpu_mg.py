@@ -1,9 +1,10 @@
-"""Multigrid box solver on the GPU (FP64 and FP32 V-cycles inside FP64
-defect correction) against the oracle (runs on an MI355X).
+"""Multigrid box solver on the GPU (FP64 and FP32 two-grid cycles with an
+exact FP64 coarse solve, inside FP64 defect correction) against the oracle
+(runs on an MI355X).
 
-  * one and three V-cycles in FP64 equal the oracle's V-cycles element by
+  * one and three cycles in FP64 equal the oracle's cycles element by
     element (1e-12 relative: same algorithm, different summation order);
-  * one FP32 V-cycle equals the oracle's FP64 V-cycle to FP32 accuracy;
+  * one FP32 cycle equals the oracle's FP64 cycle to FP32 accuracy;
   * the converged defect-correction result satisfies the rigorous bound
     |v - A^-1 F|_2 <= |F - A v|_2 / |lambda_min| against the exact DST solve,
     and the number of corrections matches the oracle's loop (+-1);
@@ -26,7 +27,7 @@ BOXES = {
     "2d_o4_64": (2, 4, 64, 1.0),
     "2d_o4_512": (2, 4, 512, 1.0),
     "2d_o2_64": (2, 2, 64, 0.0),
-    "2d_o4_16": (2, 4, 16, 1.0),      # all levels in LDS
+    "2d_o4_16": (2, 4, 16, 1.0),      # smallest grid: coarse grid 8 x 8
     "3d_o4_32": (3, 4, 32, 0.0),
     "3d_o4_64": (3, 4, 64, 0.5),
 }
@@ -172,12 +173,12 @@ def test_relaxed_inner_tolerance(case, eps, relax):
 @pytest.mark.parametrize("case", ["c2_128", "sphere_32"])
 def test_adaptive_cycle_cap(case):
     """Inside kfbi_solve the defect-correction loop is enqueued up to the
-    most corrections the previous solve needed plus 2, not the configured
+    most corrections the previous solve needed plus 1, not the configured
     maximum.  Converged box solves do the same corrections under either
     cap, so the second solve (adapted cap) equals the first (configured cap
     40) bit for bit; a cap that stops the box solves above their tolerance
-    still gives a finished solve, after which the configured cap is used
-    again and the original result comes back."""
+    still gives a finished solve; with the configured cap set again the
+    original result comes back."""
     from paper_2309_05965_amd import kfbi
     if case == "c2_128":
         prob, sol = W.config2(128)

@@ -1,4 +1,4 @@
-"""Pins of the oracle's multigrid box solver and defect-correction loop
+"""Pins of the oracle's two-grid box solver and defect-correction loop
 (Alg. 1 Step 3.3 with multigrid in place of the FFT): transfer operators
 against their closed forms, the Jacobi weight against the Fourier symbol,
 the V-cycle contraction, and the converged result against the exact DST
@@ -61,7 +61,10 @@ def test_vcycle_contracts(d, order, N):
         e_new = e + hier.vcycle(r)
         rates.append(np.linalg.norm(e_new) / np.linalg.norm(e))
         e = e_new
-    assert max(rates[2:]) < 0.35
+    # the two-grid cycle with exact coarse solve contracts the error by
+    # 0.07 (fourth order) and 0.12 (second order) per cycle, independently
+    # of h; a wrong transfer weight or coarse spacing loses most of that
+    assert max(rates[2:]) < (0.1 if order == 4 else 0.15)
 
 
 @pytest.mark.parametrize("d,order,N,inner", [(2, 4, 64, np.float64), (2, 4, 64, np.float32),
