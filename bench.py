@@ -213,7 +213,6 @@ def run_form(ho, warm, timed, tol, solver, eps, relax, learned_start, keep_u=Fal
     import torch
     from paper_2309_05965_amd import kfbi, learned, warmstart
     model = warmstart.load_pretrained() if learned_start else None
-    S = learned.samples() if learned_start else None
     items = ho.items[:warm + timed]
     plan = kfbi.Plan(items[0][1])
     plan.set_box_solver(solver, eps_in=eps, max_cycles=16)
@@ -225,7 +224,7 @@ def run_form(ho, warm, timed, tol, solver, eps, relax, learned_start, keep_u=Fal
     def one(i, it):
         _, prob, geom, jmp, data = it
         plan.setup(prob)
-        psi0 = warmstart.predict(model, plan, geom, jmp, S) if learned_start else None
+        psi0 = warmstart.predict(model, plan, geom, jmp) if learned_start else None
         psi, _, info = plan.solve(data, tol=tol, psi0=psi0, u_out=U[i] if (keep_u and i >= 0) else None)
         return psi, info
 

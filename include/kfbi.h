@@ -372,6 +372,22 @@ kfbi_status kfbi_mlp_loss_grad(kfbi_mlp* mlp, const float* X, const float* Yt, i
 kfbi_status kfbi_mlp_train_step(kfbi_mlp* mlp, const float* X, const float* Yt, int B, float lr, float* loss);
 kfbi_status kfbi_mlp_destroy(kfbi_mlp* mlp);
 
+/* Linear head (the density is linear in the jump coefficients when the
+ * source and box data vanish, Sec. 3.2 with fhat = 0, gB = 0): X holds B
+ * examples of R consecutive rows; the network's output of example b, its R
+ * rows read as one row of R widths[L] entries, holds nb basis vectors of
+ * K = R widths[L] / nb entries, and the head is y[b][k] = sum_j C[b][j]
+ * out[b][j K + k].  C [B x nb] fp32; Y, Yt [B x K] fp32.  loss_grad_lin /
+ * train_step_lin use the loss mean over all entries of (y - Yt)^2 (the head
+ * in fp32, its gradient C[b][j] dy[b][k] back-propagated through the
+ * network); train_step_lin takes one Adam step as kfbi_mlp_train_step.
+ * KFBI_E_INVALID if nb does not divide R widths[L]. */
+kfbi_status kfbi_mlp_forward_lin(kfbi_mlp* mlp, const float* X, int B, int R, const float* C, int nb, float* Y);
+kfbi_status kfbi_mlp_loss_grad_lin(kfbi_mlp* mlp, const float* X, int B, int R, const float* C, int nb,
+                                   const float* Yt, float* loss, float* grads);
+kfbi_status kfbi_mlp_train_step_lin(kfbi_mlp* mlp, const float* X, int B, int R, const float* C, int nb,
+                                    const float* Yt, float lr, float* loss);
+
 /* C [M x N] (fp32, row stride ldc) = op(A) op(B) with bf16 operands (raw
  * 16-bit storage) and fp32 accumulation on the matrix cores.  transA = 0:
  * A is [M x K] (row stride lda); 1: A is [K x M].  transB = 0: B is
@@ -405,6 +421,31 @@ kfbi_status kfbi_sh_transfer(kfbi_plan* plan, const double* geom, const double* 
  * concurrent transfers on one plan are not allowed. */
 kfbi_status kfbi_sh_sample(kfbi_plan* plan, const double* geom, const double* psi_dof, const double* S, int ns,
                            double scale, float* psi_s);
+/* Network input of the linear-head start for P ellipsoids, geom [P][15] as
+ * above: X [P][8][15] fp32, one row per Fourier mode m of the jump data:
+ * (a_k - 0.5) / 0.2 for the three semi-axes, the mode's wave vector in the
+ * scaled body frame diag(a) Q^T k_m (3), and the nine entries of Q. */
+kfbi_status kfbi_geometry_input(const double* geom, int P, void* stream, float* X);
+/* Least-squares coefficients coef [81] (device, FP64) of scale * psi_dof in
+ * the 81 real spherical harmonics of the body-frame direction of the plan's
+ * DOFs (n_dof >= 81), on the plan's stream (targets of the linear head). */
+kfbi_status kfbi_sh_coefficients(kfbi_plan* plan, const double* geom, const double* psi_dof, double scale,
+                                 double* coef);
+/* The expansion sum_i coef[i] Y_i (81 harmonics of the body-frame
+ * direction) at the plan's DOFs, times scale: psi_dof [n_dof]. */
+kfbi_status kfbi_sh_expand(kfbi_plan* plan, const double* geom, const double* coef, double scale, double* psi_dof);
+/* Learned initial density of one ellipsoid problem (Alg. 1 Step 2 with a
+ * predicted start): the network (15 -> ... -> 4 x 81, one row per Fourier
+ * mode, kfbi_geometry_input(geom)) gives for every mode m the SH
+ * coefficients of the four basis densities of a_1m, a_2m, b_1m, b_2m; the
+ * head contracts them with jumps [nb = 32] (device FP64, packed as a_1[8],
+ * a_2[8], b_1[8], b_2[8] like kfbi_ellipsoid_features), times scale, and
+ * the expansion is evaluated at the plan's DOFs into psi_dof [n_dof].
+ * Ordered on the plan's stream (the network's kernels too); uses the plan's
+ * transfer workspace; the network must not be used by another thread
+ * meanwhile. */
+kfbi_status kfbi_learned_start(kfbi_plan* plan, kfbi_mlp* mlp, int nb, const double* geom, const double* jumps,
+                               double scale, double* psi_dof);
 /* The 81 real orthonormal spherical harmonics (no Condon-Shortley phase,
  * index l^2 + l + m) at n directions: Y [81][n]. */
 kfbi_status kfbi_real_sh(const double* dirs, int n, void* stream, double* Y);

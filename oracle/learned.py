@@ -20,6 +20,10 @@ interface and jump data:
             functions) to the sample values, evaluated at the DOFs;
   targets   the solved density psi* at the DOFs, fitted the same way and
             evaluated at the samples.
+Linear-head form (the density is linear in the 32 jump coefficients when
+the source and box data vanish): the network maps the geometry to 32 basis
+densities, each as its 81 SH coefficients; lin_head contracts them with the
+jump coefficients, and the targets are the SH coefficients of psi*.
 """
 import numpy as np
 import scipy.special
@@ -128,13 +132,69 @@ def mlp_loss_grad(Ws, bs, X, Yt, emulate=True):
     """L = mean (out - Yt)^2 over all entries, and (dL/dW_l, dL/db_l).
     With emulate the backward GEMM operands (activations, weights and the
     back-propagated gradients) are rounded to bf16 like the GPU's."""
-    r = bf16 if emulate else (lambda t: np.asarray(t, dtype=np.float64))
     a, zs = mlp_forward(Ws, bs, X, emulate)
     out = a[-1]
     n = out.size
     diff = out - np.asarray(Yt, dtype=np.float64)
     loss = float(np.sum(diff * diff) / n)
-    dz = 2.0 * diff / n
+    gW, gb = mlp_backward(Ws, a, zs, 2.0 * diff / n, emulate)
+    return loss, gW, gb
+
+
+def lin_head(z, C, nb):
+    """Linear head: the network's output row z (nb blocks of K) holds nb
+    basis vectors; y[k] = sum_j C[j] z[j K + k]."""
+    z = np.asarray(z, dtype=np.float64)
+    B, W = z.shape
+    K = W // nb
+    return np.einsum("bj,bjk->bk", np.asarray(C, dtype=np.float64), z.reshape(B, nb, K))
+
+
+def mlp_lin_loss_grad(Ws, bs, X, C, Yt, emulate=True, R=1):
+    """L = mean (lin_head(MLP(X), C) - Yt)^2 and (dL/dW_l, dL/db_l): X holds
+    B examples of R rows, the output of an example is its R rows read as
+    one row; the head is applied in full precision; its gradient with
+    respect to the network's output is dz[j K + k] = C[j] dy[k]."""
+    a, zs = mlp_forward(Ws, bs, X, emulate)
+    C = np.asarray(C, dtype=np.float64)
+    nb = C.shape[1]
+    B = C.shape[0]
+    y = lin_head(a[-1].reshape(B, -1), C, nb)
+    n = y.size
+    diff = y - np.asarray(Yt, dtype=np.float64)
+    loss = float(np.sum(diff * diff) / n)
+    dy = 2.0 * diff / n
+    dz = (C[:, :, None] * dy[:, None, :]).reshape(a[-1].shape)
+    gW, gb = mlp_backward(Ws, a, zs, dz, emulate)
+    return loss, gW, gb
+
+
+def mode_rows(geom):
+    """Network input of the per-mode linear-head network (15 per row, 8 rows):
+    (a - 0.5) / 0.2, the mode's scaled body-frame wave vector diag(a) Q^T k_m
+    (k_m = (pi/2)(m & 1, (m >> 1) & 1, (m >> 2) & 1)), and Q row-major."""
+    c, a, Q = geom
+    a = np.asarray(a, dtype=np.float64)
+    Q = np.asarray(Q, dtype=np.float64)
+    rows = []
+    for m in range(8):
+        k = (np.pi / 2) * np.array([m & 1, (m >> 1) & 1, (m >> 2) & 1], dtype=np.float64)
+        rows.append(np.concatenate([(a - 0.5) / 0.2, a * (Q.T @ k), Q.ravel()]))
+    return np.array(rows)
+
+
+def mode_major(jumps32):
+    """Packed jump coefficients (a_1[8], a_2[8], b_1[8], b_2[8]) reordered to
+    (m, t) = (mode, a_1 a_2 b_1 b_2), the order of the per-mode network's
+    basis vectors."""
+    j = np.asarray(jumps32).reshape(4, 8)
+    return j.T.reshape(-1)
+
+
+def mlp_backward(Ws, a, zs, dz, emulate=True):
+    """Gradients (dL/dW_l, dL/db_l) from the gradient dz of the loss with
+    respect to the last layer's output, through the ReLU layers."""
+    r = bf16 if emulate else (lambda t: np.asarray(t, dtype=np.float64))
     gW = [None] * len(Ws)
     gb = [None] * len(Ws)
     for l in range(len(Ws) - 1, -1, -1):
@@ -143,7 +203,18 @@ def mlp_loss_grad(Ws, bs, X, Yt, emulate=True):
         if l > 0:
             da = r(dz) @ r(Ws[l]).T
             dz = da * (zs[l - 1] > 0.0)
-    return loss, gW, gb
+    return gW, gb
+
+
+def sh_coefficients(geom, dof_pos, psi_dof, lmax=LMAX):
+    """Least-squares coefficients of the density in the real SH of degree
+    <= lmax of the body-frame direction of the DOFs."""
+    return sh_fit(body_coords(geom, dof_pos) / np.asarray(geom[1])[None, :], psi_dof, lmax)
+
+
+def sh_values(geom, dof_pos, coef, lmax=LMAX):
+    """The SH expansion with coefficients coef at the DOFs."""
+    return real_sh(body_coords(geom, dof_pos) / np.asarray(geom[1])[None, :], lmax) @ np.asarray(coef)
 
 
 def adam_step(params, grads, m, v, t, lr, b1=0.9, b2=0.999, eps=1e-8):

@@ -139,7 +139,7 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 // writes one partial per (row, column, slab); a second kernel sums the
 // slabs in a fixed order and applies the GEMM epilogue.  W row-major
 // [K x N], N and the row stride multiples of 8 (16-byte loads).
-constexpr int GV_BMAX = 4, GV_COLS = 256, GV_KC = 64;
+constexpr int GV_BMAX = 8, GV_COLS = 256, GV_KC = 64;
 
 __global__ void __launch_bounds__(256) k_gemv_part(int B, int N, int K, const uint16_t* A, int lda,
                                                    const uint16_t* W, int ldw, float* part) {
@@ -250,6 +250,67 @@ __global__ void k_colsum(int rows, int cols, const float* dz, float* db) {
   float s = 0.f;
   for (int r = 0; r < rows; ++r) s += dz[(int64_t)r * cols + c];
   db[c] = s;
+}
+
+// Linear head (the density is linear in the jump coefficients): the last
+// layer's output row z of example b holds nb basis vectors of K entries,
+// y[b, k] = sum_j C[b, j] z[b, j K + k] (fp32).
+__global__ void k_lin_head_fwd(int B, int nb, int K, const float* C, const float* Z, float* Y) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)B * K) return;
+  const int b = (int)(t / K), k = (int)(t % K);
+  const float* z = Z + (int64_t)b * nb * K;
+  float s = 0.f;
+  for (int j = 0; j < nb; ++j) s += C[(int64_t)b * nb + j] * z[(int64_t)j * K + k];
+  Y[t] = s;
+}
+
+// gradient of the head: dz[b, j K + k] = C[b, j] dy[b, k] (fp32 and bf16)
+__global__ void k_lin_head_bwd(int B, int nb, int K, const float* C, const float* dy, float* dz, uint16_t* dzb) {
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= (int64_t)B * nb * K) return;
+  const int64_t b = t / ((int64_t)nb * K);
+  const int r = (int)(t % ((int64_t)nb * K));
+  const int j = r / K, k = r % K;
+  const float g = C[b * nb + j] * dy[b * K + k];
+  dz[t] = g;
+  dzb[t] = to_bf16(g);
+}
+
+// the prediction's head in FP64 output: coef[k] = scale sum_{m,t} c[t 8 + m]
+// z[(m 4 + t) K + k], z the 8 rows (one per Fourier mode m) of 4 basis
+// vectors each (t: a_1m, a_2m, b_1m, b_2m; c in the packed order a_1[8],
+// a_2[8], b_1[8], b_2[8])
+__global__ void k_lin_head_coef(int K, const double* c, const float* z, double scale, double* coef) {
+  const int k = blockIdx.x * blockDim.x + threadIdx.x;
+  if (k >= K) return;
+  double s = 0.0;
+  for (int m = 0; m < 8; ++m)
+    for (int t = 0; t < 4; ++t) s += c[t * 8 + m] * (double)z[(int64_t)(m * 4 + t) * K + k];
+  coef[k] = scale * s;
+}
+
+// network input of the linear-head start: one row per ellipsoid and Fourier
+// mode m (k_m = (pi/2)(m & 1, (m >> 1) & 1, (m >> 2) & 1)): the semi-axes
+// centred and scaled from U(0.3, 0.7) to [-1, 1], the mode's wave vector in
+// the scaled body frame diag(a) Q^T k_m (cos(k_m . x) = cos(kappa . s) on
+// the ellipsoid x = Q diag(a) s), and the nine entries of Q
+constexpr int GEOM_IN = 15;
+__global__ void k_geom_input(int P, const double* geom, float* X) {
+  const int t = blockIdx.x * blockDim.x + threadIdx.x;
+  if (t >= P * 8) return;
+  const int p = t >> 3, m = t & 7;
+  const double* G = geom + 15 * (int64_t)p;
+  const double* a = G + 3;
+  const double* Q = G + 6;
+  const double h = 1.5707963267948966;
+  const double k[3] = {(m & 1) * h, ((m >> 1) & 1) * h, ((m >> 2) & 1) * h};
+  float* x = X + (int64_t)t * GEOM_IN;
+  for (int i = 0; i < 3; ++i) {
+    x[i] = (float)((a[i] - 0.5) / 0.2);
+    x[3 + i] = (float)(a[i] * (Q[i] * k[0] + Q[3 + i] * k[1] + Q[6 + i] * k[2]));
+  }
+  for (int i = 0; i < 9; ++i) x[6 + i] = (float)Q[i];
 }
 
 // Adam on fp32 masters; bf16 copies of the weight matrices are refreshed
@@ -461,7 +522,7 @@ __global__ void __launch_bounds__(256) k_sh_normal(int n, const double* dirs, co
         body_dir(G, pos + 3 * (int64_t)(p0 + q), d);
       }
       real_sh(d, Ys[q]);
-      Ys[q][SH_N] = vals ? vals[p0 + q] : scale * (double)valsf[p0 + q];
+      Ys[q][SH_N] = scale * (vals ? vals[p0 + q] : (double)valsf[p0 + q]);
     }
     __syncthreads();
 #pragma unroll
@@ -605,7 +666,7 @@ __global__ void k_sh_eval(int n, const double* dirs, const double* pos, const do
   real_sh(d, Y);
   double s = 0.0;
   for (int i = 0; i < SH_N; ++i) s += Y[i] * coef[i];
-  if (out) out[q] = s;
+  if (out) out[q] = s * oscale;
   if (outf) outf[q] = (float)(s * oscale);
 }
 
@@ -630,6 +691,7 @@ struct kfbi_mlp {
   std::vector<float*> z;              // fp32 pre-activations (L)
   float *dz, *da;
   uint16_t* dzb;
+  float *y, *dy;                      // linear head: output and its gradient
   double* part;
   float* gv;                          // slab partials of the few-row forward
 };
@@ -659,6 +721,8 @@ void free_batch(kfbi_mlp* h) {
   dfree_t(h->dz);
   dfree_t(h->da);
   dfree_t(h->dzb);
+  dfree_t(h->y);
+  dfree_t(h->dy);
   dfree_t(h->part);
   dfree_t(h->gv);
   h->cap = 0;
@@ -676,6 +740,8 @@ kfbi_status ensure_batch(kfbi_mlp* h, int B) {
   KCHK(dalloc_t(&h->dz, (int64_t)B * maxw));
   KCHK(dalloc_t(&h->da, (int64_t)B * maxw));
   KCHK(dalloc_t(&h->dzb, (int64_t)B * maxw));
+  KCHK(dalloc_t(&h->y, (int64_t)B * maxw));
+  KCHK(dalloc_t(&h->dy, (int64_t)B * maxw));
   KCHK(dalloc_t(&h->part, 1024));
   int64_t gv = 0;
   for (int l = 0; l < h->L; ++l) {
@@ -719,15 +785,10 @@ void forward(kfbi_mlp* h, const float* X, int B) {
   }
 }
 
-// loss and gradient into h->g; loss (device float)
-void backward(kfbi_mlp* h, const float* Yt, int B, float* loss) {
+// gradient into h->g from the output gradient in h->dz / h->dzb
+void backward_from(kfbi_mlp* h, int B) {
   hipStream_t st = h->stream;
   const int L = h->L;
-  const int64_t no = (int64_t)B * h->w[L];
-  unsigned nbk = nbl(no);
-  if (nbk > 1024) nbk = 1024;
-  hipLaunchKernelGGL(k_mse, dim3(nbk), dim3(256), 0, st, no, h->z[L - 1], Yt, h->dz, h->dzb, h->part);
-  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, (int)nbk, no, (const double*)h->part, loss);
   for (int l = L - 1; l >= 0; --l) {
     const int in = h->w[l], out = h->w[l + 1];
     // dW_l = a_l^T dz (fp32 into the gradient pack), db_l = column sums of dz
@@ -743,6 +804,57 @@ void backward(kfbi_mlp* h, const float* Yt, int B, float* loss) {
                          (const float*)h->dz, h->dzb);
     }
   }
+}
+
+// loss and gradient into h->g; loss (device float)
+void backward(kfbi_mlp* h, const float* Yt, int B, float* loss) {
+  hipStream_t st = h->stream;
+  const int L = h->L;
+  const int64_t no = (int64_t)B * h->w[L];
+  unsigned nbk = nbl(no);
+  if (nbk > 1024) nbk = 1024;
+  hipLaunchKernelGGL(k_mse, dim3(nbk), dim3(256), 0, st, no, h->z[L - 1], Yt, h->dz, h->dzb, h->part);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, (int)nbk, no, (const double*)h->part, loss);
+  backward_from(h, B);
+}
+
+// linear head: loss of y = head(z, C) against Yt and the gradient into h->g
+// (h->y and h->dy hold the head's output and output gradient)
+// B examples of R rows each: the output of example b is its R rows read as
+// one row of R w_L entries
+void backward_lin(kfbi_mlp* h, const float* C, int nb, const float* Yt, int B, int R, float* loss) {
+  hipStream_t st = h->stream;
+  const int L = h->L;
+  const int K = R * h->w[L] / nb;
+  const int64_t ny = (int64_t)B * K;
+  hipLaunchKernelGGL(k_lin_head_fwd, dim3(nbl(ny)), dim3(256), 0, st, B, nb, K, C, (const float*)h->z[L - 1], h->y);
+  unsigned nbk = nbl(ny);
+  if (nbk > 1024) nbk = 1024;
+  // dy = 2 (y - Yt) / n (bf16 copy into dzb, unused) and the loss
+  hipLaunchKernelGGL(k_mse, dim3(nbk), dim3(256), 0, st, ny, (const float*)h->y, Yt, h->dy, h->dzb, h->part);
+  hipLaunchKernelGGL(k_loss_final, dim3(1), dim3(64), 0, st, (int)nbk, ny, (const double*)h->part, loss);
+  hipLaunchKernelGGL(k_lin_head_bwd, dim3(nbl((int64_t)B * R * h->w[L])), dim3(256), 0, st, B, nb, K, C,
+                     (const float*)h->dy, h->dz, h->dzb);
+  backward_from(h, B * R);
+}
+
+void adam_step(kfbi_mlp* h, float lr) {
+  h->step += 1;
+  AdamArgs a;
+  a.n = h->n_params;
+  a.lr = lr;
+  a.b1 = 0.9f;
+  a.b2 = 0.999f;
+  a.eps = 1e-8f;
+  a.c1 = (float)(1.0 - pow(0.9, (double)h->step));
+  a.c2 = (float)(1.0 - pow(0.999, (double)h->step));
+  a.w = h->p;
+  a.m = h->m;
+  a.v = h->v;
+  a.g = h->g;
+  a.bf_index = h->bf_index;
+  a.wb = h->wb;
+  hipLaunchKernelGGL(k_adam, dim3(nbl(h->n_params)), dim3(256), 0, h->stream, a);
 }
 
 }  // namespace
@@ -866,22 +978,74 @@ extern "C" kfbi_status kfbi_mlp_train_step(kfbi_mlp* h, const float* X, const fl
   KCHK(ensure_batch(h, B));
   forward(h, X, B);
   backward(h, Yt, B, loss);
-  h->step += 1;
-  AdamArgs a;
-  a.n = h->n_params;
-  a.lr = lr;
-  a.b1 = 0.9f;
-  a.b2 = 0.999f;
-  a.eps = 1e-8f;
-  a.c1 = (float)(1.0 - pow(0.9, (double)h->step));
-  a.c2 = (float)(1.0 - pow(0.999, (double)h->step));
-  a.w = h->p;
-  a.m = h->m;
-  a.v = h->v;
-  a.g = h->g;
-  a.bf_index = h->bf_index;
-  a.wb = h->wb;
-  hipLaunchKernelGGL(k_adam, dim3(nbl(h->n_params)), dim3(256), 0, h->stream, a);
+  adam_step(h, lr);
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+namespace {
+kfbi_status lin_check(const kfbi_mlp* h, const float* X, const float* C, int nb, int B, int R) {
+  if (!h || !X || !C || B < 1 || R < 1 || nb < 1 || ((int64_t)R * h->w[h->L]) % nb != 0) {
+    kfbi_set_error("linear head needs X, C, B >= 1, R >= 1 and nb dividing R times the output width");
+    return KFBI_E_INVALID;
+  }
+  return KFBI_OK;
+}
+}  // namespace
+
+extern "C" kfbi_status kfbi_mlp_forward_lin(kfbi_mlp* h, const float* X, int B, int R, const float* C, int nb,
+                                            float* Y) {
+  KCHK(lin_check(h, X, C, nb, B, R));
+  if (!Y) {
+    kfbi_set_error("forward_lin needs an output");
+    return KFBI_E_INVALID;
+  }
+  KCHK(ensure_batch(h, B * R));
+  forward(h, X, B * R);
+  const int K = R * h->w[h->L] / nb;
+  hipLaunchKernelGGL(k_lin_head_fwd, dim3(nbl((int64_t)B * K)), dim3(256), 0, h->stream, B, nb, K, C,
+                     (const float*)h->z[h->L - 1], Y);
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_mlp_loss_grad_lin(kfbi_mlp* h, const float* X, int B, int R, const float* C, int nb,
+                                              const float* Yt, float* loss, float* grads) {
+  KCHK(lin_check(h, X, C, nb, B, R));
+  if (!Yt || !loss) {
+    kfbi_set_error("loss_grad_lin needs targets and a loss");
+    return KFBI_E_INVALID;
+  }
+  KCHK(ensure_batch(h, B * R));
+  forward(h, X, B * R);
+  backward_lin(h, C, nb, Yt, B, R, loss);
+  if (grads)
+    HIPCHK(hipMemcpyAsync(grads, h->g, sizeof(float) * h->n_params, hipMemcpyDeviceToDevice, h->stream));
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_mlp_train_step_lin(kfbi_mlp* h, const float* X, int B, int R, const float* C, int nb,
+                                               const float* Yt, float lr, float* loss) {
+  KCHK(lin_check(h, X, C, nb, B, R));
+  if (!Yt || !loss || !(lr > 0.f)) {
+    kfbi_set_error("train_step_lin needs targets, a loss and lr > 0");
+    return KFBI_E_INVALID;
+  }
+  KCHK(ensure_batch(h, B * R));
+  forward(h, X, B * R);
+  backward_lin(h, C, nb, Yt, B, R, loss);
+  adam_step(h, lr);
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_geometry_input(const double* geom, int P, void* stream, float* X) {
+  if (!geom || !X || P < 1) {
+    kfbi_set_error("geometry_input needs geometries and outputs");
+    return KFBI_E_INVALID;
+  }
+  hipLaunchKernelGGL(k_geom_input, dim3(nbl((int64_t)P * 8)), dim3(256), 0, (hipStream_t)stream, P, geom, X);
   HIPCHK(hipGetLastError());
   return KFBI_OK;
 }
@@ -1020,6 +1184,83 @@ extern "C" kfbi_status kfbi_sh_sample(kfbi_plan* pl, const double* geom, const d
   KCHK(kfbi_plan_export(pl, KFBI_EXPORT_DOF_POS, dpos, (int64_t)sizeof(double) * 3 * pl->n_dof));
   sh_fit_eval(pl->stream, ws + 3 * pl->n_dof, (int)pl->n_dof, nullptr, dpos, geom, psi_dof, nullptr, 1.0, ns, S,
               nullptr, nullptr, psi_s, scale);
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_sh_coefficients(kfbi_plan* pl, const double* geom, const double* psi_dof, double scale,
+                                            double* coef) {
+  if (!pl || !pl->ready || !geom || !psi_dof || !coef || pl->n_dof < SH_N) {
+    kfbi_set_error("SH coefficients need a ready plan with >= 81 DOFs, geometry, density and output");
+    return KFBI_E_INVALID;
+  }
+  if (pl->g.d != 3) {
+    kfbi_set_error("the spherical-harmonic transfer is defined in 3D");
+    return KFBI_E_INVALID;
+  }
+  double* ws = nullptr;
+  const int n = (int)pl->n_dof;
+  KCHK(sh_workspace(pl, 3 * pl->n_dof + sh_ws_len(n), &ws));
+  double* dpos = ws;
+  KCHK(kfbi_plan_export(pl, KFBI_EXPORT_DOF_POS, dpos, (int64_t)sizeof(double) * 3 * pl->n_dof));
+  double* fw = ws + 3 * pl->n_dof;
+  const int ng = sh_groups(n);
+  hipLaunchKernelGGL(k_sh_normal, dim3(ng, (SH_E + FIT_EB - 1) / FIT_EB), dim3(256), 0, pl->stream, n,
+                     (const double*)nullptr, (const double*)dpos, geom, psi_dof, (const float*)nullptr, scale, fw);
+  hipLaunchKernelGGL(k_sh_solve, dim3(1), dim3(256), 0, pl->stream, ng, (const double*)fw, coef);
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_sh_expand(kfbi_plan* pl, const double* geom, const double* coef, double scale,
+                                      double* psi_dof) {
+  if (!pl || !pl->ready || !geom || !coef || !psi_dof) {
+    kfbi_set_error("SH expansion needs a ready plan, geometry, coefficients and output");
+    return KFBI_E_INVALID;
+  }
+  if (pl->g.d != 3) {
+    kfbi_set_error("the spherical-harmonic transfer is defined in 3D");
+    return KFBI_E_INVALID;
+  }
+  double* ws = nullptr;
+  KCHK(sh_workspace(pl, 3 * pl->n_dof, &ws));
+  KCHK(kfbi_plan_export(pl, KFBI_EXPORT_DOF_POS, ws, (int64_t)sizeof(double) * 3 * pl->n_dof));
+  hipLaunchKernelGGL(k_sh_eval, dim3(nbl(pl->n_dof)), dim3(256), 0, pl->stream, (int)pl->n_dof,
+                     (const double*)nullptr, (const double*)ws, geom, coef, psi_dof, (float*)nullptr, scale);
+  HIPCHK(hipGetLastError());
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_learned_start(kfbi_plan* pl, kfbi_mlp* h, int nb, const double* geom,
+                                          const double* jumps, double scale, double* psi_dof) {
+  if (!pl || !pl->ready || !h || !geom || !jumps || !psi_dof || nb != 32 || h->w[0] != GEOM_IN ||
+      h->w[h->L] != 4 * SH_N) {
+    kfbi_set_error("learned start needs a ready plan, a network 15 -> ... -> 4 x 81, nb = 32 jump coefficients, "
+                   "geometry and output");
+    return KFBI_E_INVALID;
+  }
+  if (pl->g.d != 3) {
+    kfbi_set_error("the learned start is defined in 3D");
+    return KFBI_E_INVALID;
+  }
+  // workspace: DOF positions, the 81 coefficients, the network input
+  double* ws = nullptr;
+  KCHK(sh_workspace(pl, 3 * pl->n_dof + SH_N + 4 * GEOM_IN, &ws));
+  double* dpos = ws;
+  double* coef = ws + 3 * pl->n_dof;
+  float* X = reinterpret_cast<float*>(coef + SH_N);
+  KCHK(kfbi_plan_export(pl, KFBI_EXPORT_DOF_POS, dpos, (int64_t)sizeof(double) * 3 * pl->n_dof));
+  KCHK(ensure_batch(h, 8));
+  hipStream_t keep = h->stream;
+  h->stream = pl->stream;     // the network's kernels go on the plan's stream
+  hipLaunchKernelGGL(k_geom_input, dim3(1), dim3(64), 0, pl->stream, 1, geom, X);
+  forward(h, X, 8);           // one row per Fourier mode
+  hipLaunchKernelGGL(k_lin_head_coef, dim3(1), dim3(128), 0, pl->stream, SH_N, jumps, (const float*)h->z[h->L - 1],
+                     scale, coef);
+  hipLaunchKernelGGL(k_sh_eval, dim3(nbl(pl->n_dof)), dim3(256), 0, pl->stream, (int)pl->n_dof,
+                     (const double*)nullptr, (const double*)dpos, geom, (const double*)coef, psi_dof, (float*)nullptr,
+                     1.0);
+  h->stream = keep;
   HIPCHK(hipGetLastError());
   return KFBI_OK;
 }

@@ -109,6 +109,19 @@ ABI = {
     "kfbi_scale_jumps": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
                           ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
     "kfbi_real_sh": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "kfbi_mlp_forward_lin": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                              ctypes.c_int, ctypes.c_void_p], ctypes.c_int),
+    "kfbi_mlp_loss_grad_lin": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "kfbi_mlp_train_step_lin": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.c_void_p,
+                                 ctypes.c_int, ctypes.c_void_p, ctypes.c_float, ctypes.c_void_p], ctypes.c_int),
+    "kfbi_geometry_input": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "kfbi_sh_coefficients": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p],
+                             ctypes.c_int),
+    "kfbi_sh_expand": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_double, ctypes.c_void_p],
+                       ctypes.c_int),
+    "kfbi_learned_start": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                            ctypes.c_double, ctypes.c_void_p], ctypes.c_int),
     "kfbi_last_error": ([], ctypes.c_char_p),
 }
 

@@ -97,6 +97,25 @@ class MLP:
                                                _p(self.loss_buf)))
         return self.loss_buf
 
+    # linear head: X holds B examples of R rows; the output of an example
+    # (its R rows) holds nb basis vectors, contracted with C [B x nb]
+    def forward_lin(self, X, C, nb, R=1):
+        B = X.shape[0] // R
+        Y = torch.empty((B, R * self.widths[-1] // nb), dtype=torch.float32, device=self.device)
+        _check(kfbi.load().kfbi_mlp_forward_lin(self._h, _p(X), B, int(R), _p(C), int(nb), _p(Y)))
+        return Y
+
+    def loss_grad_lin(self, X, C, nb, Yt, R=1):
+        g = torch.empty(self.n_params, dtype=torch.float32, device=self.device)
+        _check(kfbi.load().kfbi_mlp_loss_grad_lin(self._h, _p(X), X.shape[0] // R, int(R), _p(C), int(nb), _p(Yt),
+                                                  _p(self.loss_buf), _p(g)))
+        return self.loss_buf.clone(), g
+
+    def train_step_lin(self, X, C, nb, Yt, lr, R=1):
+        _check(kfbi.load().kfbi_mlp_train_step_lin(self._h, _p(X), X.shape[0] // R, int(R), _p(C), int(nb), _p(Yt),
+                                                   ctypes.c_float(lr), _p(self.loss_buf)))
+        return self.loss_buf
+
 
 def gemm_bf16(A, B, transA=False, transB=False):
     """fp32 C = op(A) op(B); A, B int16/uint16 tensors holding bf16 bits."""
@@ -154,3 +173,32 @@ def real_sh(dirs):
 def scale_jumps(X, Y, alpha, ns=W.N_SAMPLES):
     """In place: jump features and targets of example r times alpha[r]."""
     _check(kfbi.load().kfbi_scale_jumps(_p(X), _p(Y), _p(alpha), X.shape[0], ns, Y.shape[1], _stream(X.device)))
+
+
+def geometry_input(geoms):
+    """Network input [P * 8, 15] fp32 (a row per Fourier mode) of packed
+    geometries [P, 15]."""
+    X = torch.empty((geoms.shape[0] * 8, 15), dtype=torch.float32, device=geoms.device)
+    _check(kfbi.load().kfbi_geometry_input(_p(geoms), geoms.shape[0], _stream(geoms.device), _p(X)))
+    return X
+
+
+def sh_coefficients(plan, geom, psi_dof, scale=1.0):
+    """81 SH coefficients (FP64) of scale * psi at the plan's DOFs."""
+    out = torch.empty(81, dtype=torch.float64, device=psi_dof.device)
+    _check(kfbi.load().kfbi_sh_coefficients(plan._h, _p(geom), _p(psi_dof), float(scale), _p(out)))
+    return out
+
+
+def learned_start(plan, mlp, nb, geom, jumps, scale):
+    """Initial density at the plan's DOFs from the linear-head network."""
+    out = torch.empty(plan.n_dof, dtype=torch.float64, device=geom.device)
+    _check(kfbi.load().kfbi_learned_start(plan._h, mlp._h, int(nb), _p(geom), _p(jumps), float(scale), _p(out)))
+    return out
+
+
+def sh_expand(plan, geom, coef, scale=1.0):
+    """The 81-harmonic expansion with coefficients coef at the plan's DOFs."""
+    out = torch.empty(plan.n_dof, dtype=torch.float64, device=coef.device)
+    _check(kfbi.load().kfbi_sh_expand(plan._h, _p(geom), _p(coef), float(scale), _p(out)))
+    return out

@@ -108,7 +108,7 @@ def _near_midpoint(x, e):
     return np.abs(np.abs(x - lo) - half) <= e
 
 
-def _error_bounds(Ws, bs, X, Y):
+def _error_bounds(Ws, bs, X, Y, C=None):
     """Worst-case elementwise bounds of the GPU's forward output and
     gradients against the bf16-emulating oracle.  Both sides round the same
     fp32 inputs and masters to bf16; they differ in the accumulation (fp32
@@ -132,9 +132,26 @@ def _error_bounds(Ws, bs, X, Y):
             ea, fa = e, _near_midpoint(a[l + 1], e)
             EA.append(ea)
             FA.append(fa)
-    n = a[-1].size
-    dz = 2.0 * (a[-1] - np.asarray(Y, dtype=np.float64)) / n
-    edz = 2.0 * EZ[-1] / n
+    out, eout = a[-1], EZ[-1]
+    if C is not None:
+        # linear head in fp32: y[k] = sum_j C_j z[j K + k]
+        C = np.asarray(C, dtype=np.float64)
+        nb = C.shape[1]
+        K = out.shape[1] // nb
+        z3 = out.reshape(-1, nb, K)
+        e3 = eout.reshape(-1, nb, K)
+        y = np.einsum("bj,bjk->bk", C, z3)
+        ey = nb * U32 * np.einsum("bj,bjk->bk", np.abs(C), np.abs(z3)) + np.einsum("bj,bjk->bk", np.abs(C), e3)
+        n = y.size
+        dy = 2.0 * (y - np.asarray(Y, dtype=np.float64)) / n
+        edy = 2.0 * ey / n + U32 * np.abs(dy)
+        dz = (C[:, :, None] * dy[:, None, :]).reshape(out.shape)
+        edz = (np.abs(C)[:, :, None] * (edy[:, None, :] + U32 * np.abs(dy)[:, None, :])).reshape(out.shape)
+        out, eout = y, ey
+    else:
+        n = out.size
+        dz = 2.0 * (out - np.asarray(Y, dtype=np.float64)) / n
+        edz = 2.0 * eout / n
     gW_b, gb_b = [None] * L, [None] * L
     for l in range(L - 1, -1, -1):
         fdz = _near_midpoint(dz, edz)
@@ -150,7 +167,7 @@ def _error_bounds(Ws, bs, X, Y):
             on = zs[l - 1] > 0.0
             dz = da * on
             edz = np.where(amb, np.abs(da) + eda, np.where(on, eda, 0.0))
-    return a[-1], EZ[-1], gW_b, gb_b
+    return out, eout, gW_b, gb_b
 
 
 @pytest.mark.parametrize("widths,B", [((40, 24, 24, 16), 20), ((9216, 256, 256, 256, 1024), 64),
@@ -262,14 +279,15 @@ def test_training_reduces_the_loss():
 
 
 def test_pretrained_warm_start_gains_on_heldout_seeds():
-    """The network trained on 20,000 solver densities (N = 128 ellipsoids)
-    predicts held-out densities to ~20% and saves GMRES iterations against
-    the zero start and the control g2 / (beta_in + beta_out); the solve
-    still reaches the tolerance."""
+    """The stored network (trained on solver densities of N = 128
+    ellipsoids) predicts held-out densities to well under the zero start's
+    100% error, saves GMRES iterations, and the whole solve including the
+    prediction takes less time than the solve from the zero start; every
+    solve still reaches the tolerance."""
+    import time
     from paper_2309_05965_amd import kfbi, learned, warmstart
     model = warmstart.load_pretrained()
-    S = learned.samples()
-    zero, ctrl_it, learn, err_l, err_c = [], [], [], [], []
+    zero, learn, err_l, tz, tl = [], [], [], [], []
     plan = None
     for seed in range(1_000_100, 1_000_116):
         prob, geom, jmp = W.config5(seed, 128)
@@ -283,20 +301,107 @@ def test_pretrained_warm_start_gains_on_heldout_seeds():
             continue
         d = kfbi.device_jump_data(plan, jmp)
         ref, _, _ = plan.solve(d, tol=1e-11)
-        _, _, iz = plan.solve(d, tol=1e-8)
-        dsurf = plan.export("dof_surf").long()
-        ctrl = (d["g2"][dsurf] / (prob["beta_in"] + prob["beta_out"])).contiguous()
-        _, _, ic = plan.solve(d, tol=1e-8, psi0=ctrl)
-        p0 = warmstart.predict(model, plan, geom, jmp, S)
-        _, _, il = plan.solve(d, tol=1e-8, psi0=p0)
+        best_z, best_l = np.inf, np.inf
+        for _ in range(3):                          # best of three of each (graph warm-up included)
+            torch.cuda.synchronize()
+            t = time.perf_counter()
+            _, _, iz = plan.solve(d, tol=1e-8)
+            torch.cuda.synchronize()
+            best_z = min(best_z, time.perf_counter() - t)
+            t = time.perf_counter()
+            p0 = warmstart.predict(model, plan, geom, jmp)
+            _, _, il = plan.solve(d, tol=1e-8, psi0=p0)
+            torch.cuda.synchronize()
+            best_l = min(best_l, time.perf_counter() - t)
         assert il["status"] == 0 and il["true_rel_res"] < 2e-8
         zero.append(iz["iters"])
-        ctrl_it.append(ic["iters"])
         learn.append(il["iters"])
+        tz.append(best_z)
+        tl.append(best_l)
         err_l.append(float(((p0 - ref).norm() / ref.norm()).item()))
-        err_c.append(float(((ctrl - ref).norm() / ref.norm()).item()))
-    print("iters zero %.2f control %.2f learned %.2f; density error control %.2f learned %.2f"
-          % (np.mean(zero), np.mean(ctrl_it), np.mean(learn), np.mean(err_c), np.mean(err_l)))
+    print("iters zero %.2f learned %.2f; density error %.3f; solve ms zero %.2f learned %.2f"
+          % (np.mean(zero), np.mean(learn), np.mean(err_l), 1e3 * np.mean(tz), 1e3 * np.mean(tl)))
     assert len(zero) >= 12
-    assert np.mean(err_l) < 0.35 < np.mean(err_c)
-    assert np.mean(learn) < np.mean(zero)
+    assert np.mean(err_l) < 0.25
+    assert np.mean(learn) < np.mean(zero) - 1.0
+    assert np.sum(tl) < np.sum(tz)
+
+
+def test_linear_head_matches_oracle():
+    """The linear head (density linear in the jump coefficients): forward
+    output and every gradient entry of a small network within the
+    worst-case bounds of _error_bounds with the head."""
+    widths, B, nb = (15, 24, 24, 3 * 4), 20, 3
+    m, Ws, bs = _small_mlp(widths, 11)
+    rng = np.random.default_rng(12)
+    X = rng.standard_normal((B, widths[0])).astype(np.float32)
+    C = rng.standard_normal((B, nb)).astype(np.float32)
+    Y = rng.standard_normal((B, widths[-1] // nb)).astype(np.float32)
+    Xt, Ct, Yt = (torch.from_numpy(v).cuda() for v in (X, C, Y))
+    out = m.forward_lin(Xt, Ct, nb).cpu().numpy()
+    ref, ob, gWb, gbb = _error_bounds(Ws, bs, X, Y, C)
+    assert np.all(np.abs(out - ref) <= ob)
+    loss, g = m.loss_grad_lin(Xt, Ct, nb, Yt)
+    lref, gW, gb = OL.mlp_lin_loss_grad(Ws, bs, X, C, Y, emulate=True)
+    assert float(loss.item()) == pytest.approx(lref, rel=1e-4)
+    g = g.cpu().numpy()
+    for l, (ow, (i, o), ob_, nbias) in enumerate(m.layout()):
+        assert np.all(np.abs(g[ow:ow + i * o].reshape(i, o) - gW[l]) <= gWb[l]), l
+        assert np.all(np.abs(g[ob_:ob_ + nbias] - gb[l]) <= gbb[l]), l
+
+
+def test_sh_coefficients_and_expansion_match_oracle():
+    from paper_2309_05965_amd import kfbi, learned
+    prob, geom, jmp = W.config5(4, N=64)
+    gp = kfbi.Plan(prob)
+    dof_pos = gp.export("dof_pos").cpu().numpy()
+    rng = np.random.default_rng(6)
+    psi = rng.standard_normal(gp.n_dof)
+    g = torch.tensor(learned.pack_geometry(geom)).cuda()
+    coef = learned.sh_coefficients(gp, g, torch.from_numpy(psi).cuda(), 0.5).cpu().numpy()
+    ref = 0.5 * OL.sh_coefficients(geom, dof_pos, psi)
+    assert np.max(np.abs(coef - ref)) <= 1e-9 * np.max(np.abs(ref))
+    c2 = rng.standard_normal(81)
+    vals = learned.sh_expand(gp, g, torch.from_numpy(c2).cuda(), 2.0).cpu().numpy()
+    assert np.max(np.abs(vals - 2.0 * OL.sh_values(geom, dof_pos, c2))) <= 1e-12 * np.max(np.abs(vals))
+
+
+def test_learned_start_pipeline_matches_oracle():
+    """kfbi_learned_start (geometry input, network, linear head with the
+    jump coefficients, harmonics at the DOFs) against the oracle's steps
+    with a random network of the stored model's shape."""
+    from paper_2309_05965_amd import kfbi, learned, warmstart
+    widths = warmstart.WIDTHS
+    m, Ws, bs = _small_mlp(widths, 13)
+    prob, geom, jmp = W.config5(5, N=64)
+    gp = kfbi.Plan(prob)
+    g = torch.tensor(learned.pack_geometry(geom)).cuda()
+    j = torch.tensor(learned.pack_jumps(jmp)).cuda()
+    psi = learned.learned_start(gp, m, warmstart.NB, g, j, 0.7).cpu().numpy()
+    x = OL.mode_rows(geom).astype(np.float32)
+    Xg = learned.geometry_input(g[None, :]).cpu().numpy()
+    assert np.max(np.abs(Xg - x)) <= 1e-6 * np.max(np.abs(x))
+    z = OL.mlp_forward(Ws, bs, x, emulate=True)[0][-1].reshape(1, -1)
+    coef = 0.7 * OL.lin_head(z, OL.mode_major(learned.pack_jumps(jmp))[None, :], warmstart.NB)[0]
+    ref = OL.sh_values(geom, gp.export("dof_pos").cpu().numpy(), coef)
+    # fp32 accumulation in the network (about 1e-6 of its sums) against fp64
+    assert np.max(np.abs(psi - ref)) <= 1e-3 * np.max(np.abs(ref))
+
+
+def test_linear_head_rows_per_example():
+    """R rows per example: the head reads an example's R rows as one row
+    (forward and loss against the oracle, FP32 accumulation)."""
+    widths, B, R, nb = (15, 24, 24, 8), 6, 4, 8
+    m, Ws, bs = _small_mlp(widths, 14)
+    rng = np.random.default_rng(15)
+    X = rng.standard_normal((B * R, widths[0])).astype(np.float32)
+    C = rng.standard_normal((B, nb)).astype(np.float32)
+    Y = rng.standard_normal((B, R * widths[-1] // nb)).astype(np.float32)
+    Xt, Ct, Yt = (torch.from_numpy(v).cuda() for v in (X, C, Y))
+    out = m.forward_lin(Xt, Ct, nb, R).cpu().numpy()
+    z = OL.mlp_forward(Ws, bs, X, emulate=True)[0][-1].reshape(B, -1)
+    ref = OL.lin_head(z, C, nb)
+    assert np.max(np.abs(out - ref)) <= 1e-4 * np.max(np.abs(ref))
+    loss, _ = m.loss_grad_lin(Xt, Ct, nb, Yt, R)
+    lref, _, _ = OL.mlp_lin_loss_grad(Ws, bs, X, C, Y, emulate=True, R=R)
+    assert float(loss.item()) == pytest.approx(lref, rel=1e-4)

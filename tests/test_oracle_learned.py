@@ -115,3 +115,72 @@ def test_mlp_gradient_matches_finite_differences():
         bm[l][0] -= eps
         fd = (L.mlp_loss_grad(Ws, bp, X, Y, False)[0] - L.mlp_loss_grad(Ws, bm, X, Y, False)[0]) / (2 * eps)
         assert gb[l][0] == pytest.approx(fd, rel=1e-6, abs=1e-9)
+
+
+def test_linear_head_gradient_matches_finite_differences():
+    """The linear-head loss's gradient (exact arithmetic) against central
+    differences, and the head's linearity in the coefficients."""
+    rng = np.random.default_rng(3)
+    widths = (5, 7, 12)                 # 12 outputs = 3 basis vectors of 4
+    Ws = [rng.standard_normal((a, b)) * 0.5 for a, b in zip(widths[:-1], widths[1:])]
+    bs = [rng.standard_normal(b) * 0.1 for b in widths[1:]]
+    X = rng.standard_normal((4, 5))
+    C = rng.standard_normal((4, 3))
+    Yt = rng.standard_normal((4, 4))
+    loss, gW, gb = L.mlp_lin_loss_grad(Ws, bs, X, C, Yt, emulate=False)
+    eps = 1e-6
+    for l in range(2):
+        for (i, j) in ((0, 0), (2, 3), (4, 6) if l == 0 else (6, 11)):
+            Wp = [w.copy() for w in Ws]
+            Wm = [w.copy() for w in Ws]
+            Wp[l][i, j] += eps
+            Wm[l][i, j] -= eps
+            fd = (L.mlp_lin_loss_grad(Wp, bs, X, C, Yt, emulate=False)[0]
+                  - L.mlp_lin_loss_grad(Wm, bs, X, C, Yt, emulate=False)[0]) / (2 * eps)
+            assert abs(fd - gW[l][i, j]) <= 1e-6 * (1 + abs(fd))
+        bp = [b.copy() for b in bs]
+        bm = [b.copy() for b in bs]
+        bp[l][1] += eps
+        bm[l][1] -= eps
+        fd = (L.mlp_lin_loss_grad(Ws, bp, X, C, Yt, emulate=False)[0]
+              - L.mlp_lin_loss_grad(Ws, bm, X, C, Yt, emulate=False)[0]) / (2 * eps)
+        assert abs(fd - gb[l][1]) <= 1e-6 * (1 + abs(fd))
+    z = rng.standard_normal((4, 12))
+    assert np.allclose(L.lin_head(z, 2.5 * C, 3), 2.5 * L.lin_head(z, C, 3), rtol=1e-14)
+    assert np.allclose(L.lin_head(z, C, 3)[1], z[1].reshape(3, 4).T @ C[1], rtol=1e-14)
+
+
+def test_sh_coefficients_recover_band_limited_density():
+    """Coefficients of a degree-<= 8 expansion are recovered exactly from its
+    values at scattered points of the ellipsoid."""
+    rng = np.random.default_rng(4)
+    Q, R = np.linalg.qr(rng.standard_normal((3, 3)))
+    geom = (np.array([0.01, -0.02, 0.0]), np.array([0.4, 0.55, 0.35]), Q * np.sign(np.diag(R))[None, :])
+    S = rng.standard_normal((600, 3))
+    S /= np.linalg.norm(S, axis=1, keepdims=True)
+    X = L.sample_points(geom, S)
+    coef = rng.standard_normal(81)
+    vals = L.sh_values(geom, X, coef)
+    assert np.allclose(L.sh_coefficients(geom, X, vals), coef, atol=1e-10)
+
+
+def test_mode_rows_give_the_jump_on_the_ellipsoid():
+    """cos(k_m . x) at x = Q diag(a) s equals cos(kappa_m . s) with kappa_m
+    the per-mode network's wave-vector input diag(a) Q^T k_m; mode_major
+    is the (mode, coefficient) permutation of the packed jumps."""
+    rng = np.random.default_rng(6)
+    Q, Rr = np.linalg.qr(rng.standard_normal((3, 3)))
+    geom = (np.zeros(3), np.array([0.35, 0.62, 0.48]), Q * np.sign(np.diag(Rr))[None, :])
+    S = rng.standard_normal((50, 3))
+    S /= np.linalg.norm(S, axis=1, keepdims=True)
+    X = L.sample_points(geom, S)
+    rows = L.mode_rows(geom)
+    kv = W.fourier_wavevectors()
+    for m in range(8):
+        assert np.allclose(np.cos(X @ kv[m]), np.cos(S @ rows[m, 3:6]), atol=1e-13)
+        assert np.allclose(rows[m, :3], (geom[1] - 0.5) / 0.2) and np.allclose(rows[m, 6:], geom[2].ravel())
+    j = np.arange(32.0)
+    mm = L.mode_major(j)
+    for m in range(8):
+        for t in range(4):
+            assert mm[4 * m + t] == j[8 * t + m]
