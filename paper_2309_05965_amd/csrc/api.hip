@@ -125,6 +125,9 @@ void free_plan(kfbi_plan* pl) {
   dfree(pl->mg_ctl);
   dfree(pl->mg_scal);
   dfree(pl->Fmg);
+  dfree(pl->ustore);
+  pl->ustore_slots = 0;
+  pl->ustore_n = 0;
   dfree(pl->cond);
   dfree(pl->psiS);
   dfree(pl->aS);
@@ -182,6 +185,7 @@ void free_plan(kfbi_plan* pl) {
     pl->prof_ev = nullptr;
   }
   destroy_graphs(pl);
+  mg_graphs_clear(pl);
   if (pl->gstream) (void)hipStreamDestroy(pl->gstream);
   if (pl->ev_in) (void)hipEventDestroy(pl->ev_in);
   if (pl->ev_out) (void)hipEventDestroy(pl->ev_out);
@@ -194,8 +198,6 @@ void free_plan(kfbi_plan* pl) {
   if (pl->h_dpinned) (void)hipHostFree(pl->h_dpinned);
   if (pl->mbox) (void)hipHostFree(pl->mbox);
   pl->mbox = nullptr;
-  if (pl->h_log) (void)hipHostFree(pl->h_log);
-  pl->h_log = nullptr;
   pl->h_pinned = nullptr;
   pl->h_dpinned = nullptr;
 }
@@ -267,10 +269,6 @@ kfbi_status alloc_fixed(kfbi_plan* pl) {
     return KFBI_E_OOM;
   }
   memset((void*)pl->mbox, 0, sizeof(KfbiMailbox));
-  if (hipHostMalloc((void**)&pl->h_log, (KFBI_GMRES_MAX + 2) * sizeof(int), 0) != hipSuccess) {
-    kfbi_set_error("pinned host allocation failed");
-    return KFBI_E_OOM;
-  }
   if (hipHostMalloc((void**)&pl->h_ctl, 16 * sizeof(int), 0) != hipSuccess) {
     kfbi_set_error("pinned host allocation failed");
     return KFBI_E_OOM;
@@ -354,26 +352,38 @@ void destroy_graphs(kfbi_plan* pl) {
     pl->graph_execs[v] = nullptr;
     pl->graphs[v] = nullptr;
   }
-  for (int c = 0; c <= KFBI_MG_CAPS; ++c) {
-    if (pl->mg_gexec[c]) (void)hipGraphExecDestroy(pl->mg_gexec[c]);
-    if (pl->mg_graph[c]) (void)hipGraphDestroy(pl->mg_graph[c]);
-    pl->mg_gexec[c] = nullptr;
-    pl->mg_graph[c] = nullptr;
-  }
 }
 
-// cap of the box solve of GMRES iteration j under relaxation: one more
-// correction than the plan's previous solve needed there; 0 means the
-// plan-wide cap (no record, relaxation off, or beyond the captured caps)
-int iteration_cap(const kfbi_plan* pl, int j) {
-  if (pl->box_solver == KFBI_BOX_FFT || !(pl->relax_word > 0.0) || j >= pl->log_n) return 0;
+// cap of a relaxed box solve launched when the host's latest GMRES
+// residual estimate is res (|b| = nb): its tolerance relax tol |b| / res,
+// clamped to [eps_in, 1e-2], reached at the two-grid cycle's contraction
+// (0.07 per correction, 0.085 taken).  The device applies the same rule
+// with the iteration's own estimate, which is no larger, so it needs no
+// more.  0 means the plan-wide cap (no estimate, or no smaller cap).
+int relaxed_cap(const kfbi_plan* pl, double tol, double nb, double res) {
+  if (pl->box_solver == KFBI_BOX_FFT || !(pl->relax_word > 0.0) || !(res > 0.0) || !(nb > 0.0)) return 0;
   const int full = pl->mg_run_cap > 0 ? pl->mg_run_cap : pl->mg_maxit;
-  int c = pl->log_prev[j] + 1;
-  if (c > full) c = full;
-  return c >= 1 && c <= KFBI_MG_CAPS && c < full ? c : 0;
+  double e = pl->relax_word * tol * nb / res;
+  if (e > 1e-2) e = 1e-2;
+  if (e < pl->mg_eps) e = pl->mg_eps;
+  const int c = (int)ceil(log(e) / log(0.085));
+  return c >= 1 && c < full ? c : 0;
 }
 
-// one captured iteration (matvec + Arnoldi step)
+// one GMRES iteration with a multigrid box solver, enqueued as it goes: the
+// few kernels of the matvec that depend on the interfaces, the captured box
+// solve (capped at mg_run_cap corrections), the store of its solution, the
+// Arnoldi step.  Every kernel reads j and the stop flag from the device
+// control word, so iterations enqueued past convergence do nothing.
+void enqueue_mg_iteration(kfbi_plan* pl) {
+  pl->ctl_active = pl->ctl;
+  op_matvec(pl, nullptr, nullptr);
+  mg_store_solution(pl, pl->vbuf);
+  gm_arnoldi(pl);
+  pl->ctl_active = nullptr;
+}
+
+// FFT box solver: captured iterations (matvec + Arnoldi step)
 kfbi_status capture_iterations(kfbi_plan* pl, int iters, hipGraph_t* gr_out, hipGraphExec_t* ex_out) {
   HIPCHK(hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal));
   pl->ctl_active = pl->ctl;
@@ -405,10 +415,11 @@ kfbi_status capture_iterations(kfbi_plan* pl, int iters, hipGraph_t* gr_out, hip
 // possible, but capturing and instantiating a graph costs about as much as
 // launching its kernels, so a graph set is only worth it when the key is
 // reused: the first solve with a key captures the graphs of 1 and 4
-// iterations, later solves all (FFT box solver).  Multigrid iterations run
-// hundreds of kernels, so the gaps do not count: one graph of 1 iteration.
+// iterations, later solves all.  Multigrid iterations are enqueued kernel by
+// kernel around captured box solves (enqueue_mg_iteration), which stay
+// valid from one geometry to the next.
 bool graph_wanted(const kfbi_plan* pl, int v) {
-  if (pl->box_solver != KFBI_BOX_FFT) return v == 0;
+  if (pl->box_solver != KFBI_BOX_FFT) return false;
   return pl->graph_uses > 0 || v == 0 || v == 2;
 }
 
@@ -422,7 +433,8 @@ kfbi_status ensure_graph(kfbi_plan* pl) {
                       (uint64_t)(uintptr_t)pl->FI, (uint64_t)(uintptr_t)pl->IW, (uint64_t)(uintptr_t)pl->stN,
                       (uint64_t)(uintptr_t)pl->ext_idx, (uint64_t)(uintptr_t)pl->irr,
                       (uint64_t)(uintptr_t)pl->ce_node, (uint64_t)pl->gm_cap, (uint64_t)(uintptr_t)pl->d2s,
-                      (uint64_t)(uintptr_t)pl->PA ^ (uint64_t)(uintptr_t)pl->GI ^ (uint64_t)(uintptr_t)pl->mg_u};
+                      (uint64_t)(uintptr_t)pl->PA ^ (uint64_t)(uintptr_t)pl->GI ^ (uint64_t)(uintptr_t)pl->mg_u ^
+                          (uint64_t)(uintptr_t)pl->ustore};
   if (!pl->graph_execs[0] || memcmp(key, pl->graph_key, sizeof(key)) != 0) {
     destroy_graphs(pl);
     pl->graph_uses = 0;
@@ -433,26 +445,14 @@ kfbi_status ensure_graph(kfbi_plan* pl) {
     want[v] = graph_wanted(pl, v) && !pl->graph_execs[v];
     missing = missing || want[v];
   }
-  bool wantc[KFBI_MG_CAPS + 1] = {};
-  for (int j = 0; j < pl->log_n; ++j) {
-    const int c = iteration_cap(pl, j);
-    if (c > 0 && !pl->mg_gexec[c]) missing = wantc[c] = true;
-  }
   ++pl->graph_uses;
   if (!missing) return KFBI_OK;
   std::unique_lock<std::shared_mutex> lock(kfbi_capture_mutex);
   for (int v = 0; v < KFBI_NGRAPH; ++v)
     if (want[v]) KCHK(capture_iterations(pl, 1 << v, &pl->graphs[v], &pl->graph_execs[v]));
-  const int run_cap = pl->mg_run_cap;
-  for (int c = 1; c <= KFBI_MG_CAPS; ++c) {
-    if (!wantc[c]) continue;
-    pl->mg_run_cap = c;
-    const kfbi_status cs = capture_iterations(pl, 1, &pl->mg_graph[c], &pl->mg_gexec[c]);
-    pl->mg_run_cap = run_cap;
-    KCHK(cs);
-  }
   return KFBI_OK;
 }
+
 
 }  // namespace
 
@@ -861,19 +861,45 @@ kfbi_status gmres_run(kfbi_plan* pl, double tol, int m, int first_batch, GmresOu
                       const GmresSpec& spec = GmresSpec()) {
   o->spec_ok = false;
   hipStream_t st = pl->stream;
+  // Multigrid iterations cost hundreds of microseconds each, and one
+  // launched after convergence still costs its launches: their batches stay
+  // short (a host round trip costs some tens of microseconds).
+  const bool mgs = pl->box_solver != KFBI_BOX_FFT;
+  const bool relaxed = mgs && pl->relax_word > 0.0;
   int launched = 0;
   int batch = first_batch;
-  double nb = 0.0, res_prev = 0.0;
+  double nb = 0.0, res_prev = 0.0, res_host = 0.0;
   int k_prev = 0;
   bool first = true;
-  for (;;) {
+  bool stop = false;
+  if (relaxed) {
+    // |r_0| and |b| before the first batch: the caps of the relaxed
+    // iterations follow from the residual estimate
+    PostReq q{};
+    q.ni = 4;
+    for (int i = 0; i < 4; ++i) q.isrc[i] = pl->ctl + i;
+    q.nd = 7;
+    for (int i = 0; i < 7; ++i) q.dsrc[i] = pl->scal + i;
+    unsigned seq = 0;
+    KCHK(kfbi_post_launch(pl, q, &seq));
+    int iv[6] = {0, 0, 0, 0, 0, 0};
+    KCHK(kfbi_post_collect(pl, q, seq, iv, pl->h_dpinned));
+    for (int i = 0; i < 4; ++i) pl->h_ctl[i] = iv[i];
+    nb = pl->h_dpinned[1];
+    res_prev = res_host = pl->h_dpinned[6];
+    first = false;
+    stop = pl->h_ctl[1] != 0;
+  }
+  while (!stop) {
     const int B = batch < m - launched ? batch : m - launched;
-    if (iteration_cap(pl, launched) > 0) {
-      // relaxed multigrid: each iteration with its own correction cap
-      for (int b = 0; b < B; ++b) {
-        const int c = iteration_cap(pl, launched + b);
-        HIPCHK(hipGraphLaunch(c > 0 && pl->mg_gexec[c] ? pl->mg_gexec[c] : pl->graph_execs[0], st));
-      }
+    if (mgs) {
+      // relaxed: each iteration with its own correction cap
+      const int c = relaxed ? relaxed_cap(pl, tol, nb, res_host) : 0;
+      const int run_cap = pl->mg_run_cap;
+      if (c > 0) pl->mg_run_cap = c;
+      for (int b = 0; b < B; ++b) enqueue_mg_iteration(pl);
+      pl->mg_run_cap = run_cap;
+      HIPCHK(hipGetLastError());
     } else {
       // the graph of exactly B iterations if there is one, else the
       // largest captured graphs first (graph 0 always exists)
@@ -922,11 +948,13 @@ kfbi_status gmres_run(kfbi_plan* pl, double tol, int m, int first_batch, GmresOu
     if (pl->h_ctl[1] || launched >= m) break;
     const int k = pl->h_ctl[2];
     const double res = pl->h_dpinned[0];
-    batch = 4;
+    res_host = res;
+    const int bmax = mgs ? 4 : 16;
+    batch = mgs ? 2 : 4;
     if (k > k_prev && res > 0.0 && res < res_prev && res_prev > 0.0) {
       double rate = pow(res / res_prev, 1.0 / (double)(k - k_prev));
       double need = log(tol * nb / res) / log(rate);
-      batch = need < 1.0 ? 1 : (need > 16.0 ? 16 : (int)ceil(need));
+      batch = need < 1.0 ? 1 : (need > (double)bmax ? bmax : (int)ceil(need));
     }
     res_prev = res;
     k_prev = k;
@@ -994,11 +1022,10 @@ kfbi_status solve_body(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* op
   // needed plus 1 (the count hardly varies with the right-hand side); a
   // box solve to eps_in stopped by it above its tolerance raises it by 2
   // for the next solves.  Relaxed GMRES iterations run with caps of their
-  // own (the previous solve's count of that iteration plus 1), and their
-  // record is kept across solves: an iteration that hit its cap records the
-  // cap, so the next solve's cap for it is one higher.
+  // own, from the residual estimate (relaxed_cap).
   const bool mg = pl->box_solver != KFBI_BOX_FFT;
   if (mg) {
+    KCHK(mg_store_reserve(pl));
     pl->mg_run_cap = pl->mg_cap_eff > 0 ? pl->mg_cap_eff : pl->mg_maxit;
     HIPCHK(hipMemsetAsync(pl->mg_ctl + 2, 0, 2 * sizeof(int), pl->stream));
   }
@@ -1011,9 +1038,6 @@ kfbi_status solve_body(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* op
         pl->mg_cap_eff = run + 2 < pl->mg_maxit ? run + 2 : pl->mg_maxit;
       else if (most > 0)
         pl->mg_cap_eff = most + 1 < pl->mg_maxit ? most + 1 : pl->mg_maxit;
-      // per-iteration record of the relaxed pass
-      for (int j = 0; j < pl->log_k; ++j) pl->log_prev[j] = pl->h_log[j];
-      pl->log_n = pl->log_k;
     }
     pl->mg_run_cap = 0;
   }
@@ -1037,39 +1061,78 @@ kfbi_status solve_report(kfbi_plan* pl, kfbi_info* info, const GmresOut& o, int 
   return s;
 }
 
+// |b - A psi| / |b| with the multigrid box solvers.  psi = x0 + sum y_j v_j,
+// so the box solution of A psi is U(x0) + sum y_j U(v_j) up to the box
+// solves' tolerances: its box solve starts from that combination of the
+// stored solutions and stops after at most 3 corrections; short of eps_in
+// there, it continues from where it stopped with the full cap.  `then` is
+// enqueued behind the residual's kernels, before the host waits (again
+// after a continuation).  The box solution of A psi is left in vbuf.
+template <class Then>
+kfbi_status mg_true_residual(kfbi_plan* pl, const double* psi, int k, int use_x0, double* tr, Then then) {
+  const bool guess = pl->ustore && k + 1 <= pl->ustore_slots;
+  if (guess) mg_guess_from_store(pl, k, use_x0, pl->scal + 8, pl->vbuf);
+  for (int pass = 0; pass < 2; ++pass) {
+    const int run_cap = pl->mg_run_cap;
+    if (pass == 0 && guess && (run_cap == 0 || run_cap > 3)) pl->mg_run_cap = 3;
+    pl->mg_guess = guess;
+    matvec_impl(pl, psi, pl->work2);
+    pl->mg_guess = false;
+    pl->mg_run_cap = run_cap;
+    gm_true_residual(pl, pl->bvec, pl->work2, pl->scal + 4);
+    PostReq q{};
+    q.nd = 3;
+    q.dsrc[0] = pl->scal + 4;
+    q.dsrc[1] = pl->scal + 5;
+    q.dsrc[2] = pl->mg_scal + 1;      // relative residual the box solve stopped at
+    q.ni = 2;
+    q.isrc[0] = pl->mg_ctl + 2;
+    q.isrc[1] = pl->mg_ctl + 3;
+    unsigned seq = 0;
+    KCHK(kfbi_post_launch(pl, q, &seq));
+    then();
+    KCHK(kfbi_post_collect(pl, q, seq, pl->h_pinned + 2, pl->h_dpinned + 4));
+    *tr = rel_residual(pl->h_dpinned[4], pl->h_dpinned[5]);
+    if (!guess || pl->h_dpinned[6] <= pl->mg_eps) break;
+  }
+  return KFBI_OK;
+}
+
 kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* opts, double* psi, double* u_out,
                         kfbi_info* info, int m, double tol) {
-  // Step 1: right-hand side
+  // Step 1: right-hand side (its grid solution stays in vsbuf)
   simple_solve_impl(pl, data->g1, nullptr, data->ftilde, data->fhat, data->gB, pl->vsbuf, pl->dn_in, pl->dn_out);
   op_bie_rhs(pl, data->g2, pl->dn_in, pl->dn_out, pl->bvec);
-  const bool relax = pl->mg_relax > 0.0 && pl->box_solver != KFBI_BOX_FFT;
+  const bool mg = pl->box_solver != KFBI_BOX_FFT;
+  const bool relax = pl->mg_relax > 0.0 && mg;
   KCHK(set_relax_word(pl, relax ? pl->mg_relax : 0.0));
-  // Step 2: initial residual and control word
-  if (opts->use_x0) matvec_impl(pl, psi, pl->work);
+  // Step 2: initial residual and control word (multigrid: the box solution
+  // of A x0 goes to the store's slot 0)
+  if (opts->use_x0) {
+    matvec_impl(pl, psi, pl->work);
+    if (mg) mg_store_solution(pl, pl->vbuf);
+  }
   gm_residual_start(pl, pl->bvec, pl->work, opts->use_x0, tol, m);
   KCHK(ensure_graph(pl));
-  // Steps 3-4; the first batch is the previous solve's iteration count on
-  // this plan (at least 4: an over-long batch costs a few microseconds, a
-  // short one a host round trip)
   // final solve u = w(g1, E psi, ftilde, fhat, gB)
   double* u = u_out ? u_out : pl->vsbuf;
   auto final_solve = [&] {
     op_extend(pl, psi, pl->aS);
     simple_solve_impl(pl, data->g1, pl->aS, data->ftilde, data->fhat, data->gB, u, pl->dn_in, pl->dn_out);
   };
-  // Without relaxation and from a zero start, on a graph key already solved
-  // with (a repeated problem, so the first batch, sized to the previous
-  // iteration count, usually converges), the update, the true residual and
-  // the final solve go out right behind the first batch: a solve that
-  // converges within it waits on the host once; otherwise they are redone
-  // after convergence.
+  // Steps 3-4.  FFT box solver: without relaxation and from a zero start,
+  // on a graph key already solved with (a repeated problem, so the first
+  // batch, sized to the previous iteration count, usually converges), the
+  // update, the true residual and the final solve go out right behind the
+  // first batch: a solve that converges within it waits on the host once;
+  // otherwise they are redone after convergence.
   struct SpecCtx {
     kfbi_plan* pl;
     double* psi;
     decltype(final_solve)* fin;
   } sc{pl, psi, &final_solve};
   GmresSpec spec;
-  spec.active = !relax && !opts->use_x0 && pl->graph_uses > 1;
+  spec.active = !mg && !opts->use_x0 && pl->graph_uses > 1;
   spec.ctx = &sc;
   spec.before = [](void* c) {
     SpecCtx* x = (SpecCtx*)c;
@@ -1079,11 +1142,15 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
   };
   spec.after = [](void* c) { (*((SpecCtx*)c)->fin)(); };
   GmresOut o;
-  const int fb = pl->last_iters > 4 ? (pl->last_iters < 64 ? pl->last_iters : 64) : 4;
+  // the first batch: the previous solve's iteration count on this plan (at
+  // least 4: an over-long batch costs a few microseconds, a short one a host
+  // round trip), at most 4 with the multigrid box solvers
+  int fb = pl->last_iters > 4 ? (pl->last_iters < 64 ? pl->last_iters : 64) : 4;
+  if (mg && fb > 4) fb = 4;
   // a key solved with more than once (a repeated problem): its first batch,
   // when no power of two, as one graph instead of several (each graph
   // launch idles the GPU for a few microseconds)
-  if (pl->box_solver == KFBI_BOX_FFT && pl->graph_uses > 1 && (fb & (fb - 1)) != 0 && pl->graph_xn != fb) {
+  if (!mg && pl->graph_uses > 1 && (fb & (fb - 1)) != 0 && pl->graph_xn != fb) {
     // like every capture, exclusive of other threads' set-up and allocations
     std::unique_lock<std::shared_mutex> lock(kfbi_capture_mutex);
     if (pl->graph_xe) HIPCHK(hipStreamSynchronize(pl->stream));   // no launch of the old one in flight
@@ -1101,36 +1168,36 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
     return solve_report(pl, info, o, o.k, tr, tol, m);
   }
   gm_update(pl, o.k, psi, opts->use_x0);
-  pl->log_k = 0;
-  if (relax && o.k > 0) {
-    // corrections per iteration of this pass, read after the true residual's wait
-    HIPCHK(hipMemcpyAsync(pl->h_log, pl->mg_ctl + 4, sizeof(int) * o.k, hipMemcpyDeviceToHost, pl->stream));
-    pl->log_k = o.k;
-  }
-  // without relaxation psi is final here: the final solve is enqueued
-  // before the host waits for the true residual
   double tr = 0.0;
-  if (relax)
-    KCHK(true_residual(pl, psi, &tr));
-  else
+  if (!mg) {
+    // psi is final here: the final solve is enqueued before the host waits
+    // for the true residual
     KCHK(true_residual(pl, psi, &tr, final_solve));
+    return solve_report(pl, info, o, o.k, tr, tol, m);
+  }
+  // Multigrid: the final solve's grid solution is, by linearity in the
+  // data and the density, the step-1 solution (vsbuf) plus the box
+  // solution of A psi (vbuf, left by the true residual); enqueued behind
+  // the residual on the guess that no continuation follows.
+  auto final_sum = [&] { mg_sum(pl, pl->vsbuf, pl->vbuf, u); };
   int k = o.k;
+  KCHK(mg_true_residual(pl, psi, o.k, opts->use_x0, &tr, [] {}));
   // with a relaxed inner tolerance the GMRES estimate can run ahead of the
   // true residual: if it misses tol, continue from psi with full-accuracy
-  // box solves until it meets it
+  // box solves until it meets it (A psi and its box solution are at hand)
   if (relax && o.conv && tr > tol && k < m) {
     KCHK(set_relax_word(pl, 0.0));
-    matvec_impl(pl, psi, pl->work);
-    gm_residual_start(pl, pl->bvec, pl->work, 1, tol, m - k);
+    mg_store_solution(pl, pl->vbuf);
+    gm_residual_start(pl, pl->bvec, pl->work2, 1, tol, m - k);
     GmresOut o2;
     KCHK(gmres_run(pl, tol, m - k, 4, &o2));
     gm_update(pl, o2.k, psi, 1);
-    KCHK(true_residual(pl, psi, &tr));
+    KCHK(mg_true_residual(pl, psi, o2.k, 1, &tr, [] {}));
     k += o2.k;
     o.est = o2.est;
     o.conv = o2.conv;
   }
-  if (relax) final_solve();
+  final_sum();
   return solve_report(pl, info, o, k, tr, tol, m);
 }
 }  // namespace

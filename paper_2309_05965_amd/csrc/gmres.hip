@@ -192,12 +192,14 @@ __device__ __forceinline__ int wave_reduce8_index(int lane) {
   return ((lane & 32) ? 4 : 0) + ((lane & 16) ? 2 : 0) + ((lane & 8) ? 1 : 0);
 }
 
-// Single work group (n <= 8192): w is staged in LDS for the whole step.
+// Single work group (n <= 4096): w is staged in LDS for the whole step.
+// (Beyond, one compute unit reading the whole basis takes longer than the
+// four launches of the many-work-group chain.)
 // A pass computes the j+1 dot products one wavefront per basis vector
 // (lanes over the elements, eight loads of V in flight per lane, w from
 // LDS, fixed-order wave reduction), then every thread updates its elements
 // of w in LDS, eight basis vectors per round.
-constexpr int ARN1_MAXN = 8192;
+constexpr int ARN1_MAXN = 4096;
 __global__ void __launch_bounds__(GB) k_arnoldi1(int64_t n, int* ctl, int ldh, double* V, double* Hm, double* cs,
                                                 double* sn, double* gv, double* scal) {
   __shared__ double wl[ARN1_MAXN];
@@ -691,7 +693,7 @@ void gm_residual_start(kfbi_plan* pl, const double* b, const double* Ax0, int us
                      pl->gv, pl->scal, pl->ctl, tol, maxit);
 }
 
-// one work group up to 8192 unknowns (the step is latency-bound there),
+// one work group up to 4096 unknowns (the step is latency-bound there),
 // with the basis in registers up to 2048; beyond, the basis is read by many
 // compute units
 void gm_arnoldi(kfbi_plan* pl) {

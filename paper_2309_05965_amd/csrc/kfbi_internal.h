@@ -19,7 +19,7 @@
 #define KFBI_MAXN 10       // max Neumann points
 #define KFBI_GMRES_MAX 512
 #define KFBI_NGRAPH 5      // captured GMRES graphs of 1, 2, 4, 8 and 16 iterations
-#define KFBI_MG_CAPS 16    // per-iteration multigrid caps captured as graphs of their own
+#define KFBI_MG_GRAPHS 48  // captured multigrid box solves kept per plan
 
 // device-side status bits (OR-ed into plan->d_flags)
 enum {
@@ -165,14 +165,30 @@ struct kfbi_plan {
                                  //  iteration j the corrections of its box solve at 4 + j]
   int mg_cap_eff;                // cap used inside kfbi_solve: observed need + 2 (0: unknown)
   int mg_run_cap;                // cap of the box solves being enqueued (0: mg_maxit)
-  // relaxed multigrid inside GMRES: iteration j of a solve runs at most
-  // log_prev[j] + 1 corrections, log_prev[j] being what it needed in the
-  // plan's previous solve (log_n iterations recorded; 0: none)
-  int log_prev[KFBI_GMRES_MAX + 2];
-  int log_n, log_k;
-  int* h_log;                    // pinned copy of the device log
-  hipGraph_t mg_graph[KFBI_MG_CAPS + 1];
-  hipGraphExec_t mg_gexec[KFBI_MG_CAPS + 1];   // one iteration, at most c corrections
+  bool mg_guess;                 // the box solve being enqueued starts from v as it stands
+  // box solutions of a solve's matvecs (multigrid): slot 0 the initial
+  // iterate's, slot 1 + j GMRES iteration j's.  The iterate x0 + sum y_j v_j
+  // has the same combination of them as its box solution, which starts the
+  // box solve of the true residual.
+  double* ustore;
+  int ustore_slots;              // slots allocated (0: none)
+  int64_t ustore_n;              // nodes per slot
+  // captured multigrid box solves, one per (right-hand side, solution,
+  // GMRES control word, cap, start), valid while the multigrid configuration
+  // key mg_sg_key holds: they do not depend on the interfaces, so every
+  // geometry on the same grid reuses them
+  struct MgSolveGraph {
+    const double* F;
+    double* v;
+    const int* gctl;
+    int cap, guess;
+    hipGraph_t g;
+    hipGraphExec_t e;
+  };
+  MgSolveGraph mg_sg[KFBI_MG_GRAPHS];
+  int mg_sg_n;
+  uint64_t mg_sg_key[48];
+  bool mg_graphs_off;            // a capture failed: solves are enqueued kernel by kernel
   double mg_relax;               // inexact-Krylov relaxation of eps inside GMRES (0: off)
   double relax_word;             // host copy of the factor last written to GMRES scal[7] (NaN: none)
   double* mg_scal;               // [|F|, last relative residual]
@@ -266,8 +282,16 @@ void dst_solve_grid(const GridDesc& g, const double* tw, const double* eig1, dou
 // twiddles exp(-2 pi i m / 2N) (m < 2N, interleaved re, im) and the 1D
 // eigenvalues s_k = -4/h^2 sin^2(k pi / 2N) (k <= N) of the sine transform
 void dst_host_tables(int N, double h, double* tw, double* eig1);
+// v = A_h^-1 F to eps_in (at most mg_run_cap corrections), sent as a
+// captured graph when the stream is not being captured itself
 void mg_solve(kfbi_plan* pl, const double* F, double* v);
+void mg_graphs_clear(kfbi_plan* pl);
 void mg_matvec_rhs(kfbi_plan* pl);
+// the box-solution store of a solve (see kfbi_plan::ustore)
+kfbi_status mg_store_reserve(kfbi_plan* pl);
+void mg_store_solution(kfbi_plan* pl, const double* v);
+void mg_guess_from_store(kfbi_plan* pl, int k, int use_x0, const double* y, double* v);
+void mg_sum(kfbi_plan* pl, const double* a, const double* b, double* out);
 void dst_solve_corrections(kfbi_plan* pl, const double* psi, double* v);
 // gmres.hip (step S6)
 void gm_residual_start(kfbi_plan* pl, const double* b, const double* Ax0, int use_x0, double tol, int maxit);

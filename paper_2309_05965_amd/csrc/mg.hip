@@ -31,6 +31,8 @@
 
 #include <vector>
 
+#include <string.h>
+
 #include "kfbi_internal.h"
 
 namespace {
@@ -661,6 +663,37 @@ __global__ void __launch_bounds__(MG_BLOCK) k_prolong(Ctl ctl, Lev<T> Fl, int n1
   }
 }
 
+// ---------------------------------------------------------------- box-solution store
+// slot 1 + j of GMRES iteration j (control word; nothing once GMRES has
+// converged or beyond the slots) or slot 0 (no control word)
+__global__ void __launch_bounds__(MG_BLOCK) k_ustore(const int* gctl, int64_t n, int slots, const double* v,
+                                                    double* store) {
+  int slot = 0;
+  if (gctl) {
+    if (gctl[1]) return;
+    slot = 1 + gctl[0];
+    if (slot >= slots) return;
+  }
+  double* dst = store + (int64_t)slot * n;
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    dst[t] = v[t];
+}
+
+// v = (use_x0 ? slot 0 : 0) + sum_{j < k} y_j slot(1 + j)
+__global__ void __launch_bounds__(MG_BLOCK) k_ucombine(int64_t n, int k, int use_x0, const double* y,
+                                                      const double* store, double* v) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x) {
+    double s = use_x0 ? store[t] : 0.0;
+    for (int j = 0; j < k; ++j) s += y[j] * store[(int64_t)(1 + j) * n + t];
+    v[t] = s;
+  }
+}
+
+__global__ void __launch_bounds__(MG_BLOCK) k_usum(int64_t n, const double* a, const double* b, double* out) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    out[t] = a[t] + b[t];
+}
+
 // ---------------------------------------------------------------- FP64 outer loop
 struct OuterArgs {
   Ctl ctl;
@@ -713,7 +746,7 @@ __global__ void __launch_bounds__(MG_BLOCK) k_outer_resid(OuterArgs a, T* f0) {
 // from the GMRES scalars (gs[0] = |r_j| estimate, gs[1] = |b|, gs[3] =
 // tol, gs[7] = relax, 0 for off), clamped to [eps, 1e-2].
 __global__ void __launch_bounds__(MG_BLOCK) k_check(Ctl ctl, const double* part, int nblk, int first, double eps,
-                                                   int maxit, double* scal, const double* gs) {
+                                                   int maxit, double* scal, const double* gs, int count_hit) {
   if ((ctl.gctl && ctl.gctl[1]) || ctl.mctl[0]) return;
   const double relax = (ctl.gctl && gs) ? gs[7] : 0.0;
   if (relax > 0.0) {
@@ -752,7 +785,7 @@ __global__ void __launch_bounds__(MG_BLOCK) k_check(Ctl ctl, const double* part,
       if (ctl.mctl[1] > ctl.mctl[2]) ctl.mctl[2] = ctl.mctl[1];
       // a box solve stopped by its cap above eps_in (the relaxed iterations
       // keep a record of their own, mctl[4 + j])
-      if (!conv && !(relax > 0.0)) ctl.mctl[3] += 1;
+      if (!conv && !(relax > 0.0) && count_hit) ctl.mctl[3] += 1;
       if (ctl.gctl) ctl.mctl[4 + ctl.gctl[0]] = ctl.mctl[1];   // corrections of GMRES iteration j
     }
   }
@@ -1029,6 +1062,10 @@ void solve_t(kfbi_plan* pl, const double* F, double* v) {
   oa.v = v;
   oa.part = pl->mg_part;
   oa.first = 1;
+  // from a given v (its box boundary zero like every stored solution) the
+  // first correction takes the full outer residual too, and a stop at the
+  // cap is no sign of a short cap (the caller continues such a solve)
+  const bool guess = pl->mg_guess;
   hipLaunchKernelGGL(k_start, dim3(1), dim3(1), 0, st, ctl);
   {
     const int64_t nb = 2 * g.d * (g.d == 3 ? (int64_t)g.n1 * g.n1 : (int64_t)g.n1);
@@ -1038,12 +1075,12 @@ void solve_t(kfbi_plan* pl, const double* F, double* v) {
   const int cap = pl->mg_run_cap > 0 ? pl->mg_run_cap : pl->mg_maxit;
   for (int it = 0; it < cap; ++it) {
     int nb_part = (int)gout;
-    if (it == 0)
+    if (it == 0 && !guess)
       hipLaunchKernelGGL((k_outer_resid<T>), dim3(gout), dim3(MG_BLOCK), 0, st, oa, f0);
     else
       sweep<double, T, SW_OUTER>(pl, ctl, g.N, pl->mg_c, 0.0, v, F, f0, &nb_part);
     hipLaunchKernelGGL(k_check, dim3(1), dim3(MG_BLOCK), 0, st, ctl, (const double*)pl->mg_part, nb_part,
-                       it == 0 ? 1 : 0, pl->mg_eps, cap, pl->mg_scal, (const double*)pl->scal);
+                       it == 0 ? 1 : 0, pl->mg_eps, cap, pl->mg_scal, (const double*)pl->scal, guess ? 0 : 1);
     if (fused_path(pl)) {
       vcycle_fused<T>(pl, L, ctl, v);
     } else {
@@ -1056,7 +1093,7 @@ void solve_t(kfbi_plan* pl, const double* F, double* v) {
   int nb_part = 0;
   sweep<double, T, SW_OUTER>(pl, ctl, g.N, pl->mg_c, 0.0, v, F, f0, &nb_part);
   hipLaunchKernelGGL(k_check, dim3(1), dim3(MG_BLOCK), 0, st, ctl, (const double*)pl->mg_part, nb_part, 0,
-                     pl->mg_eps, cap, pl->mg_scal, (const double*)pl->scal);
+                     pl->mg_eps, cap, pl->mg_scal, (const double*)pl->scal, guess ? 0 : 1);
 }
 
 double jacobi_weight(const double* c, int d) {
@@ -1098,7 +1135,7 @@ kfbi_status mg_configure(kfbi_plan* pl, int solver, double eps, int maxit) {
   pl->mg_maxit = maxit;
   pl->mg_cap_eff = 0;
   pl->mg_run_cap = 0;
-  pl->log_n = 0;
+  pl->mg_guess = false;
   if (solver == KFBI_BOX_FFT) return KFBI_OK;
   const GridDesc& g = pl->g;
   if (g.N < 16) {
@@ -1193,11 +1230,138 @@ kfbi_status mg_configure(kfbi_plan* pl, int solver, double eps, int maxit) {
   return KFBI_OK;
 }
 
-void mg_solve(kfbi_plan* pl, const double* F, double* v) {
+namespace {
+void solve_enqueue(kfbi_plan* pl, const double* F, double* v) {
   if (pl->box_solver == KFBI_BOX_MG32)
     solve_t<float>(pl, F, v);
   else
     solve_t<double>(pl, F, v);
+}
+
+// everything the kernels of a captured solve take by value or by address,
+// other than F, v, the control word, the cap and the start
+void config_key(const kfbi_plan* pl, uint64_t* key) {
+  memset(key, 0, sizeof(uint64_t) * 48);
+  int i = 0;
+  auto put = [&](uint64_t x) { key[i++] = x; };
+  auto putd = [&](double x) {
+    uint64_t u;
+    memcpy(&u, &x, 8);
+    put(u);
+  };
+  put((uint64_t)pl->g.d | (uint64_t)pl->g.N << 8 | (uint64_t)pl->box_solver << 40);
+  putd(pl->mg_eps);
+  putd(pl->mg_w);
+  for (int c = 0; c < 27; ++c) putd(pl->mg_c[c]);
+  for (const void* q : {(const void*)pl->mg_u, (const void*)pl->mg_t, (const void*)pl->mg_f, (const void*)pl->mg_Fc,
+                        (const void*)pl->mg_Uc, (const void*)pl->mg_T1c, (const void*)pl->mg_T2c,
+                        (const void*)pl->mg_twc, (const void*)pl->mg_eigc, (const void*)pl->mg_part,
+                        (const void*)pl->mg_ctl, (const void*)pl->mg_scal, (const void*)pl->scal})
+    put((uint64_t)(uintptr_t)q);
+}
+}  // namespace
+
+void mg_graphs_clear(kfbi_plan* pl) {
+  for (int i = 0; i < pl->mg_sg_n; ++i) {
+    if (pl->mg_sg[i].e) (void)hipGraphExecDestroy(pl->mg_sg[i].e);
+    if (pl->mg_sg[i].g) (void)hipGraphDestroy(pl->mg_sg[i].g);
+  }
+  pl->mg_sg_n = 0;
+}
+
+// A solve is a few hundred short kernels whose launches cost more than
+// their work on small grids: it goes out as one graph, captured on first
+// use.  Inside a capture of the caller's (or with the tracing events of
+// profile mode 2) the kernels are enqueued as they are.
+void mg_solve(kfbi_plan* pl, const double* F, double* v) {
+  hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+  const hipStream_t st = pl->stream;
+  // (the default streams cannot be captured)
+  if (pl->mg_graphs_off || pl->prof_on == 2 || st == nullptr || st == hipStreamLegacy || st == hipStreamPerThread ||
+      hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
+    solve_enqueue(pl, F, v);
+    return;
+  }
+  uint64_t key[48];
+  config_key(pl, key);
+  if (memcmp(key, pl->mg_sg_key, sizeof(key)) != 0) {
+    mg_graphs_clear(pl);
+    memcpy(pl->mg_sg_key, key, sizeof(key));
+  }
+  const int cap = pl->mg_run_cap > 0 ? pl->mg_run_cap : pl->mg_maxit;
+  const int guess = pl->mg_guess ? 1 : 0;
+  for (int i = 0; i < pl->mg_sg_n; ++i) {
+    const kfbi_plan::MgSolveGraph& e = pl->mg_sg[i];
+    if (e.F == F && e.v == v && e.gctl == pl->ctl_active && e.cap == cap && e.guess == guess) {
+      if (hipGraphLaunch(e.e, pl->stream) == hipSuccess) return;
+      (void)hipGetLastError();
+      pl->mg_graphs_off = true;
+      solve_enqueue(pl, F, v);
+      return;
+    }
+  }
+  // capture exclusive of other threads' set-up and allocations; a thread
+  // that cannot have the lock now enqueues the kernels instead
+  std::unique_lock<std::shared_mutex> lock(kfbi_capture_mutex, std::try_to_lock);
+  if (!lock.owns_lock()) {
+    solve_enqueue(pl, F, v);
+    return;
+  }
+  if (pl->mg_sg_n == KFBI_MG_GRAPHS) mg_graphs_clear(pl);
+  hipGraph_t g = nullptr;
+  hipGraphExec_t ex = nullptr;
+  bool ok = hipStreamBeginCapture(pl->stream, hipStreamCaptureModeThreadLocal) == hipSuccess;
+  if (ok) {
+    solve_enqueue(pl, F, v);
+    ok = hipStreamEndCapture(pl->stream, &g) == hipSuccess && g;
+  }
+  ok = ok && hipGraphInstantiate(&ex, g, nullptr, nullptr, 0) == hipSuccess;
+  ok = ok && hipGraphLaunch(ex, pl->stream) == hipSuccess;
+  if (!ok) {
+    (void)hipGetLastError();
+    if (ex) (void)hipGraphExecDestroy(ex);
+    if (g) (void)hipGraphDestroy(g);
+    pl->mg_graphs_off = true;
+    solve_enqueue(pl, F, v);
+    return;
+  }
+  pl->mg_sg[pl->mg_sg_n++] = kfbi_plan::MgSolveGraph{F, v, pl->ctl_active, cap, guess, g, ex};
+}
+
+// 1 + 64 slots, and at most 2 GiB
+kfbi_status mg_store_reserve(kfbi_plan* pl) {
+  const int64_t n = pl->g.n_nodes;
+  if (pl->ustore && pl->ustore_n == n) return KFBI_OK;
+  if (pl->ustore) (void)hipFree(pl->ustore);
+  pl->ustore = nullptr;
+  pl->ustore_slots = 0;
+  pl->ustore_n = 0;
+  int64_t slots = ((int64_t)2 << 30) / (8 * n);
+  if (slots > 65) slots = 65;
+  if (slots < 2) return KFBI_OK;         // too large a grid: solves run without the store
+  if (hipMalloc((void**)&pl->ustore, sizeof(double) * n * slots) != hipSuccess) {
+    (void)hipGetLastError();
+    pl->ustore = nullptr;
+    return KFBI_OK;                      // the store is an optimisation: go without it
+  }
+  pl->ustore_slots = (int)slots;
+  pl->ustore_n = n;
+  return KFBI_OK;
+}
+
+void mg_store_solution(kfbi_plan* pl, const double* v) {
+  if (!pl->ustore) return;
+  hipLaunchKernelGGL(k_ustore, dim3(gsblk(pl->ustore_n)), dim3(MG_BLOCK), 0, pl->stream, pl->ctl_active,
+                     pl->ustore_n, pl->ustore_slots, v, pl->ustore);
+}
+
+void mg_guess_from_store(kfbi_plan* pl, int k, int use_x0, const double* y, double* v) {
+  hipLaunchKernelGGL(k_ucombine, dim3(gsblk(pl->ustore_n)), dim3(MG_BLOCK), 0, pl->stream, pl->ustore_n, k,
+                     use_x0, y, (const double*)pl->ustore, v);
+}
+
+void mg_sum(kfbi_plan* pl, const double* a, const double* b, double* out) {
+  hipLaunchKernelGGL(k_usum, dim3(gsblk(pl->g.n_nodes)), dim3(MG_BLOCK), 0, pl->stream, pl->g.n_nodes, a, b, out);
 }
 
 void mg_matvec_rhs(kfbi_plan* pl) {

@@ -1,7 +1,7 @@
 """Device GMRES (Arnoldi step) against a plain host GMRES driven by the
 same device matvec, on problems that take each Arnoldi path: one work
 group with 1, 2, 4 or 8 unknowns per thread, and the many-work-group
-chain (more than 8192 unknowns).  The matvec itself is pinned to the
+chain (more than 4096 unknowns).  The matvec itself is pinned to the
 oracle in test_gpu_parity; here the Krylov machinery is checked: the
 solution of A psi = b, the iteration count, and run-to-run bitwise
 reproducibility."""
@@ -24,7 +24,7 @@ CASES = {
     "c2_512": lambda: W.config2(512),        # 1,038 unknowns: 5 per thread, 4 wavefronts
     "c1_1024": lambda: W.config1(1024),      # 1280 < n <= 2048: 2 per thread, 16 wavefronts
     "sphere_64": lambda: sphere(64),         # ~3.5e3: one work group, w in LDS
-    "torus_64": lambda: W.config3(64),       # ~6.1e3: one work group, w in LDS
+    "torus_64": lambda: W.config3(64),       # ~6.1e3: many work groups, few of them
     "sphere_128": lambda: sphere(128),       # ~1.4e4: many work groups
 }
 
