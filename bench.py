@@ -224,8 +224,8 @@ def run_form(ho, warm, timed, tol, solver, eps, relax, learned_start, keep_u=Fal
     def one(i, it):
         _, prob, geom, jmp, data = it
         plan.setup(prob)
-        psi0 = warmstart.predict(model, plan, geom, jmp) if learned_start else None
-        psi, _, info = plan.solve(data, tol=tol, psi0=psi0, u_out=U[i] if (keep_u and i >= 0) else None)
+        la = warmstart.learned_args(model, geom, jmp) if learned_start else None
+        psi, _, info = plan.solve(data, tol=tol, learned=la, u_out=U[i] if (keep_u and i >= 0) else None)
         return psi, info
 
     for it in items[:warm]:
@@ -354,15 +354,17 @@ def forms_batch(workers=(1, 8)):
     oracle's set-up reports them, and are not counted as solved)."""
     import torch
     from paper_2309_05965_amd import kfbi
+    from paper_2309_05965_amd import manufactured as M
     from paper_2309_05965_amd import workloads as W
     probs = [p for p, _ in W.config4_batch(512)]
+    gen = M.BatchData(probs, ["star2d"] * len(probs))
     out = {}
     for w in workers:
-        b = kfbi.Batch(probs, ["star2d"] * len(probs), workers=w)
-        b.solve(tol=1e-8, raise_on_fail=False)
+        b = kfbi.Batch(probs, workers=w)
+        b.solve(gen.fn, gen.ctx, tol=1e-8, raise_on_fail=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, info, _ = b.solve(tol=1e-8, raise_on_fail=False)
+        _, info, _ = b.solve(gen.fn, gen.ctx, tol=1e-8, raise_on_fail=False)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         ok = sum(1 for i in info if i["status"] == 0)

@@ -131,10 +131,37 @@ typedef struct {
   const double* gB;
 } kfbi_data;
 
+typedef struct kfbi_mlp kfbi_mlp;
+
+/* Initial density of a solve (Alg. 1 Step 2 gives GMRES an initial guess):
+ * zero, the caller's (psi_inout), or predicted by a trained network for an
+ * ellipsoid problem (kfbi_learned_start with the fields of kfbi_learned). */
+enum { KFBI_START_ZERO = 0, KFBI_START_GIVEN = 1, KFBI_START_LEARNED = 2 };
+/* Box solver of a solve: the plan's (kfbi_plan_set_box_solver), or one of
+ * KFBI_BOX_FFT / MG64 / MG32 (as 1 + KFBI_BOX_*) set on the plan first. */
+enum { KFBI_SOLVER_PLAN = 0, KFBI_SOLVER_FFT = 1, KFBI_SOLVER_MG64 = 2, KFBI_SOLVER_MG32 = 3 };
+
+typedef struct {
+  kfbi_mlp* mlp;        /* network 15 -> ... -> 4 x 81 (kfbi_learned_start) */
+  int32_t nb;           /* jump coefficients, 32 */
+  const double* geom;   /* [15] device: centre, semi-axes, orientation Q row-major */
+  const double* jumps;  /* [nb] device: a_1[8], a_2[8], b_1[8], b_2[8] */
+  double scale;         /* scale of the network's output */
+} kfbi_learned;
+
+/* Options of kfbi_solve.  Zero-initialised apart from tol and max_iter,
+ * they give the plain solve: zero start with the plan's box solver. */
 typedef struct {
   double tol;           /* GMRES stop: |r_k| <= tol |b| (default 1e-10) */
   int32_t max_iter;     /* unrestarted GMRES length (<= 512) */
-  int32_t use_x0;       /* 1: psi_inout holds the initial guess; 0: zero start */
+  int32_t start;        /* KFBI_START_*: zero, psi_inout as given, or learned from *learned */
+  int32_t solver;       /* KFBI_SOLVER_*: with other than PLAN the plan's box solver becomes this one
+                           with eps_in, max_cycles and relax (kept for later solves; as
+                           kfbi_plan_set_box_solver and kfbi_plan_set_box_relaxation) */
+  int32_t max_cycles;   /* multigrid correction cap, 1..64 (0: 40) */
+  double eps_in;        /* multigrid tolerance |F - A_h v| <= eps_in |F| (0: 1e-12) */
+  double relax;         /* relaxed multigrid tolerance inside GMRES, >= 0 (0: off) */
+  const kfbi_learned* learned;   /* KFBI_START_LEARNED: the network and the problem's geometry and jumps */
 } kfbi_opts;
 
 typedef struct {
@@ -172,7 +199,9 @@ kfbi_status kfbi_plan_sizes(const kfbi_plan* plan, kfbi_sizes* out);
  *   PDE_PTS    double [n_dof][n_pde][dim] PDE collocation points
  *   IRREGULAR  [n_irregular]              irregular node indices
  *   CORR       [n_corr][3]                interface, node, owner centre
- *   COND       double [n_dof]             collocation 1-norm condition numbers */
+ *   COND       double [n_dof]             collocation 1-norm condition numbers
+ *   DOF_POS    double [n_dof][dim]        primary points
+ * The copy is ordered on the plan's stream (no host wait). */
 enum {
   KFBI_EXPORT_REGION = 0,
   KFBI_EXPORT_SURF_POS = 1,
@@ -277,8 +306,13 @@ kfbi_status kfbi_matvec(kfbi_plan* plan, const double* psi, double* Apsi);
 kfbi_status kfbi_rhs(kfbi_plan* plan, const kfbi_data* data, double* b);
 
 /* Full solve (Alg. 1): b, GMRES on kfbi_matvec to opts->tol, then
- * u = w(g1, E psi, ftilde, fhat, gB).  psi_inout [n_dof] (initial guess if
- * opts->use_x0, density on return); u_out [n_nodes] (may be NULL).
+ * u = w(g1, E psi, ftilde, fhat, gB).  psi_inout [n_dof] (initial guess
+ * with KFBI_START_GIVEN; with KFBI_START_LEARNED the predicted density is
+ * written there first; density on return); u_out [n_nodes] (may be NULL).
+ * With a multigrid box solver, u is the step-1 grid solution plus the box
+ * solution of the true residual's matvec (the solution is linear in the
+ * data and the density), and that box solve starts from the iterations'
+ * stored box solutions combined with the GMRES coefficients.
  * The host waits for the device between batches of captured GMRES
  * iterations and for the true residual; on a plan solved before (same graph
  * key), without relaxation and from a zero start, the update, the true
@@ -308,39 +342,42 @@ kfbi_status kfbi_plan_timing(kfbi_plan* plan, int64_t* solves, int64_t* launches
 kfbi_status kfbi_plan_destroy(kfbi_plan* plan);
 
 /* ----------------------------------------------------------------------
- * Many independent problems (batched solves).  Each problem is a
- * kfbi_problem whose data are a manufactured solution evaluated on the
- * device at the plan's own query points:
- *   KFBI_MANU_STAR2D   u_in = cos 2x e^y, u_out = x^2 - y^3 (2D)
- *   KFBI_MANU_TORUS3D  u_in = sin x sin y sin z, u_out = e^(x+y+z)/10 (3D)
- * (fhat_s = Lap u_s - kappa u_s, g1 = [u], g2 = [beta d_n u], gB = u_out).
+ * Many independent problems (batched solves, Alg. 1 per problem).
  * -------------------------------------------------------------------- */
-enum { KFBI_MANU_STAR2D = 1, KFBI_MANU_TORUS3D = 2 };
-
-/* Data of a manufactured solution at a ready plan's query points, written
- * on the plan's stream: g1, g2 [n_surf], ftilde [n_dof][n_pde],
- * fhat [n_iface+1][n_nodes], gB [n_nodes]. */
-kfbi_status kfbi_plan_manufactured_data(kfbi_plan* plan, int kind, double* g1, double* g2, double* ftilde,
-                                        double* fhat, double* gB);
-
 typedef struct kfbi_batch kfbi_batch;
-/* A batch of n problems (copied) with their manufactured-solution kinds,
- * solved by n_workers (1..16) host threads, each with its own stream and
- * one plan per grid shape (created on first use, re-set-up for every
- * problem).  Device of the calling thread. */
-kfbi_status kfbi_batch_create(const kfbi_problem* probs, const int* manu, int n, int n_workers,
-                              kfbi_batch** out);
+
+/* Data of one problem, supplied by the caller once a worker's plan is set
+ * up for it (its query points are then known: kfbi_plan_sizes,
+ * kfbi_plan_export).  Called on the worker's host thread; work the callback
+ * enqueues must go on `stream` (the worker's stream, which is the plan's).
+ * It fills *data with device arrays laid out as kfbi_data for that plan,
+ * which must stay valid until the same worker calls it again or the batch
+ * solve returns, and sets *psi_out to a device array of n_dof doubles for
+ * the problem's density (the initial guess too with KFBI_START_GIVEN), or
+ * to NULL to discard it.  A status other than KFBI_OK fails the problem
+ * with that status. */
+typedef kfbi_status (*kfbi_batch_data_fn)(void* ctx, int problem, kfbi_plan* plan, void* stream, kfbi_data* data,
+                                          double** psi_out);
+
+/* A batch of n problems (copied), solved by n_workers (1..16) host
+ * threads, each with its own stream and one plan per grid shape (created
+ * on first use, set up again for every problem).  Device of the calling
+ * thread. */
+kfbi_status kfbi_batch_create(const kfbi_problem* probs, int n, int n_workers, kfbi_batch** out);
 /* Number of problems and sum of their node counts (the length of u_all). */
 kfbi_status kfbi_batch_sizes(const kfbi_batch* batch, int64_t* n_problems, int64_t* total_nodes);
-/* Solve every problem (Alg. 1, zero start, opts->tol / max_iter): workers
- * take problems in order of decreasing node count.  u_all (device, may be
- * NULL): the solutions concatenated in problem order, (N_i+1)^d values
- * each.  infos (host, [n]) and seconds (host, [n], may be NULL: wall time
- * of each problem on its worker, set-up included) are filled for every
- * problem; returns KFBI_OK only if every problem is OK, else the first
- * failure's status with its message.  The densities are not kept. */
-kfbi_status kfbi_batch_solve(kfbi_batch* batch, const kfbi_opts* opts, double* u_all, kfbi_info* infos,
-                             double* seconds);
+/* Solve every problem with opts (box solver, tolerance, start; a learned
+ * start is per problem and is rejected here): workers take problems in
+ * order of decreasing node count, set up the plan, ask data_fn(ctx, ...)
+ * for the data and solve.  u_all (device, may be NULL): the solutions
+ * concatenated in problem order, (N_i+1)^d values each.  infos (host, [n])
+ * and seconds (host, [n], may be NULL: wall time of each problem on its
+ * worker, set-up and data included) are filled for every problem; a problem
+ * whose set-up fails (e.g. KFBI_E_UNRESOLVED) is skipped with that status.
+ * Returns KFBI_OK only if every problem is OK, else the first failure's
+ * status with its message. */
+kfbi_status kfbi_batch_solve(kfbi_batch* batch, const kfbi_opts* opts, kfbi_batch_data_fn data_fn, void* ctx,
+                             double* u_all, kfbi_info* infos, double* seconds);
 kfbi_status kfbi_batch_destroy(kfbi_batch* batch);
 
 /* ----------------------------------------------------------------------
@@ -349,8 +386,6 @@ kfbi_status kfbi_batch_destroy(kfbi_batch* batch);
  * the given stream (the plan's stream for the plan calls); the MLP object
  * and its buffers are library-owned.
  * -------------------------------------------------------------------- */
-typedef struct kfbi_mlp kfbi_mlp;
-
 /* MLP widths[0] -> widths[1] -> ... -> widths[n_layers], ReLU after every
  * layer but the last.  Weights are bf16 copies of fp32 master weights
  * (all zero until kfbi_mlp_set_params); GEMMs accumulate in fp32.

@@ -3,7 +3,9 @@
     python -m paper_2309_05965_amd.build
 
 Every source under csrc/ is compiled by hipcc for gfx950 (packed-FP32
-instruction selection disabled) and linked into paper_2309_05965_amd/libkfbi.so.
+instruction selection disabled) and linked into paper_2309_05965_amd/libkfbi.so;
+the test-data generator under gen/ into libkfbi_gen.so, which uses only the
+C ABI of libkfbi.so.
 """
 import concurrent.futures
 import os
@@ -16,6 +18,8 @@ ROOT = os.path.dirname(HERE)
 CSRC = os.path.join(HERE, "csrc")
 OBJ = os.path.join(ROOT, "_build", "kfbi")
 LIB = os.path.join(HERE, "libkfbi.so")
+GEN = os.path.join(HERE, "gen")
+GEN_LIB = os.path.join(HERE, "libkfbi_gen.so")
 SOURCES = ["geometry.hip", "collocation.hip", "operator.hip", "dst.hip", "mg.hip", "gmres.hip", "learned.hip", "batch.hip", "api.hip"]
 ARCH = os.environ.get("KFBI_OFFLOAD_ARCH", "gfx950")
 
@@ -33,9 +37,9 @@ def flags():
             "-I", os.path.join(ROOT, "include"), "-Wno-unused-result"]
 
 
-def _compile(src):
+def _compile(src, folder=CSRC):
     out = os.path.join(OBJ, src + ".o")
-    cmd = [hipcc()] + flags() + ["-c", os.path.join(CSRC, src), "-o", out]
+    cmd = [hipcc()] + flags() + ["-c", os.path.join(folder, src), "-o", out]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("hipcc failed for %s:\n%s\n%s" % (src, " ".join(cmd), r.stderr))
@@ -52,8 +56,16 @@ def build(verbose=False):
     if r.returncode != 0:
         raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
     os.replace(tmp, LIB)
+    gobj = _compile("manufactured.hip", GEN)
+    tmp = GEN_LIB + ".tmp"
+    cmd = [hipcc(), "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp, gobj, "-L" + HERE, "-lkfbi",
+           "-Wl,-rpath,$ORIGIN"]
+    r = subprocess.run(cmd, capture_output=True, text=True)
+    if r.returncode != 0:
+        raise RuntimeError("link failed:\n%s\n%s" % (" ".join(cmd), r.stderr))
+    os.replace(tmp, GEN_LIB)
     if verbose:
-        print("built", LIB)
+        print("built", LIB, "and", GEN_LIB)
     return LIB
 
 

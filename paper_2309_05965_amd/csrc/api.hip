@@ -660,14 +660,18 @@ extern "C" kfbi_status kfbi_plan_destroy(kfbi_plan* pl) {
 }
 
 namespace {
+struct PdeOffsets {
+  int o[KFBI_MAXP * 3];
+};
+
 __global__ void k_pde_points(int64_t n_dof, int d, int nP, double h, const int* d2s, const double* spos,
-                             const int* offs, double* out) {
+                             PdeOffsets offs, double* out) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   if (t >= n_dof * nP) return;
   int64_t c = t / nP;
   int j = (int)(t % nP);
   const double* P = spos + (int64_t)d2s[c] * d;
-  for (int a = 0; a < d; ++a) out[t * d + a] = P[a] + (double)offs[j * 3 + a] * h;
+  for (int a = 0; a < d; ++a) out[t * d + a] = P[a] + (double)offs.o[j * 3 + a] * h;
 }
 
 __global__ void k_corr_table(int64_t n, const int* k, const int* node, const int* own, int* out) {
@@ -732,14 +736,12 @@ extern "C" kfbi_status kfbi_plan_export(const kfbi_plan* pl_c, int which, void* 
   }
   int offP[KFBI_MAXP][3], nP;
   kfbi_pde_lattice(d, pl->g.p, offP, &nP);
-  int* doff;
-  KCHK(dalloc(&doff, 3 * KFBI_MAXP));
-  HIPCHK(hipMemcpyAsync(doff, offP, sizeof(offP), hipMemcpyHostToDevice, pl->stream));
+  PdeOffsets po;
+  memcpy(po.o, offP, sizeof(po.o));
   int64_t n = pl->n_dof * nP;
   hipLaunchKernelGGL(k_pde_points, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, pl->stream, pl->n_dof, d, nP,
-                     pl->g.h, pl->d2s, pl->s_pos, doff, (double*)dst);
-  HIPCHK(hipStreamSynchronize(pl->stream));
-  dfree(doff);
+                     pl->g.h, pl->d2s, pl->s_pos, po, (double*)dst);
+  HIPCHK(hipGetLastError());
   return KFBI_OK;
 }
 
@@ -1108,11 +1110,12 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
   KCHK(set_relax_word(pl, relax ? pl->mg_relax : 0.0));
   // Step 2: initial residual and control word (multigrid: the box solution
   // of A x0 goes to the store's slot 0)
-  if (opts->use_x0) {
+  const int use_x0 = opts->start == KFBI_START_GIVEN ? 1 : 0;
+  if (use_x0) {
     matvec_impl(pl, psi, pl->work);
     if (mg) mg_store_solution(pl, pl->vbuf);
   }
-  gm_residual_start(pl, pl->bvec, pl->work, opts->use_x0, tol, m);
+  gm_residual_start(pl, pl->bvec, pl->work, use_x0, tol, m);
   KCHK(ensure_graph(pl));
   // final solve u = w(g1, E psi, ftilde, fhat, gB)
   double* u = u_out ? u_out : pl->vsbuf;
@@ -1132,7 +1135,7 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
     decltype(final_solve)* fin;
   } sc{pl, psi, &final_solve};
   GmresSpec spec;
-  spec.active = !mg && !opts->use_x0 && pl->graph_uses > 1;
+  spec.active = !mg && !use_x0 && pl->graph_uses > 1;
   spec.ctx = &sc;
   spec.before = [](void* c) {
     SpecCtx* x = (SpecCtx*)c;
@@ -1167,7 +1170,7 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
     const double tr = rel_residual(pl->h_dpinned[4], pl->h_dpinned[5]);
     return solve_report(pl, info, o, o.k, tr, tol, m);
   }
-  gm_update(pl, o.k, psi, opts->use_x0);
+  gm_update(pl, o.k, psi, use_x0);
   double tr = 0.0;
   if (!mg) {
     // psi is final here: the final solve is enqueued before the host waits
@@ -1181,7 +1184,7 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
   // the residual on the guess that no continuation follows.
   auto final_sum = [&] { mg_sum(pl, pl->vsbuf, pl->vbuf, u); };
   int k = o.k;
-  KCHK(mg_true_residual(pl, psi, o.k, opts->use_x0, &tr, [] {}));
+  KCHK(mg_true_residual(pl, psi, o.k, use_x0, &tr, [] {}));
   // with a relaxed inner tolerance the GMRES estimate can run ahead of the
   // true residual: if it misses tol, continue from psi with full-accuracy
   // box solves until it meets it (A psi and its box solution are at hand)
@@ -1202,12 +1205,37 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
 }
 }  // namespace
 
-extern "C" kfbi_status kfbi_solve(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* opts, double* psi,
+// the box solver the options ask for, set on the plan when it differs
+kfbi_status apply_solver(kfbi_plan* pl, const kfbi_opts& o) {
+  const int solver = o.solver - 1;
+  const double eps = o.eps_in > 0.0 ? o.eps_in : 1e-12;
+  const int cycles = o.max_cycles > 0 ? o.max_cycles : 40;
+  if (solver != pl->box_solver || (solver != KFBI_BOX_FFT && (eps != pl->mg_eps || cycles != pl->mg_maxit)))
+    KCHK(kfbi_plan_set_box_solver(pl, solver, eps, cycles));
+  if (o.relax != pl->mg_relax) KCHK(kfbi_plan_set_box_relaxation(pl, o.relax));
+  return KFBI_OK;
+}
+
+extern "C" kfbi_status kfbi_solve(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* opts_in, double* psi,
                                   double* u_out, kfbi_info* info) {
   KCHK(need_ready(pl));
-  if (!data || !opts || !psi || !data->g2) {
+  if (!data || !opts_in || !psi || !data->g2) {
     kfbi_set_error("NULL argument");
     return KFBI_E_INVALID;
+  }
+  kfbi_opts o = *opts_in;
+  const kfbi_opts* opts = &o;
+  if (o.start < KFBI_START_ZERO || o.start > KFBI_START_LEARNED || o.solver < KFBI_SOLVER_PLAN ||
+      o.solver > KFBI_SOLVER_MG32 || (o.start == KFBI_START_LEARNED && !o.learned)) {
+    kfbi_set_error("opts: start must be KFBI_START_* (learned needs opts->learned), solver KFBI_SOLVER_*");
+    return KFBI_E_INVALID;
+  }
+  if (o.solver != KFBI_SOLVER_PLAN) KCHK(apply_solver(pl, o));
+  if (o.start == KFBI_START_LEARNED) {
+    // the predicted density, on the plan's stream ahead of the solve
+    const kfbi_learned* L = o.learned;
+    KCHK(kfbi_learned_start(pl, L->mlp, L->nb, L->geom, L->jumps, L->scale, psi));
+    o.start = KFBI_START_GIVEN;
   }
   int m = opts->max_iter;
   if (m < 1 || m > KFBI_GMRES_MAX) {

@@ -48,8 +48,27 @@ class Data(ctypes.Structure):
                 ("fhat", c_double_p), ("gB", c_double_p)]
 
 
+class Learned(ctypes.Structure):
+    _fields_ = [("mlp", ctypes.c_void_p), ("nb", ctypes.c_int32), ("geom", ctypes.c_void_p),
+                ("jumps", ctypes.c_void_p), ("scale", ctypes.c_double)]
+
+
 class Opts(ctypes.Structure):
-    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("use_x0", ctypes.c_int32)]
+    _fields_ = [("tol", ctypes.c_double), ("max_iter", ctypes.c_int32), ("start", ctypes.c_int32),
+                ("solver", ctypes.c_int32), ("max_cycles", ctypes.c_int32), ("eps_in", ctypes.c_double),
+                ("relax", ctypes.c_double), ("learned", ctypes.c_void_p)]
+
+
+START = {"zero": 0, "given": 1, "learned": 2}
+SOLVER = {None: 0, "fft": 1, "mg64": 2, "mg32": 3}
+DATA_FN = ctypes.CFUNCTYPE(ctypes.c_int, ctypes.c_void_p, ctypes.c_int, ctypes.c_void_p, ctypes.c_void_p,
+                           ctypes.c_void_p, ctypes.c_void_p)
+
+
+def make_opts(tol, max_iter, start="zero", solver=None, eps_in=0.0, max_cycles=0, relax=0.0, learned=None):
+    """kfbi_opts (learned: a Learned struct, kept alive by the caller)."""
+    return Opts(float(tol), int(max_iter), START[start], SOLVER[solver], int(max_cycles), float(eps_in),
+                float(relax), ctypes.cast(ctypes.pointer(learned), ctypes.c_void_p) if learned is not None else None)
 
 
 class Info(ctypes.Structure):
@@ -78,13 +97,12 @@ ABI = {
     "kfbi_plan_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "kfbi_box_solve_noalloc": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double, c_double_p, c_double_p, ctypes.c_void_p], ctypes.c_int),
-    "kfbi_plan_manufactured_data": ([ctypes.c_void_p, ctypes.c_int] + [ctypes.c_void_p] * 5, ctypes.c_int),
-    "kfbi_batch_create": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_int, ctypes.c_int,
-                           ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "kfbi_batch_create": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)],
+                          ctypes.c_int),
     "kfbi_batch_sizes": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
                          ctypes.c_int),
-    "kfbi_batch_solve": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p],
-                         ctypes.c_int),
+    "kfbi_batch_solve": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                          ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
     "kfbi_batch_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "kfbi_mlp_create": ([ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
                          ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
@@ -312,13 +330,18 @@ class Plan:
         _check(load().kfbi_rhs(self._h, ctypes.byref(ds), _ptr(b)))
         return b
 
-    def solve(self, data, tol=1e-10, max_iter=200, psi0=None, u_out=None, raise_on_fail=True):
-        """Full KFBI solve; returns (psi, u, info dict)."""
+    def solve(self, data, tol=1e-10, max_iter=200, psi0=None, u_out=None, raise_on_fail=True, learned=None,
+              solver=None, eps_in=0.0, max_cycles=0, relax=0.0):
+        """Full KFBI solve; returns (psi, u, info dict).  psi0: initial
+        density; learned: a Learned struct (the start predicted inside the
+        solve); solver ("fft", "mg64", "mg32"; None keeps the plan's) with
+        eps_in, max_cycles and relax set on the plan first."""
         # every entry of psi (from a zero start) and of u is written by the solve
         psi = self._empty(self.n_dof) if psi0 is None else psi0.clone()
         u = self._empty(self.n_nodes) if u_out is None else u_out
         ds = self.data_struct(data)
-        o = Opts(tol, max_iter, 0 if psi0 is None else 1)
+        start = "learned" if learned is not None else ("zero" if psi0 is None else "given")
+        o = make_opts(tol, max_iter, start, solver, eps_in, max_cycles, relax, learned)
         info = Info()
         st = load().kfbi_solve(self._h, ctypes.byref(ds), ctypes.byref(o), _ptr(psi), _ptr(u), ctypes.byref(info))
         if st != 0 and raise_on_fail:
@@ -364,49 +387,36 @@ def device_jump_data(plan, jumps):
             "ftilde": None, "fhat": None, "gB": None}
 
 
-MANU = {"star2d": 1, "torus3d": 2}
-
-
-def manufactured_data(plan, kind):
-    """Manufactured-solution data at the plan's query points, generated on
-    the device (kind "star2d" or "torus3d")."""
-    s = plan.sizes
-    K = plan.prob["n_iface"] if "n_iface" in plan.prob else len(plan.prob["ifaces"])
-    z = lambda n: torch.empty(n, dtype=torch.float64, device=plan.device)
-    d = {"g1": z(s.n_surf), "g2": z(s.n_surf), "ftilde": z(s.n_dof * s.n_pde), "fhat": z((K + 1) * s.n_nodes),
-         "gB": z(s.n_nodes)}
-    _check(load().kfbi_plan_manufactured_data(plan._h, MANU[kind], *[_ptr(d[k]) for k in
-                                                                      ("g1", "g2", "ftilde", "fhat", "gB")]))
-    return d
-
-
 class Batch:
     """Many independent problems solved by a pool of workers (threads with
-    their own streams and plans)."""
+    their own streams and plans); the data of each problem come from a C
+    callback (kfbi_batch_data_fn) once its plan is set up."""
 
-    def __init__(self, probs, kinds, workers=4):
+    def __init__(self, probs, workers=4):
         lib = load()
         self.n = len(probs)
         arr = (Problem * self.n)(*[problem_struct(p) for p in probs])
         self._arr = arr
-        km = (ctypes.c_int * self.n)(*[MANU[k] for k in kinds])
         h = ctypes.c_void_p()
-        _check(lib.kfbi_batch_create(ctypes.cast(arr, ctypes.c_void_p), ctypes.cast(km, ctypes.c_void_p), self.n,
-                                     int(workers), ctypes.byref(h)))
+        _check(lib.kfbi_batch_create(ctypes.cast(arr, ctypes.c_void_p), self.n, int(workers), ctypes.byref(h)))
         self._h = h
         a, b = ctypes.c_int64(), ctypes.c_int64()
         _check(lib.kfbi_batch_sizes(self._h, ctypes.byref(a), ctypes.byref(b)))
         self.total_nodes = b.value
 
-    def solve(self, tol=1e-8, max_iter=300, keep_u=False, raise_on_fail=True):
+    def solve(self, data_fn, ctx, tol=1e-8, max_iter=300, keep_u=False, raise_on_fail=True, **solver):
+        """data_fn: address of a kfbi_batch_data_fn (C function) and ctx its
+        argument; solver: solver / eps_in / max_cycles / relax as in
+        Plan.solve."""
         lib = load()
         u = torch.zeros(self.total_nodes, dtype=torch.float64, device="cuda") if keep_u else None
         infos = (Info * self.n)()
         secs = (ctypes.c_double * self.n)()
-        o = Opts(tol, max_iter, 0)
+        o = make_opts(tol, max_iter, "zero", solver.get("solver"), solver.get("eps_in", 0.0),
+                      solver.get("max_cycles", 0), solver.get("relax", 0.0))
         torch.cuda.synchronize()
-        st = lib.kfbi_batch_solve(self._h, ctypes.byref(o), _ptr(u), ctypes.cast(infos, ctypes.c_void_p),
-                                  ctypes.cast(secs, ctypes.c_void_p))
+        st = lib.kfbi_batch_solve(self._h, ctypes.byref(o), ctypes.c_void_p(data_fn), ctypes.c_void_p(ctx), _ptr(u),
+                                  ctypes.cast(infos, ctypes.c_void_p), ctypes.cast(secs, ctypes.c_void_p))
         if st != 0 and raise_on_fail:
             raise KfbiError(st, lib.kfbi_last_error().decode())
         info = [{"iters": x.iters, "status": x.status, "true_rel_res": x.true_rel_res} for x in infos]

@@ -15,6 +15,7 @@ densities of a_1m, a_2m, b_1m, b_2m:
     model, hist = train(data, epochs=60)          # bf16-MFMA MLP with the linear head, Adam
     psi0 = predict(model, plan, geom, jumps)      # initial density at the DOFs
     plan.solve(jump_data, psi0=psi0)
+    plan.solve(jump_data, learned=learned_args(model, geom, jumps))   # the same, predicted inside the solve
 
 Every numerical step runs in libkfbi.so (solver, SH fit, MLP, head,
 evaluation at the DOFs); this module sequences the calls and holds the
@@ -119,6 +120,15 @@ def predict(model, plan, geom, jumps):
     library call on the plan's stream)."""
     g, j = _pack(geom, jumps, model.mlp.device)
     return learned.learned_start(plan, model.mlp, NB, g, j, model.out_scale)
+
+
+def learned_args(model, geom, jumps):
+    """The kfbi_learned of one ellipsoid problem, for a solve that predicts
+    its own start (Plan.solve(..., learned=...))."""
+    g, j = _pack(geom, jumps, model.mlp.device)
+    L = kfbi.Learned(model.mlp._h, NB, g.data_ptr(), j.data_ptr(), model.out_scale)
+    L._keep = (g, j)
+    return L
 
 
 PRETRAINED = "data/warmstart_ellipsoid128.safetensors"

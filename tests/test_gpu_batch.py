@@ -1,7 +1,10 @@
 """Batched solves of many problems of uneven grid sizes (runs on an MI355X):
-device-generated manufactured data against the host generator, every
-batched solution bitwise equal to the same problem solved alone, parity
-with the oracle, and per-problem failure reporting."""
+the test-data generator library against the host generator, every batched
+density and solution bitwise equal to the same problem solved alone, parity
+with the oracle, the multigrid box solver in the batch, and per-problem
+statuses (unresolved set-up, non-finite data, no convergence)."""
+import ctypes
+
 import numpy as np
 import pytest
 
@@ -39,8 +42,9 @@ def small_batch():
 def test_device_data_matches_host_generator(which):
     from paper_2309_05965_amd import kfbi
     prob, sol = W.config2(128) if which == "star" else W.config3(64)
+    from paper_2309_05965_amd import manufactured as M
     gp = kfbi.Plan(prob)
-    dev = kfbi.manufactured_data(gp, "star2d" if which == "star" else "torus3d")
+    dev = M.plan_data(gp, "star2d" if which == "star" else "torus3d")
     host = kfbi.device_data(gp, prob, sol)
     for k in ("g1", "g2", "ftilde", "fhat", "gB"):
         a, b = dev[k].cpu().numpy().ravel(), host[k].cpu().numpy().ravel()
@@ -52,20 +56,36 @@ def test_device_data_matches_host_generator(which):
         assert np.max(np.abs(a - b)) <= 1e-13 * (1 + np.max(np.abs(b))), k
 
 
-def test_batch_equals_single_solves_bitwise():
+PSI_STRIDE = 20000
+
+
+@pytest.mark.parametrize("solver", [None, "mg32"])
+def test_batch_equals_single_solves_bitwise(solver):
     from paper_2309_05965_amd import kfbi
+    from paper_2309_05965_amd import manufactured as M
     probs, kinds = small_batch()
-    b = kfbi.Batch(probs, kinds, workers=3)
-    u, info, secs = b.solve(tol=1e-8, keep_u=True)
+    gen = M.BatchData(probs, kinds, psi_stride=PSI_STRIDE)
+    b = kfbi.Batch(probs, workers=3)
+    extra = {} if solver is None else {"solver": solver, "eps_in": 1e-10, "max_cycles": 16, "relax": 0.1}
+    u, info, secs = b.solve(gen.fn, gen.ctx, tol=1e-8, keep_u=True, **extra)
     off = 0
-    for p, k, inf in zip(probs, kinds, info):
+    for i, (p, k, inf) in enumerate(zip(probs, kinds, info)):
         n = (p["N"] + 1) ** p["dim"]
         gp = kfbi.Plan(p)
-        d = kfbi.manufactured_data(gp, k)
-        d["ftilde"] = d["ftilde"]
-        _, u1, i1 = gp.solve(d, tol=1e-8)
-        assert inf["status"] == 0 and inf["iters"] == i1["iters"]
-        assert torch.equal(u[off:off + n], u1)
+        d = M.plan_data(gp, k)
+        psi1, u1, i1 = gp.solve(d, tol=1e-8, **extra)
+        psib = gen.psi[i * PSI_STRIDE:i * PSI_STRIDE + gp.n_dof]
+        assert inf["status"] == 0
+        if solver is None:
+            assert inf["iters"] == i1["iters"]
+            assert torch.equal(u[off:off + n], u1)
+            assert torch.equal(psib, psi1)
+        else:
+            # a worker's plan adapts its multigrid caps to the problems it
+            # solved before, a fresh plan does not: equal to the solves'
+            # tolerances, not bitwise
+            assert abs(inf["iters"] - i1["iters"]) <= 1 and inf["true_rel_res"] < 1e-8
+            assert float((psib - psi1).norm() / psi1.norm()) < 1e-7
         off += n
     assert off == b.total_nodes
     assert all(s > 0 for s in secs)
@@ -75,8 +95,10 @@ def test_batch_matches_oracle():
     from paper_2309_05965_amd import kfbi
     probs = [p for p in smooth_stars(6, seed=3) if p["N"] == 64][:2]
     sol = {0: W.f_x2_my3, 1: W.f_cos2x_expy}
-    b = kfbi.Batch(probs, ["star2d"] * len(probs), workers=2)
-    u, info, _ = b.solve(tol=1e-13, keep_u=True)
+    from paper_2309_05965_amd import manufactured as M
+    gen = M.BatchData(probs, ["star2d"] * len(probs))
+    b = kfbi.Batch(probs, workers=2)
+    u, info, _ = b.solve(gen.fn, gen.ctx, tol=1e-13, keep_u=True)
     off = 0
     for p in probs:
         op = okfbi.Plan(p)
@@ -92,7 +114,72 @@ def test_batch_reports_failures_per_problem():
     from paper_2309_05965_amd import kfbi
     good = W.config2(64)[0]
     bad = W.problem(2, 4, 16, -1.0, 1.0, 1.0, 1.0, 0.0, [W.star2d(0.0, 0.0, 0.5, None, [0, 0, 0, 0, 0, 0, 0.3, 0])])
-    b = kfbi.Batch([good, bad, good], ["star2d"] * 3, workers=2)
-    _, info, _ = b.solve(tol=1e-8, raise_on_fail=False)
+    from paper_2309_05965_amd import manufactured as M
+    gen = M.BatchData([good, bad, good], ["star2d"] * 3)
+    b = kfbi.Batch([good, bad, good], workers=2)
+    _, info, _ = b.solve(gen.fn, gen.ctx, tol=1e-8, raise_on_fail=False)
     assert info[0]["status"] == 0 and info[2]["status"] == 0
-    assert info[1]["status"] != 0
+    assert info[1]["status"] != 0                         # the set-up's status
+
+
+def py_data_fn(probs, kinds, nan_in):
+    """A kfbi_batch_data_fn written in Python: the generator's data in
+    tensors of its own, with a NaN in g1 at the first primary point of the
+    problems in nan_in (tensors kept alive in the returned dict)."""
+    from paper_2309_05965_amd import kfbi
+    from paper_2309_05965_amd import manufactured as M
+    g, lib = M.load(), kfbi.load()
+    keep = {}
+
+    def fn(ctx, problem, plan, stream, data_p, psi_p):
+        try:
+            p = probs[problem]
+            sz = kfbi.Sizes()
+            if lib.kfbi_plan_sizes(ctypes.c_void_p(plan), ctypes.byref(sz)) != 0:
+                return 1
+            with torch.cuda.stream(torch.cuda.ExternalStream(stream)):
+                z = lambda n: torch.empty(n, dtype=torch.float64, device="cuda")
+                d = {"g1": z(sz.n_surf), "g2": z(sz.n_surf), "ftilde": z(sz.n_dof * sz.n_pde),
+                     "fhat": z((len(p["ifaces"]) + 1) * sz.n_nodes), "gB": z(sz.n_nodes)}
+                ps = kfbi.problem_struct(p)
+                st = g.kfbi_gen_plan_data(ctypes.c_void_p(plan), ctypes.byref(ps), M.KIND[kinds[problem]],
+                                          ctypes.c_void_p(stream),
+                                          *[kfbi._ptr(d[k]) for k in ("g1", "g2", "ftilde", "fhat", "gB")])
+                if st != 0:
+                    return st
+                if problem in nan_in:
+                    ds = torch.empty(sz.n_dof, dtype=torch.int32, device="cuda")
+                    if lib.kfbi_plan_export(ctypes.c_void_p(plan), kfbi.EXPORT["dof_surf"],
+                                            ctypes.c_void_p(ds.data_ptr()), 4 * sz.n_dof) != 0:
+                        return 1
+                    d["g1"][ds[:1].long()] = float("nan")
+            keep[problem] = d
+            data = ctypes.cast(data_p, ctypes.POINTER(kfbi.Data)).contents
+            for k in ("g1", "g2", "ftilde", "fhat", "gB"):
+                setattr(data, k, d[k].data_ptr())
+            ctypes.cast(psi_p, ctypes.POINTER(ctypes.c_void_p))[0] = None
+            return 0
+        except Exception as e:                      # noqa: BLE001 -- reported as a failed problem
+            print("data callback:", e, flush=True)
+            return 1
+
+    return kfbi.DATA_FN(fn), keep
+
+
+def test_batch_statuses_nonfinite_and_not_converged():
+    """Caller data from a Python callback: a NaN in one problem's g1 gives
+    KFBI_E_NONFINITE for that problem only; max_iter = 1 at tol 1e-14 gives
+    KFBI_E_NOT_CONVERGED for every problem."""
+    from paper_2309_05965_amd import kfbi
+    probs = [W.config2(64)[0]] * 3
+    kinds = ["star2d"] * 3
+    b = kfbi.Batch(probs, workers=2)
+    cb, keep = py_data_fn(probs, kinds, nan_in={1})
+    fp = ctypes.cast(cb, ctypes.c_void_p).value
+    _, info, _ = b.solve(fp, 0, tol=1e-8, raise_on_fail=False)
+    print([i["status"] for i in info], flush=True)
+    assert [i["status"] for i in info] == [0, 5, 0]
+    cb2, keep2 = py_data_fn(probs, kinds, nan_in=set())
+    _, info, _ = b.solve(ctypes.cast(cb2, ctypes.c_void_p).value, 0, tol=1e-14, max_iter=1, raise_on_fail=False)
+    assert [i["status"] for i in info] == [4, 4, 4]
+    assert all(i["iters"] == 1 for i in info)

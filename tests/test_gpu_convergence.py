@@ -19,7 +19,8 @@ def max_error(N):
     prob, sol = W.config3(N)
     print("torus + sphere", N, flush=True)
     gp = kfbi.Plan(prob)
-    data = kfbi.manufactured_data(gp, "torus3d")
+    from paper_2309_05965_amd import manufactured as M
+    data = M.plan_data(gp, "torus3d")
     psi, u, info = gp.solve(data, tol=1e-11, max_iter=300)
     assert info["status"] == 0
     reg = gp.export("region").cpu().numpy().reshape((N + 1,) * 3)

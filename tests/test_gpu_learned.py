@@ -313,6 +313,9 @@ def test_pretrained_warm_start_gains_on_heldout_seeds():
             _, _, il = plan.solve(d, tol=1e-8, psi0=p0)
             torch.cuda.synchronize()
             best_l = min(best_l, time.perf_counter() - t)
+            # the same start predicted inside the solve (kfbi_opts)
+            psi_o, _, io = plan.solve(d, tol=1e-8, learned=warmstart.learned_args(model, geom, jmp))
+            assert io["iters"] == il["iters"] and io["status"] == 0
         assert il["status"] == 0 and il["true_rel_res"] < 2e-8
         zero.append(iz["iters"])
         learn.append(il["iters"])
