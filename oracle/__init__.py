@@ -7,19 +7,39 @@ reference that the HIP library is checked against.  Only the test-suite,
 import it; the product path never does, and it shares no code with the HIP
 library.
 
-Modules
-  levelset     level-set functions H and their gradients (Sec. 5.1)
-  geometry     node regions, surface points, collocation stencils,
-               irregular nodes, closest-centre map, interpolation blocks
-               (Secs. 5.1, 5.2, 5.3, 5.5)
-  collocation  local Cauchy problem by square collocation (Secs. 5.3.1, 5.4)
+Modules and their pins (tests/test_oracle_*.py, run with -m "not gpu")
+  levelset     level-set functions H and their gradients (Sec. 5.1); pinned
+               by the closed-form normals and curvatures of the sample tests
+               and the exact intersections of the geometry tests
+  geometry     node regions, surface points, collocation stencils, density
+               extension, irregular nodes, closest-centre map, interpolation
+               blocks, correction entries (Secs. 5.1, 5.2, 5.3, 5.5); pinned
+               by the paper's printed N_b, brute-force closest centres,
+               extension exactness on polynomials, and (two interfaces) the
+               polynomial patch test of the whole simple solve
+  collocation  local Cauchy problem by square collocation (Secs. 5.3.1, 5.4);
+               pinned by exact reproduction of polynomials
   fd           compact finite-difference operators and the DST box solve
-               (Sec. 5.2, eqs. 9p-cds / 27p-cds; FFT solver of Alg. 1 Step 3.3)
+               (Sec. 5.2, eqs. 9p-cds / 27p-cds; Alg. 1 Step 3.3); pinned by
+               the printed stencil coefficients, exactness on quintics, sine
+               eigenmodes and sparse-LU solves
   kfbi         simple interface solve, BIE operator, GMRES, full solve
-               (Secs. 3.2, 4, 5.5, Alg. 1)
+               (Secs. 3.2, 4, 5.5, Alg. 1); pinned by patch tests (one and
+               two interfaces), A = I/2 for equal coefficients, a dense
+               brute-force BIE, GMRES against a dense solve and the 2nd/4th
+               order convergence rates
+  mg           two-grid multigrid box solver (a textbook method, not in the
+               paper; its converged result is A_h^-1 F); pinned by the
+               transfer identities, the Jacobi weight against the Fourier
+               symbol, the per-cycle contraction and the converged result
+               against the exact sine-transform solve within its bound
+  learned      learned initial density (features, spherical harmonics,
+               MLP with bf16 rounding, linear head, Adam); pinned by closed
+               forms, quadrature orthonormality, exact band-limited
+               transfers and coefficient recovery, bf16 tie cases, finite
+               differences of every gradient and the published Adam update
 
-Every readings of the paper that the oracle takes where the paper is silent
-is listed in the repository design notes; each function cites the passage it
-follows.  Parity status: every function is pinned by a ``-m "not gpu"`` test
-(see tests/test_oracle_*.py); none is "parity unpinned".
+Every reading of the paper that the oracle takes where the paper is silent
+is stated beside the code that takes it; each function cites the passage it
+follows.  Every function above is pinned by one of those tests.
 """

@@ -42,19 +42,18 @@ def main():
     data = kfbi.device_jump_data(plan, jmp)
     plan.set_box_solver(a.solver, eps_in=a.eps, max_cycles=a.max_cycles)
     plan.set_box_relaxation(a.relax if a.solver != "fft" else 0.0)
-    model = S = None
+    model = None
     if a.learned:
-        from . import learned, warmstart
+        from . import warmstart
         model = warmstart.load_pretrained()
-        S = learned.samples()
 
     def solve():
         t0 = time.perf_counter()
         plan.setup(prob)
         torch.cuda.synchronize()
         t1 = time.perf_counter()
-        psi0 = warmstart.predict(model, plan, geom, jmp, S) if a.learned else None
-        _, _, info = plan.solve(data, tol=a.tol, psi0=psi0)
+        la = warmstart.learned_args(model, geom, jmp) if a.learned else None
+        _, _, info = plan.solve(data, tol=a.tol, learned=la)
         torch.cuda.synchronize()
         return t1 - t0, time.perf_counter() - t1, info
 

@@ -184,3 +184,32 @@ def test_mode_rows_give_the_jump_on_the_ellipsoid():
     for m in range(8):
         for t in range(4):
             assert mm[4 * m + t] == j[8 * t + m]
+
+
+def test_linear_head_rows_gradient_matches_finite_differences():
+    """R = 2 rows per example: the loss's gradient against central
+    differences, and the head of an example equal to the head applied to
+    its two rows' outputs written side by side."""
+    rng = np.random.default_rng(7)
+    widths = (4, 6, 6)                  # 2 rows x 6 outputs = 3 basis vectors of 4
+    Ws = [rng.standard_normal((a, b)) * 0.5 for a, b in zip(widths[:-1], widths[1:])]
+    bs = [rng.standard_normal(b) * 0.1 for b in widths[1:]]
+    X = rng.standard_normal((6, 4))     # 3 examples of 2 rows
+    C = rng.standard_normal((3, 3))
+    Yt = rng.standard_normal((3, 4))
+    loss, gW, _ = L.mlp_lin_loss_grad(Ws, bs, X, C, Yt, emulate=False, R=2)
+    eps = 1e-6
+    for l, (i, j) in ((0, (1, 2)), (1, (5, 4)), (1, (0, 0))):
+        Wp = [w.copy() for w in Ws]
+        Wm = [w.copy() for w in Ws]
+        Wp[l][i, j] += eps
+        Wm[l][i, j] -= eps
+        fd = (L.mlp_lin_loss_grad(Wp, bs, X, C, Yt, emulate=False, R=2)[0]
+              - L.mlp_lin_loss_grad(Wm, bs, X, C, Yt, emulate=False, R=2)[0]) / (2 * eps)
+        assert abs(fd - gW[l][i, j]) <= 1e-6 * (1 + abs(fd))
+    out = L.mlp_forward(Ws, bs, X, emulate=False)[0][-1]
+    b = 1
+    z = np.concatenate([out[2 * b], out[2 * b + 1]])
+    y = sum(C[b, jj] * z[4 * jj:4 * jj + 4] for jj in range(3))
+    d = y - Yt[b]
+    assert loss > np.sum(d * d) / Yt.size - 1e-15
