@@ -243,32 +243,40 @@ def run_form(ho, warm, timed, tol, solver, eps, relax, learned_start, keep_u=Fal
     return timed / el, its, trs, psis, U
 
 
-def smoothing_roofline(prob, N, solver):
-    """Average duration of the finest-level post-smoothing sweep of the
-    multigrid V-cycle (HIP events on the plan's stream around the two
-    sweeps of every V-cycle of eager box solves, every correction active)."""
+# HBM traffic of one active coarse sine-transform pass on the 64^3 coarse grid
+# of a 128^3 box (FETCH_SIZE x 2 + WRITE_SIZE x 1 per dispatch, the factors
+# read off a plain 256 MiB copy; profiles/mg_kernels_torus128_256_hbm_counters.md)
+COARSE_PASS_TRAFFIC_128 = 4.39e6
+
+
+def coarse_pass_roofline(prob, N, solver):
+    """Average duration of a pass of the multigrid's exact coarse solve (the
+    kernel that takes the most time in both forms; HIP events on the plan's
+    stream around the five passes of every cycle of eager box solves, every
+    correction active).  Algorithmic bytes: one FP64 read and one FP64
+    write of each interior coarse node per pass."""
     import torch
     from paper_2309_05965_amd import kfbi
     plan = kfbi.Plan(prob)
     plan.set_box_solver(solver, eps_in=1e-30, max_cycles=8)     # all 8 corrections active
     F = torch.randn(plan.n_nodes, dtype=torch.float64, device="cuda")
     plan.box_solve(F)
-    plan.profile(2)
+    plan.profile(3)
     for _ in range(10):
         plan.box_solve(F)
     ivals, launches, ms = plan.timing()
     plan.profile(False)
     plan.close()
-    es = 4 if solver == "mg32" else 8
-    bytes_per_launch = 3 * es * (N - 1) ** 3          # read u and f, write u' at every interior node
+    nc = N // 2
+    bytes_per_launch = 16 * (nc - 1) ** 3
     avg_s = ms / 1e3 / launches
     achieved = bytes_per_launch / avg_s / 1e9
-    return {"kernel": "k_sweep3 smoothing sweep, finest level (%s)" % ("FP32" if es == 4 else "FP64"),
+    return {"kernel": "k_dst coarse sine-transform pass, %d^3 coarse grid of the %d^3 multigrid (FP64)" % (nc, N),
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": None, "avg_launch_us": avg_s * 1e6,
-            "algorithmic_bytes_per_launch": bytes_per_launch,
-            "timing": "HIP events around the two finest-level post-smoothing sweeps of %d V-cycles (%d launches) "
-                      "of eager box solves after the timed region" % (ivals, launches)}
+            "frac": achieved / HBM_PEAK_GBS, "traffic": COARSE_PASS_TRAFFIC_128 if N == 128 else None,
+            "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_per_launch,
+            "timing": "HIP events around the %d coarse solves (%d launches) of 10 eager box solves after the "
+                      "timed region" % (ivals, launches)}
 
 
 def forms_config5_ingredients(ho, warm, timed, tol):
@@ -401,7 +409,7 @@ def main():
     dpsi = max(float(((a - b).norm() / b.norm()).item()) for a, b in zip(psi_m, psi_p))
     del U_m, U_p
     torch.cuda.empty_cache()
-    roof = smoothing_roofline(ho.items[0][1], N, "mg32")
+    roof = coarse_pass_roofline(ho.items[0][1], N, "mg32")
 
     out = {
         "metric": METRIC,

@@ -329,9 +329,12 @@ kfbi_status kfbi_solve(kfbi_plan* plan, const kfbi_data* data, const kfbi_opts* 
 
 /* Event timing of the box-solve kernels (tracing aid).  With enable = 1
  * every subsequent FFT box solve of the plan is bracketed by two HIP events
- * on the plan's stream; with enable = 2 the two post-smoothing sweeps of the
- * finest level of every multigrid V-cycle are (eager box solves only, not
- * the captured GMRES iterations).  kfbi_plan_timing synchronises the stream
+ * on the plan's stream; with enable = 2 the finest-level post-smoothing
+ * sweeps of every multigrid cycle that are not fused with the update (one
+ * on 3D grids up to 128^3, two otherwise), with enable = 3 the passes of
+ * every cycle's exact coarse solve (five in 3D, three in 2D); modes 2 and 3
+ * trace the multigrid solves outside GMRES iterations, which are then
+ * enqueued kernel by kernel instead of as graphs.  kfbi_plan_timing synchronises the stream
  * and returns the number of bracketed intervals and kernel launches
  * recorded since enabling and their total elapsed milliseconds (launches
  * are back to back, so ms / launches is the average launch duration).

@@ -7,6 +7,11 @@ N^d grid, sets the box solver (fft, mg64 or mg32; multigrid to --eps) and
 runs --solves box solves of a seeded random right-hand side after one
 untimed solve.  Prints one JSON line: ms per box solve (host clock around
 the timed solves), multigrid corrections and relative residual reached.
+
+    python -m paper_2309_05965_amd.boxbench --copy-mib 256
+
+instead runs three plain device copies of that many MiB (the reference
+kernel that scales the memory counters of a profile to bytes).
 """
 import argparse
 import json
@@ -26,7 +31,17 @@ def main():
     ap.add_argument("--eps", type=float, default=1e-10)
     ap.add_argument("--max-cycles", type=int, default=14)
     ap.add_argument("--solves", type=int, default=5)
+    ap.add_argument("--copy-mib", type=int, default=0)
     a = ap.parse_args()
+    if a.copy_mib:
+        n = a.copy_mib * (1 << 20) // 4
+        src = torch.ones(n, dtype=torch.float32, device="cuda")
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        print(json.dumps({"copy_mib": a.copy_mib, "copies": 3}), flush=True)
+        return
     prob = (W.config3(a.N) if a.dim == 3 else W.config2(a.N))[0]
     plan = kfbi.Plan(prob)
     plan.set_box_solver(a.solver, eps_in=a.eps, max_cycles=a.max_cycles)

@@ -1283,7 +1283,7 @@ extern "C" kfbi_status kfbi_plan_profile(kfbi_plan* pl, int enable) {
     }
   }
   pl->prof_launches = 0;
-  pl->prof_on = enable == 2 ? 2 : (enable ? 1 : 0);
+  pl->prof_on = enable == 2 || enable == 3 ? enable : (enable ? 1 : 0);
   return KFBI_OK;
 }
 

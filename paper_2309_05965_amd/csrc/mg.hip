@@ -971,6 +971,26 @@ void sweep(kfbi_plan* pl, Ctl ctl, int N, const TS* c27, TS coef, const TS* src,
 // the fused kernels cover 3D grids up to 128^3 (partial sums and tile counts)
 inline bool fused_path(const kfbi_plan* pl) { return pl->g.d == 3 && pl->g.N <= 128; }
 
+// the exact FP64 solve of the coarse grid (tracing aid, profile mode 3:
+// events around its passes in eager box solves)
+void coarse_solve(kfbi_plan* pl, Ctl ctl, hipStream_t st) {
+  const GridDesc& gc = pl->mg_gc;
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  if (pl->prof_on == 3 && pl->prof_ev && !pl->ctl_active) {
+    if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess)
+      (void)hipEventRecord(e0, st);
+    else
+      e0 = e1 = nullptr;
+  }
+  dst_solve_grid(gc, pl->mg_twc, pl->mg_eigc, pl->mg_T1c, pl->mg_T2c, pl->mg_Fc, pl->mg_Uc, ctl.gctl, ctl.mctl, st);
+  if (e0 && e1) {
+    (void)hipEventRecord(e1, st);
+    pl->prof_ev->push_back(e0);
+    pl->prof_ev->push_back(e1);
+    pl->prof_launches += gc.d == 3 ? 5 : 3;
+  }
+}
+
 // one two-grid cycle with the update v += e folded into the last smoothing
 // sweep (3D, N <= 128: the whole-tile sweeps)
 template <typename T>
@@ -985,7 +1005,7 @@ void vcycle_fused(kfbi_plan* pl, const Lev<T>& L, Ctl ctl, double* v) {
   sweep<T, T, SW_RESID>(pl, ctl, L.N, L.c, L.coef, u, f, tb);
   hipLaunchKernelGGL((k_restrict<T>), dim3(gsblk(mc)), dim3(MG_BLOCK), 0, st, ctl, L, gc.N, gc.n1, (const T*)tb,
                      pl->mg_Fc);
-  dst_solve_grid(gc, pl->mg_twc, pl->mg_eigc, pl->mg_T1c, pl->mg_T2c, pl->mg_Fc, pl->mg_Uc, ctl.gctl, ctl.mctl, st);
+  coarse_solve(pl, ctl, st);
   {
     const int m = L.N - 1;
     const dim3 grid((m + 63) / 64, (m + 3) / 4, (m + 3) / 4);
@@ -1021,7 +1041,7 @@ void vcycle(kfbi_plan* pl, const Lev<T>& L, Ctl ctl) {
   sweep<T, T, SW_RESID>(pl, ctl, L.N, L.c, L.coef, u, f, tb);
   hipLaunchKernelGGL((k_restrict<T>), dim3(gsblk(mc)), dim3(MG_BLOCK), 0, st, ctl, L, gc.N, gc.n1, (const T*)tb,
                      pl->mg_Fc);
-  dst_solve_grid(gc, pl->mg_twc, pl->mg_eigc, pl->mg_T1c, pl->mg_T2c, pl->mg_Fc, pl->mg_Uc, ctl.gctl, ctl.mctl, st);
+  coarse_solve(pl, ctl, st);
   hipLaunchKernelGGL((k_prolong<T>), dim3(gsblk(mf)), dim3(MG_BLOCK), 0, st, ctl, L, gc.n1,
                      (const double*)pl->mg_Uc, u);
   // tracing aid (profile mode 2, eager solves only): events around the
@@ -1272,12 +1292,12 @@ void mg_graphs_clear(kfbi_plan* pl) {
 // A solve is a few hundred short kernels whose launches cost more than
 // their work on small grids: it goes out as one graph, captured on first
 // use.  Inside a capture of the caller's (or with the tracing events of
-// profile mode 2) the kernels are enqueued as they are.
+// profile modes 2 and 3) the kernels are enqueued as they are.
 void mg_solve(kfbi_plan* pl, const double* F, double* v) {
   hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
   const hipStream_t st = pl->stream;
   // (the default streams cannot be captured)
-  if (pl->mg_graphs_off || pl->prof_on == 2 || st == nullptr || st == hipStreamLegacy || st == hipStreamPerThread ||
+  if (pl->mg_graphs_off || pl->prof_on >= 2 || st == nullptr || st == hipStreamLegacy || st == hipStreamPerThread ||
       hipStreamIsCapturing(st, &cs) != hipSuccess || cs != hipStreamCaptureStatusNone) {
     solve_enqueue(pl, F, v);
     return;

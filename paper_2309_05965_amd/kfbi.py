@@ -264,7 +264,8 @@ class Plan:
     # ------------------------------------------------------------------ tracing
     def profile(self, enable=True):
         """Start (or stop) HIP-event timing of the box-solve kernels: True or
-        1 the FFT box solves, 2 the finest-level multigrid smoothing sweeps."""
+        1 the FFT box solves, 2 the finest-level multigrid smoothing sweeps,
+        3 the passes of the multigrid's exact coarse solve."""
         _check(load().kfbi_plan_profile(self._h, int(enable)))
 
     def timing(self):
