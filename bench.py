@@ -358,8 +358,11 @@ def forms_config3(tol, N):
 def forms_batch(workers=(1, 8)):
     """The 512-problem batch of random stars (N in {64, 128, 256, 512},
     beta_in log-uniform 1e-2..1e2): solved problems per second over the
-    whole batch (stars under-resolved on their grid fail in set-up, as the
-    oracle's set-up reports them, and are not counted as solved)."""
+    whole batch, set-up and data generation included (stars the grid does
+    not resolve fail in set-up, as the oracle's set-up reports them, and are
+    not counted as solved).  Set up, then solve (a plan per problem, the data
+    generated at every plan's query points) and streaming (a plan per grid
+    shape per worker, the data from the generator's callback)."""
     import torch
     from paper_2309_05965_amd import kfbi
     from paper_2309_05965_amd import manufactured as M
@@ -369,16 +372,36 @@ def forms_batch(workers=(1, 8)):
     out = {}
     for w in workers:
         b = kfbi.Batch(probs, workers=w)
-        b.solve(gen.fn, gen.ctx, tol=1e-8, raise_on_fail=False)
+        b.solve_stream(gen.fn, gen.ctx, tol=1e-8, raise_on_fail=False)
         torch.cuda.synchronize()
         t0 = time.perf_counter()
-        _, info, _ = b.solve(gen.fn, gen.ctx, tol=1e-8, raise_on_fail=False)
+        _, info, _ = b.solve_stream(gen.fn, gen.ctx, tol=1e-8, raise_on_fail=False)
         torch.cuda.synchronize()
         el = time.perf_counter() - t0
         ok = sum(1 for i in info if i["status"] == 0)
-        out["workers_%d" % w] = {"solved_per_s": ok / el, "solved": ok, "unresolved": len(probs) - ok,
-                                 "wall_s": el}
+        out["stream_workers_%d" % w] = {"solved_per_s": ok / el, "solved": ok, "unresolved": len(probs) - ok,
+                                        "wall_s": el}
         b.close()
+        for rep in range(2):
+            b = kfbi.Batch(probs, workers=w)
+            torch.cuda.synchronize()
+            t0 = time.perf_counter()
+            b.setup()
+            t1 = time.perf_counter()
+            plans = [b.plan(i) for i in range(len(probs))]
+            data = [M.plan_data(pl, "star2d") if pl is not None else None for pl in plans]
+            torch.cuda.synchronize()
+            t2 = time.perf_counter()
+            _, info, _ = b.solve(data, tol=1e-8, raise_on_fail=False)
+            torch.cuda.synchronize()
+            t3 = time.perf_counter()
+            ok = sum(1 for i in info if i["status"] == 0)
+            if rep == 1:
+                out["setup_then_solve_workers_%d" % w] = {
+                    "solved_per_s": ok / (t3 - t0), "solved": ok, "wall_s": t3 - t0, "setup_s": t1 - t0,
+                    "data_s": t2 - t1, "solve_s": t3 - t2}
+            del plans, data
+            b.close()
     return out
 
 

@@ -184,6 +184,8 @@ kfbi_status kfbi_plan_create(const kfbi_problem* prob, void* stream, kfbi_plan**
 kfbi_status kfbi_plan_setup(kfbi_plan* plan, const kfbi_problem* prob);
 
 kfbi_status kfbi_plan_sizes(const kfbi_plan* plan, kfbi_sizes* out);
+/* The stream the plan orders its work on (the one it was created with). */
+kfbi_status kfbi_plan_stream(const kfbi_plan* plan, void** stream);
 
 /* Copy a plan table to caller memory (device pointer, `bytes` available).
  * Layouts (int32 unless stated):
@@ -345,42 +347,67 @@ kfbi_status kfbi_plan_timing(kfbi_plan* plan, int64_t* solves, int64_t* launches
 kfbi_status kfbi_plan_destroy(kfbi_plan* plan);
 
 /* ----------------------------------------------------------------------
- * Many independent problems (batched solves, Alg. 1 per problem).
+ * Many independent problems (batched solves, Alg. 1 per problem).  Two
+ * ways to give the data, both with n_workers host threads that each own a
+ * stream and take problems largest first:
+ *   set up, then solve: kfbi_batch_setup builds one plan per problem;
+ *     the caller reads each plan's query points (kfbi_batch_plan, then
+ *     kfbi_plan_sizes / kfbi_plan_export) and passes every problem's
+ *     kfbi_data and density buffer to kfbi_batch_solve;
+ *   streaming: kfbi_batch_solve_stream keeps one plan per grid shape per
+ *     worker, sets it up for each problem in turn and asks a callback for
+ *     the problem's data (memory bounded by the workers, not the batch).
  * -------------------------------------------------------------------- */
 typedef struct kfbi_batch kfbi_batch;
 
-/* Data of one problem, supplied by the caller once a worker's plan is set
- * up for it (its query points are then known: kfbi_plan_sizes,
- * kfbi_plan_export).  Called on the worker's host thread; work the callback
- * enqueues must go on `stream` (the worker's stream, which is the plan's).
- * It fills *data with device arrays laid out as kfbi_data for that plan,
- * which must stay valid until the same worker calls it again or the batch
- * solve returns, and sets *psi_out to a device array of n_dof doubles for
- * the problem's density (the initial guess too with KFBI_START_GIVEN), or
- * to NULL to discard it.  A status other than KFBI_OK fails the problem
- * with that status. */
-typedef kfbi_status (*kfbi_batch_data_fn)(void* ctx, int problem, kfbi_plan* plan, void* stream, kfbi_data* data,
-                                          double** psi_out);
-
-/* A batch of n problems (copied), solved by n_workers (1..16) host
- * threads, each with its own stream and one plan per grid shape (created
- * on first use, set up again for every problem).  Device of the calling
- * thread. */
+/* A batch of n problems (copied) with n_workers (1..16) workers.  Device
+ * of the calling thread. */
 kfbi_status kfbi_batch_create(const kfbi_problem* probs, int n, int n_workers, kfbi_batch** out);
 /* Number of problems and sum of their node counts (the length of u_all). */
 kfbi_status kfbi_batch_sizes(const kfbi_batch* batch, int64_t* n_problems, int64_t* total_nodes);
-/* Solve every problem with opts (box solver, tolerance, start; a learned
- * start is per problem and is rejected here): workers take problems in
- * order of decreasing node count, set up the plan, ask data_fn(ctx, ...)
- * for the data and solve.  u_all (device, may be NULL): the solutions
- * concatenated in problem order, (N_i+1)^d values each.  infos (host, [n])
- * and seconds (host, [n], may be NULL: wall time of each problem on its
- * worker, set-up and data included) are filled for every problem; a problem
- * whose set-up fails (e.g. KFBI_E_UNRESOLVED) is skipped with that status.
- * Returns KFBI_OK only if every problem is OK, else the first failure's
- * status with its message. */
-kfbi_status kfbi_batch_solve(kfbi_batch* batch, const kfbi_opts* opts, kfbi_batch_data_fn data_fn, void* ctx,
+
+/* S0 + S1 of every problem, one plan each (kept until kfbi_batch_destroy;
+ * a plan is ordered on the stream of the worker that built it).  infos
+ * (host, [n], may be NULL): status of each set-up in .status (e.g.
+ * KFBI_E_UNRESOLVED for a geometry the grid does not resolve); seconds
+ * (host, [n], may be NULL): wall time of each set-up.  Returns KFBI_OK if
+ * every set-up succeeded, else the first failure's status with its
+ * message; the other problems are set up all the same.  Waits for the
+ * device. */
+kfbi_status kfbi_batch_setup(kfbi_batch* batch, kfbi_info* infos, double* seconds);
+/* The plan of problem i after kfbi_batch_setup (owned by the batch; NULL
+ * with the set-up's status if it failed). */
+kfbi_status kfbi_batch_plan(kfbi_batch* batch, int i, kfbi_plan** plan);
+/* Solve every set-up problem with opts (box solver, tolerance, start; a
+ * learned start is per problem and is rejected here), on the worker and
+ * stream that set it up: data [n] (host array of kfbi_data with device
+ * arrays at each plan's query points), psi [n] (host array of device
+ * arrays of n_dof doubles: the density out, and the initial guess with
+ * KFBI_START_GIVEN; psi or an entry may be NULL to discard it), u_all
+ * (device, may be NULL): the solutions concatenated in problem order,
+ * (N_i+1)^d values each.  infos (host, [n]) and seconds (host, [n], may be
+ * NULL) are filled for every problem (a problem whose set-up failed keeps
+ * that status).  Returns KFBI_OK only if every problem is OK, else the
+ * first failure's status with its message.  Waits for the device. */
+kfbi_status kfbi_batch_solve(kfbi_batch* batch, const kfbi_opts* opts, const kfbi_data* data, double* const* psi,
                              double* u_all, kfbi_info* infos, double* seconds);
+
+/* Streaming data: once a worker's plan is set up for a problem (its query
+ * points are then known: kfbi_plan_sizes, kfbi_plan_export), the callback
+ * is called on the worker's host thread with the plan and its stream; work
+ * it enqueues must go on that stream.  It fills *data with device arrays
+ * laid out as kfbi_data for that plan, which must stay valid until the same
+ * worker calls it again or the solve returns, and sets *psi_out to a device
+ * array of n_dof doubles for the problem's density (the initial guess too
+ * with KFBI_START_GIVEN), or to NULL to discard it.  A status other than
+ * KFBI_OK fails the problem with that status. */
+typedef kfbi_status (*kfbi_batch_data_fn)(void* ctx, int problem, kfbi_plan* plan, void* stream, kfbi_data* data,
+                                          double** psi_out);
+/* Set up and solve every problem, streaming (see above): u_all, infos and
+ * seconds as in kfbi_batch_solve (seconds include the set-up and the
+ * callback).  Independent of kfbi_batch_setup's plans. */
+kfbi_status kfbi_batch_solve_stream(kfbi_batch* batch, const kfbi_opts* opts, kfbi_batch_data_fn data_fn, void* ctx,
+                                    double* u_all, kfbi_info* infos, double* seconds);
 kfbi_status kfbi_batch_destroy(kfbi_batch* batch);
 
 /* ----------------------------------------------------------------------

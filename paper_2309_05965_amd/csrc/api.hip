@@ -649,6 +649,15 @@ extern "C" kfbi_status kfbi_plan_sizes(const kfbi_plan* pl, kfbi_sizes* out) {
   return KFBI_OK;
 }
 
+extern "C" kfbi_status kfbi_plan_stream(const kfbi_plan* pl, void** stream) {
+  if (!pl || !stream) {
+    kfbi_set_error("NULL argument");
+    return KFBI_E_INVALID;
+  }
+  *stream = (void*)pl->stream;
+  return KFBI_OK;
+}
+
 extern "C" kfbi_status kfbi_plan_destroy(kfbi_plan* pl) {
   if (!pl) return KFBI_OK;
   std::shared_lock<std::shared_mutex> lock(kfbi_capture_mutex);

@@ -1,15 +1,17 @@
 // Step S9 -- many independent interface problems of uneven grid sizes.
 //
 // A batch owns a pool of workers.  Each worker is a host thread with its
-// own HIP stream (default priority) and one plan per grid shape it has
-// met; the workers pull problems from a shared counter in order of
-// decreasing node count (largest first, so the tail of the batch is made
-// of small problems), re-run S0 + S1 on the plan for the problem's
-// geometry, take the problem's data from the caller's callback (the query
-// points are known only after the set-up) and run the whole solve
-// (Alg. 1) on their stream.  Host-side waits of one worker (compaction
-// counts, GMRES convergence checks) overlap with the other workers'
-// kernels, so several problems share the GPU at every moment.
+// own HIP stream (default priority); the workers pull problems from a
+// shared counter in order of decreasing node count (largest first, so the
+// tail of the batch is made of small problems).  Host-side waits of one
+// worker (compaction counts, GMRES convergence checks) overlap with the
+// other workers' kernels, so several problems share the GPU at every
+// moment.  Set-up then solve: kfbi_batch_setup builds a plan per problem
+// (on the worker's stream), the caller fills the data at the plans' query
+// points, and kfbi_batch_solve runs every problem on the worker that set
+// it up.  Streaming: each worker keeps one plan per grid shape, re-runs
+// S0 + S1 on it for every problem and takes the data from the caller's
+// callback.
 #include <math.h>
 
 #include <algorithm>
@@ -59,7 +61,56 @@ struct kfbi_batch {
   std::vector<int64_t> u_off;
   std::vector<Worker> workers;
   int device = 0;
+  // set up, then solve: one plan per problem, the worker that built it,
+  // the set-up's status
+  std::vector<kfbi_plan*> pplan;
+  std::vector<int> owner;
+  std::vector<kfbi_status> pstat;
+  bool setup_done = false;
 };
+
+namespace {
+// largest problems first
+std::vector<int> work_order(const kfbi_batch* b) {
+  const int n = (int)b->probs.size();
+  std::vector<int> order(n);
+  for (int i = 0; i < n; ++i) order[i] = i;
+  std::stable_sort(order.begin(), order.end(),
+                   [&](int x, int y) { return b->u_off[x + 1] - b->u_off[x] > b->u_off[y + 1] - b->u_off[y]; });
+  return order;
+}
+
+// run fn(worker index, worker) on every worker's thread (the caller's
+// thread is worker 0)
+template <class F>
+void on_workers(kfbi_batch* b, F fn) {
+  std::vector<std::thread> th;
+  for (size_t i = 1; i < b->workers.size(); ++i) th.emplace_back([&, i] {
+    (void)hipSetDevice(b->device);
+    fn((int)i, b->workers[i]);
+  });
+  (void)hipSetDevice(b->device);
+  fn(0, b->workers[0]);
+  for (auto& t : th) t.join();
+}
+
+struct FirstError {
+  std::mutex mu;
+  std::string msg;
+  kfbi_status st = KFBI_OK;
+  void note(int p, kfbi_status s) {
+    std::lock_guard<std::mutex> g(mu);
+    if (st == KFBI_OK) {
+      st = s;
+      msg = "problem " + std::to_string(p) + ": " + kfbi_last_error();
+    }
+  }
+  kfbi_status done() {
+    if (st != KFBI_OK) kfbi_set_error("%s", msg.c_str());
+    return st;
+  }
+};
+}  // namespace
 
 extern "C" kfbi_status kfbi_batch_create(const kfbi_problem* probs, int n, int n_workers, kfbi_batch** out) {
   if (!probs || !out || n < 1 || n_workers < 1 || n_workers > 16) {
@@ -99,8 +150,108 @@ extern "C" kfbi_status kfbi_batch_sizes(const kfbi_batch* b, int64_t* n_problems
   return KFBI_OK;
 }
 
-extern "C" kfbi_status kfbi_batch_solve(kfbi_batch* b, const kfbi_opts* opts, kfbi_batch_data_fn data_fn, void* ctx,
+extern "C" kfbi_status kfbi_batch_setup(kfbi_batch* b, kfbi_info* infos, double* seconds) {
+  if (!b) {
+    kfbi_set_error("batch is NULL");
+    return KFBI_E_INVALID;
+  }
+  const int n = (int)b->probs.size();
+  for (kfbi_plan* pl : b->pplan)
+    if (pl) kfbi_plan_destroy(pl);
+  b->pplan.assign(n, nullptr);
+  b->owner.assign(n, 0);
+  b->pstat.assign(n, KFBI_E_INVALID);
+  const std::vector<int> order = work_order(b);
+  std::atomic<int> next(0);
+  FirstError fe;
+  on_workers(b, [&](int wi, Worker& w) {
+    for (;;) {
+      const int k = next.fetch_add(1);
+      if (k >= n) break;
+      const int p = order[k];
+      auto t0 = std::chrono::steady_clock::now();
+      kfbi_plan* pl = nullptr;
+      kfbi_status st = kfbi_plan_create(&b->probs[p], (void*)w.stream, &pl);
+      if (st == KFBI_OK && hipStreamSynchronize(w.stream) != hipSuccess) st = KFBI_E_DEVICE;
+      if (st != KFBI_OK) {
+        fe.note(p, st);
+        if (pl) kfbi_plan_destroy(pl);
+        pl = nullptr;
+      }
+      b->pplan[p] = pl;
+      b->owner[p] = wi;
+      b->pstat[p] = st;
+      if (infos) infos[p] = kfbi_info{0, st, 0.0, 0.0};
+      if (seconds) seconds[p] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+    }
+  });
+  b->setup_done = true;
+  return fe.done();
+}
+
+extern "C" kfbi_status kfbi_batch_plan(kfbi_batch* b, int i, kfbi_plan** out) {
+  if (!b || !out || i < 0 || i >= (int)b->probs.size() || !b->setup_done) {
+    kfbi_set_error("batch plan needs a set-up batch, a problem index and an output");
+    return KFBI_E_INVALID;
+  }
+  *out = b->pplan[i];
+  if (!*out) kfbi_set_error("problem %d did not set up", i);
+  return b->pstat[i];
+}
+
+extern "C" kfbi_status kfbi_batch_solve(kfbi_batch* b, const kfbi_opts* opts, const kfbi_data* data, double* const* psi,
                                         double* u_all, kfbi_info* infos, double* seconds) {
+  if (!b || !opts || !data || !infos || !b->setup_done) {
+    kfbi_set_error("batch solve needs a set-up batch, options, the data and an info array");
+    return KFBI_E_INVALID;
+  }
+  if (opts->start == KFBI_START_LEARNED || (opts->start == KFBI_START_GIVEN && !psi)) {
+    kfbi_set_error("batch solve: a learned start is per problem (kfbi_solve); a given start needs psi");
+    return KFBI_E_INVALID;
+  }
+  const int n = (int)b->probs.size();
+  const std::vector<int> order = work_order(b);
+  FirstError fe;
+  on_workers(b, [&](int wi, Worker& w) {
+    for (int p : order) {
+      if (b->owner[p] != wi) continue;
+      auto t0 = std::chrono::steady_clock::now();
+      kfbi_info info{0, b->pstat[p], 0.0, 0.0};
+      kfbi_status st = b->pstat[p];
+      kfbi_plan* pl = b->pplan[p];
+      const int64_t nn = b->u_off[p + 1] - b->u_off[p];
+      double* ps = psi ? psi[p] : nullptr;
+      if (st == KFBI_OK && !ps) {
+        if (opts->start == KFBI_START_GIVEN) {
+          kfbi_set_error("KFBI_START_GIVEN needs the initial density of problem %d", p);
+          st = KFBI_E_INVALID;
+        } else {
+          std::shared_lock<std::shared_mutex> lock(kfbi_capture_mutex);
+          st = grow(&w.psi, &w.c_psi, pl->n_dof);
+          ps = w.psi;
+        }
+      }
+      if (st == KFBI_OK && !u_all) {
+        std::shared_lock<std::shared_mutex> lock(kfbi_capture_mutex);
+        st = grow(&w.u, &w.c_u, nn);
+      }
+      if (st == KFBI_OK) {
+        hipStream_t ps_st = pl->stream;
+        st = kfbi_solve(pl, &data[p], opts, ps, u_all ? u_all + b->u_off[p] : w.u, &info);
+        if (hipStreamSynchronize(ps_st) != hipSuccess && st == KFBI_OK) st = KFBI_E_DEVICE;
+      }
+      info.status = st;
+      infos[p] = info;
+      if (seconds) seconds[p] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+      if (st != KFBI_OK) fe.note(p, st);
+    }
+  });
+  (void)n;
+  return fe.done();
+}
+
+extern "C" kfbi_status kfbi_batch_solve_stream(kfbi_batch* b, const kfbi_opts* opts, kfbi_batch_data_fn data_fn,
+                                               void* ctx, double* u_all, kfbi_info* infos, double* seconds) {
   if (!b || !opts || !data_fn || !infos) {
     kfbi_set_error("batch solve needs a batch, options, a data callback and an info array");
     return KFBI_E_INVALID;
@@ -182,6 +333,10 @@ extern "C" kfbi_status kfbi_batch_destroy(kfbi_batch* b) {
       if (kv.second) kfbi_plan_destroy(kv.second);
     for (double* p : {w.psi, w.u})
       if (p) (void)hipFree(p);
+  }
+  for (kfbi_plan* pl : b->pplan)
+    if (pl) kfbi_plan_destroy(pl);
+  for (auto& w : b->workers) {
     if (w.stream) (void)hipStreamDestroy(w.stream);
   }
   delete b;

@@ -103,6 +103,11 @@ ABI = {
                          ctypes.c_int),
     "kfbi_batch_solve": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
                           ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "kfbi_batch_solve_stream": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p,
+                                 ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "kfbi_batch_setup": ([ctypes.c_void_p, ctypes.c_void_p, ctypes.c_void_p], ctypes.c_int),
+    "kfbi_batch_plan": ([ctypes.c_void_p, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
+    "kfbi_plan_stream": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
     "kfbi_batch_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "kfbi_mlp_create": ([ctypes.c_int, ctypes.POINTER(ctypes.c_int), ctypes.c_void_p,
                          ctypes.POINTER(ctypes.c_void_p)], ctypes.c_int),
@@ -215,6 +220,23 @@ class Plan:
             raise KfbiError(st, msg)
         self._sizes()
 
+    @classmethod
+    def view(cls, handle, prob, device="cuda"):
+        """A plan owned by someone else (a batch's): sizes, exports and
+        solves, not destroyed on close."""
+        self = cls.__new__(cls)
+        self.device = torch.device(device)
+        st = ctypes.c_void_p()
+        _check(load().kfbi_plan_stream(ctypes.c_void_p(handle), ctypes.byref(st)))
+        self.stream = torch.cuda.ExternalStream(st.value, device=self.device) if st.value else \
+            torch.cuda.default_stream(self.device)
+        self.prob = prob
+        self._p = problem_struct(prob)
+        self._h = ctypes.c_void_p(handle)
+        self._owned = False
+        self._sizes()
+        return self
+
     def _sizes(self):
         s = Sizes()
         _check(load().kfbi_plan_sizes(self._h, ctypes.byref(s)))
@@ -229,7 +251,7 @@ class Plan:
         self._sizes()
 
     def close(self):
-        if getattr(self, "_h", None) is not None and self._h.value:
+        if getattr(self, "_h", None) is not None and self._h.value and getattr(self, "_owned", True):
             load().kfbi_plan_destroy(self._h)
         self._h = ctypes.c_void_p()
 
@@ -293,6 +315,8 @@ class Plan:
         nbytes = out.numel() * out.element_size()
         _check(load().kfbi_plan_export(self._h, EXPORT[name], ctypes.c_void_p(out.data_ptr() if nbytes else 0),
                                        nbytes))
+        # the copy is ordered on the plan's stream: order torch's after it
+        torch.cuda.current_stream(self.device).wait_stream(self.stream)
         return out
 
     def _zeros(self, n):
@@ -390,11 +414,15 @@ def device_jump_data(plan, jumps):
 
 class Batch:
     """Many independent problems solved by a pool of workers (threads with
-    their own streams and plans); the data of each problem come from a C
-    callback (kfbi_batch_data_fn) once its plan is set up."""
+    their own streams).  Set up, then solve: setup() builds a plan per
+    problem, plan(i) gives it (for its query points), solve(data, psi)
+    takes every problem's data.  Streaming: solve_stream(fn, ctx) takes
+    each problem's data from a C callback (kfbi_batch_data_fn) once a
+    worker's plan is set up for it."""
 
     def __init__(self, probs, workers=4):
         lib = load()
+        self.probs = list(probs)
         self.n = len(probs)
         arr = (Problem * self.n)(*[problem_struct(p) for p in probs])
         self._arr = arr
@@ -405,23 +433,55 @@ class Batch:
         _check(lib.kfbi_batch_sizes(self._h, ctypes.byref(a), ctypes.byref(b)))
         self.total_nodes = b.value
 
-    def solve(self, data_fn, ctx, tol=1e-8, max_iter=300, keep_u=False, raise_on_fail=True, **solver):
-        """data_fn: address of a kfbi_batch_data_fn (C function) and ctx its
-        argument; solver: solver / eps_in / max_cycles / relax as in
-        Plan.solve."""
+    def setup(self):
+        """S0 + S1 of every problem; returns the statuses and seconds."""
+        infos = (Info * self.n)()
+        secs = (ctypes.c_double * self.n)()
+        load().kfbi_batch_setup(self._h, ctypes.cast(infos, ctypes.c_void_p), ctypes.cast(secs, ctypes.c_void_p))
+        return [x.status for x in infos], list(secs)
+
+    def plan(self, i):
+        """Problem i's plan (a view owned by the batch), or None if its
+        set-up failed."""
+        h = ctypes.c_void_p()
+        st = load().kfbi_batch_plan(self._h, int(i), ctypes.byref(h))
+        return Plan.view(h.value, self.probs[i]) if st == 0 and h.value else None
+
+    def _opts(self, tol, max_iter, solver):
+        return make_opts(tol, max_iter, "zero", solver.get("solver"), solver.get("eps_in", 0.0),
+                         solver.get("max_cycles", 0), solver.get("relax", 0.0))
+
+    def _run(self, call, keep_u, raise_on_fail):
         lib = load()
         u = torch.zeros(self.total_nodes, dtype=torch.float64, device="cuda") if keep_u else None
         infos = (Info * self.n)()
         secs = (ctypes.c_double * self.n)()
-        o = make_opts(tol, max_iter, "zero", solver.get("solver"), solver.get("eps_in", 0.0),
-                      solver.get("max_cycles", 0), solver.get("relax", 0.0))
         torch.cuda.synchronize()
-        st = lib.kfbi_batch_solve(self._h, ctypes.byref(o), ctypes.c_void_p(data_fn), ctypes.c_void_p(ctx), _ptr(u),
-                                  ctypes.cast(infos, ctypes.c_void_p), ctypes.cast(secs, ctypes.c_void_p))
+        st = call(_ptr(u), ctypes.cast(infos, ctypes.c_void_p), ctypes.cast(secs, ctypes.c_void_p))
         if st != 0 and raise_on_fail:
             raise KfbiError(st, lib.kfbi_last_error().decode())
         info = [{"iters": x.iters, "status": x.status, "true_rel_res": x.true_rel_res} for x in infos]
         return u, info, list(secs)
+
+    def solve(self, data, psi=None, tol=1e-8, max_iter=300, keep_u=False, raise_on_fail=True, **solver):
+        """data: per problem a dict of device tensors as Plan.solve takes
+        (None for a problem that did not set up); psi: per problem a device
+        tensor for the density, or None."""
+        ds = (Data * self.n)(*[Plan.data_struct(d) if d is not None else Data() for d in data])
+        pp = (ctypes.c_void_p * self.n)(*[(p.data_ptr() if p is not None else None) for p in (psi or [None] * self.n)])
+        o = self._opts(tol, max_iter, solver)
+        return self._run(lambda u, i, s: load().kfbi_batch_solve(self._h, ctypes.byref(o), ctypes.cast(ds, ctypes.c_void_p),
+                                                                 ctypes.cast(pp, ctypes.c_void_p), u, i, s),
+                         keep_u, raise_on_fail)
+
+    def solve_stream(self, data_fn, ctx, tol=1e-8, max_iter=300, keep_u=False, raise_on_fail=True, **solver):
+        """data_fn: address of a kfbi_batch_data_fn (C function) and ctx its
+        argument; solver: solver / eps_in / max_cycles / relax as in
+        Plan.solve."""
+        o = self._opts(tol, max_iter, solver)
+        return self._run(lambda u, i, s: load().kfbi_batch_solve_stream(self._h, ctypes.byref(o), ctypes.c_void_p(data_fn),
+                                                                        ctypes.c_void_p(ctx), u, i, s),
+                         keep_u, raise_on_fail)
 
     def close(self):
         if getattr(self, "_h", None):

@@ -47,6 +47,7 @@ def plan_data(plan, kind):
                                    ctypes.c_void_p(plan.stream.cuda_stream),
                                    *[kfbi._ptr(d[k]) for k in ("g1", "g2", "ftilde", "fhat", "gB")])
     kfbi._check(st)
+    torch.cuda.current_stream(plan.device).wait_stream(plan.stream)
     return d
 
 

@@ -56,7 +56,16 @@ def test_device_data_matches_host_generator(which):
         assert np.max(np.abs(a - b)) <= 1e-13 * (1 + np.max(np.abs(b))), k
 
 
-PSI_STRIDE = 20000
+def batch_data(b, probs, kinds):
+    """Set up the batch and generate every problem's data at its plan's
+    query points; returns (plans, data, psi buffers)."""
+    from paper_2309_05965_amd import manufactured as M
+    st, _ = b.setup()
+    plans = [b.plan(i) for i in range(len(probs))]
+    data = [M.plan_data(pl, k) if pl is not None else None for pl, k in zip(plans, kinds)]
+    psi = [torch.empty(pl.n_dof, dtype=torch.float64, device="cuda") if pl is not None else None for pl in plans]
+    torch.cuda.synchronize()
+    return st, plans, data, psi
 
 
 @pytest.mark.parametrize("solver", [None, "mg32"])
@@ -64,30 +73,53 @@ def test_batch_equals_single_solves_bitwise(solver):
     from paper_2309_05965_amd import kfbi
     from paper_2309_05965_amd import manufactured as M
     probs, kinds = small_batch()
-    gen = M.BatchData(probs, kinds, psi_stride=PSI_STRIDE)
     b = kfbi.Batch(probs, workers=3)
+    st, plans, data, psi = batch_data(b, probs, kinds)
+    assert st == [0] * len(probs)
     extra = {} if solver is None else {"solver": solver, "eps_in": 1e-10, "max_cycles": 16, "relax": 0.1}
-    u, info, secs = b.solve(gen.fn, gen.ctx, tol=1e-8, keep_u=True, **extra)
+    u, info, secs = b.solve(data, psi, tol=1e-8, keep_u=True, **extra)
     off = 0
     for i, (p, k, inf) in enumerate(zip(probs, kinds, info)):
         n = (p["N"] + 1) ** p["dim"]
         gp = kfbi.Plan(p)
         d = M.plan_data(gp, k)
         psi1, u1, i1 = gp.solve(d, tol=1e-8, **extra)
-        psib = gen.psi[i * PSI_STRIDE:i * PSI_STRIDE + gp.n_dof]
         assert inf["status"] == 0
         if solver is None:
             assert inf["iters"] == i1["iters"]
             assert torch.equal(u[off:off + n], u1)
-            assert torch.equal(psib, psi1)
+            assert torch.equal(psi[i], psi1)
         else:
-            # a worker's plan adapts its multigrid caps to the problems it
-            # solved before, a fresh plan does not: equal to the solves'
-            # tolerances, not bitwise
+            # the batch's plans and the fresh one start from different
+            # multigrid caps: equal to the solves' tolerances, not bitwise
             assert abs(inf["iters"] - i1["iters"]) <= 1 and inf["true_rel_res"] < 1e-8
-            assert float((psib - psi1).norm() / psi1.norm()) < 1e-7
+            assert float((psi[i] - psi1).norm() / psi1.norm()) < 1e-7
         off += n
     assert off == b.total_nodes
+    assert all(s > 0 for s in secs)
+
+
+PSI_STRIDE = 20000
+
+
+def test_streaming_batch_equals_single_solves_bitwise():
+    """The streaming mode (one plan per grid shape per worker, data from
+    the generator library's callback, densities at a fixed stride)."""
+    from paper_2309_05965_amd import kfbi
+    from paper_2309_05965_amd import manufactured as M
+    probs, kinds = small_batch()
+    gen = M.BatchData(probs, kinds, psi_stride=PSI_STRIDE)
+    b = kfbi.Batch(probs, workers=3)
+    u, info, secs = b.solve_stream(gen.fn, gen.ctx, tol=1e-8, keep_u=True)
+    off = 0
+    for i, (p, k, inf) in enumerate(zip(probs, kinds, info)):
+        n = (p["N"] + 1) ** p["dim"]
+        gp = kfbi.Plan(p)
+        psi1, u1, i1 = gp.solve(M.plan_data(gp, k), tol=1e-8)
+        assert inf["status"] == 0 and inf["iters"] == i1["iters"]
+        assert torch.equal(u[off:off + n], u1)
+        assert torch.equal(gen.psi[i * PSI_STRIDE:i * PSI_STRIDE + gp.n_dof], psi1)
+        off += n
     assert all(s > 0 for s in secs)
 
 
@@ -95,10 +127,9 @@ def test_batch_matches_oracle():
     from paper_2309_05965_amd import kfbi
     probs = [p for p in smooth_stars(6, seed=3) if p["N"] == 64][:2]
     sol = {0: W.f_x2_my3, 1: W.f_cos2x_expy}
-    from paper_2309_05965_amd import manufactured as M
-    gen = M.BatchData(probs, ["star2d"] * len(probs))
     b = kfbi.Batch(probs, workers=2)
-    u, info, _ = b.solve(gen.fn, gen.ctx, tol=1e-13, keep_u=True)
+    _, _, data, psi = batch_data(b, probs, ["star2d"] * len(probs))
+    u, info, _ = b.solve(data, psi, tol=1e-13, keep_u=True)
     off = 0
     for p in probs:
         op = okfbi.Plan(p)
@@ -112,14 +143,37 @@ def test_batch_matches_oracle():
 
 def test_batch_reports_failures_per_problem():
     from paper_2309_05965_amd import kfbi
+    from paper_2309_05965_amd import manufactured as M
     good = W.config2(64)[0]
     bad = W.problem(2, 4, 16, -1.0, 1.0, 1.0, 1.0, 0.0, [W.star2d(0.0, 0.0, 0.5, None, [0, 0, 0, 0, 0, 0, 0.3, 0])])
-    from paper_2309_05965_amd import manufactured as M
-    gen = M.BatchData([good, bad, good], ["star2d"] * 3)
-    b = kfbi.Batch([good, bad, good], workers=2)
-    _, info, _ = b.solve(gen.fn, gen.ctx, tol=1e-8, raise_on_fail=False)
+    probs = [good, bad, good]
+    b = kfbi.Batch(probs, workers=2)
+    st, plans, data, psi = batch_data(b, probs, ["star2d"] * 3)
+    assert st[0] == 0 and st[2] == 0 and st[1] != 0 and plans[1] is None
+    _, info, _ = b.solve(data, psi, tol=1e-8, raise_on_fail=False)
     assert info[0]["status"] == 0 and info[2]["status"] == 0
-    assert info[1]["status"] != 0                         # the set-up's status
+    assert info[1]["status"] == st[1]                     # the set-up's status
+    gen = M.BatchData(probs, ["star2d"] * 3)
+    _, info, _ = kfbi.Batch(probs, workers=2).solve_stream(gen.fn, gen.ctx, tol=1e-8, raise_on_fail=False)
+    assert info[0]["status"] == 0 and info[2]["status"] == 0 and info[1]["status"] == st[1]
+
+
+def test_batch_statuses_nonfinite_and_not_converged():
+    """A NaN in one problem's g1 (at a primary point) gives
+    KFBI_E_NONFINITE for that problem only; max_iter = 1 at tol 1e-14 gives
+    KFBI_E_NOT_CONVERGED for every problem."""
+    from paper_2309_05965_amd import kfbi
+    probs = [W.config2(64)[0]] * 3
+    b = kfbi.Batch(probs, workers=2)
+    _, plans, data, psi = batch_data(b, probs, ["star2d"] * 3)
+    good = data[1]["g1"].clone()
+    data[1]["g1"][plans[1].export("dof_surf")[:1].long()] = float("nan")
+    _, info, _ = b.solve(data, psi, tol=1e-8, raise_on_fail=False)
+    assert [i["status"] for i in info] == [0, 5, 0]
+    data[1]["g1"].copy_(good)
+    _, info, _ = b.solve(data, psi, tol=1e-14, max_iter=1, raise_on_fail=False)
+    assert [i["status"] for i in info] == [4, 4, 4]
+    assert all(i["iters"] == 1 for i in info)
 
 
 def py_data_fn(probs, kinds, nan_in):
@@ -166,20 +220,14 @@ def py_data_fn(probs, kinds, nan_in):
     return kfbi.DATA_FN(fn), keep
 
 
-def test_batch_statuses_nonfinite_and_not_converged():
-    """Caller data from a Python callback: a NaN in one problem's g1 gives
-    KFBI_E_NONFINITE for that problem only; max_iter = 1 at tol 1e-14 gives
-    KFBI_E_NOT_CONVERGED for every problem."""
+def test_streaming_statuses_from_a_python_callback():
+    """Caller data from a Python callback in the streaming mode: a NaN in
+    one problem's g1 gives KFBI_E_NONFINITE for that problem only."""
     from paper_2309_05965_amd import kfbi
     probs = [W.config2(64)[0]] * 3
     kinds = ["star2d"] * 3
     b = kfbi.Batch(probs, workers=2)
     cb, keep = py_data_fn(probs, kinds, nan_in={1})
     fp = ctypes.cast(cb, ctypes.c_void_p).value
-    _, info, _ = b.solve(fp, 0, tol=1e-8, raise_on_fail=False)
-    print([i["status"] for i in info], flush=True)
+    _, info, _ = b.solve_stream(fp, 0, tol=1e-8, raise_on_fail=False)
     assert [i["status"] for i in info] == [0, 5, 0]
-    cb2, keep2 = py_data_fn(probs, kinds, nan_in=set())
-    _, info, _ = b.solve(ctypes.cast(cb2, ctypes.c_void_p).value, 0, tol=1e-14, max_iter=1, raise_on_fail=False)
-    assert [i["status"] for i in info] == [4, 4, 4]
-    assert all(i["iters"] == 1 for i in info)
