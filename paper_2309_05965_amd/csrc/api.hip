@@ -274,9 +274,8 @@ kfbi_status alloc_fixed(kfbi_plan* pl) {
     return KFBI_E_OOM;
   }
   KCHK(dalloc(&pl->ctl, 8));
-  HIPCHK(hipStreamCreateWithFlags(&pl->gstream, hipStreamNonBlocking));
-  HIPCHK(hipEventCreateWithFlags(&pl->ev_in, hipEventDisableTiming));
-  HIPCHK(hipEventCreateWithFlags(&pl->ev_out, hipEventDisableTiming));
+  // the private stream of solves on a default stream and its two events
+  // are made on first use (a stream costs about 1.5 ms to create)
   return KFBI_OK;
 }
 
@@ -1214,6 +1213,193 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
 }
 }  // namespace
 
+// ---------------------------------------------------------------- solves of a group in lockstep
+kfbi_status apply_solver(kfbi_plan* pl, const kfbi_opts& o);
+
+namespace {
+__global__ void k_group_open(int* const* ctls, int G, int* open) {
+  __shared__ int cnt;
+  if (threadIdx.x == 0) cnt = 0;
+  __syncthreads();
+  for (int p = threadIdx.x; p < G; p += blockDim.x)
+    if (!ctls[p][1]) atomicAdd(&cnt, 1);
+  __syncthreads();
+  if (threadIdx.x == 0) *open = cnt;
+}
+
+// per problem: done, k, |r_k| estimate, |b|, breakdown flag, true residual sums
+__global__ void k_group_state(int* const* ctls, double* const* scals, int G, double* out) {
+  const int p = blockIdx.x * blockDim.x + threadIdx.x;
+  if (p >= G) return;
+  const int* c = ctls[p];
+  const double* s = scals[p];
+  double* o = out + 8 * (int64_t)p;
+  o[0] = c[1];
+  o[1] = c[2];
+  o[2] = s[0];
+  o[3] = s[1];
+  o[4] = s[2];
+  o[5] = s[4];
+  o[6] = s[5];
+  o[7] = 0.0;
+}
+}  // namespace
+
+// Alg. 1 for G problems of one grid shape with the FFT box solver, their
+// GMRES iterations in lockstep: per iteration the interface-dependent
+// kernels of every problem and one launch per box-solve pass for the whole
+// group, captured once as a graph of four iterations; every kernel of a
+// problem that has converged returns at once.  The right-hand sides, the
+// updates, true residuals and final solves are those of kfbi_solve, so
+// every problem's density and solution equal its own solve's bit for bit.
+// All on `st`; the plans' own streams are restored at the end.
+kfbi_status kfbi_solve_group(kfbi_plan* const* pls, int G, const kfbi_data* data, double* const* psi,
+                             double* const* u, const kfbi_opts* opts, hipStream_t st, kfbi_info* infos) {
+  const int m = opts->max_iter;
+  const double tol = opts->tol > 0.0 ? opts->tol : 1e-10;
+  const int use_x0 = opts->start == KFBI_START_GIVEN ? 1 : 0;
+  if (G < 1 || m < 1 || m > KFBI_GMRES_MAX || opts->start == KFBI_START_LEARNED) {
+    kfbi_set_error("group solve: G >= 1, 1 <= max_iter <= %d, no learned start", KFBI_GMRES_MAX);
+    return KFBI_E_INVALID;
+  }
+  for (int p = 0; p < G; ++p) {
+    KCHK(need_ready(pls[p]));
+    if (opts->solver != KFBI_SOLVER_PLAN) KCHK(apply_solver(pls[p], *opts));
+    if (pls[p]->box_solver != KFBI_BOX_FFT || pls[p]->g.N != pls[0]->g.N || pls[p]->g.d != pls[0]->g.d ||
+        pls[p]->g.order != pls[0]->g.order) {
+      kfbi_set_error("group solve: FFT box solver and one grid shape");
+      return KFBI_E_INVALID;
+    }
+    HIPCHK(hipStreamSynchronize(pls[p]->stream));
+    {
+      std::shared_lock<std::shared_mutex> lock(kfbi_capture_mutex);
+      KCHK(ensure_gmres(pls[p], m));
+    }
+  }
+  std::vector<hipStream_t> own(G);
+  for (int p = 0; p < G; ++p) {
+    own[p] = pls[p]->stream;
+    pls[p]->stream = st;
+  }
+  kfbi_status status = KFBI_OK;
+  DstBatch* db = nullptr;
+  int** d_ctl = nullptr;
+  double** d_scal = nullptr;
+  int* d_open = nullptr;
+  double* d_state = nullptr;
+  int* h_open = nullptr;
+  hipGraph_t gr = nullptr;
+  hipGraphExec_t ex = nullptr;
+  std::vector<double> state((size_t)8 * G);
+  auto run = [&]() -> kfbi_status {
+    // steps 1-2 of every problem
+    for (int p = 0; p < G; ++p) {
+      kfbi_plan* pl = pls[p];
+      simple_solve_impl(pl, data[p].g1, nullptr, data[p].ftilde, data[p].fhat, data[p].gB, pl->vsbuf, pl->dn_in,
+                        pl->dn_out);
+      op_bie_rhs(pl, data[p].g2, pl->dn_in, pl->dn_out, pl->bvec);
+      KCHK(set_relax_word(pl, 0.0));
+      if (use_x0) matvec_impl(pl, psi[p], pl->work);
+      gm_residual_start(pl, pl->bvec, pl->work, use_x0, tol, m);
+    }
+    HIPCHK(hipGetLastError());
+    kfbi_status s = KFBI_OK;
+    db = dst_batch_create(pls, G, st, &s);
+    KCHK(s);
+    std::vector<int*> hc(G);
+    std::vector<double*> hs(G);
+    for (int p = 0; p < G; ++p) {
+      hc[p] = pls[p]->ctl;
+      hs[p] = pls[p]->scal;
+    }
+    if (hipMalloc((void**)&d_ctl, sizeof(int*) * G) != hipSuccess ||
+        hipMalloc((void**)&d_scal, sizeof(double*) * G) != hipSuccess ||
+        hipMalloc((void**)&d_open, sizeof(int)) != hipSuccess ||
+        hipMalloc((void**)&d_state, sizeof(double) * 8 * G) != hipSuccess ||
+        hipHostMalloc((void**)&h_open, sizeof(int), 0) != hipSuccess) {
+      (void)hipGetLastError();
+      kfbi_set_error("group solve: device allocation failed");
+      return KFBI_E_OOM;
+    }
+    HIPCHK(hipMemcpyAsync(d_ctl, hc.data(), sizeof(int*) * G, hipMemcpyHostToDevice, st));
+    HIPCHK(hipMemcpyAsync(d_scal, hs.data(), sizeof(double*) * G, hipMemcpyHostToDevice, st));
+    // steps 3-4: four lockstep iterations and the count of open problems,
+    // captured once
+    {
+      std::unique_lock<std::shared_mutex> lock(kfbi_capture_mutex);
+      HIPCHK(hipStreamBeginCapture(st, hipStreamCaptureModeThreadLocal));
+      for (int it = 0; it < 4; ++it) {
+        for (int p = 0; p < G; ++p) {
+          pls[p]->ctl_active = pls[p]->ctl;
+          op_matvec_head(pls[p], nullptr);
+          pls[p]->ctl_active = nullptr;
+        }
+        dst_batch_corrections(db, st);
+        for (int p = 0; p < G; ++p) {
+          pls[p]->ctl_active = pls[p]->ctl;
+          op_matvec_tail(pls[p], nullptr, nullptr);
+          gm_arnoldi(pls[p]);
+          pls[p]->ctl_active = nullptr;
+        }
+      }
+      hipLaunchKernelGGL(k_group_open, dim3(1), dim3(256), 0, st, d_ctl, G, d_open);
+      const hipError_t e = hipStreamEndCapture(st, &gr);
+      if (e != hipSuccess) return kfbi_hip_status(e, "hipStreamEndCapture");
+      const hipError_t e2 = hipGraphInstantiate(&ex, gr, nullptr, nullptr, 0);
+      if (e2 != hipSuccess) return kfbi_hip_status(e2, "hipGraphInstantiate");
+    }
+    for (int launched = 0; launched < m; launched += 4) {
+      HIPCHK(hipGraphLaunch(ex, st));
+      HIPCHK(hipMemcpyAsync(h_open, d_open, sizeof(int), hipMemcpyDeviceToHost, st));
+      HIPCHK(hipStreamSynchronize(st));
+      if (*h_open == 0) break;
+    }
+    // update, true residual and final solve of every problem
+    for (int p = 0; p < G; ++p) {
+      kfbi_plan* pl = pls[p];
+      gm_update_device(pl, psi[p], use_x0);
+      matvec_impl(pl, psi[p], pl->work2);
+      gm_true_residual(pl, pl->bvec, pl->work2, pl->scal + 4);
+      op_extend(pl, psi[p], pl->aS);
+      simple_solve_impl(pl, data[p].g1, pl->aS, data[p].ftilde, data[p].fhat, data[p].gB, u[p], pl->dn_in,
+                        pl->dn_out);
+    }
+    hipLaunchKernelGGL(k_group_state, dim3((G + 255) / 256), dim3(256), 0, st, d_ctl, d_scal, G, d_state);
+    HIPCHK(hipMemcpyAsync(state.data(), d_state, sizeof(double) * 8 * G, hipMemcpyDeviceToHost, st));
+    HIPCHK(hipStreamSynchronize(st));
+    for (int p = 0; p < G; ++p) {
+      const double* o = &state[(size_t)8 * p];
+      GmresOut go;
+      go.k = (int)o[1];
+      const double nb = o[3];
+      go.est = nb == 0.0 ? 0.0 : o[2] / nb;
+      go.conv = o[0] != 0.0 && (nb == 0.0 || o[2] <= tol * nb || o[4] != 0.0);
+      go.spec_ok = false;
+      const double tr = rel_residual(o[5], o[6]);
+      kfbi_info info{0, KFBI_OK, 0.0, 0.0};
+      infos[p].status = solve_report(pls[p], &info, go, go.k, tr, tol, m);
+      infos[p].iters = info.iters;
+      infos[p].est_rel_res = info.est_rel_res;
+      infos[p].true_rel_res = info.true_rel_res;
+    }
+    return KFBI_OK;
+  };
+  status = run();
+  for (int p = 0; p < G; ++p) {
+    pls[p]->ctl_active = nullptr;
+    pls[p]->stream = own[p];
+  }
+  if (ex) (void)hipGraphExecDestroy(ex);
+  if (gr) (void)hipGraphDestroy(gr);
+  dst_batch_destroy(db);
+  if (d_ctl) (void)hipFree(d_ctl);
+  if (d_scal) (void)hipFree(d_scal);
+  if (d_open) (void)hipFree(d_open);
+  if (d_state) (void)hipFree(d_state);
+  if (h_open) (void)hipHostFree(h_open);
+  return status;
+}
+
 // the box solver the options ask for, set on the plan when it differs
 kfbi_status apply_solver(kfbi_plan* pl, const kfbi_opts& o) {
   const int solver = o.solver - 1;
@@ -1262,6 +1448,11 @@ extern "C" kfbi_status kfbi_solve(kfbi_plan* pl, const kfbi_data* data, const kf
   hipStream_t user = pl->stream;
   if (user != nullptr && user != hipStreamLegacy && user != hipStreamPerThread)
     return solve_body(pl, data, opts, psi, u_out, info, m, tol);
+  if (!pl->gstream) {
+    HIPCHK(hipStreamCreateWithFlags(&pl->gstream, hipStreamNonBlocking));
+    HIPCHK(hipEventCreateWithFlags(&pl->ev_in, hipEventDisableTiming));
+    HIPCHK(hipEventCreateWithFlags(&pl->ev_out, hipEventDisableTiming));
+  }
   HIPCHK(hipEventRecord(pl->ev_in, user));
   HIPCHK(hipStreamWaitEvent(pl->gstream, pl->ev_in, 0));
   pl->stream = pl->gstream;

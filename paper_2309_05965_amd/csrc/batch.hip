@@ -199,6 +199,12 @@ extern "C" kfbi_status kfbi_batch_plan(kfbi_batch* b, int i, kfbi_plan** out) {
   return b->pstat[i];
 }
 
+// Problems of one grid shape solved by one worker go in groups of up to
+// GROUP_MAX in lockstep (kfbi_solve_group: one launch per box-solve pass
+// for the whole group) when their box solver is the FFT; others one by
+// one.
+constexpr int GROUP_MAX = 32;
+
 extern "C" kfbi_status kfbi_batch_solve(kfbi_batch* b, const kfbi_opts* opts, const kfbi_data* data, double* const* psi,
                                         double* u_all, kfbi_info* infos, double* seconds) {
   if (!b || !opts || !data || !infos || !b->setup_done) {
@@ -209,44 +215,91 @@ extern "C" kfbi_status kfbi_batch_solve(kfbi_batch* b, const kfbi_opts* opts, co
     kfbi_set_error("batch solve: a learned start is per problem (kfbi_solve); a given start needs psi");
     return KFBI_E_INVALID;
   }
-  const int n = (int)b->probs.size();
   const std::vector<int> order = work_order(b);
+  const bool fft = opts->solver == KFBI_SOLVER_FFT ||
+                   (opts->solver == KFBI_SOLVER_PLAN);   // refined per plan below
   FirstError fe;
   on_workers(b, [&](int wi, Worker& w) {
+    // this worker's problems that set up, grouped by grid shape (largest first)
+    std::map<std::vector<double>, std::vector<int>> groups;
+    std::vector<std::vector<double>> shapes;
     for (int p : order) {
       if (b->owner[p] != wi) continue;
-      auto t0 = std::chrono::steady_clock::now();
-      kfbi_info info{0, b->pstat[p], 0.0, 0.0};
-      kfbi_status st = b->pstat[p];
-      kfbi_plan* pl = b->pplan[p];
-      const int64_t nn = b->u_off[p + 1] - b->u_off[p];
-      double* ps = psi ? psi[p] : nullptr;
-      if (st == KFBI_OK && !ps) {
-        if (opts->start == KFBI_START_GIVEN) {
-          kfbi_set_error("KFBI_START_GIVEN needs the initial density of problem %d", p);
-          st = KFBI_E_INVALID;
-        } else {
+      if (b->pstat[p] != KFBI_OK) {
+        infos[p] = kfbi_info{0, b->pstat[p], 0.0, 0.0};
+        if (seconds) seconds[p] = 0.0;
+        continue;
+      }
+      const std::vector<double> key = shape_key(b->probs[p]);
+      if (!groups.count(key)) shapes.push_back(key);
+      groups[key].push_back(p);
+    }
+    for (const auto& key : shapes) {
+      const std::vector<int>& ps = groups[key];
+      for (size_t c0 = 0; c0 < ps.size(); c0 += GROUP_MAX) {
+        const int G = (int)std::min(ps.size() - c0, (size_t)GROUP_MAX);
+        auto t0 = std::chrono::steady_clock::now();
+        std::vector<kfbi_plan*> pls(G);
+        std::vector<kfbi_data> dat(G);
+        std::vector<double*> pv(G), uv(G);
+        kfbi_status st = KFBI_OK;
+        int64_t npsi = 0, nu = 0;
+        for (int i = 0; i < G; ++i) {
+          const int p = ps[c0 + i];
+          pls[i] = b->pplan[p];
+          dat[i] = data[p];
+          if (!(psi && psi[p])) npsi += pls[i]->n_dof;
+          if (!u_all) nu += b->u_off[p + 1] - b->u_off[p];
+        }
+        {
           std::shared_lock<std::shared_mutex> lock(kfbi_capture_mutex);
-          st = grow(&w.psi, &w.c_psi, pl->n_dof);
-          ps = w.psi;
+          if (npsi > 0) st = grow(&w.psi, &w.c_psi, npsi);
+          if (st == KFBI_OK && nu > 0) st = grow(&w.u, &w.c_u, nu);
+        }
+        int64_t op = 0, ou = 0;
+        for (int i = 0; i < G && st == KFBI_OK; ++i) {
+          const int p = ps[c0 + i];
+          if (psi && psi[p]) {
+            pv[i] = psi[p];
+          } else {
+            pv[i] = w.psi + op;
+            op += pls[i]->n_dof;
+          }
+          if (u_all) {
+            uv[i] = u_all + b->u_off[p];
+          } else {
+            uv[i] = w.u + ou;
+            ou += b->u_off[p + 1] - b->u_off[p];
+          }
+        }
+        bool grouped = st == KFBI_OK && fft && G > 1;
+        for (int i = 0; i < G && grouped; ++i)
+          grouped = (opts->solver == KFBI_SOLVER_FFT) || pls[i]->box_solver == KFBI_BOX_FFT;
+        std::vector<kfbi_info> inf(G, kfbi_info{0, st, 0.0, 0.0});
+        if (st == KFBI_OK && grouped) {
+          st = kfbi_solve_group(pls.data(), G, dat.data(), pv.data(), uv.data(), opts, w.stream, inf.data());
+          if (st != KFBI_OK)
+            for (int i = 0; i < G; ++i)
+              if (inf[i].status == KFBI_OK) inf[i].status = st;
+        } else if (st == KFBI_OK) {
+          for (int i = 0; i < G; ++i) {
+            const kfbi_status si = kfbi_solve(pls[i], &dat[i], opts, pv[i], uv[i], &inf[i]);
+            if (hipStreamSynchronize(pls[i]->stream) != hipSuccess && si == KFBI_OK)
+              inf[i].status = KFBI_E_DEVICE;
+            else
+              inf[i].status = si;
+          }
+        }
+        const double secs = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
+        for (int i = 0; i < G; ++i) {
+          const int p = ps[c0 + i];
+          infos[p] = inf[i];
+          if (seconds) seconds[p] = secs / G;
+          if (inf[i].status != KFBI_OK) fe.note(p, (kfbi_status)inf[i].status);
         }
       }
-      if (st == KFBI_OK && !u_all) {
-        std::shared_lock<std::shared_mutex> lock(kfbi_capture_mutex);
-        st = grow(&w.u, &w.c_u, nn);
-      }
-      if (st == KFBI_OK) {
-        hipStream_t ps_st = pl->stream;
-        st = kfbi_solve(pl, &data[p], opts, ps, u_all ? u_all + b->u_off[p] : w.u, &info);
-        if (hipStreamSynchronize(ps_st) != hipSuccess && st == KFBI_OK) st = KFBI_E_DEVICE;
-      }
-      info.status = st;
-      infos[p] = info;
-      if (seconds) seconds[p] = std::chrono::duration<double>(std::chrono::steady_clock::now() - t0).count();
-      if (st != KFBI_OK) fe.note(p, st);
     }
   });
-  (void)n;
   return fe.done();
 }
 

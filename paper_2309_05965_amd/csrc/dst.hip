@@ -25,6 +25,7 @@
 #include <math.h>
 
 #include <mutex>
+#include <new>
 #include <vector>
 
 #include "kfbi_internal.h"
@@ -385,7 +386,7 @@ size_t tile_lds(int TL, int N) { return sizeof(double2) * 2 * (size_t)(TL / 2) *
 // twiddles and (MODE 1) the 1D eigenvalues -- is issued up front, so the
 // work group waits on HBM once before its FFT stages.
 template <int LOGM, int MODE, bool FS>
-__global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
+__device__ __forceinline__ void dst_pass(const DstArgs& a, const int tile) {
   static_assert(!FS || (LOGM == 10 && MODE == 0), "the four-step FFT is written for M = 1024, one transform");
   // a converged multigrid loop skips most of its coarse solves: tested
   // before any load
@@ -400,9 +401,6 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
   const int TL = a.TL, nf = TL / 2;
   double2* A = lds;                                 // [nf][Mp]
   double2* B = lds + nf * Mp;                       // [nf][Mp]
-  // tiles in XCD-contiguous order (neighbouring tiles share cache lines
-  // along the strided axes)
-  const int tile = kfbi_xcd_block(blockIdx.x, gridDim.x);
   const int w = tile / a.tiles_u + 1;               // remaining interior coordinate (3D)
   const int u0 = 1 + (tile % a.tiles_u) * TL;       // first tile coordinate
   constexpr int nl = N - 1;
@@ -528,14 +526,13 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
 // divides those outputs by the eigenvalues, writes the odd extension of the
 // divided spectrum to LDS and transforms it again.
 template <int MODE>
-__global__ void __launch_bounds__(KFBI_BLOCK) k_dst1024(DstArgs a) {
+__device__ __forceinline__ void dst1024_pass(const DstArgs& a, const int tile) {
   if (a.mctl && a.mctl[0]) return;
   const int stop = a.ctl ? a.ctl[1] : 0;
   constexpr int M = 1024, N = 512, nl = N - 1, Mp = padded_len(M);
   __shared__ double2 S[MODE == 1 ? Mp : 1];   // divided spectrum (MODE 1)
   __shared__ double2 X[Mp];                   // transpose buffer
   const GridDesc& g = a.g;
-  const int tile = kfbi_xcd_block(blockIdx.x, gridDim.x);
   const int w = tile / a.tiles_u + 1;
   const int u0 = 1 + (tile % a.tiles_u) * 2;
   const bool hasB = u0 + 1 <= nl;
@@ -599,6 +596,35 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst1024(DstArgs a) {
     a.out[elem_addr(a, u0, w, k)] = -0.5 * y[q].y;
     if (hasB) a.out[elem_addr(a, u0 + 1, w, k)] = 0.5 * y[q].x;
   }
+}
+
+// Tiles in XCD-contiguous order (neighbouring tiles share cache lines along
+// the strided axes).
+template <int LOGM, int MODE, bool FS>
+__global__ void __launch_bounds__(KFBI_BLOCK) k_dst(DstArgs a) {
+  dst_pass<LOGM, MODE, FS>(a, kfbi_xcd_block(blockIdx.x, gridDim.x));
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(KFBI_BLOCK) k_dst1024(DstArgs a) {
+  dst1024_pass<MODE>(a, kfbi_xcd_block(blockIdx.x, gridDim.x));
+}
+
+// The same pass for several problems of one grid shape in one launch: work
+// group b (in XCD-contiguous order over the whole launch) does tile b mod
+// nbp of problem b / nbp, whose arguments it reads from A.
+template <int LOGM, int MODE, bool FS>
+__global__ void __launch_bounds__(KFBI_BLOCK) k_dstb(const DstArgs* __restrict__ A, int nbp) {
+  const int lb = kfbi_xcd_block(blockIdx.x, gridDim.x);
+  const DstArgs a = A[lb / nbp];
+  dst_pass<LOGM, MODE, FS>(a, lb % nbp);
+}
+
+template <int MODE>
+__global__ void __launch_bounds__(KFBI_BLOCK) k_dst1024b(const DstArgs* __restrict__ A, int nbp) {
+  const int lb = kfbi_xcd_block(blockIdx.x, gridDim.x);
+  const DstArgs a = A[lb / nbp];
+  dst1024_pass<MODE>(a, lb % nbp);
 }
 
 // lines per tile: the largest even TL <= 8 whose LDS footprint still lets
@@ -691,7 +717,129 @@ void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out,
   launch_args(a, src_corr, pl->stream);
 }
 
+// the arguments of pass q of the matvec's box solve of pl (as
+// dst_solve_corrections launches them), with the plan's GMRES control word
+DstArgs corrections_args(kfbi_plan* pl, int q) {
+  static const int ax2[3] = {0, 1, 0}, md2[3] = {0, 1, 0};
+  static const int ax3[5] = {0, 1, 2, 1, 0}, md3[5] = {0, 0, 1, 0, 0};
+  DstArgs a{};
+  a.ctl = pl->ctl;
+  a.mctl = nullptr;
+  a.src_corr = q == 0 ? 1 : 0;
+  a.row_start = pl->row_start;
+  a.row_end = pl->row_end;
+  a.irr = pl->irr;
+  a.PE1 = pl->PE1;
+  a.PE2 = pl->PE2;
+  a.PA = pl->PA;
+  a.Cv = pl->Cv;
+  a.Firr = kfbi_irr_rhs_used(pl) ? pl->Firr : nullptr;
+  a.maxpairs = pl->maxpairs;
+  a.g = pl->g;
+  const bool d2 = pl->g.d == 2;
+  a.ax = d2 ? ax2[q] : ax3[q];
+  a.mode = d2 ? md2[q] : md3[q];
+  double* const in2[3] = {nullptr, pl->T1, pl->T2};
+  double* const out2[3] = {pl->T1, pl->T2, pl->vbuf};
+  double* const in3[5] = {nullptr, pl->T1, pl->T2, pl->T1, pl->T2};
+  double* const out3[5] = {pl->T1, pl->T2, pl->T1, pl->T2, pl->vbuf};
+  a.in = d2 ? in2[q] : in3[q];
+  a.out = d2 ? out2[q] : out3[q];
+  a.tw = (const double2*)pl->tw;
+  a.eig1 = pl->eig1;
+  const int N = pl->g.N, nl = N - 1;
+  a.TL = tile_lines(pl->g.d, N);
+  a.tiles_u = (nl + a.TL - 1) / a.TL;
+  a.scale = 1.0;
+  for (int t = 0; t < pl->g.d; ++t) a.scale *= 2.0 / N;
+  return a;
+}
+
+template <int LOGM>
+void launch_tb(const DstArgs& a0, const DstArgs* A, int G, unsigned nbp, size_t lds, hipStream_t st) {
+  const dim3 grid(nbp * (unsigned)G);
+  if constexpr (LOGM == 10) {
+    if (a0.TL == 2 && a0.mode == 0 && a0.src_corr && KFBI_BLOCK == 256) {
+      hipLaunchKernelGGL((k_dstb<10, 0, true>), grid, dim3(KFBI_BLOCK), lds, st, A, (int)nbp);
+      return;
+    }
+  }
+  if (a0.mode == 1)
+    hipLaunchKernelGGL((k_dstb<LOGM, 1, false>), grid, dim3(KFBI_BLOCK), lds, st, A, (int)nbp);
+  else
+    hipLaunchKernelGGL((k_dstb<LOGM, 0, false>), grid, dim3(KFBI_BLOCK), lds, st, A, (int)nbp);
+}
+
+// one pass of G problems of one shape: a0 the host copy of the first
+// problem's arguments (shape, mode, tiles), A the G arguments on the device
+void launch_batched(const DstArgs& a0, const DstArgs* A, int G, hipStream_t st) {
+  const GridDesc& g = a0.g;
+  const int N = g.N, nl = N - 1;
+  const unsigned nbp = (unsigned)(a0.tiles_u * (g.d == 3 ? nl : 1));
+  if (N == 512 && a0.TL == 2 && !a0.src_corr && KFBI_BLOCK == 256) {
+    if (a0.mode == 1)
+      hipLaunchKernelGGL(k_dst1024b<1>, dim3(nbp * (unsigned)G), dim3(KFBI_BLOCK), 0, st, A, (int)nbp);
+    else
+      hipLaunchKernelGGL(k_dst1024b<0>, dim3(nbp * (unsigned)G), dim3(KFBI_BLOCK), 0, st, A, (int)nbp);
+    return;
+  }
+  const size_t lds = tile_lds(a0.TL, N);
+  switch (N) {
+    case 8: launch_tb<4>(a0, A, G, nbp, lds, st); break;
+    case 16: launch_tb<5>(a0, A, G, nbp, lds, st); break;
+    case 32: launch_tb<6>(a0, A, G, nbp, lds, st); break;
+    case 64: launch_tb<7>(a0, A, G, nbp, lds, st); break;
+    case 128: launch_tb<8>(a0, A, G, nbp, lds, st); break;
+    case 256: launch_tb<9>(a0, A, G, nbp, lds, st); break;
+    case 512: launch_tb<10>(a0, A, G, nbp, lds, st); break;
+    default: launch_tb<11>(a0, A, G, nbp, lds, st); break;
+  }
+}
+
 }  // namespace
+
+// Batched matvec box solves of a group of plans of one grid shape (FFT box
+// solver): the arguments of every pass of every plan, on the device.
+struct DstBatch {
+  int G = 0, npass = 0;
+  std::vector<DstArgs> host;   // [npass][G]
+  DstArgs* dev = nullptr;      // [npass][G]
+};
+
+DstBatch* dst_batch_create(kfbi_plan* const* pls, int G, hipStream_t st, kfbi_status* status) {
+  *status = KFBI_OK;
+  DstBatch* b = new (std::nothrow) DstBatch();
+  if (!b) {
+    *status = KFBI_E_OOM;
+    return nullptr;
+  }
+  b->G = G;
+  b->npass = pls[0]->g.d == 2 ? 3 : 5;
+  b->host.resize((size_t)b->npass * G);
+  for (int q = 0; q < b->npass; ++q)
+    for (int p = 0; p < G; ++p) b->host[(size_t)q * G + p] = corrections_args(pls[p], q);
+  if (hipMalloc((void**)&b->dev, sizeof(DstArgs) * b->host.size()) != hipSuccess ||
+      hipMemcpyAsync(b->dev, b->host.data(), sizeof(DstArgs) * b->host.size(), hipMemcpyHostToDevice, st) !=
+          hipSuccess ||
+      hipStreamSynchronize(st) != hipSuccess) {
+    (void)hipGetLastError();
+    kfbi_set_error("device allocation of the batched pass arguments failed");
+    *status = KFBI_E_OOM;
+    dst_batch_destroy(b);
+    return nullptr;
+  }
+  return b;
+}
+
+void dst_batch_corrections(DstBatch* b, hipStream_t st) {
+  for (int q = 0; q < b->npass; ++q) launch_batched(b->host[(size_t)q * b->G], b->dev + (size_t)q * b->G, b->G, st);
+}
+
+void dst_batch_destroy(DstBatch* b) {
+  if (!b) return;
+  if (b->dev) (void)hipFree(b->dev);
+  delete b;
+}
 
 void dst_host_tables(int N, double h, double* tw, double* eig1) {
   const int M = 2 * N;

@@ -262,6 +262,8 @@ void op_normal_derivatives(kfbi_plan* pl, const double* v, double* dn_in, double
                            double* Apsi);
 kfbi_status op_fold(kfbi_plan* pl);
 void op_matvec(kfbi_plan* pl, const double* psi, double* Apsi);
+void op_matvec_head(kfbi_plan* pl, const double* psi);
+void op_matvec_tail(kfbi_plan* pl, const double* psi, double* Apsi);
 void op_bie_rhs(kfbi_plan* pl, const double* g2, const double* dn_in, const double* dn_out,
                 double* b);
 // dst.hip (step S3)
@@ -293,6 +295,18 @@ void mg_store_solution(kfbi_plan* pl, const double* v);
 void mg_guess_from_store(kfbi_plan* pl, int k, int use_x0, const double* y, double* v);
 void mg_sum(kfbi_plan* pl, const double* a, const double* b, double* out);
 void dst_solve_corrections(kfbi_plan* pl, const double* psi, double* v);
+// the matvec box solves of G plans of one grid shape (FFT solver) as one
+// launch per pass; each plan's GMRES control word stops its own work
+struct DstBatch;
+DstBatch* dst_batch_create(kfbi_plan* const* pls, int G, hipStream_t st, kfbi_status* status);
+void dst_batch_corrections(DstBatch* b, hipStream_t st);
+void dst_batch_destroy(DstBatch* b);
+// Alg. 1 for G set-up plans of one grid shape with the FFT box solver,
+// their GMRES iterations in lockstep with batched box-solve passes, on st
+// (api.hip); psi[p] (n_dof) and u[p] ((N+1)^d) device arrays per problem;
+// infos[p] filled for every problem.
+kfbi_status kfbi_solve_group(kfbi_plan* const* pls, int G, const kfbi_data* data, double* const* psi,
+                             double* const* u, const kfbi_opts* opts, hipStream_t st, kfbi_info* infos);
 // gmres.hip (step S6)
 void gm_residual_start(kfbi_plan* pl, const double* b, const double* Ax0, int use_x0, double tol, int maxit);
 void gm_arnoldi(kfbi_plan* pl);

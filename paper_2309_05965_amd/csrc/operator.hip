@@ -979,18 +979,30 @@ void kfbi_stencil_A(const GridDesc& g, double* A27) {
 // side is formed inside the first box-solve pass, the correction values
 // inside the interpolation
 void op_matvec(kfbi_plan* pl, const double* psi, double* Apsi) {
-  if (pl->n_corr > 0)
-    hipLaunchKernelGGL(k_centry<16>, dim3(nb(pl->n_corr * 16)), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_corr,
-                       pl->nF, pl->FI, pl->FW, psi, pl->Cv, pl->ctl_active, pl->V, pl->n_dof);
+  op_matvec_head(pl, psi);
   if (pl->box_solver == KFBI_BOX_FFT) {
-    if (kfbi_irr_rhs_used(pl) && pl->n_irr > 0)
-      hipLaunchKernelGGL(k_irr_rhs, dim3(nb(pl->n_irr * IRR_G)), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_irr,
-                         pl->maxpairs, pl->PA, pl->PE1, pl->PE2, pl->Cv, pl->Firr, pl->ctl_active);
     dst_solve_corrections(pl, psi, pl->vbuf);
   } else {
     mg_matvec_rhs(pl);
     mg_solve(pl, pl->Fmg, pl->vbuf);
   }
+  op_matvec_tail(pl, psi, Apsi);
+}
+
+// the matvec's steps before its box solve: correction values of the
+// density (and, FFT, the corrected right-hand side at the irregular nodes
+// when its pair lists are long)
+void op_matvec_head(kfbi_plan* pl, const double* psi) {
+  if (pl->n_corr > 0)
+    hipLaunchKernelGGL(k_centry<16>, dim3(nb(pl->n_corr * 16)), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_corr,
+                       pl->nF, pl->FI, pl->FW, psi, pl->Cv, pl->ctl_active, pl->V, pl->n_dof);
+  if (pl->box_solver == KFBI_BOX_FFT && kfbi_irr_rhs_used(pl) && pl->n_irr > 0)
+    hipLaunchKernelGGL(k_irr_rhs, dim3(nb(pl->n_irr * IRR_G)), dim3(KFBI_BLOCK), 0, pl->stream, pl->n_irr,
+                       pl->maxpairs, pl->PA, pl->PE1, pl->PE2, pl->Cv, pl->Firr, pl->ctl_active);
+}
+
+// after the box solve: the corrected interpolation and the combination
+void op_matvec_tail(kfbi_plan* pl, const double* psi, double* Apsi) {
   launch_interp(pl, pl->vbuf, nullptr, psi, nullptr, nullptr, Apsi);
 }
 

@@ -99,6 +99,40 @@ def test_batch_equals_single_solves_bitwise(solver):
     assert all(s > 0 for s in secs)
 
 
+def test_lockstep_group_equals_single_solves_bitwise():
+    """Ten stars of one grid (different contrasts, so different iteration
+    counts) on two workers: each worker solves its five in lockstep, one
+    launch per box-solve pass for the group; every density, solution and
+    iteration count equals the problem's own solve."""
+    from paper_2309_05965_amd import kfbi
+    from paper_2309_05965_amd import manufactured as M
+    rng = np.random.default_rng(21)
+    probs = []
+    for i in range(10):
+        a = rng.uniform(0.0, 0.01, 7)
+        ph = rng.uniform(0.0, 2 * np.pi, 7)
+        probs.append(W.problem(2, 4, 128, -1.0, 1.0, 10.0 ** rng.uniform(-2, 2), 1.0, 1.0,
+                               [W.star2d(0.0, 0.0, 0.4, [0.0] + list(a * np.cos(ph)), [0.0] + list(-a * np.sin(ph)))]))
+    b = kfbi.Batch(probs, workers=2)
+    st, plans, data, psi = batch_data(b, probs, ["star2d"] * 10)
+    ok = [i for i in range(10) if st[i] == 0]       # a draw the grid does not resolve is reported, not solved
+    assert len(ok) >= 8
+    u, info, _ = b.solve(data, psi, tol=1e-10, keep_u=True, raise_on_fail=False)
+    n = 129 * 129
+    its = []
+    for i in ok:
+        p = probs[i]
+        gp = kfbi.Plan(p)
+        psi1, u1, i1 = gp.solve(M.plan_data(gp, "star2d"), tol=1e-10)
+        assert info[i]["status"] == 0 and info[i]["iters"] == i1["iters"]
+        assert info[i]["true_rel_res"] == i1["true_rel_res"]
+        assert torch.equal(psi[i], psi1)
+        assert torch.equal(u[i * n:(i + 1) * n], u1)
+        its.append(i1["iters"])
+    print("iterations", its, flush=True)
+    assert len(set(its)) > 1
+
+
 PSI_STRIDE = 20000
 
 
