@@ -11,6 +11,7 @@
 #include <math.h>
 #include <stdint.h>
 
+#include <algorithm>
 #include <vector>
 
 #include "kfbi_internal.h"
@@ -38,7 +39,11 @@ __device__ __forceinline__ float from_bf16(uint16_t h) { return __uint_as_float(
 // v = z[r, c] > 0 ? v : 0 (ReLU derivative of a stored pre-activation);
 // written to Cf (fp32) as is and to Cb (bf16) after max(v, 0) when relu_b,
 // row stride ldc.  Workgroup tile 64 x 64 (four wavefronts of 32 x 32, each
-// 2 x 2 MFMA 16 x 16 tiles), K step 32 through LDS.
+// 2 x 2 MFMA 16 x 16 tiles), K step 32.  Each thread moves eight
+// consecutive bf16 of each operand tile per step, as one 16-byte load when
+// the rows are 16-byte aligned (vec) and the eight are in range; the next
+// step's loads are issued before the current step's MFMAs and land in the
+// other of two LDS buffers, so one barrier per step separates them.
 constexpr int GBM = 64, GBN = 64, GBK = 32, GPAD = 8;
 
 struct GemmArgs {
@@ -50,67 +55,103 @@ struct GemmArgs {
   int relu_b;           // bf16 output is max(v, 0)
   float* Cf;
   uint16_t* Cb;
+  int vec_a, vec_b;     // rows 16-byte aligned: eight-element chunks as one load
+  int kchunk;           // split K: work group z multiplies K range [z kchunk, (z + 1) kchunk)
+  int64_t zstride;      // and writes its partial product to Cf + z zstride (no epilogue)
 };
+
+union Chunk8 {
+  uint4 v;
+  uint16_t h[8];
+};
+
+// eight consecutive elements p[0..7] of a row, n of them in range (the rest 0)
+__device__ __forceinline__ Chunk8 load8(const uint16_t* p, int n, bool vec) {
+  Chunk8 c;
+  if (vec && n >= 8) {
+    c.v = *reinterpret_cast<const uint4*>(p);
+  } else {
+#pragma unroll
+    for (int i = 0; i < 8; ++i) c.h[i] = i < n ? p[i] : (uint16_t)0;
+  }
+  return c;
+}
 
 template <bool AT, bool BT>
 __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
-  __shared__ __attribute__((aligned(16))) uint16_t As[GBM][GBK + GPAD];
-  __shared__ __attribute__((aligned(16))) uint16_t Bs[GBN][GBK + GPAD];
+  __shared__ __attribute__((aligned(16))) uint16_t As[2][GBM][GBK + GPAD];
+  __shared__ __attribute__((aligned(16))) uint16_t Bs[2][GBN][GBK + GPAD];
   const int t = threadIdx.x;
   const int lane = t & 63, wave = t >> 6;
   const int m0 = blockIdx.y * GBM, n0 = blockIdx.x * GBN;
   const int wr = (wave >> 1) * 32, wc = (wave & 1) * 32;
+  // this thread's chunk of the A and B tiles: non-transposed, row r and
+  // columns kc..kc+7 of K; transposed, K row kk and columns c8..c8+7
+  const int r = t >> 2, kc = (t & 3) * 8, kk = t >> 3, c8 = (t & 7) * 8;
+  const int kbeg = blockIdx.z * g.kchunk;
+  const int kend = kbeg + g.kchunk < g.K ? kbeg + g.kchunk : g.K;
+  auto load_a = [&](int k0) -> Chunk8 {
+    if (!AT) {
+      const int gm = m0 + r, gk = k0 + kc;
+      const int n = gm < g.M ? kend - gk : 0;
+      return load8(g.A + (int64_t)gm * g.lda + gk, n < 8 ? (n < 0 ? 0 : n) : 8, g.vec_a);
+    }
+    const int gk = k0 + kk, gm = m0 + c8;
+    const int n = gk < kend ? g.M - gm : 0;
+    return load8(g.A + (int64_t)gk * g.lda + gm, n < 8 ? (n < 0 ? 0 : n) : 8, g.vec_a);
+  };
+  auto load_b = [&](int k0) -> Chunk8 {
+    if (BT) {
+      const int gn = n0 + r, gk = k0 + kc;
+      const int n = gn < g.N ? kend - gk : 0;
+      return load8(g.B + (int64_t)gn * g.ldb + gk, n < 8 ? (n < 0 ? 0 : n) : 8, g.vec_b);
+    }
+    const int gk = k0 + kk, gn = n0 + c8;
+    const int n = gk < kend ? g.N - gn : 0;
+    return load8(g.B + (int64_t)gk * g.ldb + gn, n < 8 ? (n < 0 ? 0 : n) : 8, g.vec_b);
+  };
+  auto store = [&](int buf, const Chunk8& ca, const Chunk8& cb) {
+    if (!AT) {
+      *reinterpret_cast<uint4*>(&As[buf][r][kc]) = ca.v;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) As[buf][c8 + i][kk] = ca.h[i];
+    }
+    if (BT) {
+      *reinterpret_cast<uint4*>(&Bs[buf][r][kc]) = cb.v;
+    } else {
+#pragma unroll
+      for (int i = 0; i < 8; ++i) Bs[buf][c8 + i][kk] = cb.h[i];
+    }
+  };
   f32x4 acc[2][2];
   for (int i = 0; i < 2; ++i)
     for (int j = 0; j < 2; ++j) acc[i][j] = (f32x4){0.f, 0.f, 0.f, 0.f};
-  for (int k0 = 0; k0 < g.K; k0 += GBK) {
-    // ---- A tile -> As[m][k]
-    if (!AT) {
-      const int r = t >> 2, kc = (t & 3) * 8;
-      const int gm = m0 + r;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int gk = k0 + kc + i;
-        As[r][kc + i] = (gm < g.M && gk < g.K) ? g.A[(int64_t)gm * g.lda + gk] : (uint16_t)0;
-      }
-    } else {
-      const int kk = t >> 3, mc = (t & 7) * 8;
-      const int gk = k0 + kk;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int gm = m0 + mc + i;
-        As[mc + i][kk] = (gm < g.M && gk < g.K) ? g.A[(int64_t)gk * g.lda + gm] : (uint16_t)0;
-      }
+  const int nk = kend > kbeg ? (kend - kbeg + GBK - 1) / GBK : 0;
+  {
+    const Chunk8 ca = load_a(kbeg), cb = load_b(kbeg);
+    store(0, ca, cb);
+  }
+  __syncthreads();
+  for (int kt = 0; kt < nk; ++kt) {
+    const int cur = kt & 1;
+    Chunk8 na, nbv;
+    const bool more = kt + 1 < nk;
+    if (more) {
+      na = load_a(kbeg + (kt + 1) * GBK);
+      nbv = load_b(kbeg + (kt + 1) * GBK);
     }
-    // ---- B tile -> Bs[n][k]
-    if (BT) {
-      const int r = t >> 2, kc = (t & 3) * 8;
-      const int gn = n0 + r;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int gk = k0 + kc + i;
-        Bs[r][kc + i] = (gn < g.N && gk < g.K) ? g.B[(int64_t)gn * g.ldb + gk] : (uint16_t)0;
-      }
-    } else {
-      const int kk = t >> 3, nc = (t & 7) * 8;
-      const int gk = k0 + kk;
-#pragma unroll
-      for (int i = 0; i < 8; ++i) {
-        const int gn = n0 + nc + i;
-        Bs[nc + i][kk] = (gn < g.N && gk < g.K) ? g.B[(int64_t)gk * g.ldb + gn] : (uint16_t)0;
-      }
-    }
-    __syncthreads();
     const int ko = (lane >> 4) * 8;
     bf16x8 a[2], b[2];
 #pragma unroll
-    for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[wr + 16 * i + (lane & 15)][ko]);
+    for (int i = 0; i < 2; ++i) a[i] = *reinterpret_cast<const bf16x8*>(&As[cur][wr + 16 * i + (lane & 15)][ko]);
 #pragma unroll
-    for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[wc + 16 * j + (lane & 15)][ko]);
+    for (int j = 0; j < 2; ++j) b[j] = *reinterpret_cast<const bf16x8*>(&Bs[cur][wc + 16 * j + (lane & 15)][ko]);
 #pragma unroll
     for (int i = 0; i < 2; ++i)
 #pragma unroll
       for (int j = 0; j < 2; ++j) acc[i][j] = __builtin_amdgcn_mfma_f32_16x16x32_bf16(a[i], b[j], acc[i][j], 0, 0, 0);
+    if (more) store(cur ^ 1, na, nbv);
     __syncthreads();
   }
 #pragma unroll
@@ -118,13 +159,17 @@ __global__ void __launch_bounds__(256) k_gemm(GemmArgs g) {
 #pragma unroll
     for (int j = 0; j < 2; ++j)
 #pragma unroll
-      for (int r = 0; r < 4; ++r) {
-        const int row = m0 + wr + 16 * i + 4 * (lane >> 4) + r;
+      for (int q = 0; q < 4; ++q) {
+        const int row = m0 + wr + 16 * i + 4 * (lane >> 4) + q;
         const int col = n0 + wc + 16 * j + (lane & 15);
         if (row >= g.M || col >= g.N) continue;
-        float v = acc[i][j][r];
-        if (g.bias) v += g.bias[col];
+        float v = acc[i][j][q];
         const int64_t o = (int64_t)row * g.ldc + col;
+        if (gridDim.z > 1) {
+          g.Cf[blockIdx.z * g.zstride + o] = v;
+          continue;
+        }
+        if (g.bias) v += g.bias[col];
         if (g.z) v = g.z[o] > 0.f ? v : 0.f;
         if (g.Cf) g.Cf[o] = v;
         if (g.Cb) g.Cb[o] = to_bf16(g.relu_b && v < 0.f ? 0.f : v);
@@ -243,13 +288,41 @@ __global__ void k_loss_final(int nb, int64_t n, const double* part, float* loss)
   *loss = (float)(s / (double)n);
 }
 
-// db[c] = sum over rows of dz[r, c]
-__global__ void k_colsum(int rows, int cols, const float* dz, float* db) {
-  int c = blockIdx.x * blockDim.x + threadIdx.x;
+// db[c] = sum over rows of dz[r, c], in a fixed order: work group (x, y)
+// sums 64 columns over row slab y (4 row phases of 64 threads, then the
+// phases in order) into part[y][c]; k_colsum_final adds the slabs in order
+constexpr int CS_SLABS = 16;
+constexpr int SK_MAX = 16;   // split-K partials at most
+__global__ void __launch_bounds__(256) k_colsum(int rows, int cols, const float* dz, float* part) {
+  __shared__ float sh[4][64];
+  const int c = blockIdx.x * 64 + (threadIdx.x & 63), ph = threadIdx.x >> 6;
+  const int per = (rows + CS_SLABS - 1) / CS_SLABS;
+  const int r0 = blockIdx.y * per, r1 = r0 + per < rows ? r0 + per : rows;
+  float s = 0.f;
+  if (c < cols)
+    for (int r = r0 + ph; r < r1; r += 4) s += dz[(int64_t)r * cols + c];
+  sh[ph][threadIdx.x & 63] = s;
+  __syncthreads();
+  if (ph == 0 && c < cols)
+    part[(int64_t)blockIdx.y * cols + c] = ((sh[0][threadIdx.x] + sh[1][threadIdx.x]) + sh[2][threadIdx.x]) +
+                                           sh[3][threadIdx.x];
+}
+
+__global__ void k_colsum_final(int cols, int slabs, const float* part, float* db) {
+  const int c = blockIdx.x * blockDim.x + threadIdx.x;
   if (c >= cols) return;
   float s = 0.f;
-  for (int r = 0; r < rows; ++r) s += dz[(int64_t)r * cols + c];
+  for (int y = 0; y < slabs; ++y) s += part[(int64_t)y * cols + c];
   db[c] = s;
+}
+
+// C = sum over the split-K partials, in order
+__global__ void k_splitk_sum(int64_t n, int S, int64_t stride, const float* part, float* C) {
+  const int64_t i = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  if (i >= n) return;
+  float s = 0.f;
+  for (int z = 0; z < S; ++z) s += part[z * stride + i];
+  C[i] = s;
 }
 
 // Linear head (the density is linear in the jump coefficients): the last
@@ -694,6 +767,8 @@ struct kfbi_mlp {
   float *y, *dy;                      // linear head: output and its gradient
   double* part;
   float* gv;                          // slab partials of the few-row forward
+  float* sk;                          // split-K partials of the weight gradients
+  float* cs;                          // row-slab partials of the bias gradients
 };
 
 namespace {
@@ -725,6 +800,8 @@ void free_batch(kfbi_mlp* h) {
   dfree_t(h->dy);
   dfree_t(h->part);
   dfree_t(h->gv);
+  dfree_t(h->sk);
+  dfree_t(h->cs);
   h->cap = 0;
 }
 
@@ -749,6 +826,13 @@ kfbi_status ensure_batch(kfbi_mlp* h, int B) {
     gv = n > gv ? n : gv;
   }
   KCHK(dalloc_t(&h->gv, gv));
+  int64_t mn = 0, wmax = 0;
+  for (int l = 0; l < h->L; ++l) {
+    mn = std::max(mn, (int64_t)h->w[l] * h->w[l + 1]);
+    wmax = std::max(wmax, (int64_t)h->w[l + 1]);
+  }
+  KCHK(dalloc_t(&h->sk, (int64_t)SK_MAX * mn));
+  KCHK(dalloc_t(&h->cs, (int64_t)CS_SLABS * wmax));
   h->cap = B;
   return KFBI_OK;
 }
@@ -756,9 +840,37 @@ kfbi_status ensure_batch(kfbi_mlp* h, int B) {
 template <bool AT, bool BT>
 void gemm(hipStream_t st, int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B, int ldb,
           const float* bias, const float* z, int relu_b, float* Cf, uint16_t* Cb, int ldc) {
-  GemmArgs g{M, N, K, lda, ldb, ldc, A, B, bias, z, relu_b, Cf, Cb};
+  GemmArgs g{M, N, K, lda, ldb, ldc, A, B, bias, z, relu_b, Cf, Cb,
+             lda % 8 == 0 && ((uintptr_t)A & 15) == 0, ldb % 8 == 0 && ((uintptr_t)B & 15) == 0, K, 0};
   dim3 grid((unsigned)((N + GBN - 1) / GBN), (unsigned)((M + GBM - 1) / GBM));
   hipLaunchKernelGGL((k_gemm<AT, BT>), grid, dim3(256), 0, st, g);
+}
+
+// C [M x N] (row stride N, no epilogue) with K split over up to SK_MAX work
+// groups per tile when the tiles alone leave most of the chip idle: each
+// writes its partial product into ws, k_splitk_sum adds them in order
+// (the weight gradients: M, N <= a few hundred, K = the batch rows)
+template <bool AT, bool BT>
+void gemm_splitk(hipStream_t st, int M, int N, int K, const uint16_t* A, int lda, const uint16_t* B, int ldb,
+                 float* C, float* ws) {
+  const int tiles = ((N + GBN - 1) / GBN) * ((M + GBM - 1) / GBM);
+  int S = K >= 4 * GBK * 2 && tiles < 256 ? (256 + tiles - 1) / tiles : 1;
+  if (S > SK_MAX) S = SK_MAX;
+  if (S > K / (2 * GBK)) S = K / (2 * GBK);
+  if (S <= 1) {
+    gemm<AT, BT>(st, M, N, K, A, lda, B, ldb, nullptr, nullptr, 0, C, nullptr, N);
+    return;
+  }
+  const int kchunk = ((K + S - 1) / S + GBK - 1) / GBK * GBK;
+  S = (K + kchunk - 1) / kchunk;
+  GemmArgs g{M, N, K, lda, ldb, N, A, B, nullptr, nullptr, 0, ws, nullptr,
+             lda % 8 == 0 && ((uintptr_t)A & 15) == 0, ldb % 8 == 0 && ((uintptr_t)B & 15) == 0, kchunk,
+             (int64_t)M * N};
+  dim3 grid((unsigned)((N + GBN - 1) / GBN), (unsigned)((M + GBM - 1) / GBM), (unsigned)S);
+  hipLaunchKernelGGL((k_gemm<AT, BT>), grid, dim3(256), 0, st, g);
+  const int64_t n = (int64_t)M * N;
+  hipLaunchKernelGGL(k_splitk_sum, dim3((unsigned)((n + 255) / 256)), dim3(256), 0, st, n, S, n, (const float*)ws,
+                     C);
 }
 
 // forward pass of B rows; X fp32 [B x w0]; the output is z[L-1]
@@ -792,9 +904,11 @@ void backward_from(kfbi_mlp* h, int B) {
   for (int l = L - 1; l >= 0; --l) {
     const int in = h->w[l], out = h->w[l + 1];
     // dW_l = a_l^T dz (fp32 into the gradient pack), db_l = column sums of dz
-    gemm<true, false>(st, in, out, B, h->a_b[l], in, h->dzb, out, nullptr, nullptr, 0, h->g + h->off_w[l], nullptr,
-                      out);
-    hipLaunchKernelGGL(k_colsum, dim3(nbl(out)), dim3(256), 0, st, B, out, (const float*)h->dz, h->g + h->off_b[l]);
+    gemm_splitk<true, false>(st, in, out, B, h->a_b[l], in, h->dzb, out, h->g + h->off_w[l], h->sk);
+    hipLaunchKernelGGL(k_colsum, dim3((unsigned)((out + 63) / 64), CS_SLABS), dim3(256), 0, st, B, out,
+                       (const float*)h->dz, h->cs);
+    hipLaunchKernelGGL(k_colsum_final, dim3(nbl(out)), dim3(256), 0, st, out, CS_SLABS, (const float*)h->cs,
+                       h->g + h->off_b[l]);
     if (l > 0) {
       // dz_{l-1} = (dz W_l^T) masked by z_{l-1} > 0
       gemm<false, true>(st, B, in, out, h->dzb, out, h->wb + h->off_wb[l], out, nullptr, h->z[l - 1], 0, h->da,
