@@ -149,6 +149,7 @@ struct kfbi_plan {
   // defect correction to |F - A v| <= mg_eps |F|, at most mg_maxit cycles
   int box_solver;
   double mg_eps;
+  double mg_eps_out;             // inside kfbi_solve: tolerance of the box solves outside the GMRES iterations
   int mg_maxit;
   double mg_c[27];                // A_h on the 3^d cube (fine grid)
   double mg_w;                   // Jacobi weight of the fine grid
@@ -174,7 +175,7 @@ struct kfbi_plan {
   int ustore_slots;              // slots allocated (0: none)
   int64_t ustore_n;              // nodes per slot
   // captured multigrid box solves, one per (right-hand side, solution,
-  // GMRES control word, cap, start), valid while the multigrid configuration
+  // GMRES control word, cap, start, tolerance), valid while the multigrid configuration
   // key mg_sg_key holds: they do not depend on the interfaces, so every
   // geometry on the same grid reuses them
   struct MgSolveGraph {
@@ -182,6 +183,7 @@ struct kfbi_plan {
     double* v;
     const int* gctl;
     int cap, guess;
+    double eps;
     hipGraph_t g;
     hipGraphExec_t e;
   };

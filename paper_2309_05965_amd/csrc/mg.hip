@@ -1270,7 +1270,6 @@ void config_key(const kfbi_plan* pl, uint64_t* key) {
     put(u);
   };
   put((uint64_t)pl->g.d | (uint64_t)pl->g.N << 8 | (uint64_t)pl->box_solver << 40);
-  putd(pl->mg_eps);
   putd(pl->mg_w);
   for (int c = 0; c < 27; ++c) putd(pl->mg_c[c]);
   for (const void* q : {(const void*)pl->mg_u, (const void*)pl->mg_t, (const void*)pl->mg_f, (const void*)pl->mg_Fc,
@@ -1312,7 +1311,7 @@ void mg_solve(kfbi_plan* pl, const double* F, double* v) {
   const int guess = pl->mg_guess ? 1 : 0;
   for (int i = 0; i < pl->mg_sg_n; ++i) {
     const kfbi_plan::MgSolveGraph& e = pl->mg_sg[i];
-    if (e.F == F && e.v == v && e.gctl == pl->ctl_active && e.cap == cap && e.guess == guess) {
+    if (e.F == F && e.v == v && e.gctl == pl->ctl_active && e.cap == cap && e.guess == guess && e.eps == pl->mg_eps) {
       if (hipGraphLaunch(e.e, pl->stream) == hipSuccess) return;
       (void)hipGetLastError();
       pl->mg_graphs_off = true;
@@ -1345,7 +1344,7 @@ void mg_solve(kfbi_plan* pl, const double* F, double* v) {
     solve_enqueue(pl, F, v);
     return;
   }
-  pl->mg_sg[pl->mg_sg_n++] = kfbi_plan::MgSolveGraph{F, v, pl->ctl_active, cap, guess, g, ex};
+  pl->mg_sg[pl->mg_sg_n++] = kfbi_plan::MgSolveGraph{F, v, pl->ctl_active, cap, guess, pl->mg_eps, g, ex};
 }
 
 // 1 + 64 slots, and at most 2 GiB
