@@ -8,7 +8,9 @@ import it; the product path never does, and it shares no code with the HIP
 library.
 
 Modules and their pins (tests/test_oracle_*.py, run with -m "not gpu")
-  levelset     level-set functions H and their gradients (Sec. 5.1); pinned
+  levelset     level-set functions H and their gradients (Sec. 5.1; the
+               product3d family is the domain of the 3D Dirichlet example of
+               Sec. 6.2.2); pinned
                by the closed-form normals and curvatures of the sample tests
                and the exact intersections of the geometry tests
   geometry     node regions, surface points, collocation stencils, density
@@ -28,6 +30,15 @@ Modules and their pins (tests/test_oracle_*.py, run with -m "not gpu")
                two interfaces), A = I/2 for equal coefficients, a dense
                brute-force BIE, GMRES against a dense solve and the 2nd/4th
                order convergence rates
+  bvp          interior Dirichlet and Neumann problems (eqs. bie-D, bie-N;
+               Secs. 3.1, 4, 5.5): one-sided values of the corrected
+               interpolation, the density as the jump [u] (Dirichlet) or
+               [d_n u] (Neumann), the zero-mean shift of Sec. 6.2.1; pinned
+               by exact polynomial traces, the double-layer potential of a
+               constant density (exactly the indicator of Omega), the
+               paper's printed Table 2d-poi-o4 (iterations and errors at
+               paper level), the Neumann convergence rate, and the Neumann
+               operator as the interface operator with beta_out = 0
   mg           two-grid multigrid box solver (a textbook method, not in the
                paper; its converged result is A_h^-1 F); pinned by the
                transfer identities, the Jacobi weight against the Fourier

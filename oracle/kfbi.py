@@ -83,10 +83,11 @@ class Plan:
         return np.stack([self.prob["lo"] + ind[a].astype(np.float64) * self.h
                          for a in range(self.d)], axis=1)
 
-    def simple_solve(self, a=None, b=None, ftilde=None, fhat=None, gB=None):
+    def simple_solve(self, a=None, b=None, ftilde=None, fhat=None, gB=None, trace=False):
         """Grid solution v (full grid, box boundary = gB), one-sided normal
-        derivatives (d_n v_in, d_n v_out) at the DOFs, and U.  a, b are given
-        on the whole surface-point table; ftilde at the PDE points."""
+        derivatives (d_n v_in, d_n v_out) at the DOFs (with trace=True the
+        one-sided values (v_in, v_out) instead), and U.  a, b are given on
+        the whole surface-point table; ftilde at the PDE points."""
         geo = self.geo
         d, N, h = self.d, self.N, self.h
         Q = collocation.rhs(geo, a, b, ftilde)
@@ -132,8 +133,42 @@ class Plan:
         v = np.zeros((N + 1,) * d) if gB is None else np.array(gB, dtype=np.float64)
         v[(slice(1, N),) * d] = vin
         # corrected interpolation at the DOFs (Sec. 5.5)
+        if trace:
+            v_in, v_out = self.traces(v, Cg, U)
+            return v, v_in, v_out, U
         dn_in, dn_out = self.normal_derivatives(v, Cg, U)
         return v, dn_in, dn_out, U
+
+    def _smoothed_block(self, vf, flat, Cg, U, blk):
+        """Grid values of the block node blk of every DOF, made smooth
+        across the interface as normal_derivatives describes."""
+        geo = self.geo
+        dofs = geo["dofs"]
+        ind = [geo["blocks"][:, a] + blk[a] for a in range(self.d)]
+        qn = geometry.ravel(ind, self.prob)
+        rq = flat[qn]
+        xi = (self.node_coords(qn) - dofs["pos"]) / self.h
+        Cown = (collocation.mono(xi, self.E) * U).sum(axis=1)
+        return vf[qn] + np.where(rq != dofs["iface"], Cown - Cg[rq, qn], 0.0)
+
+    def traces(self, v, Cg, U):
+        """One-sided values at the DOFs (Sec. 5.5, which obtains the value
+        and the derivatives of the smooth extension v_h^+ at p from the same
+        interpolation): the value of the tensor-product Lagrange interpolant
+        of the smoothed block data at p is v_in(p), and v_out(p) =
+        v_in(p) - C_{h,p}(p), the constant coefficient of p's polynomial."""
+        d, q = self.d, self.p
+        flat = self.geo["reg"].ravel()
+        vf = v.ravel()
+        val = np.zeros(self.Nb)
+        for blk in np.ndindex(*(q + 1,) * d):
+            vt = self._smoothed_block(vf, flat, Cg, U, blk)
+            w = np.ones(self.Nb)
+            for a in range(d):
+                w = w * self.ival[:, a, blk[a]]
+            val += w * vt
+        c0 = int(np.nonzero((self.E == 0).all(axis=1))[0][0])
+        return val, val - U[:, c0]
 
     def normal_derivatives(self, v, Cg, U):
         """One-sided normal derivatives at the DOFs (Sec. 5.5).  The grid

@@ -20,11 +20,15 @@ design notes):
   ellipsoid3d [cx, cy, cz, a0, a1, a2, R00..R22]  X = R^T d (R row-major),
                                             H = sum (X_j/a_j)^2 - 1
   torus3d     [cx, cy, cz, R, r]            H = (sqrt(dx^2+dy^2) - R)^2 + dz^2 - r^2
+  product3d   [cx, cy, cz, s]               X = s dx, Y = s dy, Z = s dz,
+                                            H = (1+X^2)(1+Y^2)(1+Z^2) + 8XYZ + X^2 + Y^2 + Z^2 - 3
+              (with s = 2 the domain of the paper's 3D modified-Helmholtz Dirichlet
+              example, Sec. 6.2.2: (1+4x^2)(1+4y^2)(1+4z^2) + 64xyz + 4x^2+4y^2+4z^2 < 3)
 """
 import numpy as np
 
-KINDS = ("ellipse2d", "star2d", "sphere3d", "ellipsoid3d", "torus3d")
-DIM_OF = {"ellipse2d": 2, "star2d": 2, "sphere3d": 3, "ellipsoid3d": 3, "torus3d": 3}
+KINDS = ("ellipse2d", "star2d", "sphere3d", "ellipsoid3d", "torus3d", "product3d")
+DIM_OF = {"ellipse2d": 2, "star2d": 2, "sphere3d": 3, "ellipsoid3d": 3, "torus3d": 3, "product3d": 3}
 NMODES = 8
 
 
@@ -110,8 +114,25 @@ def _torus(p, X, grad):
     return (2.0 * q * d0 / safe, 2.0 * q * d1 / safe, 2.0 * d2)
 
 
+def _product(p, X, grad):
+    x, y, z = X
+    sc = p[3]
+    X0 = sc * (x - p[0])
+    Y0 = sc * (y - p[1])
+    Z0 = sc * (z - p[2])
+    x2 = X0 * X0
+    y2 = Y0 * Y0
+    z2 = Z0 * Z0
+    if not grad:
+        return (1.0 + x2) * (1.0 + y2) * (1.0 + z2) + 8.0 * X0 * Y0 * Z0 + x2 + y2 + z2 - 3.0
+    gx = 2.0 * X0 * (1.0 + y2) * (1.0 + z2) + 8.0 * Y0 * Z0 + 2.0 * X0
+    gy = 2.0 * Y0 * (1.0 + x2) * (1.0 + z2) + 8.0 * X0 * Z0 + 2.0 * Y0
+    gz = 2.0 * Z0 * (1.0 + x2) * (1.0 + y2) + 8.0 * X0 * Y0 + 2.0 * Z0
+    return (sc * gx, sc * gy, sc * gz)
+
+
 _FUN = {"ellipse2d": _ellipse, "star2d": _star, "sphere3d": _sphere,
-        "ellipsoid3d": _ellipsoid, "torus3d": _torus}
+        "ellipsoid3d": _ellipsoid, "torus3d": _torus, "product3d": _product}
 
 
 def H(iface, X):

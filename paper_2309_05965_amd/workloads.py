@@ -50,6 +50,10 @@ def torus3d(cx, cy, cz, R, r):
     return ("torus3d", [cx, cy, cz, R, r])
 
 
+def product3d(cx, cy, cz, s):
+    return ("product3d", [cx, cy, cz, s])
+
+
 # ----------------------------------------------------------------------------
 # manufactured functions: each returns (value, grad tuple, laplacian)
 # ----------------------------------------------------------------------------
@@ -88,6 +92,29 @@ def f_exp3(X):                          # exp(x + y + z) / 10
     x, y, z = X
     v = np.exp(x + y + z) / 10.0
     return v, (v, v, v), 3.0 * v
+
+
+def f_e1(X):                            # exp(x) sin(cos(pi/3) x + sin(pi/3) y)
+    x, y = X[0], X[1]
+    c, s = 0.5, math.sqrt(3.0) / 2.0
+    e = np.exp(x)
+    t = c * x + s * y
+    st, ct = np.sin(t), np.cos(t)
+    return e * st, (e * st + c * e * ct, s * e * ct), 2.0 * c * e * ct
+
+
+def f_e3(X):                            # exp(z) (cos 2x + cos 3y)
+    x, y, z = X
+    e = np.exp(z)
+    c2, c3 = np.cos(2 * x), np.cos(3 * y)
+    return e * (c2 + c3), (-2 * e * np.sin(2 * x), -3 * e * np.sin(3 * y), e * (c2 + c3)), e * (-3 * c2 - 8 * c3)
+
+
+def f_e4(X):                            # exp(z) (cos 5x + cos 2y)
+    x, y, z = X
+    e = np.exp(z)
+    c5, c2 = np.cos(5 * x), np.cos(2 * y)
+    return e * (c5 + c2), (-5 * e * np.sin(5 * x), -2 * e * np.sin(2 * y), e * (c5 + c2)), e * (-24 * c5 - 3 * c2)
 
 
 def f_zero(X):
@@ -155,6 +182,71 @@ def config3(N=128):
     prob = problem(3, 4, N, -1.0, 1.0, 1.0, 100.0, 0.0,
                    [torus3d(0.0, 0.0, 0.0, 0.6, 0.25), sphere3d(0.0, 0.0, 0.0, 0.35 - 2.0 * h)])
     return prob, {0: f_exp3, 1: f_sin3, 2: f_sin3}
+
+
+# ----------------------------------------------------------------------------
+# interior boundary value problems (Sec. 2.1): Omega = the interiors
+# ----------------------------------------------------------------------------
+BIE_KINDS = ("interface", "dirichlet", "neumann")
+
+
+def bvp_problem(dim, order, N, lo, hi, kappa, ifaces, bie, cos_alpha=0.5):
+    """An interior Dirichlet or Neumann problem Lap u - kappa u = fhat in the
+    interiors of ifaces (beta_in and beta_out are not used: 1 and 0)."""
+    prob = problem(dim, order, N, lo, hi, 1.0, 0.0, kappa, ifaces, cos_alpha)
+    prob["bie"] = bie
+    return prob
+
+
+def e1_dirichlet(N=64):
+    """2D Poisson Dirichlet problem on the rotated ellipse a = 1, b = 0.5,
+    theta = -pi/6 in [-1.2, 1.2]^2, 4th order, u = exp(x) sin(cos(pi/3) x +
+    sin(pi/3) y) (paper Sec. 6.1.1, Table 2d-poi-o4)."""
+    prob = bvp_problem(2, 4, N, -1.2, 1.2, 0.0, [ellipse2d(0.0, 0.0, 1.0, 0.5, -math.pi / 6.0)], "dirichlet")
+    return prob, f_e1
+
+
+def e3_neumann(N=64):
+    """3D Poisson Neumann problem in the torus (1 - sqrt(x^2+y^2))^2 + z^2 <
+    0.4^2, box [-1.5, 1.5]^3, 4th order, u = exp(z)(cos 2x + cos 3y)
+    (Sec. 6.2.1, Table 3d-neu-poi)."""
+    prob = bvp_problem(3, 4, N, -1.5, 1.5, 0.0, [torus3d(0.0, 0.0, 0.0, 1.0, 0.4)], "neumann")
+    return prob, f_e3
+
+
+def e4_dirichlet(N=64):
+    """3D modified-Helmholtz Dirichlet problem, kappa = 100, in
+    (1+4x^2)(1+4y^2)(1+4z^2) + 64xyz + 4x^2 + 4y^2 + 4z^2 < 3, box
+    [-0.7, 0.7]^3, 4th order, u = exp(z)(cos 5x + cos 2y) (Sec. 6.2.2,
+    Table 3d-Diri-Hel)."""
+    prob = bvp_problem(3, 4, N, -0.7, 0.7, 100.0, [product3d(0.0, 0.0, 0.0, 2.0)], "dirichlet")
+    return prob, f_e4
+
+
+def make_bvp_data(prob, u, surf_pos, surf_nrm, pde_pts):
+    """Data of an interior BVP at the solver's query points: g2 = u
+    (Dirichlet) or d_n u (Neumann) on all surface points, ftilde = fhat at
+    the PDE points (the exterior extension is zero), fhat per region (zero
+    in region 0), no box data."""
+    X = _cols(surf_pos)
+    v, gr, _ = u(X)
+    if prob["bie"] == "dirichlet":
+        g2 = np.array(np.broadcast_to(v, X[0].shape), dtype=np.float64)
+    else:
+        n = np.asarray(surf_nrm, dtype=np.float64)
+        g2 = sum(np.asarray(gr[a]) * n[:, a] for a in range(n.shape[1]))
+    ft = np.array(fhat_fn(prob, u)(_cols(pde_pts)), dtype=np.float64)
+    G = grid_coords(prob)
+    K = len(prob["ifaces"])
+    f_in = np.broadcast_to(fhat_fn(prob, u)(G), G[0].shape)
+    fhat = np.stack([np.zeros(G[0].shape)] + [f_in] * K)
+    return {"g1": None, "g2": g2, "ftilde": ft, "fhat": fhat, "gB": None}
+
+
+def bvp_exact(prob, u):
+    """u at every node (compare on the nodes of Omega only)."""
+    G = grid_coords(prob)
+    return np.array(np.broadcast_to(u(G)[0], G[0].shape))
 
 
 def two_circles(order=4, N=64, gap=0.5, kappa=0.4):
