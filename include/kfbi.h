@@ -69,14 +69,35 @@ typedef enum {
  *   SPHERE3D    p = [cx, cy, cz, r]:  H = |x - c|^2 - r^2
  *   ELLIPSOID3D p = [cx, cy, cz, a0, a1, a2, R00..R22]: X = R^T (x - c)
  *               (R row-major), H = sum_j (X_j / a_j)^2 - 1
- *   TORUS3D     p = [cx, cy, cz, R, r]: H = (sqrt(dx^2+dy^2) - R)^2 + dz^2 - r^2 */
+ *   TORUS3D     p = [cx, cy, cz, R, r]: H = (sqrt(dx^2+dy^2) - R)^2 + dz^2 - r^2
+ *   PRODUCT3D   p = [cx, cy, cz, s]: X = s dx, Y = s dy, Z = s dz,
+ *               H = (1+X^2)(1+Y^2)(1+Z^2) + 8XYZ + X^2 + Y^2 + Z^2 - 3
+ *               (s = 2: the domain of the 3D Dirichlet example of Sec. 6.2.2) */
 enum {
   KFBI_LS_ELLIPSE2D = 1,
   KFBI_LS_STAR2D = 2,
   KFBI_LS_SPHERE3D = 3,
   KFBI_LS_ELLIPSOID3D = 4,
-  KFBI_LS_TORUS3D = 5
+  KFBI_LS_TORUS3D = 5,
+  KFBI_LS_PRODUCT3D = 6
 };
+
+/* Boundary integral equation of a problem (Sec. 3):
+ *   INTERFACE  the interface problem, unknown psi = [d_n u], psi/2 + mu K' psi
+ *              (Sec. 3.2, with beta_in inside every interface, beta_out outside);
+ *   DIRICHLET  the interior Dirichlet problem u = gD on Gamma (eq. bie-D):
+ *              unknown phi = [u] of u = D phi + N fhat, (1/2 + K) phi = gD - G fhat;
+ *   NEUMANN    the interior Neumann problem d_n u = gN on Gamma (eq. bie-N,
+ *              gN = sigma^-1 times the paper's g_N): unknown psi = [d_n u] of
+ *              u = -S psi + N fhat, (1/2 - K') psi = gN - d_n G fhat.
+ * For DIRICHLET and NEUMANN the domain Omega is the union of the interiors,
+ * the equation there is Lap u - kappa u = fhat (divided by sigma), the
+ * volume potential extends fhat by zero outside Omega (Sec. 4), and the box
+ * Green's function vanishes on the box boundary; beta_in and beta_out are
+ * not used.  With kappa = 0 the Neumann operator has a one-dimensional null
+ * space (u is fixed up to a constant): the right-hand side and every
+ * product are shifted to zero mean over the DOFs (Sec. 6.2.1). */
+enum { KFBI_BIE_INTERFACE = 0, KFBI_BIE_DIRICHLET = 1, KFBI_BIE_NEUMANN = 2 };
 
 #define KFBI_MAX_IFACE 4
 #define KFBI_LS_NPARAM 32
@@ -87,15 +108,16 @@ typedef struct {
   double p[KFBI_LS_NPARAM];
 } kfbi_levelset;
 
-/* Problem descriptor (Sec. 2.2).  dim 2|3; order 2 (5/7-point scheme,
+/* Problem descriptor (Secs. 2.1, 2.2).  dim 2|3; order 2 (5/7-point scheme,
  * quadratic correction) or 4 (eqs. 9p-cds / 27p-cds, quartic correction);
  * N a power of two, 8 <= N <= 1024; interiors of the interfaces must be
  * disjoint and stay 3 nodes away from the box boundary; kappa is the
  * reduced reaction coefficient kappa_i / beta_i (equal on both sides);
  * cos_alpha in (0, 1/sqrt(dim)) defines the overlapping surface sets
- * Gamma_r = {|n_r| > cos alpha} (Sec. 5.1). */
+ * Gamma_r = {|n_r| > cos alpha} (Sec. 5.1); bie one of KFBI_BIE_*. */
 typedef struct {
   int32_t dim, order, N, n_iface;
+  int32_t bie, reserved;
   double lo, hi;
   double beta_in, beta_out, kappa, cos_alpha;
   kfbi_levelset iface[KFBI_MAX_IFACE];
@@ -122,7 +144,10 @@ typedef struct {
  *   ftilde  [n_dof][n_pde]       fhat_in - fhat_out at the PDE collocation points
  *   fhat    [n_iface+1][n_nodes] fhat_s at every node for every region s
  *                                (s = 0 exterior, s = k inside interface k)
- *   gB      [n_nodes]            box data; only box-boundary nodes are read */
+ *   gB      [n_nodes]            box data; only box-boundary nodes are read
+ * Of a Dirichlet or Neumann problem: g2 holds gD resp. gN at the surface
+ * points (the DOFs' entries are read), ftilde = fhat at the PDE points,
+ * fhat[0] = 0 (the extension by zero), g1 and gB are not read (NULL). */
 typedef struct {
   const double* g1;
   const double* g2;
@@ -179,7 +204,7 @@ typedef struct {
  * descriptor check. */
 kfbi_status kfbi_plan_create(const kfbi_problem* prob, void* stream, kfbi_plan** out);
 
-/* Re-run S0 + S1 for another problem with the same dim, order and N,
+/* Re-run S0 + S1 for another problem with the same dim, order, N and bie,
  * reusing the plan's buffers (they grow when the new geometry needs more). */
 kfbi_status kfbi_plan_setup(kfbi_plan* plan, const kfbi_problem* prob);
 
@@ -290,8 +315,10 @@ kfbi_status kfbi_box_solve_noalloc(int dim, int order, int N, double lo, double 
 /* One simple interface problem (eq. con-ifp with box data; Secs. 4, 5):
  * w with [w] = a, [d_n w] = b, Lap w - kappa w = fhat_s, w = gB on the box.
  * a, b: [n_surf] (NULL = 0); ftilde [n_dof][n_pde], fhat, gB as in
- * kfbi_data (NULL = 0).  Outputs: v [n_nodes] (may be NULL), d_n w_in and
- * d_n w_out at the primary points [n_dof] (may be NULL). */
+ * kfbi_data (NULL = 0).  Outputs: v [n_nodes] (may be NULL), and at the
+ * primary points [n_dof] (may be NULL) the one-sided limits of the
+ * corrected interpolation (Sec. 5.5): d_n w_in and d_n w_out, or, on a
+ * plan of a Dirichlet problem, the values w_in and w_out. */
 kfbi_status kfbi_simple_solve(kfbi_plan* plan, const double* a, const double* b,
                               const double* ftilde, const double* fhat, const double* gB,
                               double* v, double* dn_in, double* dn_out);
@@ -300,15 +327,23 @@ kfbi_status kfbi_simple_solve(kfbi_plan* plan, const double* a, const double* b,
  * (beta_in + beta_out), J = beta_in d_n w_in - beta_out d_n w_out, E the
  * density extension to the surface table.  Equals psi/2 + mu K' psi of
  * Sec. 3.2 with mu = (beta_out - beta_in)/(beta_out + beta_in).
+ * Dirichlet problem: Aphi = w_in(E phi, 0, 0, 0, 0), the interior value,
+ * = (1/2 + K) phi (eq. bie-D); Neumann problem: Apsi = d_n w_in(0, E psi,
+ * 0, 0, 0) = (1/2 - K') psi (eq. bie-N), shifted to zero mean when kappa = 0.
  * psi, Apsi: [n_dof], distinct buffers. */
 kfbi_status kfbi_matvec(kfbi_plan* plan, const double* psi, double* Apsi);
 
 /* BIE right-hand side (Alg. 1 Step 1):
- * b = (g2 - J[w(g1, 0, ftilde, fhat, gB)]) / (beta_in + beta_out), b [n_dof]. */
+ * b = (g2 - J[w(g1, 0, ftilde, fhat, gB)]) / (beta_in + beta_out), b [n_dof];
+ * Dirichlet: b = gD - w_in(0, 0, ftilde, fhat, 0); Neumann: b = gN -
+ * d_n w_in(0, 0, ftilde, fhat, 0) (zero mean when kappa = 0). */
 kfbi_status kfbi_rhs(kfbi_plan* plan, const kfbi_data* data, double* b);
 
 /* Full solve (Alg. 1): b, GMRES on kfbi_matvec to opts->tol, then
- * u = w(g1, E psi, ftilde, fhat, gB).  psi_inout [n_dof] (initial guess
+ * u = w(g1, E psi, ftilde, fhat, gB) (Dirichlet: w(E phi, 0, ftilde, fhat,
+ * 0), Neumann: w(0, E psi, ftilde, fhat, 0); the solution is u on the nodes
+ * of Omega, the Neumann one up to an additive constant; a learned start is
+ * for interface problems only).  psi_inout [n_dof] (initial guess
  * with KFBI_START_GIVEN; with KFBI_START_LEARNED the predicted density is
  * written there first; density on return); u_out [n_nodes] (may be NULL).
  * With a multigrid box solver, u is the step-1 grid solution plus the box

@@ -61,8 +61,13 @@ kfbi_status check_problem(const kfbi_problem* pr) {
     kfbi_set_error("n_iface must be in [1, %d] (got %d)", KFBI_MAX_IFACE, pr->n_iface);
     return KFBI_E_INVALID;
   }
-  if (!(pr->hi > pr->lo) || !(pr->beta_in > 0.0) || !(pr->beta_out > 0.0) || !(pr->kappa >= 0.0)) {
-    kfbi_set_error("need hi > lo, beta_in > 0, beta_out > 0, kappa >= 0");
+  if (pr->bie != KFBI_BIE_INTERFACE && pr->bie != KFBI_BIE_DIRICHLET && pr->bie != KFBI_BIE_NEUMANN) {
+    kfbi_set_error("bie must be KFBI_BIE_INTERFACE, _DIRICHLET or _NEUMANN (got %d)", pr->bie);
+    return KFBI_E_INVALID;
+  }
+  const bool betas = pr->bie != KFBI_BIE_INTERFACE || (pr->beta_in > 0.0 && pr->beta_out > 0.0);
+  if (!(pr->hi > pr->lo) || !betas || !(pr->kappa >= 0.0)) {
+    kfbi_set_error("need hi > lo, beta_in > 0, beta_out > 0 (interface problems), kappa >= 0");
     return KFBI_E_INVALID;
   }
   if (!(pr->cos_alpha > 0.0) || !(pr->cos_alpha * pr->cos_alpha * pr->dim < 1.0)) {
@@ -72,7 +77,8 @@ kfbi_status check_problem(const kfbi_problem* pr) {
   for (int k = 0; k < pr->n_iface; ++k) {
     int kind = pr->iface[k].kind;
     bool two = kind == KFBI_LS_ELLIPSE2D || kind == KFBI_LS_STAR2D;
-    bool three = kind == KFBI_LS_SPHERE3D || kind == KFBI_LS_ELLIPSOID3D || kind == KFBI_LS_TORUS3D;
+    bool three = kind == KFBI_LS_SPHERE3D || kind == KFBI_LS_ELLIPSOID3D || kind == KFBI_LS_TORUS3D ||
+                 kind == KFBI_LS_PRODUCT3D;
     if ((pr->dim == 2 && !two) || (pr->dim == 3 && !three)) {
       kfbi_set_error("level set %d: kind %d does not fit dim %d", k, kind, pr->dim);
       return KFBI_E_INVALID;
@@ -215,8 +221,11 @@ GridDesc make_grid(const kfbi_problem& pr) {
   g.h = (pr.hi - pr.lo) / pr.N;
   g.kappa = pr.kappa;
   g.cos_alpha = pr.cos_alpha;
-  g.beta_in = pr.beta_in;
-  g.beta_out = pr.beta_out;
+  g.bie = pr.bie;
+  // a boundary value problem's operator is the interior one-sided limit:
+  // the interface combination with weights 1 inside and 0 outside
+  g.beta_in = pr.bie == KFBI_BIE_INTERFACE ? pr.beta_in : 1.0;
+  g.beta_out = pr.bie == KFBI_BIE_INTERFACE ? pr.beta_out : 0.0;
   g.n_nodes = 1;
   for (int a = 0; a < g.d; ++a) g.n_nodes *= g.n1;
   return g;
@@ -338,6 +347,28 @@ void simple_solve_impl(kfbi_plan* pl, const double* a, const double* b, const do
 }
 
 void matvec_impl(kfbi_plan* pl, const double* psi, double* Apsi) { op_matvec(pl, psi, Apsi); }
+
+// Alg. 1 Step 1: the BIE right-hand side into b, its grid solution into
+// vsbuf.  A boundary value problem has no jump data and zero box data.
+void rhs_impl(kfbi_plan* pl, const kfbi_data& d, double* b) {
+  const bool ifc = pl->g.bie == KFBI_BIE_INTERFACE;
+  simple_solve_impl(pl, ifc ? d.g1 : nullptr, nullptr, d.ftilde, d.fhat, ifc ? d.gB : nullptr, pl->vsbuf,
+                    pl->dn_in, pl->dn_out);
+  op_bie_rhs(pl, d.g2, pl->dn_in, pl->dn_out, b);
+}
+
+// the grid solution of the density psi: w(g1, E psi, ftilde, fhat, gB); of
+// a Dirichlet problem w(E phi, 0, ftilde, fhat, 0) (the density is [u]),
+// of a Neumann problem w(0, E psi, ftilde, fhat, 0)
+void final_impl(kfbi_plan* pl, const kfbi_data& d, const double* psi, double* u) {
+  op_extend(pl, psi, pl->aS);
+  if (pl->g.bie == KFBI_BIE_DIRICHLET)
+    simple_solve_impl(pl, pl->aS, nullptr, d.ftilde, d.fhat, nullptr, u, pl->dn_in, pl->dn_out);
+  else if (pl->g.bie == KFBI_BIE_NEUMANN)
+    simple_solve_impl(pl, nullptr, pl->aS, d.ftilde, d.fhat, nullptr, u, pl->dn_in, pl->dn_out);
+  else
+    simple_solve_impl(pl, d.g1, pl->aS, d.ftilde, d.fhat, d.gB, u, pl->dn_in, pl->dn_out);
+}
 
 void destroy_graphs(kfbi_plan* pl) {
   if (pl->graph_xe) (void)hipGraphExecDestroy(pl->graph_xe);
@@ -620,8 +651,9 @@ extern "C" kfbi_status kfbi_plan_setup(kfbi_plan* pl, const kfbi_problem* prob) 
   }
   KCHK(check_problem(prob));
   if (prob->dim != pl->prob.dim || prob->order != pl->prob.order || prob->N != pl->prob.N ||
-      prob->n_iface != pl->prob.n_iface || prob->lo != pl->prob.lo || prob->hi != pl->prob.hi) {
-    kfbi_set_error("kfbi_plan_setup needs the same dim, order, N, n_iface and box");
+      prob->n_iface != pl->prob.n_iface || prob->lo != pl->prob.lo || prob->hi != pl->prob.hi ||
+      prob->bie != pl->prob.bie) {
+    kfbi_set_error("kfbi_plan_setup needs the same dim, order, N, n_iface, box and bie");
     return KFBI_E_INVALID;
   }
   pl->prob = *prob;
@@ -837,8 +869,7 @@ extern "C" kfbi_status kfbi_rhs(kfbi_plan* pl, const kfbi_data* data, double* b)
     kfbi_set_error("NULL argument");
     return KFBI_E_INVALID;
   }
-  simple_solve_impl(pl, data->g1, nullptr, data->ftilde, data->fhat, data->gB, pl->vsbuf, pl->dn_in, pl->dn_out);
-  op_bie_rhs(pl, data->g2, pl->dn_in, pl->dn_out, b);
+  rhs_impl(pl, *data, b);
   HIPCHK(hipGetLastError());
   return KFBI_OK;
 }
@@ -1138,8 +1169,7 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
   const double eps_in = pl->mg_eps, eps_out = mg ? pl->mg_eps_out : eps_in;
   // Step 1: right-hand side (its grid solution stays in vsbuf)
   pl->mg_eps = eps_out;
-  simple_solve_impl(pl, data->g1, nullptr, data->ftilde, data->fhat, data->gB, pl->vsbuf, pl->dn_in, pl->dn_out);
-  op_bie_rhs(pl, data->g2, pl->dn_in, pl->dn_out, pl->bvec);
+  rhs_impl(pl, *data, pl->bvec);
   KCHK(set_relax_word(pl, relax ? pl->mg_relax : 0.0));
   // Step 2: initial residual and control word (multigrid: the box solution
   // of A x0 goes to the store's slot 0)
@@ -1153,10 +1183,7 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
   KCHK(ensure_graph(pl));
   // final solve u = w(g1, E psi, ftilde, fhat, gB)
   double* u = u_out ? u_out : pl->vsbuf;
-  auto final_solve = [&] {
-    op_extend(pl, psi, pl->aS);
-    simple_solve_impl(pl, data->g1, pl->aS, data->ftilde, data->fhat, data->gB, u, pl->dn_in, pl->dn_out);
-  };
+  auto final_solve = [&] { final_impl(pl, *data, psi, u); };
   // Steps 3-4.  FFT box solver: without relaxation and from a zero start,
   // on a graph key already solved with (a repeated problem, so the first
   // batch, sized to the previous iteration count, usually converges), the
@@ -1325,9 +1352,7 @@ kfbi_status kfbi_solve_group(kfbi_plan* const* pls, int G, const kfbi_data* data
     // steps 1-2 of every problem
     for (int p = 0; p < G; ++p) {
       kfbi_plan* pl = pls[p];
-      simple_solve_impl(pl, data[p].g1, nullptr, data[p].ftilde, data[p].fhat, data[p].gB, pl->vsbuf, pl->dn_in,
-                        pl->dn_out);
-      op_bie_rhs(pl, data[p].g2, pl->dn_in, pl->dn_out, pl->bvec);
+      rhs_impl(pl, data[p], pl->bvec);
       KCHK(set_relax_word(pl, 0.0));
       if (use_x0) matvec_impl(pl, psi[p], pl->work);
       gm_residual_start(pl, pl->bvec, pl->work, use_x0, tol, m);
@@ -1390,9 +1415,7 @@ kfbi_status kfbi_solve_group(kfbi_plan* const* pls, int G, const kfbi_data* data
       gm_update_device(pl, psi[p], use_x0);
       matvec_impl(pl, psi[p], pl->work2);
       gm_true_residual(pl, pl->bvec, pl->work2, pl->scal + 4);
-      op_extend(pl, psi[p], pl->aS);
-      simple_solve_impl(pl, data[p].g1, pl->aS, data[p].ftilde, data[p].fhat, data[p].gB, u[p], pl->dn_in,
-                        pl->dn_out);
+      final_impl(pl, data[p], psi[p], u[p]);
     }
     hipLaunchKernelGGL(k_group_state, dim3((G + 255) / 256), dim3(256), 0, st, d_ctl, d_scal, G, d_state);
     HIPCHK(hipMemcpyAsync(state.data(), d_state, sizeof(double) * 8 * G, hipMemcpyDeviceToHost, st));
@@ -1453,6 +1476,10 @@ extern "C" kfbi_status kfbi_solve(kfbi_plan* pl, const kfbi_data* data, const kf
   if (o.start < KFBI_START_ZERO || o.start > KFBI_START_LEARNED || o.solver < KFBI_SOLVER_PLAN ||
       o.solver > KFBI_SOLVER_MG32 || (o.start == KFBI_START_LEARNED && !o.learned)) {
     kfbi_set_error("opts: start must be KFBI_START_* (learned needs opts->learned), solver KFBI_SOLVER_*");
+    return KFBI_E_INVALID;
+  }
+  if (o.start == KFBI_START_LEARNED && pl->g.bie != KFBI_BIE_INTERFACE) {
+    kfbi_set_error("a learned start is for interface problems");
     return KFBI_E_INVALID;
   }
   if (o.solver != KFBI_SOLVER_PLAN) KCHK(apply_solver(pl, o));

@@ -99,6 +99,11 @@ __device__ double ls_value(const LSet& L, int k, double x, double y, double z) {
       double q = rho - p[3];
       return q * q + d2 * d2 - p[4] * p[4];
     }
+    case KFBI_LS_PRODUCT3D: {
+      double X = p[3] * (x - p[0]), Y = p[3] * (y - p[1]), Z = p[3] * (z - p[2]);
+      double x2 = X * X, y2 = Y * Y, z2 = Z * Z;
+      return (1.0 + x2) * (1.0 + y2) * (1.0 + z2) + 8.0 * X * Y * Z + x2 + y2 + z2 - 3.0;
+    }
   }
   return 1.0;
 }
@@ -159,6 +164,17 @@ __device__ void ls_grad(const LSet& L, int k, double x, double y, double z, doub
       g[0] = 2.0 * q * d0 / safe;
       g[1] = 2.0 * q * d1 / safe;
       g[2] = 2.0 * d2;
+      return;
+    }
+    case KFBI_LS_PRODUCT3D: {
+      double X = p[3] * (x - p[0]), Y = p[3] * (y - p[1]), Z = p[3] * (z - p[2]);
+      double x2 = X * X, y2 = Y * Y, z2 = Z * Z;
+      double gx = 2.0 * X * (1.0 + y2) * (1.0 + z2) + 8.0 * Y * Z + 2.0 * X;
+      double gy = 2.0 * Y * (1.0 + x2) * (1.0 + z2) + 8.0 * X * Z + 2.0 * Y;
+      double gz = 2.0 * Z * (1.0 + x2) * (1.0 + y2) + 8.0 * X * Y + 2.0 * Z;
+      g[0] = p[3] * gx;
+      g[1] = p[3] * gy;
+      g[2] = p[3] * gz;
       return;
     }
   }
@@ -720,7 +736,12 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_stencils(StencilArgs a) {
     if (lane < a.lat.nN) a.stN[c * a.lat.nN + lane] = i;
     return;
   }
-  if (lane < a.lat.nD) a.stD[c * a.lat.nD + lane] = pD;
+  if (lane < a.lat.nD) {
+    a.stD[c * a.lat.nD + lane] = pD;
+    // a Dirichlet problem's density is the jump [u]: the collocation reads
+    // it at the Dirichlet points
+    if (S.g.bie == KFBI_BIE_DIRICHLET) a.s_need[pD] = 1;
+  }
   if (lane < a.lat.nN) {
     a.stN[c * a.lat.nN + lane] = pN;
     a.s_need[pN] = 1;

@@ -34,6 +34,7 @@ enum {
 
 struct GridDesc {           // plain-value grid/problem description for kernels
   int d, order, p, N, n1, K;
+  int bie;                  // KFBI_BIE_*: what the density is and what the interpolation returns
   double lo, hi, h, kappa, cos_alpha, beta_in, beta_out;
   int64_t n_nodes;
 };
@@ -266,6 +267,7 @@ kfbi_status op_fold(kfbi_plan* pl);
 void op_matvec(kfbi_plan* pl, const double* psi, double* Apsi);
 void op_matvec_head(kfbi_plan* pl, const double* psi);
 void op_matvec_tail(kfbi_plan* pl, const double* psi, double* Apsi);
+bool op_zero_mean_used(const kfbi_plan* pl);
 void op_bie_rhs(kfbi_plan* pl, const double* g2, const double* dn_in, const double* dn_out,
                 double* b);
 // dst.hip (step S3)

@@ -381,7 +381,11 @@ __global__ void k_bie_rhs(GridDesc g, int64_t n_dof, const int* d2s, const doubl
 
 // ---------------------------------------------------------------- folded operators
 // At set-up the inverses and the density extension are folded into the
-// linear maps the matvec needs (U = Minv Q with Q = [0; 0; h psiS(N pts)]):
+// linear maps the matvec needs (U = Minv Q with Q = [0; 0; h psiS(N pts)];
+// for a Dirichlet problem the density is the jump [u], Q = [0; phiS(D pts);
+// 0], the maps use the Dirichlet columns without the factor h, and the
+// interpolation returns values: IW are the value weights of the block and
+// C_c(p_c) = U[0] takes the place of d_n C_c(p_c)):
 //   C at entry e        = sum_t FW[e][t] psi[FI[e][t]]
 //                         (FW = h phi(xi_e)^T Minv[:, N col j] * extension weight)
 //   d_n C_c(p_c)        = sum_t GW[c][t] psi[GI[c][t]]
@@ -398,7 +402,7 @@ struct FoldArgs {
   Mono M;
   int nP, nD, nN, nC, nF, maxpairs;
   int64_t n_dof, n_corr, n_irr;
-  const int *d2s, *ck, *cnode, *cown, *stN, *ext_idx, *irr, *EI, *meta;
+  const int *d2s, *ck, *cnode, *cown, *stD, *stN, *ext_idx, *irr, *EI, *meta;
   const int8_t* region;
   const double *spos, *snrm, *MinvT, *ext_w;
   int *FI, *GI, *IB, *IE2, *PE1, *PE2;
@@ -430,13 +434,16 @@ __global__ void k_fold_corr(FoldArgs a) {
   double phi[NC];
   monomials<D, P>(xi, phi);
   const double* Mi = a.MinvT + (int64_t)own * NC * NC;
-  for (int j = 0; j < a.nN; ++j) {
-    const double* col = Mi + (int64_t)(a.nP + a.nD + j) * NC;
+  const bool dir = g.bie == KFBI_BIE_DIRICHLET;
+  const int nDen = dir ? a.nD : a.nN, col0 = dir ? a.nP : a.nP + a.nD;
+  const int* stDen = dir ? a.stD : a.stN;
+  for (int j = 0; j < nDen; ++j) {
+    const double* col = Mi + (int64_t)(col0 + j) * NC;
     double sacc = 0.0;
 #pragma unroll
     for (int al = 0; al < NC; ++al) sacc += col[al] * phi[al];
-    const double rn = g.h * sacc;
-    const int sN = a.stN[(int64_t)own * a.nN + j];
+    const double rn = dir ? sacc : g.h * sacc;
+    const int sN = stDen[(int64_t)own * nDen + j];
 #pragma unroll
     for (int m = 0; m < P; ++m) {
       const int idx = a.ext_idx[(int64_t)sN * P + m];
@@ -485,12 +492,18 @@ __global__ void k_fold_dof(FoldArgs a) {
     val[ax] = v;
     der[ax] = dv;
   }
+  const bool dir = g.bie == KFBI_BIE_DIRICHLET;
   double w = 0.0;
-  for (int ax = 0; ax < g.d; ++ax) {
-    double t2 = der[ax] / g.h;
-    for (int o = 0; o < g.d; ++o)
-      if (o != ax) t2 = t2 * val[o];
-    w += nv[ax] * t2;
+  if (dir) {
+    w = 1.0;
+    for (int ax = 0; ax < g.d; ++ax) w = w * val[ax];
+  } else {
+    for (int ax = 0; ax < g.d; ++ax) {
+      double t2 = der[ax] / g.h;
+      for (int o = 0; o < g.d; ++o)
+        if (o != ax) t2 = t2 * val[o];
+      w += nv[ax] * t2;
+    }
   }
   a.IW[c * nbk + b] = w;
   // entry of C^(reg q) at a block node inside another interface (-1 elsewhere)
@@ -500,11 +513,16 @@ __global__ void k_fold_dof(FoldArgs a) {
   if (b == 0) {
     a.IB[c] = (int)ravel(g, st[0], st[1], st[2]);
     const double* Mi = a.MinvT + c * (int64_t)a.nC * a.nC;
-    for (int j = 0; j < a.nN; ++j) {
-      const double* col = Mi + (int64_t)(a.nP + a.nD + j) * a.nC;
+    const int nDen = dir ? a.nD : a.nN, col0 = dir ? a.nP : a.nP + a.nD;
+    const int* stDen = dir ? a.stD : a.stN;
+    for (int j = 0; j < nDen; ++j) {
+      const double* col = Mi + (int64_t)(col0 + j) * a.nC;
       double gsum = 0.0;
-      for (int ax = 0; ax < g.d; ++ax) gsum += nv[ax] * col[1 + ax];   // graded order: 1, x, y(, z)
-      const int sN = a.stN[c * a.nN + j];
+      if (dir)
+        gsum = col[0];                                                   // C_c(p_c) = U[0]
+      else
+        for (int ax = 0; ax < g.d; ++ax) gsum += nv[ax] * col[1 + ax];   // graded order: 1, x, y(, z)
+      const int sN = stDen[c * nDen + j];
       for (int m = 0; m < g.p; ++m) {
         const int idx = a.ext_idx[(int64_t)sN * g.p + m];
         const int64_t o = c * a.nF + (int64_t)j * g.p + m;
@@ -565,14 +583,17 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_fold_own(FoldArgs a) {
     for (int al = 0; al < NC; ++al) a.TI[c * NC + al] = T[al];
   }
   const double* Mi = a.MinvT + c * (int64_t)NC * NC;
-  for (int q = lane; q < a.nN * P; q += FOLD_G) {
+  const bool dir = g.bie == KFBI_BIE_DIRICHLET;
+  const int nDen = dir ? a.nD : a.nN, col0 = dir ? a.nP : a.nP + a.nD;
+  const int* stDen = dir ? a.stD : a.stN;
+  for (int q = lane; q < nDen * P; q += FOLD_G) {
     const int j = q / P, m = q % P;
-    const double* col = Mi + (int64_t)(a.nP + a.nD + j) * NC;
+    const double* col = Mi + (int64_t)(col0 + j) * NC;
     double sacc = 0.0;
 #pragma unroll
     for (int al = 0; al < NC; ++al) sacc += T[al] * col[al];
-    const double rn = g.h * sacc;
-    const int sN = a.stN[c * a.nN + j];
+    const double rn = dir ? sacc : g.h * sacc;
+    const int sN = stDen[c * nDen + j];
     const int idx = a.ext_idx[(int64_t)sN * P + m];
     a.HW[c * a.nF + (int64_t)j * P + m] = idx >= 0 ? rn * a.ext_w[(int64_t)sN * P + m] : 0.0;
   }
@@ -760,15 +781,41 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_interp(InterpArgs a) {
   }
   if (lane != 0) return;
   if (a.U) {
-    const double* nv = a.snrm + (int64_t)s * g.d;
     const double* Uc = a.U + c * (int64_t)a.nC;
-    for (int ax = 0; ax < g.d; ++ax) dnC += nv[ax] * Uc[1 + ax];
-    dnC = dnC / g.h;
+    if (g.bie == KFBI_BIE_DIRICHLET) {
+      dnC = Uc[0];   // value trace: the jump C_{h,p}(p)
+    } else {
+      const double* nv = a.snrm + (int64_t)s * g.d;
+      for (int ax = 0; ax < g.d; ++ax) dnC += nv[ax] * Uc[1 + ax];
+      dnC = dnC / g.h;
+    }
   }
   double dout = acc - dnC;
   if (a.dn_in) a.dn_in[c] = acc;
   if (a.dn_out) a.dn_out[c] = dout;
   if (a.Apsi) a.Apsi[c] = (g.beta_in * acc - g.beta_out * dout) / (g.beta_in + g.beta_out);
+}
+
+// Zero-mean shift of a Neumann problem with kappa = 0 (Sec. 6.2.1): one
+// work group sums x in a fixed order and subtracts the mean.  With ctl, x is
+// the GMRES basis vector V[j + 1], j = ctl[0].
+constexpr int ZM_BLOCK = 1024;
+__global__ void __launch_bounds__(ZM_BLOCK) k_zero_mean(int64_t n, double* x, const int* ctl, double* Vb) {
+  if (ctl) {
+    if (ctl[1]) return;
+    x = Vb + ((int64_t)ctl[0] + 1) * n;
+  }
+  __shared__ double red[ZM_BLOCK];
+  double s = 0.0;
+  for (int64_t i = threadIdx.x; i < n; i += ZM_BLOCK) s += x[i];
+  red[threadIdx.x] = s;
+  __syncthreads();
+  for (int off = ZM_BLOCK / 2; off > 0; off >>= 1) {
+    if ((int)threadIdx.x < off) red[threadIdx.x] += red[threadIdx.x + off];
+    __syncthreads();
+  }
+  const double mean = red[0] / (double)n;
+  for (int64_t i = threadIdx.x; i < n; i += ZM_BLOCK) x[i] -= mean;
 }
 
 }  // namespace
@@ -870,7 +917,7 @@ kfbi_status op_fold(kfbi_plan* pl) {
   const GridDesc& g = pl->g;
   const int q1 = g.p + 1;
   const int nbk = g.d == 3 ? q1 * q1 * q1 : q1 * q1;
-  pl->nF = pl->nN * g.p;
+  pl->nF = (g.bie == KFBI_BIE_DIRICHLET ? pl->nD : pl->nN) * g.p;
   pl->maxpairs = g.order == 2 ? 2 * g.d : (g.d == 3 ? 26 : 8);
   if (pl->n_corr > pl->cap_fold_corr) {
     int64_t cap = pl->n_corr + pl->n_corr / 4 + 64;
@@ -922,6 +969,7 @@ kfbi_status op_fold(kfbi_plan* pl) {
   A.ck = pl->ce_k;
   A.cnode = pl->ce_node;
   A.cown = pl->ce_owner;
+  A.stD = pl->stD;
   A.stN = pl->stN;
   A.ext_idx = pl->ext_idx;
   A.irr = pl->irr;
@@ -1004,9 +1052,17 @@ void op_matvec_head(kfbi_plan* pl, const double* psi) {
 // after the box solve: the corrected interpolation and the combination
 void op_matvec_tail(kfbi_plan* pl, const double* psi, double* Apsi) {
   launch_interp(pl, pl->vbuf, nullptr, psi, nullptr, nullptr, Apsi);
+  if (op_zero_mean_used(pl))
+    hipLaunchKernelGGL(k_zero_mean, dim3(1), dim3(ZM_BLOCK), 0, pl->stream, pl->n_dof, Apsi, pl->ctl_active, pl->V);
 }
 
 void op_bie_rhs(kfbi_plan* pl, const double* g2, const double* dn_in, const double* dn_out, double* b) {
   hipLaunchKernelGGL(k_bie_rhs, dim3(nb(pl->n_dof)), dim3(KFBI_BLOCK), 0, pl->stream, pl->g, pl->n_dof, pl->d2s,
                      g2, dn_in, dn_out, b);
+  if (op_zero_mean_used(pl))
+    hipLaunchKernelGGL(k_zero_mean, dim3(1), dim3(ZM_BLOCK), 0, pl->stream, pl->n_dof, b, nullptr, nullptr);
+}
+
+bool op_zero_mean_used(const kfbi_plan* pl) {
+  return pl->g.bie == KFBI_BIE_NEUMANN && pl->g.kappa == 0.0 && pl->n_dof > 0;
 }

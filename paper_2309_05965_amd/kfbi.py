@@ -14,7 +14,8 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkfbi.so")
 
-KINDS = {"ellipse2d": 1, "star2d": 2, "sphere3d": 3, "ellipsoid3d": 4, "torus3d": 5}
+KINDS = {"ellipse2d": 1, "star2d": 2, "sphere3d": 3, "ellipsoid3d": 4, "torus3d": 5, "product3d": 6}
+BIE = {"interface": 0, "dirichlet": 1, "neumann": 2}
 STATUS = {0: "OK", 1: "INVALID", 2: "UNRESOLVED", 3: "SINGULAR", 4: "NOT_CONVERGED",
           5: "NONFINITE", 6: "DEVICE", 7: "OOM"}
 EXPORT = {"region": 0, "surf_pos": 1, "surf_nrm": 2, "surf_meta": 3, "dof_surf": 4,
@@ -30,7 +31,8 @@ class LevelSet(ctypes.Structure):
 
 class Problem(ctypes.Structure):
     _fields_ = [("dim", ctypes.c_int32), ("order", ctypes.c_int32), ("N", ctypes.c_int32),
-                ("n_iface", ctypes.c_int32), ("lo", ctypes.c_double), ("hi", ctypes.c_double),
+                ("n_iface", ctypes.c_int32), ("bie", ctypes.c_int32), ("reserved", ctypes.c_int32),
+                ("lo", ctypes.c_double), ("hi", ctypes.c_double),
                 ("beta_in", ctypes.c_double), ("beta_out", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("cos_alpha", ctypes.c_double),
                 ("iface", LevelSet * 4)]
@@ -182,6 +184,7 @@ def problem_struct(prob):
     s = Problem()
     s.dim, s.order, s.N = prob["dim"], prob["order"], prob["N"]
     s.n_iface = len(prob["ifaces"])
+    s.bie = BIE[prob.get("bie", "interface")]
     s.lo, s.hi = prob["lo"], prob["hi"]
     s.beta_in, s.beta_out, s.kappa = prob["beta_in"], prob["beta_out"], prob["kappa"]
     s.cos_alpha = prob.get("cos_alpha", 0.5)
@@ -398,6 +401,21 @@ def device_data(plan, prob, sol):
     data = W.make_data(prob, sol, pos, nrm, meta[:, 3], pde, meta[dsurf, 3])
     dev = plan.device
     return {k: torch.from_numpy(v.reshape(-1).copy() if k != "ftilde" else v.copy()).to(dev).contiguous()
+            for k, v in data.items()}
+
+
+def device_bvp_data(plan, prob, u):
+    """Manufactured data of an interior Dirichlet or Neumann problem with the
+    solution u at the plan's own query points, as device tensors (input
+    generation; uses the workloads module)."""
+    from . import workloads as W
+    pos = plan.export("surf_pos").cpu().numpy()
+    nrm = plan.export("surf_nrm").cpu().numpy()
+    pde = plan.export("pde_pts").cpu().numpy()
+    data = W.make_bvp_data(prob, u, pos, nrm, pde)
+    dev = plan.device
+    return {k: None if v is None else
+            torch.from_numpy(v.reshape(-1).copy() if k != "ftilde" else v.copy()).to(dev).contiguous()
             for k, v in data.items()}
 
 

@@ -79,6 +79,10 @@ def rel(a, b):
 @pytest.mark.parametrize("name", list(CASES))
 def test_geometry_matches_exactly(name):
     prob, sol, gp, op = case(name)
+    assert_same_geometry(gp, op)
+
+
+def assert_same_geometry(gp, op):
     geo = op.geo
     assert np.array_equal(host(gp.export("region")), geo["reg"].ravel())
     s = geo["surf"]
