@@ -39,6 +39,13 @@ Modules and their pins (tests/test_oracle_*.py, run with -m "not gpu")
                paper's printed Table 2d-poi-o4 (iterations and errors at
                paper level), the Neumann convergence rate, and the Neumann
                operator as the interface operator with beta_out = 0
+  twodensity   two-density interface BIE (eq. bie-ifp-1) for different
+               kappa_i / sigma_i on the two sides, as two simple solves per
+               product (one per Green's function); pinned by the exact
+               densities of piecewise-polynomial solutions (one and two
+               interfaces, 2D and 3D) satisfying the discrete system to
+               rounding, and the 2nd/4th-order convergence of a
+               Poisson / modified-Helmholtz problem
   mg           two-grid multigrid box solver (a textbook method, not in the
                paper; its converged result is A_h^-1 F); pinned by the
                transfer identities, the Jacobi weight against the Fourier

@@ -392,8 +392,9 @@ def _lagrange(u, nodes):
 
 def extension(prob, surf, st):
     """Values of the density at the non-primary surface points used as
-    Neumann collocation points (and as Dirichlet points when the density is
-    the jump [u] of an interior Dirichlet problem), as combinations of primary values by degree
+    Neumann collocation points (and as Dirichlet points when a density is
+    the jump [u]: interior Dirichlet problems and the two-density
+    formulation), as combinations of primary values by degree
     p-1 Lagrange interpolation along one grid direction on the surface.
 
     Candidate stencils for a non-primary point q on a family-r line (its
@@ -428,8 +429,8 @@ def extension(prob, surf, st):
     w[prim, 0] = 1.0
     need = np.zeros(ns, dtype=bool)
     need[st["N"].ravel()] = True
-    if prob.get("bie") == "dirichlet":
-        # the density is the jump [u]: it enters at the Dirichlet points
+    if prob.get("bie") in ("dirichlet", "two_density"):
+        # a density is the jump [u]: it enters at the Dirichlet points
         need[st["D"].ravel()] = True
     need &= ~prim
     table = line_table(prob, surf)

@@ -86,7 +86,8 @@ class Plan:
     def simple_solve(self, a=None, b=None, ftilde=None, fhat=None, gB=None, trace=False):
         """Grid solution v (full grid, box boundary = gB), one-sided normal
         derivatives (d_n v_in, d_n v_out) at the DOFs (with trace=True the
-        one-sided values (v_in, v_out) instead), and U.  a, b are given on
+        one-sided values (v_in, v_out) instead; with trace="both" the pairs
+        (v_in, v_out) and (d_n v_in, d_n v_out)), and U.  a, b are given on
         the whole surface-point table; ftilde at the PDE points."""
         geo = self.geo
         d, N, h = self.d, self.N, self.h
@@ -133,6 +134,8 @@ class Plan:
         v = np.zeros((N + 1,) * d) if gB is None else np.array(gB, dtype=np.float64)
         v[(slice(1, N),) * d] = vin
         # corrected interpolation at the DOFs (Sec. 5.5)
+        if trace == "both":
+            return v, self.traces(v, Cg, U), self.normal_derivatives(v, Cg, U), U
         if trace:
             v_in, v_out = self.traces(v, Cg, U)
             return v, v_in, v_out, U

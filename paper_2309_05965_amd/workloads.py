@@ -249,6 +249,64 @@ def bvp_exact(prob, u):
     return np.array(np.broadcast_to(u(G)[0], G[0].shape))
 
 
+# ----------------------------------------------------------------------------
+# two-density interface problems (eq. bie-ifp-1): kappa_i / sigma_i may differ
+# ----------------------------------------------------------------------------
+def td_problem(dim, order, N, lo, hi, sigma_in, sigma_out, kappa_in, kappa_out, ifaces, cos_alpha=0.5):
+    """sigma_i Lap u - kappa_i u = f_i; kappa and kappa_out are the reduced
+    coefficients kappa_i / sigma_i inside and outside."""
+    prob = problem(dim, order, N, lo, hi, sigma_in, sigma_out, kappa_in, ifaces, cos_alpha)
+    prob["bie"] = "two_density"
+    prob["kappa_out"] = float(kappa_out)
+    return prob
+
+
+def e7_heterogeneous(N=64):
+    """Three spheres of radius 0.7 centred at (0.5, 0.5, 0.5), (-0.5, -0.5,
+    0.5), (0.5, -0.5, -0.5), sigma_i = 1, kappa_i = 0, sigma_e = 4, kappa_e =
+    10 (Poisson inside, modified Helmholtz outside; paper Sec. 6.2.5, Table
+    3d-ifp-heter).  The paper gives neither the box nor the exact solution:
+    box [-1.5, 1.5]^3 (its printed N_b fits this box) and u_i = sin x sin y
+    sin z, u_e = exp(x + y + z) / 10."""
+    sph = [sphere3d(0.5, 0.5, 0.5, 0.7), sphere3d(-0.5, -0.5, 0.5, 0.7), sphere3d(0.5, -0.5, -0.5, 0.7)]
+    prob = td_problem(3, 4, N, -1.5, 1.5, 1.0, 4.0, 0.0, 10.0 / 4.0, sph)
+    return prob, {0: f_exp3, 1: f_sin3, 2: f_sin3, 3: f_sin3}
+
+
+def make_td_data(prob, sol, surf_pos, surf_nrm, surf_iface, pde_pts, cen_iface):
+    """Data of a two-density problem at the solver's query points: g1 = u_k -
+    u_0, g2 = sigma_in d_n u_k - sigma_out d_n u_0 on all surface points;
+    ftilde = (fhat_in, fhat_out) at the PDE points, shape (2, Nb, nP), with
+    fhat_s = Lap u_s - kappa~_s u_s; fhat per region; gB = u_0."""
+    K = len(prob["ifaces"])
+    kap = lambda s: prob["kappa_out"] if s == 0 else prob["kappa"]
+    X = _cols(surf_pos)
+    k = np.asarray(surf_iface)
+    n = np.asarray(surf_nrm, dtype=np.float64)
+    v0, gr0, _ = sol[0](X)
+    dn0 = sum(np.asarray(gr0[a]) * n[:, a] for a in range(n.shape[1]))
+    g1 = np.zeros(k.size)
+    g2 = np.zeros(k.size)
+    for kk in range(1, K + 1):
+        vk, grk, _ = sol[kk](X)
+        dnk = sum(np.asarray(grk[a]) * n[:, a] for a in range(n.shape[1]))
+        g1 = np.where(k == kk, vk - v0, g1)
+        g2 = np.where(k == kk, prob["beta_in"] * dnk - prob["beta_out"] * dn0, g2)
+
+    def fh(s, Y):
+        v, _, lap = sol[s](Y)
+        return lap - kap(s) * v
+    Xp = _cols(pde_pts)
+    fin = np.zeros(np.asarray(pde_pts).shape[:-1])
+    for kk in range(1, K + 1):
+        fin = np.where(np.asarray(cen_iface)[:, None] == kk, fh(kk, Xp), fin)
+    fout = np.broadcast_to(fh(0, Xp), fin.shape)
+    G = grid_coords(prob)
+    fhat = np.stack([np.broadcast_to(fh(s, G), G[0].shape) for s in range(K + 1)])
+    gB = np.array(np.broadcast_to(sol[0](G)[0], G[0].shape))
+    return {"g1": g1, "g2": g2, "ftilde": np.stack([fin, fout]), "fhat": fhat, "gB": gB}
+
+
 def two_circles(order=4, N=64, gap=0.5, kappa=0.4):
     """Two disjoint circles (radii 0.27, 0.21) in [-1, 1]^2 whose closest
     points are gap * h apart along a direction 0.35 rad from the x axis;
