@@ -96,8 +96,18 @@ enum {
  * Green's function vanishes on the box boundary; beta_in and beta_out are
  * not used.  With kappa = 0 the Neumann operator has a one-dimensional null
  * space (u is fixed up to a constant): the right-hand side and every
- * product are shifted to zero mean over the DOFs (Sec. 6.2.1). */
-enum { KFBI_BIE_INTERFACE = 0, KFBI_BIE_DIRICHLET = 1, KFBI_BIE_NEUMANN = 2 };
+ * product are shifted to zero mean over the DOFs (Sec. 6.2.1).
+ *   TWO_DENSITY the interface problem with different reduced reaction
+ *              coefficients on the two sides, kappa = kappa_1 / sigma_1
+ *              inside and kappa_out = kappa_2 / sigma_2 outside (sigma_1 =
+ *              beta_in, sigma_2 = beta_out): the system of eq. bie-ifp-1 in
+ *              phi = u_1 and psi = sigma_2 d_n u_2 on Gamma, of 2 n_dof
+ *              unknowns (phi then psi).  Each product takes one simple solve
+ *              per Green's function (the superposition remark after Alg. 1);
+ *              the plan keeps a second plan of the same geometry for the
+ *              exterior operator.  FFT box solver only; no batches, no
+ *              learned start. */
+enum { KFBI_BIE_INTERFACE = 0, KFBI_BIE_DIRICHLET = 1, KFBI_BIE_NEUMANN = 2, KFBI_BIE_TWO_DENSITY = 3 };
 
 #define KFBI_MAX_IFACE 4
 #define KFBI_LS_NPARAM 32
@@ -114,12 +124,14 @@ typedef struct {
  * disjoint and stay 3 nodes away from the box boundary; kappa is the
  * reduced reaction coefficient kappa_i / beta_i (equal on both sides);
  * cos_alpha in (0, 1/sqrt(dim)) defines the overlapping surface sets
- * Gamma_r = {|n_r| > cos alpha} (Sec. 5.1); bie one of KFBI_BIE_*. */
+ * Gamma_r = {|n_r| > cos alpha} (Sec. 5.1); bie one of KFBI_BIE_*;
+ * kappa_out the exterior's reduced coefficient (KFBI_BIE_TWO_DENSITY only). */
 typedef struct {
   int32_t dim, order, N, n_iface;
   int32_t bie, reserved;
   double lo, hi;
   double beta_in, beta_out, kappa, cos_alpha;
+  double kappa_out;
   kfbi_levelset iface[KFBI_MAX_IFACE];
 } kfbi_problem;
 
@@ -147,7 +159,10 @@ typedef struct {
  *   gB      [n_nodes]            box data; only box-boundary nodes are read
  * Of a Dirichlet or Neumann problem: g2 holds gD resp. gN at the surface
  * points (the DOFs' entries are read), ftilde = fhat at the PDE points,
- * fhat[0] = 0 (the extension by zero), g1 and gB are not read (NULL). */
+ * fhat[0] = 0 (the extension by zero), g1 and gB are not read (NULL).
+ * Of a two-density problem: g1 = [u], g2 = [sigma d_n u] on the surface
+ * points, ftilde [2][n_dof][n_pde] = fhat_1 then fhat_2 at the PDE points
+ * (fhat_i = f_i / sigma_i), fhat per region (fhat_2 in region 0), gB. */
 typedef struct {
   const double* g1;
   const double* g2;
@@ -330,20 +345,26 @@ kfbi_status kfbi_simple_solve(kfbi_plan* plan, const double* a, const double* b,
  * Dirichlet problem: Aphi = w_in(E phi, 0, 0, 0, 0), the interior value,
  * = (1/2 + K) phi (eq. bie-D); Neumann problem: Apsi = d_n w_in(0, E psi,
  * 0, 0, 0) = (1/2 - K') psi (eq. bie-N), shifted to zero mean when kappa = 0.
- * psi, Apsi: [n_dof], distinct buffers. */
+ * Two-density problem: the operator of eq. bie-ifp-1 on [phi; psi].
+ * psi, Apsi: [n_dof] ([2 n_dof] for a two-density plan), distinct buffers. */
 kfbi_status kfbi_matvec(kfbi_plan* plan, const double* psi, double* Apsi);
 
 /* BIE right-hand side (Alg. 1 Step 1):
  * b = (g2 - J[w(g1, 0, ftilde, fhat, gB)]) / (beta_in + beta_out), b [n_dof];
  * Dirichlet: b = gD - w_in(0, 0, ftilde, fhat, 0); Neumann: b = gN -
- * d_n w_in(0, 0, ftilde, fhat, 0) (zero mean when kappa = 0). */
+ * d_n w_in(0, 0, ftilde, fhat, 0) (zero mean when kappa = 0); two-density:
+ * the right-hand side of eq. bie-ifp-1, b [2 n_dof]. */
 kfbi_status kfbi_rhs(kfbi_plan* plan, const kfbi_data* data, double* b);
 
 /* Full solve (Alg. 1): b, GMRES on kfbi_matvec to opts->tol, then
  * u = w(g1, E psi, ftilde, fhat, gB) (Dirichlet: w(E phi, 0, ftilde, fhat,
  * 0), Neumann: w(0, E psi, ftilde, fhat, 0); the solution is u on the nodes
  * of Omega, the Neumann one up to an additive constant; a learned start is
- * for interface problems only).  psi_inout [n_dof] (initial guess
+ * for interface problems only).  A two-density plan solves eq. bie-ifp-1
+ * by GMRES with classical Gram-Schmidt applied twice (host Hessenberg, one
+ * host wait per orthogonalisation pass), psi_inout holding [phi; psi]
+ * (2 n_dof), u = u_1 = W_1(phi, (psi + g2)/sigma_1, ...) inside and u_2 =
+ * W_2(g1 - phi, -psi/sigma_2, ...; gB) outside.  psi_inout [n_dof] (initial guess
  * with KFBI_START_GIVEN; with KFBI_START_LEARNED the predicted density is
  * written there first; density on return); u_out [n_nodes] (may be NULL).
  * With a multigrid box solver, u is the step-1 grid solution plus the box

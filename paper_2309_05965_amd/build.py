@@ -20,7 +20,7 @@ OBJ = os.path.join(ROOT, "_build", "kfbi")
 LIB = os.path.join(HERE, "libkfbi.so")
 GEN = os.path.join(HERE, "gen")
 GEN_LIB = os.path.join(HERE, "libkfbi_gen.so")
-SOURCES = ["geometry.hip", "collocation.hip", "operator.hip", "dst.hip", "mg.hip", "gmres.hip", "learned.hip", "batch.hip", "api.hip"]
+SOURCES = ["geometry.hip", "collocation.hip", "operator.hip", "dst.hip", "mg.hip", "gmres.hip", "learned.hip", "batch.hip", "twodensity.hip", "api.hip"]
 ARCH = os.environ.get("KFBI_OFFLOAD_ARCH", "gfx950")
 
 

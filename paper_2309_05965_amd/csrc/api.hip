@@ -61,13 +61,16 @@ kfbi_status check_problem(const kfbi_problem* pr) {
     kfbi_set_error("n_iface must be in [1, %d] (got %d)", KFBI_MAX_IFACE, pr->n_iface);
     return KFBI_E_INVALID;
   }
-  if (pr->bie != KFBI_BIE_INTERFACE && pr->bie != KFBI_BIE_DIRICHLET && pr->bie != KFBI_BIE_NEUMANN) {
-    kfbi_set_error("bie must be KFBI_BIE_INTERFACE, _DIRICHLET or _NEUMANN (got %d)", pr->bie);
+  if (pr->bie != KFBI_BIE_INTERFACE && pr->bie != KFBI_BIE_DIRICHLET && pr->bie != KFBI_BIE_NEUMANN &&
+      pr->bie != KFBI_BIE_TWO_DENSITY) {
+    kfbi_set_error("bie must be KFBI_BIE_INTERFACE, _DIRICHLET, _NEUMANN or _TWO_DENSITY (got %d)", pr->bie);
     return KFBI_E_INVALID;
   }
-  const bool betas = pr->bie != KFBI_BIE_INTERFACE || (pr->beta_in > 0.0 && pr->beta_out > 0.0);
-  if (!(pr->hi > pr->lo) || !betas || !(pr->kappa >= 0.0)) {
-    kfbi_set_error("need hi > lo, beta_in > 0, beta_out > 0 (interface problems), kappa >= 0");
+  const bool ifc = pr->bie == KFBI_BIE_INTERFACE || pr->bie == KFBI_BIE_TWO_DENSITY;
+  const bool betas = !ifc || (pr->beta_in > 0.0 && pr->beta_out > 0.0);
+  if (!(pr->hi > pr->lo) || !betas || !(pr->kappa >= 0.0) ||
+      (pr->bie == KFBI_BIE_TWO_DENSITY && !(pr->kappa_out >= 0.0))) {
+    kfbi_set_error("need hi > lo, beta_in > 0, beta_out > 0 (interface problems), kappa >= 0, kappa_out >= 0");
     return KFBI_E_INVALID;
   }
   if (!(pr->cos_alpha > 0.0) || !(pr->cos_alpha * pr->cos_alpha * pr->dim < 1.0)) {
@@ -88,6 +91,7 @@ kfbi_status check_problem(const kfbi_problem* pr) {
 }
 
 void free_plan(kfbi_plan* pl) {
+  td_free(pl);
   dfree(pl->region);
   dfree(pl->need);
   dfree(pl->Cg);
@@ -224,8 +228,9 @@ GridDesc make_grid(const kfbi_problem& pr) {
   g.bie = pr.bie;
   // a boundary value problem's operator is the interior one-sided limit:
   // the interface combination with weights 1 inside and 0 outside
-  g.beta_in = pr.bie == KFBI_BIE_INTERFACE ? pr.beta_in : 1.0;
-  g.beta_out = pr.bie == KFBI_BIE_INTERFACE ? pr.beta_out : 0.0;
+  const bool bvp = pr.bie == KFBI_BIE_DIRICHLET || pr.bie == KFBI_BIE_NEUMANN;
+  g.beta_in = bvp ? 1.0 : pr.beta_in;
+  g.beta_out = bvp ? 0.0 : pr.beta_out;
   g.n_nodes = 1;
   for (int a = 0; a < g.d; ++a) g.n_nodes *= g.n1;
   return g;
@@ -296,6 +301,7 @@ kfbi_status run_setup(kfbi_plan* pl) {
   // (they do nothing when a status flag is set)
   KCHK(op_fold(pl));
   KCHK(colloc_finish(pl));
+  if (pl->g.bie == KFBI_BIE_TWO_DENSITY && !pl->is_aux) KCHK(td_setup(pl));
   // the multigrid matvec right-hand side is zero away from the irregular nodes
   if (pl->Fmg) HIPCHK(hipMemsetAsync(pl->Fmg, 0, sizeof(double) * pl->g.n_nodes, pl->stream));
   // everything after the set-up is ordered behind it on the plan's stream
@@ -605,6 +611,23 @@ extern "C" const char* kfbi_last_error(void) { return g_err; }
 // ---------------------------------------------------------------- plan
 extern "C" kfbi_status kfbi_plan_create(const kfbi_problem* prob, void* stream, kfbi_plan** out) {
   std::shared_lock<std::shared_mutex> lock(kfbi_capture_mutex);
+  return plan_create_impl(prob, (hipStream_t)stream, out);
+}
+
+void plan_box_solve(kfbi_plan* pl, const double* F, double* v) { box_solve_any(pl, F, v); }
+
+kfbi_status plan_resetup(kfbi_plan* pl, const kfbi_problem* prob) {
+  pl->prob = *prob;
+  pl->g = make_grid(*prob);
+  return run_setup(pl);
+}
+
+void plan_release(kfbi_plan* pl) {
+  free_plan(pl);
+  delete pl;
+}
+
+kfbi_status plan_create_impl(const kfbi_problem* prob, hipStream_t stream, kfbi_plan** out, bool is_aux) {
   if (!out) {
     kfbi_set_error("out is NULL");
     return KFBI_E_INVALID;
@@ -618,6 +641,7 @@ extern "C" kfbi_status kfbi_plan_create(const kfbi_problem* prob, void* stream, 
   }
   memset((void*)pl, 0, sizeof(*pl));
   pl->relax_word = NAN;
+  pl->is_aux = is_aux;
   pl->prob = *prob;
   pl->g = make_grid(*prob);
   pl->stream = (hipStream_t)stream;
@@ -808,6 +832,10 @@ extern "C" kfbi_status kfbi_plan_set_box_solver(kfbi_plan* pl, int solver, doubl
     kfbi_set_error("box solver needs eps_in > 0 and 1 <= max_cycles <= 64");
     return KFBI_E_INVALID;
   }
+  if (pl->g.bie == KFBI_BIE_TWO_DENSITY && solver != KFBI_BOX_FFT) {
+    kfbi_set_error("the two-density form uses the FFT box solver");
+    return KFBI_E_INVALID;
+  }
   destroy_graphs(pl);
   std::shared_lock<std::shared_mutex> lock(kfbi_capture_mutex);
   return mg_configure(pl, solver, eps_in, max_cycles);
@@ -858,6 +886,7 @@ extern "C" kfbi_status kfbi_matvec(kfbi_plan* pl, const double* psi, double* Aps
     kfbi_set_error("matvec needs distinct psi and Apsi");
     return KFBI_E_INVALID;
   }
+  if (pl->g.bie == KFBI_BIE_TWO_DENSITY) return td_matvec(pl, psi, Apsi);
   matvec_impl(pl, psi, Apsi);
   HIPCHK(hipGetLastError());
   return KFBI_OK;
@@ -869,6 +898,7 @@ extern "C" kfbi_status kfbi_rhs(kfbi_plan* pl, const kfbi_data* data, double* b)
     kfbi_set_error("NULL argument");
     return KFBI_E_INVALID;
   }
+  if (pl->g.bie == KFBI_BIE_TWO_DENSITY) return td_rhs(pl, data, b);
   rhs_impl(pl, *data, b);
   HIPCHK(hipGetLastError());
   return KFBI_OK;
@@ -1481,6 +1511,14 @@ extern "C" kfbi_status kfbi_solve(kfbi_plan* pl, const kfbi_data* data, const kf
   if (o.start == KFBI_START_LEARNED && pl->g.bie != KFBI_BIE_INTERFACE) {
     kfbi_set_error("a learned start is for interface problems");
     return KFBI_E_INVALID;
+  }
+  if (pl->g.bie == KFBI_BIE_TWO_DENSITY) {
+    if (o.solver != KFBI_SOLVER_PLAN && o.solver != KFBI_SOLVER_FFT) {
+      kfbi_set_error("the two-density form uses the FFT box solver");
+      return KFBI_E_INVALID;
+    }
+    std::shared_lock<std::shared_mutex> lock(kfbi_capture_mutex);
+    return td_solve(pl, data, &o, psi, u_out, info);
   }
   if (o.solver != KFBI_SOLVER_PLAN) KCHK(apply_solver(pl, o));
   if (o.start == KFBI_START_LEARNED) {

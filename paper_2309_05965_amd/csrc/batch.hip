@@ -117,6 +117,11 @@ extern "C" kfbi_status kfbi_batch_create(const kfbi_problem* probs, int n, int n
     kfbi_set_error("batch needs problems, n >= 1 and 1..16 workers");
     return KFBI_E_INVALID;
   }
+  for (int i = 0; i < n; ++i)
+    if (probs[i].bie == KFBI_BIE_TWO_DENSITY) {
+      kfbi_set_error("problem %d: batches take single-density problems", i);
+      return KFBI_E_INVALID;
+    }
   kfbi_batch* b = new (std::nothrow) kfbi_batch();
   if (!b) return KFBI_E_OOM;
   b->probs.assign(probs, probs + n);

@@ -738,9 +738,9 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_stencils(StencilArgs a) {
   }
   if (lane < a.lat.nD) {
     a.stD[c * a.lat.nD + lane] = pD;
-    // a Dirichlet problem's density is the jump [u]: the collocation reads
-    // it at the Dirichlet points
-    if (S.g.bie == KFBI_BIE_DIRICHLET) a.s_need[pD] = 1;
+    // a density that is the jump [u] (Dirichlet problems, the two-density
+    // form) is read by the collocation at the Dirichlet points
+    if (S.g.bie == KFBI_BIE_DIRICHLET || S.g.bie == KFBI_BIE_TWO_DENSITY) a.s_need[pD] = 1;
   }
   if (lane < a.lat.nN) {
     a.stN[c * a.lat.nN + lane] = pN;

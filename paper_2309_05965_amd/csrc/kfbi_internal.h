@@ -138,6 +138,18 @@ struct kfbi_plan {
   double* sh_ws;                 // spherical-harmonic transfer workspace (learned start)
   int64_t sh_ws_cap;
   double* Firr;                  // [n_irr] corrected right-hand side at the irregular nodes (many pairs)
+  // two-density BIE (eq. bie-ifp-1): value interpolation weights, the plan
+  // of the exterior operator (same geometry, Lap - kappa_out), one-sided
+  // values at the DOFs, GMRES over [phi; psi]
+  double *IWv, *TIv;             // [n_dof][(q+1)^d] value weights, [n_dof][nC] their own-polynomial sums
+  kfbi_plan* aux;
+  bool is_aux;
+  double *tv_in, *tv_out;        // [cap_dof]
+  int64_t td_cap_dof;
+  double *td_V, *td_b, *td_w, *td_part, *td_h;   // basis [(m+1)][2 n], right-hand side, work, dot partials
+  double* h_td;                  // pinned host copy of the dots
+  int td_m;
+  int64_t td_n;
   int* IB;                       // [n_dof] first node of the interpolation block
   int* IE2;                      // [n_dof][(q+1)^d] entry of C^(reg q) at block nodes
                                  // inside another interface, -1 elsewhere
@@ -256,9 +268,14 @@ kfbi_status colloc_factor(kfbi_plan* pl);      // enqueues the factorisation and
 kfbi_status colloc_finish(kfbi_plan* pl);      // waits for that post: status flags, largest condition number
 // operator.hip (steps S2, S4, S5 and right-hand sides)
 void op_extend(kfbi_plan* pl, const double* psi, double* psiS);
-void op_coefficients(kfbi_plan* pl, const double* a, const double* b, const double* ftilde);
+void op_coefficients(kfbi_plan* pl, const double* a, const double* b, const double* ftilde,
+                     double bscale = 1.0, double fscale = 1.0);
 void op_correction_values(kfbi_plan* pl);
-void op_rhs_base(kfbi_plan* pl, const double* fhat, const double* gB, double* F, bool corrected = false);
+// fsel: fhat of every region (0), of the interiors only (1), of the exterior only (2)
+void op_rhs_base(kfbi_plan* pl, const double* fhat, const double* gB, double* F, bool corrected = false,
+                 int fsel = 0);
+// one-sided values at the DOFs with the value weights (two-density plans)
+void op_values(kfbi_plan* pl, const double* v, double* v_in, double* v_out);
 void op_rhs_correct(kfbi_plan* pl, double* F, bool overwrite);
 void op_boundary(kfbi_plan* pl, const double* gB, double* v);
 void op_normal_derivatives(kfbi_plan* pl, const double* v, double* dn_in, double* dn_out,
@@ -270,6 +287,18 @@ void op_matvec_tail(kfbi_plan* pl, const double* psi, double* Apsi);
 bool op_zero_mean_used(const kfbi_plan* pl);
 void op_bie_rhs(kfbi_plan* pl, const double* g2, const double* dn_in, const double* dn_out,
                 double* b);
+// twodensity.hip (eq. bie-ifp-1)
+kfbi_status td_setup(kfbi_plan* pl);
+void td_free(kfbi_plan* pl);
+kfbi_status td_matvec(kfbi_plan* pl, const double* x, double* out);
+kfbi_status td_rhs(kfbi_plan* pl, const kfbi_data* d, double* b);
+kfbi_status td_solve(kfbi_plan* pl, const kfbi_data* d, const kfbi_opts* o, double* x, double* u, kfbi_info* info);
+// api.hip: plan creation without the capture lock (for a plan made inside
+// another's set-up), the box solve of the plan's solver, a plan's release
+kfbi_status plan_create_impl(const kfbi_problem* prob, hipStream_t stream, kfbi_plan** out, bool is_aux = false);
+void plan_box_solve(kfbi_plan* pl, const double* F, double* v);
+kfbi_status plan_resetup(kfbi_plan* pl, const kfbi_problem* prob);   // S0 + S1 for another problem
+void plan_release(kfbi_plan* pl);
 // dst.hip (step S3)
 kfbi_status dst_init(kfbi_plan* pl);
 void dst_solve(kfbi_plan* pl, const double* F, double* v);

@@ -174,6 +174,7 @@ struct CoefArgs {
   int64_t n_dof;
   int n, nP, nD, nN;
   double h;
+  double bscale, fscale;   // b and ftilde enter multiplied by these (1 but for the two-density form)
   const double *MinvT, *MT;
   const double *a, *b, *ftilde;
   const int *stD, *stN;
@@ -205,11 +206,11 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_coef(CoefArgs a) {
     const int j = lane;
     double q = 0.0;
     if (j < a.nP) {
-      if (a.ftilde) q = (a.h * a.h) * a.ftilde[c * a.nP + j];
+      if (a.ftilde) q = (a.h * a.h) * (a.fscale * a.ftilde[c * a.nP + j]);
     } else if (j < a.nP + a.nD) {
       if (a.a) q = a.a[a.stD[c * a.nD + (j - a.nP)]];
     } else {
-      if (a.b) q = a.h * a.b[a.stN[c * a.nN + (j - a.nP - a.nD)]];
+      if (a.b) q = a.h * (a.bscale * a.b[a.stN[c * a.nN + (j - a.nP - a.nD)]]);
     }
     Qs[wv][j] = q;
   }
@@ -273,6 +274,7 @@ struct RhsArgs {
   const double *fhat, *gB;
   double* F;
   const double* Cg;   // non-null: the correction of k_rhs_correct is added in the same pass
+  int fsel;           // fhat of every region (0), the interiors only (1), the exterior only (2)
 };
 
 // F(P) = B_h fhat_{reg P}(P) - sum_{Q on the box boundary} A_PQ gB(Q); with
@@ -288,7 +290,9 @@ __global__ void k_rhs_base(RhsArgs a) {
     if (c[ax] < 1 || c[ax] > g.N - 1) return;
   int zr = g.d == 3 ? 1 : 0;
   double s = 0.0;
-  const double* f = a.fhat ? a.fhat + (int64_t)a.region[i] * g.n_nodes : nullptr;
+  const int ri = a.region[i];
+  const bool fon = a.fsel == 0 || (a.fsel == 1 ? ri != 0 : ri == 0);
+  const double* f = a.fhat && fon ? a.fhat + (int64_t)ri * g.n_nodes : nullptr;
   for (int o2 = -zr; o2 <= zr; ++o2)
     for (int o1 = -1; o1 <= 1; ++o1)
       for (int o0 = -1; o0 <= 1; ++o0) {
@@ -722,6 +726,7 @@ struct InterpArgs {
   const double *Cv, *GW, *HW, *TI, *psi;
   const int8_t* region;
   double *dn_in, *dn_out, *Apsi;
+  int value;             // 1: one-sided values (IW value weights, C_{h,p}(p) = U[0]); 0: normal derivatives
 };
 
 // one group of G lanes per centre: sum_b IW[c][b] vtilde(b), then the combine
@@ -782,7 +787,7 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_interp(InterpArgs a) {
   if (lane != 0) return;
   if (a.U) {
     const double* Uc = a.U + c * (int64_t)a.nC;
-    if (g.bie == KFBI_BIE_DIRICHLET) {
+    if (a.value) {
       dnC = Uc[0];   // value trace: the jump C_{h,p}(p)
     } else {
       const double* nv = a.snrm + (int64_t)s * g.d;
@@ -794,6 +799,82 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_interp(InterpArgs a) {
   if (a.dn_in) a.dn_in[c] = acc;
   if (a.dn_out) a.dn_out[c] = dout;
   if (a.Apsi) a.Apsi[c] = (g.beta_in * acc - g.beta_out * dout) / (g.beta_in + g.beta_out);
+}
+
+// Value weights of the interpolation blocks, for plans that need both
+// one-sided values and normal derivatives (the two-density BIE): IWv[c][b]
+// = prod_ax L_{b_ax}(t_ax), the tensor Lagrange basis of the block at the
+// centre (Sec. 5.5), in the order the value weights of a Dirichlet plan use.
+__global__ void k_fold_values(GridDesc g, int64_t n_dof, const int* d2s, const double* spos, const int* flags,
+                              double* IWv) {
+  if (*flags) return;
+  const int q = g.p, q1 = q + 1;
+  const int nbk = g.d == 3 ? q1 * q1 * q1 : q1 * q1;
+  int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  int64_t c = t / nbk;
+  int b = (int)(t % nbk);
+  if (c >= n_dof) return;
+  const double* P = spos + (int64_t)d2s[c] * g.d;
+  int bb[3] = {b % q1, (b / q1) % q1, b / (q1 * q1)};
+  double w = 1.0;
+  for (int ax = 0; ax < g.d; ++ax) {
+    double tt = (P[ax] - g.lo) / g.h;
+    int b0 = (int)floor(tt + 0.5) - q / 2;
+    if (b0 < 0) b0 = 0;
+    if (b0 > g.N - q) b0 = g.N - q;
+    double u = tt - (double)b0;
+    int j = bb[ax];
+    double v = 1.0;
+    for (int m = 0; m <= q; ++m)
+      if (m != j) v = v * (u - (double)m) / (double)(j - m);
+    w = w * v;
+  }
+  IWv[c * nbk + b] = w;
+}
+
+// TIv[c] = sum over the block nodes outside the centre's region of IWv *
+// monomials(xi_b): the centre's own polynomial in its value interpolation
+template <int D, int P>
+__global__ void __launch_bounds__(KFBI_BLOCK) k_fold_tiv(FoldArgs a, const double* IWv, double* TIv) {
+  if (*a.flags) return;
+  constexpr int NC = ncoef_t<D, P>();
+  constexpr int Q1 = P + 1;
+  constexpr int NBK = D == 3 ? Q1 * Q1 * Q1 : Q1 * Q1;
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = t / FOLD_G;
+  const int lane = (int)(t % FOLD_G);
+  if (c >= a.n_dof) return;   // whole groups leave together
+  const GridDesc& g = a.g;
+  const int s = a.d2s[c];
+  const int k = a.meta[(int64_t)s * 5 + 3];
+  const double* P0 = a.spos + (int64_t)s * D;
+  int st[3] = {0, 0, 0};
+  unravel(g, a.IB[c], st);
+  double T[NC];
+#pragma unroll
+  for (int al = 0; al < NC; ++al) T[al] = 0.0;
+  for (int b = lane; b < NBK; b += FOLD_G) {
+    const int bb[3] = {b % Q1, (b / Q1) % Q1, b / (Q1 * Q1)};
+    const int64_t Q = ravel(g, st[0] + bb[0], st[1] + bb[1], st[2] + bb[2]);
+    if (a.region[Q] == k) continue;
+    double xi[3] = {0.0, 0.0, 0.0};
+#pragma unroll
+    for (int ax = 0; ax < D; ++ax) xi[ax] = ((g.lo + (double)(st[ax] + bb[ax]) * g.h) - P0[ax]) / g.h;
+    double phi[NC];
+    monomials<D, P>(xi, phi);
+    const double w = IWv[c * NBK + b];
+#pragma unroll
+    for (int al = 0; al < NC; ++al) T[al] += w * phi[al];
+  }
+#pragma unroll
+  for (int off = FOLD_G / 2; off > 0; off >>= 1) {
+#pragma unroll
+    for (int al = 0; al < NC; ++al) T[al] += __shfl_xor(T[al], off, FOLD_G);
+  }
+  if (lane == 0) {
+#pragma unroll
+    for (int al = 0; al < NC; ++al) TIv[c * NC + al] = T[al];
+  }
 }
 
 // Zero-mean shift of a Neumann problem with kappa = 0 (Sec. 6.2.1): one
@@ -826,9 +907,10 @@ void op_extend(kfbi_plan* pl, const double* psi, double* psiS) {
                      pl->ext_idx, pl->ext_w, psi, psiS, pl->ctl_active, pl->V, pl->n_dof);
 }
 
-void op_coefficients(kfbi_plan* pl, const double* a, const double* b, const double* ftilde) {
-  CoefArgs A{pl->n_dof, pl->nC, pl->nP, pl->nD, pl->nN, pl->g.h, pl->MinvT, pl->MT, a, b, ftilde, pl->stD,
-             pl->stN, pl->U};
+void op_coefficients(kfbi_plan* pl, const double* a, const double* b, const double* ftilde, double bscale,
+                     double fscale) {
+  CoefArgs A{pl->n_dof, pl->nC, pl->nP, pl->nD, pl->nN, pl->g.h, bscale, fscale, pl->MinvT, pl->MT, a, b, ftilde,
+             pl->stD, pl->stN, pl->U};
   unsigned blocks = (unsigned)((pl->n_dof + COEF_WAVES - 1) / COEF_WAVES);
   hipLaunchKernelGGL(k_coef, dim3(blocks), dim3(KFBI_BLOCK), 0, pl->stream, A);
 }
@@ -840,8 +922,9 @@ void op_correction_values(kfbi_plan* pl) {
   hipLaunchKernelGGL(k_corr_values, dim3(nb(pl->n_corr)), dim3(KFBI_BLOCK), 0, pl->stream, A);
 }
 
-void op_rhs_base(kfbi_plan* pl, const double* fhat, const double* gB, double* F, bool corrected) {
-  RhsArgs A{pl->g, make_stencil(pl->g), pl->region, fhat, gB, F, corrected && pl->n_irr > 0 ? pl->Cg : nullptr};
+void op_rhs_base(kfbi_plan* pl, const double* fhat, const double* gB, double* F, bool corrected, int fsel) {
+  RhsArgs A{pl->g, make_stencil(pl->g), pl->region, fhat, gB, F, corrected && pl->n_irr > 0 ? pl->Cg : nullptr,
+            fsel};
   hipLaunchKernelGGL(k_rhs_base, dim3(nb(pl->g.n_nodes)), dim3(KFBI_BLOCK), 0, pl->stream, A);
 }
 
@@ -858,9 +941,10 @@ void op_boundary(kfbi_plan* pl, const double* gB, double* v) {
 
 namespace {
 void launch_interp(kfbi_plan* pl, const double* v, const double* U, const double* psi, double* dn_in,
-                   double* dn_out, double* Apsi) {
+                   double* dn_out, double* Apsi, bool values = false) {
   const int q1 = pl->g.p + 1;
   InterpArgs A;
+  A.value = values || pl->g.bie == KFBI_BIE_DIRICHLET ? 1 : 0;
   A.ctl = pl->ctl_active;
   A.Vb = pl->V;
   A.g = pl->g;
@@ -871,7 +955,7 @@ void launch_interp(kfbi_plan* pl, const double* v, const double* U, const double
   A.d2s = pl->d2s;
   A.meta = pl->s_meta;
   A.IB = pl->IB;
-  A.IW = pl->IW;
+  A.IW = values ? pl->IWv : pl->IW;
   A.U = U;
   A.snrm = pl->s_nrm;
   A.v = v;
@@ -881,7 +965,7 @@ void launch_interp(kfbi_plan* pl, const double* v, const double* U, const double
   A.Cv = pl->Cv;
   A.GW = pl->GW;
   A.HW = pl->HW;
-  A.TI = pl->TI;
+  A.TI = values ? pl->TIv : pl->TI;
   A.psi = psi;
   A.region = pl->region;
   A.dn_in = dn_in;
@@ -898,6 +982,10 @@ void launch_interp(kfbi_plan* pl, const double* v, const double* U, const double
 
 void op_normal_derivatives(kfbi_plan* pl, const double* v, double* dn_in, double* dn_out, double* Apsi) {
   launch_interp(pl, v, pl->U, nullptr, dn_in, dn_out, Apsi);
+}
+
+void op_values(kfbi_plan* pl, const double* v, double* v_in, double* v_out) {
+  launch_interp(pl, v, pl->U, nullptr, v_in, v_out, nullptr, true);
 }
 
 template <class T>
@@ -937,6 +1025,10 @@ kfbi_status op_fold(kfbi_plan* pl) {
     KCHK(regrow(&pl->IW, cap * nbk));
     KCHK(regrow(&pl->IE2, cap * nbk));
     KCHK(regrow(&pl->IB, cap));
+    if (g.bie == KFBI_BIE_TWO_DENSITY) {
+      KCHK(regrow(&pl->IWv, cap * nbk));
+      KCHK(regrow(&pl->TIv, cap * pl->nC));
+    }
     pl->cap_fold_dof = cap;
   }
   if (pl->n_irr > pl->cap_fold_irr) {
@@ -1008,6 +1100,15 @@ kfbi_status op_fold(kfbi_plan* pl) {
     if (g.d == 2 && g.p == 4) hipLaunchKernelGGL((k_fold_own<2, 4>), gr, bl, 0, pl->stream, A);
     if (g.d == 3 && g.p == 2) hipLaunchKernelGGL((k_fold_own<3, 2>), gr, bl, 0, pl->stream, A);
     if (g.d == 3 && g.p == 4) hipLaunchKernelGGL((k_fold_own<3, 4>), gr, bl, 0, pl->stream, A);
+  }
+  if (g.bie == KFBI_BIE_TWO_DENSITY) {
+    hipLaunchKernelGGL(k_fold_values, dim3(nb(pl->n_dof * nbk)), dim3(KFBI_BLOCK), 0, pl->stream, g, pl->n_dof,
+                       pl->d2s, pl->s_pos, pl->d_flags, pl->IWv);
+    dim3 gr(nb(pl->n_dof * FOLD_G)), bl(KFBI_BLOCK);
+    if (g.d == 2 && g.p == 2) hipLaunchKernelGGL((k_fold_tiv<2, 2>), gr, bl, 0, pl->stream, A, pl->IWv, pl->TIv);
+    if (g.d == 2 && g.p == 4) hipLaunchKernelGGL((k_fold_tiv<2, 4>), gr, bl, 0, pl->stream, A, pl->IWv, pl->TIv);
+    if (g.d == 3 && g.p == 2) hipLaunchKernelGGL((k_fold_tiv<3, 2>), gr, bl, 0, pl->stream, A, pl->IWv, pl->TIv);
+    if (g.d == 3 && g.p == 4) hipLaunchKernelGGL((k_fold_tiv<3, 4>), gr, bl, 0, pl->stream, A, pl->IWv, pl->TIv);
   }
   if (pl->n_irr > 0) {
     hipLaunchKernelGGL(k_fold_pairs, dim3(nb(pl->n_irr)), dim3(KFBI_BLOCK), 0, pl->stream, A);

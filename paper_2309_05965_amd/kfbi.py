@@ -15,7 +15,7 @@ _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkfbi.so")
 
 KINDS = {"ellipse2d": 1, "star2d": 2, "sphere3d": 3, "ellipsoid3d": 4, "torus3d": 5, "product3d": 6}
-BIE = {"interface": 0, "dirichlet": 1, "neumann": 2}
+BIE = {"interface": 0, "dirichlet": 1, "neumann": 2, "two_density": 3}
 STATUS = {0: "OK", 1: "INVALID", 2: "UNRESOLVED", 3: "SINGULAR", 4: "NOT_CONVERGED",
           5: "NONFINITE", 6: "DEVICE", 7: "OOM"}
 EXPORT = {"region": 0, "surf_pos": 1, "surf_nrm": 2, "surf_meta": 3, "dof_surf": 4,
@@ -35,7 +35,7 @@ class Problem(ctypes.Structure):
                 ("lo", ctypes.c_double), ("hi", ctypes.c_double),
                 ("beta_in", ctypes.c_double), ("beta_out", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("cos_alpha", ctypes.c_double),
-                ("iface", LevelSet * 4)]
+                ("kappa_out", ctypes.c_double), ("iface", LevelSet * 4)]
 
 
 class Sizes(ctypes.Structure):
@@ -188,6 +188,7 @@ def problem_struct(prob):
     s.lo, s.hi = prob["lo"], prob["hi"]
     s.beta_in, s.beta_out, s.kappa = prob["beta_in"], prob["beta_out"], prob["kappa"]
     s.cos_alpha = prob.get("cos_alpha", 0.5)
+    s.kappa_out = prob.get("kappa_out", prob["kappa"])
     for k, (kind, params) in enumerate(prob["ifaces"]):
         s.iface[k].kind = KINDS[kind]
         for j, v in enumerate(params):
@@ -245,6 +246,8 @@ class Plan:
         _check(load().kfbi_plan_sizes(self._h, ctypes.byref(s)))
         self.sizes = s
         self.n_nodes, self.n_surf, self.n_dof = s.n_nodes, s.n_surf, s.n_dof
+        # unknowns of the BIE: [phi; psi] for the two-density form
+        self.n_unknowns = s.n_dof * (2 if self.prob.get("bie") == "two_density" else 1)
 
     def setup(self, prob):
         """Re-run S0 + S1 for another problem on the same grid."""
@@ -343,7 +346,7 @@ class Plan:
         return v, dn_in, dn_out
 
     def matvec(self, psi, out=None):
-        out = self._zeros(self.n_dof) if out is None else out
+        out = self._zeros(self.n_unknowns) if out is None else out
         _check(load().kfbi_matvec(self._h, _ptr(psi), _ptr(out)))
         return out
 
@@ -353,7 +356,7 @@ class Plan:
                     _ptr(data["gB"]))
 
     def rhs(self, data):
-        b = self._zeros(self.n_dof)
+        b = self._zeros(self.n_unknowns)
         ds = self.data_struct(data)
         _check(load().kfbi_rhs(self._h, ctypes.byref(ds), _ptr(b)))
         return b
@@ -365,7 +368,7 @@ class Plan:
         solve); solver ("fft", "mg64", "mg32"; None keeps the plan's) with
         eps_in, max_cycles and relax set on the plan first."""
         # every entry of psi (from a zero start) and of u is written by the solve
-        psi = self._empty(self.n_dof) if psi0 is None else psi0.clone()
+        psi = self._empty(self.n_unknowns) if psi0 is None else psi0.clone()
         u = self._empty(self.n_nodes) if u_out is None else u_out
         ds = self.data_struct(data)
         start = "learned" if learned is not None else ("zero" if psi0 is None else "given")
@@ -416,6 +419,22 @@ def device_bvp_data(plan, prob, u):
     dev = plan.device
     return {k: None if v is None else
             torch.from_numpy(v.reshape(-1).copy() if k != "ftilde" else v.copy()).to(dev).contiguous()
+            for k, v in data.items()}
+
+
+def device_td_data(plan, prob, sol):
+    """Manufactured data of a two-density problem with the solutions `sol`
+    per region at the plan's own query points, as device tensors (input
+    generation; uses the workloads module)."""
+    from . import workloads as W
+    pos = plan.export("surf_pos").cpu().numpy()
+    nrm = plan.export("surf_nrm").cpu().numpy()
+    meta = plan.export("surf_meta").cpu().numpy()
+    pde = plan.export("pde_pts").cpu().numpy()
+    dsurf = plan.export("dof_surf").cpu().numpy()
+    data = W.make_td_data(prob, sol, pos, nrm, meta[:, 3], pde, meta[dsurf, 3])
+    dev = plan.device
+    return {k: torch.from_numpy(v.reshape(-1).copy()).to(dev).contiguous()
             for k, v in data.items()}
 
 
