@@ -72,14 +72,20 @@ typedef enum {
  *   TORUS3D     p = [cx, cy, cz, R, r]: H = (sqrt(dx^2+dy^2) - R)^2 + dz^2 - r^2
  *   PRODUCT3D   p = [cx, cy, cz, s]: X = s dx, Y = s dy, Z = s dz,
  *               H = (1+X^2)(1+Y^2)(1+Z^2) + 8XYZ + X^2 + Y^2 + Z^2 - 3
- *               (s = 2: the domain of the 3D Dirichlet example of Sec. 6.2.2) */
+ *               (s = 2: the domain of the 3D Dirichlet example of Sec. 6.2.2)
+ *   MOLECULE3D  p = [c, r, m, x1, y1, z1, ..., xm, ym, zm], 1 <= m <= 8:
+ *               H = c - sum_k E(-|x - x_k|^2 / r^2), the molecular surface of
+ *               Sec. 6.2.3, with E(t) = P(t/1024)^1024, P the degree-12 Taylor
+ *               polynomial of exp (Horner), ten squarings: exp to a relative
+ *               1e-13 on [-40, 0] from +, -, *, / only */
 enum {
   KFBI_LS_ELLIPSE2D = 1,
   KFBI_LS_STAR2D = 2,
   KFBI_LS_SPHERE3D = 3,
   KFBI_LS_ELLIPSOID3D = 4,
   KFBI_LS_TORUS3D = 5,
-  KFBI_LS_PRODUCT3D = 6
+  KFBI_LS_PRODUCT3D = 6,
+  KFBI_LS_MOLECULE3D = 7
 };
 
 /* Boundary integral equation of a problem (Sec. 3):
@@ -109,7 +115,7 @@ enum {
  *              learned start. */
 enum { KFBI_BIE_INTERFACE = 0, KFBI_BIE_DIRICHLET = 1, KFBI_BIE_NEUMANN = 2, KFBI_BIE_TWO_DENSITY = 3 };
 
-#define KFBI_MAX_IFACE 4
+#define KFBI_MAX_IFACE 10
 #define KFBI_LS_NPARAM 32
 
 typedef struct {

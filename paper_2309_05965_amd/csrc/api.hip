@@ -81,10 +81,17 @@ kfbi_status check_problem(const kfbi_problem* pr) {
     int kind = pr->iface[k].kind;
     bool two = kind == KFBI_LS_ELLIPSE2D || kind == KFBI_LS_STAR2D;
     bool three = kind == KFBI_LS_SPHERE3D || kind == KFBI_LS_ELLIPSOID3D || kind == KFBI_LS_TORUS3D ||
-                 kind == KFBI_LS_PRODUCT3D;
+                 kind == KFBI_LS_PRODUCT3D || kind == KFBI_LS_MOLECULE3D;
     if ((pr->dim == 2 && !two) || (pr->dim == 3 && !three)) {
       kfbi_set_error("level set %d: kind %d does not fit dim %d", k, kind, pr->dim);
       return KFBI_E_INVALID;
+    }
+    if (kind == KFBI_LS_MOLECULE3D) {
+      const double m = pr->iface[k].p[2];
+      if (!(m >= 1.0 && m <= 8.0 && m == (double)(int)m) || !(pr->iface[k].p[1] > 0.0)) {
+        kfbi_set_error("level set %d: a molecule needs 1..8 atoms and r > 0", k);
+        return KFBI_E_INVALID;
+      }
     }
   }
   return KFBI_OK;

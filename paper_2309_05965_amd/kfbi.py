@@ -14,7 +14,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkfbi.so")
 
-KINDS = {"ellipse2d": 1, "star2d": 2, "sphere3d": 3, "ellipsoid3d": 4, "torus3d": 5, "product3d": 6}
+KINDS = {"ellipse2d": 1, "star2d": 2, "sphere3d": 3, "ellipsoid3d": 4, "torus3d": 5, "product3d": 6, "molecule3d": 7}
 BIE = {"interface": 0, "dirichlet": 1, "neumann": 2, "two_density": 3}
 STATUS = {0: "OK", 1: "INVALID", 2: "UNRESOLVED", 3: "SINGULAR", 4: "NOT_CONVERGED",
           5: "NONFINITE", 6: "DEVICE", 7: "OOM"}
@@ -35,7 +35,7 @@ class Problem(ctypes.Structure):
                 ("lo", ctypes.c_double), ("hi", ctypes.c_double),
                 ("beta_in", ctypes.c_double), ("beta_out", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("cos_alpha", ctypes.c_double),
-                ("kappa_out", ctypes.c_double), ("iface", LevelSet * 4)]
+                ("kappa_out", ctypes.c_double), ("iface", LevelSet * 10)]
 
 
 class Sizes(ctypes.Structure):

@@ -54,6 +54,11 @@ def product3d(cx, cy, cz, s):
     return ("product3d", [cx, cy, cz, s])
 
 
+def molecule3d(level, r, atoms):
+    atoms = [float(v) for a in atoms for v in a]
+    return ("molecule3d", [level, r, len(atoms) // 3] + atoms)
+
+
 # ----------------------------------------------------------------------------
 # manufactured functions: each returns (value, grad tuple, laplacian)
 # ----------------------------------------------------------------------------
@@ -115,6 +120,34 @@ def f_e4(X):                            # exp(z) (cos 5x + cos 2y)
     e = np.exp(z)
     c5, c2 = np.cos(5 * x), np.cos(2 * y)
     return e * (c5 + c2), (-5 * e * np.sin(5 * x), -2 * e * np.sin(2 * y), e * (c5 + c2)), e * (-24 * c5 - 3 * c2)
+
+
+def f_e5_in(X):                         # sin^2(2x) cos^2(2y) cos z
+    x, y, z = X
+    A, B, C = np.sin(2 * x) ** 2, np.cos(2 * y) ** 2, np.cos(z)
+    A1, B1, C1 = 2 * np.sin(4 * x), -2 * np.sin(4 * y), -np.sin(z)
+    A2, B2 = 8 * np.cos(4 * x), -8 * np.cos(4 * y)
+    return A * B * C, (A1 * B * C, A * B1 * C, A * B * C1), A2 * B * C + A * B2 * C - A * B * C
+
+
+def f_cos3(X):                          # cos x cos y cos z
+    x, y, z = X
+    cx, cy, cz = np.cos(x), np.cos(y), np.cos(z)
+    v = cx * cy * cz
+    return v, (-np.sin(x) * cy * cz, -cx * np.sin(y) * cz, -cx * cy * np.sin(z)), -3.0 * v
+
+
+def f_e2_in(X):                         # exp(0.6 x + 0.8 y)
+    x, y = X[0], X[1]
+    e = np.exp(0.6 * x + 0.8 * y)
+    return e, (0.6 * e, 0.8 * e), e
+
+
+def f_e2_out(X):                        # sin(pi (x+1)/2) sin(pi (y+1)/2)
+    x, y = X[0], X[1]
+    k = math.pi / 2.0
+    sx, sy = np.sin(k * (x + 1)), np.sin(k * (y + 1))
+    return sx * sy, (k * np.cos(k * (x + 1)) * sy, k * sx * np.cos(k * (y + 1))), -2.0 * k * k * sx * sy
 
 
 def f_zero(X):
@@ -247,6 +280,41 @@ def bvp_exact(prob, u):
     """u at every node (compare on the nodes of Omega only)."""
     G = grid_coords(prob)
     return np.array(np.broadcast_to(u(G)[0], G[0].shape))
+
+
+def e2_circles_star(N=64, r=0.3826):
+    """Poisson interface problem with eight circles of radius r centred at
+    (cos(m pi/4), sin(m pi/4)) and a five-fold star r(t) = 0.514 (1 + 0.2 sin
+    5t) in [-1.7, 1.7]^2, sigma_i = 1, sigma_e = 3, u_i = exp(0.6x + 0.8y),
+    u_e = sin(pi(x+1)/2) sin(pi(y+1)/2) (paper Sec. 6.1.2, Table
+    2d-poi-ifp-mul).  The printed r = 0.383 makes neighbouring circles
+    overlap by 6e-4 (their centres are 2 sin(pi/8) = 0.76537 apart): r =
+    0.3826 keeps them 1.5e-4 apart; the star's angle is read as atan2."""
+    B = [0.0] * 8
+    B[4] = 0.514 * 0.2
+    ifs = [ellipse2d(math.cos(m * math.pi / 4), math.sin(m * math.pi / 4), r, r) for m in range(1, 9)]
+    ifs.append(star2d(0.0, 0.0, 0.514, None, B))
+    prob = problem(2, 4, N, -1.7, 1.7, 1.0, 3.0, 0.0, ifs)
+    sol = {0: f_e2_out}
+    for k in range(1, 10):
+        sol[k] = f_e2_in
+    return prob, sol
+
+
+MOLECULE_ATOMS = ((math.sqrt(3.0) / 3.0, 0.0, -math.sqrt(6.0) / 12.0),
+                  (-math.sqrt(3.0) / 6.0, 0.5, -math.sqrt(6.0) / 12.0),
+                  (-math.sqrt(3.0) / 6.0, -0.5, -math.sqrt(6.0) / 12.0),
+                  (0.0, 0.0, math.sqrt(6.0) / 4.0))
+
+
+def e5_molecule(N=128, ratio=10.0, r=0.5):
+    """Poisson interface problem with the four-atom molecular surface sum_k
+    exp(-|x - x_k|^2 / r^2) = 0.6 in [-1.2, 1.2]^3, sigma_i = 1, sigma_e =
+    ratio, u_i = sin^2(2x) cos^2(2y) cos z, u_e = cos x cos y cos z (paper
+    Sec. 6.2.3, Table 3d-ifp-ratio).  The paper does not give the atom
+    radius r: 0.5 is taken."""
+    prob = problem(3, 4, N, -1.2, 1.2, 1.0, float(ratio), 0.0, [molecule3d(0.6, r, MOLECULE_ATOMS)])
+    return prob, {0: f_cos3, 1: f_e5_in}
 
 
 # ----------------------------------------------------------------------------

@@ -41,6 +41,10 @@ CASES = {
                          {0: W.f_exp3, 1: W.f_sin3}),
     "ellipsoid_64": lambda: (W.config5(1_000_003, 64)[0], {0: W.f_exp3, 1: W.f_sin3}),
     "ellipsoid_128": lambda: (W.config5(1_000_003, 128)[0], {0: W.f_exp3, 1: W.f_sin3}),
+    # nine interfaces 1.5e-4 apart (eight circles around a star), the
+    # four-atom molecular surface (level set through the arithmetic exponential)
+    "circles_star_128": lambda: W.e2_circles_star(128),
+    "molecule_64": lambda: W.e5_molecule(64, 10.0),
 }
 
 _cache = {}
@@ -177,12 +181,16 @@ def test_matvec(name):
     ref = op.matvec(psi)
     out1 = gp.matvec(dev(psi))
     out2 = gp.matvec(dev(psi))
-    assert rel(host(out1), ref) < 1e-11
+    # the two sides sum in different orders; a local collocation system of
+    # condition number c amplifies those rounding differences about c-fold
+    # (the molecular surface at N = 64 has c = 2.5e8)
+    assert rel(host(out1), ref) < 1e-11 * max(1.0, op.cond.max() / 1e7)
     assert torch.equal(out1, out2)             # bitwise deterministic
 
 
 @pytest.mark.parametrize("name", ["c1_64", "c2_128", "c2_512", "sphere_32", "ellipse_o4_64", "circles2_o2_64",
-                                  "circles2_o4_64", "spheres2_64", "torus_sphere_64", "torus_64", "ellipsoid_128"])
+                                  "circles2_o4_64", "spheres2_64", "torus_sphere_64", "torus_64", "ellipsoid_128",
+                                  "circles_star_128"])
 def test_full_solve(name):
     """Full solves at GMRES tol 1e-13 (1e-12 at 128^3).  The ellipsoid runs at
     128^3: at 64^3 the thinnest parts of the surface are about ten grid
