@@ -10,7 +10,11 @@ library.
 Modules and their pins (tests/test_oracle_*.py, run with -m "not gpu")
   levelset     level-set functions H and their gradients (Sec. 5.1; the
                product3d family is the domain of the 3D Dirichlet example of
-               Sec. 6.2.2); pinned
+               Sec. 6.2.2, molecule3d the molecular surface of Sec. 6.2.3,
+               grid a level set known only at the nodes, Sec. 7); the grid
+               family is pinned by exact reproduction of polynomials, the
+               sampled sphere's analytic geometry and the sampled star's
+               solution (tests/test_oracle_sampled.py); the others
                by the closed-form normals and curvatures of the sample tests
                and the exact intersections of the geometry tests
   geometry     node regions, surface points, collocation stencils, density

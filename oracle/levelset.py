@@ -31,10 +31,19 @@ design notes):
               P(t / 1024)^1024 with P the degree-12 Taylor polynomial of exp
               in Horner form and ten squarings (relative error about 1e-13 for
               -40 <= t <= 0, far below any grid spacing's effect)
+  grid        [q, lo, hi, N] and the samples S (shape (N+1,)*d, x fastest) of
+              H at the nodes of the computational grid (the level set known
+              only at Cartesian nodes, Sec. 7): H is the tensor-product
+              Lagrange interpolant of degree q (3 or 5) on the (q+1)^d nodes
+              around the point's cell (base floor(t) - (q-1)/2 clamped to
+              [0, N-q] per axis, t = (x - lo)/h snapped to the nearest
+              integer within 1e-9, so that along a grid line it is the 1D
+              interpolant of that line and at a node it is the sample), its
+              gradient the gradient of the same polynomial
 """
 import numpy as np
 
-KINDS = ("ellipse2d", "star2d", "sphere3d", "ellipsoid3d", "torus3d", "product3d", "molecule3d")
+KINDS = ("ellipse2d", "star2d", "sphere3d", "ellipsoid3d", "torus3d", "product3d", "molecule3d", "grid")
 DIM_OF = {"ellipse2d": 2, "star2d": 2, "sphere3d": 3, "ellipsoid3d": 3, "torus3d": 3, "product3d": 3,
           "molecule3d": 3}
 NMODES = 8
@@ -173,15 +182,78 @@ _FUN = {"ellipse2d": _ellipse, "star2d": _star, "sphere3d": _sphere,
         "ellipsoid3d": _ellipsoid, "torus3d": _torus, "product3d": _product, "molecule3d": _molecule}
 
 
+def _axis_weights(x, lo, h, N, q):
+    """Stencil base, Lagrange weights and their derivatives (in t) of one
+    axis for the sampled level set."""
+    t = (np.asarray(x, dtype=np.float64) - lo) / h
+    r = np.floor(t + 0.5)
+    t = np.where(np.abs(t - r) < 1e-9, r, t)
+    base = np.clip(np.floor(t).astype(np.int64) - (q - 1) // 2, 0, N - q)
+    u = t - base.astype(np.float64)
+    W, D = [], []
+    for j in range(q + 1):
+        v = np.ones_like(u)
+        for m in range(q + 1):
+            if m != j:
+                v = v * (u - float(m)) / float(j - m)
+        dv = np.zeros_like(u)
+        for l in range(q + 1):
+            if l == j:
+                continue
+            w = np.ones_like(u) / float(j - l)
+            for m in range(q + 1):
+                if m != j and m != l:
+                    w = w * (u - float(m)) / float(j - m)
+            dv = dv + w
+        W.append(v)
+        D.append(dv)
+    return base, W, D
+
+
+def _grid(p, X, grad, S):
+    q, lo, hi, N = int(p[0]), float(p[1]), float(p[2]), int(p[3])
+    h = (hi - lo) / N
+    d = len(X)
+    S = np.asarray(S, dtype=np.float64).reshape(-1)
+    ax = [_axis_weights(X[a], lo, h, N, q) for a in range(d)]
+    n1 = N + 1
+    val = np.zeros(np.shape(X[0]))
+    gr = [np.zeros(np.shape(X[0])) for _ in range(d)]
+    for blk in np.ndindex(*(q + 1,) * d):
+        j = blk[::-1]                    # j[0] (x) varies fastest
+        idx = ax[0][0] + j[0]
+        mul = n1
+        for a in range(1, d):
+            idx = idx + (ax[a][0] + j[a]) * mul
+            mul = mul * n1
+        s = S[idx]
+        w = ax[0][1][j[0]]
+        for a in range(1, d):
+            w = w * ax[a][1][j[a]]
+        val = val + w * s
+        for g in range(d):
+            c = ax[0][2][j[0]] if g == 0 else ax[0][1][j[0]]
+            for a in range(1, d):
+                c = c * (ax[a][2][j[a]] if g == a else ax[a][1][j[a]])
+            gr[g] = gr[g] + c * s
+    if not grad:
+        return val
+    return tuple(gg / h for gg in gr)
+
+
 def H(iface, X):
     """Level-set value at points X = (x, y[, z]) (arrays of equal shape)."""
-    kind, p = iface
+    kind, p = iface[0], iface[1]
+    if kind == "grid":
+        return _grid(p, X, False, iface[2])
     return _FUN[kind](np.asarray(p, dtype=np.float64), X, False)
 
 
 def gradH(iface, X):
     """Gradient of H at points X, as a tuple of d arrays."""
-    kind, p = iface
+    kind, p = iface[0], iface[1]
+    if kind == "grid":
+        return _grid(p, X, True, iface[2])
     return _FUN[kind](np.asarray(p, dtype=np.float64), X, True)
 
 

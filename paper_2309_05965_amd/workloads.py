@@ -218,6 +218,36 @@ def config3(N=128):
 
 
 # ----------------------------------------------------------------------------
+# level sets given only at the grid nodes (Sec. 7)
+# ----------------------------------------------------------------------------
+def sampled(prob, H, q=5):
+    """A level set known only by its values H(node) at the nodes of the
+    problem's grid, read through the degree-q interpolant of the library:
+    ("grid", [q, lo, hi, N], samples) with samples[(z,) y, x]."""
+    G = grid_coords(prob)
+    S = np.array(np.broadcast_to(H(G), G[0].shape), dtype=np.float64)
+    return ("grid", [float(q), prob["lo"], prob["hi"], float(prob["N"])], S)
+
+
+def H_sphere(cx, cy, cz, r):
+    return lambda X: (X[0] - cx) ** 2 + (X[1] - cy) ** 2 + (X[2] - cz) ** 2 - r * r
+
+
+def H_torus(R, r):
+    return lambda X: (np.sqrt(X[0] ** 2 + X[1] ** 2) - R) ** 2 + X[2] ** 2 - r * r
+
+
+def H_star(c0, eps, m):
+    """rho - c0 (1 + eps sin(m theta)) with theta = atan2(y, x)."""
+    return lambda X: np.sqrt(X[0] ** 2 + X[1] ** 2) - c0 * (1.0 + eps * np.sin(m * np.arctan2(X[1], X[0])))
+
+
+def with_sampled(prob, H, q=5):
+    """The problem with its single interface replaced by the sampled H."""
+    return dict(prob, ifaces=[sampled(prob, H, q)])
+
+
+# ----------------------------------------------------------------------------
 # interior boundary value problems (Sec. 2.1): Omega = the interiors
 # ----------------------------------------------------------------------------
 BIE_KINDS = ("interface", "dirichlet", "neumann")
