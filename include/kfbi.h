@@ -77,7 +77,14 @@ typedef enum {
  *               H = c - sum_k E(-|x - x_k|^2 / r^2), the molecular surface of
  *               Sec. 6.2.3, with E(t) = P(t/1024)^1024, P the degree-12 Taylor
  *               polynomial of exp (Horner), ten squarings: exp to a relative
- *               1e-13 on [-40, 0] from +, -, *, / only */
+ *               1e-13 on [-40, 0] from +, -, *, / only
+ *   GRID        p = [q] (3 or 5), 2D or 3D: the level set known only at the
+ *               grid nodes (Sec. 7), from kfbi_problem.samples[k]: H is the
+ *               tensor-product Lagrange interpolant of degree q on the
+ *               (q+1)^d nodes around the point's cell (per axis base
+ *               floor(t) - (q-1)/2 clamped to [0, N-q], t = (x - lo)/h
+ *               snapped to the nearest integer within 1e-9), grad H the
+ *               gradient of the same polynomial; H at a node is its sample */
 enum {
   KFBI_LS_ELLIPSE2D = 1,
   KFBI_LS_STAR2D = 2,
@@ -85,7 +92,8 @@ enum {
   KFBI_LS_ELLIPSOID3D = 4,
   KFBI_LS_TORUS3D = 5,
   KFBI_LS_PRODUCT3D = 6,
-  KFBI_LS_MOLECULE3D = 7
+  KFBI_LS_MOLECULE3D = 7,
+  KFBI_LS_GRID = 8
 };
 
 /* Boundary integral equation of a problem (Sec. 3):
@@ -131,7 +139,10 @@ typedef struct {
  * reduced reaction coefficient kappa_i / beta_i (equal on both sides);
  * cos_alpha in (0, 1/sqrt(dim)) defines the overlapping surface sets
  * Gamma_r = {|n_r| > cos alpha} (Sec. 5.1); bie one of KFBI_BIE_*;
- * kappa_out the exterior's reduced coefficient (KFBI_BIE_TWO_DENSITY only). */
+ * kappa_out the exterior's reduced coefficient (KFBI_BIE_TWO_DENSITY only);
+ * samples[k] (KFBI_LS_GRID interfaces only): device array of the (N+1)^dim
+ * node values of H_k, x fastest, read by kfbi_plan_create / kfbi_plan_setup
+ * (the plan keeps a copy). */
 typedef struct {
   int32_t dim, order, N, n_iface;
   int32_t bie, reserved;
@@ -139,6 +150,7 @@ typedef struct {
   double beta_in, beta_out, kappa, cos_alpha;
   double kappa_out;
   kfbi_levelset iface[KFBI_MAX_IFACE];
+  const double* samples[KFBI_MAX_IFACE];
 } kfbi_problem;
 
 typedef struct kfbi_plan kfbi_plan;

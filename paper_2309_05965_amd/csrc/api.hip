@@ -79,6 +79,14 @@ kfbi_status check_problem(const kfbi_problem* pr) {
   }
   for (int k = 0; k < pr->n_iface; ++k) {
     int kind = pr->iface[k].kind;
+    if (kind == KFBI_LS_GRID) {
+      const double q = pr->iface[k].p[0];
+      if (!(q == 3.0 || q == 5.0) || !pr->samples[k]) {
+        kfbi_set_error("level set %d: a sampled level set needs degree 3 or 5 and samples", k);
+        return KFBI_E_INVALID;
+      }
+      continue;
+    }
     bool two = kind == KFBI_LS_ELLIPSE2D || kind == KFBI_LS_STAR2D;
     bool three = kind == KFBI_LS_SPHERE3D || kind == KFBI_LS_ELLIPSOID3D || kind == KFBI_LS_TORUS3D ||
                  kind == KFBI_LS_PRODUCT3D || kind == KFBI_LS_MOLECULE3D;
@@ -99,6 +107,7 @@ kfbi_status check_problem(const kfbi_problem* pr) {
 
 void free_plan(kfbi_plan* pl) {
   td_free(pl);
+  dfree(pl->ls_samples);
   dfree(pl->region);
   dfree(pl->need);
   dfree(pl->Cg);

@@ -35,6 +35,10 @@ struct LSet {
   int K;
   int kind[KFBI_MAX_IFACE];
   double p[KFBI_MAX_IFACE][KFBI_LS_NPARAM];
+  // sampled level sets: the plan's copy of the node samples, and the grid
+  const double* S[KFBI_MAX_IFACE];
+  double lo, h;
+  int N, d;
 };
 
 // Collocation lattices and window shifts (host-built, mirrors of the lattice
@@ -60,9 +64,82 @@ __device__ double exp_arith(double t) {
   return s;
 }
 
+// Sampled level set (the level set known only at the grid nodes): the
+// tensor-product Lagrange interpolant of degree q on the (q+1)^d nodes
+// around the point's cell, per axis base floor(t) - (q-1)/2 clamped to
+// [0, N-q], t = (x - lo)/h snapped to the nearest integer within 1e-9 (on a
+// grid line the interpolant is the line's 1D one, at a node the sample).
+// grad != null: the gradient of the same polynomial instead of the value.
+constexpr int LS_QMAX = 5;
+__device__ double ls_grid(const LSet& L, int k, const double X[3], double* grad) {
+  const int q = (int)L.p[k][0];
+  int base[3] = {0, 0, 0};
+  double W[3][LS_QMAX + 1], D[3][LS_QMAX + 1];
+  for (int a = 0; a < L.d; ++a) {
+    double t = (X[a] - L.lo) / L.h;
+    const double r = floor(t + 0.5);
+    if (fabs(t - r) < 1e-9) t = r;
+    int b = (int)floor(t) - (q - 1) / 2;
+    if (b < 0) b = 0;
+    if (b > L.N - q) b = L.N - q;
+    base[a] = b;
+    const double u = t - (double)b;
+    for (int j = 0; j <= q; ++j) {
+      double v = 1.0;
+      for (int m = 0; m <= q; ++m)
+        if (m != j) v = v * (u - (double)m) / (double)(j - m);
+      double dv = 0.0;
+      for (int l = 0; l <= q; ++l) {
+        if (l == j) continue;
+        double w = 1.0 / (double)(j - l);
+        for (int m = 0; m <= q; ++m)
+          if (m != j && m != l) w = w * (u - (double)m) / (double)(j - m);
+        dv = dv + w;
+      }
+      W[a][j] = v;
+      D[a][j] = dv;
+    }
+  }
+  const double* S = L.S[k];
+  const int64_t n1 = L.N + 1;
+  const int q2 = L.d == 3 ? q : 0;
+  double val = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
+  for (int j2 = 0; j2 <= q2; ++j2)
+    for (int j1 = 0; j1 <= q; ++j1)
+      for (int j0 = 0; j0 <= q; ++j0) {
+        int64_t idx = (int64_t)(base[0] + j0) + (int64_t)(base[1] + j1) * n1;
+        if (L.d == 3) idx = idx + (int64_t)(base[2] + j2) * (n1 * n1);
+        const double s = S[idx];
+        if (!grad) {
+          double w = W[0][j0] * W[1][j1];
+          if (L.d == 3) w = w * W[2][j2];
+          val = val + w * s;
+        } else {
+          double c0 = D[0][j0] * W[1][j1], c1 = W[0][j0] * D[1][j1];
+          if (L.d == 3) {
+            c0 = c0 * W[2][j2];
+            c1 = c1 * W[2][j2];
+            g2 = g2 + (W[0][j0] * W[1][j1] * D[2][j2]) * s;
+          }
+          g0 = g0 + c0 * s;
+          g1 = g1 + c1 * s;
+        }
+      }
+  if (grad) {
+    grad[0] = g0 / L.h;
+    grad[1] = g1 / L.h;
+    grad[2] = L.d == 3 ? g2 / L.h : 0.0;
+  }
+  return val;
+}
+
 __device__ double ls_value(const LSet& L, int k, double x, double y, double z) {
   const double* p = L.p[k];
   switch (L.kind[k]) {
+    case KFBI_LS_GRID: {
+      const double X[3] = {x, y, z};
+      return ls_grid(L, k, X, nullptr);
+    }
     case KFBI_LS_ELLIPSE2D: {
       double dx = x - p[0], dy = y - p[1];
       double XX = p[2] * dx + p[3] * dy;
@@ -134,6 +211,11 @@ __device__ void ls_grad(const LSet& L, int k, double x, double y, double z, doub
   const double* p = L.p[k];
   g[0] = g[1] = g[2] = 0.0;
   switch (L.kind[k]) {
+    case KFBI_LS_GRID: {
+      const double X[3] = {x, y, z};
+      (void)ls_grid(L, k, X, g);
+      return;
+    }
     case KFBI_LS_ELLIPSE2D: {
       double dx = x - p[0], dy = y - p[1];
       double XX = p[2] * dx + p[3] * dy;
@@ -416,7 +498,10 @@ __global__ void k_regions(RegionArgs a) {
   double x = node_x(a.g, c[0]), y = node_x(a.g, c[1]), z = a.g.d == 3 ? node_x(a.g, c[2]) : 0.0;
   int reg = 0, fl = 0;
   for (int k = 0; k < a.L.K; ++k) {
-    if (ls_value(a.L, k, x, y, z) < 0.0) {
+    // a sampled level set at a node is its sample (the interpolant's
+    // weights there are exactly one and zeros)
+    const double hv = a.L.kind[k] == KFBI_LS_GRID ? a.L.S[k][i] : ls_value(a.L, k, x, y, z);
+    if (hv < 0.0) {
       if (reg != 0) fl |= FLAG_OVERLAP;
       reg = k + 1;
     }
@@ -1414,10 +1499,31 @@ kfbi_status geo_setup(kfbi_plan* pl) {
   GridDesc g = pl->g;
   hipStream_t st = pl->stream;
   LSet L;
+  bool sampled = false;
+  for (int k = 0; k < g.K; ++k) sampled = sampled || pl->prob.iface[k].kind == KFBI_LS_GRID;
+  if (sampled && !pl->ls_samples) {
+    if (hipMalloc((void**)&pl->ls_samples, sizeof(double) * (size_t)g.K * g.n_nodes) != hipSuccess) {
+      (void)hipGetLastError();
+      pl->ls_samples = nullptr;
+      kfbi_set_error("device allocation of the level-set samples failed");
+      return KFBI_E_OOM;
+    }
+  }
   L.K = g.K;
+  L.lo = g.lo;
+  L.h = g.h;
+  L.N = g.N;
+  L.d = g.d;
   for (int k = 0; k < g.K; ++k) {
     L.kind[k] = pl->prob.iface[k].kind;
     for (int j = 0; j < KFBI_LS_NPARAM; ++j) L.p[k][j] = pl->prob.iface[k].p[j];
+    L.S[k] = nullptr;
+    if (L.kind[k] == KFBI_LS_GRID) {
+      // the plan's own copy of the samples (the caller's may go away)
+      double* dst = pl->ls_samples + (int64_t)k * g.n_nodes;
+      HIPCHK(hipMemcpyAsync(dst, pl->prob.samples[k], sizeof(double) * g.n_nodes, hipMemcpyDeviceToDevice, st));
+      L.S[k] = dst;
+    }
   }
   // every grid-sized table that the set-up fills sparsely starts from its
   // reset value: one launch instead of a memset each

@@ -138,6 +138,7 @@ struct kfbi_plan {
   double* sh_ws;                 // spherical-harmonic transfer workspace (learned start)
   int64_t sh_ws_cap;
   double* Firr;                  // [n_irr] corrected right-hand side at the irregular nodes (many pairs)
+  double* ls_samples;            // [K][n_nodes] the plan's copy of sampled level sets
   // two-density BIE (eq. bie-ifp-1): value interpolation weights, the plan
   // of the exterior operator (same geometry, Lap - kappa_out), one-sided
   // values at the DOFs, GMRES over [phi; psi]

@@ -14,7 +14,7 @@ import torch
 _HERE = os.path.dirname(os.path.abspath(__file__))
 LIB_PATH = os.path.join(_HERE, "libkfbi.so")
 
-KINDS = {"ellipse2d": 1, "star2d": 2, "sphere3d": 3, "ellipsoid3d": 4, "torus3d": 5, "product3d": 6, "molecule3d": 7}
+KINDS = {"ellipse2d": 1, "star2d": 2, "sphere3d": 3, "ellipsoid3d": 4, "torus3d": 5, "product3d": 6, "molecule3d": 7, "grid": 8}
 BIE = {"interface": 0, "dirichlet": 1, "neumann": 2, "two_density": 3}
 STATUS = {0: "OK", 1: "INVALID", 2: "UNRESOLVED", 3: "SINGULAR", 4: "NOT_CONVERGED",
           5: "NONFINITE", 6: "DEVICE", 7: "OOM"}
@@ -35,7 +35,7 @@ class Problem(ctypes.Structure):
                 ("lo", ctypes.c_double), ("hi", ctypes.c_double),
                 ("beta_in", ctypes.c_double), ("beta_out", ctypes.c_double),
                 ("kappa", ctypes.c_double), ("cos_alpha", ctypes.c_double),
-                ("kappa_out", ctypes.c_double), ("iface", LevelSet * 10)]
+                ("kappa_out", ctypes.c_double), ("iface", LevelSet * 10), ("samples", ctypes.c_void_p * 10)]
 
 
 class Sizes(ctypes.Structure):
@@ -180,7 +180,7 @@ def _check(st):
         raise KfbiError(st, load().kfbi_last_error().decode())
 
 
-def problem_struct(prob):
+def problem_struct(prob, samples=None):
     s = Problem()
     s.dim, s.order, s.N = prob["dim"], prob["order"], prob["N"]
     s.n_iface = len(prob["ifaces"])
@@ -189,11 +189,23 @@ def problem_struct(prob):
     s.beta_in, s.beta_out, s.kappa = prob["beta_in"], prob["beta_out"], prob["kappa"]
     s.cos_alpha = prob.get("cos_alpha", 0.5)
     s.kappa_out = prob.get("kappa_out", prob["kappa"])
-    for k, (kind, params) in enumerate(prob["ifaces"]):
+    for k, iface in enumerate(prob["ifaces"]):
+        kind, params = iface[0], iface[1]
         s.iface[k].kind = KINDS[kind]
         for j, v in enumerate(params):
             s.iface[k].p[j] = float(v)
+        if kind == "grid":
+            if samples is None or samples[k] is None:
+                raise ValueError("a sampled level set needs its samples on the device")
+            s.samples[k] = samples[k].data_ptr()
     return s
+
+
+def device_samples(prob, device):
+    """Device copies of the node samples of the problem's sampled level sets
+    (None for the analytic ones); they must live while a set-up reads them."""
+    return [torch.as_tensor(i[2], dtype=torch.float64).reshape(-1).to(device).contiguous() if i[0] == "grid" else None
+            for i in prob["ifaces"]]
 
 
 def _ptr(t):
@@ -213,7 +225,8 @@ class Plan:
         self.device = torch.device(device)
         self.stream = torch.cuda.current_stream(self.device)
         self.prob = prob
-        self._p = problem_struct(prob)
+        self._samples = device_samples(prob, self.device)
+        self._p = problem_struct(prob, self._samples)
         h = ctypes.c_void_p()
         st = lib.kfbi_plan_create(ctypes.byref(self._p), ctypes.c_void_p(self.stream.cuda_stream),
                                   ctypes.byref(h))
@@ -235,7 +248,8 @@ class Plan:
         self.stream = torch.cuda.ExternalStream(st.value, device=self.device) if st.value else \
             torch.cuda.default_stream(self.device)
         self.prob = prob
-        self._p = problem_struct(prob)
+        self._samples = device_samples(prob, self.device)
+        self._p = problem_struct(prob, self._samples)
         self._h = ctypes.c_void_p(handle)
         self._owned = False
         self._sizes()
@@ -252,7 +266,8 @@ class Plan:
     def setup(self, prob):
         """Re-run S0 + S1 for another problem on the same grid."""
         self.prob = prob
-        self._p = problem_struct(prob)
+        self._samples = device_samples(prob, self.device)
+        self._p = problem_struct(prob, self._samples)
         _check(load().kfbi_plan_setup(self._h, ctypes.byref(self._p)))
         self._sizes()
 
@@ -461,7 +476,8 @@ class Batch:
         lib = load()
         self.probs = list(probs)
         self.n = len(probs)
-        arr = (Problem * self.n)(*[problem_struct(p) for p in probs])
+        self._samples = [device_samples(p, torch.device("cuda")) for p in probs]
+        arr = (Problem * self.n)(*[problem_struct(p, sm) for p, sm in zip(probs, self._samples)])
         self._arr = arr
         h = ctypes.c_void_p()
         _check(lib.kfbi_batch_create(ctypes.cast(arr, ctypes.c_void_p), self.n, int(workers), ctypes.byref(h)))

@@ -59,7 +59,8 @@ class BatchData:
     def __init__(self, probs, kinds, psi_stride=0):
         g = load()
         n = len(probs)
-        self._arr = (kfbi.Problem * n)(*[kfbi.problem_struct(p) for p in probs])
+        self._samples = [kfbi.device_samples(p, "cuda") for p in probs]
+        self._arr = (kfbi.Problem * n)(*[kfbi.problem_struct(p, sm) for p, sm in zip(probs, self._samples)])
         km = (ctypes.c_int * n)(*[KIND[k] for k in kinds])
         self.psi = torch.zeros(n * psi_stride, dtype=torch.float64, device="cuda") if psi_stride else None
         h = ctypes.c_void_p()

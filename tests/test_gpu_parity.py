@@ -45,6 +45,14 @@ CASES = {
     # four-atom molecular surface (level set through the arithmetic exponential)
     "circles_star_128": lambda: W.e2_circles_star(128),
     "molecule_64": lambda: W.e5_molecule(64, 10.0),
+    # level sets known only at the grid nodes (quintic interpolant)
+    "sampled_sphere_32": lambda: (W.with_sampled(W.problem(3, 4, 32, -1.0, 1.0, 1.0, 5.0, 0.5, []),
+                                                 W.H_sphere(0.03, -0.02, 0.01, 0.52)),
+                                  {0: W.f_exp3, 1: W.f_sin3}),
+    "sampled_star_128": lambda: (W.with_sampled(W.config2(128)[0], W.H_star(0.5, 0.3, 5)), W.config2(128)[1]),
+    "sampled_torus_64": lambda: (W.with_sampled(W.problem(3, 4, 64, -1.0, 1.0, 1.0, 100.0, 0.0, []),
+                                                W.H_torus(0.6, 0.25), 3),
+                                 {0: W.f_exp3, 1: W.f_sin3}),
 }
 
 _cache = {}
@@ -190,7 +198,7 @@ def test_matvec(name):
 
 @pytest.mark.parametrize("name", ["c1_64", "c2_128", "c2_512", "sphere_32", "ellipse_o4_64", "circles2_o2_64",
                                   "circles2_o4_64", "spheres2_64", "torus_sphere_64", "torus_64", "ellipsoid_128",
-                                  "circles_star_128"])
+                                  "circles_star_128", "sampled_sphere_32", "sampled_star_128", "sampled_torus_64"])
 def test_full_solve(name):
     """Full solves at GMRES tol 1e-13 (1e-12 at 128^3).  The ellipsoid runs at
     128^3: at 64^3 the thinnest parts of the surface are about ten grid
