@@ -40,6 +40,9 @@ PAPER = {
                    512: (10, 2.29e-10, 1.02e-09, 7.59e-11, 1.06e-09)},
            1e4: {128: (14, 5.86e-08, 2.81e-07, 1.94e-08, 2.99e-07), 256: (11, 3.68e-09, 1.66e-08, 1.21e-09, 1.75e-08),
                  512: (10, 2.33e-10, 1.05e-09, 7.83e-11, 1.09e-09)}},
+    # E6: (N_b, iterations, max error in the torus, in the ellipsoid, outside)
+    "E6": {64: (8738, 22, 2.33e-03, 5.56e-05, 3.24e-03), 128: (34866, 21, 6.75e-07, 7.72e-07, 5.97e-07),
+           256: (139454, 19, 4.38e-08, 4.39e-08, 3.65e-08), 512: (557794, 17, 2.13e-09, 2.11e-09, 2.06e-09)},
     "E7": {64: (6987, 21, 6.71e-06, 3.89e-06), 128: (27939, 20, 4.79e-07, 2.65e-07),
            256: (111774, 20, 3.32e-08, 1.73e-08), 512: (447264, 20, 2.26e-09, 1.15e-09)},
 }
@@ -62,6 +65,8 @@ def run_case(case, N, ratio=None, device="cuda"):
         prob, sol = W.e4_dirichlet(N)
     elif case == "E5":
         prob, sol = W.e5_molecule(N, ratio)
+    elif case == "E6":
+        prob, sol = W.e6_touching(N)
     elif case == "E7":
         prob, sol = W.e7_heterogeneous(N)
     else:
@@ -121,6 +126,8 @@ def table(rows):
             pnb, pit = (p[0], p[1]) if p else (None, None)
             if c in ("E1", "E3", "E4"):
                 pin, pout = (p[3] if p else None), None
+            elif c == "E6":
+                pin, pout = (max(p[2], p[3]) if p else None), (p[4] if p else None)
             else:
                 pin, pout = (p[2] if p else None), (p[3] if p else None)
             name = c
@@ -134,12 +141,12 @@ def table(rows):
 
 def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
-    ap.add_argument("--cases", default="E1,E2,E3,E4,E5,E7")
+    ap.add_argument("--cases", default="E1,E2,E3,E4,E5,E6,E7")
     ap.add_argument("--max-n", type=int, default=512)
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     grids = {"E1": (64, 128, 256, 512, 1024), "E2": (64, 128, 256, 512, 1024), "E3": (64, 128, 256, 512),
-             "E4": (64, 128, 256, 512), "E5": (128, 256, 512), "E7": (64, 128, 256, 512)}
+             "E4": (64, 128, 256, 512), "E5": (128, 256, 512), "E6": (64, 128, 256, 512), "E7": (64, 128, 256, 512)}
     rows = []
     for c in a.cases.split(","):
         for N in grids[c]:

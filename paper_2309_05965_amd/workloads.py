@@ -331,6 +331,18 @@ def e2_circles_star(N=64, r=0.3826):
     return prob, sol
 
 
+def e6_touching(N=64):
+    """Poisson interface problem with a torus (1 - sqrt(x^2+y^2))^2 + z^2 =
+    0.4^2 and the ellipsoid x^2/0.36 + y^2/0.36 + z^2 = 1, which touch along
+    the circle x^2 + y^2 = 0.36, z = 0, in [-1.5, 1.5]^3, sigma_i = 1,
+    sigma_e = 3, u = sin^2(2x) cos^2(2y) cos z in the torus, exp(z)(cos 2x +
+    cos 3y) in the ellipsoid, cos x cos y cos z outside (paper Sec. 6.2.4,
+    Table poi-ifp-3d-toch-cur)."""
+    prob = problem(3, 4, N, -1.5, 1.5, 1.0, 3.0, 0.0,
+                   [torus3d(0.0, 0.0, 0.0, 1.0, 0.4), ellipsoid3d((0.0, 0.0, 0.0), (0.6, 0.6, 1.0), np.eye(3))])
+    return prob, {0: f_cos3, 1: f_e5_in, 2: f_e3}
+
+
 MOLECULE_ATOMS = ((math.sqrt(3.0) / 3.0, 0.0, -math.sqrt(6.0) / 12.0),
                   (-math.sqrt(3.0) / 6.0, 0.5, -math.sqrt(6.0) / 12.0),
                   (-math.sqrt(3.0) / 6.0, -0.5, -math.sqrt(6.0) / 12.0),

@@ -2,9 +2,10 @@
 at paper level: GMRES iteration counts within a few of the printed ones
 and error maxima within the stated factors, on the grids where the
 discretisation is resolved (the coarsest 3D grids of the product domain,
-the torus and the three spheres have local collocation systems with
-condition numbers of 1e5-1e7 and are outside these bounds; the full table
-with every grid is the reproduction summary).  Readings where the paper is
+the torus and the three spheres, and the touching torus and ellipsoid up to
+256^3, have local collocation systems with condition numbers of 1e5-1e7 and
+need more iterations than printed; the full table with every grid is the
+reproduction summary).  Readings where the paper is
 silent: E2 circle radius 0.3826, E5 atom radius 0.5, E7 box and exact
 solution (its errors are therefore not compared)."""
 import pytest
@@ -17,15 +18,19 @@ from paper_2309_05965_amd import paper_tables as PT  # noqa: E402
 
 
 @pytest.mark.parametrize("case,N,it_tol,err_fac", [("E1", 128, 2, 4.0), ("E1", 256, 2, 4.0), ("E1", 512, 2, 4.0),
-                                                   ("E1", 1024, 2, 4.0), ("E2", 512, 2, 4.0),
-                                                   ("E3", 128, 2, 8.0), ("E3", 256, 2, 8.0), ("E4", 512, 1, None)])
+                                                   ("E1", 1024, 2, 4.0), ("E2", 512, 2, 4.0), ("E2", 1024, 2, 4.0),
+                                                   ("E3", 128, 2, 8.0), ("E3", 256, 2, 8.0), ("E4", 512, 1, None),
+                                                   ("E6", 128, None, 4.0)])
 def test_single_density_and_bvp_tables(case, N, it_tol, err_fac):
+    """(E6, the touching torus and ellipsoid: errors only; its iteration
+    counts are about twice the printed ones, see the module docstring.)"""
     r = PT.run_case(case, N)
     p = PT.PAPER[case][N]
     assert r["status"] == 0
-    assert abs(r["iters"] - p[1]) <= it_tol, (r["iters"], p)
+    if it_tol is not None:
+        assert abs(r["iters"] - p[1]) <= it_tol, (r["iters"], p)
     if err_fac is not None:
-        printed = p[3] if case in ("E1", "E3", "E4") else p[2]
+        printed = p[3] if case in ("E1", "E3", "E4") else (max(p[2], p[3]) if case == "E6" else p[2])
         assert printed / err_fac < r["in"][1] < printed * err_fac, (r["in"], p)
 
 

@@ -93,8 +93,9 @@ def _paper_nb():
 @pytest.mark.parametrize("case,N,nb", [r for r in _paper_nb() if r[0] in ("E1", "E2") or r[1] == 64])
 def test_primary_count_matches_paper(case, N, nb):
     """The primary points (argmax family) reproduce the N_b printed in the
-    paper's Tables 2d-poi-o4, 2d-poi-ifp-mul, 3d-neu-poi and 3d-ifp-heter
-    within 2% (for the last, with the box [-1.5, 1.5]^3 read for it)."""
+    paper's Tables 2d-poi-o4, 2d-poi-ifp-mul, 3d-neu-poi, poi-ifp-3d-toch-cur
+    and 3d-ifp-heter within 2% (for the last, with the box [-1.5, 1.5]^3
+    read for it)."""
     if case == "E1":
         prob = W.problem(2, 4, N, -1.2, 1.2, 1.0, 1.0, 0.0,
                          [W.ellipse2d(0.0, 0.0, 1.0, 0.5, theta=-math.pi / 6)])
@@ -102,6 +103,8 @@ def test_primary_count_matches_paper(case, N, nb):
         prob = W.e2_circles_star(N)[0]
     elif case == "E7":
         prob = W.e7_heterogeneous(N)[0]
+    elif case == "E6":
+        prob = W.e6_touching(N)[0]
     else:
         prob = W.problem(3, 4, N, -1.5, 1.5, 1.0, 1.0, 0.0, [W.torus3d(0.0, 0.0, 0.0, 1.0, 0.4)])
     sp = G.surface_points(prob, G.node_regions(prob))
