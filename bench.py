@@ -355,6 +355,66 @@ def forms_config3(tol, N):
     return out
 
 
+def forms_widened(tol, reps=5):
+    """The widened rows on repeated problems (FFT box solver, GMRES to tol):
+    the interior Neumann problem in the torus and the two-density
+    three-sphere problem at 128^3, the molecular surface at contrast 1e4:1,
+    and the torus of the 3D workload given only by its node samples next to
+    the same torus given analytically.  Solve time with the plan set up and
+    the data resident; the set-up (S0 + S1) timed separately; maximum error
+    against the exact solution on the nodes of the solution's regions."""
+    import torch
+    from paper_2309_05965_amd import kfbi
+    from paper_2309_05965_amd import workloads as W
+    torus = W.problem(3, 4, 128, -1.0, 1.0, 1.0, 100.0, 0.0, [W.torus3d(0.0, 0.0, 0.0, 0.6, 0.25)])
+    cases = {
+        "neumann_torus128": W.e3_neumann(128),
+        "two_density_three_spheres128": W.e7_heterogeneous(128),
+        "molecule128_contrast1e4": W.e5_molecule(128, 1e4),
+        "torus128_analytic": (torus, {0: W.f_exp3, 1: W.f_sin3}),
+        "torus128_sampled_quintic": (W.with_sampled(torus, W.H_torus(0.6, 0.25), 5), {0: W.f_exp3, 1: W.f_sin3}),
+    }
+    out = {}
+    for name, (prob, sol) in cases.items():
+        bie = prob.get("bie", "interface")
+        plan = kfbi.Plan(prob)
+        if bie in ("dirichlet", "neumann"):
+            data = kfbi.device_bvp_data(plan, prob, sol)
+        elif bie == "two_density":
+            data = kfbi.device_td_data(plan, prob, sol)
+        else:
+            data = kfbi.device_data(plan, prob, sol)
+        u = torch.empty(plan.n_nodes, dtype=torch.float64, device="cuda")
+        plan.solve(data, tol=tol, u_out=u, max_iter=300)
+        torch.cuda.synchronize()
+        t0 = time.perf_counter()
+        for _ in range(reps):
+            _, _, info = plan.solve(data, tol=tol, u_out=u, max_iter=300)
+        torch.cuda.synchronize()
+        t_solve = (time.perf_counter() - t0) / reps
+        t0 = time.perf_counter()
+        for _ in range(2):
+            plan.setup(prob)
+        torch.cuda.synchronize()
+        t_setup = (time.perf_counter() - t0) / 2
+        reg = plan.export("region").cpu().numpy().ravel()
+        un = u.cpu().numpy()
+        if bie in ("dirichlet", "neumann"):
+            ue = W.bvp_exact(prob, sol).ravel()
+            m = reg > 0
+            d = (un - ue)[m]
+            err = float(np.max(np.abs(d - d.mean()))) if bie == "neumann" else float(np.max(np.abs(d)))
+        else:
+            ue = W.exact_solution(prob, sol, reg.reshape((128 + 1,) * 3)).ravel()
+            err = float(np.max(np.abs(un - ue)))
+        out[name] = {"solves_per_s": 1.0 / t_solve, "setup_ms": 1e3 * t_setup, "iters": info["iters"],
+                     "unknowns": int(plan.n_unknowns), "true_rel_res": info["true_rel_res"],
+                     "max_error_vs_exact": err}
+        plan.close()
+        torch.cuda.empty_cache()
+    return out
+
+
 def forms_batch(workers=(1, 8)):
     """The 512-problem batch of random stars (N in {64, 128, 256, 512},
     beta_in log-uniform 1e-2..1e2): solved problems per second over the
@@ -470,6 +530,7 @@ def main():
             "torus_sphere128": forms_config3(tol, 128),
             "torus_sphere256": forms_config3(tol, 256),
             "batch512_random_stars": forms_batch(),
+            "widened_rows": forms_widened(tol),
         }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, tol)

@@ -74,15 +74,21 @@ constexpr int LS_QMAX = 5;
 __device__ double ls_grid(const LSet& L, int k, const double X[3], double* grad) {
   const int q = (int)L.p[k][0];
   int base[3] = {0, 0, 0};
+  // value: an axis on which the point sits at a node has one nonzero
+  // weight (exactly 1); the zero terms are skipped, which leaves the sum
+  // bit for bit unchanged (they add +-0)
+  int jlo[3] = {0, 0, 0}, jhi[3] = {q, q, q};
   double W[3][LS_QMAX + 1], D[3][LS_QMAX + 1];
   for (int a = 0; a < L.d; ++a) {
     double t = (X[a] - L.lo) / L.h;
     const double r = floor(t + 0.5);
-    if (fabs(t - r) < 1e-9) t = r;
+    const bool snap = fabs(t - r) < 1e-9;
+    if (snap) t = r;
     int b = (int)floor(t) - (q - 1) / 2;
     if (b < 0) b = 0;
     if (b > L.N - q) b = L.N - q;
     base[a] = b;
+    if (snap && !grad) jlo[a] = jhi[a] = (int)t - b;
     const double u = t - (double)b;
     for (int j = 0; j <= q; ++j) {
       double v = 1.0;
@@ -102,11 +108,11 @@ __device__ double ls_grid(const LSet& L, int k, const double X[3], double* grad)
   }
   const double* S = L.S[k];
   const int64_t n1 = L.N + 1;
-  const int q2 = L.d == 3 ? q : 0;
+  if (L.d == 2) jlo[2] = jhi[2] = 0;
   double val = 0.0, g0 = 0.0, g1 = 0.0, g2 = 0.0;
-  for (int j2 = 0; j2 <= q2; ++j2)
-    for (int j1 = 0; j1 <= q; ++j1)
-      for (int j0 = 0; j0 <= q; ++j0) {
+  for (int j2 = jlo[2]; j2 <= jhi[2]; ++j2)
+    for (int j1 = jlo[1]; j1 <= jhi[1]; ++j1)
+      for (int j0 = jlo[0]; j0 <= jhi[0]; ++j0) {
         int64_t idx = (int64_t)(base[0] + j0) + (int64_t)(base[1] + j1) * n1;
         if (L.d == 3) idx = idx + (int64_t)(base[2] + j2) * (n1 * n1);
         const double s = S[idx];

@@ -143,6 +143,7 @@ struct kfbi_plan {
   // of the exterior operator (same geometry, Lap - kappa_out), one-sided
   // values at the DOFs, GMRES over [phi; psi]
   double *IWv, *TIv;             // [n_dof][(q+1)^d] value weights, [n_dof][nC] their own-polynomial sums
+  double *GWv, *HWv;             // [n_dof][nF] folds of C_c(p_c) and of the value interpolation's own term
   kfbi_plan* aux;
   bool is_aux;
   double *tv_in, *tv_out;        // [cap_dof]
@@ -277,6 +278,9 @@ void op_rhs_base(kfbi_plan* pl, const double* fhat, const double* gB, double* F,
                  int fsel = 0);
 // one-sided values at the DOFs with the value weights (two-density plans)
 void op_values(kfbi_plan* pl, const double* v, double* v_in, double* v_out);
+// folded interpolation of the density x (values or normal derivatives)
+void op_interp_folded(kfbi_plan* pl, const double* v, const double* x, double* t_in, double* t_out, bool values);
+void dst_solve_corrections(kfbi_plan* pl, const double* psi, double* v);
 void op_rhs_correct(kfbi_plan* pl, double* F, bool overwrite);
 void op_boundary(kfbi_plan* pl, const double* gB, double* v);
 void op_normal_derivatives(kfbi_plan* pl, const double* v, double* dn_in, double* dn_out,

@@ -413,7 +413,48 @@ struct FoldArgs {
   const int* flags;    // status flags: the folds do nothing when one is set (the tables may be invalid)
   double *FW, *GW, *HW, *IW, *TI, *PA;
   Stencil S;
+  // two-density plans: the scale h / sigma of the flux density's columns,
+  // and the value-interpolation folds (C_c(p_c) and the own-polynomial term)
+  double nscale;
+  double *GWv, *HWv;
+  const double* TIv;
 };
+
+// The density columns of the folds.  Single density: the flux jump in the
+// Neumann columns (scale h), or for a Dirichlet problem the value jump in
+// the Dirichlet columns (scale 1).  Two-density: group 0 is phi in the
+// Dirichlet columns (scale 1, density indices 0..n), group 1 psi in the
+// Neumann columns (scale h / sigma of the plan, indices n..2n); their terms
+// are stored one after the other (jbase).
+struct DenCols {
+  int col0, cnt, jbase;
+  const int* st;
+  double scale;
+  int ioff;
+};
+
+__device__ __forceinline__ int den_groups(const FoldArgs& a) { return a.g.bie == KFBI_BIE_TWO_DENSITY ? 2 : 1; }
+
+__device__ __forceinline__ DenCols den_cols(const FoldArgs& a, int grp) {
+  const bool dir = a.g.bie == KFBI_BIE_DIRICHLET, td = a.g.bie == KFBI_BIE_TWO_DENSITY;
+  DenCols c;
+  if (dir || (td && grp == 0)) {
+    c.col0 = a.nP;
+    c.cnt = a.nD;
+    c.st = a.stD;
+    c.scale = 1.0;
+    c.ioff = 0;
+    c.jbase = 0;
+  } else {
+    c.col0 = a.nP + a.nD;
+    c.cnt = a.nN;
+    c.st = a.stN;
+    c.scale = td ? a.nscale : a.g.h;
+    c.ioff = td ? (int)a.n_dof : 0;
+    c.jbase = td ? a.nD : 0;
+  }
+  return c;
+}
 
 __global__ void k_entry_map(int64_t n_corr, int64_t n_nodes, const int* ck, const int* cnode, int* EI) {
   int64_t e = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
@@ -438,22 +479,22 @@ __global__ void k_fold_corr(FoldArgs a) {
   double phi[NC];
   monomials<D, P>(xi, phi);
   const double* Mi = a.MinvT + (int64_t)own * NC * NC;
-  const bool dir = g.bie == KFBI_BIE_DIRICHLET;
-  const int nDen = dir ? a.nD : a.nN, col0 = dir ? a.nP : a.nP + a.nD;
-  const int* stDen = dir ? a.stD : a.stN;
-  for (int j = 0; j < nDen; ++j) {
-    const double* col = Mi + (int64_t)(col0 + j) * NC;
-    double sacc = 0.0;
+  for (int grp = 0; grp < den_groups(a); ++grp) {
+    const DenCols dc = den_cols(a, grp);
+    for (int j = 0; j < dc.cnt; ++j) {
+      const double* col = Mi + (int64_t)(dc.col0 + j) * NC;
+      double sacc = 0.0;
 #pragma unroll
-    for (int al = 0; al < NC; ++al) sacc += col[al] * phi[al];
-    const double rn = dir ? sacc : g.h * sacc;
-    const int sN = stDen[(int64_t)own * nDen + j];
+      for (int al = 0; al < NC; ++al) sacc += col[al] * phi[al];
+      const double rn = dc.scale * sacc;
+      const int sN = dc.st[(int64_t)own * dc.cnt + j];
 #pragma unroll
-    for (int m = 0; m < P; ++m) {
-      const int idx = a.ext_idx[(int64_t)sN * P + m];
-      const int64_t o = e * a.nF + (int64_t)j * P + m;
-      a.FI[o] = idx >= 0 ? idx : 0;
-      a.FW[o] = idx >= 0 ? rn * a.ext_w[(int64_t)sN * P + m] : 0.0;
+      for (int m = 0; m < P; ++m) {
+        const int idx = a.ext_idx[(int64_t)sN * P + m];
+        const int64_t o = e * a.nF + (int64_t)(dc.jbase + j) * P + m;
+        a.FI[o] = idx >= 0 ? dc.ioff + idx : 0;
+        a.FW[o] = idx >= 0 ? rn * a.ext_w[(int64_t)sN * P + m] : 0.0;
+      }
     }
   }
 }
@@ -517,21 +558,27 @@ __global__ void k_fold_dof(FoldArgs a) {
   if (b == 0) {
     a.IB[c] = (int)ravel(g, st[0], st[1], st[2]);
     const double* Mi = a.MinvT + c * (int64_t)a.nC * a.nC;
-    const int nDen = dir ? a.nD : a.nN, col0 = dir ? a.nP : a.nP + a.nD;
-    const int* stDen = dir ? a.stD : a.stN;
-    for (int j = 0; j < nDen; ++j) {
-      const double* col = Mi + (int64_t)(col0 + j) * a.nC;
-      double gsum = 0.0;
-      if (dir)
-        gsum = col[0];                                                   // C_c(p_c) = U[0]
-      else
-        for (int ax = 0; ax < g.d; ++ax) gsum += nv[ax] * col[1 + ax];   // graded order: 1, x, y(, z)
-      const int sN = stDen[c * nDen + j];
-      for (int m = 0; m < g.p; ++m) {
-        const int idx = a.ext_idx[(int64_t)sN * g.p + m];
-        const int64_t o = c * a.nF + (int64_t)j * g.p + m;
-        a.GI[o] = idx >= 0 ? idx : 0;
-        a.GW[o] = idx >= 0 ? gsum * a.ext_w[(int64_t)sN * g.p + m] : 0.0;
+    const bool td = g.bie == KFBI_BIE_TWO_DENSITY;
+    for (int grp = 0; grp < den_groups(a); ++grp) {
+      const DenCols dc = den_cols(a, grp);
+      for (int j = 0; j < dc.cnt; ++j) {
+        const double* col = Mi + (int64_t)(dc.col0 + j) * a.nC;
+        double gsum = 0.0;
+        if (dir)
+          gsum = col[0];                                                   // C_c(p_c) = U[0]
+        else
+          for (int ax = 0; ax < g.d; ++ax) gsum += nv[ax] * col[1 + ax];   // graded order: 1, x, y(, z)
+        // two-density: d_n C_c(p_c) = U[1 + ax] n_ax / h with U = scale Minv Q
+        if (td) gsum = gsum * (dc.scale / g.h);
+        const int sN = dc.st[c * dc.cnt + j];
+        for (int m = 0; m < g.p; ++m) {
+          const int idx = a.ext_idx[(int64_t)sN * g.p + m];
+          const int64_t o = c * a.nF + (int64_t)(dc.jbase + j) * g.p + m;
+          const double ew = idx >= 0 ? a.ext_w[(int64_t)sN * g.p + m] : 0.0;
+          a.GI[o] = idx >= 0 ? dc.ioff + idx : 0;
+          a.GW[o] = idx >= 0 ? gsum * ew : 0.0;
+          if (td) a.GWv[o] = idx >= 0 ? (col[0] * dc.scale) * ew : 0.0;
+        }
       }
     }
   }
@@ -544,6 +591,30 @@ __global__ void k_fold_dof(FoldArgs a) {
 // partial sums of T are combined by a fixed butterfly, and the lanes then
 // split the nN * P folded weights.
 constexpr int FOLD_G = 32;
+
+// HW[c][t] (or HWv) = scale T . Minv[:, column] * extension weight over the
+// density columns; the lanes of the centre's group split the terms
+template <int NC, int P>
+__device__ __forceinline__ void fold_own_terms(const FoldArgs& a, int64_t c, int lane, const double* T, double* out) {
+  const double* Mi = a.MinvT + c * (int64_t)NC * NC;
+  const DenCols d0 = den_cols(a, 0);
+  const int n0 = d0.cnt * P;
+  const int tot = den_groups(a) == 2 ? n0 + a.nN * P : n0;
+  for (int q = lane; q < tot; q += FOLD_G) {
+    const DenCols dc = q < n0 ? d0 : den_cols(a, 1);
+    const int qq = q < n0 ? q : q - n0;
+    const int j = qq / P, m = qq % P;
+    const double* col = Mi + (int64_t)(dc.col0 + j) * NC;
+    double sacc = 0.0;
+#pragma unroll
+    for (int al = 0; al < NC; ++al) sacc += T[al] * col[al];
+    const double rn = dc.scale * sacc;
+    const int sN = dc.st[c * dc.cnt + j];
+    const int idx = a.ext_idx[(int64_t)sN * P + m];
+    out[c * a.nF + (int64_t)(dc.jbase + j) * P + m] = idx >= 0 ? rn * a.ext_w[(int64_t)sN * P + m] : 0.0;
+  }
+}
+
 template <int D, int P>
 __global__ void __launch_bounds__(KFBI_BLOCK) k_fold_own(FoldArgs a) {
   if (*a.flags) return;
@@ -586,21 +657,23 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_fold_own(FoldArgs a) {
 #pragma unroll
     for (int al = 0; al < NC; ++al) a.TI[c * NC + al] = T[al];
   }
-  const double* Mi = a.MinvT + c * (int64_t)NC * NC;
-  const bool dir = g.bie == KFBI_BIE_DIRICHLET;
-  const int nDen = dir ? a.nD : a.nN, col0 = dir ? a.nP : a.nP + a.nD;
-  const int* stDen = dir ? a.stD : a.stN;
-  for (int q = lane; q < nDen * P; q += FOLD_G) {
-    const int j = q / P, m = q % P;
-    const double* col = Mi + (int64_t)(col0 + j) * NC;
-    double sacc = 0.0;
+  fold_own_terms<NC, P>(a, c, lane, T, a.HW);
+}
+
+// the own-polynomial fold of the value interpolation (two-density plans):
+// the same terms with TIv
+template <int D, int P>
+__global__ void __launch_bounds__(KFBI_BLOCK) k_fold_hwv(FoldArgs a) {
+  if (*a.flags) return;
+  constexpr int NC = ncoef_t<D, P>();
+  const int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
+  const int64_t c = t / FOLD_G;
+  const int lane = (int)(t % FOLD_G);
+  if (c >= a.n_dof) return;
+  double T[NC];
 #pragma unroll
-    for (int al = 0; al < NC; ++al) sacc += T[al] * col[al];
-    const double rn = dir ? sacc : g.h * sacc;
-    const int sN = stDen[c * nDen + j];
-    const int idx = a.ext_idx[(int64_t)sN * P + m];
-    a.HW[c * a.nF + (int64_t)j * P + m] = idx >= 0 ? rn * a.ext_w[(int64_t)sN * P + m] : 0.0;
-  }
+  for (int al = 0; al < NC; ++al) T[al] = a.TIv[c * NC + al];
+  fold_own_terms<NC, P>(a, c, lane, T, a.HWv);
 }
 
 // cut neighbours of every irregular node: stencil coefficient and the
@@ -963,8 +1036,8 @@ void launch_interp(kfbi_plan* pl, const double* v, const double* U, const double
   A.IE2 = pl->IE2;
   A.GI = pl->GI;
   A.Cv = pl->Cv;
-  A.GW = pl->GW;
-  A.HW = pl->HW;
+  A.GW = values ? pl->GWv : pl->GW;
+  A.HW = values ? pl->HWv : pl->HW;
   A.TI = values ? pl->TIv : pl->TI;
   A.psi = psi;
   A.region = pl->region;
@@ -988,6 +1061,10 @@ void op_values(kfbi_plan* pl, const double* v, double* v_in, double* v_out) {
   launch_interp(pl, v, pl->U, nullptr, v_in, v_out, nullptr, true);
 }
 
+void op_interp_folded(kfbi_plan* pl, const double* v, const double* x, double* t_in, double* t_out, bool values) {
+  launch_interp(pl, v, nullptr, x, t_in, t_out, nullptr, values);
+}
+
 template <class T>
 static kfbi_status regrow(T** p, int64_t n) {
   if (*p) (void)hipFree(*p);
@@ -1005,7 +1082,7 @@ kfbi_status op_fold(kfbi_plan* pl) {
   const GridDesc& g = pl->g;
   const int q1 = g.p + 1;
   const int nbk = g.d == 3 ? q1 * q1 * q1 : q1 * q1;
-  pl->nF = (g.bie == KFBI_BIE_DIRICHLET ? pl->nD : pl->nN) * g.p;
+  pl->nF = (g.bie == KFBI_BIE_DIRICHLET ? pl->nD : g.bie == KFBI_BIE_TWO_DENSITY ? pl->nD + pl->nN : pl->nN) * g.p;
   pl->maxpairs = g.order == 2 ? 2 * g.d : (g.d == 3 ? 26 : 8);
   if (pl->n_corr > pl->cap_fold_corr) {
     int64_t cap = pl->n_corr + pl->n_corr / 4 + 64;
@@ -1028,6 +1105,8 @@ kfbi_status op_fold(kfbi_plan* pl) {
     if (g.bie == KFBI_BIE_TWO_DENSITY) {
       KCHK(regrow(&pl->IWv, cap * nbk));
       KCHK(regrow(&pl->TIv, cap * pl->nC));
+      KCHK(regrow(&pl->GWv, cap * pl->nF));
+      KCHK(regrow(&pl->HWv, cap * pl->nF));
     }
     pl->cap_fold_dof = cap;
   }
@@ -1086,6 +1165,10 @@ kfbi_status op_fold(kfbi_plan* pl) {
   A.PA = pl->PA;
   A.S = make_stencil(g);
   A.flags = pl->d_flags;
+  A.nscale = g.h / (pl->is_aux ? pl->prob.beta_out : pl->prob.beta_in);
+  A.GWv = pl->GWv;
+  A.HWv = pl->HWv;
+  A.TIv = pl->TIv;
   if (pl->n_corr > 0) {
     dim3 gr(nb(pl->n_corr)), bl(KFBI_BLOCK);
     if (g.d == 2 && g.p == 2) hipLaunchKernelGGL((k_fold_corr<2, 2>), gr, bl, 0, pl->stream, A);
@@ -1109,6 +1192,10 @@ kfbi_status op_fold(kfbi_plan* pl) {
     if (g.d == 2 && g.p == 4) hipLaunchKernelGGL((k_fold_tiv<2, 4>), gr, bl, 0, pl->stream, A, pl->IWv, pl->TIv);
     if (g.d == 3 && g.p == 2) hipLaunchKernelGGL((k_fold_tiv<3, 2>), gr, bl, 0, pl->stream, A, pl->IWv, pl->TIv);
     if (g.d == 3 && g.p == 4) hipLaunchKernelGGL((k_fold_tiv<3, 4>), gr, bl, 0, pl->stream, A, pl->IWv, pl->TIv);
+    if (g.d == 2 && g.p == 2) hipLaunchKernelGGL((k_fold_hwv<2, 2>), gr, bl, 0, pl->stream, A);
+    if (g.d == 2 && g.p == 4) hipLaunchKernelGGL((k_fold_hwv<2, 4>), gr, bl, 0, pl->stream, A);
+    if (g.d == 3 && g.p == 2) hipLaunchKernelGGL((k_fold_hwv<3, 2>), gr, bl, 0, pl->stream, A);
+    if (g.d == 3 && g.p == 4) hipLaunchKernelGGL((k_fold_hwv<3, 4>), gr, bl, 0, pl->stream, A);
   }
   if (pl->n_irr > 0) {
     hipLaunchKernelGGL(k_fold_pairs, dim3(nb(pl->n_irr)), dim3(KFBI_BLOCK), 0, pl->stream, A);

@@ -16,10 +16,12 @@
 // Every product is one simple solve per Green's function, i.e. two box
 // solves (the superposition remark after Alg. 1).  The plan holds W_1 (its
 // own kappa) and keeps a second plan of the same geometry for W_2
-// (kappa_out).  Both solves run the unfolded simple-solve kernels (the
-// density enters through the value and the flux columns at once); the
-// one-sided values come from the value weights of the interpolation blocks,
-// the normal derivatives from the derivative weights.
+// (kappa_out).  In a product both solves run the folded operator, whose
+// weight lists cover both densities (phi through the value columns, psi
+// through the flux columns); the right-hand side and the final solution use
+// the general simple-solve kernels.  The one-sided values come from the
+// value weights of the interpolation blocks, the normal derivatives from the
+// derivative weights.
 //
 // GMRES (Alg. 1 Steps 2-4) on the 2 n_dof system: classical Gram-Schmidt
 // applied twice, with the dot products reduced on the device in a fixed
@@ -225,7 +227,7 @@ kfbi_status td_setup(kfbi_plan* pl) {
 void td_free(kfbi_plan* pl) {
   if (pl->aux) plan_release(pl->aux);
   pl->aux = nullptr;
-  double** bufs[] = {&pl->IWv, &pl->TIv, &pl->tv_in, &pl->tv_out, &pl->td_V, &pl->td_b, &pl->td_w, &pl->td_part,
+  double** bufs[] = {&pl->IWv, &pl->TIv, &pl->GWv, &pl->HWv, &pl->tv_in, &pl->tv_out, &pl->td_V, &pl->td_b, &pl->td_w, &pl->td_part,
                      &pl->td_h};
   for (double** b : bufs) {
     if (*b) (void)hipFree(*b);
@@ -249,15 +251,21 @@ kfbi_status td_check(kfbi_plan* pl) {
   return KFBI_OK;
 }
 
-// out = A x (both [2 n_dof], distinct)
+// out = A x (both [2 n_dof], distinct): per Green's function the folded
+// operator (the density extension and the local inverses folded at set-up
+// into weight lists over [phi; psi]): correction values, the box solve that
+// builds the corrected right-hand side in its first pass, and the two
+// interpolations
 void td_apply(kfbi_plan* pl, const double* x, double* out) {
   kfbi_plan* q = pl->aux;
   const int64_t n = pl->n_dof;
   const double s1 = pl->prob.beta_in, s2 = pl->prob.beta_out;
-  op_extend(pl, x, pl->aS);          // E phi
-  op_extend(pl, x + n, pl->psiS);    // E psi
-  td_simple(pl, pl->aS, pl->psiS, 1.0 / s1, nullptr, 1.0, nullptr, 0, nullptr, pl->vsbuf);
-  td_simple(q, pl->aS, pl->psiS, 1.0 / s2, nullptr, 1.0, nullptr, 0, nullptr, q->vsbuf);
+  for (kfbi_plan* P : {pl, q}) {
+    op_matvec_head(P, x);
+    dst_solve_corrections(P, x, P->vbuf);
+    op_interp_folded(P, P->vbuf, x, P->dn_in, P->dn_out, false);
+    op_interp_folded(P, P->vbuf, x, P->tv_in, P->tv_out, true);
+  }
   hipLaunchKernelGGL(k_td_combine, dim3(nblocks(n)), dim3(TD_BLOCK), 0, pl->stream, n, x, pl->tv_in, pl->tv_out,
                      pl->dn_in, pl->dn_out, q->tv_in, q->tv_out, q->dn_in, q->dn_out, s1, s2, out);
 }

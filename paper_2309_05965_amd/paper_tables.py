@@ -1,7 +1,7 @@
 """Reproduction of the paper's numerical tables on the GPU (Sec. 6):
 iteration counts and error norms of every example next to the printed ones.
 
-    python -m paper_2309_05965_amd.paper_tables [--cases E1,E2,...] [--max-n 512] [--out table.md]
+    python -m paper_2309_05965_amd.paper_tables [--cases E1,E2,...] [--max-n 512] [--n 128,256] [--out table.md]
 
 Each example is the workload of the same name in `workloads` (the problem,
 its manufactured solution and the readings where the paper is silent or
@@ -143,6 +143,7 @@ def main(argv=None):
     ap = argparse.ArgumentParser(description=__doc__.split("\n")[0])
     ap.add_argument("--cases", default="E1,E2,E3,E4,E5,E6,E7")
     ap.add_argument("--max-n", type=int, default=512)
+    ap.add_argument("--n", default=None, help="only these grid sizes (comma list)")
     ap.add_argument("--out", default=None)
     a = ap.parse_args(argv)
     grids = {"E1": (64, 128, 256, 512, 1024), "E2": (64, 128, 256, 512, 1024), "E3": (64, 128, 256, 512),
@@ -150,7 +151,7 @@ def main(argv=None):
     rows = []
     for c in a.cases.split(","):
         for N in grids[c]:
-            if N > a.max_n:
+            if N > a.max_n or (a.n and N not in [int(v) for v in a.n.split(",")]):
                 continue
             for ratio in ((10.0, 100.0, 1e4) if c == "E5" else (None,)):
                 try:
