@@ -160,6 +160,7 @@ def cpu_suite(tol):
     ok = sum(1 for r in rows if r)
     res["config4_batch512"] = {"wall_s": el, "solved": ok, "solved_per_s": ok / el, "processes": min(16, os.cpu_count() or 1)}
     print("config4", res["config4_batch512"], flush=True)
+    res["widened_2d"] = oracle_widened(tol)
     return res
 
 
@@ -355,6 +356,50 @@ def forms_config3(tol, N):
     return out
 
 
+def widened_2d():
+    """2D problems of the widened rows, small enough for the oracle: the
+    paper's Dirichlet ellipse, a Neumann problem on it, a two-density
+    Poisson / modified-Helmholtz ellipse and the workload star given by its
+    node samples, all at 256^2."""
+    from paper_2309_05965_amd import workloads as W
+    neu, u1 = W.e1_dirichlet(256)
+    neu = dict(neu, bie="neumann")
+    td = W.td_problem(2, 4, 256, -1.0, 1.0, 1.0, 4.0, 0.0, 2.5, [W.ellipse2d(0.05, -0.02, 0.6, 0.45, theta=0.3)])
+    star, ssol = W.config2(256)
+    return [("dirichlet_ellipse256", W.e1_dirichlet(256)), ("neumann_ellipse256", (neu, u1)),
+            ("two_density_ellipse256", (td, {0: W.f_sin_sin, 1: W.f_exp_cos})),
+            ("star256_sampled_quintic", (W.with_sampled(star, W.H_star(0.5, 0.3, 5), 5), ssol))]
+
+
+def oracle_widened(tol):
+    """The oracle's whole solves (set-up included) of the 2D widened problems,
+    one thread each."""
+    from oracle import bvp, kfbi as okfbi, twodensity
+    from paper_2309_05965_amd import workloads as W
+    out = {}
+    for name, (prob, sol) in widened_2d():
+        t0 = time.perf_counter()
+        bie = prob.get("bie", "interface")
+        if bie in ("dirichlet", "neumann"):
+            pl = bvp.BVPPlan(prob)
+            s = pl.geo["surf"]
+            res = pl.solve(W.make_bvp_data(prob, sol, s["pos"], s["nrm"], pl.geo["st"]["pde_pts"]), tol=tol)
+        elif bie == "two_density":
+            pl = twodensity.TwoDensityPlan(prob)
+            s = pl.geo["surf"]
+            res = pl.solve(W.make_td_data(prob, sol, s["pos"], s["nrm"], s["iface"], pl.geo["st"]["pde_pts"],
+                                          pl.geo["dofs"]["iface"]), tol=tol)
+        else:
+            pl = okfbi.Plan(prob)
+            s = pl.geo["surf"]
+            res = pl.solve(W.make_data(prob, sol, s["pos"], s["nrm"], s["iface"], pl.geo["st"]["pde_pts"],
+                                       pl.geo["dofs"]["iface"]), tol=tol)
+        el = time.perf_counter() - t0
+        out[name] = {"seconds": el, "solves_per_s": 1.0 / el, "iters": res["iters"]}
+        print(name, out[name], flush=True)
+    return out
+
+
 def forms_widened(tol, reps=5):
     """The widened rows on repeated problems (FFT box solver, GMRES to tol):
     the interior Neumann problem in the torus and the two-density
@@ -366,14 +411,15 @@ def forms_widened(tol, reps=5):
     import torch
     from paper_2309_05965_amd import kfbi
     from paper_2309_05965_amd import workloads as W
+    cases = dict(widened_2d())
     torus = W.problem(3, 4, 128, -1.0, 1.0, 1.0, 100.0, 0.0, [W.torus3d(0.0, 0.0, 0.0, 0.6, 0.25)])
-    cases = {
+    cases.update({
         "neumann_torus128": W.e3_neumann(128),
         "two_density_three_spheres128": W.e7_heterogeneous(128),
         "molecule128_contrast1e4": W.e5_molecule(128, 1e4),
         "torus128_analytic": (torus, {0: W.f_exp3, 1: W.f_sin3}),
         "torus128_sampled_quintic": (W.with_sampled(torus, W.H_torus(0.6, 0.25), 5), {0: W.f_exp3, 1: W.f_sin3}),
-    }
+    })
     out = {}
     for name, (prob, sol) in cases.items():
         bie = prob.get("bie", "interface")
@@ -405,7 +451,7 @@ def forms_widened(tol, reps=5):
             d = (un - ue)[m]
             err = float(np.max(np.abs(d - d.mean()))) if bie == "neumann" else float(np.max(np.abs(d)))
         else:
-            ue = W.exact_solution(prob, sol, reg.reshape((128 + 1,) * 3)).ravel()
+            ue = W.exact_solution(prob, sol, reg.reshape((prob["N"] + 1,) * prob["dim"])).ravel()
             err = float(np.max(np.abs(un - ue)))
         out[name] = {"solves_per_s": 1.0 / t_solve, "setup_ms": 1e3 * t_setup, "iters": info["iters"],
                      "unknowns": int(plan.n_unknowns), "true_rel_res": info["true_rel_res"],
@@ -534,6 +580,8 @@ def main():
         }
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, tol)
+        # the oracle beside the widened rows' GPU solves (forms.widened_rows, the 2D problems)
+        out["cpu_baseline"]["widened_2d"] = oracle_widened(tol)
     print(json.dumps(out), flush=True)
 
 
