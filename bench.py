@@ -461,6 +461,11 @@ def forms_widened(tol, reps=5):
     return out
 
 
+def tile_lines_of(dim, n):
+    from paper_2309_05965_amd import kfbi
+    return kfbi.tile_lines(dim, n)
+
+
 def forms_batch(workers=(1, 8)):
     """The 512-problem batch of random stars (N in {64, 128, 256, 512},
     beta_in log-uniform 1e-2..1e2): solved problems per second over the
@@ -566,6 +571,7 @@ def main():
             "gmres_iters_mean": {"mixed": float(np.mean(its_m)), "plain": float(np.mean(its_p))},
             "true_rel_res_max": {"mixed": float(np.max(trs_m)), "plain": float(np.max(trs_p))},
             "mixed_vs_plain_max_rel_diff": {"u": du, "psi_l2": dpsi},
+            "sine_transform_tile_lines": {"3d_%d" % n: tile_lines_of(3, n) for n in (N // 2, N)},
         },
         "roofline": roof,
     }

@@ -342,6 +342,21 @@ kfbi_status kfbi_box_solve(kfbi_plan* plan, const double* F, double* v);
  * allocating library routine).  Every call on a device shares that array:
  * calls that overlap on one device (two streams, two threads) race and
  * must be serialised by the caller. */
+/* Lines per tile of the sine-transform passes (S3) on a grid (dim, N): the
+ * caller's override (kfbi_set_tile_lines), else the autotuner's choice (at
+ * the first plan of that grid in the process the library times the x pass
+ * and the most strided pass for every candidate tile and keeps the fastest
+ * unless it is within 3% of the built-in rule; KFBI_TILE_AUTOTUNE=0 in the
+ * environment keeps the rule), else the rule.  Results do not depend on it:
+ * every even tile pairs the lines the same way and each line's transform is
+ * the same.  Returns 0 for an invalid grid. */
+int kfbi_tile_lines(int dim, int N);
+/* Override the tile lines of a grid: an even TL of 2..8 that fits the LDS
+ * (twice per compute unit) and leaves at least 256 tiles; 0 removes the
+ * override.  The 2D grids of 512 and 1024 run their own kernels with fixed
+ * tiles and take no override.  Affects launches made after the call. */
+kfbi_status kfbi_set_tile_lines(int dim, int N, int TL);
+
 kfbi_status kfbi_box_solve_noalloc(int dim, int order, int N, double lo, double hi, double kappa,
                                    const double* F, double* v, void* stream);
 

@@ -1348,10 +1348,11 @@ __global__ void k_group_state(int* const* ctls, double* const* scals, int G, dou
 }
 }  // namespace
 
-// Alg. 1 for G problems of one grid shape with the FFT box solver, their
-// GMRES iterations in lockstep: per iteration the interface-dependent
-// kernels of every problem and one launch per box-solve pass for the whole
-// group, captured once as a graph of four iterations; every kernel of a
+// Alg. 1 for G problems of one dimension (any grid sizes) with the FFT box
+// solver, their GMRES iterations in lockstep: per iteration the
+// interface-dependent kernels of every problem and one launch per box-solve
+// pass for all the problems up to N = 256 (plus one per pass per larger
+// size), captured once as a graph of four iterations; every kernel of a
 // problem that has converged returns at once.  The right-hand sides, the
 // updates, true residuals and final solves are those of kfbi_solve, so
 // every problem's density and solution equal its own solve's bit for bit.
@@ -1368,9 +1369,9 @@ kfbi_status kfbi_solve_group(kfbi_plan* const* pls, int G, const kfbi_data* data
   for (int p = 0; p < G; ++p) {
     KCHK(need_ready(pls[p]));
     if (opts->solver != KFBI_SOLVER_PLAN) KCHK(apply_solver(pls[p], *opts));
-    if (pls[p]->box_solver != KFBI_BOX_FFT || pls[p]->g.N != pls[0]->g.N || pls[p]->g.d != pls[0]->g.d ||
-        pls[p]->g.order != pls[0]->g.order) {
-      kfbi_set_error("group solve: FFT box solver and one grid shape");
+    if (pls[p]->box_solver != KFBI_BOX_FFT || pls[p]->g.d != pls[0]->g.d ||
+        pls[p]->g.bie == KFBI_BIE_TWO_DENSITY) {
+      kfbi_set_error("group solve: FFT box solver, one dimension, single-density plans");
       return KFBI_E_INVALID;
     }
     HIPCHK(hipStreamSynchronize(pls[p]->stream));

@@ -204,9 +204,10 @@ extern "C" kfbi_status kfbi_batch_plan(kfbi_batch* b, int i, kfbi_plan** out) {
   return b->pstat[i];
 }
 
-// Problems of one grid shape solved by one worker go in groups of up to
-// GROUP_MAX in lockstep (kfbi_solve_group: one launch per box-solve pass
-// for the whole group) when their box solver is the FFT; others one by
+// Problems of one dimension solved by one worker go in groups of up to
+// GROUP_MAX (largest first, grid sizes mixed) in lockstep (kfbi_solve_group:
+// one launch per box-solve pass for the group's problems up to N = 256 and
+// one per larger size) when their box solver is the FFT; others one by
 // one.
 constexpr int GROUP_MAX = 32;
 
@@ -225,7 +226,7 @@ extern "C" kfbi_status kfbi_batch_solve(kfbi_batch* b, const kfbi_opts* opts, co
                    (opts->solver == KFBI_SOLVER_PLAN);   // refined per plan below
   FirstError fe;
   on_workers(b, [&](int wi, Worker& w) {
-    // this worker's problems that set up, grouped by grid shape (largest first)
+    // this worker's problems that set up, grouped by dimension (largest first)
     std::map<std::vector<double>, std::vector<int>> groups;
     std::vector<std::vector<double>> shapes;
     for (int p : order) {
@@ -235,7 +236,7 @@ extern "C" kfbi_status kfbi_batch_solve(kfbi_batch* b, const kfbi_opts* opts, co
         if (seconds) seconds[p] = 0.0;
         continue;
       }
-      const std::vector<double> key = shape_key(b->probs[p]);
+      const std::vector<double> key{(double)b->probs[p].dim};
       if (!groups.count(key)) shapes.push_back(key);
       groups[key].push_back(p);
     }

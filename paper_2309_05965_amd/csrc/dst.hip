@@ -24,6 +24,9 @@
 // from a global table (L2-resident).
 #include <math.h>
 
+#include <algorithm>
+#include <atomic>
+#include <cstdlib>
 #include <mutex>
 #include <new>
 #include <vector>
@@ -627,13 +630,44 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_dst1024b(const DstArgs* __restri
   dst1024_pass<MODE>(a, lb % nbp);
 }
 
-// lines per tile: the largest even TL <= 8 whose LDS footprint still lets
-// 4 work groups (16 waves) share a compute unit and that leaves at least
-// 1024 tiles (4 per compute unit); else 2.  More lines per tile amortise a
-// work group's fixed latency; the residency and tile-count floors keep
-// enough loads in flight.  (Measured on the 3D 64/128/256 and 2D grids:
-// TL = 2, 8, 4 and 2 respectively.)
-int tile_lines(int d, int N) {
+// The same pass for problems of different grid sizes (N = 8..256, any
+// mix) in one launch: start[p] is the first work group of problem p (its
+// tiles follow in order); work group b (in XCD-contiguous order over the
+// whole launch) finds its problem by bisection over start and runs that
+// problem's pass body for its size, with that problem's arguments, so the
+// arithmetic is the one of the problem's own launch.  The dynamic LDS is
+// sized for the largest tile of the group.
+template <int MODE>
+__global__ void __launch_bounds__(KFBI_BLOCK) k_dstm(const DstArgs* __restrict__ A, const int* __restrict__ start,
+                                                   int G) {
+  const int lb = kfbi_xcd_block(blockIdx.x, gridDim.x);
+  int lo = 0, hi = G;   // start[lo] <= lb < start[hi]
+  while (hi - lo > 1) {
+    const int mid = (lo + hi) >> 1;
+    if (start[mid] <= lb)
+      lo = mid;
+    else
+      hi = mid;
+  }
+  const DstArgs a = A[lo];
+  const int tile = lb - start[lo];
+  switch (a.g.N) {
+    case 8: dst_pass<4, MODE, false>(a, tile); break;
+    case 16: dst_pass<5, MODE, false>(a, tile); break;
+    case 32: dst_pass<6, MODE, false>(a, tile); break;
+    case 64: dst_pass<7, MODE, false>(a, tile); break;
+    case 128: dst_pass<8, MODE, false>(a, tile); break;
+    default: dst_pass<9, MODE, false>(a, tile); break;
+  }
+}
+
+// lines per tile, the built-in rule: the largest even TL <= 8 whose LDS
+// footprint still lets 4 work groups (16 waves) share a compute unit and
+// that leaves at least 1024 tiles (4 per compute unit); else 2.  More lines
+// per tile amortise a work group's fixed latency; the residency and
+// tile-count floors keep enough loads in flight.  (Measured on the 3D
+// 64/128/256 and 2D grids: TL = 2, 8, 4 and 2 respectively.)
+int tile_rule(int d, int N) {
   const int nl = N - 1;
   const int64_t lines = d == 3 ? (int64_t)nl * nl : nl;
   // 64^3 (the coarse grid of the 128^3 two-grid cycle): two 128-point
@@ -645,6 +679,43 @@ int tile_lines(int d, int N) {
     return tl;
   }
   return 2;
+}
+
+// The tile lines in use per grid (dim, log2 N): a caller's override, else
+// the autotuner's measurement, else the rule.  A line's transform does not
+// depend on the tile it is in (lines are paired the same way for every even
+// TL), so results are the same bit for bit whatever the choice.
+std::atomic<int> g_tl_forced[2][12];
+std::atomic<int> g_tl_tuned[2][12];
+std::mutex g_tune_mu;
+
+int log2i(int N) {
+  int l = 0;
+  while ((1 << l) < N) ++l;
+  return l;
+}
+
+int tile_lines(int d, int N) {
+  const int l = log2i(N);
+  if (d >= 2 && d <= 3 && l < 12) {
+    const int f = g_tl_forced[d - 2][l].load(std::memory_order_relaxed);
+    if (f > 0) return f;
+    const int t = g_tl_tuned[d - 2][l].load(std::memory_order_relaxed);
+    if (t > 0) return t;
+  }
+  return tile_rule(d, N);
+}
+
+// the tile line counts worth trying for a grid: even, at most 8, at least
+// two work groups' LDS per compute unit and 256 tiles (one per CU); the
+// 2D grids of 512 and 1024 run their own kernels with fixed tiles
+std::vector<int> tile_candidates(int d, int N) {
+  std::vector<int> out;
+  if (d == 2 && N >= 512) return out;
+  const int64_t nl = N - 1, lines = d == 3 ? nl * nl : nl;
+  for (int tl = 2; tl <= 8; tl += 2)
+    if (tile_lds(tl, N) * 2 <= DST_LDS_CU && (lines + tl - 1) / tl >= 256) out.push_back(tl);
+  return out;
 }
 
 template <int LOGM>
@@ -665,10 +736,10 @@ void launch_t(const DstArgs& a, unsigned blocks, size_t lds, hipStream_t st) {
 
 // launch one axis pass; a.g, a.ax, a.mode, a.in, a.out, a.tw, a.eig1 and
 // the corrected-source fields are set by the caller
-void launch_args(DstArgs& a, bool src_corr, hipStream_t st) {
+void launch_args(DstArgs& a, bool src_corr, hipStream_t st, int tl = 0) {
   const GridDesc& g = a.g;
   const int N = g.N, nl = N - 1;
-  a.TL = tile_lines(g.d, N);
+  a.TL = tl > 0 ? tl : tile_lines(g.d, N);
   a.tiles_u = (nl + a.TL - 1) / a.TL;
   a.scale = 1.0;
   for (int t = 0; t < g.d; ++t) a.scale *= 2.0 / N;
@@ -798,12 +869,22 @@ void launch_batched(const DstArgs& a0, const DstArgs* A, int G, hipStream_t st) 
 
 }  // namespace
 
-// Batched matvec box solves of a group of plans of one grid shape (FFT box
-// solver): the arguments of every pass of every plan, on the device.
+// Batched matvec box solves of a group of plans of one dimension (FFT box
+// solver): the arguments of every pass of every plan, on the device.  The
+// plans with N <= 256 share one launch per pass (k_dstm); the larger ones,
+// whose passes are other kernels (the register four-step FFT at N = 512),
+// one launch per pass per grid size (k_dstb, k_dst1024b).
 struct DstBatch {
-  int G = 0, npass = 0;
-  std::vector<DstArgs> host;   // [npass][G]
+  int npass = 0;
+  int G = 0;                   // plans
+  int Gm = 0;                  // plans in the mixed launch (the first Gm of the order below)
+  size_t lds_m = 0;            // dynamic LDS of the mixed launch
+  unsigned blocks_m = 0;       // work groups of the mixed launch
+  std::vector<int> order;      // plan index of each slot: mixed ones, then the large ones by size
+  std::vector<std::pair<int, int>> big;   // (first slot, count) per large grid size
+  std::vector<DstArgs> host;   // [npass][G] in slot order
   DstArgs* dev = nullptr;      // [npass][G]
+  int* start = nullptr;        // [Gm + 1] first work group of each mixed plan
 };
 
 DstBatch* dst_batch_create(kfbi_plan* const* pls, int G, hipStream_t st, kfbi_status* status) {
@@ -815,12 +896,32 @@ DstBatch* dst_batch_create(kfbi_plan* const* pls, int G, hipStream_t st, kfbi_st
   }
   b->G = G;
   b->npass = pls[0]->g.d == 2 ? 3 : 5;
+  for (int p = 0; p < G; ++p)
+    if (pls[p]->g.N <= 256) b->order.push_back(p);
+  b->Gm = (int)b->order.size();
+  for (int N = 512; N <= 1024; N *= 2) {
+    const int first = (int)b->order.size();
+    for (int p = 0; p < G; ++p)
+      if (pls[p]->g.N == N) b->order.push_back(p);
+    if ((int)b->order.size() > first) b->big.push_back({first, (int)b->order.size() - first});
+  }
   b->host.resize((size_t)b->npass * G);
   for (int q = 0; q < b->npass; ++q)
-    for (int p = 0; p < G; ++p) b->host[(size_t)q * G + p] = corrections_args(pls[p], q);
+    for (int i = 0; i < G; ++i) b->host[(size_t)q * G + i] = corrections_args(pls[b->order[i]], q);
+  std::vector<int> start(b->Gm + 1, 0);
+  for (int i = 0; i < b->Gm; ++i) {
+    const DstArgs& a = b->host[i];
+    const int nl = a.g.N - 1;
+    start[i + 1] = start[i] + a.tiles_u * (a.g.d == 3 ? nl : 1);
+    const size_t l = tile_lds(a.TL, a.g.N);
+    if (l > b->lds_m) b->lds_m = l;
+  }
+  b->blocks_m = (unsigned)start[b->Gm];
   if (hipMalloc((void**)&b->dev, sizeof(DstArgs) * b->host.size()) != hipSuccess ||
+      hipMalloc((void**)&b->start, sizeof(int) * start.size()) != hipSuccess ||
       hipMemcpyAsync(b->dev, b->host.data(), sizeof(DstArgs) * b->host.size(), hipMemcpyHostToDevice, st) !=
           hipSuccess ||
+      hipMemcpyAsync(b->start, start.data(), sizeof(int) * start.size(), hipMemcpyHostToDevice, st) != hipSuccess ||
       hipStreamSynchronize(st) != hipSuccess) {
     (void)hipGetLastError();
     kfbi_set_error("device allocation of the batched pass arguments failed");
@@ -832,12 +933,23 @@ DstBatch* dst_batch_create(kfbi_plan* const* pls, int G, hipStream_t st, kfbi_st
 }
 
 void dst_batch_corrections(DstBatch* b, hipStream_t st) {
-  for (int q = 0; q < b->npass; ++q) launch_batched(b->host[(size_t)q * b->G], b->dev + (size_t)q * b->G, b->G, st);
+  for (int q = 0; q < b->npass; ++q) {
+    const DstArgs* A = b->dev + (size_t)q * b->G;
+    if (b->Gm > 0) {
+      if (b->host[(size_t)q * b->G].mode == 1)
+        hipLaunchKernelGGL(k_dstm<1>, dim3(b->blocks_m), dim3(KFBI_BLOCK), b->lds_m, st, A, b->start, b->Gm);
+      else
+        hipLaunchKernelGGL(k_dstm<0>, dim3(b->blocks_m), dim3(KFBI_BLOCK), b->lds_m, st, A, b->start, b->Gm);
+    }
+    for (const auto& g : b->big)
+      launch_batched(b->host[(size_t)q * b->G + g.first], A + g.first, g.second, st);
+  }
 }
 
 void dst_batch_destroy(DstBatch* b) {
   if (!b) return;
   if (b->dev) (void)hipFree(b->dev);
+  if (b->start) (void)hipFree(b->start);
   delete b;
 }
 
@@ -878,6 +990,8 @@ void dst_solve_grid(const GridDesc& g, const double* tw, const double* eig1, dou
   }
 }
 
+static kfbi_status dst_autotune(kfbi_plan* pl);
+
 kfbi_status dst_init(kfbi_plan* pl) {
   int N = pl->g.N, M = 2 * N;
   std::vector<double> tw((size_t)2 * M), eig((size_t)N + 1);
@@ -890,6 +1004,91 @@ kfbi_status dst_init(kfbi_plan* pl) {
     kfbi_set_error("box solver LDS footprint too large (N = %d)", N);
     return KFBI_E_INVALID;
   }
+  return dst_autotune(pl);
+}
+
+// Tile autotuner: at the first plan of a grid (dim, N) in the process, time
+// the x pass and the last (most strided) pass of the sine transform for
+// every candidate tile (HIP events, three launches each after one warm-up,
+// on the plan's own pass buffers) and keep the fastest for every later
+// launch on that grid.  KFBI_TILE_AUTOTUNE=0 keeps the rule.
+static kfbi_status dst_autotune(kfbi_plan* pl) {
+  const int d = pl->g.d, N = pl->g.N, l = log2i(N);
+  if (l >= 12 || g_tl_tuned[d - 2][l].load() > 0) return KFBI_OK;
+  const char* env = getenv("KFBI_TILE_AUTOTUNE");
+  if (env && env[0] == '0') return KFBI_OK;
+  std::lock_guard<std::mutex> lk(g_tune_mu);
+  if (g_tl_tuned[d - 2][l].load() > 0) return KFBI_OK;
+  const std::vector<int> cand = tile_candidates(d, N);
+  const int rule = tile_rule(d, N);
+  if (cand.size() < 2) {
+    g_tl_tuned[d - 2][l].store(rule);
+    return KFBI_OK;
+  }
+  hipStream_t st = pl->stream;
+  HIPCHK(hipMemsetAsync(pl->T1, 0, sizeof(double) * pl->g.n_nodes, st));
+  hipEvent_t e0 = nullptr, e1 = nullptr;
+  HIPCHK(hipEventCreate(&e0));
+  if (hipEventCreate(&e1) != hipSuccess) {
+    (void)hipEventDestroy(e0);
+    return kfbi_hip_status(hipErrorOutOfMemory, "hipEventCreate");
+  }
+  int best = rule;
+  float best_ms = -1.0f;
+  kfbi_status status = KFBI_OK;
+  for (int tl : cand) {
+    float tot = 0.0f;
+    for (int ax : {0, d - 1}) {
+      DstArgs a{};
+      a.g = pl->g;
+      a.ax = ax;
+      a.mode = 0;
+      a.in = pl->T1;
+      a.out = pl->T2;
+      a.tw = (const double2*)pl->tw;
+      a.eig1 = pl->eig1;
+      launch_args(a, false, st, tl);
+      (void)hipEventRecord(e0, st);
+      for (int r = 0; r < 3; ++r) launch_args(a, false, st, tl);
+      (void)hipEventRecord(e1, st);
+      if (hipEventSynchronize(e1) != hipSuccess) {
+        status = kfbi_hip_status(hipGetLastError(), "tile autotuner");
+        break;
+      }
+      float ms = 0.0f;
+      (void)hipEventElapsedTime(&ms, e0, e1);
+      tot += ms;
+    }
+    if (status != KFBI_OK) break;
+    // the rule's tile unless another is at least 3% faster
+    const bool better = best_ms < 0.0f || (tl == rule ? tot <= best_ms * 1.03f : tot * 1.03f < best_ms);
+    if (better || (tl == rule && best != rule && tot <= best_ms * 1.03f)) {
+      best = tl;
+      best_ms = tot;
+    }
+  }
+  (void)hipEventDestroy(e0);
+  (void)hipEventDestroy(e1);
+  if (status == KFBI_OK) g_tl_tuned[d - 2][l].store(best);
+  return status;
+}
+
+extern "C" int kfbi_tile_lines(int dim, int N) {
+  if ((dim != 2 && dim != 3) || N < 8 || N > 1024 || (N & (N - 1))) return 0;
+  return tile_lines(dim, N);
+}
+
+extern "C" kfbi_status kfbi_set_tile_lines(int dim, int N, int TL) {
+  if ((dim != 2 && dim != 3) || N < 8 || N > 1024 || (N & (N - 1))) {
+    kfbi_set_error("tile lines: dim 2 or 3 and N a power of two in [8, 1024]");
+    return KFBI_E_INVALID;
+  }
+  const std::vector<int> cand = tile_candidates(dim, N);
+  if (TL != 0 && std::find(cand.begin(), cand.end(), TL) == cand.end()) {
+    kfbi_set_error("tile lines %d is not a candidate for dim %d, N %d", TL, dim, N);
+    return KFBI_E_INVALID;
+  }
+  g_tl_forced[dim - 2][log2i(N)].store(TL);
   return KFBI_OK;
 }
 

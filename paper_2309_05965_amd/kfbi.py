@@ -99,6 +99,8 @@ ABI = {
     "kfbi_plan_destroy": ([ctypes.c_void_p], ctypes.c_int),
     "kfbi_box_solve_noalloc": ([ctypes.c_int, ctypes.c_int, ctypes.c_int, ctypes.c_double, ctypes.c_double,
                                 ctypes.c_double, c_double_p, c_double_p, ctypes.c_void_p], ctypes.c_int),
+    "kfbi_tile_lines": ([ctypes.c_int, ctypes.c_int], ctypes.c_int),
+    "kfbi_set_tile_lines": ([ctypes.c_int, ctypes.c_int, ctypes.c_int], ctypes.c_int),
     "kfbi_batch_create": ([ctypes.c_void_p, ctypes.c_int, ctypes.c_int, ctypes.POINTER(ctypes.c_void_p)],
                           ctypes.c_int),
     "kfbi_batch_sizes": ([ctypes.c_void_p, ctypes.POINTER(ctypes.c_int64), ctypes.POINTER(ctypes.c_int64)],
@@ -394,6 +396,17 @@ class Plan:
             _check(st)
         return psi, u, {"iters": info.iters, "status": info.status, "est_rel_res": info.est_rel_res,
                         "true_rel_res": info.true_rel_res}
+
+
+def tile_lines(dim, N):
+    """Lines per tile of the sine-transform passes on a (dim, N) grid (the
+    override, the autotuner's choice or the built-in rule)."""
+    return int(load().kfbi_tile_lines(int(dim), int(N)))
+
+
+def set_tile_lines(dim, N, TL):
+    """Override the tile lines of a grid (0 removes the override)."""
+    _check(load().kfbi_set_tile_lines(int(dim), int(N), int(TL)))
 
 
 def box_solve_noalloc(dim, order, N, lo, hi, kappa, F, v):

@@ -21,7 +21,7 @@ def _lib():
 
 def declared_functions():
     src = open(HEADER).read()
-    return sorted(set(re.findall(r"^(?:kfbi_status|const char\*)\s+(kfbi_\w+)\s*\(", src, re.M)))
+    return sorted(set(re.findall(r"^(?:kfbi_status|const char\*|int)\s+(kfbi_\w+)\s*\(", src, re.M)))
 
 
 def test_every_declared_symbol_is_exported():

@@ -133,6 +133,35 @@ def test_lockstep_group_equals_single_solves_bitwise():
     assert len(set(its)) > 1
 
 
+def test_lockstep_mixed_grid_sizes_equal_single_solves_bitwise():
+    """Stars on 64^2, 128^2, 256^2 and 512^2 grids in one worker's lockstep
+    group: the passes of the problems up to 256^2 share one launch
+    (k_dstm: each work group finds its problem and runs that size's pass),
+    the 512^2 ones their own per pass; every density, solution and
+    iteration count equals the problem's own solve bit for bit."""
+    from paper_2309_05965_amd import kfbi
+    from paper_2309_05965_amd import manufactured as M
+    rng = np.random.default_rng(5)
+    probs = []
+    for N in (64, 128, 256, 512, 64, 256, 128, 512):
+        a = rng.uniform(0.0, 0.01, 7)
+        ph = rng.uniform(0.0, 2 * np.pi, 7)
+        probs.append(W.problem(2, 4, N, -1.0, 1.0, 10.0 ** rng.uniform(-2, 2), 1.0, 1.0,
+                               [W.star2d(0.0, 0.0, 0.4, [0.0] + list(a * np.cos(ph)), [0.0] + list(-a * np.sin(ph)))]))
+    b = kfbi.Batch(probs, workers=1)
+    st, plans, data, psi = batch_data(b, probs, ["star2d"] * len(probs))
+    ok = [i for i in range(len(probs)) if st[i] == 0]
+    assert len(ok) >= 6
+    u, info, _ = b.solve(data, psi, tol=1e-10, keep_u=True, raise_on_fail=False)
+    off = np.concatenate([[0], np.cumsum([(p["N"] + 1) ** 2 for p in probs])])
+    for i in ok:
+        gp = kfbi.Plan(probs[i])
+        psi1, u1, i1 = gp.solve(M.plan_data(gp, "star2d"), tol=1e-10)
+        assert info[i]["status"] == 0 and info[i]["iters"] == i1["iters"], (i, info[i], i1)
+        assert torch.equal(psi[i], psi1), i
+        assert torch.equal(u[int(off[i]):int(off[i + 1])], u1), i
+
+
 PSI_STRIDE = 20000
 
 

@@ -298,3 +298,35 @@ def test_torus_sphere_unresolved_at_32():
     with pytest.raises(kfbi.KfbiError) as eg:
         kfbi.Plan(prob)
     assert eg.value.name.lower() == eo.value.status == "unresolved"
+
+
+@pytest.mark.parametrize("dim,N", [(3, 64), (3, 128), (3, 256)])
+def test_tile_lines_do_not_change_results(dim, N):
+    """The tile autotuner may pick any candidate tile: box solves with every
+    candidate are bitwise equal, and the tile in use after a plan's creation
+    is one of them (the autotuner's or the rule's).  (2D grids have fewer
+    than 256 tiles at any tile and keep the rule.)"""
+    from paper_2309_05965_amd import kfbi
+    if dim == 3:
+        prob = W.problem(3, 4, N, -1.0, 1.0, 1.0, 5.0, 0.5, [W.sphere3d(0.03, -0.02, 0.01, 0.52)])
+    else:
+        prob = W.problem(2, 4, N, -1.0, 1.0, 1.0, 1.0, 1.0, [W.ellipse2d(0.0, 0.0, 0.45, 0.45)])
+    gp = kfbi.Plan(prob)
+    tuned = kfbi.tile_lines(dim, N)
+    assert tuned in (2, 4, 6, 8)
+    F = dev(np.random.default_rng(N).standard_normal((N + 1) ** dim))
+    outs = {}
+    try:
+        for tl in (2, 4, 6, 8):
+            try:
+                kfbi.set_tile_lines(dim, N, tl)
+            except kfbi.KfbiError:
+                continue
+            outs[tl] = gp.box_solve(F).clone()
+    finally:
+        kfbi.set_tile_lines(dim, N, 0)
+    assert len(outs) >= 2 and tuned in outs
+    ref = outs[min(outs)]
+    for tl, o in outs.items():
+        assert torch.equal(o, ref), tl
+    assert kfbi.tile_lines(dim, N) == tuned
