@@ -346,7 +346,7 @@ kfbi_status kfbi_box_solve(kfbi_plan* plan, const double* F, double* v);
  * caller's override (kfbi_set_tile_lines), else the autotuner's choice (at
  * the first plan of that grid in the process the library times the x pass
  * and the most strided pass for every candidate tile and keeps the fastest
- * unless it is within 3% of the built-in rule; KFBI_TILE_AUTOTUNE=0 in the
+ * unless it is within 10% of the built-in rule's tile; KFBI_TILE_AUTOTUNE=0 in the
  * environment keeps the rule), else the rule.  Results do not depend on it:
  * every even tile pairs the lines the same way and each line's transform is
  * the same.  Returns 0 for an invalid grid. */

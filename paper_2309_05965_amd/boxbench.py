@@ -59,7 +59,9 @@ def main():
     ms = (time.perf_counter() - t0) / a.solves * 1e3
     cycles, rel = plan.box_stats()
     print(json.dumps({"dim": a.dim, "N": a.N, "solver": a.solver, "eps": a.eps, "ms_per_box_solve": ms,
-                      "corrections": cycles, "rel_residual": rel}), flush=True)
+                      "corrections": cycles, "rel_residual": rel,
+                      "tile_lines": {"N": kfbi.tile_lines(a.dim, a.N), "N/2": kfbi.tile_lines(a.dim, a.N // 2)}}),
+          flush=True)
 
 
 if __name__ == "__main__":

@@ -306,6 +306,10 @@ kfbi_status plan_resetup(kfbi_plan* pl, const kfbi_problem* prob);   // S0 + S1 
 void plan_release(kfbi_plan* pl);
 // dst.hip (step S3)
 kfbi_status dst_init(kfbi_plan* pl);
+// the tile autotuner of the sine-transform passes of grid g (once per grid
+// and process), on that grid's tables and pass buffers
+kfbi_status dst_autotune_grid(const GridDesc& g, const double* tw, const double* eig1, double* T1, double* T2,
+                              hipStream_t st);
 void dst_solve(kfbi_plan* pl, const double* F, double* v);
 // Graph capture takes this exclusively; plan creation, set-up, buffer
 // growth and destruction (allocations, frees and host copies, which may

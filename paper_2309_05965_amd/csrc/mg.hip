@@ -1227,6 +1227,7 @@ kfbi_status mg_configure(kfbi_plan* pl, int solver, double eps, int maxit) {
     HIPCHK(hipMemcpyAsync(pl->mg_eigc, eig.data(), sizeof(double) * eig.size(), hipMemcpyHostToDevice, pl->stream));
     HIPCHK(hipStreamSynchronize(pl->stream));   // the host tables go out of scope
   }
+  KCHK(dst_autotune_grid(gc, pl->mg_twc, pl->mg_eigc, pl->mg_T1c, pl->mg_T2c, pl->stream));
   if (!pl->mg_part) {
     if (hipMalloc((void**)&pl->mg_part, sizeof(double) * 2 * MG_PART) != hipSuccess ||
         hipMalloc((void**)&pl->mg_ctl, sizeof(int) * (4 + KFBI_GMRES_MAX + 2)) != hipSuccess ||
