@@ -56,6 +56,8 @@ def parse():
     ap.add_argument("--tol", type=float, default=1e-8)
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-forms", action="store_true")
+    ap.add_argument("--workers", type=int, default=1,
+                    help="also time both forms with this many host threads, each with its own plan and stream")
     ap.add_argument("--cpu-suite", action="store_true",
                     help="only time the oracle on every workload (long; one JSON line)")
     return ap.parse_args()
@@ -205,6 +207,63 @@ class HeldOut:
         torch.cuda.synchronize()
         plan.close()
         self.seeds = [it[0] for it in self.items]
+
+
+def run_form_workers(ho, warm, timed, tol, solver, eps, relax, learned_start, workers):
+    """Solves/s of one form with `workers` host threads, each with a plan
+    and a model of its own on a stream of its own, taking every workers-th
+    held-out problem (the library waits on the host inside a solve, so the
+    threads overlap one solve's device work with another's host waits).
+    Returns (solves/s, iterations, true residuals)."""
+    import threading
+    import torch
+    from paper_2309_05965_amd import kfbi, warmstart
+    items = ho.items[:warm + timed]
+    streams = [torch.cuda.Stream() for _ in range(workers)]
+    plans, models = [], []
+    for w in range(workers):
+        with torch.cuda.stream(streams[w]):
+            pl = kfbi.Plan(items[0][1])
+        pl.set_box_solver(solver, eps_in=eps, max_cycles=16)
+        pl.set_box_relaxation(relax)
+        plans.append(pl)
+        models.append(warmstart.load_pretrained() if learned_start else None)
+    errors = []
+
+    def worker(w, idx, out):
+        try:
+            torch.cuda.set_stream(streams[w])
+            for i in idx:
+                _, prob, geom, jmp, data = items[i]
+                plans[w].setup(prob)
+                la = warmstart.learned_args(models[w], geom, jmp) if learned_start else None
+                _, _, info = plans[w].solve(data, tol=tol, learned=la)
+                out.append(info)
+            streams[w].synchronize()
+        except Exception as e:   # reported after the join
+            errors.append(e)
+
+    def run(first, count):
+        outs = [[] for _ in range(workers)]
+        ths = [threading.Thread(target=worker, args=(w, [first + i for i in range(count) if i % workers == w], outs[w]))
+               for w in range(workers)]
+        for t in ths:
+            t.start()
+        for t in ths:
+            t.join()
+        if errors:
+            raise errors[0]
+        return [x for o in outs for x in o]
+
+    run(0, warm)
+    torch.cuda.synchronize()
+    t0 = time.perf_counter()
+    infos = run(warm, timed)
+    torch.cuda.synchronize()
+    el = time.perf_counter() - t0
+    for pl in plans:
+        pl.close()
+    return timed / el, [i["iters"] for i in infos], [i["true_rel_res"] for i in infos]
 
 
 def run_form(ho, warm, timed, tol, solver, eps, relax, learned_start, keep_u=False):
@@ -575,6 +634,12 @@ def main():
         },
         "roofline": roof,
     }
+    if args.workers > 1:
+        wm = run_form_workers(ho, W_, K, tol, "mg32", EPS_FRAC * tol, RELAX, True, args.workers)
+        wp = run_form_workers(ho, W_, K, tol, "mg64", 1e-12, 0.0, False, args.workers)
+        out["config"]["workers_%d" % args.workers] = {
+            "mixed_solves_per_s": wm[0], "plain_fp64_solves_per_s": wp[0], "mixed_learned_over_plain": wm[0] / wp[0],
+            "true_rel_res_max": {"mixed": float(np.max(wm[2])), "plain": float(np.max(wp[2]))}}
     if not args.no_forms:
         out["forms"] = {
             "ellipsoid128_ingredients": forms_config5_ingredients(ho, W_, min(K, 8), tol),
