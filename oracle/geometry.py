@@ -323,9 +323,19 @@ def stencils(prob, surf):
     each transverse axis.  The point on line a0 + o + s is the surface point
     (primary or not) of the same interface on that family-r line nearest to
     p along e_r (lowest index on ties); it is valid when
-    |delta| <= 2 h (|o + s|_1 + 1).  For the Dirichlet and the Neumann
-    lattice independently, the first shift s of shift_list for which every
-    point is valid is used; none -> GeometryError('unresolved')."""
+    |delta| <= 2 h (|o + s|_1 + 1).
+
+    Window shifts (rule (b) of Sec. 5.4: the two boundary sets stay
+    together around the centre):
+      (1) both windows moved by the same s, the first s of the Neumann
+          lattice's shift list (each has -s in both lattices) for which every
+          point of both is valid; when the Neumann data is a density (every
+          kind but the interior Dirichlet problem) a first pass over the list
+          takes primary Neumann points only;
+      (2) if no common shift exists, each lattice on its own: the first valid
+          shift of its own list (the Neumann lattice again primary-only first
+          when its data is a density).
+    None -> GeometryError('unresolved')."""
     d = prob["dim"]
     p = degree(prob)
     h = grid_h(prob)
@@ -340,6 +350,8 @@ def stencils(prob, surf):
     fam = surf["fam"].tolist()
     ifc = surf["iface"].tolist()
     primlist = surf["prim"].tolist()
+    n_density = prob.get("bie", "interface") != "dirichlet"
+    npasses = (primlist, None) if n_density else (None,)
     cen = np.nonzero(surf["prim"])[0]
     Nb = cen.size
     Didx = np.zeros((Nb, len(offD)), dtype=np.int64)
@@ -350,20 +362,38 @@ def stencils(prob, surf):
         rs = fam[i]
         T = transverse_axes(d, rs)
         a0 = [int(np.floor((pos[i][b] - lo) / h + 0.5)) for b in T]
-        for out, sh, offs, SL, passes in ((Didx, shD, offD, SD, (None,)),
-                                          (Nidx, shN, offN, SN, (primlist, None))):
-            done = False
-            for pi, req in enumerate(passes):
+        done = False
+        # (1) one shift for both windows
+        for req in npasses:
+            for si, s in enumerate(SN):
+                selD = _pick(prob, table, pos, ifc, i, rs, a0, offD, s, None)
+                if selD is None:
+                    continue
+                selN = _pick(prob, table, pos, ifc, i, rs, a0, offN, s, req)
+                if selN is None:
+                    continue
+                Didx[c], Nidx[c] = selD, selN
+                shD[c] = shN[c] = si
+                done = True
+                break
+            if done:
+                break
+        if done:
+            continue
+        # (2) each lattice on its own (shift numbers offset by 100)
+        for out, sh, offs, SL, passes in ((Didx, shD, offD, SD, (None,)), (Nidx, shN, offN, SN, npasses)):
+            found = False
+            for req in passes:
                 for si, s in enumerate(SL):
                     sel = _pick(prob, table, pos, ifc, i, rs, a0, offs, s, req)
                     if sel is not None:
                         out[c] = sel
-                        sh[c] = si + pi * len(SL)
-                        done = True
+                        sh[c] = 100 + si
+                        found = True
                         break
-                if done:
+                if found:
                     break
-            if not done:
+            if not found:
                 raise GeometryError("unresolved", "no valid collocation stencil for centre %d" % c)
     P = surf["pos"][cen]
     pde = np.zeros((Nb, len(offP), d))

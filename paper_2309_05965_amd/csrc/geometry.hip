@@ -823,8 +823,13 @@ __device__ __forceinline__ bool group_all(bool v) {
 }
 
 // Collocation stencils, one group of STG lanes per centre: every window
-// shift is tested with one lane per lattice offset, the first shift whose
-// points are all valid wins (same order as a sequential search).
+// shift is tested with one lane per lattice offset (both lattices at once
+// for a common shift), the first shift whose points are all valid wins
+// (same order as a sequential search).  First one shift for both windows,
+// from the Neumann lattice's list (its shifts keep offset 0 in both), with
+// primary Neumann points only in a first pass when the Neumann data is a
+// density (all kinds but the interior Dirichlet problem); failing that,
+// each lattice on its own list.
 __global__ void __launch_bounds__(KFBI_BLOCK) k_stencils(StencilArgs a) {
   int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x;
   int64_t c = t / STG;
@@ -838,8 +843,19 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_stencils(StencilArgs a) {
   trans_axes(g.d, r, T);
   int a0[2] = {0, 0};
   for (int j = 0; j < g.d - 1; ++j) a0[j] = (int)floor((S.x(i, T[j]) - g.lo) / g.h + 0.5);
+  const int pass0 = g.bie == KFBI_BIE_DIRICHLET ? 1 : 0;   // 0: primary Neumann points first
   int pD = -1, pN = -1;
   bool okD = false, okN = false;
+  for (int pass = pass0; pass < 2 && !okD; ++pass)
+    for (int si = 0; si < a.lat.nSN && !okD; ++si) {
+      int myD = lane < a.lat.nD ? pick_one(S, i, r, a0, a.lat.offD[lane], a.lat.shN[si], false) : 0;
+      int myN = lane < a.lat.nN ? pick_one(S, i, r, a0, a.lat.offN[lane], a.lat.shN[si], pass == 0) : 0;
+      if (group_all(myD >= 0 && myN >= 0)) {
+        okD = okN = true;
+        pD = myD;
+        pN = myN;
+      }
+    }
   for (int si = 0; si < a.lat.nSD && !okD; ++si) {
     int my = lane < a.lat.nD ? pick_one(S, i, r, a0, a.lat.offD[lane], a.lat.shD[si], false) : 0;
     if (group_all(my >= 0)) {
@@ -847,7 +863,7 @@ __global__ void __launch_bounds__(KFBI_BLOCK) k_stencils(StencilArgs a) {
       pD = my;
     }
   }
-  for (int pass = 0; pass < 2 && !okN; ++pass)
+  for (int pass = pass0; pass < 2 && !okN; ++pass)
     for (int si = 0; si < a.lat.nSN && !okN; ++si) {
       int my = lane < a.lat.nN ? pick_one(S, i, r, a0, a.lat.offN[lane], a.lat.shN[si], pass == 0) : 0;
       if (group_all(my >= 0)) {
