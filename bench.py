@@ -18,11 +18,14 @@ solve (S7).  The jump data are resident in HBM before the timed region.
       relaxed inside GMRES (inexact Krylov), learned initial density;
   config.plain_fp64_solves_per_s: FP64 multigrid to 1e-12, zero start, on
       the same held-out problems (on a plan of its own);
-  config.mixed_learned_over_plain: their ratio (the metric's comparison).
+  config.mixed_learned_over_plain: their ratio (the metric's comparison);
+  forms.ellipsoid128_ingredients: each ingredient alone on the same
+      problems, with the controls of the start: zero, the learned density and
+      psi0 = g2 / (beta_in + beta_out).
 
 Prints one JSON line (rank 0, N=1 only).  The roofline object reports the
-finest-level multigrid smoothing sweep (the most-launched kernel of the
-headline), timed with HIP events on the plan's stream after the timed
+exact coarse-grid solve's sine-transform pass (the kernel with the most time
+in both forms), timed with HIP events on the plan's stream after the timed
 region; cpu_baseline times the FP64 NumPy oracle on this host on one
 held-out problem of the same workload.
 """
@@ -272,7 +275,7 @@ def run_form(ho, warm, timed, tol, solver, eps, relax, learned_start, keep_u=Fal
     Returns (solves/s, iterations, true residuals, densities, solutions)."""
     import torch
     from paper_2309_05965_amd import kfbi, learned, warmstart
-    model = warmstart.load_pretrained() if learned_start else None
+    model = warmstart.load_pretrained() if learned_start is True else None
     items = ho.items[:warm + timed]
     plan = kfbi.Plan(items[0][1])
     plan.set_box_solver(solver, eps_in=eps, max_cycles=16)
@@ -284,8 +287,13 @@ def run_form(ho, warm, timed, tol, solver, eps, relax, learned_start, keep_u=Fal
     def one(i, it):
         _, prob, geom, jmp, data = it
         plan.setup(prob)
-        la = warmstart.learned_args(model, geom, jmp) if learned_start else None
-        psi, _, info = plan.solve(data, tol=tol, learned=la, u_out=U[i] if (keep_u and i >= 0) else None)
+        la = warmstart.learned_args(model, geom, jmp) if learned_start is True else None
+        # the control start psi0 = g2 / (beta_in + beta_out) at the unknowns
+        psi0 = None
+        if learned_start == "g2":
+            psi0 = data["g2"][plan.export("dof_surf").long()] / (prob["beta_in"] + prob["beta_out"])
+        psi, _, info = plan.solve(data, tol=tol, learned=la, psi0=psi0,
+                                  u_out=U[i] if (keep_u and i >= 0) else None)
         return psi, info
 
     for it in items[:warm]:
@@ -346,6 +354,7 @@ def forms_config5_ingredients(ho, warm, timed, tol):
     for name, solver, eps, relax, ls in (
             ("fp32_mg_relaxed_zero_start", "mg32", EPS_FRAC * tol, RELAX, False),
             ("fp64_mg_relaxed_zero_start", "mg64", EPS_FRAC * tol, RELAX, False),
+            ("fp32_mg_relaxed_g2_start", "mg32", EPS_FRAC * tol, RELAX, "g2"),
             ("fp32_mg_unrelaxed_learned_start", "mg32", EPS_FRAC * tol, 0.0, True),
             ("fp64_fft_zero_start", "fft", 1e-12, 0.0, False),
             ("fp64_fft_learned_start", "fft", 1e-12, 0.0, True)):
