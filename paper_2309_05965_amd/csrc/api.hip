@@ -4,6 +4,7 @@
 #include <math.h>
 #include <stdarg.h>
 #include <stdio.h>
+#include <stdlib.h>
 #include <string.h>
 
 #include <chrono>
@@ -1188,6 +1189,59 @@ kfbi_status mg_true_residual(kfbi_plan* pl, const double* psi, int k, int use_x0
   return KFBI_OK;
 }
 
+// A multigrid solve of an interface problem from a given start takes its
+// initial residual from one box solve instead of two: by linearity in the
+// data and the density, r0 = b - A x0 = (g2 - J(w(g1, E x0, ftilde, fhat,
+// gB))) / (beta_in + beta_out) (Alg. 1 steps 1-2 with the same w as step 4).
+// b itself then sets only the scale |b| of the stopping test, which a box
+// solve stopped after 3 corrections gives to about 1e-3.  The grid solution
+// w(E x0, data) is slot 0 of the store, so the true residual's box solve
+// starts from w(E psi, data) and leaves the final solution.  Off with
+// KFBI_MERGED_START=0 in the environment.
+bool merged_start(const kfbi_plan* pl, int use_x0) {
+  if (!use_x0 || pl->box_solver == KFBI_BOX_FFT || pl->g.bie != KFBI_BIE_INTERFACE || !pl->ustore ||
+      pl->ustore_slots < 2)
+    return false;
+  const char* e = getenv("KFBI_MERGED_START");
+  return !(e && e[0] == '0');
+}
+
+// |b - A psi| / |b| of a merged start (psi = x0 + sum y_j v_j): the box
+// solve of (data, E psi) starts from slot 0 + sum y_j slot(1 + j) and stops
+// after at most 3 corrections, continuing with the full cap if short of
+// eps; r = (g2 - J(w)) / (beta_in + beta_out) directly, passed to the
+// residual kernel as b~ - (b~ - r).  w is left in u; b~ - r in work.
+kfbi_status merged_true_residual(kfbi_plan* pl, const kfbi_data& data, const double* psi, int k, double* u,
+                                 double* tr) {
+  const bool guess = k + 1 <= pl->ustore_slots;
+  if (guess) mg_guess_from_store(pl, k, 1, pl->scal + 8, u);
+  for (int pass = 0; pass < 2; ++pass) {
+    const int run_cap = pl->mg_run_cap;
+    if (pass == 0 && guess && (run_cap == 0 || run_cap > 3)) pl->mg_run_cap = 3;
+    pl->mg_guess = guess;
+    final_impl(pl, data, psi, u);
+    pl->mg_guess = false;
+    pl->mg_run_cap = run_cap;
+    op_bie_rhs(pl, data.g2, pl->dn_in, pl->dn_out, pl->work2);
+    vec_diff(pl, pl->n_dof, pl->bvec, pl->work2, pl->work);
+    gm_true_residual(pl, pl->bvec, pl->work, pl->scal + 4);
+    PostReq q{};
+    q.nd = 3;
+    q.dsrc[0] = pl->scal + 4;
+    q.dsrc[1] = pl->scal + 5;
+    q.dsrc[2] = pl->mg_scal + 1;
+    q.ni = 2;
+    q.isrc[0] = pl->mg_ctl + 2;
+    q.isrc[1] = pl->mg_ctl + 3;
+    unsigned seq = 0;
+    KCHK(kfbi_post_launch(pl, q, &seq));
+    KCHK(kfbi_post_collect(pl, q, seq, pl->h_pinned + 2, pl->h_dpinned + 4));
+    *tr = rel_residual(pl->h_dpinned[4], pl->h_dpinned[5]);
+    if (!guess || pl->h_dpinned[6] <= pl->mg_eps) break;
+  }
+  return KFBI_OK;
+}
+
 kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* opts, double* psi, double* u_out,
                         kfbi_info* info, int m, double tol);
 
@@ -1213,14 +1267,32 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
   const bool mg = pl->box_solver != KFBI_BOX_FFT;
   const bool relax = pl->mg_relax > 0.0 && mg;
   const double eps_in = pl->mg_eps, eps_out = mg ? pl->mg_eps_out : eps_in;
-  // Step 1: right-hand side (its grid solution stays in vsbuf)
+  const int use_x0 = opts->start == KFBI_START_GIVEN ? 1 : 0;
+  const bool merged = merged_start(pl, use_x0);
+  // Step 1: right-hand side (its grid solution stays in vsbuf); of a merged
+  // start only its scale, from zero (as a guess: a stop at the cap is no
+  // sign of a short cap) in 3 corrections
   pl->mg_eps = eps_out;
-  rhs_impl(pl, *data, pl->bvec);
+  if (merged) {
+    grid_zero(pl, pl->vsbuf);
+    const int run_cap = pl->mg_run_cap;
+    pl->mg_run_cap = 3;
+    pl->mg_guess = true;
+    rhs_impl(pl, *data, pl->bvec);
+    pl->mg_guess = false;
+    pl->mg_run_cap = run_cap;
+  } else {
+    rhs_impl(pl, *data, pl->bvec);
+  }
   KCHK(set_relax_word(pl, relax ? pl->mg_relax : 0.0));
   // Step 2: initial residual and control word (multigrid: the box solution
-  // of A x0 goes to the store's slot 0)
-  const int use_x0 = opts->start == KFBI_START_GIVEN ? 1 : 0;
-  if (use_x0) {
+  // of A x0, or of a merged start w(E x0, data), goes to the store's slot 0)
+  if (merged) {
+    final_impl(pl, *data, psi, pl->vsbuf);
+    op_bie_rhs(pl, data->g2, pl->dn_in, pl->dn_out, pl->work2);     // r0
+    vec_diff(pl, pl->n_dof, pl->bvec, pl->work2, pl->work);          // b~ - r0 in place of A x0
+    mg_store_solution(pl, pl->vsbuf);
+  } else if (use_x0) {
     matvec_impl(pl, psi, pl->work);
     if (mg) mg_store_solution(pl, pl->vbuf);
   }
@@ -1285,12 +1357,35 @@ kfbi_status solve_steps(kfbi_plan* pl, const kfbi_data* data, const kfbi_opts* o
     KCHK(true_residual(pl, psi, &tr, final_solve));
     return solve_report(pl, info, o, o.k, tr, tol, m);
   }
+  int k = o.k;
+  if (merged) {
+    pl->mg_eps = eps_out;
+    KCHK(merged_true_residual(pl, *data, psi, o.k, u, &tr));
+    // as below: continue from psi with full-accuracy box solves if the
+    // relaxed estimate ran ahead of the true residual (its box solution
+    // becomes slot 0, b~ - r(psi) is in work)
+    if (relax && o.conv && tr > tol && k < m) {
+      KCHK(set_relax_word(pl, 0.0));
+      mg_store_solution(pl, u);
+      gm_residual_start(pl, pl->bvec, pl->work, 1, tol, m - k);
+      GmresOut o2;
+      pl->mg_eps = eps_in;
+      KCHK(gmres_run(pl, tol, m - k, 4, &o2));
+      gm_update(pl, o2.k, psi, 1);
+      pl->mg_eps = eps_out;
+      KCHK(merged_true_residual(pl, *data, psi, o2.k, u, &tr));
+      k += o2.k;
+      o.est = o2.est;
+      o.conv = o2.conv;
+    }
+    pl->mg_eps = eps_in;
+    return solve_report(pl, info, o, k, tr, tol, m);
+  }
   // Multigrid: the final solve's grid solution is, by linearity in the
   // data and the density, the step-1 solution (vsbuf) plus the box
   // solution of A psi (vbuf, left by the true residual); enqueued behind
   // the residual on the guess that no continuation follows.
   auto final_sum = [&] { mg_sum(pl, pl->vsbuf, pl->vbuf, u); };
-  int k = o.k;
   pl->mg_eps = eps_out;
   KCHK(mg_true_residual(pl, psi, o.k, use_x0, &tr, [] {}));
   // with a relaxed inner tolerance the GMRES estimate can run ahead of the

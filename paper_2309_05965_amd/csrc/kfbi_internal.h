@@ -336,6 +336,9 @@ kfbi_status mg_store_reserve(kfbi_plan* pl);
 void mg_store_solution(kfbi_plan* pl, const double* v);
 void mg_guess_from_store(kfbi_plan* pl, int k, int use_x0, const double* y, double* v);
 void mg_sum(kfbi_plan* pl, const double* a, const double* b, double* out);
+// out = a - b over n entries; v = 0 over the grid (fill kernels, safe under capture)
+void vec_diff(kfbi_plan* pl, int64_t n, const double* a, const double* b, double* out);
+void grid_zero(kfbi_plan* pl, double* v);
 void dst_solve_corrections(kfbi_plan* pl, const double* psi, double* v);
 // the matvec box solves of G plans of one grid shape (FFT solver) as one
 // launch per pass; each plan's GMRES control word stops its own work

@@ -694,6 +694,16 @@ __global__ void __launch_bounds__(MG_BLOCK) k_usum(int64_t n, const double* a, c
     out[t] = a[t] + b[t];
 }
 
+__global__ void __launch_bounds__(MG_BLOCK) k_udiff(int64_t n, const double* a, const double* b, double* out) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    out[t] = a[t] - b[t];
+}
+
+__global__ void __launch_bounds__(MG_BLOCK) k_uzero(int64_t n, double* v) {
+  for (int64_t t = (int64_t)blockIdx.x * blockDim.x + threadIdx.x; t < n; t += (int64_t)gridDim.x * blockDim.x)
+    v[t] = 0.0;
+}
+
 // ---------------------------------------------------------------- FP64 outer loop
 struct OuterArgs {
   Ctl ctl;
@@ -1382,6 +1392,14 @@ void mg_guess_from_store(kfbi_plan* pl, int k, int use_x0, const double* y, doub
 
 void mg_sum(kfbi_plan* pl, const double* a, const double* b, double* out) {
   hipLaunchKernelGGL(k_usum, dim3(gsblk(pl->g.n_nodes)), dim3(MG_BLOCK), 0, pl->stream, pl->g.n_nodes, a, b, out);
+}
+
+void vec_diff(kfbi_plan* pl, int64_t n, const double* a, const double* b, double* out) {
+  if (n > 0) hipLaunchKernelGGL(k_udiff, dim3(gsblk(n)), dim3(MG_BLOCK), 0, pl->stream, n, a, b, out);
+}
+
+void grid_zero(kfbi_plan* pl, double* v) {
+  hipLaunchKernelGGL(k_uzero, dim3(gsblk(pl->g.n_nodes)), dim3(MG_BLOCK), 0, pl->stream, pl->g.n_nodes, v);
 }
 
 void mg_matvec_rhs(kfbi_plan* pl) {

@@ -234,8 +234,9 @@ def test_relaxed_iteration_caps(case):
 @pytest.mark.parametrize("start", ["zero", "given"])
 def test_mixed_true_residual_against_accurate_operator(case, start):
     """The mixed form (FP32 multigrid to eps_in = tol / 10, relaxed inside
-    GMRES; the right-hand side, A x0 and the true residual to tol / 100)
-    from a zero and from a given start: the reported true residual agrees
+    GMRES; the right-hand side, A x0 -- from a given start the initial
+    residual of one box solve of the data and x0 together -- and the true
+    residual to tol / 100) from a zero and from a given start: the reported true residual agrees
     with one recomputed against a right-hand side and matvec to 1e-13
     within tol / 10 and that one meets tol too; the density equals the
     exact-box-solve density to its conditioning (1e-6; 1e-4 on the
@@ -265,3 +266,39 @@ def test_mixed_true_residual_against_accurate_operator(case, start):
         case, start, info["iters"], info["true_rel_res"], tr))
     assert abs(tr - info["true_rel_res"]) <= 1e-9 and tr < 1e-8
     assert float(((psi - ref).norm() / ref.norm()).item()) < (1e-4 if case == "ellipsoid_64" else 1e-6)
+
+
+@pytest.mark.parametrize("case", ["c2_128", "ellipsoid_64"])
+def test_merged_start_matches_two_box_solve_start(case, monkeypatch):
+    """From a given start with a multigrid box solver, the initial residual
+    b - A x0 = (g2 - J(w(g1, E x0, ...))) / (beta_in + beta_out) comes from
+    one box solve of the data and x0 together (linearity of the simple
+    interface problem, Sec. 3.2 / Alg. 1); with KFBI_MERGED_START=0 from
+    separate box solves of b and A x0.  Both meet the tolerance against an
+    accurate operator; densities and solutions agree to the solves'
+    accuracy."""
+    from paper_2309_05965_amd import kfbi
+    if case == "c2_128":
+        prob, sol = W.config2(128)
+    else:
+        prob, sol = W.config5(1_000_003, 64)[0], {0: W.f_exp3, 1: W.f_sin3}
+    gp = kfbi.Plan(prob)
+    data = kfbi.device_data(gp, prob, sol)
+    ref, _, _ = gp.solve(data, tol=1e-12)
+    g = torch.Generator(device="cpu").manual_seed(5)
+    x0 = (ref * (1.0 + 0.05 * torch.randn(ref.shape, generator=g, dtype=torch.float64).cuda())).contiguous()
+    gp.set_box_solver("mg64", eps_in=1e-12, max_cycles=40)
+    out = {}
+    for merged in ("1", "0"):
+        monkeypatch.setenv("KFBI_MERGED_START", merged)
+        psi, u, info = gp.solve(data, tol=1e-10, psi0=x0)
+        assert info["status"] == 0 and info["true_rel_res"] < 1e-10, (merged, info)
+        out[merged] = (psi.clone(), u.clone(), info)
+    (p1, u1, i1), (p0, u0, i0) = out["1"], out["0"]
+    assert abs(i1["iters"] - i0["iters"]) <= 1, (i1, i0)
+    b = gp.rhs(data)
+    for psi in (p1, p0):
+        assert float(((b - gp.matvec(psi)).norm() / b.norm()).item()) < 2e-10
+    rel = lambda a, c: float(((a - c).norm() / c.norm()).item())
+    bound = 1e-7 if case == "c2_128" else 1e-5
+    assert rel(p1, p0) < bound and rel(u1, u0) < bound, (rel(p1, p0), rel(u1, u0))
