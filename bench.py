@@ -63,6 +63,9 @@ def parse():
                     help="also time both forms with this many host threads, each with its own plan and stream")
     ap.add_argument("--cpu-suite", action="store_true",
                     help="only time the oracle on every workload (long; one JSON line)")
+    ap.add_argument("--form", default=None,
+                    choices=("star512", "torus_sphere128", "torus_sphere256", "batch512_random_stars", "widened_rows"),
+                    help="only this entry of `forms` (for profiling; one JSON line)")
     return ap.parse_args()
 
 
@@ -600,6 +603,12 @@ def main():
     # used for the solve as it is; on the default stream the library orders
     # a private stream before and after every solve with events)
     torch.cuda.set_stream(torch.cuda.Stream())
+    if args.form:
+        run = {"star512": lambda: forms_star512(args.tol), "torus_sphere128": lambda: forms_config3(args.tol, 128),
+               "torus_sphere256": lambda: forms_config3(args.tol, 256), "batch512_random_stars": forms_batch,
+               "widened_rows": lambda: forms_widened(args.tol)}[args.form]
+        print(json.dumps({"forms": {args.form: run()}}), flush=True)
+        return
     N, tol = args.N, args.tol
     W_, K = args.warmup, args.steps
     ho = HeldOut(W_ + K, N)
