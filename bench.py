@@ -47,7 +47,7 @@ HBM_PEAK_GBS = 8000.0
 HELDOUT0 = 1_000_000
 # mixed form: inner tolerance tol * EPS_FRAC, relaxed inside GMRES by RELAX
 EPS_FRAC = 0.1
-RELAX = 0.1
+RELAX = 3.0
 
 
 def parse():

@@ -168,8 +168,8 @@ __device__ __forceinline__ double wave_max(double v) {
 // the pivot is the unused row with the largest |entry| in column k (lowest
 // lane on ties: a max reduction, then the first lane of the ballot of lanes
 // holding it); rows are not swapped.  The pivot lane scales its row
-// (column k becomes 1/pivot) and the other lanes read it lane to lane
-// (readlane, no LDS round trip or barrier) and eliminate.  With p_k the pivot lane of step k, lane p_a ends up holding
+// (column k becomes 1/pivot) and writes it to LDS, and after a barrier the
+// other lanes read it (broadcast reads) and eliminate.  With p_k the pivot lane of step k, lane p_a ends up holding
 // row a of the inverse with its column j at position p_j.
 template <int NC>
 __global__ void __launch_bounds__(64) k_factor(FactorArgs a) {
@@ -200,13 +200,16 @@ __global__ void __launch_bounds__(64) k_factor(FactorArgs a) {
   bool singular = false;
   // the lanes that hold rows: the pivot search reduces over W lanes
   constexpr int W = NC <= 16 ? 16 : (NC <= 32 ? 32 : 64);
-  constexpr int KU = NC <= 16 ? NC : 1;   // unrolled steps: small systems only (registers)
-#pragma unroll KU
-  for (int k = 0; k < NC; ++k) {
-    // column k of this lane's row
-    double rk = 0.0;
+  // the scaled pivot row of step k goes through prow[k & 1]: written by the
+  // pivot lane, read by every lane after the barrier (the other buffer is
+  // the one the next step writes, so no read of step k races with it)
+  __shared__ double prow[2][NC];
+  // every step unrolled: column k of the row is a fixed register (a zero
+  // or non-finite pivot ends the elimination: the later steps do nothing)
 #pragma unroll
-    for (int m = 0; m < NC; ++m) rk = m == k ? row[m] : rk;
+  for (int k = 0; k < NC; ++k) {
+    if (singular) continue;
+    const double rk = row[k];
     // pivot: the largest |value| among unused rows, the lowest lane on ties
     const double best = used ? -1.0 : fabs(rk);
     double mx = best;
@@ -214,7 +217,7 @@ __global__ void __launch_bounds__(64) k_factor(FactorArgs a) {
     mx = lane_value(mx, 0);
     if (!(mx > 0.0) || !isfinite(mx)) {
       singular = true;
-      break;
+      continue;
     }
     const int pl = __ffsll((unsigned long long)__ballot(best == mx)) - 1;
     if (lane == 0) pvt[k] = pl;
@@ -222,16 +225,20 @@ __global__ void __launch_bounds__(64) k_factor(FactorArgs a) {
       const double ri = 1.0 / rk;
 #pragma unroll
       for (int m = 0; m < NC; ++m) row[m] = m == k ? ri : row[m] * ri;
+#pragma unroll
+      for (int m = 0; m < NC; ++m) prow[k & 1][m] = row[m];
       used = true;
       myk = k;
     }
-    // the scaled pivot row, lane to lane, eight entries at a time
+    __syncthreads();
+    // the scaled pivot row from LDS (one broadcast read per entry), eight
+    // entries at a time
     const double f = (lane != pl && live) ? rk : 0.0;
 #pragma unroll
     for (int m0 = 0; m0 < NC; m0 += 8) {
       double pr[8];
 #pragma unroll
-      for (int m = m0; m < NC && m < m0 + 8; ++m) pr[m - m0] = lane_value(row[m], pl);
+      for (int m = m0; m < NC && m < m0 + 8; ++m) pr[m - m0] = prow[k & 1][m];
       if (lane != pl && live) {
 #pragma unroll
         for (int m = m0; m < NC && m < m0 + 8; ++m) row[m] = m == k ? -(f * pr[m - m0]) : row[m] - f * pr[m - m0];

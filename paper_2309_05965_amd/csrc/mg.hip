@@ -39,6 +39,7 @@ namespace {
 
 constexpr int MG_BLOCK = 256;
 constexpr int MG_PART = 8192;            // partial sums of the outer residual (per block)
+constexpr int CHECK_BLOCK = 1024;        // threads of the stopping test
 
 template <typename T>
 struct Lev {
@@ -92,6 +93,34 @@ struct Ctl {
 };
 
 __device__ __forceinline__ bool skip(const Ctl& c) { return (c.gctl && c.gctl[1]) || c.mctl[0]; }
+
+// sums of a and b over the work group (NT threads): a butterfly within each
+// wavefront, then the wavefront sums in order (one barrier); the results
+// are valid in thread 0.  sh holds 2 NT / 64 values.
+template <int NT>
+__device__ __forceinline__ void block_sum2(double& a, double& b, double* sh) {
+#pragma unroll
+  for (int o = 32; o > 0; o >>= 1) {
+    a += __shfl_xor(a, o, 64);
+    b += __shfl_xor(b, o, 64);
+  }
+  constexpr int NW = NT / 64;
+  const int w = threadIdx.x >> 6;
+  if ((threadIdx.x & 63) == 0) {
+    sh[w] = a;
+    sh[NW + w] = b;
+  }
+  __syncthreads();
+  if (threadIdx.x == 0) {
+    a = sh[0];
+    b = sh[NW];
+#pragma unroll
+    for (int i = 1; i < NW; ++i) {
+      a += sh[i];
+      b += sh[NW + i];
+    }
+  }
+}
 
 // grid index of interior node t (x fastest); grids have at most 1025^3
 // nodes, so 32-bit arithmetic is exact
@@ -170,7 +199,7 @@ __device__ __forceinline__ void coords(int d, int n1, int64_t idx, int& i0, int&
 // z; 2D: 256 nodes along x, marching along y) and a chunk of KZ planes; the
 // planes z-1, z, z+1 of the stencil input (with a one-node halo) rotate
 // through LDS, so every input value is read from memory about once.
-enum { SW_SMOOTH = 0, SW_SMOOTH2 = 1, SW_RESID = 2, SW_OUTER = 3, SW_SMOOTH_UPD = 4 };
+enum { SW_SMOOTH = 0, SW_SMOOTH2 = 1, SW_RESID = 2, SW_OUTER = 3, SW_SMOOTH_UPD = 4, SW_PSMOOTH = 5 };
 
 template <typename TS, typename TO>
 struct SweepArgs {
@@ -184,6 +213,8 @@ struct SweepArgs {
   double* part;      // SW_OUTER: per-block sums of r^2 (and F^2 at part + MG_PART)
   double* v;         // SW_SMOOTH_UPD: v += (double) smoothed value (out unused)
   int* mctl;         // SW_SMOOTH_UPD: corrections counter mctl[1], raised once
+  const double* ec;  // SW_PSMOOTH: FP64 coarse correction (full coarse grid)
+  int Nc, n1c;       // SW_PSMOOTH: coarse grid size
 };
 
 template <int D>
@@ -203,12 +234,16 @@ struct Tile {
 //        SW_SMOOTH_UPD  the last smoothing step of a cycle and the update of
 //                    the outer iterate in one: v += (double)(u + coef (f - A u))
 //                    (3D tile sweep only)
+//        SW_PSMOOTH  the prolongation of the coarse correction and the first
+//                    post-smoothing step in one: u' = u + (TS) P e_c at every
+//                    staged interior node, out = u' + coef (f - A u')
+//                    (3D tile sweep only; u' itself is not stored)
 template <typename TS, typename TO, int D, int MODE>
 __global__ void __launch_bounds__(256) k_sweep(Ctl ctl, SweepArgs<TS, TO> a) {
   using TT = Tile<D>;
   constexpr int NL = (TT::PL + 255) / 256;     // plane elements per thread
   __shared__ TS pl[3][TT::PL];
-  __shared__ double red[MODE == SW_OUTER ? 2 : 1][MODE == SW_OUTER ? 256 : 1];
+  __shared__ double red[MODE == SW_OUTER ? 8 : 1];
   double acc_r = 0.0, acc_f = 0.0;
   const bool active = !skip(ctl);
   if (active) {
@@ -309,20 +344,11 @@ __global__ void __launch_bounds__(256) k_sweep(Ctl ctl, SweepArgs<TS, TO> a) {
     }
   }
   if (MODE == SW_OUTER) {
-    red[0][threadIdx.x] = acc_r;
-    red[1][threadIdx.x] = acc_f;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (threadIdx.x < (unsigned)o) {
-        red[0][threadIdx.x] += red[0][threadIdx.x + o];
-        red[1][threadIdx.x] += red[1][threadIdx.x + o];
-      }
-      __syncthreads();
-    }
+    block_sum2<256>(acc_r, acc_f, red);
     if (threadIdx.x == 0) {
       const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-      a.part[b] = red[0][0];
-      a.part[MG_PART + b] = red[1][0];
+      a.part[b] = acc_r;
+      a.part[MG_PART + b] = acc_f;
     }
   }
 }
@@ -350,7 +376,7 @@ template <typename TS, typename TO, int MODE, int NX>
 __global__ void __launch_bounds__(256) k_sweep3(Ctl ctl, SweepArgs<TS, TO> a) {
   using TT = Tile3<NX>;
   __shared__ TS pl[2][TT::PY * TT::PXS];
-  __shared__ double red[MODE == SW_OUTER ? 2 : 1][MODE == SW_OUTER ? 256 : 1];
+  __shared__ double red[MODE == SW_OUTER ? 8 : 1];
   double acc_r = 0.0, acc_f = 0.0;
   if (!skip(ctl)) {
     const int m = a.N - 1, n1 = a.n1;
@@ -448,20 +474,11 @@ __global__ void __launch_bounds__(256) k_sweep3(Ctl ctl, SweepArgs<TS, TO> a) {
     }
   }
   if (MODE == SW_OUTER) {
-    red[0][threadIdx.x] = acc_r;
-    red[1][threadIdx.x] = acc_f;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (threadIdx.x < (unsigned)o) {
-        red[0][threadIdx.x] += red[0][threadIdx.x + o];
-        red[1][threadIdx.x] += red[1][threadIdx.x + o];
-      }
-      __syncthreads();
-    }
+    block_sum2<256>(acc_r, acc_f, red);
     if (threadIdx.x == 0) {
       const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-      a.part[b] = red[0][0];
-      a.part[MG_PART + b] = red[1][0];
+      a.part[b] = acc_r;
+      a.part[MG_PART + b] = acc_f;
     }
   }
 }
@@ -481,7 +498,7 @@ __global__ void __launch_bounds__(256) k_sweep3t(Ctl ctl, SweepArgs<TS, TO> a) {
   constexpr int PL = ST_PX * ST_PY * PZ;            // staged input values
   constexpr int NL = (PL + 255) / 256;
   __shared__ TS blk[PZ * ST_PY * ST_PXS];
-  __shared__ double red[MODE == SW_OUTER ? 2 : 1][MODE == SW_OUTER ? 256 : 1];
+  __shared__ double red[MODE == SW_OUTER ? 8 : 1];
   double acc_r = 0.0, acc_f = 0.0;
   if (!skip(ctl)) {
     if (MODE == SW_SMOOTH_UPD && threadIdx.x == 0 && blockIdx.x + blockIdx.y + blockIdx.z == 0)
@@ -503,6 +520,25 @@ __global__ void __launch_bounds__(256) k_sweep3t(Ctl ctl, SweepArgs<TS, TO> a) {
                  ? a.s[gx + (int64_t)n1 * (gy + (int64_t)n1 * gz)]
                  : (TS)0;
     }
+    // SW_PSMOOTH: the coarse nodes under the staged fine block (fine
+    // x0 .. x0+65 needs coarse x0/2 .. x0/2+33, likewise 4 in y and z),
+    // staged in LDS with one round of loads
+    constexpr int CX = 34, CY = 4, CZ = 4, NCB = CX * CY * CZ;
+    constexpr int NCL = MODE == SW_PSMOOTH ? (NCB + 255) / 256 : 1;
+    __shared__ double cb[MODE == SW_PSMOOTH ? NCB : 1];
+    const int X0 = x0 / 2, Y0 = y0 / 2, Z0 = z0 / 2;
+    double rc[NCL];
+    if constexpr (MODE == SW_PSMOOTH) {
+#pragma unroll
+      for (int q = 0; q < NCL; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        const int px = i % CX, py = (i / CX) % CY, pz = i / (CX * CY);
+        const int gx = X0 + px, gy = Y0 + py, gz = Z0 + pz;
+        rc[q] = (i < NCB && gx <= a.Nc && gy <= a.Nc && gz <= a.Nc)
+                    ? a.ec[gx + (int64_t)a.n1c * (gy + (int64_t)a.n1c * gz)]
+                    : 0.0;
+      }
+    }
     const int ox = x0 + tx + 1, oy = y0 + ty + 1;
     const bool colok = ox <= m && oy <= m;
     constexpr bool NEEDF = MODE != SW_SMOOTH2;
@@ -511,6 +547,40 @@ __global__ void __launch_bounds__(256) k_sweep3t(Ctl ctl, SweepArgs<TS, TO> a) {
     for (int k = 0; k < TZ; ++k) {
       const int oz = z0 + k + 1;
       fv[k] = (NEEDF && colok && oz <= m) ? a.f[ox + (int64_t)n1 * (oy + (int64_t)n1 * oz)] : (TS)0;
+    }
+    if constexpr (MODE == SW_PSMOOTH) {
+#pragma unroll
+      for (int q = 0; q < NCL; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        if (i < NCB) cb[i] = rc[q];
+      }
+      __syncthreads();
+      // u' = u + (TS) P e_c at the interior nodes of the block (the box
+      // boundary keeps its zero): the average of the coarse values at the
+      // corners of the coarse cell face / edge the node lies on, summed in
+      // FP64 with c0 fastest (the reciprocal of the count is exact).  All
+      // eight corners are read (every one lies inside the staged coarse
+      // block) and the ones off the node's face add zero, so the loads
+      // issue together and no lane branches.
+#pragma unroll
+      for (int q = 0; q < NL; ++q) {
+        const int i = threadIdx.x + 256 * q;
+        const int ii = i < PL ? i : PL - 1;   // the block's last node for the unused slots
+        const int px = ii % ST_PX, py = (ii / ST_PX) % ST_PY, pz = ii / (ST_PX * ST_PY);
+        const int gx = x0 + px, gy = y0 + py, gz = z0 + pz;
+        const int p0 = gx & 1, p1 = gy & 1, p2 = gz & 1;
+        const int I0 = (gx >> 1) - X0, I1 = (gy >> 1) - Y0, I2 = (gz >> 1) - Z0;
+        const double* cq = cb + I0 + CX * (I1 + CY * I2);
+        double cv[8];
+#pragma unroll
+        for (int c = 0; c < 8; ++c) cv[c] = cq[(c & 1) + CX * (((c >> 1) & 1) + CY * (c >> 2))];
+        double sc = 0.0;
+#pragma unroll
+        for (int c = 0; c < 8; ++c)
+          sc += ((c & 1) <= p0 && ((c >> 1) & 1) <= p1 && (c >> 2) <= p2) ? cv[c] : 0.0;
+        if (i < PL && gx >= 1 && gx <= m && gy >= 1 && gy <= m && gz >= 1 && gz <= m)
+          r[q] = r[q] + (TS)(sc * (1.0 / (double)(1 << (p0 + p1 + p2))));
+      }
     }
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
@@ -542,7 +612,7 @@ __global__ void __launch_bounds__(256) k_sweep3t(Ctl ctl, SweepArgs<TS, TO> a) {
         if (colok && oz <= m) {
           const TS sv = acc1 + q2;
           const int64_t idx = ox + (int64_t)n1 * (oy + (int64_t)n1 * oz);
-          if (MODE == SW_SMOOTH) {
+          if (MODE == SW_SMOOTH || MODE == SW_PSMOOTH) {
             a.out[idx] = (TO)(ctr + a.coef * (fv[k] - sv));
           } else if (MODE == SW_SMOOTH2) {
             const TS u1 = a.coef * ctr;
@@ -566,73 +636,11 @@ __global__ void __launch_bounds__(256) k_sweep3t(Ctl ctl, SweepArgs<TS, TO> a) {
     }
   }
   if (MODE == SW_OUTER) {
-    red[0][threadIdx.x] = acc_r;
-    red[1][threadIdx.x] = acc_f;
-    __syncthreads();
-    for (int o = 128; o > 0; o >>= 1) {
-      if (threadIdx.x < (unsigned)o) {
-        red[0][threadIdx.x] += red[0][threadIdx.x + o];
-        red[1][threadIdx.x] += red[1][threadIdx.x + o];
-      }
-      __syncthreads();
-    }
+    block_sum2<256>(acc_r, acc_f, red);
     if (threadIdx.x == 0) {
       const int b = blockIdx.x + gridDim.x * (blockIdx.y + gridDim.y * blockIdx.z);
-      a.part[b] = red[0][0];
-      a.part[MG_PART + b] = red[1][0];
-    }
-  }
-}
-
-// u_f += (T) P e_c on 3D grids up to 128^3, tile by tile: a work group
-// stages the coarse nodes under its 64 x 4 x 4 fine nodes (a 34 x 4 x 4
-// block) in LDS with one round of loads, then each thread updates a column
-// of 4 fine nodes.  Same arithmetic as op_prolong.
-template <typename T>
-__global__ void __launch_bounds__(256) k_prolong3t(Ctl ctl, Lev<T> Fl, int Nc, int n1c, const double* ec, T* u) {
-  if (skip(ctl)) return;
-  constexpr int CX = 34, CY = 4, CZ = 4, NC = CX * CY * CZ;
-  __shared__ double cb[NC];
-  const int N = Fl.N, n1 = Fl.n1;
-  const int nbx = gridDim.x, nby = gridDim.y;
-  const int lb = kfbi_xcd_block(blockIdx.x + nbx * (blockIdx.y + nby * blockIdx.z), nbx * nby * gridDim.z);
-  const int bx = lb % nbx, by = (lb / nbx) % nby, bz = lb / (nbx * nby);
-  const int x0 = 64 * bx, y0 = 4 * by, z0 = 4 * bz;
-  const int X0 = x0 / 2, Y0 = y0 / 2, Z0 = z0 / 2;
-  double rc[(NC + 255) / 256];
-#pragma unroll
-  for (int q = 0; q < (NC + 255) / 256; ++q) {
-    const int i = threadIdx.x + 256 * q;
-    const int px = i % CX, py = (i / CX) % CY, pz = i / (CX * CY);
-    const int gx = X0 + px, gy = Y0 + py, gz = Z0 + pz;
-    rc[q] = (i < NC && gx <= Nc && gy <= Nc && gz <= Nc) ? ec[gx + (int64_t)n1c * (gy + (int64_t)n1c * gz)] : 0.0;
-  }
-  const int tx = threadIdx.x & 63, ty = threadIdx.x >> 6;
-  const int ox = x0 + tx + 1, oy = y0 + ty + 1;
-  T uv[4];
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int oz = z0 + k + 1;
-    uv[k] = (ox < N && oy < N && oz < N) ? u[ox + (int64_t)n1 * (oy + (int64_t)n1 * oz)] : (T)0;
-  }
-#pragma unroll
-  for (int q = 0; q < (NC + 255) / 256; ++q) {
-    const int i = threadIdx.x + 256 * q;
-    if (i < NC) cb[i] = rc[q];
-  }
-  __syncthreads();
-  const int p0 = ox & 1, p1 = oy & 1;
-  const int I0 = (ox >> 1) - X0, I1 = (oy >> 1) - Y0;
-#pragma unroll
-  for (int k = 0; k < 4; ++k) {
-    const int oz = z0 + k + 1;
-    if (ox < N && oy < N && oz < N) {
-      const int p2 = oz & 1, I2 = (oz >> 1) - Z0;
-      double s = 0.0;
-      for (int c2 = 0; c2 <= p2; ++c2)
-        for (int c1 = 0; c1 <= p1; ++c1)
-          for (int c0 = 0; c0 <= p0; ++c0) s += cb[(I0 + c0) + CX * ((I1 + c1) + CY * (I2 + c2))];
-      u[ox + (int64_t)n1 * (oy + (int64_t)n1 * oz)] = uv[k] + (T)(s * (1.0 / (double)(1 << (p0 + p1 + p2))));
+      a.part[b] = acc_r;
+      a.part[MG_PART + b] = acc_f;
     }
   }
 }
@@ -719,7 +727,7 @@ struct OuterArgs {
 // (later corrections use the SW_OUTER sweep)
 template <typename T>
 __global__ void __launch_bounds__(MG_BLOCK) k_outer_resid(OuterArgs a, T* f0) {
-  __shared__ double sr[MG_BLOCK], sf[MG_BLOCK];
+  __shared__ double red[2 * MG_BLOCK / 64];
   double acc_r = 0.0, acc_f = 0.0;
   if (!skip(a.ctl)) {
     const int64_t m = a.d == 3 ? (int64_t)(a.N - 1) * (a.N - 1) * (a.N - 1) : (int64_t)(a.N - 1) * (a.N - 1);
@@ -733,19 +741,10 @@ __global__ void __launch_bounds__(MG_BLOCK) k_outer_resid(OuterArgs a, T* f0) {
       acc_f += Fv * Fv;
     }
   }
-  sr[threadIdx.x] = acc_r;
-  sf[threadIdx.x] = acc_f;
-  __syncthreads();
-  for (int o = MG_BLOCK / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < (unsigned)o) {
-      sr[threadIdx.x] += sr[threadIdx.x + o];
-      sf[threadIdx.x] += sf[threadIdx.x + o];
-    }
-    __syncthreads();
-  }
+  block_sum2<MG_BLOCK>(acc_r, acc_f, red);
   if (threadIdx.x == 0) {
-    a.part[blockIdx.x] = sr[0];
-    a.part[MG_PART + blockIdx.x] = sf[0];
+    a.part[blockIdx.x] = acc_r;
+    a.part[MG_PART + blockIdx.x] = acc_f;
   }
 }
 
@@ -755,8 +754,9 @@ __global__ void __launch_bounds__(MG_BLOCK) k_outer_resid(OuterArgs a, T* f0) {
 // tol |b| / |r_j| (inexact Krylov), so eps becomes relax tol |b| / |r_j|
 // from the GMRES scalars (gs[0] = |r_j| estimate, gs[1] = |b|, gs[3] =
 // tol, gs[7] = relax, 0 for off), clamped to [eps, 1e-2].
-__global__ void __launch_bounds__(MG_BLOCK) k_check(Ctl ctl, const double* part, int nblk, int first, double eps,
-                                                   int maxit, double* scal, const double* gs, int count_hit) {
+__global__ void __launch_bounds__(CHECK_BLOCK) k_check(Ctl ctl, const double* part, int nblk, int first,
+                                                      double eps, int maxit, double* scal, const double* gs,
+                                                      int count_hit) {
   if ((ctl.gctl && ctl.gctl[1]) || ctl.mctl[0]) return;
   const double relax = (ctl.gctl && gs) ? gs[7] : 0.0;
   if (relax > 0.0) {
@@ -767,25 +767,16 @@ __global__ void __launch_bounds__(MG_BLOCK) k_check(Ctl ctl, const double* part,
       if (e > eps) eps = e;
     }
   }
-  __shared__ double sr[MG_BLOCK], sf[MG_BLOCK];
+  __shared__ double red[2 * CHECK_BLOCK / 64];
   double r = 0.0, f = 0.0;
-  for (int i = threadIdx.x; i < nblk; i += MG_BLOCK) {
+  for (int i = threadIdx.x; i < nblk; i += CHECK_BLOCK) {
     r += part[i];
     f += part[MG_PART + i];
   }
-  sr[threadIdx.x] = r;
-  sf[threadIdx.x] = f;
-  __syncthreads();
-  for (int o = MG_BLOCK / 2; o > 0; o >>= 1) {
-    if (threadIdx.x < (unsigned)o) {
-      sr[threadIdx.x] += sr[threadIdx.x + o];
-      sf[threadIdx.x] += sf[threadIdx.x + o];
-    }
-    __syncthreads();
-  }
+  block_sum2<CHECK_BLOCK>(r, f, red);
   if (threadIdx.x == 0) {
-    if (first) scal[0] = sqrt(sf[0]);
-    const double nr = sqrt(sr[0]);
+    if (first) scal[0] = sqrt(f);
+    const double nr = sqrt(r);
     const double nf = scal[0];
     const double rel = nf > 0.0 ? nr / nf : 0.0;
     scal[1] = rel;
@@ -949,16 +940,17 @@ void sweep(kfbi_plan* pl, Ctl ctl, int N, const TS* c27, TS coef, const TS* src,
   a.f = f;
   a.out = out;
   a.part = pl->mg_part;
-  if constexpr (MODE == SW_SMOOTH_UPD) {
+  a.ec = pl->mg_Uc;
+  a.Nc = pl->mg_gc.N;
+  a.n1c = pl->mg_gc.n1;
+  if constexpr (MODE == SW_SMOOTH_UPD || MODE == SW_PSMOOTH) {
     // the tile sweep only (the caller's grid is 3D with N <= 128)
     const int m = N - 1;
     const dim3 grid((m + ST_TX - 1) / ST_TX, (m + ST_TY - 1) / ST_TY, (m + 3) / 4);
     a.KZ = 4;
     hipLaunchKernelGGL((k_sweep3t<TS, TO, MODE, 4>), grid, dim3(256), 0, pl->stream, ctl, a);
     if (nblocks) *nblocks = (int)(grid.x * grid.y * grid.z);
-    return;
-  }
-  if (pl->g.d == 3 && N <= 128) {
+  } else if (pl->g.d == 3 && N <= 128) {
     // whole tile at once: 64 x 4 x 4 outputs per work group (2048 at 128^3)
     const int m = N - 1;
     const dim3 grid((m + ST_TX - 1) / ST_TX, (m + ST_TY - 1) / ST_TY, (m + 3) / 4);
@@ -1016,11 +1008,6 @@ void vcycle_fused(kfbi_plan* pl, const Lev<T>& L, Ctl ctl, double* v) {
   hipLaunchKernelGGL((k_restrict<T>), dim3(gsblk(mc)), dim3(MG_BLOCK), 0, st, ctl, L, gc.N, gc.n1, (const T*)tb,
                      pl->mg_Fc);
   coarse_solve(pl, ctl, st);
-  {
-    const int m = L.N - 1;
-    const dim3 grid((m + 63) / 64, (m + 3) / 4, (m + 3) / 4);
-    hipLaunchKernelGGL((k_prolong3t<T>), grid, dim3(256), 0, st, ctl, L, gc.N, gc.n1, (const double*)pl->mg_Uc, u);
-  }
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (pl->prof_on == 2 && pl->prof_ev && !pl->ctl_active) {
     if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess)
@@ -1028,7 +1015,9 @@ void vcycle_fused(kfbi_plan* pl, const Lev<T>& L, Ctl ctl, double* v) {
     else
       e0 = e1 = nullptr;
   }
-  sweep<T, T, SW_SMOOTH>(pl, ctl, L.N, L.c, L.coef, u, f, tb);
+  // the prolongation of the coarse correction inside the first
+  // post-smoothing step (the prolonged u is not stored)
+  sweep<T, T, SW_PSMOOTH>(pl, ctl, L.N, L.c, L.coef, u, f, tb);
   if (e0 && e1) {
     (void)hipEventRecord(e1, st);
     pl->prof_ev->push_back(e0);
@@ -1109,7 +1098,7 @@ void solve_t(kfbi_plan* pl, const double* F, double* v) {
       hipLaunchKernelGGL((k_outer_resid<T>), dim3(gout), dim3(MG_BLOCK), 0, st, oa, f0);
     else
       sweep<double, T, SW_OUTER>(pl, ctl, g.N, pl->mg_c, 0.0, v, F, f0, &nb_part);
-    hipLaunchKernelGGL(k_check, dim3(1), dim3(MG_BLOCK), 0, st, ctl, (const double*)pl->mg_part, nb_part,
+    hipLaunchKernelGGL(k_check, dim3(1), dim3(CHECK_BLOCK), 0, st, ctl, (const double*)pl->mg_part, nb_part,
                        it == 0 ? 1 : 0, pl->mg_eps, cap, pl->mg_scal, (const double*)pl->scal, guess ? 0 : 1);
     if (fused_path(pl)) {
       vcycle_fused<T>(pl, L, ctl, v);
@@ -1122,7 +1111,7 @@ void solve_t(kfbi_plan* pl, const double* F, double* v) {
   // residual of the final iterate (the stopping value reported)
   int nb_part = 0;
   sweep<double, T, SW_OUTER>(pl, ctl, g.N, pl->mg_c, 0.0, v, F, f0, &nb_part);
-  hipLaunchKernelGGL(k_check, dim3(1), dim3(MG_BLOCK), 0, st, ctl, (const double*)pl->mg_part, nb_part, 0,
+  hipLaunchKernelGGL(k_check, dim3(1), dim3(CHECK_BLOCK), 0, st, ctl, (const double*)pl->mg_part, nb_part, 0,
                      pl->mg_eps, cap, pl->mg_scal, (const double*)pl->scal, guess ? 0 : 1);
 }
 

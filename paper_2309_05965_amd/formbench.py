@@ -24,7 +24,7 @@ def main():
     ap = argparse.ArgumentParser()
     ap.add_argument("--solver", default="mg32", choices=["fft", "mg64", "mg32"])
     ap.add_argument("--eps", type=float, default=1e-9)
-    ap.add_argument("--relax", type=float, default=0.1)
+    ap.add_argument("--relax", type=float, default=3.0)
     ap.add_argument("--max-cycles", type=int, default=16)
     ap.add_argument("--learned", action="store_true")
     ap.add_argument("--tol", type=float, default=1e-8)

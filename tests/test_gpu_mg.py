@@ -130,10 +130,10 @@ def test_kfbi_solve_with_fp32_multigrid(case):
 
 
 @pytest.mark.parametrize("case", ["c2_128", "sphere_32"])
-@pytest.mark.parametrize("eps,relax", [(1e-10, 0.1), (1e-9, 0.1)])
+@pytest.mark.parametrize("eps,relax", [(1e-10, 0.1), (1e-9, 0.1), (1e-9, 3.0)])
 def test_relaxed_inner_tolerance(case, eps, relax):
     """Inexact Krylov: with the multigrid tolerance relaxed inside GMRES
-    (relax 0.1 with eps_in 1e-10, or with eps_in = tol / 10) the
+    (relax 0.1 with eps_in 1e-10, or relax 0.1 or 3 with eps_in = tol / 10) the
     solve still meets the GMRES tolerance in the true
     residual of a fresh full-accuracy matvec (a continuation pass without
     relaxation takes over when the relaxed iterations stop short of it;
@@ -232,9 +232,10 @@ def test_relaxed_iteration_caps(case):
 
 @pytest.mark.parametrize("case", ["c2_128", "sphere_32", "ellipsoid_64"])
 @pytest.mark.parametrize("start", ["zero", "given"])
-def test_mixed_true_residual_against_accurate_operator(case, start):
+@pytest.mark.parametrize("relax", [0.1, 3.0])
+def test_mixed_true_residual_against_accurate_operator(case, start, relax):
     """The mixed form (FP32 multigrid to eps_in = tol / 10, relaxed inside
-    GMRES; the right-hand side, A x0 -- from a given start the initial
+    GMRES by a factor 0.1 or 3; the right-hand side, A x0 -- from a given start the initial
     residual of one box solve of the data and x0 together -- and the true
     residual to tol / 100) from a zero and from a given start: the reported true residual agrees
     with one recomputed against a right-hand side and matvec to 1e-13
@@ -255,7 +256,7 @@ def test_mixed_true_residual_against_accurate_operator(case, start):
     g = torch.Generator(device="cpu").manual_seed(3)
     x0 = (ref * (1.0 + 0.05 * torch.randn(ref.shape, generator=g, dtype=torch.float64).cuda())).contiguous()
     gp.set_box_solver("mg32", eps_in=1e-9, max_cycles=40)
-    gp.set_box_relaxation(0.1)
+    gp.set_box_relaxation(relax)
     psi, u, info = gp.solve(data, tol=1e-8, psi0=x0 if start == "given" else None)
     assert info["status"] == 0 and info["true_rel_res"] < 1e-8
     gp.set_box_relaxation(0.0)
