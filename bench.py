@@ -35,6 +35,8 @@ for _v in ("OMP_NUM_THREADS", "OPENBLAS_NUM_THREADS", "MKL_NUM_THREADS"):
     os.environ[_v] = "1"
 
 import argparse  # noqa: E402
+import contextlib  # noqa: E402
+import gc  # noqa: E402
 import json  # noqa: E402
 import platform  # noqa: E402
 import sys  # noqa: E402
@@ -184,6 +186,22 @@ def _oracle_batch_one(i):
 
 
 # ---------------------------------------------------------------- GPU forms
+@contextlib.contextmanager
+def no_gc():
+    """The timed regions run with Python's cyclic garbage collector off (as
+    timeit does), after a full collection: with torch loaded a generation-2
+    pass walks about 170,000 objects and stalls the host for about 35 ms,
+    which would land on whichever solve happened to trigger it."""
+    was = gc.isenabled()
+    gc.collect()
+    gc.disable()
+    try:
+        yield
+    finally:
+        if was:
+            gc.enable()
+
+
 class HeldOut:
     """The first `count` held-out problems of the ellipsoid workload that
     the set-up resolves on the N^3 grid, with their jump data resident on
@@ -263,10 +281,11 @@ def run_form_workers(ho, warm, timed, tol, solver, eps, relax, learned_start, wo
 
     run(0, warm)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    infos = run(warm, timed)
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    with no_gc():
+        t0 = time.perf_counter()
+        infos = run(warm, timed)
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
     for pl in plans:
         pl.close()
     return timed / el, [i["iters"] for i in infos], [i["true_rel_res"] for i in infos]
@@ -302,14 +321,15 @@ def run_form(ho, warm, timed, tol, solver, eps, relax, learned_start, keep_u=Fal
     for it in items[:warm]:
         one(-1, it)
     torch.cuda.synchronize()
-    t0 = time.perf_counter()
-    for i, it in enumerate(items[warm:]):
-        psi, info = one(i, it)
-        psis.append(psi)
-        its.append(info["iters"])
-        trs.append(info["true_rel_res"])
-    torch.cuda.synchronize()
-    el = time.perf_counter() - t0
+    with no_gc():
+        t0 = time.perf_counter()
+        for i, it in enumerate(items[warm:]):
+            psi, info = one(i, it)
+            psis.append(psi)
+            its.append(info["iters"])
+            trs.append(info["true_rel_res"])
+        torch.cuda.synchronize()
+        el = time.perf_counter() - t0
     plan.close()
     return timed / el, its, trs, psis, U
 
@@ -603,6 +623,10 @@ def main():
     # used for the solve as it is; on the default stream the library orders
     # a private stream before and after every solve with events)
     torch.cuda.set_stream(torch.cuda.Stream())
+    # the GPU phases run with the cyclic collector off (collections between
+    # phases only; see no_gc)
+    gc.collect()
+    gc.disable()
     if args.form:
         run = {"star512": lambda: forms_star512(args.tol), "torus_sphere128": lambda: forms_config3(args.tol, 128),
                "torus_sphere256": lambda: forms_config3(args.tol, 256), "batch512_random_stars": forms_batch,
@@ -658,6 +682,7 @@ def main():
         out["config"]["workers_%d" % args.workers] = {
             "mixed_solves_per_s": wm[0], "plain_fp64_solves_per_s": wp[0], "mixed_learned_over_plain": wm[0] / wp[0],
             "true_rel_res_max": {"mixed": float(np.max(wm[2])), "plain": float(np.max(wp[2]))}}
+    gc.collect()
     if not args.no_forms:
         out["forms"] = {
             "ellipsoid128_ingredients": forms_config5_ingredients(ho, W_, min(K, 8), tol),
@@ -667,6 +692,7 @@ def main():
             "batch512_random_stars": forms_batch(),
             "widened_rows": forms_widened(tol),
         }
+    gc.enable()
     if not args.no_cpu_baseline:
         out["cpu_baseline"] = cpu_baseline(N, tol)
         # the oracle beside the widened rows' GPU solves (forms.widened_rows, the 2D problems)

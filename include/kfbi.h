@@ -303,7 +303,7 @@ kfbi_status kfbi_plan_set_box_solver(kfbi_plan* plan, int solver, double eps_in,
 /* Relaxed multigrid tolerance inside GMRES (inexact Krylov; not in the
  * paper, whose box solve is exact): with relax > 0, the box solve of the
  * matvec at GMRES step j stops at
- *   eps_j = min(1e-2, max(eps_in, relax * tol * |b| / |r_j|)),
+ *   eps_j = min(1e-1, max(eps_in, relax * tol * |b| / |r_j|)),
  * |r_j| the current GMRES residual estimate, |b| the right-hand side norm
  * and tol the solve's tolerance, all read on the device from the GMRES
  * control data, so the captured iterations stay valid.  The right-hand

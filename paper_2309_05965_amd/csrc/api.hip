@@ -409,7 +409,7 @@ void destroy_graphs(kfbi_plan* pl) {
 
 // cap of a relaxed box solve launched when the host's latest GMRES
 // residual estimate is res (|b| = nb): its tolerance relax tol |b| / res,
-// clamped to [eps_in, 1e-2], reached at the two-grid cycle's contraction
+// clamped to [eps_in, 1e-1], reached at the two-grid cycle's contraction
 // (0.07 per correction, 0.085 taken).  The device applies the same rule
 // with the iteration's own estimate, which is no larger, so it needs no
 // more.  0 means the plan-wide cap (no estimate, or no smaller cap).
@@ -417,7 +417,7 @@ int relaxed_cap(const kfbi_plan* pl, double tol, double nb, double res) {
   if (pl->box_solver == KFBI_BOX_FFT || !(pl->relax_word > 0.0) || !(res > 0.0) || !(nb > 0.0)) return 0;
   const int full = pl->mg_run_cap > 0 ? pl->mg_run_cap : pl->mg_maxit;
   double e = pl->relax_word * tol * nb / res;
-  if (e > 1e-2) e = 1e-2;
+  if (e > 1e-1) e = 1e-1;
   if (e < pl->mg_eps) e = pl->mg_eps;
   const int c = (int)ceil(log(e) / log(0.085));
   return c >= 1 && c < full ? c : 0;

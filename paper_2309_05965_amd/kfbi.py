@@ -296,7 +296,7 @@ class Plan:
 
     def set_box_relaxation(self, relax):
         """Relax the multigrid tolerance inside GMRES (inexact Krylov):
-        eps_j = min(1e-2, max(eps_in, relax tol |b| / |r_j|)); 0 turns it off."""
+        eps_j = min(1e-1, max(eps_in, relax tol |b| / |r_j|)); 0 turns it off."""
         _check(load().kfbi_plan_set_box_relaxation(self._h, float(relax)))
         self.box_relax = float(relax)
 
