@@ -497,7 +497,17 @@ __global__ void __launch_bounds__(256) k_sweep3t(Ctl ctl, SweepArgs<TS, TO> a) {
   constexpr int PZ = TZ + 2;
   constexpr int PL = ST_PX * ST_PY * PZ;            // staged input values
   constexpr int NL = (PL + 255) / 256;
-  __shared__ TS blk[PZ * ST_PY * ST_PXS];
+  // SW_PSMOOTH: the coarse block under the staged fine block (fine x0 ..
+  // x0+65 needs coarse x0/2 .. x0/2+33, likewise 4 in y and z) shares the
+  // memory of the staged block (it is dead before the block is written);
+  // its interpolation along y and z to the fine planes and rows of the
+  // block (at coarse x resolution) follows the block
+  constexpr int CX = 34, CY = 4, CZ = 4, NCB = CX * CY * CZ, NYZ = PZ * ST_PY * CX;
+  constexpr int BLK_BYTES = PZ * ST_PY * ST_PXS * (int)sizeof(TS);
+  static_assert(BLK_BYTES >= NCB * 8, "coarse block larger than the staged block");
+  constexpr int EYZ_BYTES = MODE == SW_PSMOOTH ? NYZ * 8 : 0;
+  __shared__ __align__(16) unsigned char smem[BLK_BYTES + EYZ_BYTES];
+  TS* const blk = (TS*)smem;
   __shared__ double red[MODE == SW_OUTER ? 8 : 1];
   double acc_r = 0.0, acc_f = 0.0;
   if (!skip(ctl)) {
@@ -520,13 +530,8 @@ __global__ void __launch_bounds__(256) k_sweep3t(Ctl ctl, SweepArgs<TS, TO> a) {
                  ? a.s[gx + (int64_t)n1 * (gy + (int64_t)n1 * gz)]
                  : (TS)0;
     }
-    // SW_PSMOOTH: the coarse nodes under the staged fine block (fine
-    // x0 .. x0+65 needs coarse x0/2 .. x0/2+33, likewise 4 in y and z),
-    // staged in LDS with one round of loads
-    constexpr int CX = 34, CY = 4, CZ = 4, NCB = CX * CY * CZ;
-    constexpr int NCL = MODE == SW_PSMOOTH ? (NCB + 255) / 256 : 1;
-    __shared__ double cb[MODE == SW_PSMOOTH ? NCB : 1];
     const int X0 = x0 / 2, Y0 = y0 / 2, Z0 = z0 / 2;
+    constexpr int NCL = MODE == SW_PSMOOTH ? (NCB + 255) / 256 : 1;
     double rc[NCL];
     if constexpr (MODE == SW_PSMOOTH) {
 #pragma unroll
@@ -548,39 +553,33 @@ __global__ void __launch_bounds__(256) k_sweep3t(Ctl ctl, SweepArgs<TS, TO> a) {
       const int oz = z0 + k + 1;
       fv[k] = (NEEDF && colok && oz <= m) ? a.f[ox + (int64_t)n1 * (oy + (int64_t)n1 * oz)] : (TS)0;
     }
+    double* const eyz = (double*)(smem + BLK_BYTES);
     if constexpr (MODE == SW_PSMOOTH) {
+      double* const cb = (double*)smem;
 #pragma unroll
       for (int q = 0; q < NCL; ++q) {
         const int i = threadIdx.x + 256 * q;
         if (i < NCB) cb[i] = rc[q];
       }
       __syncthreads();
-      // u' = u + (TS) P e_c at the interior nodes of the block (the box
-      // boundary keeps its zero): the average of the coarse values at the
-      // corners of the coarse cell face / edge the node lies on, summed in
-      // FP64 with c0 fastest (the reciprocal of the count is exact).  All
-      // eight corners are read (every one lies inside the staged coarse
-      // block) and the ones off the node's face add zero, so the loads
-      // issue together and no lane branches.
-#pragma unroll
-      for (int q = 0; q < NL; ++q) {
-        const int i = threadIdx.x + 256 * q;
-        const int ii = i < PL ? i : PL - 1;   // the block's last node for the unused slots
-        const int px = ii % ST_PX, py = (ii / ST_PX) % ST_PY, pz = ii / (ST_PX * ST_PY);
-        const int gx = x0 + px, gy = y0 + py, gz = z0 + pz;
-        const int p0 = gx & 1, p1 = gy & 1, p2 = gz & 1;
-        const int I0 = (gx >> 1) - X0, I1 = (gy >> 1) - Y0, I2 = (gz >> 1) - Z0;
-        const double* cq = cb + I0 + CX * (I1 + CY * I2);
-        double cv[8];
-#pragma unroll
-        for (int c = 0; c < 8; ++c) cv[c] = cq[(c & 1) + CX * (((c >> 1) & 1) + CY * (c >> 2))];
-        double sc = 0.0;
-#pragma unroll
-        for (int c = 0; c < 8; ++c)
-          sc += ((c & 1) <= p0 && ((c >> 1) & 1) <= p1 && (c >> 2) <= p2) ? cv[c] : 0.0;
-        if (i < PL && gx >= 1 && gx <= m && gy >= 1 && gy <= m && gz >= 1 && gz <= m)
-          r[q] = r[q] + (TS)(sc * (1.0 / (double)(1 << (p0 + p1 + p2))));
+      // along y and z: eyz[pz][py][X] is the average of the coarse values at
+      // the (y, z) corners of the coarse cell face / edge that fine row
+      // (y0 + py, z0 + pz) lies on, at coarse x = X0 + X (the reciprocal of
+      // the count is exact; all four corners lie in the coarse block and
+      // the ones off the face add zero)
+      for (int i = threadIdx.x; i < NYZ; i += 256) {
+        const int X = i % CX, py = (i / CX) % ST_PY, pz = i / (CX * ST_PY);
+        const int gy = y0 + py, gz = z0 + pz;
+        const int p1 = gy & 1, p2 = gz & 1;
+        const double* cq = cb + X + CX * (((gy >> 1) - Y0) + CY * ((gz >> 1) - Z0));
+        const double c00 = cq[0], c01 = cq[CX], c10 = cq[CX * CY], c11 = cq[CX * CY + CX];
+        double sc = c00;
+        sc += p1 ? c01 : 0.0;
+        sc += p2 ? c10 : 0.0;
+        sc += (p1 && p2) ? c11 : 0.0;
+        eyz[i] = sc * (1.0 / (double)(1 << (p1 + p2)));
       }
+      __syncthreads();   // the staged block overwrites cb below
     }
 #pragma unroll
     for (int q = 0; q < NL; ++q) {
@@ -591,6 +590,21 @@ __global__ void __launch_bounds__(256) k_sweep3t(Ctl ctl, SweepArgs<TS, TO> a) {
       }
     }
     __syncthreads();
+    if constexpr (MODE == SW_PSMOOTH) {
+      // then along x: u' = u + (TS) P e_c at the interior nodes of the block
+      // (the box boundary keeps its zero), in place in the staged block
+      for (int i = threadIdx.x; i < PL; i += 256) {
+        const int px = i % ST_PX, py = (i / ST_PX) % ST_PY, pz = i / (ST_PX * ST_PY);
+        const int gx = x0 + px, gy = y0 + py, gz = z0 + pz;
+        if (gx >= 1 && gx <= m && gy >= 1 && gy <= m && gz >= 1 && gz <= m) {
+          const double* eq = eyz + ((gx >> 1) - X0) + CX * (py + ST_PY * pz);
+          const double sc = (gx & 1) ? (eq[0] + eq[1]) * 0.5 : eq[0];
+          TS* const bq = blk + (pz * ST_PY + py) * ST_PXS + px;
+          *bq = *bq + (TS)sc;
+        }
+      }
+      __syncthreads();
+    }
     TS acc0 = 0, acc1 = 0, ctr = 0;   // ctr: centre value of the previous plane
 #pragma unroll
     for (int p = 0; p < PZ; ++p) {
