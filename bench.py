@@ -344,8 +344,12 @@ def coarse_pass_roofline(prob, N, solver):
     """Average duration of a pass of the multigrid's exact coarse solve (the
     kernel that takes the most time in both forms; HIP events on the plan's
     stream around the five passes of every cycle of eager box solves, every
-    correction active).  Algorithmic bytes: one FP64 read and one FP64
-    write of each interior coarse node per pass."""
+    correction active).  Algorithmic bytes per coarse solve: one FP64 read
+    and one FP64 write of each interior coarse node in each of the last four
+    passes; the first pass forms the coarse right-hand side from the fine
+    residual as it loads (one read of each interior fine node in the inner
+    precision, one FP64 write of each interior coarse node); reported per
+    launch (the solve's total over its five launches)."""
     import torch
     from paper_2309_05965_amd import kfbi
     plan = kfbi.Plan(prob)
@@ -359,7 +363,8 @@ def coarse_pass_roofline(prob, N, solver):
     plan.profile(False)
     plan.close()
     nc = N // 2
-    bytes_per_launch = 16 * (nc - 1) ** 3
+    inner = 4 if solver == "mg32" else 8
+    bytes_per_launch = (4 * 16 * (nc - 1) ** 3 + inner * (N - 1) ** 3 + 8 * (nc - 1) ** 3) / 5
     avg_s = ms / 1e3 / launches
     achieved = bytes_per_launch / avg_s / 1e9
     return {"kernel": "k_dst coarse sine-transform pass, %d^3 coarse grid of the %d^3 multigrid (FP64)" % (nc, N),

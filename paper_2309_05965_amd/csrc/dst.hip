@@ -60,6 +60,11 @@ struct DstArgs {
   const double2* tw;   // exp(-2 pi i m / M), m < M
   const double* eig1;  // s_k, k = 0..N
   double scale;        // (2/N)^d
+  // first pass of a multigrid coarse solve (3D, x axis): instead of reading
+  // `in`, the coarse right-hand side is the full weighting of this fine
+  // residual (FP32 if rsrc_f32, else FP64; n1f nodes per axis), formed on load
+  const void* rsrc;
+  int rsrc_f32, n1f;
 };
 
 // LDS layout of a sequence: element i at i + (i >> PS), one pad slot per 8
@@ -290,6 +295,27 @@ __device__ __forceinline__ int64_t elem_addr(const DstArgs& a, int u, int w, int
   return (int64_t)c[0] + (int64_t)g.n1 * ((int64_t)c[1] + (int64_t)g.n1 * c[2]);
 }
 
+// full weighting at coarse node (I0, I1, I2) of the fine residual r (3D):
+// the tensor product of (1/4, 1/2, 1/4) about fine node 2I, summed in T with
+// o0 fastest
+template <typename T>
+__device__ __forceinline__ T restrict_fine(const T* __restrict__ r, int n1f, int I0, int I1, int I2) {
+  const T w1[3] = {(T)0.25, (T)0.5, (T)0.25};
+  T s = 0;
+#pragma unroll
+  for (int o2 = -1; o2 <= 1; ++o2)
+#pragma unroll
+    for (int o1 = -1; o1 <= 1; ++o1)
+#pragma unroll
+      for (int o0 = -1; o0 <= 1; ++o0) {
+        T w = w1[o0 + 1] * w1[o1 + 1];
+        w *= w1[o2 + 1];
+        const int64_t fi = (2 * I0 + o0) + (int64_t)n1f * ((2 * I1 + o1) + (int64_t)n1f * (2 * I2 + o2));
+        s += w * r[fi];
+      }
+  return s;
+}
+
 // lambda from the 1D eigenvalues s_k (k along the transform axis), s_u and,
 // in 3D, s_w
 __device__ __forceinline__ double eigenvalue(const GridDesc& g, double sk, double su, double sw) {
@@ -435,6 +461,28 @@ __device__ __forceinline__ void dst_pass(const DstArgs& a, const int tile) {
       A[f * Mp] = make_double2(0.0, 0.0);
       A[f * Mp + padi(N)] = make_double2(0.0, 0.0);
     }
+    if (a.rsrc) {
+      // the coarse right-hand side from the fine residual (x pass: element
+      // j of the line at tile coordinate u, remaining coordinate w is coarse
+      // node (j, u, w)); one coarse value per thread and round, its 27 fine
+      // loads in flight together
+      for (int idx = threadIdx.x; idx < total; idx += KFBI_BLOCK) {
+        int l, j;
+        tile_pos(a, idx, nl, l, j);
+        double xv = 0.0;
+        if (u0 + l <= nl)
+          xv = a.rsrc_f32 ? (double)restrict_fine<float>((const float*)a.rsrc, a.n1f, j, u0 + l, w)
+                          : restrict_fine<double>((const double*)a.rsrc, a.n1f, j, u0 + l, w);
+        double2* z = A + (l >> 1) * Mp;
+        if (l & 1) {
+          z[padi(j)].y = xv;
+          z[padi(M - j)].y = -xv;
+        } else {
+          z[padi(j)].x = xv;
+          z[padi(M - j)].x = -xv;
+        }
+      }
+    } else
     // all loads of a chunk are issued before the LDS stores
     for (int base = threadIdx.x; base < total; base += DST_CH * KFBI_BLOCK) {
       double xv[DST_CH];
@@ -765,7 +813,7 @@ void launch_args(DstArgs& a, bool src_corr, hipStream_t st, int tl = 0) {
 }
 
 void launch_pass(kfbi_plan* pl, int ax, int mode, const double* in, double* out, bool src_corr = false) {
-  DstArgs a;
+  DstArgs a{};
   a.ctl = pl->ctl_active;
   a.mctl = nullptr;
   a.src_corr = src_corr ? 1 : 0;
@@ -967,7 +1015,8 @@ void dst_host_tables(int N, double h, double* tw, double* eig1) {
 }
 
 void dst_solve_grid(const GridDesc& g, const double* tw, const double* eig1, double* T1, double* T2,
-                    const double* F, double* v, const int* ctl, const int* mctl, hipStream_t st) {
+                    const double* F, double* v, const int* ctl, const int* mctl, hipStream_t st,
+                    const void* rsrc, int rsrc_f32, int n1f) {
   DstArgs a{};
   a.ctl = ctl;
   a.mctl = mctl;
@@ -986,6 +1035,10 @@ void dst_solve_grid(const GridDesc& g, const double* tw, const double* eig1, dou
     a.mode = g.d == 2 ? md2[q] : md3[q];
     a.in = src[q];
     a.out = g.d == 2 ? dst2[q] : dst3[q];
+    // the first (x) pass forms the right-hand side from the fine residual
+    a.rsrc = (q == 0 && g.d == 3) ? rsrc : nullptr;
+    a.rsrc_f32 = rsrc_f32;
+    a.n1f = n1f;
     launch_args(a, false, st);
   }
 }

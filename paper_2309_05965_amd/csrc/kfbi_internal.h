@@ -320,9 +320,13 @@ extern std::shared_mutex kfbi_capture_mutex;
 kfbi_status mg_configure(kfbi_plan* pl, int solver, double eps, int maxit);
 // exact solve A_h v = F (zero box data) of the grid g by the sine transform
 // with the given tables and pass buffers; skipped when ctl[1] (GMRES
-// converged) or mctl[0] (multigrid converged) is set
+// converged) or mctl[0] (multigrid converged) is set.  With rsrc (3D only)
+// F is not read: the first pass forms F on load as the full weighting of
+// the fine residual rsrc (FP32 if rsrc_f32, else FP64; n1f nodes per axis,
+// the fine grid twice g's), in that precision, taken to FP64
 void dst_solve_grid(const GridDesc& g, const double* tw, const double* eig1, double* T1, double* T2,
-                    const double* F, double* v, const int* ctl, const int* mctl, hipStream_t st);
+                    const double* F, double* v, const int* ctl, const int* mctl, hipStream_t st,
+                    const void* rsrc = nullptr, int rsrc_f32 = 0, int n1f = 0);
 // twiddles exp(-2 pi i m / 2N) (m < 2N, interleaved re, im) and the 1D
 // eigenvalues s_k = -4/h^2 sin^2(k pi / 2N) (k <= N) of the sine transform
 void dst_host_tables(int N, double h, double* tw, double* eig1);

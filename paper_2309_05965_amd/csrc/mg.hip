@@ -990,7 +990,7 @@ inline bool fused_path(const kfbi_plan* pl) { return pl->g.d == 3 && pl->g.N <= 
 
 // the exact FP64 solve of the coarse grid (tracing aid, profile mode 3:
 // events around its passes in eager box solves)
-void coarse_solve(kfbi_plan* pl, Ctl ctl, hipStream_t st) {
+void coarse_solve(kfbi_plan* pl, Ctl ctl, hipStream_t st, const void* rsrc = nullptr, int rsrc_f32 = 0) {
   const GridDesc& gc = pl->mg_gc;
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (pl->prof_on == 3 && pl->prof_ev && !pl->ctl_active) {
@@ -999,7 +999,8 @@ void coarse_solve(kfbi_plan* pl, Ctl ctl, hipStream_t st) {
     else
       e0 = e1 = nullptr;
   }
-  dst_solve_grid(gc, pl->mg_twc, pl->mg_eigc, pl->mg_T1c, pl->mg_T2c, pl->mg_Fc, pl->mg_Uc, ctl.gctl, ctl.mctl, st);
+  dst_solve_grid(gc, pl->mg_twc, pl->mg_eigc, pl->mg_T1c, pl->mg_T2c, pl->mg_Fc, pl->mg_Uc, ctl.gctl, ctl.mctl, st,
+                 rsrc, rsrc_f32, pl->g.n1);
   if (e0 && e1) {
     (void)hipEventRecord(e1, st);
     pl->prof_ev->push_back(e0);
@@ -1016,13 +1017,11 @@ void vcycle_fused(kfbi_plan* pl, const Lev<T>& L, Ctl ctl, double* v) {
   T* tb = (T*)pl->mg_t;
   T* f = (T*)pl->mg_f;
   hipStream_t st = pl->stream;
-  const GridDesc& gc = pl->mg_gc;
-  const int64_t mc = (int64_t)(gc.N - 1) * (gc.N - 1) * (gc.N - 1);
   sweep<T, T, SW_SMOOTH2>(pl, ctl, L.N, L.c, L.coef, f, f, u);
   sweep<T, T, SW_RESID>(pl, ctl, L.N, L.c, L.coef, u, f, tb);
-  hipLaunchKernelGGL((k_restrict<T>), dim3(gsblk(mc)), dim3(MG_BLOCK), 0, st, ctl, L, gc.N, gc.n1, (const T*)tb,
-                     pl->mg_Fc);
-  coarse_solve(pl, ctl, st);
+  // the restriction of the residual is formed by the coarse solve's first
+  // pass as it loads its lines
+  coarse_solve(pl, ctl, st, (const void*)tb, sizeof(T) == 4 ? 1 : 0);
   hipEvent_t e0 = nullptr, e1 = nullptr;
   if (pl->prof_on == 2 && pl->prof_ev && !pl->ctl_active) {
     if (hipEventCreate(&e0) == hipSuccess && hipEventCreate(&e1) == hipSuccess)
