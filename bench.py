@@ -334,10 +334,12 @@ def run_form(ho, warm, timed, tol, solver, eps, relax, learned_start, keep_u=Fal
     return timed / el, its, trs, psis, U
 
 
-# HBM traffic of one active coarse sine-transform pass on the 64^3 coarse grid
-# of a 128^3 box (FETCH_SIZE x 2 + WRITE_SIZE x 1 per dispatch, the factors
-# read off a plain 256 MiB copy; profiles/mg_kernels_torus128_256_hbm_counters.md)
-COARSE_PASS_TRAFFIC_128 = 4.39e6
+# HBM traffic of an active coarse solve on the 64^3 coarse grid of a 128^3
+# box with the FP32 inner cycle, per launch averaged over its five passes
+# (the first restricts the fine residual as it loads; FETCH_SIZE x 2 +
+# WRITE_SIZE x 1 per dispatch, the factors read off a plain 256 MiB copy;
+# profiles/mg_kernels_torus128_256_hbm_counters.md)
+COARSE_PASS_TRAFFIC_128 = 5.755e6
 
 
 def coarse_pass_roofline(prob, N, solver):
@@ -367,9 +369,10 @@ def coarse_pass_roofline(prob, N, solver):
     bytes_per_launch = (4 * 16 * (nc - 1) ** 3 + inner * (N - 1) ** 3 + 8 * (nc - 1) ** 3) / 5
     avg_s = ms / 1e3 / launches
     achieved = bytes_per_launch / avg_s / 1e9
-    return {"kernel": "k_dst coarse sine-transform pass, %d^3 coarse grid of the %d^3 multigrid (FP64)" % (nc, N),
+    return {"kernel": "k_dst coarse sine-transform passes, %d^3 coarse grid of the %d^3 multigrid (FP64; the "
+                      "first restricts the fine residual on load)" % (nc, N),
             "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s",
-            "frac": achieved / HBM_PEAK_GBS, "traffic": COARSE_PASS_TRAFFIC_128 if N == 128 else None,
+            "frac": achieved / HBM_PEAK_GBS, "traffic": COARSE_PASS_TRAFFIC_128 if (N == 128 and solver == "mg32") else None,
             "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_per_launch,
             "timing": "HIP events around the %d coarse solves (%d launches) of 10 eager box solves after the "
                       "timed region" % (ivals, launches)}
