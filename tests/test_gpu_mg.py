@@ -70,9 +70,22 @@ def test_fp64_vcycles_match_oracle(name, cycles):
     assert c == cycles
 
 
-@pytest.mark.parametrize("name", ["2d_o4_64", "3d_o4_32"])
+def test_fp64_vcycle_matches_oracle_128():
+    """The 128^3 cycle of the benchmark's grid (whole-tile sweeps, the coarse
+    solve's first pass restricting the residual on load, the prolongation
+    inside the first post-smoothing sweep) against the oracle's cycle."""
+    d, order, N, kappa = 3, 4, 128, 0.0
+    gp, prob = plan_for(d, order, N, kappa)
+    gp.set_box_solver("mg64", eps_in=1e-300, max_cycles=1)
+    F = rhs(d, N, 6)
+    v = gp.box_solve(dev(F)).cpu().numpy().reshape(F.shape)
+    ref = mg.Hierarchy(d, order, N, 2.0 / N, kappa, np.float64).vcycle(F)
+    assert np.max(np.abs(v - ref)) <= 1e-12 * np.max(np.abs(ref))
+
+
+@pytest.mark.parametrize("name", ["2d_o4_64", "3d_o4_32", "3d_o4_128"])
 def test_fp32_vcycle_matches_oracle_to_fp32(name):
-    d, order, N, kappa = BOXES[name]
+    d, order, N, kappa = BOXES[name] if name in BOXES else (3, 4, 128, 0.0)
     gp, prob = plan_for(d, order, N, kappa)
     gp.set_box_solver("mg32", eps_in=1e-300, max_cycles=1)
     F = rhs(d, N, 4)
