@@ -66,7 +66,8 @@ def parse():
     ap.add_argument("--cpu-suite", action="store_true",
                     help="only time the oracle on every workload (long; one JSON line)")
     ap.add_argument("--form", default=None,
-                    choices=("star512", "torus_sphere128", "torus_sphere256", "batch512_random_stars", "widened_rows"),
+                    choices=("star512", "torus_sphere128", "torus_sphere256", "batch512_random_stars", "widened_rows",
+                             "mg_smoothing_sweep_roofline_256"),
                     help="only this entry of `forms` (for profiling; one JSON line)")
     return ap.parse_args()
 
@@ -378,6 +379,40 @@ def coarse_pass_roofline(prob, N, solver):
                       "timed region" % (ivals, launches)}
 
 
+def sweep_roofline_256():
+    """The finest-level smoothing sweep of the multigrid at 256^3 (torus +
+    sphere box, 2.5D-blocked sweeps): HIP events on the plan's stream around
+    the two post-smoothing steps of every cycle of eager box solves (every
+    correction active).  Algorithmic bytes per launch: u and f read, u'
+    written, 4 B each in FP32 and 8 B in FP64, per interior node."""
+    import torch
+    from paper_2309_05965_amd import kfbi
+    from paper_2309_05965_amd import workloads as W
+    N = 256
+    prob, _ = W.config3(N)
+    plan = kfbi.Plan(prob)
+    out = {}
+    for solver, b in (("mg32", 12), ("mg64", 24)):
+        plan.set_box_solver(solver, eps_in=1e-30, max_cycles=4)
+        F = torch.randn(plan.n_nodes, dtype=torch.float64, device="cuda")
+        plan.box_solve(F)
+        plan.profile(2)
+        for _ in range(3):
+            plan.box_solve(F)
+        ivals, launches, ms = plan.timing()
+        plan.profile(False)
+        bytes_per_launch = b * (N - 1) ** 3
+        avg_s = ms / 1e3 / launches
+        achieved = bytes_per_launch / avg_s / 1e9
+        out["fp32" if solver == "mg32" else "fp64"] = {
+            "kernel": "k_sweep3 smoothing step, %d^3 (%s)" % (N, "FP32" if solver == "mg32" else "FP64"),
+            "bound": "hbm", "achieved": achieved, "peak": HBM_PEAK_GBS, "unit": "GB/s", "frac": achieved / HBM_PEAK_GBS,
+            "avg_launch_us": avg_s * 1e6, "algorithmic_bytes_per_launch": bytes_per_launch,
+            "timing": "HIP events around %d launches in %d events of 3 eager box solves" % (launches, ivals)}
+    plan.close()
+    return out
+
+
 def forms_config5_ingredients(ho, warm, timed, tol):
     """Each ingredient of the mixed form alone, on the same held-out problems
     (a plan per form, each problem solved once per plan)."""
@@ -638,6 +673,7 @@ def main():
     if args.form:
         run = {"star512": lambda: forms_star512(args.tol), "torus_sphere128": lambda: forms_config3(args.tol, 128),
                "torus_sphere256": lambda: forms_config3(args.tol, 256), "batch512_random_stars": forms_batch,
+               "mg_smoothing_sweep_roofline_256": sweep_roofline_256,
                "widened_rows": lambda: forms_widened(args.tol)}[args.form]
         print(json.dumps({"forms": {args.form: run()}}), flush=True)
         return
@@ -697,6 +733,7 @@ def main():
             "star512": forms_star512(tol),
             "torus_sphere128": forms_config3(tol, 128),
             "torus_sphere256": forms_config3(tol, 256),
+            "mg_smoothing_sweep_roofline_256": sweep_roofline_256(),
             "batch512_random_stars": forms_batch(),
             "widened_rows": forms_widened(tol),
         }

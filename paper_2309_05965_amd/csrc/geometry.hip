@@ -1362,7 +1362,7 @@ kfbi_status grow(T** p, int64_t* cap, int64_t n) {
   if (n <= *cap && *p) return KFBI_OK;
   if (*p) (void)hipFree(*p);
   *p = nullptr;
-  int64_t c = n + n / 4 + 64;
+  int64_t c = kfbi_headroom(n);
   if (hipMalloc((void**)p, (size_t)c * sizeof(T)) != hipSuccess) {
     *cap = 0;
     kfbi_set_error("device allocation of %lld bytes failed", (long long)(c * sizeof(T)));
@@ -1386,7 +1386,7 @@ kfbi_status realloc_n(T** p, int64_t n) {
   return KFBI_OK;
 }
 
-inline int64_t headroom(int64_t n) { return n + n / 4 + 64; }
+inline int64_t headroom(int64_t n) { return kfbi_headroom(n); }
 
 kfbi_status ensure_blk(kfbi_plan* pl, int64_t nb) { return grow(&pl->blk, &pl->cap_blk, nb + 1); }
 

@@ -317,6 +317,12 @@ void dst_solve(kfbi_plan* pl, const double* F, double* v);
 // can drive their own plans while one of them captures.
 extern std::shared_mutex kfbi_capture_mutex;
 
+// capacity for n elements when a plan's buffer grows: twice the need, so
+// that a plan set up again for problems of varying size reallocates (and
+// synchronises the device on the frees) a few times, not at every new
+// largest problem
+inline int64_t kfbi_headroom(int64_t n) { return 2 * n + 64; }
+
 kfbi_status mg_configure(kfbi_plan* pl, int solver, double eps, int maxit);
 // exact solve A_h v = F (zero box data) of the grid g by the sine transform
 // with the given tables and pass buffers; skipped when ctl[1] (GMRES

@@ -1085,7 +1085,7 @@ kfbi_status op_fold(kfbi_plan* pl) {
   pl->nF = (g.bie == KFBI_BIE_DIRICHLET ? pl->nD : g.bie == KFBI_BIE_TWO_DENSITY ? pl->nD + pl->nN : pl->nN) * g.p;
   pl->maxpairs = g.order == 2 ? 2 * g.d : (g.d == 3 ? 26 : 8);
   if (pl->n_corr > pl->cap_fold_corr) {
-    int64_t cap = pl->n_corr + pl->n_corr / 4 + 64;
+    int64_t cap = kfbi_headroom(pl->n_corr);
     pl->cap_fold_corr = 0;
     KCHK(regrow(&pl->FI, cap * pl->nF));
     KCHK(regrow(&pl->FW, cap * pl->nF));
@@ -1093,7 +1093,7 @@ kfbi_status op_fold(kfbi_plan* pl) {
     pl->cap_fold_corr = cap;
   }
   if (pl->n_dof > pl->cap_fold_dof) {
-    int64_t cap = pl->n_dof + pl->n_dof / 4 + 64;
+    int64_t cap = kfbi_headroom(pl->n_dof);
     pl->cap_fold_dof = 0;
     KCHK(regrow(&pl->GI, cap * pl->nF));
     KCHK(regrow(&pl->GW, cap * pl->nF));
@@ -1111,7 +1111,7 @@ kfbi_status op_fold(kfbi_plan* pl) {
     pl->cap_fold_dof = cap;
   }
   if (pl->n_irr > pl->cap_fold_irr) {
-    int64_t cap = pl->n_irr + pl->n_irr / 4 + 64;
+    int64_t cap = kfbi_headroom(pl->n_irr);
     pl->cap_fold_irr = 0;
     KCHK(regrow(&pl->PA, cap * pl->maxpairs));
     KCHK(regrow(&pl->PE1, cap * pl->maxpairs));
