@@ -44,8 +44,13 @@ class Model:
 
 
 def _pack(geom, jumps, device):
-    return (torch.tensor(learned.pack_geometry(geom), device=device),
-            torch.tensor(learned.pack_jumps(jumps), device=device))
+    """Geometry and jump coefficients on the device: one pinned host buffer
+    and one copy enqueued on the current stream (the host does not wait;
+    the stream orders the copy before the kernels that read it)."""
+    h = torch.from_numpy(np.concatenate([learned.pack_geometry(geom), learned.pack_jumps(jumps)])).pin_memory()
+    d = h.to(device, non_blocking=True)
+    ng = 15
+    return d[:ng], d[ng:]
 
 
 def generate(seeds, N=128, tol=1e-10, device="cuda", log_every=0):
